@@ -1,0 +1,212 @@
+/*
+ * hsrom.h -- C ABI of the MI355X (gfx950) hybrid-snapshot adaptive ROM step.
+ *
+ * Method: Zucatti & Zahr, "An adaptive, training-free reduced-order model for
+ * convection-dominated problems based on hybrid snapshots" (arXiv 2301.01718).
+ * The four calls below follow the paper's problem statement:
+ *   hdm_step        -- full HDM solve R_k(q) = 0 (Sec. 2.2, eq. hdm)
+ *   sample_select   -- error ordering, G, sampled set and its neighbours
+ *                      (Sec. 2.3.3, eq. rre; Alg. 1 set operations)
+ *   rom_hybrid_step -- partial HDM + gappy-POD fit + subiterations +
+ *                      reconstruction + residual-gated filter
+ *                      (eq. hybrid, eq. partial_hdm2, eq. red_coord,
+ *                      Sec. 2.3.2, Sec. 2.3.4; Alg. 1 hybrid branch)
+ *   basis_update    -- window mean and POD basis (eq. pod, eq. mean;
+ *                      Alg. 1 basis update)
+ *
+ * Conventions for every call
+ * --------------------------
+ * - All double / int32 / uint8 array arguments are DEVICE pointers on the
+ *   context's device unless the comment says "host".  They are owned by the
+ *   caller and never freed by the library.  Outputs must not alias inputs.
+ * - State vectors are component-major: q[c * ncell + i + nx * j], length
+ *   N = ncomp * ncell (ncomp = 1 for Burgers, 4 for Euler: rho, rho u,
+ *   rho v, E).  Bases are column-major N x m: Phi[col * N + row].
+ * - Work is enqueued on the stream given to hs_create.  Calls that must take
+ *   a data-dependent decision (Newton convergence, subiteration and filter
+ *   stopping, set sizes) synchronise that stream internally; they return
+ *   only when their outputs are complete.
+ * - Return value: HS_OK (0) or a negative status.  Argument errors are
+ *   reported before any work is enqueued.  Numerical failures
+ *   (HS_ERR_NOT_CONVERGED, HS_ERR_RANK, HS_ERR_NONFINITE) leave the outputs
+ *   undefined.  hs_last_error() gives a message for the last failure.
+ * - No C++ exception crosses this interface.  One context per stream and
+ *   host thread; a context is not thread-safe.
+ * - Arithmetic is IEEE double throughout unless a precision field says
+ *   otherwise; reductions use fixed orders, so identical inputs give
+ *   bitwise-identical outputs.
+ */
+#ifndef HSROM_H
+#define HSROM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+#define HS_OK                 0
+#define HS_ERR_INVALID_ARG   -1   /* null pointer, bad enum, bad parameter */
+#define HS_ERR_SHAPE         -2   /* size beyond the context's capacity */
+#define HS_ERR_NOT_CONVERGED -3   /* Newton / linear iteration hit its limit */
+#define HS_ERR_RANK          -4   /* empty basis or a rank-zero fit */
+#define HS_ERR_NONFINITE     -5   /* NaN or Inf met in a residual */
+#define HS_ERR_HIP           -6   /* HIP runtime failure */
+#define HS_ERR_OOM           -7   /* device allocation failed */
+
+/* --------------------------------------------------------- problem kinds */
+#define HS_BURGERS_1D 0   /* u_t + (u^2/2)_x = 0 on (0,1) */
+#define HS_BURGERS_2D 1   /* u_t + (u^2/2)_x + (u^2/2)_y = 0 on (0,1)^2 */
+#define HS_EULER_2D   2   /* 2D Euler, ideal gas (Sec. 3.1, eq. euler) */
+
+#define HS_BC_INFLOW_OUTFLOW 0 /* left ghost = inflow value, right ghost = last cell */
+#define HS_BC_PERIODIC       1
+#define HS_BC_TRANSMISSIVE   2 /* every ghost = its boundary cell */
+
+#define HS_FP64        0
+#define HS_MIXED_FP32  1   /* Grams / projections in FP32 on MFMA + FP64 refinement */
+
+typedef int32_t hs_status;
+typedef struct hs_ctx hs_ctx;          /* opaque, library-owned */
+typedef struct hs_samples hs_samples;  /* opaque, library-owned */
+
+/* Problem description; copied at hs_create.  The spatial scheme is the
+ * first-order finite-volume Rusanov flux with backward Euler in time
+ * (eq. bdf with s = 1; eq. hdm). */
+typedef struct hs_problem {
+  int32_t kind;          /* HS_BURGERS_1D / HS_BURGERS_2D / HS_EULER_2D */
+  int32_t nx, ny;        /* cells; ny = 1 for HS_BURGERS_1D */
+  int32_t bc;            /* HS_BC_* */
+  double  dx, dy, dt;    /* dy ignored in 1D */
+  double  gamma;         /* ratio of specific heats (Euler) */
+  double  inflow;        /* left Dirichlet value (HS_BC_INFLOW_OUTFLOW) */
+  double  newton_rtol;   /* stop when ||R||_inf <= newton_rtol * max(1, ||q_prev||_inf); 0 -> 1e-13 */
+  int32_t newton_maxit;  /* 0 -> 30 */
+  double  lin_rtol;      /* relative accuracy of each Newton correction; 0 -> 1e-10 */
+  int32_t lin_maxit;     /* cap on linear sweeps per Newton iteration; 0 -> 400 */
+  int32_t m_max;         /* largest basis rank used with this context (<= 64) */
+  int32_t w_max;         /* largest window length used with this context (<= 64) */
+} hs_problem;
+
+/* Per-call diagnostics, written to HOST memory when the pointer is non-null. */
+typedef struct hs_step_info {
+  int32_t newton_iters;    /* Newton iterations (summed over subiterations) */
+  int32_t lin_sweeps;      /* linear relaxation sweeps (summed) */
+  int32_t subiters;        /* J, the number of subiterations (hybrid step) */
+  int32_t filter_passes;   /* filter passes over all orders */
+  int32_t filter_kept;     /* cells whose filtered value was kept, summed */
+  int32_t n_s, l;          /* sampled cells and neighbour cells */
+  int32_t fit_rank;        /* rank kept by the truncated pseudo-inverse */
+  double  residual_inf;    /* final ||R||_inf of the (restricted) Newton solve */
+  double  dy_last;         /* last ||y^(j) - y^(j-1)||_2 */
+  double  fit_cond;        /* sigma_max / sigma_min(kept) of the gathered basis */
+} hs_step_info;
+
+/* ------------------------------------------------------------ lifetime */
+/* Create a context on the current HIP device.  hip_stream may be NULL (the
+ * null stream).  Allocates all workspace for the problem size, m_max and
+ * w_max. */
+hs_status hs_create(const hs_problem* problem /* host */, void* hip_stream, hs_ctx** out /* host */);
+hs_status hs_destroy(hs_ctx* ctx);
+/* Wait for all work enqueued by this context. */
+hs_status hs_sync(hs_ctx* ctx);
+const char* hs_status_string(hs_status s);
+const char* hs_last_error(const hs_ctx* ctx);
+
+/* -------------------------------------------------------- A1/A2 kernels */
+/* R = R_k(q) = q - q_prev + dt * div_h F(q), full mesh (eq. hdm, BDF1). */
+hs_status hs_residual(hs_ctx* ctx, const double* q, const double* q_prev, double* R);
+/* out = (dR/dq)(q) * v, the exact Jacobian of hs_residual at q. */
+hs_status hs_jvp(hs_ctx* ctx, const double* q, const double* v, double* out);
+
+/* ------------------------------------------------------------ hdm_step */
+/* Full HDM step: Newton from the guess q_prev until
+ * ||R_k(q_out)||_inf <= newton_rtol * max(1, ||q_prev||_inf) (eq. hdm).
+ * Each correction solves the exact Jacobian system by (block-)Jacobi
+ * relaxation to relative accuracy lin_rtol, with the sweep count set from a
+ * computed contraction bound.  Errors: HS_ERR_NOT_CONVERGED,
+ * HS_ERR_NONFINITE. */
+hs_status hdm_step(hs_ctx* ctx, const double* q_prev, double* q_out, hs_step_info* info /* host, may be NULL */);
+
+/* -------------------------------------------------------- sample_select */
+#define HS_RULE_FRACTION 0   /* n_g = min(ceil(fraction * ncell), #{eps > 0}) */
+#define HS_RULE_RRE      1   /* smallest n_g with RRE(n_g) >= delta (eq. rre) */
+
+typedef struct hs_sample_params {
+  int32_t rule;       /* HS_RULE_* */
+  double  fraction;   /* HS_RULE_FRACTION */
+  double  delta;      /* HS_RULE_RRE */
+  int32_t halo;       /* Chebyshev dilation radius of G (0..8) */
+} hs_sample_params;
+
+hs_status hs_samples_create(hs_ctx* ctx, hs_samples** out /* host */);
+hs_status hs_samples_destroy(hs_samples* s);
+/* From the per-cell indicator eps (ncell doubles, >= 0) build G (the n_g
+ * largest, ties to the lower cell index; Sec. 2.3.3), the sampled set
+ * hat-S = dilate(G, halo), its face-neighbour ring tilde-S and the
+ * complement (Alg. 1: union, setdiff, Neighbors).  The sets are stored in
+ * the library-owned object; their sizes are known on return. */
+hs_status sample_select(hs_ctx* ctx, const double* eps, const hs_sample_params* params /* host */,
+                        hs_samples* out);
+/* Set the sampled set directly from a sorted, duplicate-free cell list
+ * (hat, n_s entries, device); tilde-S is derived as in sample_select. */
+hs_status hs_samples_set(hs_ctx* ctx, hs_samples* s, const int32_t* hat, int32_t n_s);
+/* counts[0..2] = n_g, n_s, l (host). */
+hs_status hs_samples_counts(const hs_samples* s, int32_t* counts /* host, 3 */);
+/* Copy the sorted lists and the mask out (any pointer may be NULL):
+ * hat (n_s int32), tilde (l int32), mask (ncell uint8, 1 on hat-S). */
+hs_status hs_samples_export(hs_ctx* ctx, const hs_samples* s, int32_t* hat, int32_t* tilde, uint8_t* mask);
+
+/* ---------------------------------------------------- indicator (A4) */
+/* eps_j = sum_c (gamma - psi - Phi y)^2 at cell j with y = Phi^T (gamma - psi)
+ * (a snapshot known everywhere; Sec. 2.3.3).  Cells whose error norm is below
+ * floor_rel * max(1, ||gamma||_inf) get eps = 0.  y_out (m doubles) may be NULL. */
+hs_status hs_indicator_full(hs_ctx* ctx, const double* gamma, const double* Phi, const double* psi,
+                            int32_t m, double floor_rel, double* eps, double* y_out);
+
+/* ------------------------------------------------------ basis_update */
+/* snaps: HOST array of nsnap DEVICE pointers to N-vectors, oldest first:
+ * gamma_{k-w}..gamma_k (nsnap = w + 1) or gamma_0..gamma_{w-1} (nsnap = w,
+ * the first update).  Centring state = mean of the first w snapshots (the
+ * lagged reference state psi_k); psi_out = mean of the last w (psi_{k+1},
+ * eq. mean).  Phi_out (N x m, column-major) = the first m_eff left singular
+ * vectors of X = [snap - centre] over the last w snapshots (eq. pod), with
+ * m_eff = #{i < m : sigma_i > tau_pod * sigma_0}; columns beyond m_eff are
+ * left untouched.  sigma_out gets all w singular values (descending).
+ * Sign: each right singular vector has its largest-magnitude entry positive.
+ * precision: HS_FP64 or HS_MIXED_FP32 (FP32 Gram + FP64 Rayleigh-Ritz refinement). */
+hs_status basis_update(hs_ctx* ctx, const double* const* snaps /* host */, int32_t nsnap, int32_t w,
+                       int32_t m, double tau_pod, int32_t precision,
+                       double* Phi_out, double* psi_out, double* sigma_out, int32_t* m_eff /* host */);
+
+/* --------------------------------------------------- rom_hybrid_step */
+typedef struct hs_hybrid_params {
+  double  eps_y;            /* subiteration tolerance (paper: 1e-4) */
+  int32_t jmax;             /* max subiterations (paper: 10) */
+  int32_t n_orders;         /* number of filter orders applied (0..4) */
+  int32_t filter_orders[4]; /* n of S_n = I - (-delta^2/4)^n: 1, 2, 3 = orders 2, 4, 6 */
+  double  eps_f;            /* filter stop tolerance on the relative l1 decrease (paper: 1e-2) */
+  int32_t jfmax;            /* max passes per filter order (paper: 10) */
+  double  rcond_fit;        /* pseudo-inverse cutoff relative to sigma_max (1e-6) */
+  double  floor_rel;        /* indicator floor (1e-11) */
+  int32_t precision;        /* HS_FP64 or HS_MIXED_FP32 (fit Gram/projections) */
+} hs_hybrid_params;
+
+/* One hybrid snapshot from q_prev = gamma_{k-1} with basis (Phi, psi; m
+ * columns) and the sampled sets s (eq. hybrid).  Writes gamma_k to q_out,
+ * the reduced coordinates y^(J) to y_out (m, may be NULL) and the indicator
+ * of the filtered snapshot to eps_out (ncell, may be NULL).
+ * Errors: HS_ERR_RANK (m = 0 or empty hat-S), HS_ERR_NOT_CONVERGED. */
+hs_status rom_hybrid_step(hs_ctx* ctx, const double* q_prev, const double* Phi, const double* psi,
+                          int32_t m, const hs_samples* s, const hs_hybrid_params* params /* host */,
+                          double* q_out, double* eps_out, double* y_out, hs_step_info* info /* host */);
+
+/* The residual-gated filter sequence alone (Sec. 2.3.4), on a full state. */
+hs_status hs_filter(hs_ctx* ctx, const double* gamma_in, const double* q_prev,
+                    const hs_hybrid_params* params /* host */, double* gamma_out, hs_step_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HSROM_H */

@@ -1,0 +1,281 @@
+"""ctypes binding of libhsrom.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module only converts torch
+tensors (float64 / int32 / uint8, contiguous, on the context's device) into
+pointers and checks status codes.  Importing it without a built library
+raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libhsrom.so")
+
+HS_OK = 0
+STATUS = {0: "HS_OK", -1: "HS_ERR_INVALID_ARG", -2: "HS_ERR_SHAPE", -3: "HS_ERR_NOT_CONVERGED",
+          -4: "HS_ERR_RANK", -5: "HS_ERR_NONFINITE", -6: "HS_ERR_HIP", -7: "HS_ERR_OOM"}
+HS_ERR_NOT_CONVERGED = -3
+HS_ERR_RANK = -4
+
+BURGERS_1D, BURGERS_2D, EULER_2D = 0, 1, 2
+RULE_FRACTION, RULE_RRE = 0, 1
+FP64, MIXED_FP32 = 0, 1
+
+
+class HsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("bc", ctypes.c_int32), ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+                ("dt", ctypes.c_double), ("gamma", ctypes.c_double), ("inflow", ctypes.c_double),
+                ("newton_rtol", ctypes.c_double), ("newton_maxit", ctypes.c_int32),
+                ("lin_rtol", ctypes.c_double), ("lin_maxit", ctypes.c_int32),
+                ("m_max", ctypes.c_int32), ("w_max", ctypes.c_int32)]
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [("newton_iters", ctypes.c_int32), ("lin_sweeps", ctypes.c_int32),
+                ("subiters", ctypes.c_int32), ("filter_passes", ctypes.c_int32),
+                ("filter_kept", ctypes.c_int32), ("n_s", ctypes.c_int32), ("l", ctypes.c_int32),
+                ("fit_rank", ctypes.c_int32), ("residual_inf", ctypes.c_double),
+                ("dy_last", ctypes.c_double), ("fit_cond", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SampleParams(ctypes.Structure):
+    _fields_ = [("rule", ctypes.c_int32), ("fraction", ctypes.c_double),
+                ("delta", ctypes.c_double), ("halo", ctypes.c_int32)]
+
+
+class HybridParams(ctypes.Structure):
+    _fields_ = [("eps_y", ctypes.c_double), ("jmax", ctypes.c_int32), ("n_orders", ctypes.c_int32),
+                ("filter_orders", ctypes.c_int32 * 4), ("eps_f", ctypes.c_double),
+                ("jfmax", ctypes.c_int32), ("rcond_fit", ctypes.c_double),
+                ("floor_rel", ctypes.c_double), ("precision", ctypes.c_int32)]
+
+
+def hybrid_params(eps_y=1e-4, jmax=10, filter_orders=(1, 2, 3), eps_f=1e-2, jfmax=10,
+                  rcond_fit=1e-6, floor_rel=1e-11, precision=FP64) -> HybridParams:
+    hp = HybridParams()
+    hp.eps_y, hp.jmax, hp.eps_f, hp.jfmax = eps_y, jmax, eps_f, jfmax
+    hp.rcond_fit, hp.floor_rel, hp.precision = rcond_fit, floor_rel, precision
+    hp.n_orders = len(filter_orders)
+    for i, o in enumerate(filter_orders):
+        hp.filter_orders[i] = o
+    return hp
+
+
+_lib = None
+P = ctypes.c_void_p
+I32 = ctypes.c_int32
+D = ctypes.c_double
+
+_SIGS = {
+    "hs_create": [ctypes.POINTER(Problem), P, ctypes.POINTER(P)],
+    "hs_destroy": [P],
+    "hs_sync": [P],
+    "hs_status_string": [I32],
+    "hs_last_error": [P],
+    "hs_residual": [P, P, P, P],
+    "hs_jvp": [P, P, P, P],
+    "hdm_step": [P, P, P, ctypes.POINTER(StepInfo)],
+    "hs_samples_create": [P, ctypes.POINTER(P)],
+    "hs_samples_destroy": [P],
+    "sample_select": [P, P, ctypes.POINTER(SampleParams), P],
+    "hs_samples_set": [P, P, P, I32],
+    "hs_samples_counts": [P, ctypes.POINTER(I32)],
+    "hs_samples_export": [P, P, P, P, P],
+    "hs_indicator_full": [P, P, P, P, I32, D, P, P],
+    "basis_update": [P, ctypes.POINTER(P), I32, I32, I32, D, I32, P, P, P, ctypes.POINTER(I32)],
+    "rom_hybrid_step": [P, P, P, P, I32, P, ctypes.POINTER(HybridParams), P, P, P,
+                        ctypes.POINTER(StepInfo)],
+    "hs_filter": [P, P, P, ctypes.POINTER(HybridParams), P, ctypes.POINTER(StepInfo)],
+}
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2301_01718_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_char_p if name in ("hs_status_string", "hs_last_error") else I32
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One problem on one device and stream.  Tensors are float64 (states),
+    int32 (cell lists) or uint8 (masks), contiguous, on ``device``."""
+
+    def __init__(self, prob, m_max=64, w_max=64, device="cuda", stream=None,
+                 newton_rtol=0.0, newton_maxit=0, lin_rtol=0.0, lin_maxit=0):
+        d = torch.device(device)
+        if d.type == "cuda" and d.index is None:
+            d = torch.device("cuda", torch.cuda.current_device())
+        self.device = d
+        self.prob = prob
+        p = Problem(kind=prob.kind, nx=prob.nx, ny=prob.ny, bc=prob.bc, dx=prob.dx, dy=prob.dy,
+                    dt=prob.dt, gamma=prob.gamma, inflow=prob.inflow, newton_rtol=newton_rtol,
+                    newton_maxit=newton_maxit, lin_rtol=lin_rtol, lin_maxit=lin_maxit,
+                    m_max=m_max, w_max=w_max)
+        self.ncomp = 4 if prob.kind == EULER_2D else 1
+        self.ncell = prob.nx * prob.ny
+        self.n = self.ncomp * self.ncell
+        with torch.cuda.device(self.device):
+            s = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.stream = s
+            h = P()
+            self._check(lib().hs_create(ctypes.byref(p), P(s.cuda_stream), ctypes.byref(h)), None)
+            self.h = h
+
+    def _check(self, st, h=None):
+        if st != HS_OK:
+            msg = lib().hs_last_error(h if h is not None else self.h)
+            raise HsError(st, (msg or b"").decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def empty(self, n=None, dtype=torch.float64):
+        return torch.empty(self.n if n is None else n, dtype=dtype, device=self.device)
+
+    def _in(self, t, n=None, dtype=torch.float64):
+        n = self.n if n is None else n
+        if t.dtype != dtype or not t.is_contiguous() or t.numel() != n or t.device != self.device:
+            raise ValueError(f"expected contiguous {dtype} tensor of {n} elements on {self.device}")
+        return t
+
+    def sync(self):
+        self._check(lib().hs_sync(self.h))
+
+    # ----------------------------------------------------------- kernels
+    def residual(self, q, q_prev, out=None):
+        out = self.empty() if out is None else out
+        self._check(lib().hs_residual(self.h, _ptr(self._in(q)), _ptr(self._in(q_prev)), _ptr(self._in(out))))
+        return out
+
+    def jvp(self, q, v, out=None):
+        out = self.empty() if out is None else out
+        self._check(lib().hs_jvp(self.h, _ptr(self._in(q)), _ptr(self._in(v)), _ptr(self._in(out))))
+        return out
+
+    def hdm_step(self, q_prev, out=None):
+        out = self.empty() if out is None else out
+        info = StepInfo()
+        self._check(lib().hdm_step(self.h, _ptr(self._in(q_prev)), _ptr(self._in(out)), ctypes.byref(info)))
+        return out, info.as_dict()
+
+    # ----------------------------------------------------------- sampling
+    def samples(self):
+        return Samples(self)
+
+    def sample_select(self, eps, fraction, halo=2, samples=None, rule=RULE_FRACTION, delta=0.9):
+        s = samples or Samples(self)
+        sp = SampleParams(rule=rule, fraction=fraction, delta=delta, halo=halo)
+        self._check(lib().sample_select(self.h, _ptr(self._in(eps, self.ncell)), ctypes.byref(sp), s.h))
+        return s
+
+    def samples_set(self, hat, samples=None):
+        s = samples or Samples(self)
+        hat = self._in(hat, hat.numel(), torch.int32)
+        self._check(lib().hs_samples_set(self.h, s.h, _ptr(hat) if hat.numel() else None, hat.numel()))
+        return s
+
+    def indicator_full(self, gamma, Phi, psi, m, floor_rel=1e-11, eps=None, y=None):
+        eps = self.empty(self.ncell) if eps is None else self._in(eps, self.ncell)
+        y = self.empty(m) if y is None else y
+        self._check(lib().hs_indicator_full(self.h, _ptr(self._in(gamma)), _ptr(Phi), _ptr(self._in(psi)), m,
+                                            floor_rel, _ptr(eps), _ptr(y)))
+        return eps, y
+
+    # ------------------------------------------------------------- basis
+    def basis_update(self, snaps, w, m, Phi_out, psi_out, sigma_out, tau_pod=1e-4, precision=FP64):
+        arr = (P * len(snaps))(*[P(self._in(s).data_ptr()) for s in snaps])
+        me = I32(0)
+        self._check(lib().basis_update(self.h, arr, len(snaps), w, m, tau_pod, precision, _ptr(Phi_out),
+                                       _ptr(self._in(psi_out)), _ptr(sigma_out), ctypes.byref(me)))
+        return me.value
+
+    # -------------------------------------------------------------- hybrid
+    def rom_hybrid_step(self, q_prev, Phi, psi, m, samples, params=None, out=None, eps=None, y=None):
+        params = params or hybrid_params()
+        out = self.empty() if out is None else out
+        info = StepInfo()
+        self._check(lib().rom_hybrid_step(self.h, _ptr(self._in(q_prev)), _ptr(Phi), _ptr(self._in(psi)), m,
+                                          samples.h, ctypes.byref(params), _ptr(self._in(out)),
+                                          _ptr(eps), _ptr(y), ctypes.byref(info)))
+        return out, info.as_dict()
+
+    def filter(self, gamma, q_prev, params=None, out=None):
+        params = params or hybrid_params()
+        out = self.empty() if out is None else out
+        info = StepInfo()
+        self._check(lib().hs_filter(self.h, _ptr(self._in(gamma)), _ptr(self._in(q_prev)), ctypes.byref(params),
+                                    _ptr(self._in(out)), ctypes.byref(info)))
+        return out, info.as_dict()
+
+
+class Samples:
+    """Library-owned sampled sets (hat-S, tilde-S, mask)."""
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+        h = P()
+        ctx._check(lib().hs_samples_create(ctx.h, ctypes.byref(h)))
+        self.h = h
+
+    def counts(self):
+        c = (I32 * 3)()
+        self.ctx._check(lib().hs_samples_counts(self.h, c))
+        return {"n_g": c[0], "n_s": c[1], "l": c[2]}
+
+    def export(self):
+        c = self.counts()
+        hat = torch.empty(max(c["n_s"], 1), dtype=torch.int32, device=self.ctx.device)
+        tilde = torch.empty(max(c["l"], 1), dtype=torch.int32, device=self.ctx.device)
+        mask = torch.empty(self.ctx.ncell, dtype=torch.uint8, device=self.ctx.device)
+        self.ctx._check(lib().hs_samples_export(self.ctx.h, self.h, _ptr(hat), _ptr(tilde), _ptr(mask)))
+        return hat[:c["n_s"]], tilde[:c["l"]], mask
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hs_samples_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,246 @@
+// Internal definitions shared by the HIP translation units of libhsrom.
+// Not part of the public interface (see include/hsrom.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "hsrom.h"
+
+namespace hs {
+
+constexpr int kBlock = 256;          // threads per block for streaming kernels
+constexpr int kWave = 64;            // CDNA wavefront width
+constexpr int kMaxBasis = 64;        // m_max, w_max limit (one workgroup small solves)
+constexpr int kRedBlocks = 1024;     // upper bound on blocks of a reduction pass
+
+// Problem geometry and constants passed by value to every kernel.
+struct Grid {
+  int nx, ny, ncell, nc, kind, bc;
+  double lx, ly, gamma, inflow;
+};
+
+// Small statistics slots (uint64 bit patterns of non-negative doubles, so an
+// integer atomicMax is an exact, order-independent maximum).
+enum StatSlot : int {
+  kStatResMax = 0,     // max |R|
+  kStatRho = 1,        // Jacobi contraction bound
+  kStatQMax = 2,       // max |q_prev|
+  kStatNonFinite = 3,  // != 0 if a non-finite residual was met
+  kStatCount = 4,      // generic integer counter
+  kStatDiff = 5,       // max |delta_new - delta_old| of a recorded sweep
+  kStatDnorm = 6,      // max |delta_new| of a recorded sweep
+  kStatSlots = 8
+};
+
+}  // namespace hs
+
+// ------------------------------------------------------------------ context
+struct hs_ctx {
+  hs_problem p{};
+  hs::Grid g{};
+  int nc = 1, ncell = 0, n = 0, nnb = 4;   // nnb: stencil neighbours per cell
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+
+  // device workspaces (allocated once at create)
+  double* u = nullptr;        // N  working state (hybrid step)
+  double* R = nullptr;        // N  residual / scratch
+  double* rhs = nullptr;      // N  Jacobi right-hand side b = -D^{-1} R
+  double* d0 = nullptr;       // N  Jacobi iterate
+  double* d1 = nullptr;       // N  Jacobi iterate
+  double* coef = nullptr;     // nnb * nc * nc * ncell : M_X = D^{-1} O_X
+  double* rho = nullptr;      // N  reconstruction psi + Phi y
+  double* gf = nullptr;       // N  filtered state
+  double* gtmp = nullptr;     // N  filter scratch / merged state
+  double* rcell = nullptr;    // ncell cell residual norms
+  double* rcell2 = nullptr;   // ncell cell residual norms
+  double* red = nullptr;      // reduction partials (kRedBlocks * 64 * 64 doubles)
+  double* small = nullptr;    // small dense matrices and vectors (16 * 64 * 64 doubles)
+  unsigned long long* stats = nullptr;   // kStatSlots
+  int* ibuf = nullptr;        // integer scratch (ncell + 1024)
+  void* hpin = nullptr;       // pinned host readback buffer (64 KiB)
+
+  hs_status fail(hs_status s, const std::string& msg) {
+    err = msg;
+    return s;
+  }
+};
+
+struct hs_samples {
+  hs_ctx* ctx = nullptr;
+  int ncell = 0;
+  int n_g = 0, n_s = 0, l = 0;
+  uint8_t* gmask = nullptr;   // ncell, G
+  uint8_t* mask = nullptr;    // ncell, hat-S
+  uint8_t* tmask = nullptr;   // ncell, tilde-S
+  uint8_t* dtmp = nullptr;    // ncell, dilation scratch
+  int32_t* hat = nullptr;     // ncell capacity, sorted hat-S cells
+  int32_t* tilde = nullptr;   // ncell capacity, sorted tilde-S cells
+  int32_t* pos = nullptr;     // ncell, compact index of a hat-S cell or -1
+  int32_t* nbr = nullptr;     // 4 * ncell, compact index of each stencil neighbour in hat-S or -1
+  int32_t* scan = nullptr;    // scan scratch
+};
+
+// ----------------------------------------------------------------- helpers
+#define HS_TRY(expr)                     \
+  do {                                   \
+    hs_status _s = (expr);               \
+    if (_s != HS_OK) return _s;          \
+  } while (0)
+
+#define HIP_TRY(ctx, expr)                                                            \
+  do {                                                                                \
+    hipError_t _e = (expr);                                                           \
+    if (_e != hipSuccess)                                                             \
+      return (ctx)->fail(HS_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+#define HS_LAUNCH(ctx, kernel, grid, block, ...)                                        \
+  do {                                                                                  \
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, (ctx)->stream, __VA_ARGS__); \
+    hipError_t _e = hipGetLastError();                                                  \
+    if (_e != hipSuccess)                                                               \
+      return (ctx)->fail(HS_ERR_HIP, std::string("launch " #kernel ": ") + hipGetErrorString(_e)); \
+  } while (0)
+
+namespace hs {
+
+inline int blocks_for(long long n, int per_block = kBlock, int cap = 1 << 30) {
+  long long b = (n + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return static_cast<int>(b);
+}
+
+inline double bits_to_double(unsigned long long b) {
+  double d;
+  static_assert(sizeof(d) == sizeof(b), "");
+  __builtin_memcpy(&d, &b, sizeof d);
+  return d;
+}
+
+// ------------------------------------------------------- device utilities
+__device__ inline unsigned long long dbits(double d) { return __double_as_longlong(d); }
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+__device__ inline int wave_sum_int(int v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Block-wide sum with a fixed tree (deterministic for a fixed block size).
+// The result is valid in thread 0.  lds needs blockDim.x / 64 doubles.
+__device__ inline double block_sum(double v, double* lds) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  const int nw = blockDim.x / kWave;
+  if (l == 0) lds[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (w == 0) {
+    r = (l < nw) ? lds[l] : 0.0;
+    r = wave_sum(r);
+  }
+  __syncthreads();
+  return r;
+}
+
+__device__ inline double block_max(double v, double* lds) {
+  v = wave_max(v);
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  const int nw = blockDim.x / kWave;
+  if (l == 0) lds[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (w == 0) {
+    r = (l < nw) ? lds[l] : 0.0;
+    r = wave_max(r);
+  }
+  __syncthreads();
+  return r;
+}
+
+__device__ inline int block_sum_int(int v, int* lds) {
+  v = wave_sum_int(v);
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  const int nw = blockDim.x / kWave;
+  if (l == 0) lds[w] = v;
+  __syncthreads();
+  int r = 0;
+  if (w == 0) {
+    r = (l < nw) ? lds[l] : 0;
+    r = wave_sum_int(r);
+  }
+  __syncthreads();
+  return r;
+}
+
+// Record max(|x|) of non-negative x into a stats slot.
+__device__ inline void stat_max(unsigned long long* slot, double x) {
+  atomicMax(slot, dbits(x));
+}
+
+// ---------------------------------------------------------- grid helpers
+// Neighbour of cell (i, j) across a face.  dir: 0 = W, 1 = E, 2 = S, 3 = N.
+// Returns the neighbour cell, the cell itself for a zeroth-order-extrapolation
+// ghost, or -1 for the constant inflow ghost (1D left boundary).
+__device__ inline int neighbour(const Grid& g, int i, int j, int dir) {
+  const bool per = g.bc == HS_BC_PERIODIC;
+  if (dir < 2) {
+    int ii = dir == 0 ? i - 1 : i + 1;
+    if (ii < 0) {
+      if (per) ii = g.nx - 1;
+      else if (g.bc == HS_BC_INFLOW_OUTFLOW) return -1;
+      else ii = 0;
+    } else if (ii >= g.nx) {
+      ii = per ? 0 : g.nx - 1;
+    }
+    return ii + g.nx * j;
+  }
+  int jj = dir == 2 ? j - 1 : j + 1;
+  if (jj < 0) jj = per ? g.ny - 1 : 0;
+  else if (jj >= g.ny) jj = per ? 0 : g.ny - 1;
+  return i + g.nx * jj;
+}
+
+// Whether the neighbour across face dir is a distinct real cell (its state is
+// an independent unknown) rather than a ghost that copies the cell itself.
+__device__ inline bool neighbour_is_other(const Grid& g, int cell, int nb) {
+  return nb >= 0 && nb != cell;
+}
+
+}  // namespace hs
+
+// ------------------------------------------ cross-translation-unit internals
+namespace hs {
+hs_status readback(hs_ctx* ctx, const void* dsrc, size_t bytes, void* hdst);
+hs_status zero_stats(hs_ctx* ctx);
+hs_status read_stats(hs_ctx* ctx, unsigned long long* out /* kStatSlots */);
+hs_status max_abs(hs_ctx* ctx, const double* x, long long n, double* out);
+// Newton on the full mesh (hat == nullptr) or on a compact cell list.
+hs_status newton_solve(hs_ctx* ctx, double* q, const double* q_prev, double tol,
+                       const hs_samples* s, hs_step_info* info);
+hs_status cell_residual_norm(hs_ctx* ctx, const double* q, const double* q_prev, double* rcell,
+                             double* sum_out);
+hs_status run_filter(hs_ctx* ctx, double* gamma, const double* q_prev, const hs_hybrid_params* hp,
+                     hs_step_info* info);
+}  // namespace hs

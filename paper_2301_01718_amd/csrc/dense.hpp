@@ -1,0 +1,189 @@
+// Tall-skinny dense kernels on FP64 MFMA (v_mfma_f64_16x16x4f64) and the
+// one-wave symmetric Jacobi eigensolver used for the small (<= 64 x 64)
+// problems of the basis update and of the gappy fit.
+//
+// MFMA operand layout (16x16x4, wave64): lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16]; accumulator element i of lane l is
+// C[l / 16 + 4 i][l % 16] (measured on gfx950 with a known product).
+#pragma once
+
+#include "common.hpp"
+
+namespace hs {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline double4_t mfma_f64(double a, double b, double4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int kChunk = 64;   // rows staged per LDS chunk
+
+// Gram G = X^T X of a tall matrix whose rows are produced by a Loader into
+// LDS (kChunk rows x ldx, zero padded), accumulated over all chunks of this
+// block; the block's partial wp x wp matrix goes to part[blockIdx.x].
+//   Loader::load(chunk_row0, X /*LDS kChunk x ldx*/) fills the rows.
+// Block: 256 threads = 4 waves; wave v owns tiles t = v, v + 4, ... of the
+// (wp/16)^2 output tiles.
+template <class Loader>
+__global__ void __launch_bounds__(256) gram_kernel(Loader ld, long long nrows, int wp,
+                                                   double* __restrict__ part) {
+  extern __shared__ double X[];   // kChunk x (wp + 1)
+  const int ldx = wp + 1;
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int nt = wp / 16;
+  const int ntiles = nt * nt;
+  double4_t acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  const long long nchunks = (nrows + kChunk - 1) / kChunk;
+  for (long long ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    __syncthreads();
+    ld.load(ch * kChunk, X, ldx, wp);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int tile = wave + 4 * t;
+      if (tile >= ntiles) break;
+      const int ti = tile / nt, tj = tile % nt;
+#pragma unroll 4
+      for (int k0 = 0; k0 < kChunk; k0 += 4) {
+        const int k = k0 + lane / 16;
+        const double a = X[k * ldx + ti * 16 + lane % 16];   // A = X^T: A[r][k] = X[k][ti*16 + r]
+        const double b = X[k * ldx + tj * 16 + lane % 16];   // B[k][c] = X[k][tj*16 + c]
+        acc[t] = mfma_f64(a, b, acc[t]);
+      }
+    }
+  }
+  double* out = part + (size_t)blockIdx.x * wp * wp;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int tile = wave + 4 * t;
+    if (tile >= ntiles) break;
+    const int ti = tile / nt, tj = tile % nt;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = ti * 16 + lane / 16 + 4 * i, c = tj * 16 + lane % 16;
+      out[r * wp + c] = acc[t][i];
+    }
+  }
+}
+
+// Sum nb partial wp x wp matrices in block order; write the w x w result
+// (row-major, leading dimension w) to G.
+static __global__ void gram_reduce_kernel(const double* __restrict__ part, int nb, int wp, int w,
+                                   double* __restrict__ G) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= w * w) return;
+  const int r = e / w, c = e % w;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += part[(size_t)b * wp * wp + r * wp + c];
+  G[e] = s;
+}
+
+// ---------------------------------------------------------------- Jacobi
+// Symmetric eigendecomposition A = V diag(lam) V^T of an n x n matrix (n <= 64)
+// by cyclic Jacobi with round-robin parallel ordering, one wave.  On return
+// lam is sorted in descending order with V's columns permuted alike.
+// A (n x n, row-major) is overwritten.  LDS: A, V (64 x 65 each).
+__device__ inline void jacobi_eig_wave(double* A, double* V, int lda, int n, double* lam, int* order,
+                                       int max_sweeps) {
+  const int t = threadIdx.x;   // 0..63
+  for (int i = t; i < n * lda; i += kWave) V[i] = 0.0;
+  __syncthreads();
+  if (t < n) V[t * lda + t] = 1.0;
+  __syncthreads();
+  const int np = (n + 1) & ~1;     // even number of players
+  __shared__ double cs[32], sn[32];
+  __shared__ int pp[32], qq[32];
+  __shared__ int rotated;
+  __shared__ double atol;
+  if (t == 0) {
+    double dmax = 0.0;
+    for (int i = 0; i < n; ++i) dmax = fmax(dmax, fabs(A[i * lda + i]));
+    atol = 1e-18 * dmax;       // below this an off-diagonal entry cannot move any eigenvalue
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    if (t == 0) rotated = 0;
+    __syncthreads();
+    for (int r = 0; r < np - 1; ++r) {
+      if (t < np / 2) {
+        int p, q;
+        if (t == 0) {
+          p = r % (np - 1);
+          q = np - 1;
+        } else {
+          p = (r + t) % (np - 1);
+          q = (r - t + (np - 1)) % (np - 1);
+        }
+        if (p > q) { const int x = p; p = q; q = x; }
+        double c = 1.0, s = 0.0;
+        if (q < n) {
+          const double apq = A[p * lda + q];
+          const double app = A[p * lda + p], aqq = A[q * lda + q];
+          if (fabs(apq) > atol && fabs(apq) > 0.25 * 2.2e-16 * sqrt(fabs(app) * fabs(aqq))) {
+            const double tau = (aqq - app) / (2.0 * apq);
+            const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            s = tt * c;
+            rotated = 1;
+          }
+        }
+        pp[t] = p; qq[t] = q; cs[t] = c; sn[t] = s;
+      }
+      __syncthreads();
+      // rows: A <- J^T A
+      for (int e = t; e < (np / 2) * n; e += kWave) {
+        const int k = e / n, col = e % n;
+        const int p = pp[k], q = qq[k];
+        if (q >= n || sn[k] == 0.0) continue;
+        const double c = cs[k], s = sn[k];
+        const double ap = A[p * lda + col], aq = A[q * lda + col];
+        A[p * lda + col] = c * ap - s * aq;
+        A[q * lda + col] = s * ap + c * aq;
+      }
+      __syncthreads();
+      // columns: A <- A J and V <- V J
+      for (int e = t; e < (np / 2) * n; e += kWave) {
+        const int k = e / n, row = e % n;
+        const int p = pp[k], q = qq[k];
+        if (q >= n || sn[k] == 0.0) continue;
+        const double c = cs[k], s = sn[k];
+        const double ap = A[row * lda + p], aq = A[row * lda + q];
+        A[row * lda + p] = c * ap - s * aq;
+        A[row * lda + q] = s * ap + c * aq;
+        const double vp = V[row * lda + p], vq = V[row * lda + q];
+        V[row * lda + p] = c * vp - s * vq;
+        V[row * lda + q] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+    if (!rotated) break;
+    __syncthreads();
+  }
+  if (t == 0) {
+    for (int i = 0; i < n; ++i) {
+      lam[i] = A[i * lda + i];
+      order[i] = i;
+    }
+    for (int i = 0; i < n; ++i) {        // stable selection sort, descending
+      int b = i;
+      for (int j = i + 1; j < n; ++j)
+        if (lam[j] > lam[b]) b = j;
+      if (b != i) {
+        const double x = lam[b];
+        const int o = order[b];
+        for (int j = b; j > i; --j) {
+          lam[j] = lam[j - 1];
+          order[j] = order[j - 1];
+        }
+        lam[i] = x;
+        order[i] = o;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace hs

@@ -1,0 +1,545 @@
+// Full-order model: context lifetime, residual (A1), Jacobian products (A2)
+// and the Newton solve (A3) of the backward-Euler HDM (eq. hdm), on the full
+// mesh or restricted to a compact list of sampled cells (eq. partial_hdm2).
+//
+// Linear systems are solved by (block-)Jacobi relaxation: per cell the
+// iteration is delta <- b - sum_X M_X delta[X] with M_X = D^{-1} O_X and
+// b = -D^{-1} R.  The residual/Jacobian kernel also returns the contraction
+// bound rho = max_cells max_rows sum |M_X|.  When rho < 1 the sweep count
+// ceil(log(lin_rtol) / log(rho)) guarantees the requested accuracy of each
+// Newton correction in the max norm without any reduction inside the sweeps
+// (the scalar Burgers systems).  Otherwise (Euler, whose components have very
+// different scales, so the max-norm bound is loose although the iteration
+// contracts) the sweeps run in batches and stop on the fixed-point difference.
+#include "physics.hpp"
+
+#include <algorithm>
+#include <cstring>
+
+namespace hs {
+
+// ----------------------------------------------------------- small kernels
+__global__ void fill_u64_kernel(unsigned long long* p, int n, unsigned long long v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void max_abs_kernel(const double* __restrict__ x, long long n, unsigned long long* slot) {
+  __shared__ double lds[kBlock / kWave];
+  double m = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    m = fmax(m, fabs(x[i]));
+  m = block_max(m, lds);
+  if (threadIdx.x == 0) stat_max(slot, m);
+}
+
+hs_status readback(hs_ctx* ctx, const void* dsrc, size_t bytes, void* hdst) {
+  if (bytes > 65536) return ctx->fail(HS_ERR_INVALID_ARG, "readback too large");
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->hpin, dsrc, bytes, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  std::memcpy(hdst, ctx->hpin, bytes);
+  return HS_OK;
+}
+
+hs_status zero_stats(hs_ctx* ctx) {
+  HS_LAUNCH(ctx, fill_u64_kernel, 1, 64, ctx->stats, (int)kStatSlots, 0ull);
+  return HS_OK;
+}
+
+hs_status read_stats(hs_ctx* ctx, unsigned long long* out) {
+  return readback(ctx, ctx->stats, kStatSlots * sizeof(unsigned long long), out);
+}
+
+hs_status max_abs(hs_ctx* ctx, const double* x, long long n, double* out) {
+  HS_TRY(zero_stats(ctx));
+  HS_LAUNCH(ctx, max_abs_kernel, blocks_for(n, kBlock, 1024), kBlock, x, n, ctx->stats + kStatQMax);
+  unsigned long long st[kStatSlots];
+  HS_TRY(read_stats(ctx, st));
+  *out = bits_to_double(st[kStatQMax]);
+  return HS_OK;
+}
+
+// ------------------------------------------------------------ dense blocks
+// Inverse of a small row-major NC x NC matrix (Gauss-Jordan, partial pivoting).
+template <int NC>
+__device__ inline void small_inverse(const double A[NC * NC], double X[NC * NC]) {
+  if constexpr (NC == 1) {
+    X[0] = 1.0 / A[0];
+  } else {
+    double M[NC][2 * NC];
+#pragma unroll
+    for (int r = 0; r < NC; ++r)
+#pragma unroll
+      for (int c = 0; c < 2 * NC; ++c) M[r][c] = c < NC ? A[r * NC + c] : (c - NC == r ? 1.0 : 0.0);
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      int piv = k;
+      double best = fabs(M[k][k]);
+#pragma unroll
+      for (int r = k + 1; r < NC; ++r)
+        if (fabs(M[r][k]) > best) { best = fabs(M[r][k]); piv = r; }
+#pragma unroll
+      for (int c = 0; c < 2 * NC; ++c) {   // swap rows k and piv
+        const double t = M[k][c];
+        M[k][c] = M[piv][c];
+        M[piv][c] = t;
+      }
+      const double inv = 1.0 / M[k][k];
+#pragma unroll
+      for (int c = 0; c < 2 * NC; ++c) M[k][c] *= inv;
+#pragma unroll
+      for (int r = 0; r < NC; ++r) {
+        if (r == k) continue;
+        const double f = M[r][k];
+#pragma unroll
+        for (int c = 0; c < 2 * NC; ++c) M[r][c] -= f * M[k][c];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NC; ++r)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) X[r * NC + c] = M[r][NC + c];
+  }
+}
+
+// --------------------------------------------------------- residual kernel
+template <int NC>
+__global__ void residual_kernel(Grid g, const double* __restrict__ q, const double* __restrict__ qp,
+                                double* __restrict__ R) {
+  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= g.ncell) return;
+  Stencil<NC> st;
+  load_stencil<NC>(g, q, cell, st);
+  double p[NC], r[NC];
+#pragma unroll
+  for (int a = 0; a < NC; ++a) p[a] = qp[a * g.ncell + cell];
+  cell_residual<NC>(g, st, p, r);
+#pragma unroll
+  for (int a = 0; a < NC; ++a) R[a * g.ncell + cell] = r[a];
+}
+
+// out = J(q) v
+template <int NC>
+__global__ void jvp_kernel(Grid g, const double* __restrict__ q, const double* __restrict__ v,
+                           double* __restrict__ out) {
+  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= g.ncell) return;
+  Stencil<NC> st;
+  load_stencil<NC>(g, q, cell, st);
+  double D[NC * NC], O[4][NC * NC];
+  cell_jacobian<NC>(g, st, D, O);
+  double acc[NC];
+#pragma unroll
+  for (int a = 0; a < NC; ++a) {
+    double s = 0.0;
+#pragma unroll
+    for (int b = 0; b < NC; ++b) s += D[a * NC + b] * v[b * g.ncell + cell];
+    acc[a] = s;
+  }
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const int nb = st.idx[d];
+    if (nb < 0 || nb == cell) continue;
+#pragma unroll
+    for (int a = 0; a < NC; ++a)
+#pragma unroll
+      for (int b = 0; b < NC; ++b) acc[a] += O[d][a * NC + b] * v[b * g.ncell + nb];
+  }
+#pragma unroll
+  for (int a = 0; a < NC; ++a) out[a * g.ncell + cell] = acc[a];
+}
+
+// Residual + Jacobi iteration data on the full mesh (hat == nullptr) or on the
+// compact list hat[0..count) whose in-set neighbours are nbr[d * cap + p].
+template <int NC>
+__global__ void resjac_kernel(Grid g, const double* __restrict__ q, const double* __restrict__ qp,
+                              const int* __restrict__ hat, const int* __restrict__ nbr, int count,
+                              int cap, double* __restrict__ coef, double* __restrict__ rhs,
+                              unsigned long long* __restrict__ stats) {
+  __shared__ double lds[kBlock / kWave];
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  double rmax = 0.0, rho = 0.0;
+  bool bad = false;
+  if (p < count) {
+    const int cell = hat ? hat[p] : p;
+    Stencil<NC> st;
+    load_stencil<NC>(g, q, cell, st);
+    double pv[NC], R[NC];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) pv[a] = qp[a * g.ncell + cell];
+    cell_residual<NC>(g, st, pv, R);
+    double D[NC * NC], O[4][NC * NC];
+    cell_jacobian<NC>(g, st, D, O);
+    if (hat) {
+#pragma unroll
+      for (int d = 0; d < 4; ++d)
+        if (nbr[d * cap + p] < 0)
+#pragma unroll
+          for (int e = 0; e < NC * NC; ++e) O[d][e] = 0.0;   // fixed (tilde-S) or ghost value
+    }
+    double Di[NC * NC];
+    small_inverse<NC>(D, Di);
+    double rowsum[NC];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      rmax = fmax(rmax, fabs(R[a]));
+      bad |= !isfinite(R[a]);
+      double b = 0.0;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) b -= Di[a * NC + c] * R[c];
+      rhs[a * cap + p] = b;
+      rowsum[a] = 0.0;
+    }
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+#pragma unroll
+      for (int a = 0; a < NC; ++a)
+#pragma unroll
+        for (int b = 0; b < NC; ++b) {
+          double m = 0.0;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) m += Di[a * NC + c] * O[d][c * NC + b];
+          coef[((d * NC + a) * NC + b) * (size_t)cap + p] = m;
+          rowsum[a] += fabs(m);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < NC; ++a) rho = fmax(rho, rowsum[a]);
+    if (!isfinite(rho)) bad = true;
+  }
+  rmax = block_max(bad ? INFINITY : rmax, lds);
+  rho = block_max(rho, lds);
+  if (threadIdx.x == 0) {
+    stat_max(&stats[kStatResMax], rmax);
+    stat_max(&stats[kStatRho], rho);
+    if (!isfinite(rmax)) atomicMax(&stats[kStatNonFinite], 1ull);
+  }
+}
+
+// One Jacobi sweep: dnew = b - sum_X M_X dold[X]; with FINAL, q[cell] += dnew.
+// With RECORD, max |dnew - dold| and max |dnew| go to the stats slots.
+template <int NC, bool FINAL, bool RECORD>
+__global__ void sweep_kernel(Grid g, const int* __restrict__ hat, const int* __restrict__ nbr, int count,
+                             int cap, const double* __restrict__ coef, const double* __restrict__ rhs,
+                             const double* __restrict__ dold, double* __restrict__ dnew,
+                             double* __restrict__ q, unsigned long long* __restrict__ stats) {
+  __shared__ double lds[kBlock / kWave];
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  double diff = 0.0, dn = 0.0;
+  if (p < count) {
+    const int ndir = g.kind == HS_BURGERS_1D ? 2 : 4;
+    double acc[NC];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) acc[a] = rhs[a * cap + p];
+    int i = 0, j = 0, cell = p;
+    if (hat) cell = hat[p];
+    else { i = p % g.nx; j = p / g.nx; }
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      if (d >= ndir) break;
+      int nb;
+      if (hat) {
+        nb = nbr[d * cap + p];
+        if (nb < 0) continue;
+      } else {
+        nb = neighbour(g, i, j, d);
+        if (nb < 0 || nb == cell) continue;
+      }
+#pragma unroll
+      for (int a = 0; a < NC; ++a)
+#pragma unroll
+        for (int b = 0; b < NC; ++b)
+          acc[a] -= coef[((d * NC + a) * NC + b) * (size_t)cap + p] * dold[b * cap + nb];
+    }
+    if (FINAL) {
+#pragma unroll
+      for (int a = 0; a < NC; ++a) q[a * g.ncell + cell] += acc[a];
+    } else {
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        dnew[a * cap + p] = acc[a];
+        if (RECORD) {
+          diff = fmax(diff, fabs(acc[a] - dold[a * cap + p]));
+          dn = fmax(dn, fabs(acc[a]));
+        }
+      }
+    }
+  }
+  if (RECORD) {
+    diff = block_max(diff, lds);
+    dn = block_max(dn, lds);
+    if (threadIdx.x == 0) {
+      stat_max(&stats[kStatDiff], diff);
+      stat_max(&stats[kStatDnorm], dn);
+    }
+  }
+}
+
+template <int NC>
+__global__ void add_update_kernel(Grid g, const int* __restrict__ hat, int count, int cap,
+                                  const double* __restrict__ d, double* __restrict__ q) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= count) return;
+  const int cell = hat ? hat[p] : p;
+#pragma unroll
+  for (int a = 0; a < NC; ++a) q[a * g.ncell + cell] += d[a * cap + p];
+}
+
+// ------------------------------------------------------------ Newton solve
+template <int NC>
+static hs_status newton_impl(hs_ctx* ctx, double* q, const double* q_prev, double tol,
+                             const hs_samples* s, hs_step_info* info) {
+  const Grid& g = ctx->g;
+  const int* hat = s ? s->hat : nullptr;
+  const int* nbr = s ? s->nbr : nullptr;
+  const int count = s ? s->n_s : ctx->ncell;
+  const int cap = ctx->ncell;
+  const int maxit = ctx->p.newton_maxit;
+  const double lin_rtol = ctx->p.lin_rtol;
+  const int nb = blocks_for(count);
+  int sweeps_total = 0;
+  for (int it = 0;; ++it) {
+    HS_TRY(zero_stats(ctx));
+    HS_LAUNCH(ctx, resjac_kernel<NC>, nb, kBlock, g, q, q_prev, hat, nbr, count, cap, ctx->coef,
+              ctx->rhs, ctx->stats);
+    unsigned long long st[kStatSlots];
+    HS_TRY(read_stats(ctx, st));
+    const double rmax = bits_to_double(st[kStatResMax]);
+    const double rho = bits_to_double(st[kStatRho]);
+    if (st[kStatNonFinite] || !std::isfinite(rmax))
+      return ctx->fail(HS_ERR_NONFINITE, "non-finite residual in Newton solve");
+    if (info) {
+      info->residual_inf = rmax;
+    }
+    if (rmax <= tol) {
+      if (info) {
+        info->newton_iters += it;
+        info->lin_sweeps += sweeps_total;
+      }
+      return HS_OK;
+    }
+    if (it >= maxit) {
+      char msg[160];
+      std::snprintf(msg, sizeof msg, "Newton: ||R||_inf = %.3e > %.3e after %d iterations", rmax, tol, it);
+      return ctx->fail(HS_ERR_NOT_CONVERGED, msg);
+    }
+    if (!std::isfinite(rho)) return ctx->fail(HS_ERR_NONFINITE, "non-finite Jacobian");
+    if (rho < 1.0) {
+      // fixed sweep count from the contraction bound: rho^nsw <= lin_rtol
+      int nsw = 1;
+      if (rho > 0.0) nsw = (int)std::ceil(std::log(lin_rtol) / std::log(rho));
+      nsw = std::max(1, std::min(nsw, ctx->p.lin_maxit));
+      sweeps_total += nsw;
+      if (nsw == 1) {
+        HS_LAUNCH(ctx, add_update_kernel<NC>, nb, kBlock, g, hat, count, cap, ctx->rhs, q);
+      } else {
+        const double* dold = ctx->rhs;
+        double* bufs[2] = {ctx->d0, ctx->d1};
+        for (int k = 2; k <= nsw; ++k) {
+          double* dnew = bufs[k & 1];
+          if (k == nsw)
+            HS_LAUNCH(ctx, (sweep_kernel<NC, true, false>), nb, kBlock, g, hat, nbr, count, cap, ctx->coef,
+                      ctx->rhs, dold, dnew, q, ctx->stats);
+          else
+            HS_LAUNCH(ctx, (sweep_kernel<NC, false, false>), nb, kBlock, g, hat, nbr, count, cap, ctx->coef,
+                      ctx->rhs, dold, dnew, q, ctx->stats);
+          dold = dnew;
+        }
+      }
+    } else {
+      // The max-norm bound does not prove contraction (components of very
+      // different scales): relax in batches and stop on the fixed-point
+      // difference, with the contraction factor estimated from successive
+      // batches (error <= r/(1-r) * ||delta_{k+1} - delta_k||).
+      constexpr int kBatch = 8;
+      const double* dold = ctx->rhs;
+      double* bufs[2] = {ctx->d0, ctx->d1};
+      int k = 1;
+      double prev_diff = -1.0, rate = 0.9;
+      bool conv = false;
+      while (k < ctx->p.lin_maxit) {
+        for (int b = 0; b < kBatch && k < ctx->p.lin_maxit; ++b, ++k) {
+          double* dnew = bufs[k & 1];
+          const bool rec = b == kBatch - 1 || k == ctx->p.lin_maxit - 1;
+          if (rec) {
+            HS_TRY(zero_stats(ctx));
+            HS_LAUNCH(ctx, (sweep_kernel<NC, false, true>), nb, kBlock, g, hat, nbr, count, cap, ctx->coef,
+                      ctx->rhs, dold, dnew, q, ctx->stats);
+          } else {
+            HS_LAUNCH(ctx, (sweep_kernel<NC, false, false>), nb, kBlock, g, hat, nbr, count, cap, ctx->coef,
+                      ctx->rhs, dold, dnew, q, ctx->stats);
+          }
+          dold = dnew;
+        }
+        unsigned long long s2[kStatSlots];
+        HS_TRY(read_stats(ctx, s2));
+        const double diff = bits_to_double(s2[kStatDiff]);
+        const double dn = bits_to_double(s2[kStatDnorm]);
+        if (!std::isfinite(diff)) return ctx->fail(HS_ERR_NONFINITE, "non-finite relaxation iterate");
+        if (prev_diff > 0.0 && diff > 0.0)
+          rate = std::min(0.99, std::pow(diff / prev_diff, 1.0 / kBatch));
+        prev_diff = diff;
+        if (diff == 0.0 || (rate < 1.0 && rate / (1.0 - rate) * diff <= lin_rtol * dn)) {
+          conv = true;
+          break;
+        }
+      }
+      sweeps_total += k;
+      if (!conv) return ctx->fail(HS_ERR_NOT_CONVERGED, "block-Jacobi relaxation did not converge");
+      HS_LAUNCH(ctx, add_update_kernel<NC>, nb, kBlock, g, hat, count, cap, dold, q);
+    }
+  }
+}
+
+hs_status newton_solve(hs_ctx* ctx, double* q, const double* q_prev, double tol, const hs_samples* s,
+                       hs_step_info* info) {
+  if (s && s->n_s == 0) return HS_OK;
+  if (ctx->nc == 1) return newton_impl<1>(ctx, q, q_prev, tol, s, info);
+  return newton_impl<4>(ctx, q, q_prev, tol, s, info);
+}
+
+}  // namespace hs
+
+using namespace hs;
+
+// ================================================================ C ABI
+extern "C" {
+
+const char* hs_status_string(hs_status s) {
+  switch (s) {
+    case HS_OK: return "ok";
+    case HS_ERR_INVALID_ARG: return "invalid argument";
+    case HS_ERR_SHAPE: return "shape beyond capacity";
+    case HS_ERR_NOT_CONVERGED: return "not converged";
+    case HS_ERR_RANK: return "rank deficient";
+    case HS_ERR_NONFINITE: return "non-finite value";
+    case HS_ERR_HIP: return "HIP runtime error";
+    case HS_ERR_OOM: return "out of device memory";
+    default: return "unknown status";
+  }
+}
+
+const char* hs_last_error(const hs_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+static hs_status alloc(hs_ctx* ctx, void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes < 256 ? 256 : bytes);
+  if (e != hipSuccess) return ctx->fail(HS_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  return HS_OK;
+}
+
+hs_status hs_destroy(hs_ctx* ctx) {
+  if (!ctx) return HS_ERR_INVALID_ARG;
+  void* bufs[] = {ctx->u,    ctx->R,     ctx->rhs,    ctx->d0,  ctx->d1,    ctx->coef, ctx->rho,
+                  ctx->gf,   ctx->gtmp,  ctx->rcell,  ctx->rcell2, ctx->red, ctx->small, ctx->stats,
+                  ctx->ibuf};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  if (ctx->hpin) (void)hipHostFree(ctx->hpin);
+  delete ctx;
+  return HS_OK;
+}
+
+hs_status hs_create(const hs_problem* pr, void* stream, hs_ctx** out) {
+  if (!pr || !out) return HS_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (pr->kind < HS_BURGERS_1D || pr->kind > HS_EULER_2D) return HS_ERR_INVALID_ARG;
+  if (pr->bc < HS_BC_INFLOW_OUTFLOW || pr->bc > HS_BC_TRANSMISSIVE) return HS_ERR_INVALID_ARG;
+  if (pr->nx < 1 || pr->ny < 1 || (pr->kind == HS_BURGERS_1D && pr->ny != 1)) return HS_ERR_INVALID_ARG;
+  if (pr->bc == HS_BC_INFLOW_OUTFLOW && pr->kind != HS_BURGERS_1D) return HS_ERR_INVALID_ARG;
+  if (!(pr->dx > 0) || !(pr->dt > 0) || (pr->kind != HS_BURGERS_1D && !(pr->dy > 0))) return HS_ERR_INVALID_ARG;
+  if (pr->m_max < 1 || pr->m_max > kMaxBasis || pr->w_max < 1 || pr->w_max > kMaxBasis) return HS_ERR_INVALID_ARG;
+  if ((long long)pr->nx * pr->ny > (1ll << 28)) return HS_ERR_SHAPE;
+
+  hs_ctx* ctx = new hs_ctx();
+  ctx->p = *pr;
+  if (ctx->p.newton_rtol <= 0) ctx->p.newton_rtol = 1e-13;
+  if (ctx->p.newton_maxit <= 0) ctx->p.newton_maxit = 30;
+  if (ctx->p.lin_rtol <= 0 || ctx->p.lin_rtol >= 1) ctx->p.lin_rtol = 1e-10;
+  if (ctx->p.lin_maxit <= 0) ctx->p.lin_maxit = 400;
+  ctx->stream = static_cast<hipStream_t>(stream);
+  (void)hipGetDevice(&ctx->device);
+  ctx->nc = pr->kind == HS_EULER_2D ? 4 : 1;
+  ctx->ncell = pr->nx * pr->ny;
+  ctx->n = ctx->nc * ctx->ncell;
+  ctx->nnb = 4;
+  Grid& g = ctx->g;
+  g.nx = pr->nx;
+  g.ny = pr->ny;
+  g.ncell = ctx->ncell;
+  g.nc = ctx->nc;
+  g.kind = pr->kind;
+  g.bc = pr->bc;
+  g.lx = pr->dt / pr->dx;
+  g.ly = pr->kind == HS_BURGERS_1D ? 0.0 : pr->dt / pr->dy;
+  g.gamma = pr->gamma;
+  g.inflow = pr->inflow;
+
+  const size_t N = ctx->n, NC = ctx->ncell, nc = ctx->nc;
+  hs_status st = HS_OK;
+  auto A = [&](void** p, size_t bytes) {
+    if (st == HS_OK) st = alloc(ctx, p, bytes);
+  };
+  A((void**)&ctx->u, N * 8);
+  A((void**)&ctx->R, N * 8);
+  A((void**)&ctx->rhs, N * 8);
+  A((void**)&ctx->d0, N * 8);
+  A((void**)&ctx->d1, N * 8);
+  A((void**)&ctx->coef, 4 * nc * nc * NC * 8);
+  A((void**)&ctx->rho, N * 8);
+  A((void**)&ctx->gf, N * 8);
+  A((void**)&ctx->gtmp, N * 8);
+  A((void**)&ctx->rcell, NC * 8);
+  A((void**)&ctx->rcell2, NC * 8);
+  A((void**)&ctx->red, (size_t)kRedBlocks * kMaxBasis * kMaxBasis * 8);
+  A((void**)&ctx->small, 16 * kMaxBasis * kMaxBasis * 8);
+  A((void**)&ctx->stats, kStatSlots * 8);
+  A((void**)&ctx->ibuf, (NC + 8192) * 4);
+  if (st == HS_OK) {
+    hipError_t e = hipHostMalloc(&ctx->hpin, 65536, hipHostMallocDefault);
+    if (e != hipSuccess) st = ctx->fail(HS_ERR_OOM, "hipHostMalloc");
+  }
+  if (st != HS_OK) {
+    hs_destroy(ctx);
+    return st;
+  }
+  *out = ctx;
+  return HS_OK;
+}
+
+hs_status hs_sync(hs_ctx* ctx) {
+  if (!ctx) return HS_ERR_INVALID_ARG;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return HS_OK;
+}
+
+hs_status hs_residual(hs_ctx* ctx, const double* q, const double* q_prev, double* R) {
+  if (!ctx || !q || !q_prev || !R) return HS_ERR_INVALID_ARG;
+  const int nb = blocks_for(ctx->ncell);
+  if (ctx->nc == 1) HS_LAUNCH(ctx, residual_kernel<1>, nb, kBlock, ctx->g, q, q_prev, R);
+  else HS_LAUNCH(ctx, residual_kernel<4>, nb, kBlock, ctx->g, q, q_prev, R);
+  return HS_OK;
+}
+
+hs_status hs_jvp(hs_ctx* ctx, const double* q, const double* v, double* out) {
+  if (!ctx || !q || !v || !out) return HS_ERR_INVALID_ARG;
+  const int nb = blocks_for(ctx->ncell);
+  if (ctx->nc == 1) HS_LAUNCH(ctx, jvp_kernel<1>, nb, kBlock, ctx->g, q, v, out);
+  else HS_LAUNCH(ctx, jvp_kernel<4>, nb, kBlock, ctx->g, q, v, out);
+  return HS_OK;
+}
+
+hs_status hdm_step(hs_ctx* ctx, const double* q_prev, double* q_out, hs_step_info* info) {
+  if (!ctx || !q_prev || !q_out || q_prev == q_out) return HS_ERR_INVALID_ARG;
+  if (info) std::memset(info, 0, sizeof *info);
+  double qmax;
+  HS_TRY(max_abs(ctx, q_prev, ctx->n, &qmax));
+  if (!std::isfinite(qmax)) return ctx->fail(HS_ERR_NONFINITE, "non-finite q_prev");
+  const double tol = ctx->p.newton_rtol * std::max(1.0, qmax);
+  HIP_TRY(ctx, hipMemcpyAsync(q_out, q_prev, ctx->n * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  HS_TRY(newton_solve(ctx, q_out, q_prev, tol, nullptr, info));
+  if (info) info->n_s = ctx->ncell;
+  return HS_OK;
+}
+
+}  // extern "C"

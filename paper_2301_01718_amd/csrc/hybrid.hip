@@ -1,0 +1,511 @@
+// Hybrid snapshot step (eq. hybrid; the hybrid branch of Alg. 1):
+//   A6  gappy-POD fit on the sampled rows with a truncated pseudo-inverse
+//       (eq. red_coord with the fit rows = hat-S), and the subiterations of
+//       Sec. 2.3.2 between the restricted Newton solve and the fit;
+//   A7  reconstruction psi + Phi y of the unsampled entries (eq. rom_approx);
+//   A8  residual-gated Shapiro filters (Sec. 2.3.4);
+//   A4  reconstruction-error indicator of the filtered snapshot (Sec. 2.3.3).
+//
+// The fit factorises the gathered Gram matrix Phi_S^T Phi_S (FP64 MFMA) once
+// per step: a Jacobi eigendecomposition gives the truncated pseudo-inverse
+// G+ (singular values of Phi_S below rcond_fit * sigma_max dropped).  Every
+// subiteration then costs two passes over the gathered rows: y0 = G+ Phi_S^T d
+// and one refinement step y = y0 + G+ Phi_S^T (d - Phi_S y0).
+#include "dense.hpp"
+#include "physics.hpp"
+
+#include <algorithm>
+#include <cstring>
+
+namespace hs {
+
+// small-buffer layout (doubles)
+constexpr int kSmG = 0;                 // Gram (m x m)
+constexpr int kSmGp = 4096;             // pseudo-inverse (m x m)
+constexpr int kSmY0 = 12288;            // y0
+constexpr int kSmY = 12288 + 64;        // y
+constexpr int kSmYPrev = 12288 + 128;   // previous y
+constexpr int kSmMisc = 12288 + 192;    // [0] = ||dy||, [1] = rank, [2] = cond
+
+// Gathered rows of Phi at the dofs of hat-S cells (all components).
+struct GatherLoader {
+  const double* Phi;
+  long long n;
+  int m, nc, ncell, ns;
+  const int* hat;
+  __device__ void load(long long row0, double* X, int ldx, int wp) const {
+    const int r = threadIdx.x % kChunk;
+    const long long row = row0 + r;
+    long long dof = -1;
+    if (row < (long long)nc * ns) {
+      const int a = (int)(row / ns), p = (int)(row % ns);
+      dof = (long long)a * ncell + hat[p];
+    }
+    for (int j = threadIdx.x / kChunk; j < wp; j += blockDim.x / kChunk)
+      X[r * ldx + j] = (dof >= 0 && j < m) ? Phi[(size_t)j * n + dof] : 0.0;
+  }
+};
+
+// Truncated pseudo-inverse of the m x m Gram: G+ = sum_{kept} v v^T / lambda.
+__global__ void __launch_bounds__(64) pinv_kernel(const double* __restrict__ G, int m, double rcond,
+                                                  double* __restrict__ Gp, double* __restrict__ misc) {
+  __shared__ double A[kMaxBasis * (kMaxBasis + 1)], V[kMaxBasis * (kMaxBasis + 1)];
+  __shared__ double lam[kMaxBasis];
+  __shared__ int order[kMaxBasis];
+  __shared__ int rank;
+  const int lda = kMaxBasis + 1;
+  const int t = threadIdx.x;
+  for (int e = t; e < m * m; e += kWave) A[(e / m) * lda + e % m] = G[e];
+  __syncthreads();
+  jacobi_eig_wave(A, V, lda, m, lam, order, 40);
+  if (t == 0) {
+    int k = 0;
+    const double lmax = lam[0];
+    for (int i = 0; i < m; ++i)
+      if (lmax > 0.0 && lam[i] > rcond * rcond * lmax) k = i + 1;
+    rank = k;
+    misc[1] = k;
+    misc[2] = k > 0 ? sqrt(lmax / lam[k - 1]) : 0.0;
+  }
+  __syncthreads();
+  for (int e = t; e < m * m; e += kWave) {
+    const int r = e / m, c = e % m;
+    double s = 0.0;
+    for (int i = 0; i < rank; ++i) s += V[r * lda + order[i]] * V[c * lda + order[i]] / lam[i];
+    Gp[e] = s;
+  }
+}
+
+// Partial projections Phi_rows^T d over rows (gathered if hat != nullptr):
+// mode 0: d = u - psi; mode 1: d = u - psi - Phi_row y0.
+template <int MP>
+__global__ void __launch_bounds__(256) project_kernel(const double* __restrict__ Phi, long long n, int m,
+                                                      int nc, int ncell, const int* __restrict__ hat, int ns,
+                                                      const double* __restrict__ u, const double* __restrict__ psi,
+                                                      const double* __restrict__ y0, int mode,
+                                                      double* __restrict__ part) {
+  __shared__ double yl[MP];
+  __shared__ double wsum[4][MP];
+  for (int j = threadIdx.x; j < MP; j += blockDim.x) yl[j] = (mode == 1 && j < m) ? y0[j] : 0.0;
+  __syncthreads();
+  double acc[MP];
+#pragma unroll
+  for (int j = 0; j < MP; ++j) acc[j] = 0.0;
+  const long long rows = hat ? (long long)nc * ns : n;
+  for (long long row = blockIdx.x * (long long)blockDim.x + threadIdx.x; row < rows;
+       row += (long long)gridDim.x * blockDim.x) {
+    long long dof = row;
+    if (hat) dof = (row / ns) * (long long)ncell + hat[row % ns];
+    double ph[MP];
+#pragma unroll
+    for (int j = 0; j < MP; ++j) ph[j] = j < m ? Phi[(size_t)j * n + dof] : 0.0;
+    double d = u[dof] - psi[dof];
+    if (mode == 1) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < MP; ++j) s += ph[j] * yl[j];
+      d -= s;
+    }
+#pragma unroll
+    for (int j = 0; j < MP; ++j) acc[j] += ph[j] * d;
+  }
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int j = 0; j < MP; ++j) {
+    const double v = wave_sum(acc[j]);
+    if (lane == 0) wsum[wave][j] = v;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < m; j += blockDim.x)
+    part[(size_t)blockIdx.x * MP + j] = ((wsum[0][j] + wsum[1][j]) + wsum[2][j]) + wsum[3][j];
+}
+
+// Reduce the projection partials in block order and apply the pseudo-inverse.
+// mode 0: y0 = G+ b.  mode 1: y = y0 + G+ b, ||y - y_prev|| to misc[0], y_prev = y.
+__global__ void __launch_bounds__(64) project_finish_kernel(const double* __restrict__ part, int nb, int mp,
+                                                            int m, const double* __restrict__ Gp, int mode,
+                                                            double* __restrict__ y0, double* __restrict__ y,
+                                                            double* __restrict__ yprev, double* __restrict__ misc,
+                                                            int first) {
+  __shared__ double b[kMaxBasis], ynew[kMaxBasis];
+  const int t = threadIdx.x;
+  if (t < m) {
+    double s = 0.0;
+    for (int k = 0; k < nb; ++k) s += part[(size_t)k * mp + t];
+    b[t] = s;
+  }
+  __syncthreads();
+  if (t < m) {
+    double s = 0.0;
+    for (int c = 0; c < m; ++c) s += Gp[t * m + c] * b[c];
+    if (mode == 0) y0[t] = s;
+    else ynew[t] = y0[t] + s;
+  }
+  __syncthreads();
+  if (mode == 1 && t == 0) {
+    double d2 = 0.0;
+    for (int i = 0; i < m; ++i) {
+      const double d = ynew[i] - yprev[i];
+      d2 += d * d;
+    }
+    misc[0] = first ? INFINITY : sqrt(d2);
+  }
+  __syncthreads();
+  if (mode == 1 && t < m) {
+    y[t] = ynew[t];
+    yprev[t] = ynew[t];
+  }
+}
+
+// u <- psi + Phi y on the dofs of the listed cells.
+__global__ void ring_update_kernel(const double* __restrict__ Phi, long long n, int m, int nc, int ncell,
+                                   const int* __restrict__ cells, int nl, const double* __restrict__ psi,
+                                   const double* __restrict__ y, double* __restrict__ u) {
+  __shared__ double yl[kMaxBasis];
+  if (threadIdx.x < m) yl[threadIdx.x] = y[threadIdx.x];
+  __syncthreads();
+  const long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (k >= (long long)nc * nl) return;
+  const long long dof = (k / nl) * (long long)ncell + cells[k % nl];
+  double s = 0.0;
+  for (int j = 0; j < m; ++j) s += Phi[(size_t)j * n + dof] * yl[j];
+  u[dof] = psi[dof] + s;
+}
+
+// rho = psi + Phi y everywhere; gamma = u on hat-S cells, rho elsewhere.
+// With mask == nullptr only rho is written.
+__global__ void recon_kernel(const double* __restrict__ Phi, long long n, int m, int ncell,
+                             const double* __restrict__ psi, const double* __restrict__ y,
+                             const uint8_t* __restrict__ mask, const double* __restrict__ u,
+                             double* __restrict__ gamma, double* __restrict__ rho) {
+  __shared__ double yl[kMaxBasis];
+  if (threadIdx.x < m) yl[threadIdx.x] = y[threadIdx.x];
+  __syncthreads();
+  const long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double s = 0.0;
+  for (int j = 0; j < m; ++j) s += Phi[(size_t)j * n + r] * yl[j];
+  const double rr = psi[r] + s;
+  rho[r] = rr;
+  if (mask) gamma[r] = mask[r % ncell] ? u[r] : rr;
+}
+
+// eps_cell = sum_c (gamma - rho)^2, flushed to 0 below floor2.
+__global__ void indicator_kernel(int ncell, int nc, const double* __restrict__ gamma,
+                                 const double* __restrict__ rho, double floor2, double* __restrict__ eps) {
+#pragma clang fp contract(off)
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  double e = 0.0;
+  for (int a = 0; a < nc; ++a) {
+    const double d = gamma[(size_t)a * ncell + c] - rho[(size_t)a * ncell + c];
+    e = a == 0 ? d * d : e + d * d;
+  }
+  eps[c] = e < floor2 ? 0.0 : e;
+}
+
+// ----------------------------------------------------------------- filter
+// out = S_n in along one axis, with S_n = I - (-delta^2/4)^n evaluated as n
+// nested second differences over the 2n+1 values of the stencil (periodic
+// wrap or repetition of the boundary value).
+__global__ void shapiro_kernel(Grid g, const double* __restrict__ in, double* __restrict__ out, int axis,
+                               int nord) {
+#pragma clang fp contract(off)
+  const long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (k >= (long long)g.nc * g.ncell) return;
+  const int a = (int)(k / g.ncell), cell = (int)(k % g.ncell);
+  const int i = cell % g.nx, j = cell / g.nx;
+  const int len = axis == 0 ? g.nx : g.ny;
+  const int x0 = axis == 0 ? i : j;
+  const bool per = g.bc == HS_BC_PERIODIC;
+  double v[7];
+  for (int s = -nord; s <= nord; ++s) {
+    int x = x0 + s;
+    if (per) x = ((x % len) + len) % len;
+    else x = x < 0 ? 0 : (x >= len ? len - 1 : x);
+    const int cc = axis == 0 ? x + g.nx * j : i + g.nx * x;
+    v[s + nord] = in[(size_t)a * g.ncell + cc];
+  }
+  const double centre = v[nord];
+  int cnt = 2 * nord + 1;
+  for (int lev = 0; lev < nord; ++lev) {
+    for (int s = 0; s + 2 < cnt; ++s) v[s] = -(v[s] - 2.0 * v[s + 1] + v[s + 2]) / 4.0;
+    cnt -= 2;
+  }
+  out[k] = centre - v[0];
+}
+
+// rcell = cellwise 2-norm of R(q); block partial sums of rcell to part.
+template <int NC>
+__global__ void cellres_kernel(Grid g, const double* __restrict__ q, const double* __restrict__ qp,
+                               double* __restrict__ rcell, double* __restrict__ part) {
+#pragma clang fp contract(off)
+  __shared__ double lds[kBlock / kWave];
+  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  double rn = 0.0;
+  if (cell < g.ncell) {
+    Stencil<NC> st;
+    load_stencil<NC>(g, q, cell, st);
+    double p[NC], R[NC];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) p[a] = qp[a * g.ncell + cell];
+    cell_residual<NC>(g, st, p, R);
+    double s = R[0] * R[0];
+#pragma unroll
+    for (int a = 1; a < NC; ++a) s = s + R[a] * R[a];
+    rn = sqrt(s);
+    rcell[cell] = rn;
+  }
+  const double bs = block_sum(rn, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = bs;
+}
+
+__global__ void sum_finish_kernel(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  __shared__ double lds[kBlock / kWave];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[b];
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) *out = s;
+}
+
+// Gate: keep the filtered value where the cell residual norm strictly decreases.
+template <int NC>
+__global__ void gate_kernel(Grid g, const double* __restrict__ cur, const double* __restrict__ gf,
+                            const double* __restrict__ qp, const double* __restrict__ r,
+                            double* __restrict__ merged, unsigned long long* __restrict__ count) {
+#pragma clang fp contract(off)
+  __shared__ int lds[kBlock / kWave];
+  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  int keep = 0;
+  if (cell < g.ncell) {
+    Stencil<NC> st;
+    load_stencil<NC>(g, gf, cell, st);
+    double p[NC], R[NC];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) p[a] = qp[a * g.ncell + cell];
+    cell_residual<NC>(g, st, p, R);
+    double s = R[0] * R[0];
+#pragma unroll
+    for (int a = 1; a < NC; ++a) s = s + R[a] * R[a];
+    keep = sqrt(s) < r[cell];
+#pragma unroll
+    for (int a = 0; a < NC; ++a)
+      merged[a * g.ncell + cell] = keep ? gf[a * g.ncell + cell] : cur[a * g.ncell + cell];
+  }
+  keep = block_sum_int(keep, lds);
+  if (threadIdx.x == 0 && keep) atomicAdd(count, (unsigned long long)keep);
+}
+
+hs_status cell_residual_norm(hs_ctx* ctx, const double* q, const double* q_prev, double* rcell,
+                             double* sum_out) {
+  const int nb = blocks_for(ctx->ncell);
+  if (nb > kRedBlocks * 64) return ctx->fail(HS_ERR_SHAPE, "grid too large for the reduction buffer");
+  if (ctx->nc == 1) HS_LAUNCH(ctx, cellres_kernel<1>, nb, kBlock, ctx->g, q, q_prev, rcell, ctx->red);
+  else HS_LAUNCH(ctx, cellres_kernel<4>, nb, kBlock, ctx->g, q, q_prev, rcell, ctx->red);
+  double* slot = ctx->small + kSmMisc + 8;
+  HS_LAUNCH(ctx, sum_finish_kernel, 1, kBlock, ctx->red, nb, slot);
+  return readback(ctx, slot, sizeof(double), sum_out);
+}
+
+static hs_status filter_apply(hs_ctx* ctx, const double* in, double* out, int nord) {
+  const long long n = ctx->n;
+  const int nb = blocks_for(n);
+  if (ctx->g.kind == HS_BURGERS_1D) {
+    HS_LAUNCH(ctx, shapiro_kernel, nb, kBlock, ctx->g, in, out, 0, nord);
+  } else {
+    HS_LAUNCH(ctx, shapiro_kernel, nb, kBlock, ctx->g, in, ctx->R, 0, nord);
+    HS_LAUNCH(ctx, shapiro_kernel, nb, kBlock, ctx->g, (const double*)ctx->R, out, 1, nord);
+  }
+  return HS_OK;
+}
+
+hs_status run_filter(hs_ctx* ctx, double* gamma, const double* q_prev, const hs_hybrid_params* hp,
+                     hs_step_info* info) {
+  double* cur = gamma;
+  double* spare = ctx->gtmp;
+  double* r = ctx->rcell;
+  double* r2 = ctx->rcell2;
+  const int nb = blocks_for(ctx->ncell);
+  for (int o = 0; o < hp->n_orders; ++o) {
+    const int nord = hp->filter_orders[o];
+    double sum_r;
+    HS_TRY(cell_residual_norm(ctx, cur, q_prev, r, &sum_r));
+    for (int it = 1; it <= hp->jfmax; ++it) {
+      HS_TRY(filter_apply(ctx, cur, ctx->gf, nord));
+      HS_TRY(zero_stats(ctx));
+      if (ctx->nc == 1)
+        HS_LAUNCH(ctx, gate_kernel<1>, nb, kBlock, ctx->g, cur, ctx->gf, q_prev, r, spare, ctx->stats + kStatCount);
+      else
+        HS_LAUNCH(ctx, gate_kernel<4>, nb, kBlock, ctx->g, cur, ctx->gf, q_prev, r, spare, ctx->stats + kStatCount);
+      unsigned long long st[kStatSlots];
+      HS_TRY(read_stats(ctx, st));
+      const long long kept = (long long)st[kStatCount];
+      if (info) {
+        info->filter_passes += 1;
+        info->filter_kept += (int)kept;
+      }
+      if (kept == 0) break;
+      std::swap(cur, spare);
+      double sum_new;
+      HS_TRY(cell_residual_norm(ctx, cur, q_prev, r2, &sum_new));
+      std::swap(r, r2);
+      const double dec = (sum_r - sum_new) / sum_r;
+      sum_r = sum_new;
+      if (dec < hp->eps_f) break;
+    }
+  }
+  if (cur != gamma)
+    HIP_TRY(ctx, hipMemcpyAsync(gamma, cur, ctx->n * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  return HS_OK;
+}
+
+// ------------------------------------------------------------- fit helpers
+static int pad16(int m) { return (m + 15) / 16 * 16; }
+
+static hs_status launch_project(hs_ctx* ctx, const double* Phi, int m, const int* hat, int ns,
+                                const double* u, const double* psi, const double* y0, int mode, int* nb_out) {
+  const long long rows = hat ? (long long)ctx->nc * ns : ctx->n;
+  const int nb = (int)std::max<long long>(1, std::min<long long>((rows + kBlock - 1) / kBlock, 512));
+  *nb_out = nb;
+  const int mp = pad16(m);
+  switch (mp) {
+    case 16: HS_LAUNCH(ctx, project_kernel<16>, nb, kBlock, Phi, (long long)ctx->n, m, ctx->nc, ctx->ncell, hat, ns, u, psi, y0, mode, ctx->red); break;
+    case 32: HS_LAUNCH(ctx, project_kernel<32>, nb, kBlock, Phi, (long long)ctx->n, m, ctx->nc, ctx->ncell, hat, ns, u, psi, y0, mode, ctx->red); break;
+    case 48: HS_LAUNCH(ctx, project_kernel<48>, nb, kBlock, Phi, (long long)ctx->n, m, ctx->nc, ctx->ncell, hat, ns, u, psi, y0, mode, ctx->red); break;
+    default: HS_LAUNCH(ctx, project_kernel<64>, nb, kBlock, Phi, (long long)ctx->n, m, ctx->nc, ctx->ncell, hat, ns, u, psi, y0, mode, ctx->red); break;
+  }
+  return HS_OK;
+}
+
+// Gram of the (gathered) rows and its truncated pseudo-inverse.
+static hs_status fit_factor(hs_ctx* ctx, const double* Phi, int m, const int* hat, int ns, double rcond) {
+  const int wp = pad16(m);
+  const long long rows = hat ? (long long)ctx->nc * ns : ctx->n;
+  const long long nchunks = (rows + kChunk - 1) / kChunk;
+  const int nb = (int)std::max<long long>(1, std::min<long long>(nchunks, 512));
+  GatherLoader ld{Phi, (long long)ctx->n, m, ctx->nc, ctx->ncell, ns, hat};
+  const size_t lds = (size_t)kChunk * (wp + 1) * sizeof(double);
+  hipLaunchKernelGGL(gram_kernel<GatherLoader>, dim3(nb), dim3(256), lds, ctx->stream, ld, rows, wp, ctx->red);
+  HIP_TRY(ctx, hipGetLastError());
+  HS_LAUNCH(ctx, gram_reduce_kernel, blocks_for(m * m), kBlock, ctx->red, nb, wp, m, ctx->small + kSmG);
+  HS_LAUNCH(ctx, pinv_kernel, 1, 64, ctx->small + kSmG, m, rcond, ctx->small + kSmGp, ctx->small + kSmMisc);
+  return HS_OK;
+}
+
+// y = pinv fit of (u - psi) on the rows, with one refinement step.
+static hs_status fit_solve(hs_ctx* ctx, const double* Phi, int m, const int* hat, int ns, const double* u,
+                           const double* psi, int first) {
+  double* sm = ctx->small;
+  int nb;
+  HS_TRY(launch_project(ctx, Phi, m, hat, ns, u, psi, nullptr, 0, &nb));
+  HS_LAUNCH(ctx, project_finish_kernel, 1, 64, ctx->red, nb, pad16(m), m, sm + kSmGp, 0, sm + kSmY0, sm + kSmY,
+            sm + kSmYPrev, sm + kSmMisc, first);
+  HS_TRY(launch_project(ctx, Phi, m, hat, ns, u, psi, sm + kSmY0, 1, &nb));
+  HS_LAUNCH(ctx, project_finish_kernel, 1, 64, ctx->red, nb, pad16(m), m, sm + kSmGp, 1, sm + kSmY0, sm + kSmY,
+            sm + kSmYPrev, sm + kSmMisc, first);
+  return HS_OK;
+}
+
+}  // namespace hs
+
+using namespace hs;
+
+extern "C" {
+
+hs_status hs_filter(hs_ctx* ctx, const double* gamma_in, const double* q_prev, const hs_hybrid_params* hp,
+                    double* gamma_out, hs_step_info* info) {
+  if (!ctx || !gamma_in || !q_prev || !hp || !gamma_out || gamma_out == q_prev) return HS_ERR_INVALID_ARG;
+  if (hp->n_orders < 0 || hp->n_orders > 4 || hp->jfmax < 0) return HS_ERR_INVALID_ARG;
+  for (int o = 0; o < hp->n_orders; ++o)
+    if (hp->filter_orders[o] < 1 || hp->filter_orders[o] > 3) return HS_ERR_INVALID_ARG;
+  if (info) std::memset(info, 0, sizeof *info);
+  if (gamma_out != gamma_in)
+    HIP_TRY(ctx, hipMemcpyAsync(gamma_out, gamma_in, ctx->n * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  HS_TRY(run_filter(ctx, gamma_out, q_prev, hp, info));
+  return hs_sync(ctx);
+}
+
+hs_status hs_indicator_full(hs_ctx* ctx, const double* gamma, const double* Phi, const double* psi, int32_t m,
+                            double floor_rel, double* eps, double* y_out) {
+  if (!ctx || !gamma || !Phi || !psi || !eps) return HS_ERR_INVALID_ARG;
+  if (m < 1 || m > ctx->p.m_max) return HS_ERR_INVALID_ARG;
+  double* sm = ctx->small;
+  int nb;
+  HS_TRY(launch_project(ctx, Phi, m, nullptr, 0, gamma, psi, nullptr, 0, &nb));
+  // y = Phi^T (gamma - psi): G+ = I
+  std::vector<double> eye(m * m, 0.0);
+  for (int i = 0; i < m; ++i) eye[i * m + i] = 1.0;
+  HIP_TRY(ctx, hipMemcpyAsync(sm + kSmGp, eye.data(), m * m * 8, hipMemcpyHostToDevice, ctx->stream));
+  HS_LAUNCH(ctx, project_finish_kernel, 1, 64, ctx->red, nb, pad16(m), m, sm + kSmGp, 0, sm + kSmY0, sm + kSmY,
+            sm + kSmYPrev, sm + kSmMisc, 1);
+  HS_LAUNCH(ctx, recon_kernel, blocks_for(ctx->n), kBlock, Phi, (long long)ctx->n, m, ctx->ncell, psi,
+            sm + kSmY0, (const uint8_t*)nullptr, (const double*)nullptr, (double*)nullptr, ctx->rho);
+  double gmax;
+  HS_TRY(max_abs(ctx, gamma, ctx->n, &gmax));
+  const double fl = floor_rel * std::max(1.0, gmax);
+  HS_LAUNCH(ctx, indicator_kernel, blocks_for(ctx->ncell), kBlock, ctx->ncell, ctx->nc, gamma, ctx->rho, fl * fl,
+            eps);
+  if (y_out) HIP_TRY(ctx, hipMemcpyAsync(y_out, sm + kSmY0, m * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  return hs_sync(ctx);
+}
+
+hs_status rom_hybrid_step(hs_ctx* ctx, const double* q_prev, const double* Phi, const double* psi, int32_t m,
+                          const hs_samples* s, const hs_hybrid_params* hp, double* q_out, double* eps_out,
+                          double* y_out, hs_step_info* info) {
+  if (!ctx || !q_prev || !Phi || !psi || !s || !hp || !q_out || s->ctx != ctx) return HS_ERR_INVALID_ARG;
+  if (q_out == q_prev || q_out == psi || q_out == Phi) return HS_ERR_INVALID_ARG;
+  if (m < 1 || m > ctx->p.m_max) return ctx->fail(HS_ERR_RANK, "empty basis");
+  if (hp->jmax < 1 || hp->n_orders < 0 || hp->n_orders > 4 || !(hp->rcond_fit > 0) || !(hp->eps_y >= 0))
+    return HS_ERR_INVALID_ARG;
+  for (int o = 0; o < hp->n_orders; ++o)
+    if (hp->filter_orders[o] < 1 || hp->filter_orders[o] > 3) return HS_ERR_INVALID_ARG;
+  if (hp->precision != HS_FP64) return ctx->fail(HS_ERR_INVALID_ARG, "rom_hybrid_step: only HS_FP64 in this build");
+  if (s->n_s == 0) return ctx->fail(HS_ERR_RANK, "empty sampled set");
+  hs_step_info local{};
+  hs_step_info* inf = info ? info : &local;
+  std::memset(inf, 0, sizeof *inf);
+  inf->n_s = s->n_s;
+  inf->l = s->l;
+
+  double qmax;
+  HS_TRY(max_abs(ctx, q_prev, ctx->n, &qmax));
+  if (!std::isfinite(qmax)) return ctx->fail(HS_ERR_NONFINITE, "non-finite q_prev");
+  const double tol = ctx->p.newton_rtol * std::max(1.0, qmax);
+  double* u = ctx->u;
+  double* sm = ctx->small;
+  HIP_TRY(ctx, hipMemcpyAsync(u, q_prev, ctx->n * 8, hipMemcpyDeviceToDevice, ctx->stream));
+
+  HS_TRY(fit_factor(ctx, Phi, m, s->hat, s->n_s, hp->rcond_fit));
+  double misc[3];
+  HS_TRY(readback(ctx, sm + kSmMisc, 3 * sizeof(double), misc));
+  inf->fit_rank = (int)misc[1];
+  inf->fit_cond = misc[2];
+  if (inf->fit_rank == 0) return ctx->fail(HS_ERR_RANK, "rank-zero fit");
+
+  for (int j = 1; j <= hp->jmax; ++j) {
+    HS_TRY(newton_solve(ctx, u, q_prev, tol, s, inf));
+    HS_TRY(fit_solve(ctx, Phi, m, s->hat, s->n_s, u, psi, j == 1));
+    if (s->l > 0)
+      HS_LAUNCH(ctx, ring_update_kernel, blocks_for((long long)ctx->nc * s->l), kBlock, Phi, (long long)ctx->n, m,
+                ctx->nc, ctx->ncell, s->tilde, s->l, psi, sm + kSmY, u);
+    double dy;
+    HS_TRY(readback(ctx, sm + kSmMisc, sizeof(double), &dy));
+    inf->subiters = j;
+    inf->dy_last = dy;
+    if (j >= 2 && dy < hp->eps_y) break;
+  }
+  HS_LAUNCH(ctx, recon_kernel, blocks_for(ctx->n), kBlock, Phi, (long long)ctx->n, m, ctx->ncell, psi, sm + kSmY,
+            s->mask, u, q_out, ctx->rho);
+  HS_TRY(run_filter(ctx, q_out, q_prev, hp, inf));
+  if (eps_out) {
+    double gmax;
+    HS_TRY(max_abs(ctx, q_out, ctx->n, &gmax));
+    const double fl = hp->floor_rel * std::max(1.0, gmax);
+    HS_LAUNCH(ctx, indicator_kernel, blocks_for(ctx->ncell), kBlock, ctx->ncell, ctx->nc, q_out, ctx->rho, fl * fl,
+              eps_out);
+  }
+  if (y_out) HIP_TRY(ctx, hipMemcpyAsync(y_out, sm + kSmY, m * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  return hs_sync(ctx);
+}
+
+}  // extern "C"

@@ -1,0 +1,125 @@
+"""Algorithm 1 (hybrid snapshot AROM) on the GPU library.
+
+The driver only sequences the four calls of the C ABI (hdm_step,
+sample_select, rom_hybrid_step, basis_update) and keeps the window of the
+last w + 1 snapshots resident in HBM as a ring of device buffers.  The
+schedule follows Alg. 1: full solves for the first w - 1 steps and every z
+steps; after step k (k >= w - 1, step k + 1 not full) the indicator of the
+newest snapshot selects the sampled set of step k + 1 and the basis and
+reference state are rebuilt from the window.  A step whose sampled set is
+empty, or that has no basis, is a full step; a hybrid step whose Newton solve
+fails is redone as a full step.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+
+import torch
+
+from ._lib import (Context, HsError, FP64, HS_ERR_NOT_CONVERGED, HS_ERR_RANK, hybrid_params)
+
+
+@dataclasses.dataclass
+class AromConfig:
+    w: int
+    m: int
+    z: int = 20
+    fraction: float = 0.1
+    halo: int = 2
+    tau_pod: float = 1e-4
+    eps_y: float = 1e-4
+    jmax: int = 10
+    filter_orders: tuple = (1, 2, 3)
+    eps_f: float = 1e-2
+    jfmax: int = 10
+    rcond_fit: float = 1e-6
+    floor_rel: float = 1e-11
+    precision: int = FP64
+
+
+def is_full_step(k, w, z):
+    return k + 1 <= w or k % z == 0
+
+
+def wants_update(k, w, z, steps):
+    return k >= w - 1 and (k + 1) % z != 0 and k < steps
+
+
+class Arom:
+    """Runs Alg. 1 on one device.  ``on_step(k, rec, used, out)`` is called
+    after every step with the step record, the device tensors the step used
+    and its output; ``on_update(k, rec, state)`` after every sampling/basis
+    update.  The tensors are valid only during the call."""
+
+    def __init__(self, prob, cfg: AromConfig, device="cuda", ctx: Context | None = None):
+        self.prob = prob
+        self.cfg = cfg
+        self.ctx = ctx or Context(prob, m_max=cfg.m, w_max=cfg.w, device=device)
+        c = self.ctx
+        self.ring = [c.empty() for _ in range(cfg.w + 2)]
+        self.Phi = torch.zeros(cfg.m * c.n, dtype=torch.float64, device=c.device)
+        self.psi = c.empty()
+        self.sigma = torch.zeros(cfg.w, dtype=torch.float64, device=c.device)
+        self.eps = c.empty(c.ncell)
+        self.samples = c.samples()
+        self.hp = hybrid_params(cfg.eps_y, cfg.jmax, cfg.filter_orders, cfg.eps_f, cfg.jfmax,
+                                cfg.rcond_fit, cfg.floor_rel, cfg.precision)
+        self.m_eff = 0
+
+    def slot(self, k):
+        return self.ring[k % (self.cfg.w + 2)]
+
+    def run(self, q0, steps, on_step=None, on_update=None, timing=False):
+        cfg, c = self.cfg, self.ctx
+        self.slot(0).copy_(q0)
+        self.m_eff = 0
+        have_samples = False
+        records = []
+        for k in range(1, steps + 1):
+            t0 = time.perf_counter() if timing else 0.0
+            rec = {"k": k}
+            prev, out = self.slot(k - 1), self.slot(k)
+            used = {"q_prev": prev, "Phi": self.Phi, "psi": self.psi, "m": self.m_eff}
+            hybrid = not is_full_step(k, cfg.w, cfg.z) and have_samples and self.m_eff > 0
+            if hybrid:
+                try:
+                    _, info = c.rom_hybrid_step(prev, self.Phi, self.psi, self.m_eff, self.samples,
+                                                self.hp, out=out, eps=self.eps)
+                    rec.update(type="hybrid", n_s=info["n_s"], l=info["l"], J=info["subiters"],
+                               newton=info["newton_iters"], filter_passes=info["filter_passes"],
+                               fit_cond=info["fit_cond"])
+                except HsError as e:
+                    if e.status not in (HS_ERR_NOT_CONVERGED, HS_ERR_RANK):
+                        raise
+                    hybrid = False
+                    rec["fallback"] = str(e)
+            if not hybrid:
+                _, info = c.hdm_step(prev, out=out)
+                rec.update(type="full", n_s=c.ncell, newton=info["newton_iters"])
+            if on_step is not None:
+                used["samples"] = self.samples if hybrid else None
+                on_step(k, rec, used, out)
+            have_samples = False
+            if wants_update(k, cfg.w, cfg.z, steps):
+                if k >= cfg.w and self.m_eff > 0:
+                    if not hybrid:
+                        c.indicator_full(out, self.Phi, self.psi, self.m_eff, cfg.floor_rel, eps=self.eps)
+                    c.sample_select(self.eps, cfg.fraction, cfg.halo, samples=self.samples)
+                    cnt = self.samples.counts()
+                    rec["n_g"] = cnt["n_g"]
+                    have_samples = cnt["n_s"] > 0
+                lo = k - cfg.w if k >= cfg.w else 0
+                window = [self.slot(j) for j in range(lo, k + 1)]
+                self.m_eff = c.basis_update(window, cfg.w, cfg.m, self.Phi, self.psi, self.sigma,
+                                            cfg.tau_pod, cfg.precision)
+                rec["m_eff"] = self.m_eff
+                if on_update is not None:
+                    on_update(k, rec, {"eps": self.eps, "samples": self.samples if have_samples else None,
+                                       "window": window, "Phi": self.Phi, "psi": self.psi,
+                                       "sigma": self.sigma, "m_eff": self.m_eff})
+            if timing:
+                torch.cuda.synchronize(c.device)
+                rec["seconds"] = time.perf_counter() - t0
+            records.append(rec)
+        return self.slot(steps), records

@@ -1,0 +1,195 @@
+"""GPU parity of the HIP kernels against the FP64 oracle (called through the
+C ABI).  Residual and filter are computed in the oracle's operation order,
+so they are compared bit for bit; the Newton solve, selection, basis and fit
+to the tolerances stated in each test."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fv, hybrid, pod, sampling
+
+from gpu_common import CASES, case, ctx_for, dev, host, indicator_close, need_gpu, print_case, rel, torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_residual_bitwise(name):
+    need_gpu()
+    print_case("residual", name)
+    wl, prob, q0 = case(name, 1)
+    q1, _ = fv.hdm_step(prob, q0)
+    rng = np.random.default_rng(2)
+    qp = q0 * (1 + 1e-3 * rng.standard_normal(q0.size))
+    ctx = ctx_for(prob)
+    R = host(ctx.residual(dev(q1), dev(qp)))
+    Ro = fv.residual(prob, q1, qp)
+    assert np.array_equal(R, Ro), np.max(np.abs(R - Ro))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_jvp_matches_oracle_jacobian(name):
+    need_gpu()
+    print_case("jvp", name)
+    wl, prob, q0 = case(name, 2)
+    rng = np.random.default_rng(3)
+    q = q0 * (1 + 0.01 * rng.standard_normal(q0.size))
+    v = rng.standard_normal(q0.size)
+    ctx = ctx_for(prob)
+    Jv = host(ctx.jvp(dev(q), dev(v)))
+    Jo = fv.jacobian(prob, q) @ v
+    assert rel(Jv, Jo) < 1e-14
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hdm_step_matches_oracle(name):
+    need_gpu()
+    print_case("hdm_step", name)
+    wl, prob, q0 = case(name, 0)
+    ctx = ctx_for(prob)
+    q = q0
+    qg = dev(q0)
+    for k in range(3):
+        qo, _ = fv.hdm_step(prob, q)
+        qn, info = ctx.hdm_step(dev(q))
+        qn = host(qn)
+        assert rel(qn, qo) < 1e-12, (k, rel(qn, qo), info)
+        # property at any size: the GPU state solves the oracle's residual
+        assert np.max(np.abs(fv.residual(prob, qn, q))) <= 2 * fv.newton_tol(q)
+        q = qo
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_sample_select_bit_exact(name):
+    need_gpu()
+    print_case("sample_select", name)
+    wl, prob, q0 = case(name, 3)
+    rng = np.random.default_rng(4)
+    eps = rng.random(prob.ncell) ** 6
+    eps[rng.random(prob.ncell) < 0.3] = 0.0
+    eps[10:20] = eps[100]                  # ties at various places
+    eps[200:260] = 0.5
+    ctx = ctx_for(prob)
+    for frac in (0.0, 0.01, wl.frac, 0.3, 1.0):
+        o = sampling.select(prob, eps, sampling.RULE_FRACTION, frac, halo=2)
+        s = ctx.sample_select(dev(eps), frac, halo=2)
+        c = s.counts()
+        hat, tilde, mask = s.export()
+        assert c["n_g"] == o["n_g"] and c["n_s"] == o["hat"].size and c["l"] == o["tilde"].size
+        assert np.array_equal(host(hat), o["hat"])
+        assert np.array_equal(host(tilde), o["tilde"])
+        assert np.array_equal(host(mask).astype(bool), o["mask"])
+
+
+def test_samples_set_derives_ring():
+    need_gpu()
+    wl, prob, q0 = case("burgers2d")
+    rng = np.random.default_rng(5)
+    hat = np.flatnonzero(rng.random(prob.ncell) < 0.05).astype(np.int32)
+    mask = np.zeros(prob.ncell, bool)
+    mask[hat] = True
+    ctx = ctx_for(prob)
+    s = ctx.samples_set(dev(hat))
+    h, t, m = s.export()
+    assert np.array_equal(host(h), hat)
+    assert np.array_equal(host(t), np.flatnonzero(sampling.neighbours(prob, mask)))
+
+
+def window(prob, q0, w, extra=1):
+    snaps = [q0]
+    for _ in range(w - 1 + extra):
+        snaps.append(fv.hdm_step(prob, snaps[-1])[0])
+    return snaps
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("first", [False, True])
+def test_basis_update_matches_oracle(name, first):
+    need_gpu()
+    print_case("basis_update", name, first)
+    wl, prob, q0 = case(name, 1)
+    w, m = 12, 8
+    snaps = window(prob, q0, w, extra=0 if first else 1)
+    o = pod.pod(snaps, w, m, tau=1e-4)
+    ctx = ctx_for(prob)
+    Phi = torch.zeros(m * prob.n, dtype=torch.float64, device="cuda")
+    psi = ctx.empty()
+    sig = torch.zeros(w, dtype=torch.float64, device="cuda")
+    me = ctx.basis_update([dev(s) for s in snaps], w, m, Phi, psi, sig, tau_pod=1e-4)
+    assert np.array_equal(host(psi), o["psi_new"])
+    sg, so = host(sig), o["sigma"]
+    assert np.max(np.abs(sg ** 2 - so ** 2)) <= 1e-13 * so[0] ** 2
+    assert me == o["m_eff"]
+    P = host(Phi).reshape(m, prob.n)[:me].T
+    # the basis is formed from the Gram matrix of the window, whose rounding
+    # (eps ||X||^2) leaves an orthogonality error of order eps (s_0/s_{m_eff-1})^2
+    orth_tol = 10 * 2.2e-16 * (so[0] / so[me - 1]) ** 2
+    assert np.max(np.abs(P.T @ P - np.eye(me))) < max(1e-13, orth_tol)
+    X = o["X"]
+    Pg = P @ (P.T @ X)
+    Po = o["Phi"] @ (o["Phi"].T @ X)
+    gap = (so[me - 1] ** 2 - (so[me] ** 2 if me < w else 0.0)) / so[0] ** 2
+    tol = max(1e-12, 1e-15 / gap)
+    assert np.linalg.norm(Pg - Po) <= tol * np.linalg.norm(X), (np.linalg.norm(Pg - Po) / np.linalg.norm(X), gap)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_filter_matches_oracle(name):
+    need_gpu()
+    print_case("filter", name)
+    wl, prob, q0 = case(name, 2)
+    q1, _ = fv.hdm_step(prob, q0)
+    rng = np.random.default_rng(6)
+    noisy = q1 + 1e-3 * np.abs(q1).max() * rng.standard_normal(q1.size) * (rng.random(q1.size) < 0.1)
+    ctx = ctx_for(prob)
+    out, info = ctx.filter(dev(noisy), dev(q0))
+    ref = hybrid.spatial_filter(prob, noisy, q0, hybrid.HybridParams())
+    assert info["filter_passes"] > 0
+    assert np.array_equal(host(out), ref), np.max(np.abs(host(out) - ref))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_indicator_full_matches_oracle(name):
+    need_gpu()
+    print_case("indicator_full", name)
+    wl, prob, q0 = case(name, 4)
+    w, m = 10, 6
+    snaps = window(prob, q0, w)
+    o = pod.pod(snaps, w, m)
+    g = fv.hdm_step(prob, snaps[-1])[0]
+    me = o["m_eff"]
+    ctx = ctx_for(prob)
+    Phi = dev(np.ascontiguousarray(o["Phi"].T).reshape(-1))
+    eps, y = ctx.indicator_full(dev(g), Phi, dev(o["psi_new"]), me)
+    eo, yo = sampling.indicator_full(prob, g, o["Phi"], o["psi_new"])
+    assert rel(host(y), yo) < 1e-12
+    ok, d = indicator_close(host(eps), eo, g)
+    assert ok, d
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hybrid_step_matches_oracle(name):
+    need_gpu()
+    print_case("rom_hybrid_step", name)
+    wl, prob, q0 = case(name, 0)
+    w, m = 12, 8
+    snaps = window(prob, q0, w)
+    o = pod.pod(snaps, w, m)
+    Phi_o, psi = o["Phi"], o["psi_new"]
+    me = o["m_eff"]
+    g = snaps[-1]
+    eps, _ = sampling.indicator_full(prob, g, Phi_o, psi)
+    sel = sampling.select(prob, eps, sampling.RULE_FRACTION, wl.frac)
+    ref = hybrid.hybrid_step(prob, g, Phi_o, psi, sel["hat"], sel["tilde"])
+    ctx = ctx_for(prob)
+    s = ctx.samples_set(dev(sel["hat"]))
+    Phi = dev(np.ascontiguousarray(Phi_o.T).reshape(-1))
+    eps_g = ctx.empty(prob.ncell)
+    y_g = ctx.empty(me)
+    out, info = ctx.rom_hybrid_step(dev(g), Phi, dev(psi), me, s, eps=eps_g, y=y_g)
+    print("  info", info, "J_oracle", ref["J"], flush=True)
+    assert info["subiters"] == ref["J"]
+    assert rel(host(y_g), ref["y"]) < 1e-10
+    assert rel(host(out), ref["gamma"]) < 1e-12, rel(host(out), ref["gamma"])
+    ok, d = indicator_close(host(eps_g), ref["eps"], ref["gamma"], tol=1e-12)
+    assert ok, d

@@ -1,0 +1,211 @@
+"""Benchmark: hybrid steps per second of the hybrid-snapshot AROM on one MI355X.
+
+Workload: 2D inviscid Burgers on [0,1]^2, 1024 x 1024 cells, periodic, eight
+seeded Gaussian bumps, backward Euler + Newton, POD rank 32 over a window of
+48 snapshots, top 5 % of cells sampled plus a 2-cell halo, a full solve every
+20 steps (FP64).  One step is one step of Algorithm 1 on the real trajectory;
+with the default window every timed step is a hybrid step, i.e. the hybrid
+snapshot (rom_hybrid_step) followed by the sampling (sample_select) and basis
+(basis_update) updates it triggers.
+
+Prints ONE JSON line.  ``value`` = hybrid steps / second (inputs resident in
+HBM).  ``roofline`` = the dominant kernel's algorithmic bytes per launch over
+its HIP-event launch time.  ``cpu_baseline`` = the FP64 oracle timed on the
+host on one hybrid step (+ its sampling and basis update) from the same state.
+
+    python bench.py [--gpus 1] [--steps 16] [--warmup 2]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("hybrid steps/sec & cell-updates/sec (2D 1024² Burgers); HBM GB/s; adjoint s/step")
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=16)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="burgers2d_1024")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--roofline-kernel", default="basis_form",
+                    choices=["basis_gram", "basis_form", "recon", "resjac", "sweep", "cellres"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one 1 GiB elementwise copy (counter calibration for rocprofv3 --pmc)")
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def source_digest():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2301_01718_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel, workload):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_digest") != source_digest():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(prob, wl, snap):
+    """Time the oracle on one hybrid step + its sampling + its basis update."""
+    import numpy as np
+    from oracle import hybrid, pod, sampling
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    out = hybrid.hybrid_step(prob, snap["q_prev"], snap["Phi"], snap["psi"], snap["hat"], snap["tilde"])
+    sampling.select(prob, out["eps"], sampling.RULE_FRACTION, wl.frac, halo=wl.halo)
+    window = snap["window"] + [out["gamma"]]
+    pod.pod(window[-(wl.w + 1):], wl.w, wl.m)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "hybrid steps/s", "cores": int(cores), "kind": "oracle",
+            "sample": (f"one hybrid step of {wl.name} ({prob.nx}x{prob.ny}) from the GPU state "
+                       f"before the first timed step, with its sampling and POD update: {dt:.1f} s")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; multi-GPU runs are not part of it "
+              "(see DESIGN.md, 'How the path would shard').", file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+    import workloads as W
+    import paper_2301_01718_amd.driver as D
+
+    wl = W.WORKLOADS[args.workload]
+    prob, q0 = W.make(wl, args.seed)
+    cfg = D.AromConfig(w=wl.w, m=wl.m, z=wl.z, fraction=wl.frac, halo=wl.halo)
+    drv = D.Arom(prob, cfg)
+    c = drv.ctx
+    dev = c.device
+    drv.start(torch.from_numpy(q0).to(dev), wl.steps)
+
+    # setup: fill the window and reach the first full step after it
+    k0 = wl.z * math.ceil((wl.w + 2) / wl.z)
+    while drv.k < k0:
+        drv.advance()
+        if drv.k % 20 == 0:
+            log(f"setup step {drv.k}/{k0}")
+    for _ in range(args.warmup):
+        drv.advance()
+    log(f"warmup done at step {drv.k}")
+
+    # inputs of the first timed step, for the CPU baseline (host copies, untimed)
+    snap = None
+    if not args.no_cpu_baseline and drv.have_samples:
+        hat, tilde, _ = drv.samples.export()
+        me = drv.m_eff
+        snap = {"q_prev": drv.state().cpu().numpy().copy(),
+                "Phi": drv.Phi[: me * c.n].view(me, c.n).t().cpu().numpy().copy(),
+                "psi": drv.psi.cpu().numpy().copy(),
+                "hat": hat.cpu().numpy(), "tilde": tilde.cpu().numpy(),
+                "window": [drv.slot(j).cpu().numpy().copy() for j in range(drv.k - wl.w + 1, drv.k + 1)]}
+
+    # timed region: exactly K steps of Algorithm 1
+    c.prof_enable(args.roofline_kernel)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    recs = []
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record()
+        recs.append(drv.advance())
+        ev[i][1].record()
+    torch.cuda.synchronize(dev)
+    elapsed = time.perf_counter() - t0
+    k_ms, k_launch, k_bytes = c.prof_read()
+    c.prof_enable(0)
+    step_ms = [a.elapsed_time(b) for a, b in ev]
+    hyb = [t for t, r in zip(step_ms, recs) if r["type"] == "hybrid"]
+    full = [t for t, r in zip(step_ms, recs) if r["type"] == "full"]
+    log(f"timed steps {recs[0]['k']}..{recs[-1]['k']}: {len(hyb)} hybrid, {len(full)} full, {elapsed:.3f} s")
+
+    # full-HDM step time on the same state (for the speedup S = t_H / t_R)
+    tmp = c.empty()
+    th = []
+    for _ in range(3):
+        torch.cuda.synchronize(dev)
+        t = time.perf_counter()
+        c.hdm_step(drv.state(), out=tmp)
+        torch.cuda.synchronize(dev)
+        th.append(time.perf_counter() - t)
+    t_H = float(np.median(th))
+
+    if args.copy_probe:
+        a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        torch.add(a, 0.0, out=b)          # one elementwise copy: 1 GiB read + 1 GiB written
+        torch.cuda.synchronize(dev)
+        del a, b
+
+    n_h = len(hyb)
+    value = n_h / (sum(hyb) / 1e3) if n_h else 0.0
+    achieved = (k_bytes / k_launch) / (k_ms / k_launch * 1e-3) / 1e9 if k_launch else None
+    traffic = traffic_for(args.roofline_kernel, wl.name)
+    roof = {"bound": "hbm", "kernel": args.roofline_kernel,
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+            "traffic": traffic,
+            "bytes_per_launch": (k_bytes / k_launch) if k_launch else None,
+            "launches": k_launch, "avg_launch_us": (1e3 * k_ms / k_launch) if k_launch else None}
+    cpu = None
+    if snap is not None:
+        log("timing the oracle on the host ...")
+        cpu = cpu_baseline(prob, wl, snap)
+    out = {
+        "metric": METRIC, "value": value, "unit": "hybrid steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "nx": prob.nx, "ny": prob.ny, "m": wl.m, "w": wl.w,
+                   "fraction": wl.frac, "halo": wl.halo, "z": wl.z, "seed": args.seed,
+                   "timed_steps": [recs[0]["k"], recs[-1]["k"]]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "cell_updates_per_s": prob.ncell * args.steps / elapsed,
+        "hybrid_step_ms": float(np.median(hyb)) if hyb else None,
+        "full_step_ms": 1e3 * t_H,
+        "speedup_S": (1e3 * t_H) / (1e3 * elapsed / args.steps),
+        "mean_n_s_frac": float(np.mean([r["n_s"] / prob.ncell for r in recs if r["type"] == "hybrid"] or [0])),
+        "mean_J": float(np.mean([r["J"] for r in recs if r["type"] == "hybrid"] or [0])),
+        "m_eff": recs[-1].get("m_eff"),
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -206,6 +206,25 @@ hs_status rom_hybrid_step(hs_ctx* ctx, const double* q_prev, const double* Phi, 
 hs_status hs_filter(hs_ctx* ctx, const double* gamma_in, const double* q_prev,
                     const hs_hybrid_params* params /* host */, double* gamma_out, hs_step_info* info);
 
+/* ------------------------------------------------------- measurement */
+/* Kernel classes that can be timed with HIP events on the context's stream. */
+#define HS_PROF_NONE        0
+#define HS_PROF_BASIS_GRAM  1   /* window pass of basis_update: means + Gram on MFMA */
+#define HS_PROF_BASIS_FORM  2   /* formation pass of basis_update: Phi = X T on MFMA */
+#define HS_PROF_RECON       3   /* reconstruction psi + Phi y (hybrid step) */
+#define HS_PROF_RESJAC      4   /* residual + Jacobian relaxation data (Newton) */
+#define HS_PROF_SWEEP       5   /* Jacobi relaxation sweeps */
+#define HS_PROF_CELLRES     6   /* cell residual norms (filter) */
+/* Start timing every launch of one kernel class (HS_PROF_NONE stops).  Each
+ * launch is bracketed by two HIP events recorded on the context's stream, and
+ * the algorithmic bytes of that launch (the minimum reads and writes the
+ * operation needs) are accumulated. */
+hs_status hs_prof_enable(hs_ctx* ctx, int32_t kernel_class);
+/* Synchronise, return the summed event time (ms), launch count and
+ * algorithmic bytes since enable or the last read, and reset the counters. */
+hs_status hs_prof_read(hs_ctx* ctx, double* total_ms /* host */, int32_t* launches /* host */,
+                       double* bytes /* host */);
+
 #ifdef __cplusplus
 }
 #endif

@@ -100,7 +100,11 @@ _SIGS = {
     "rom_hybrid_step": [P, P, P, P, I32, P, ctypes.POINTER(HybridParams), P, P, P,
                         ctypes.POINTER(StepInfo)],
     "hs_filter": [P, P, P, ctypes.POINTER(HybridParams), P, ctypes.POINTER(StepInfo)],
+    "hs_prof_enable": [P, I32],
+    "hs_prof_read": [P, ctypes.POINTER(D), ctypes.POINTER(I32), ctypes.POINTER(D)],
 }
+
+PROF_CLASSES = {"basis_gram": 1, "basis_form": 2, "recon": 3, "resjac": 4, "sweep": 5, "cellres": 6}
 
 
 def lib():
@@ -179,6 +183,16 @@ class Context:
 
     def sync(self):
         self._check(lib().hs_sync(self.h))
+
+    # ---------------------------------------------------------- measurement
+    def prof_enable(self, kernel_class):
+        cls = PROF_CLASSES[kernel_class] if isinstance(kernel_class, str) else kernel_class
+        self._check(lib().hs_prof_enable(self.h, cls))
+
+    def prof_read(self):
+        ms, n, b = D(0), I32(0), D(0)
+        self._check(lib().hs_prof_read(self.h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
+        return ms.value, n.value, b.value
 
     # ----------------------------------------------------------- kernels
     def residual(self, q, q_prev, out=None):

@@ -16,48 +16,54 @@
 namespace hs {
 
 constexpr int kMaxSnaps = kMaxBasis + 1;
+constexpr int kRawLd = kMaxSnaps + 1;   // LDS leading dimension of the raw snapshot tile
 
-struct SnapPtrs {
-  const double* p[kMaxSnaps];
-};
+// Stage the rows row0 .. row0+63 of all nsnap snapshots into LDS (raw[r][j]),
+// every thread issuing independent coalesced loads, then let one thread per
+// row form the two window means by sequential sums in snapshot order.
+__device__ inline void stage_window(const double* const* __restrict__ snaps, int nsnap, int w, long long n,
+                                    long long row0, double* raw, double* centre, double* psi_new) {
+  for (int idx = threadIdx.x; idx < kChunk * nsnap; idx += blockDim.x) {
+    const int r = idx % kChunk, j = idx / kChunk;
+    const long long row = row0 + r;
+    raw[r * kRawLd + j] = row < n ? snaps[j][row] : 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x < kChunk) {
+    const int r = threadIdx.x;
+    const double* x = raw + r * kRawLd;
+    double c = 0.0, nw = 0.0;
+    for (int j = 0; j < w; ++j) c += x[j];
+    for (int j = nsnap - w; j < nsnap; ++j) nw += x[j];
+    c = c / (double)w;
+    nw = nw / (double)w;
+    centre[r] = c;
+    if (psi_new && row0 + r < n) psi_new[row0 + r] = nw;
+  }
+  __syncthreads();
+}
 
 // Row loader of the centred window; also writes psi_new for its rows.
 struct WindowLoader {
-  SnapPtrs s;
+  const double* const* snaps;   // device table of nsnap pointers
   int nsnap, w;
   long long n;
   double* psi_new;
   __device__ void load(long long row0, double* X, int ldx, int wp) const {
-    // thread t handles row row0 + (t % 64), snapshots j = t / 64, t / 64 + 4, ...
-    // Means are computed by one thread per row (sequential sums in snapshot
-    // order, then a division by w, exactly as stated).
-    const int r = threadIdx.x % kChunk;
-    const long long row = row0 + r;
-    __shared__ double centre_s[kChunk];
-    if (threadIdx.x < kChunk) {
-      double c = 0.0, nw = 0.0;
-      if (row < n) {
-        for (int j = 0; j < w; ++j) c += s.p[j][row];
-        for (int j = nsnap - w; j < nsnap; ++j) nw += s.p[j][row];
-        c = c / (double)w;
-        nw = nw / (double)w;
-        psi_new[row] = nw;
-      }
-      centre_s[r] = c;
-    }
-    __syncthreads();
+    __shared__ double raw[kChunk * kRawLd];
+    __shared__ double centre[kChunk];
+    stage_window(snaps, nsnap, w, n, row0, raw, centre, psi_new);
     const int off = nsnap - w;
-    for (int j = threadIdx.x / kChunk; j < wp; j += blockDim.x / kChunk) {
-      double v = 0.0;
-      if (row < n && j < w) v = s.p[off + j][row] - centre_s[r];
-      X[r * ldx + j] = v;
+    for (int idx = threadIdx.x; idx < kChunk * wp; idx += blockDim.x) {
+      const int r = idx / wp, j = idx % wp;
+      X[r * ldx + j] = j < w ? raw[r * kRawLd + off + j] - centre[r] : 0.0;
     }
   }
 };
 
 // Eigen-decomposition of G (w x w) and the formation matrix
 // T = V_m diag(1/sigma) (w x mp, zero padded), sigma (w), m_eff.
-__global__ void __launch_bounds__(64) basis_eig_kernel(const double* __restrict__ G, int w, int m,
+__global__ void __launch_bounds__(256) basis_eig_kernel(const double* __restrict__ G, int w, int m,
                                                        double tau, double* __restrict__ sigma,
                                                        double* __restrict__ T, int mp,
                                                        int* __restrict__ m_eff_out) {
@@ -67,7 +73,7 @@ __global__ void __launch_bounds__(64) basis_eig_kernel(const double* __restrict_
   __shared__ int meff;
   const int lda = kMaxBasis + 1;
   const int t = threadIdx.x;
-  for (int e = t; e < w * w; e += kWave) A[(e / w) * lda + e % w] = G[e];
+  for (int e = t; e < w * w; e += blockDim.x) A[(e / w) * lda + e % w] = G[e];
   __syncthreads();
   jacobi_eig_wave(A, V, lda, w, lam, order, 40);
   if (t == 0) {
@@ -83,7 +89,7 @@ __global__ void __launch_bounds__(64) basis_eig_kernel(const double* __restrict_
   }
   __syncthreads();
   // T[:, i] = sign_i * V[:, order[i]] / sigma_i, sign making the largest |entry| positive
-  for (int i = t; i < mp; i += kWave) {
+  for (int i = t; i < mp; i += blockDim.x) {
     if (i < meff) {
       const int col = order[i];
       int best = 0;
@@ -101,15 +107,15 @@ __global__ void __launch_bounds__(64) basis_eig_kernel(const double* __restrict_
   }
 }
 
-// Phi = X T for rows of the window (centred on the fly with the stored
-// centring state).  C^T = T^T X^T so that each 16-lane group writes 16
-// consecutive rows of one column.
-__global__ void __launch_bounds__(256) basis_form_kernel(SnapPtrs s, int nsnap, int w, long long n,
-                                                         const double* __restrict__ T, int mp, int wp,
-                                                         int meff, double* __restrict__ Phi) {
-  __shared__ double X[kChunk * (kMaxBasis + 1)];
+// Phi = X T for rows of the window (centred on the fly), on MFMA.
+// C^T = T^T X^T so that each 16-lane group writes 16 consecutive rows of one
+// column of Phi.
+__global__ void __launch_bounds__(256) basis_form_kernel(const double* const* __restrict__ snaps, int nsnap,
+                                                         int w, long long n, const double* __restrict__ T,
+                                                         int mp, int wp, int meff, double* __restrict__ Phi) {
+  __shared__ double raw[kChunk * kRawLd];
   __shared__ double Ts[kMaxBasis * (kMaxBasis + 1)];
-  __shared__ double centre_s[kChunk];
+  __shared__ double centre[kChunk];
   const int ldx = kMaxBasis + 1;
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   for (int e = threadIdx.x; e < wp * mp; e += blockDim.x) Ts[(e / mp) * ldx + e % mp] = T[(e / mp) * mp + e % mp];
@@ -118,28 +124,20 @@ __global__ void __launch_bounds__(256) basis_form_kernel(SnapPtrs s, int nsnap, 
   for (long long ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
     const long long row0 = ch * kChunk;
     __syncthreads();
-    const int r = threadIdx.x % kChunk;
-    const long long row = row0 + r;
-    if (threadIdx.x < kChunk) {
-      double c = 0.0;
-      if (row < n) {
-        for (int j = 0; j < w; ++j) c += s.p[j][row];
-        c = c / (double)w;
-      }
-      centre_s[r] = c;
+    stage_window(snaps, nsnap, w, n, row0, raw, centre, nullptr);
+    // centre the X columns in place (raw[r][off + j] -> x_j - centre)
+    for (int idx = threadIdx.x; idx < kChunk * wp; idx += blockDim.x) {
+      const int r = idx / wp, j = idx % wp;
+      raw[r * kRawLd + off + j] = j < w ? raw[r * kRawLd + off + j] - centre[r] : 0.0;
     }
     __syncthreads();
-    for (int j = threadIdx.x / kChunk; j < wp; j += blockDim.x / kChunk)
-      X[r * ldx + j] = (row < n && j < w) ? s.p[off + j][row] - centre_s[r] : 0.0;
-    __syncthreads();
-    // wave v: rows rb = v (16 rows), all column blocks
-    const int rb = wave;
+    const int rb = wave;   // 16 rows per wave
     for (int mb = 0; mb * 16 < mp; ++mb) {
       double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
       for (int k0 = 0; k0 < wp; k0 += 4) {
         const int k = k0 + lane / 16;
-        const double a = Ts[k * ldx + mb * 16 + lane % 16];     // A = T^T: A[c][k] = T[k][c]
-        const double b = X[(rb * 16 + lane % 16) * ldx + k];    // B[k][r] = X[r][k]
+        const double a = Ts[k * ldx + mb * 16 + lane % 16];                 // A = T^T: A[c][k] = T[k][c]
+        const double b = raw[(rb * 16 + lane % 16) * kRawLd + off + k];     // B[k][r] = X[r][k]
         acc = mfma_f64(a, b, acc);
       }
       const long long orow = row0 + rb * 16 + lane % 16;
@@ -164,29 +162,36 @@ extern "C" hs_status basis_update(hs_ctx* ctx, const double* const* snaps, int32
   if (m < 1 || m > ctx->p.m_max || m > w) return HS_ERR_INVALID_ARG;
   if (!(tau_pod >= 0.0 && tau_pod < 1.0)) return HS_ERR_INVALID_ARG;
   if (precision != HS_FP64) return ctx->fail(HS_ERR_INVALID_ARG, "basis_update: only HS_FP64 in this build");
-  SnapPtrs sp{};
-  for (int j = 0; j < nsnap; ++j) {
+  for (int j = 0; j < nsnap; ++j)
     if (!snaps[j]) return HS_ERR_INVALID_ARG;
-    sp.p[j] = snaps[j];
-  }
+  // pointer table to device memory through the pinned staging area
+  std::memcpy(ctx->hstage, snaps, nsnap * sizeof(double*));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->ptab, ctx->hstage, nsnap * sizeof(double*), hipMemcpyHostToDevice, ctx->stream));
+  const double* const* tab = const_cast<const double* const*>(ctx->ptab);
   const long long n = ctx->n;
   const int wp = (w + 15) / 16 * 16;
   const int mp = (m + 15) / 16 * 16;
   const long long nchunks = (n + kChunk - 1) / kChunk;
   const int nb = (int)std::min<long long>(nchunks, 512);
-  WindowLoader ld{sp, nsnap, w, n, psi_out};
+  WindowLoader ld{tab, nsnap, w, n, psi_out};
   const size_t lds = (size_t)kChunk * (wp + 1) * sizeof(double);
+  HS_TRY(prof_begin(ctx, HS_PROF_BASIS_GRAM));
   hipLaunchKernelGGL(gram_kernel<WindowLoader>, dim3(nb), dim3(256), lds, ctx->stream, ld, n, wp, ctx->red);
   HIP_TRY(ctx, hipGetLastError());
+  // reads every snapshot of the window once, writes psi_{k+1}
+  HS_TRY(prof_end(ctx, HS_PROF_BASIS_GRAM, 8.0 * (double)n * (nsnap + 1)));
   double* G = ctx->small;
   double* T = ctx->small + kMaxBasis * kMaxBasis;
   int* meff_d = reinterpret_cast<int*>(ctx->small + 3 * kMaxBasis * kMaxBasis);
-  HS_LAUNCH(ctx, gram_reduce_kernel, blocks_for(w * w), kBlock, ctx->red, nb, wp, w, G);
-  HS_LAUNCH(ctx, basis_eig_kernel, 1, 64, G, w, m, tau_pod, sigma_out, T, mp, meff_d);
+  HS_LAUNCH(ctx, gram_reduce_kernel, w * w, kBlock, ctx->red, nb, wp, w, G);
+  HS_LAUNCH(ctx, basis_eig_kernel, 1, 256, G, w, m, tau_pod, sigma_out, T, mp, meff_d);
   int me = 0;
   HS_TRY(readback(ctx, meff_d, sizeof(int), &me));
   *m_eff = me;
   if (me == 0) return HS_OK;
-  HS_LAUNCH(ctx, basis_form_kernel, nb, 256, sp, nsnap, w, n, T, mp, wp, me, Phi_out);
+  HS_TRY(prof_begin(ctx, HS_PROF_BASIS_FORM));
+  HS_LAUNCH(ctx, basis_form_kernel, nb, 256, tab, nsnap, w, n, T, mp, wp, me, Phi_out);
+  // reads every snapshot of the window once, writes m_eff columns of Phi
+  HS_TRY(prof_end(ctx, HS_PROF_BASIS_FORM, 8.0 * (double)n * (nsnap + me)));
   return HS_OK;
 }

@@ -66,6 +66,14 @@ struct hs_ctx {
   unsigned long long* stats = nullptr;   // kStatSlots
   int* ibuf = nullptr;        // integer scratch (ncell + 1024)
   void* hpin = nullptr;       // pinned host readback buffer (64 KiB)
+  void* hstage = nullptr;     // pinned host staging buffer for small uploads (64 KiB)
+  const double** ptab = nullptr;   // device table of snapshot pointers (128 entries)
+
+  // kernel timing (hs_prof_enable)
+  int prof_class = 0;
+  std::vector<hipEvent_t> prof_ev;   // start/stop pairs
+  std::vector<double> prof_bytes;
+  size_t prof_used = 0;
 
   hs_status fail(hs_status s, const std::string& msg) {
     err = msg;
@@ -243,4 +251,7 @@ hs_status cell_residual_norm(hs_ctx* ctx, const double* q, const double* q_prev,
                              double* sum_out);
 hs_status run_filter(hs_ctx* ctx, double* gamma, const double* q_prev, const hs_hybrid_params* hp,
                      hs_step_info* info);
+// Bracket one launch of kernel class cls with events (no-op unless enabled).
+hs_status prof_begin(hs_ctx* ctx, int cls);
+hs_status prof_end(hs_ctx* ctx, int cls, double bytes);
 }  // namespace hs

@@ -69,27 +69,32 @@ __global__ void __launch_bounds__(256) gram_kernel(Loader ld, long long nrows, i
   }
 }
 
-// Sum nb partial wp x wp matrices in block order; write the w x w result
-// (row-major, leading dimension w) to G.
+// Sum nb partial wp x wp matrices; one block per entry of the w x w result
+// (row-major, leading dimension w), a fixed strided order and a fixed tree.
 static __global__ void gram_reduce_kernel(const double* __restrict__ part, int nb, int wp, int w,
-                                   double* __restrict__ G) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= w * w) return;
+                                          double* __restrict__ G) {
+  __shared__ double lds[kBlock / kWave];
+  const int e = blockIdx.x;
   const int r = e / w, c = e % w;
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += part[(size_t)b * wp * wp + r * wp + c];
-  G[e] = s;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[(size_t)b * wp * wp + r * wp + c];
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) G[e] = s;
 }
 
 // ---------------------------------------------------------------- Jacobi
 // Symmetric eigendecomposition A = V diag(lam) V^T of an n x n matrix (n <= 64)
-// by cyclic Jacobi with round-robin parallel ordering, one wave.  On return
-// lam is sorted in descending order with V's columns permuted alike.
+// by cyclic Jacobi with round-robin parallel ordering (any block size that is
+// a multiple of 64).  A pair is rotated only if its off-diagonal entry exceeds
+// both eps * sqrt(|a_pp a_qq|) and eps * trace|A|: below the latter an entry
+// is rounding noise that cannot move any eigenvalue by more than rounding.  On
+// return lam is sorted in descending order with V's columns permuted alike.
 // A (n x n, row-major) is overwritten.  LDS: A, V (64 x 65 each).
 __device__ inline void jacobi_eig_wave(double* A, double* V, int lda, int n, double* lam, int* order,
                                        int max_sweeps) {
-  const int t = threadIdx.x;   // 0..63
-  for (int i = t; i < n * lda; i += kWave) V[i] = 0.0;
+  const int t = threadIdx.x;
+  const int nt = blockDim.x;
+  for (int i = t; i < n * lda; i += nt) V[i] = 0.0;
   __syncthreads();
   if (t < n) V[t * lda + t] = 1.0;
   __syncthreads();
@@ -99,9 +104,9 @@ __device__ inline void jacobi_eig_wave(double* A, double* V, int lda, int n, dou
   __shared__ int rotated;
   __shared__ double atol;
   if (t == 0) {
-    double dmax = 0.0;
-    for (int i = 0; i < n; ++i) dmax = fmax(dmax, fabs(A[i * lda + i]));
-    atol = 1e-18 * dmax;       // below this an off-diagonal entry cannot move any eigenvalue
+    double tr = 0.0;
+    for (int i = 0; i < n; ++i) tr += fabs(A[i * lda + i]);
+    atol = 2.2e-16 * tr;
   }
   __syncthreads();
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
@@ -122,7 +127,7 @@ __device__ inline void jacobi_eig_wave(double* A, double* V, int lda, int n, dou
         if (q < n) {
           const double apq = A[p * lda + q];
           const double app = A[p * lda + p], aqq = A[q * lda + q];
-          if (fabs(apq) > atol && fabs(apq) > 0.25 * 2.2e-16 * sqrt(fabs(app) * fabs(aqq))) {
+          if (fabs(apq) > atol && fabs(apq) > 2.2e-16 * sqrt(fabs(app) * fabs(aqq))) {
             const double tau = (aqq - app) / (2.0 * apq);
             const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + tt * tt);
@@ -134,7 +139,7 @@ __device__ inline void jacobi_eig_wave(double* A, double* V, int lda, int n, dou
       }
       __syncthreads();
       // rows: A <- J^T A
-      for (int e = t; e < (np / 2) * n; e += kWave) {
+      for (int e = t; e < (np / 2) * n; e += nt) {
         const int k = e / n, col = e % n;
         const int p = pp[k], q = qq[k];
         if (q >= n || sn[k] == 0.0) continue;
@@ -145,7 +150,7 @@ __device__ inline void jacobi_eig_wave(double* A, double* V, int lda, int n, dou
       }
       __syncthreads();
       // columns: A <- A J and V <- V J
-      for (int e = t; e < (np / 2) * n; e += kWave) {
+      for (int e = t; e < (np / 2) * n; e += nt) {
         const int k = e / n, row = e % n;
         const int p = pp[k], q = qq[k];
         if (q >= n || sn[k] == 0.0) continue;

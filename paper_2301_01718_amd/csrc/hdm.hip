@@ -42,6 +42,27 @@ hs_status readback(hs_ctx* ctx, const void* dsrc, size_t bytes, void* hdst) {
   return HS_OK;
 }
 
+hs_status prof_begin(hs_ctx* ctx, int cls) {
+  if (ctx->prof_class != cls || cls == 0) return HS_OK;
+  if (ctx->prof_used + 2 > ctx->prof_ev.size()) {
+    for (int k = 0; k < 64; ++k) {
+      hipEvent_t e;
+      HIP_TRY(ctx, hipEventCreate(&e));
+      ctx->prof_ev.push_back(e);
+    }
+  }
+  HIP_TRY(ctx, hipEventRecord(ctx->prof_ev[ctx->prof_used], ctx->stream));
+  return HS_OK;
+}
+
+hs_status prof_end(hs_ctx* ctx, int cls, double bytes) {
+  if (ctx->prof_class != cls || cls == 0) return HS_OK;
+  HIP_TRY(ctx, hipEventRecord(ctx->prof_ev[ctx->prof_used + 1], ctx->stream));
+  ctx->prof_used += 2;
+  ctx->prof_bytes.push_back(bytes);
+  return HS_OK;
+}
+
 hs_status zero_stats(hs_ctx* ctx) {
   HS_LAUNCH(ctx, fill_u64_kernel, 1, 64, ctx->stats, (int)kStatSlots, 0ull);
   return HS_OK;
@@ -301,8 +322,13 @@ static hs_status newton_impl(hs_ctx* ctx, double* q, const double* q_prev, doubl
   int sweeps_total = 0;
   for (int it = 0;; ++it) {
     HS_TRY(zero_stats(ctx));
+    HS_TRY(prof_begin(ctx, HS_PROF_RESJAC));
     HS_LAUNCH(ctx, resjac_kernel<NC>, nb, kBlock, g, q, q_prev, hat, nbr, count, cap, ctx->coef,
               ctx->rhs, ctx->stats);
+    // reads: state of the cell (+ 4 neighbours, counted once), q_prev, the
+    // list entries; writes: 4 NC x NC relaxation blocks and the NC-vector b
+    HS_TRY(prof_end(ctx, HS_PROF_RESJAC,
+                    (double)count * (8.0 * NC * 2 + 8.0 * (4 * NC * NC + NC) + (hat ? 4.0 * 5 : 0.0))));
     unsigned long long st[kStatSlots];
     HS_TRY(read_stats(ctx, st));
     const double rmax = bits_to_double(st[kStatResMax]);
@@ -336,14 +362,19 @@ static hs_status newton_impl(hs_ctx* ctx, double* q, const double* q_prev, doubl
       } else {
         const double* dold = ctx->rhs;
         double* bufs[2] = {ctx->d0, ctx->d1};
+        const double sweep_bytes =
+            (double)count * (8.0 * (4 * NC * NC + NC) + 8.0 * NC * 2 + (hat ? 4.0 * 5 : 0.0));
         for (int k = 2; k <= nsw; ++k) {
           double* dnew = bufs[k & 1];
+          HS_TRY(prof_begin(ctx, HS_PROF_SWEEP));
           if (k == nsw)
             HS_LAUNCH(ctx, (sweep_kernel<NC, true, false>), nb, kBlock, g, hat, nbr, count, cap, ctx->coef,
                       ctx->rhs, dold, dnew, q, ctx->stats);
           else
             HS_LAUNCH(ctx, (sweep_kernel<NC, false, false>), nb, kBlock, g, hat, nbr, count, cap, ctx->coef,
                       ctx->rhs, dold, dnew, q, ctx->stats);
+          // reads the relaxation blocks, b and the previous iterate; writes the new one
+          HS_TRY(prof_end(ctx, HS_PROF_SWEEP, sweep_bytes));
           dold = dnew;
         }
       }
@@ -432,10 +463,12 @@ hs_status hs_destroy(hs_ctx* ctx) {
   if (!ctx) return HS_ERR_INVALID_ARG;
   void* bufs[] = {ctx->u,    ctx->R,     ctx->rhs,    ctx->d0,  ctx->d1,    ctx->coef, ctx->rho,
                   ctx->gf,   ctx->gtmp,  ctx->rcell,  ctx->rcell2, ctx->red, ctx->small, ctx->stats,
-                  ctx->ibuf};
+                  ctx->ibuf, (void*)ctx->ptab};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
+  for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
   if (ctx->hpin) (void)hipHostFree(ctx->hpin);
+  if (ctx->hstage) (void)hipHostFree(ctx->hstage);
   delete ctx;
   return HS_OK;
 }
@@ -495,8 +528,10 @@ hs_status hs_create(const hs_problem* pr, void* stream, hs_ctx** out) {
   A((void**)&ctx->small, 16 * kMaxBasis * kMaxBasis * 8);
   A((void**)&ctx->stats, kStatSlots * 8);
   A((void**)&ctx->ibuf, (NC + 8192) * 4);
+  A((void**)&ctx->ptab, 128 * sizeof(double*));
   if (st == HS_OK) {
     hipError_t e = hipHostMalloc(&ctx->hpin, 65536, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(&ctx->hstage, 65536, hipHostMallocDefault);
     if (e != hipSuccess) st = ctx->fail(HS_ERR_OOM, "hipHostMalloc");
   }
   if (st != HS_OK) {
@@ -504,6 +539,32 @@ hs_status hs_create(const hs_problem* pr, void* stream, hs_ctx** out) {
     return st;
   }
   *out = ctx;
+  return HS_OK;
+}
+
+hs_status hs_prof_enable(hs_ctx* ctx, int32_t cls) {
+  if (!ctx || cls < HS_PROF_NONE || cls > HS_PROF_CELLRES) return HS_ERR_INVALID_ARG;
+  ctx->prof_class = cls;
+  ctx->prof_used = 0;
+  ctx->prof_bytes.clear();
+  return HS_OK;
+}
+
+hs_status hs_prof_read(hs_ctx* ctx, double* total_ms, int32_t* launches, double* bytes) {
+  if (!ctx || !total_ms || !launches || !bytes) return HS_ERR_INVALID_ARG;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  double ms = 0.0, b = 0.0;
+  for (size_t k = 0; k + 1 < ctx->prof_used; k += 2) {
+    float e = 0.f;
+    HIP_TRY(ctx, hipEventElapsedTime(&e, ctx->prof_ev[k], ctx->prof_ev[k + 1]));
+    ms += e;
+  }
+  for (double x : ctx->prof_bytes) b += x;
+  *total_ms = ms;
+  *launches = (int32_t)(ctx->prof_used / 2);
+  *bytes = b;
+  ctx->prof_used = 0;
+  ctx->prof_bytes.clear();
   return HS_OK;
 }
 

@@ -47,7 +47,7 @@ struct GatherLoader {
 };
 
 // Truncated pseudo-inverse of the m x m Gram: G+ = sum_{kept} v v^T / lambda.
-__global__ void __launch_bounds__(64) pinv_kernel(const double* __restrict__ G, int m, double rcond,
+__global__ void __launch_bounds__(256) pinv_kernel(const double* __restrict__ G, int m, double rcond,
                                                   double* __restrict__ Gp, double* __restrict__ misc) {
   __shared__ double A[kMaxBasis * (kMaxBasis + 1)], V[kMaxBasis * (kMaxBasis + 1)];
   __shared__ double lam[kMaxBasis];
@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(64) pinv_kernel(const double* __restrict__ G, 
   __shared__ int rank;
   const int lda = kMaxBasis + 1;
   const int t = threadIdx.x;
-  for (int e = t; e < m * m; e += kWave) A[(e / m) * lda + e % m] = G[e];
+  for (int e = t; e < m * m; e += blockDim.x) A[(e / m) * lda + e % m] = G[e];
   __syncthreads();
   jacobi_eig_wave(A, V, lda, m, lam, order, 40);
   if (t == 0) {
@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(64) pinv_kernel(const double* __restrict__ G, 
     misc[2] = k > 0 ? sqrt(lmax / lam[k - 1]) : 0.0;
   }
   __syncthreads();
-  for (int e = t; e < m * m; e += kWave) {
+  for (int e = t; e < m * m; e += blockDim.x) {
     const int r = e / m, c = e % m;
     double s = 0.0;
     for (int i = 0; i < rank; ++i) s += V[r * lda + order[i]] * V[c * lda + order[i]] / lam[i];
@@ -120,19 +120,23 @@ __global__ void __launch_bounds__(256) project_kernel(const double* __restrict__
     part[(size_t)blockIdx.x * MP + j] = ((wsum[0][j] + wsum[1][j]) + wsum[2][j]) + wsum[3][j];
 }
 
-// Reduce the projection partials in block order and apply the pseudo-inverse.
+// Reduce the projection partials and apply the pseudo-inverse.  Wave v sums
+// the partials of coefficients v, v + 4, ... (lanes stride the blocks in a
+// fixed order, then a fixed shuffle tree).
 // mode 0: y0 = G+ b.  mode 1: y = y0 + G+ b, ||y - y_prev|| to misc[0], y_prev = y.
-__global__ void __launch_bounds__(64) project_finish_kernel(const double* __restrict__ part, int nb, int mp,
-                                                            int m, const double* __restrict__ Gp, int mode,
-                                                            double* __restrict__ y0, double* __restrict__ y,
-                                                            double* __restrict__ yprev, double* __restrict__ misc,
-                                                            int first) {
+__global__ void __launch_bounds__(256) project_finish_kernel(const double* __restrict__ part, int nb, int mp,
+                                                             int m, const double* __restrict__ Gp, int mode,
+                                                             double* __restrict__ y0, double* __restrict__ y,
+                                                             double* __restrict__ yprev, double* __restrict__ misc,
+                                                             int first) {
   __shared__ double b[kMaxBasis], ynew[kMaxBasis];
   const int t = threadIdx.x;
-  if (t < m) {
+  const int lane = t % kWave, wave = t / kWave, nw = blockDim.x / kWave;
+  for (int j = wave; j < m; j += nw) {
     double s = 0.0;
-    for (int k = 0; k < nb; ++k) s += part[(size_t)k * mp + t];
-    b[t] = s;
+    for (int k = lane; k < nb; k += kWave) s += part[(size_t)k * mp + j];
+    s = wave_sum(s);
+    if (lane == 0) b[j] = s;
   }
   __syncthreads();
   if (t < m) {
@@ -300,8 +304,11 @@ hs_status cell_residual_norm(hs_ctx* ctx, const double* q, const double* q_prev,
                              double* sum_out) {
   const int nb = blocks_for(ctx->ncell);
   if (nb > kRedBlocks * 64) return ctx->fail(HS_ERR_SHAPE, "grid too large for the reduction buffer");
+  HS_TRY(prof_begin(ctx, HS_PROF_CELLRES));
   if (ctx->nc == 1) HS_LAUNCH(ctx, cellres_kernel<1>, nb, kBlock, ctx->g, q, q_prev, rcell, ctx->red);
   else HS_LAUNCH(ctx, cellres_kernel<4>, nb, kBlock, ctx->g, q, q_prev, rcell, ctx->red);
+  // reads q and q_prev (neighbours counted once), writes one norm per cell
+  HS_TRY(prof_end(ctx, HS_PROF_CELLRES, (double)ctx->ncell * (16.0 * ctx->nc + 8.0)));
   double* slot = ctx->small + kSmMisc + 8;
   HS_LAUNCH(ctx, sum_finish_kernel, 1, kBlock, ctx->red, nb, slot);
   return readback(ctx, slot, sizeof(double), sum_out);
@@ -387,8 +394,8 @@ static hs_status fit_factor(hs_ctx* ctx, const double* Phi, int m, const int* ha
   const size_t lds = (size_t)kChunk * (wp + 1) * sizeof(double);
   hipLaunchKernelGGL(gram_kernel<GatherLoader>, dim3(nb), dim3(256), lds, ctx->stream, ld, rows, wp, ctx->red);
   HIP_TRY(ctx, hipGetLastError());
-  HS_LAUNCH(ctx, gram_reduce_kernel, blocks_for(m * m), kBlock, ctx->red, nb, wp, m, ctx->small + kSmG);
-  HS_LAUNCH(ctx, pinv_kernel, 1, 64, ctx->small + kSmG, m, rcond, ctx->small + kSmGp, ctx->small + kSmMisc);
+  HS_LAUNCH(ctx, gram_reduce_kernel, m * m, kBlock, ctx->red, nb, wp, m, ctx->small + kSmG);
+  HS_LAUNCH(ctx, pinv_kernel, 1, 256, ctx->small + kSmG, m, rcond, ctx->small + kSmGp, ctx->small + kSmMisc);
   return HS_OK;
 }
 
@@ -398,10 +405,10 @@ static hs_status fit_solve(hs_ctx* ctx, const double* Phi, int m, const int* hat
   double* sm = ctx->small;
   int nb;
   HS_TRY(launch_project(ctx, Phi, m, hat, ns, u, psi, nullptr, 0, &nb));
-  HS_LAUNCH(ctx, project_finish_kernel, 1, 64, ctx->red, nb, pad16(m), m, sm + kSmGp, 0, sm + kSmY0, sm + kSmY,
+  HS_LAUNCH(ctx, project_finish_kernel, 1, 256, ctx->red, nb, pad16(m), m, sm + kSmGp, 0, sm + kSmY0, sm + kSmY,
             sm + kSmYPrev, sm + kSmMisc, first);
   HS_TRY(launch_project(ctx, Phi, m, hat, ns, u, psi, sm + kSmY0, 1, &nb));
-  HS_LAUNCH(ctx, project_finish_kernel, 1, 64, ctx->red, nb, pad16(m), m, sm + kSmGp, 1, sm + kSmY0, sm + kSmY,
+  HS_LAUNCH(ctx, project_finish_kernel, 1, 256, ctx->red, nb, pad16(m), m, sm + kSmGp, 1, sm + kSmY0, sm + kSmY,
             sm + kSmYPrev, sm + kSmMisc, first);
   return HS_OK;
 }
@@ -436,7 +443,7 @@ hs_status hs_indicator_full(hs_ctx* ctx, const double* gamma, const double* Phi,
   std::vector<double> eye(m * m, 0.0);
   for (int i = 0; i < m; ++i) eye[i * m + i] = 1.0;
   HIP_TRY(ctx, hipMemcpyAsync(sm + kSmGp, eye.data(), m * m * 8, hipMemcpyHostToDevice, ctx->stream));
-  HS_LAUNCH(ctx, project_finish_kernel, 1, 64, ctx->red, nb, pad16(m), m, sm + kSmGp, 0, sm + kSmY0, sm + kSmY,
+  HS_LAUNCH(ctx, project_finish_kernel, 1, 256, ctx->red, nb, pad16(m), m, sm + kSmGp, 0, sm + kSmY0, sm + kSmY,
             sm + kSmYPrev, sm + kSmMisc, 1);
   HS_LAUNCH(ctx, recon_kernel, blocks_for(ctx->n), kBlock, Phi, (long long)ctx->n, m, ctx->ncell, psi,
             sm + kSmY0, (const uint8_t*)nullptr, (const double*)nullptr, (double*)nullptr, ctx->rho);
@@ -494,8 +501,11 @@ hs_status rom_hybrid_step(hs_ctx* ctx, const double* q_prev, const double* Phi, 
     inf->dy_last = dy;
     if (j >= 2 && dy < hp->eps_y) break;
   }
+  HS_TRY(prof_begin(ctx, HS_PROF_RECON));
   HS_LAUNCH(ctx, recon_kernel, blocks_for(ctx->n), kBlock, Phi, (long long)ctx->n, m, ctx->ncell, psi, sm + kSmY,
             s->mask, u, q_out, ctx->rho);
+  // reads m columns of Phi, psi, u and the mask; writes gamma and rho
+  HS_TRY(prof_end(ctx, HS_PROF_RECON, 8.0 * (double)ctx->n * (m + 4) + (double)ctx->ncell));
   HS_TRY(run_filter(ctx, q_out, q_prev, hp, inf));
   if (eps_out) {
     double gmax;

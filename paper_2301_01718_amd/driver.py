@@ -70,56 +70,72 @@ class Arom:
     def slot(self, k):
         return self.ring[k % (self.cfg.w + 2)]
 
-    def run(self, q0, steps, on_step=None, on_update=None, timing=False):
-        cfg, c = self.cfg, self.ctx
+    def start(self, q0, steps):
+        """Load gamma_0 and reset the schedule for a run of ``steps`` steps."""
         self.slot(0).copy_(q0)
         self.m_eff = 0
-        have_samples = False
+        self.have_samples = False
+        self.k = 0
+        self.steps = steps
+
+    def advance(self, on_step=None, on_update=None):
+        """Compute step k+1 of Alg. 1 and the updates that follow it."""
+        cfg, c = self.cfg, self.ctx
+        self.k += 1
+        k = self.k
+        rec = {"k": k}
+        prev, out = self.slot(k - 1), self.slot(k)
+        used = {"q_prev": prev, "Phi": self.Phi, "psi": self.psi, "m": self.m_eff}
+        hybrid = not is_full_step(k, cfg.w, cfg.z) and self.have_samples and self.m_eff > 0
+        if hybrid:
+            try:
+                _, info = c.rom_hybrid_step(prev, self.Phi, self.psi, self.m_eff, self.samples,
+                                            self.hp, out=out, eps=self.eps)
+                rec.update(type="hybrid", n_s=info["n_s"], l=info["l"], J=info["subiters"],
+                           newton=info["newton_iters"], sweeps=info["lin_sweeps"],
+                           filter_passes=info["filter_passes"], fit_cond=info["fit_cond"])
+            except HsError as e:
+                if e.status not in (HS_ERR_NOT_CONVERGED, HS_ERR_RANK):
+                    raise
+                hybrid = False
+                rec["fallback"] = str(e)
+        if not hybrid:
+            _, info = c.hdm_step(prev, out=out)
+            rec.update(type="full", n_s=c.ncell, newton=info["newton_iters"], sweeps=info["lin_sweeps"])
+        if on_step is not None:
+            used["samples"] = self.samples if hybrid else None
+            on_step(k, rec, used, out)
+        self.have_samples = False
+        if wants_update(k, cfg.w, cfg.z, self.steps):
+            if k >= cfg.w and self.m_eff > 0:
+                if not hybrid:
+                    c.indicator_full(out, self.Phi, self.psi, self.m_eff, cfg.floor_rel, eps=self.eps)
+                c.sample_select(self.eps, cfg.fraction, cfg.halo, samples=self.samples)
+                cnt = self.samples.counts()
+                rec["n_g"] = cnt["n_g"]
+                self.have_samples = cnt["n_s"] > 0
+            lo = k - cfg.w if k >= cfg.w else 0
+            window = [self.slot(j) for j in range(lo, k + 1)]
+            self.m_eff = c.basis_update(window, cfg.w, cfg.m, self.Phi, self.psi, self.sigma,
+                                        cfg.tau_pod, cfg.precision)
+            rec["m_eff"] = self.m_eff
+            if on_update is not None:
+                on_update(k, rec, {"eps": self.eps, "samples": self.samples if self.have_samples else None,
+                                   "window": window, "Phi": self.Phi, "psi": self.psi,
+                                   "sigma": self.sigma, "m_eff": self.m_eff})
+        return rec
+
+    def state(self):
+        return self.slot(self.k)
+
+    def run(self, q0, steps, on_step=None, on_update=None, timing=False):
+        self.start(q0, steps)
         records = []
-        for k in range(1, steps + 1):
+        for _ in range(steps):
             t0 = time.perf_counter() if timing else 0.0
-            rec = {"k": k}
-            prev, out = self.slot(k - 1), self.slot(k)
-            used = {"q_prev": prev, "Phi": self.Phi, "psi": self.psi, "m": self.m_eff}
-            hybrid = not is_full_step(k, cfg.w, cfg.z) and have_samples and self.m_eff > 0
-            if hybrid:
-                try:
-                    _, info = c.rom_hybrid_step(prev, self.Phi, self.psi, self.m_eff, self.samples,
-                                                self.hp, out=out, eps=self.eps)
-                    rec.update(type="hybrid", n_s=info["n_s"], l=info["l"], J=info["subiters"],
-                               newton=info["newton_iters"], filter_passes=info["filter_passes"],
-                               fit_cond=info["fit_cond"])
-                except HsError as e:
-                    if e.status not in (HS_ERR_NOT_CONVERGED, HS_ERR_RANK):
-                        raise
-                    hybrid = False
-                    rec["fallback"] = str(e)
-            if not hybrid:
-                _, info = c.hdm_step(prev, out=out)
-                rec.update(type="full", n_s=c.ncell, newton=info["newton_iters"])
-            if on_step is not None:
-                used["samples"] = self.samples if hybrid else None
-                on_step(k, rec, used, out)
-            have_samples = False
-            if wants_update(k, cfg.w, cfg.z, steps):
-                if k >= cfg.w and self.m_eff > 0:
-                    if not hybrid:
-                        c.indicator_full(out, self.Phi, self.psi, self.m_eff, cfg.floor_rel, eps=self.eps)
-                    c.sample_select(self.eps, cfg.fraction, cfg.halo, samples=self.samples)
-                    cnt = self.samples.counts()
-                    rec["n_g"] = cnt["n_g"]
-                    have_samples = cnt["n_s"] > 0
-                lo = k - cfg.w if k >= cfg.w else 0
-                window = [self.slot(j) for j in range(lo, k + 1)]
-                self.m_eff = c.basis_update(window, cfg.w, cfg.m, self.Phi, self.psi, self.sigma,
-                                            cfg.tau_pod, cfg.precision)
-                rec["m_eff"] = self.m_eff
-                if on_update is not None:
-                    on_update(k, rec, {"eps": self.eps, "samples": self.samples if have_samples else None,
-                                       "window": window, "Phi": self.Phi, "psi": self.psi,
-                                       "sigma": self.sigma, "m_eff": self.m_eff})
+            rec = self.advance(on_step, on_update)
             if timing:
-                torch.cuda.synchronize(c.device)
+                torch.cuda.synchronize(self.ctx.device)
                 rec["seconds"] = time.perf_counter() - t0
             records.append(rec)
         return self.slot(steps), records

@@ -4,10 +4,12 @@
 // One pass over the window forms, row by row, both window means (the
 // centring state psi_k over the first w snapshots and psi_{k+1} over the last
 // w), the centred row of X = [gamma_j - psi_k] and accumulates the Gram
-// matrix X^T X on FP64 MFMA.  A one-wave Jacobi eigensolver gives
+// matrix X^T X on FP64 MFMA.  A pivoted Cholesky reduction to the numerical
+// rank and a Jacobi eigensolver on the reduced matrix give
 // X^T X = V diag(sigma^2) V^T; a second pass forms Phi = X V_m diag(1/sigma_m),
 // the left singular vectors, again on MFMA.  The traffic is two reads of the
 // window and one write of Phi (the method-of-snapshots minimum).
+// Kernels using stage_centred must run with 256 threads (four waves).
 #include "dense.hpp"
 
 #include <algorithm>
@@ -16,31 +18,53 @@
 namespace hs {
 
 constexpr int kMaxSnaps = kMaxBasis + 1;
-constexpr int kRawLd = kMaxSnaps + 1;   // LDS leading dimension of the raw snapshot tile
+constexpr int kPerWave = (kMaxSnaps + 3) / 4;   // snapshots each of the four waves loads
 
-// Stage the rows row0 .. row0+63 of all nsnap snapshots into LDS (raw[r][j]),
-// every thread issuing independent coalesced loads, then let one thread per
-// row form the two window means by sequential sums in snapshot order.
-__device__ inline void stage_window(const double* const* __restrict__ snaps, int nsnap, int w, long long n,
-                                    long long row0, double* raw, double* centre, double* psi_new) {
-  for (int idx = threadIdx.x; idx < kChunk * nsnap; idx += blockDim.x) {
-    const int r = idx % kChunk, j = idx / kChunk;
-    const long long row = row0 + r;
-    raw[r * kRawLd + j] = row < n ? snaps[j][row] : 0.0;
+// Stage rows row0 .. row0+63 of the centred window into X (64 x ldx, LDS):
+// X[r][j] = snap[off + j][row0 + r] - centre[r] for j < w, 0 for w <= j < wp.
+// Lane = row, wave q loads snapshots q, q+4, ... (wave-uniform pointers), all
+// loads independent and in flight together.  The centring state (mean of the
+// first w snapshots) and psi_new (mean of the last w) are summed per wave
+// over its snapshots and the four partial sums combined in a fixed order.
+// Needs 256 threads; the caller synchronises before reading X.
+__device__ inline void stage_centred(const double* const* __restrict__ snaps, int nsnap, int w, long long n,
+                                     long long row0, double* X, int ldx, int wp, double* psi_new) {
+  __shared__ double part_c[4][kChunk], part_n[4][kChunk], centre[kChunk];
+  const int lane = threadIdx.x % kChunk;
+  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x / kChunk);
+  const long long row = row0 + lane;
+  const bool ok = row < n;
+  const int off = nsnap - w;
+  double v[kPerWave];
+#pragma unroll
+  for (int i = 0; i < kPerWave; ++i) {
+    const int j = q + 4 * i;
+    v[i] = (j < nsnap && ok) ? snaps[j][row] : 0.0;
   }
+  double c = 0.0, nw = 0.0;
+#pragma unroll
+  for (int i = 0; i < kPerWave; ++i) {
+    const int j = q + 4 * i;
+    if (j < w) c += v[i];
+    if (j >= off && j < nsnap) nw += v[i];
+  }
+  part_c[q][lane] = c;
+  part_n[q][lane] = nw;
   __syncthreads();
   if (threadIdx.x < kChunk) {
-    const int r = threadIdx.x;
-    const double* x = raw + r * kRawLd;
-    double c = 0.0, nw = 0.0;
-    for (int j = 0; j < w; ++j) c += x[j];
-    for (int j = nsnap - w; j < nsnap; ++j) nw += x[j];
-    c = c / (double)w;
-    nw = nw / (double)w;
-    centre[r] = c;
-    if (psi_new && row0 + r < n) psi_new[row0 + r] = nw;
+    const double cc = ((part_c[0][lane] + part_c[1][lane]) + part_c[2][lane]) + part_c[3][lane];
+    const double nn = ((part_n[0][lane] + part_n[1][lane]) + part_n[2][lane]) + part_n[3][lane];
+    centre[lane] = cc / (double)w;
+    if (psi_new && ok) psi_new[row] = nn / (double)w;
   }
   __syncthreads();
+  const double ce = centre[lane];
+#pragma unroll
+  for (int i = 0; i < kPerWave; ++i) {
+    const int j = q + 4 * i;
+    if (j >= off && j < nsnap) X[lane * ldx + (j - off)] = ok ? v[i] - ce : 0.0;
+  }
+  for (int j = w + q; j < wp; j += 4) X[lane * ldx + j] = 0.0;
 }
 
 // Row loader of the centred window; also writes psi_new for its rows.
@@ -50,37 +74,101 @@ struct WindowLoader {
   long long n;
   double* psi_new;
   __device__ void load(long long row0, double* X, int ldx, int wp) const {
-    __shared__ double raw[kChunk * kRawLd];
-    __shared__ double centre[kChunk];
-    stage_window(snaps, nsnap, w, n, row0, raw, centre, psi_new);
-    const int off = nsnap - w;
-    for (int idx = threadIdx.x; idx < kChunk * wp; idx += blockDim.x) {
-      const int r = idx / wp, j = idx % wp;
-      X[r * ldx + j] = j < w ? raw[r * kRawLd + off + j] - centre[r] : 0.0;
-    }
+    stage_centred(snaps, nsnap, w, n, row0, X, ldx, wp, psi_new);
   }
 };
 
-// Eigen-decomposition of G (w x w) and the formation matrix
-// T = V_m diag(1/sigma) (w x mp, zero padded), sigma (w), m_eff.
+// Eigen-decomposition of the window Gram G (w x w, PSD) and the formation
+// matrix T = V_m diag(1/sigma) (w x mp, zero padded), sigma (w), m_eff.
+//  1. pivoted Cholesky G = P L L^T P^T + S, stopped when the largest remaining
+//     diagonal entry is below eps * trace(G) (S is then below the rounding
+//     level of G itself), giving L (w x r), r = numerical rank;
+//  2. Jacobi eigendecomposition of the small r x r matrix L^T L = W Lam W^T;
+//  3. eigenvectors of G: V = P L W Lam^{-1/2}; singular values sigma = sqrt(Lam).
+// One block of 256 threads.
 __global__ void __launch_bounds__(256) basis_eig_kernel(const double* __restrict__ G, int w, int m,
                                                        double tau, double* __restrict__ sigma,
                                                        double* __restrict__ T, int mp,
                                                        int* __restrict__ m_eff_out) {
-  __shared__ double A[kMaxBasis * (kMaxBasis + 1)], V[kMaxBasis * (kMaxBasis + 1)];
-  __shared__ double lam[kMaxBasis];
-  __shared__ int order[kMaxBasis];
-  __shared__ int meff;
-  const int lda = kMaxBasis + 1;
-  const int t = threadIdx.x;
-  for (int e = t; e < w * w; e += blockDim.x) A[(e / w) * lda + e % w] = G[e];
+  constexpr int lda = kMaxBasis + 1;
+  __shared__ double A[kMaxBasis * lda];   // G, then L^T L
+  __shared__ double L[kMaxBasis * lda];   // pivoted Cholesky factor (permuted rows)
+  __shared__ double W[kMaxBasis * lda];   // Jacobi eigenvectors of L^T L, then V = L W
+  __shared__ double d[kMaxBasis], lam[kMaxBasis];
+  __shared__ int perm[kMaxBasis], order[kMaxBasis];
+  __shared__ int rank, piv, meff;
+  __shared__ double tolc;
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int e = t; e < w * w; e += nt) A[(e / w) * lda + e % w] = G[e];
+  for (int e = t; e < kMaxBasis * lda; e += nt) L[e] = 0.0;
   __syncthreads();
-  jacobi_eig_wave(A, V, lda, w, lam, order, 40);
+  if (t < w) {
+    d[t] = A[t * lda + t];
+    perm[t] = t;
+  }
   if (t == 0) {
-    const double s0 = sqrt(fmax(lam[0], 0.0));
+    double tr = 0.0;
+    for (int i = 0; i < w; ++i) tr += fabs(A[i * lda + i]);
+    tolc = 2.2e-16 * tr;
+    rank = 0;
+  }
+  __syncthreads();
+  // 1. pivoted Cholesky (rows of L in pivot order: row i <-> index perm[i])
+  for (int k = 0; k < w; ++k) {
+    if (t == 0) {
+      int p = k;
+      double best = d[perm[k]];
+      for (int i = k + 1; i < w; ++i)
+        if (d[perm[i]] > best) { best = d[perm[i]]; p = i; }
+      piv = best > tolc ? p : -1;
+      if (piv >= 0) rank = k + 1;
+    }
+    __syncthreads();
+    if (piv < 0) break;
+    if (piv != k) {   // swap pivot rows k <-> piv of perm and of L's first k columns
+      if (t < k) {
+        const double x = L[k * lda + t];
+        L[k * lda + t] = L[piv * lda + t];
+        L[piv * lda + t] = x;
+      }
+      __syncthreads();
+      if (t == 0) {
+        const int x = perm[k];
+        perm[k] = perm[piv];
+        perm[piv] = x;
+      }
+      __syncthreads();
+    }
+    const double lkk = sqrt(d[perm[k]]);
+    for (int i = k + t; i < w; i += nt) {
+      if (i == k) {
+        L[k * lda + k] = lkk;
+        continue;
+      }
+      double sacc = A[perm[i] * lda + perm[k]];
+      for (int j = 0; j < k; ++j) sacc -= L[i * lda + j] * L[k * lda + j];
+      const double lik = sacc / lkk;
+      L[i * lda + k] = lik;
+      d[perm[i]] -= lik * lik;
+    }
+    __syncthreads();
+  }
+  const int r = rank;
+  // 2. B = L^T L (r x r) into A, Jacobi
+  for (int e = t; e < r * r; e += nt) {
+    const int a = e / r, b = e % r;
+    double sacc = 0.0;
+    for (int i = 0; i < w; ++i) sacc += L[i * lda + a] * L[i * lda + b];
+    A[a * lda + b] = sacc;
+  }
+  __syncthreads();
+  if (r > 0) jacobi_eig_wave(A, W, lda, r, lam, order, 40);
+  // 3. sigma, m_eff
+  if (t == 0) {
+    const double s0 = r > 0 ? sqrt(fmax(lam[0], 0.0)) : 0.0;
     int me = 0;
     for (int i = 0; i < w; ++i) {
-      const double si = sqrt(fmax(lam[i], 0.0));
+      const double si = i < r ? sqrt(fmax(lam[i], 0.0)) : 0.0;
       sigma[i] = si;
       if (i < m && s0 > 0.0 && si > tau * s0) me = i + 1;
     }
@@ -88,56 +176,57 @@ __global__ void __launch_bounds__(256) basis_eig_kernel(const double* __restrict
     *m_eff_out = me;
   }
   __syncthreads();
-  // T[:, i] = sign_i * V[:, order[i]] / sigma_i, sign making the largest |entry| positive
-  for (int i = t; i < mp; i += blockDim.x) {
+  // V[:, i] = P L W[:, order[i]] / sqrt(lam_i) in original index order (stored in A)
+  for (int e = t; e < w * meff; e += nt) {
+    const int row = e / meff, i = e % meff;
+    const int col = order[i];
+    double sacc = 0.0;
+    for (int j = 0; j < r; ++j) sacc += L[row * lda + j] * W[j * lda + col];
+    A[perm[row] * lda + i] = sacc / sqrt(lam[i]);
+  }
+  __syncthreads();
+  // T[:, i] = sign_i V[:, i] / sigma_i, the sign making the largest |entry| positive
+  for (int i = t; i < mp; i += nt) {
     if (i < meff) {
-      const int col = order[i];
       int best = 0;
       double bv = -1.0;
-      for (int r = 0; r < w; ++r) {
-        const double a = fabs(V[r * lda + col]);
-        if (a > bv) { bv = a; best = r; }
+      for (int rr = 0; rr < w; ++rr) {
+        const double a = fabs(A[rr * lda + i]);
+        if (a > bv) { bv = a; best = rr; }
       }
-      const double sg = V[best * lda + col] >= 0.0 ? 1.0 : -1.0;
+      const double sg = A[best * lda + i] >= 0.0 ? 1.0 : -1.0;
       const double inv = sg / sqrt(lam[i]);
-      for (int r = 0; r < kMaxBasis; ++r) T[r * mp + i] = r < w ? V[r * lda + col] * inv : 0.0;
+      for (int rr = 0; rr < kMaxBasis; ++rr) T[rr * mp + i] = rr < w ? A[rr * lda + i] * inv : 0.0;
     } else {
-      for (int r = 0; r < kMaxBasis; ++r) T[r * mp + i] = 0.0;
+      for (int rr = 0; rr < kMaxBasis; ++rr) T[rr * mp + i] = 0.0;
     }
   }
 }
 
 // Phi = X T for rows of the window (centred on the fly), on MFMA.
 // C^T = T^T X^T so that each 16-lane group writes 16 consecutive rows of one
-// column of Phi.
+// column of Phi.  256 threads.
 __global__ void __launch_bounds__(256) basis_form_kernel(const double* const* __restrict__ snaps, int nsnap,
                                                          int w, long long n, const double* __restrict__ T,
                                                          int mp, int wp, int meff, double* __restrict__ Phi) {
-  __shared__ double raw[kChunk * kRawLd];
+  __shared__ double X[kChunk * (kMaxBasis + 1)];
   __shared__ double Ts[kMaxBasis * (kMaxBasis + 1)];
-  __shared__ double centre[kChunk];
   const int ldx = kMaxBasis + 1;
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   for (int e = threadIdx.x; e < wp * mp; e += blockDim.x) Ts[(e / mp) * ldx + e % mp] = T[(e / mp) * mp + e % mp];
-  const int off = nsnap - w;
   const long long nchunks = (n + kChunk - 1) / kChunk;
   for (long long ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
     const long long row0 = ch * kChunk;
     __syncthreads();
-    stage_window(snaps, nsnap, w, n, row0, raw, centre, nullptr);
-    // centre the X columns in place (raw[r][off + j] -> x_j - centre)
-    for (int idx = threadIdx.x; idx < kChunk * wp; idx += blockDim.x) {
-      const int r = idx / wp, j = idx % wp;
-      raw[r * kRawLd + off + j] = j < w ? raw[r * kRawLd + off + j] - centre[r] : 0.0;
-    }
+    stage_centred(snaps, nsnap, w, n, row0, X, ldx, wp, nullptr);
     __syncthreads();
     const int rb = wave;   // 16 rows per wave
     for (int mb = 0; mb * 16 < mp; ++mb) {
       double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
       for (int k0 = 0; k0 < wp; k0 += 4) {
         const int k = k0 + lane / 16;
-        const double a = Ts[k * ldx + mb * 16 + lane % 16];                 // A = T^T: A[c][k] = T[k][c]
-        const double b = raw[(rb * 16 + lane % 16) * kRawLd + off + k];     // B[k][r] = X[r][k]
+        const double a = Ts[k * ldx + mb * 16 + lane % 16];     // A = T^T: A[c][k] = T[k][c]
+        const double b = X[(rb * 16 + lane % 16) * ldx + k];    // B[k][r] = X[r][k]
         acc = mfma_f64(a, b, acc);
       }
       const long long orow = row0 + rb * 16 + lane % 16;

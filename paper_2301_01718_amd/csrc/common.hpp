@@ -38,6 +38,8 @@ enum StatSlot : int {
   kStatSlots = 8
 };
 
+constexpr int kPartCap = 4096;   // max blocks of a kernel that reports statistics
+
 }  // namespace hs
 
 // ------------------------------------------------------------------ context
@@ -64,6 +66,7 @@ struct hs_ctx {
   double* red = nullptr;      // reduction partials (kRedBlocks * 64 * 64 doubles)
   double* small = nullptr;    // small dense matrices and vectors (16 * 64 * 64 doubles)
   unsigned long long* stats = nullptr;   // kStatSlots
+  double* part = nullptr;     // per-block partial statistics: kStatSlots x kPartCap
   int* ibuf = nullptr;        // integer scratch (ncell + 1024)
   void* hpin = nullptr;       // pinned host readback buffer (64 KiB)
   void* hstage = nullptr;     // pinned host staging buffer for small uploads (64 KiB)
@@ -207,6 +210,12 @@ __device__ inline void stat_max(unsigned long long* slot, double x) {
   atomicMax(slot, dbits(x));
 }
 
+// Per-block partial of a statistic: part[slot * kPartCap + block].  A finish
+// kernel reduces the partials (no same-address atomics across blocks).
+__device__ inline void stat_part(double* part, int slot, double v) {
+  part[slot * kPartCap + blockIdx.x] = v;
+}
+
 // ---------------------------------------------------------- grid helpers
 // Neighbour of cell (i, j) across a face.  dir: 0 = W, 1 = E, 2 = S, 3 = N.
 // Returns the neighbour cell, the cell itself for a zeroth-order-extrapolation
@@ -243,6 +252,10 @@ namespace hs {
 hs_status readback(hs_ctx* ctx, const void* dsrc, size_t bytes, void* hdst);
 hs_status zero_stats(hs_ctx* ctx);
 hs_status read_stats(hs_ctx* ctx, unsigned long long* out /* kStatSlots */);
+// Reduce the per-block partials of the slots in max_mask (max) and sum_mask
+// (sum) over nb blocks into the stats slots (bit patterns of the doubles).
+hs_status finish_stats(hs_ctx* ctx, int nb, unsigned max_mask, unsigned sum_mask);
+inline int stat_blocks(long long n) { return blocks_for(n, kBlock, kPartCap); }
 hs_status max_abs(hs_ctx* ctx, const double* x, long long n, double* out);
 // Newton on the full mesh (hat == nullptr) or on a compact cell list.
 hs_status newton_solve(hs_ctx* ctx, double* q, const double* q_prev, double tol,

@@ -137,30 +137,47 @@ __device__ inline void jacobi_eig_wave(double* A, double* V, int lda, int n, dou
         }
         pp[t] = p; qq[t] = q; cs[t] = c; sn[t] = s;
       }
+      __shared__ int any;
+      if (t == 0) any = 0;
       __syncthreads();
-      // rows: A <- J^T A
-      for (int e = t; e < (np / 2) * n; e += nt) {
-        const int k = e / n, col = e % n;
-        const int p = pp[k], q = qq[k];
-        if (q >= n || sn[k] == 0.0) continue;
-        const double c = cs[k], s = sn[k];
-        const double ap = A[p * lda + col], aq = A[q * lda + col];
-        A[p * lda + col] = c * ap - s * aq;
-        A[q * lda + col] = s * ap + c * aq;
-      }
+      if (t < np / 2 && sn[t] != 0.0) any = 1;
       __syncthreads();
-      // columns: A <- A J and V <- V J
-      for (int e = t; e < (np / 2) * n; e += nt) {
-        const int k = e / n, row = e % n;
-        const int p = pp[k], q = qq[k];
-        if (q >= n || sn[k] == 0.0) continue;
-        const double c = cs[k], s = sn[k];
-        const double ap = A[row * lda + p], aq = A[row * lda + q];
-        A[row * lda + p] = c * ap - s * aq;
-        A[row * lda + q] = s * ap + c * aq;
-        const double vp = V[row * lda + p], vq = V[row * lda + q];
-        V[row * lda + p] = c * vp - s * vq;
-        V[row * lda + q] = s * vp + c * vq;
+      if (any) {
+        // A <- J^T A J on the disjoint 2x2 blocks (rows of pair k, columns of pair l)
+        const int P = np / 2;
+        for (int b = t; b < P * P; b += nt) {
+          const int k = b / P, l = b % P;
+          if (sn[k] == 0.0 && sn[l] == 0.0) continue;
+          const int rp = pp[k], rq = qq[k], cp = pp[l], cq = qq[l];
+          const bool rqv = rq < n, cqv = cq < n;
+          double a00 = A[rp * lda + cp];
+          double a01 = cqv ? A[rp * lda + cq] : 0.0;
+          double a10 = rqv ? A[rq * lda + cp] : 0.0;
+          double a11 = (rqv && cqv) ? A[rq * lda + cq] : 0.0;
+          const double ck = cs[k], sk = sn[k], cl = cs[l], sl = sn[l];
+          // rows
+          double b00 = ck * a00 - sk * a10, b01 = ck * a01 - sk * a11;
+          double b10 = sk * a00 + ck * a10, b11 = sk * a01 + ck * a11;
+          // columns
+          a00 = cl * b00 - sl * b01;
+          a01 = sl * b00 + cl * b01;
+          a10 = cl * b10 - sl * b11;
+          a11 = sl * b10 + cl * b11;
+          A[rp * lda + cp] = a00;
+          if (cqv) A[rp * lda + cq] = a01;
+          if (rqv) A[rq * lda + cp] = a10;
+          if (rqv && cqv) A[rq * lda + cq] = a11;
+        }
+        // V <- V J
+        for (int e = t; e < P * n; e += nt) {
+          const int l = e / n, row = e % n;
+          if (sn[l] == 0.0) continue;
+          const int p = pp[l], q = qq[l];
+          const double c = cs[l], s = sn[l];
+          const double vp = V[row * lda + p], vq = V[row * lda + q];
+          V[row * lda + p] = c * vp - s * vq;
+          V[row * lda + q] = s * vp + c * vq;
+        }
       }
       __syncthreads();
     }

@@ -6,11 +6,12 @@
 // iteration is delta <- b - sum_X M_X delta[X] with M_X = D^{-1} O_X and
 // b = -D^{-1} R.  The residual/Jacobian kernel also returns the contraction
 // bound rho = max_cells max_rows sum |M_X|.  When rho < 1 the sweep count
-// ceil(log(lin_rtol) / log(rho)) guarantees the requested accuracy of each
+// ceil(log(eta) / log(rho)) guarantees the requested accuracy eta of each
 // Newton correction in the max norm without any reduction inside the sweeps
 // (the scalar Burgers systems).  Otherwise (Euler, whose components have very
 // different scales, so the max-norm bound is loose although the iteration
 // contracts) the sweeps run in batches and stop on the fixed-point difference.
+// eta follows the residual (inexact Newton), floored at lin_rtol.
 #include "physics.hpp"
 
 #include <algorithm>
@@ -24,14 +25,32 @@ __global__ void fill_u64_kernel(unsigned long long* p, int n, unsigned long long
   if (i < n) p[i] = v;
 }
 
-__global__ void max_abs_kernel(const double* __restrict__ x, long long n, unsigned long long* slot) {
+__global__ void max_abs_kernel(const double* __restrict__ x, long long n, double* __restrict__ part) {
   __shared__ double lds[kBlock / kWave];
   double m = 0.0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     m = fmax(m, fabs(x[i]));
   m = block_max(m, lds);
-  if (threadIdx.x == 0) stat_max(slot, m);
+  if (threadIdx.x == 0) stat_part(part, kStatQMax, m);
+}
+
+// One block: reduce the partials of the flagged slots (fixed strided order and
+// a fixed tree) and store them as bit patterns in the stats slots.
+__global__ void finish_stats_kernel(const double* __restrict__ part, int nb, unsigned max_mask,
+                                    unsigned sum_mask, unsigned long long* __restrict__ stats) {
+  __shared__ double lds[kBlock / kWave];
+  for (int slot = 0; slot < kStatSlots; ++slot) {
+    const bool mx = (max_mask >> slot) & 1u, sm = (sum_mask >> slot) & 1u;
+    if (!mx && !sm) continue;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+      const double x = part[slot * kPartCap + b];
+      v = mx ? fmax(v, x) : v + x;
+    }
+    v = mx ? block_max(v, lds) : block_sum(v, lds);
+    if (threadIdx.x == 0) stats[slot] = dbits(v);
+  }
 }
 
 hs_status readback(hs_ctx* ctx, const void* dsrc, size_t bytes, void* hdst) {
@@ -72,9 +91,15 @@ hs_status read_stats(hs_ctx* ctx, unsigned long long* out) {
   return readback(ctx, ctx->stats, kStatSlots * sizeof(unsigned long long), out);
 }
 
+hs_status finish_stats(hs_ctx* ctx, int nb, unsigned max_mask, unsigned sum_mask) {
+  HS_LAUNCH(ctx, finish_stats_kernel, 1, kBlock, ctx->part, nb, max_mask, sum_mask, ctx->stats);
+  return HS_OK;
+}
+
 hs_status max_abs(hs_ctx* ctx, const double* x, long long n, double* out) {
-  HS_TRY(zero_stats(ctx));
-  HS_LAUNCH(ctx, max_abs_kernel, blocks_for(n, kBlock, 1024), kBlock, x, n, ctx->stats + kStatQMax);
+  const int nb = blocks_for(n, kBlock, 1024);
+  HS_LAUNCH(ctx, max_abs_kernel, nb, kBlock, x, n, ctx->part);
+  HS_TRY(finish_stats(ctx, nb, 1u << kStatQMax, 0u));
   unsigned long long st[kStatSlots];
   HS_TRY(read_stats(ctx, st));
   *out = bits_to_double(st[kStatQMax]);
@@ -177,12 +202,11 @@ template <int NC>
 __global__ void resjac_kernel(Grid g, const double* __restrict__ q, const double* __restrict__ qp,
                               const int* __restrict__ hat, const int* __restrict__ nbr, int count,
                               int cap, double* __restrict__ coef, double* __restrict__ rhs,
-                              unsigned long long* __restrict__ stats) {
+                              double* __restrict__ part) {
   __shared__ double lds[kBlock / kWave];
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
   double rmax = 0.0, rho = 0.0;
   bool bad = false;
-  if (p < count) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < count; p += gridDim.x * blockDim.x) {
     const int cell = hat ? hat[p] : p;
     Stencil<NC> st;
     load_stencil<NC>(g, q, cell, st);
@@ -232,9 +256,8 @@ __global__ void resjac_kernel(Grid g, const double* __restrict__ q, const double
   rmax = block_max(bad ? INFINITY : rmax, lds);
   rho = block_max(rho, lds);
   if (threadIdx.x == 0) {
-    stat_max(&stats[kStatResMax], rmax);
-    stat_max(&stats[kStatRho], rho);
-    if (!isfinite(rmax)) atomicMax(&stats[kStatNonFinite], 1ull);
+    stat_part(part, kStatResMax, rmax);
+    stat_part(part, kStatRho, rho);
   }
 }
 
@@ -244,7 +267,7 @@ template <int NC, bool FINAL, bool RECORD>
 __global__ void sweep_kernel(Grid g, const int* __restrict__ hat, const int* __restrict__ nbr, int count,
                              int cap, const double* __restrict__ coef, const double* __restrict__ rhs,
                              const double* __restrict__ dold, double* __restrict__ dnew,
-                             double* __restrict__ q, unsigned long long* __restrict__ stats) {
+                             double* __restrict__ q, double* __restrict__ part) {
   __shared__ double lds[kBlock / kWave];
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   double diff = 0.0, dn = 0.0;
@@ -291,8 +314,8 @@ __global__ void sweep_kernel(Grid g, const int* __restrict__ hat, const int* __r
     diff = block_max(diff, lds);
     dn = block_max(dn, lds);
     if (threadIdx.x == 0) {
-      stat_max(&stats[kStatDiff], diff);
-      stat_max(&stats[kStatDnorm], dn);
+      stat_part(part, kStatDiff, diff);
+      stat_part(part, kStatDnorm, dn);
     }
   }
 }
@@ -321,19 +344,20 @@ static hs_status newton_impl(hs_ctx* ctx, double* q, const double* q_prev, doubl
   const int nb = blocks_for(count);
   int sweeps_total = 0;
   for (int it = 0;; ++it) {
-    HS_TRY(zero_stats(ctx));
+    const int nbs = stat_blocks(count);
     HS_TRY(prof_begin(ctx, HS_PROF_RESJAC));
-    HS_LAUNCH(ctx, resjac_kernel<NC>, nb, kBlock, g, q, q_prev, hat, nbr, count, cap, ctx->coef,
-              ctx->rhs, ctx->stats);
+    HS_LAUNCH(ctx, resjac_kernel<NC>, nbs, kBlock, g, q, q_prev, hat, nbr, count, cap, ctx->coef,
+              ctx->rhs, ctx->part);
     // reads: state of the cell (+ 4 neighbours, counted once), q_prev, the
     // list entries; writes: 4 NC x NC relaxation blocks and the NC-vector b
     HS_TRY(prof_end(ctx, HS_PROF_RESJAC,
                     (double)count * (8.0 * NC * 2 + 8.0 * (4 * NC * NC + NC) + (hat ? 4.0 * 5 : 0.0))));
+    HS_TRY(finish_stats(ctx, nbs, (1u << kStatResMax) | (1u << kStatRho), 0u));
     unsigned long long st[kStatSlots];
     HS_TRY(read_stats(ctx, st));
     const double rmax = bits_to_double(st[kStatResMax]);
     const double rho = bits_to_double(st[kStatRho]);
-    if (st[kStatNonFinite] || !std::isfinite(rmax))
+    if (!std::isfinite(rmax))
       return ctx->fail(HS_ERR_NONFINITE, "non-finite residual in Newton solve");
     if (info) {
       info->residual_inf = rmax;
@@ -351,10 +375,15 @@ static hs_status newton_impl(hs_ctx* ctx, double* q, const double* q_prev, doubl
       return ctx->fail(HS_ERR_NOT_CONVERGED, msg);
     }
     if (!std::isfinite(rho)) return ctx->fail(HS_ERR_NONFINITE, "non-finite Jacobian");
+    // Inexact Newton: the correction needs relative accuracy eta ~ ||R|| (the
+    // quadratic term is of that size anyway) and never beyond what brings the
+    // next residual to a tenth of the tolerance; lin_rtol is the floor.
+    const double scale = std::max(1.0, tol / ctx->p.newton_rtol);
+    const double eta = std::min(0.1, std::max(lin_rtol, std::max(rmax / scale, 0.1 * tol / rmax)));
     if (rho < 1.0) {
-      // fixed sweep count from the contraction bound: rho^nsw <= lin_rtol
+      // fixed sweep count from the contraction bound: rho^nsw <= eta
       int nsw = 1;
-      if (rho > 0.0) nsw = (int)std::ceil(std::log(lin_rtol) / std::log(rho));
+      if (rho > 0.0) nsw = (int)std::ceil(std::log(eta) / std::log(rho));
       nsw = std::max(1, std::min(nsw, ctx->p.lin_maxit));
       sweeps_total += nsw;
       if (nsw == 1) {
@@ -369,10 +398,10 @@ static hs_status newton_impl(hs_ctx* ctx, double* q, const double* q_prev, doubl
           HS_TRY(prof_begin(ctx, HS_PROF_SWEEP));
           if (k == nsw)
             HS_LAUNCH(ctx, (sweep_kernel<NC, true, false>), nb, kBlock, g, hat, nbr, count, cap, ctx->coef,
-                      ctx->rhs, dold, dnew, q, ctx->stats);
+                      ctx->rhs, dold, dnew, q, ctx->part);
           else
             HS_LAUNCH(ctx, (sweep_kernel<NC, false, false>), nb, kBlock, g, hat, nbr, count, cap, ctx->coef,
-                      ctx->rhs, dold, dnew, q, ctx->stats);
+                      ctx->rhs, dold, dnew, q, ctx->part);
           // reads the relaxation blocks, b and the previous iterate; writes the new one
           HS_TRY(prof_end(ctx, HS_PROF_SWEEP, sweep_bytes));
           dold = dnew;
@@ -384,6 +413,7 @@ static hs_status newton_impl(hs_ctx* ctx, double* q, const double* q_prev, doubl
       // difference, with the contraction factor estimated from successive
       // batches (error <= r/(1-r) * ||delta_{k+1} - delta_k||).
       constexpr int kBatch = 8;
+      if (nb > kPartCap) return ctx->fail(HS_ERR_SHAPE, "relaxation grid beyond the statistics capacity");
       const double* dold = ctx->rhs;
       double* bufs[2] = {ctx->d0, ctx->d1};
       int k = 1;
@@ -394,15 +424,15 @@ static hs_status newton_impl(hs_ctx* ctx, double* q, const double* q_prev, doubl
           double* dnew = bufs[k & 1];
           const bool rec = b == kBatch - 1 || k == ctx->p.lin_maxit - 1;
           if (rec) {
-            HS_TRY(zero_stats(ctx));
             HS_LAUNCH(ctx, (sweep_kernel<NC, false, true>), nb, kBlock, g, hat, nbr, count, cap, ctx->coef,
-                      ctx->rhs, dold, dnew, q, ctx->stats);
+                      ctx->rhs, dold, dnew, q, ctx->part);
           } else {
             HS_LAUNCH(ctx, (sweep_kernel<NC, false, false>), nb, kBlock, g, hat, nbr, count, cap, ctx->coef,
-                      ctx->rhs, dold, dnew, q, ctx->stats);
+                      ctx->rhs, dold, dnew, q, ctx->part);
           }
           dold = dnew;
         }
+        HS_TRY(finish_stats(ctx, nb, (1u << kStatDiff) | (1u << kStatDnorm), 0u));
         unsigned long long s2[kStatSlots];
         HS_TRY(read_stats(ctx, s2));
         const double diff = bits_to_double(s2[kStatDiff]);
@@ -411,7 +441,7 @@ static hs_status newton_impl(hs_ctx* ctx, double* q, const double* q_prev, doubl
         if (prev_diff > 0.0 && diff > 0.0)
           rate = std::min(0.99, std::pow(diff / prev_diff, 1.0 / kBatch));
         prev_diff = diff;
-        if (diff == 0.0 || (rate < 1.0 && rate / (1.0 - rate) * diff <= lin_rtol * dn)) {
+        if (diff == 0.0 || (rate < 1.0 && rate / (1.0 - rate) * diff <= eta * dn)) {
           conv = true;
           break;
         }
@@ -463,7 +493,7 @@ hs_status hs_destroy(hs_ctx* ctx) {
   if (!ctx) return HS_ERR_INVALID_ARG;
   void* bufs[] = {ctx->u,    ctx->R,     ctx->rhs,    ctx->d0,  ctx->d1,    ctx->coef, ctx->rho,
                   ctx->gf,   ctx->gtmp,  ctx->rcell,  ctx->rcell2, ctx->red, ctx->small, ctx->stats,
-                  ctx->ibuf, (void*)ctx->ptab};
+                  ctx->ibuf, (void*)ctx->ptab, ctx->part};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
@@ -529,6 +559,7 @@ hs_status hs_create(const hs_problem* pr, void* stream, hs_ctx** out) {
   A((void**)&ctx->stats, kStatSlots * 8);
   A((void**)&ctx->ibuf, (NC + 8192) * 4);
   A((void**)&ctx->ptab, 128 * sizeof(double*));
+  A((void**)&ctx->part, (size_t)kStatSlots * kPartCap * 8);
   if (st == HS_OK) {
     hipError_t e = hipHostMalloc(&ctx->hpin, 65536, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc(&ctx->hstage, 65536, hipHostMallocDefault);

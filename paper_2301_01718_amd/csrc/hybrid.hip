@@ -276,7 +276,7 @@ __global__ void sum_finish_kernel(const double* __restrict__ part, int nb, doubl
 template <int NC>
 __global__ void gate_kernel(Grid g, const double* __restrict__ cur, const double* __restrict__ gf,
                             const double* __restrict__ qp, const double* __restrict__ r,
-                            double* __restrict__ merged, unsigned long long* __restrict__ count) {
+                            double* __restrict__ merged, double* __restrict__ part) {
 #pragma clang fp contract(off)
   __shared__ int lds[kBlock / kWave];
   const int cell = blockIdx.x * blockDim.x + threadIdx.x;
@@ -297,7 +297,7 @@ __global__ void gate_kernel(Grid g, const double* __restrict__ cur, const double
       merged[a * g.ncell + cell] = keep ? gf[a * g.ncell + cell] : cur[a * g.ncell + cell];
   }
   keep = block_sum_int(keep, lds);
-  if (threadIdx.x == 0 && keep) atomicAdd(count, (unsigned long long)keep);
+  if (threadIdx.x == 0) stat_part(part, kStatCount, (double)keep);
 }
 
 hs_status cell_residual_norm(hs_ctx* ctx, const double* q, const double* q_prev, double* rcell,
@@ -328,6 +328,7 @@ static hs_status filter_apply(hs_ctx* ctx, const double* in, double* out, int no
 
 hs_status run_filter(hs_ctx* ctx, double* gamma, const double* q_prev, const hs_hybrid_params* hp,
                      hs_step_info* info) {
+  if (blocks_for(ctx->ncell) > kPartCap) return ctx->fail(HS_ERR_SHAPE, "grid beyond the statistics capacity");
   double* cur = gamma;
   double* spare = ctx->gtmp;
   double* r = ctx->rcell;
@@ -339,14 +340,14 @@ hs_status run_filter(hs_ctx* ctx, double* gamma, const double* q_prev, const hs_
     HS_TRY(cell_residual_norm(ctx, cur, q_prev, r, &sum_r));
     for (int it = 1; it <= hp->jfmax; ++it) {
       HS_TRY(filter_apply(ctx, cur, ctx->gf, nord));
-      HS_TRY(zero_stats(ctx));
       if (ctx->nc == 1)
-        HS_LAUNCH(ctx, gate_kernel<1>, nb, kBlock, ctx->g, cur, ctx->gf, q_prev, r, spare, ctx->stats + kStatCount);
+        HS_LAUNCH(ctx, gate_kernel<1>, nb, kBlock, ctx->g, cur, ctx->gf, q_prev, r, spare, ctx->part);
       else
-        HS_LAUNCH(ctx, gate_kernel<4>, nb, kBlock, ctx->g, cur, ctx->gf, q_prev, r, spare, ctx->stats + kStatCount);
+        HS_LAUNCH(ctx, gate_kernel<4>, nb, kBlock, ctx->g, cur, ctx->gf, q_prev, r, spare, ctx->part);
+      HS_TRY(finish_stats(ctx, nb, 0u, 1u << kStatCount));
       unsigned long long st[kStatSlots];
       HS_TRY(read_stats(ctx, st));
-      const long long kept = (long long)st[kStatCount];
+      const long long kept = (long long)bits_to_double(st[kStatCount]);
       if (info) {
         info->filter_passes += 1;
         info->filter_kept += (int)kept;

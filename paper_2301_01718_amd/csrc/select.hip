@@ -23,12 +23,12 @@ struct SelectState {
   long long k;                 // rank still to place within the current bucket
 };
 
-__global__ void count_positive_kernel(const double* __restrict__ eps, int n, unsigned long long* slot) {
+__global__ void count_positive_kernel(const double* __restrict__ eps, int n, double* __restrict__ part) {
   __shared__ int lds[kBlock / kWave];
   int c = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) c += eps[i] > 0.0;
   c = block_sum_int(c, lds);
-  if (threadIdx.x == 0 && c) atomicAdd(slot, (unsigned long long)c);
+  if (threadIdx.x == 0) stat_part(part, kStatCount, (double)c);
 }
 
 __global__ void radix_hist_kernel(const double* __restrict__ eps, int n, const SelectState* st, int shift,
@@ -366,11 +366,12 @@ hs_status sample_select(hs_ctx* ctx, const double* eps, const hs_sample_params* 
   const int n = ctx->ncell;
   const int nb = blocks_for(n);
   // n_g = min(ceil(f * ncell), #{eps > 0})
-  HS_TRY(zero_stats(ctx));
-  HS_LAUNCH(ctx, count_positive_kernel, blocks_for(n, kBlock, 1024), kBlock, eps, n, ctx->stats + kStatCount);
+  const int nbp = blocks_for(n, kBlock, 1024);
+  HS_LAUNCH(ctx, count_positive_kernel, nbp, kBlock, eps, n, ctx->part);
+  HS_TRY(finish_stats(ctx, nbp, 0u, 1u << kStatCount));
   unsigned long long st[kStatSlots];
   HS_TRY(read_stats(ctx, st));
-  const long long npos = (long long)st[kStatCount];
+  const long long npos = (long long)bits_to_double(st[kStatCount]);
   const long long want = (long long)std::ceil(sp->fraction * (double)n);
   const long long ng = std::min(want, npos);
   s->n_g = (int)ng;

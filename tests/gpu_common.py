@@ -63,3 +63,14 @@ def indicator_close(eg, eo, gamma, floor_rel=1e-11, tol=1e-13):
     near_floor = (np.minimum(np.where(a > 0, a, np.inf), np.where(b > 0, b, np.inf)) < 1.01 * fl)
     bad = (np.abs(a - b) > tol * scale) & ~near_floor
     return not bad.any(), float(np.max(np.abs(a - b)) / scale)
+
+
+def projector_tol(sigma, me, c=10.0):
+    """Bound on ||P_gpu X - P_oracle X|| / ||X|| for two rank-me POD projectors
+    built from the same window: both are within c * eps * lambda_0 of the exact
+    Gram matrix, so the projector moves by at most that over the eigenvalue gap
+    at the cut, (lambda_{me-1} - lambda_me) (Davis-Kahan)."""
+    lam = np.asarray(sigma, float) ** 2
+    nxt = lam[me] if me < lam.size else 0.0
+    gap = (lam[me - 1] - nxt) / lam[0]
+    return max(1e-12, c * 2.2e-16 / gap)

@@ -8,7 +8,8 @@ import pytest
 import workloads as W
 from oracle import fv, hybrid, pod, sampling
 
-from gpu_common import CASES, case, ctx_for, dev, host, indicator_close, need_gpu, print_case, rel, torch
+from gpu_common import (CASES, case, ctx_for, dev, host, indicator_close, need_gpu, print_case,
+                        projector_tol, rel, torch)
 
 pytestmark = pytest.mark.gpu
 
@@ -116,7 +117,9 @@ def test_basis_update_matches_oracle(name, first):
     psi = ctx.empty()
     sig = torch.zeros(w, dtype=torch.float64, device="cuda")
     me = ctx.basis_update([dev(s) for s in snaps], w, m, Phi, psi, sig, tau_pod=1e-4)
-    assert np.array_equal(host(psi), o["psi_new"])
+    # the window means are summed in four fixed partial sums (a few ulps from
+    # the oracle's single sequential sum)
+    assert np.max(np.abs(host(psi) - o["psi_new"])) <= 1e-15 * np.max(np.abs(o["psi_new"]))
     sg, so = host(sig), o["sigma"]
     assert np.max(np.abs(sg ** 2 - so ** 2)) <= 1e-13 * so[0] ** 2
     assert me == o["m_eff"]
@@ -128,9 +131,8 @@ def test_basis_update_matches_oracle(name, first):
     X = o["X"]
     Pg = P @ (P.T @ X)
     Po = o["Phi"] @ (o["Phi"].T @ X)
-    gap = (so[me - 1] ** 2 - (so[me] ** 2 if me < w else 0.0)) / so[0] ** 2
-    tol = max(1e-12, 1e-15 / gap)
-    assert np.linalg.norm(Pg - Po) <= tol * np.linalg.norm(X), (np.linalg.norm(Pg - Po) / np.linalg.norm(X), gap)
+    tol = projector_tol(so, me)
+    assert np.linalg.norm(Pg - Po) <= tol * np.linalg.norm(X), (np.linalg.norm(Pg - Po) / np.linalg.norm(X), tol)
 
 
 @pytest.mark.parametrize("name", list(CASES))

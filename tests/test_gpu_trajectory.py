@@ -15,7 +15,7 @@ import pytest
 import workloads as W
 from oracle import arom, fv, hybrid, pod, sampling
 
-from gpu_common import ctx_for, dev, host, need_gpu, print_case, rel, torch
+from gpu_common import ctx_for, dev, host, need_gpu, print_case, projector_tol, rel, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -55,13 +55,13 @@ def run_checked(wl, seed, steps=None):
         lo = k - wl.w if k >= wl.w else 0
         window = [snaps[j] for j in range(lo, k + 1)]
         b = pod.pod(window, wl.w, wl.m)
-        assert np.array_equal(host(st["psi"]), b["psi_new"]), k
+        assert np.max(np.abs(host(st["psi"]) - b["psi_new"])) <= 1e-15 * np.max(np.abs(b["psi_new"])), k
         assert st["m_eff"] == b["m_eff"], (k, st["m_eff"], b["m_eff"])
         me = b["m_eff"]
         P = host(st["Phi"])[: me * prob.n].reshape(me, prob.n).T
         X = b["X"]
         d = np.linalg.norm(P @ (P.T @ X) - b["Phi"] @ (b["Phi"].T @ X)) / np.linalg.norm(X)
-        assert d < 1e-10, (k, d)
+        assert d <= projector_tol(b["sigma"], me), (k, d, projector_tol(b["sigma"], me))
 
     qT, recs = drv.run(dev(q0), steps, on_step=on_step, on_update=on_update)
     return prob, q0, host(qT), recs, errs, hyb

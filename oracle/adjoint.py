@@ -1,0 +1,255 @@
+"""Discrete adjoint of the hybrid-snapshot trajectory (oracle; test use only).
+
+The forward map u_0 -> u_T of Alg. 1 contains non-differentiable decisions:
+the step schedule, the sampled sets, the subiteration count J, the filter
+masks, the rank of the basis and of the fit.  The adjoint here (reading:
+SURVEY C-12) differentiates the map with all of them frozen at their forward
+values, and with the bases Phi_k and reference states psi_k frozen as well
+(they are functions of earlier snapshots; their derivatives are not taken).
+With those frozen, each step is a smooth map of its input gamma_{k-1}:
+
+* full step (eq. hdm): R(gamma_k; gamma_{k-1}) = 0, dR/dgamma_{k-1} = -I, so
+  the tangent is J^{-1} d and the adjoint J^{-T} lambda;
+* hybrid step (eq. hybrid, Sec. 2.3.2, Sec. 2.3.4): for j = 1..J the
+  restricted solve R_S(v_j, t_j; p) = 0 on the sampled cells (t_1 = p on the
+  neighbour ring), the fit y_j = A^+ (v_j - psi_S) with A = Phi on the sampled
+  rows, t_{j+1} = psi_T + Phi_T y_j; then psi + Phi y_J on the unsampled
+  cells, v_J on the sampled ones, and the frozen filter passes
+  g <- M (S g) + (1 - M) g, a linear map.
+
+Tangents (forward mode) and adjoints (reverse mode) are written separately so
+that the dot-product test <T v, w> = <v, T^T w> checks the transposition.
+The loss is L = 0.5 ||u_T - u_target||^2.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse.linalg as spla
+
+from workloads import BC_PERIODIC, BURGERS_1D, Problem
+
+from . import fv, pod, sampling
+from .arom import AromParams, is_full_step, wants_update
+from .hybrid import HybridParams, hybrid_step, shapiro
+
+
+# --------------------------------------------------------------------------
+# Forward with tape, and replay with frozen decisions
+# --------------------------------------------------------------------------
+
+def forward_with_tape(prob: Problem, q0, steps, p: AromParams):
+    """Alg. 1 as in oracle.arom.run, recording every step's frozen data."""
+    gammas = [q0.copy()]
+    basis = None
+    samples = None
+    tape = []
+    for k in range(1, steps + 1):
+        prev = gammas[-1]
+        hybrid = (not is_full_step(k, p.w, p.z) and samples is not None and samples["hat"].size > 0
+                  and basis is not None and basis[0].shape[1] > 0)
+        eps = None
+        if hybrid:
+            out = hybrid_step(prob, prev, basis[0], basis[1], samples["hat"], samples["tilde"], p.hybrid)
+            g = out["gamma"]
+            eps = out["eps"]
+            tape.append({"type": "hybrid", "hat": samples["hat"], "tilde": samples["tilde"],
+                         "Phi": basis[0], "psi": basis[1], "J": out["J"], "us": out["us"],
+                         "masks": out["masks"], "out": g})
+        else:
+            g, _ = fv.hdm_step(prob, prev)
+            tape.append({"type": "full", "out": g})
+        gammas.append(g)
+        samples = None
+        if wants_update(k, p.w, p.z, steps):
+            if k >= p.w and basis is not None and basis[0].shape[1] > 0:
+                if eps is None:
+                    eps, _ = sampling.indicator_full(prob, g, basis[0], basis[1], p.hybrid.floor_rel)
+                samples = sampling.select(prob, eps, p.rule, p.fraction, p.delta, p.halo)
+            window = gammas[k - p.w:k + 1] if k >= p.w else gammas[0:k + 1]
+            b = pod.pod(window, p.w, p.m, p.tau_pod)
+            basis = (b["Phi"], b["psi_new"])
+    return gammas[-1], tape
+
+
+def replay_hybrid(prob: Problem, q_prev, st, params: HybridParams):
+    """The hybrid step with J, the sets, the basis and the filter masks frozen."""
+    hd = fv.dofs_of_cells(prob, st["hat"])
+    td = fv.dofs_of_cells(prob, st["tilde"])
+    Phi, psi = st["Phi"], st["psi"]
+    u = q_prev.copy()
+    for _ in range(st["J"]):
+        u, _ = fv.partial_hdm_solve(prob, u, q_prev, st["hat"])
+        y, *_ = np.linalg.lstsq(Phi[hd], u[hd] - psi[hd], rcond=params.rcond_fit)
+        u[td] = psi[td] + Phi[td] @ y
+    g = psi + Phi @ y
+    g[hd] = u[hd]
+    for n, keep in st["masks"]:
+        g = np.where(np.tile(keep, prob.ncomp), shapiro(prob, g, n), g)
+    return g
+
+
+def replay(prob: Problem, q0, tape, params: HybridParams):
+    q = q0.copy()
+    for st in tape:
+        if st["type"] == "full":
+            q, _ = fv.hdm_step(prob, q)
+        else:
+            q = replay_hybrid(prob, q, st, params)
+    return q
+
+
+# --------------------------------------------------------------------------
+# Linear pieces
+# --------------------------------------------------------------------------
+
+def _stencil_weights(n):
+    """Weights of (-delta^2/4)^n on a line (length 2n+1)."""
+    e = np.zeros(4 * n + 1)
+    e[2 * n] = 1.0
+    w = e
+    for _ in range(n):
+        w = -(w[:-2] - 2.0 * w[1:-1] + w[2:]) / 4.0
+    return w[::-1]                  # correlation weights for offsets -n..n
+
+
+def shapiro_1d_T(prob: Problem, h, n, axis):
+    """Transpose of the 1D filter along ``axis`` of a (c, ny, nx) array.
+
+    The filter is S = I - K E with E the extension by n cells (periodic wrap or
+    repetition of the boundary value) and K the (2n+1)-point stencil on the
+    extended line; so S^T = I - E^T K^T."""
+    w = _stencil_weights(n)
+    L = h.shape[axis]
+    shape = list(h.shape)
+    shape[axis] = L + 2 * n
+    full = np.zeros(shape)
+    for k in range(2 * n + 1):          # K^T: scatter h back onto the extended line
+        sl = [slice(None)] * 3
+        sl[axis] = slice(k, k + L)
+        full[tuple(sl)] += w[k] * h
+    take = lambda a, b: np.take(full, np.arange(a, b), axis=axis)
+    out = take(n, n + L).copy()
+    if prob.bc == BC_PERIODIC:          # E^T: wrapped margins return to their cells
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        lo[axis] = slice(L - n, L)
+        hi[axis] = slice(0, n)
+        out[tuple(lo)] += take(0, n)
+        out[tuple(hi)] += take(n + L, L + 2 * n)
+    else:                               # E^T: repeated boundary values return to it
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        lo[axis] = slice(0, 1)
+        hi[axis] = slice(L - 1, L)
+        out[tuple(lo)] += np.sum(take(0, n), axis=axis, keepdims=True)
+        out[tuple(hi)] += np.sum(take(n + L, L + 2 * n), axis=axis, keepdims=True)
+    return h - out
+
+
+def shapiro_T(prob: Problem, q, n):
+    """Transpose of the 2D filter S = S_y S_x (S^T = S_x^T S_y^T)."""
+    g = fv.as_grid(prob, q)
+    if prob.kind != BURGERS_1D:
+        g = shapiro_1d_T(prob, g, n, 1)
+    g = shapiro_1d_T(prob, g, n, 2)
+    return g.reshape(-1)
+
+
+def _split_jacobian(prob: Problem, u, hat, tilde):
+    J = fv.jacobian(prob, u)
+    hd = fv.dofs_of_cells(prob, hat)
+    td = fv.dofs_of_cells(prob, tilde)
+    Jh = J[hd][:, hd].tocsc()
+    Jt = J[hd][:, td].tocsc() if td.size else None
+    return Jh, Jt, hd, td
+
+
+def _pinv(st, hd, params):
+    return np.linalg.pinv(st["Phi"][hd], rcond=params.rcond_fit)
+
+
+# --------------------------------------------------------------------------
+# Tangents
+# --------------------------------------------------------------------------
+
+def full_step_tangent(prob: Problem, q_out, d):
+    return spla.spsolve(fv.jacobian(prob, q_out).tocsc(), d)
+
+
+def hybrid_step_tangent(prob: Problem, st, d, params: HybridParams):
+    Phi = st["Phi"]
+    hd = fv.dofs_of_cells(prob, st["hat"])
+    td = fv.dofs_of_cells(prob, st["tilde"])
+    Ap = _pinv(st, hd, params)
+    dt = d[td]
+    for j in range(st["J"]):
+        Jh, Jt, _, _ = _split_jacobian(prob, st["us"][j], st["hat"], st["tilde"])
+        rhs = d[hd] - (Jt @ dt if Jt is not None else 0.0)
+        dv = spla.spsolve(Jh, rhs)
+        dy = Ap @ dv
+        dt = Phi[td] @ dy
+    g = Phi @ dy
+    g[hd] = dv
+    for n, keep in st["masks"]:
+        g = np.where(np.tile(keep, prob.ncomp), shapiro(prob, g, n), g)
+    return g
+
+
+# --------------------------------------------------------------------------
+# Adjoints
+# --------------------------------------------------------------------------
+
+def full_step_adjoint(prob: Problem, q_out, lam):
+    return spla.spsolve(fv.jacobian(prob, q_out).T.tocsc(), lam)
+
+
+def hybrid_step_adjoint(prob: Problem, st, lam, params: HybridParams):
+    Phi = st["Phi"]
+    N = prob.n
+    hd = fv.dofs_of_cells(prob, st["hat"])
+    td = fv.dofs_of_cells(prob, st["tilde"])
+    Ap = _pinv(st, hd, params)
+    g = lam.copy()
+    for n, keep in reversed(st["masks"]):          # pass map P = D S + (I - D)
+        km = np.tile(keep, prob.ncomp)
+        g = shapiro_T(prob, np.where(km, g, 0.0), n) + np.where(km, 0.0, g)
+    breve = np.ones(N, bool)
+    breve[hd] = False
+    ybar = Phi[breve].T @ g[breve]
+    vbar = g[hd].copy()
+    tbar_next = np.zeros(td.size)
+    pbar = np.zeros(N)
+    for j in reversed(range(st["J"])):
+        ybar_j = (ybar if j == st["J"] - 1 else 0.0) + Phi[td].T @ tbar_next
+        vbar_j = (vbar if j == st["J"] - 1 else 0.0) + Ap.T @ ybar_j
+        Jh, Jt, _, _ = _split_jacobian(prob, st["us"][j], st["hat"], st["tilde"])
+        mu = spla.spsolve(Jh.T.tocsc(), vbar_j)
+        pbar[hd] += mu
+        tbar_next = -(Jt.T @ mu) if Jt is not None else np.zeros(0)
+    pbar[td] += tbar_next
+    return pbar
+
+
+def step_adjoint(prob: Problem, st, lam, params: HybridParams):
+    if st["type"] == "full":
+        return full_step_adjoint(prob, st["out"], lam)
+    return hybrid_step_adjoint(prob, st, lam, params)
+
+
+def step_tangent(prob: Problem, st, d, params: HybridParams):
+    if st["type"] == "full":
+        return full_step_tangent(prob, st["out"], d)
+    return hybrid_step_tangent(prob, st, d, params)
+
+
+def gradient(prob: Problem, tape, qT, target, params: HybridParams):
+    """dL/du_0 for L = 0.5 ||u_T - u_target||^2 through the frozen trajectory."""
+    lam = qT - target
+    for st in reversed(tape):
+        lam = step_adjoint(prob, st, lam, params)
+    return lam
+
+
+def loss(qT, target):
+    d = qT - target
+    return 0.5 * float(d @ d)

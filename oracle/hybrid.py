@@ -82,8 +82,9 @@ def shapiro(prob: Problem, q, n):
     return g.reshape(-1)
 
 
-def spatial_filter(prob: Problem, gamma, q_prev, params: HybridParams, log=None):
-    """Residual-gated filter sequence.  Returns the filtered state."""
+def spatial_filter(prob: Problem, gamma, q_prev, params: HybridParams, log=None, masks=None):
+    """Residual-gated filter sequence.  Returns the filtered state.  If
+    ``masks`` is a list, every applied pass appends (n, kept-cell mask)."""
     c = prob.ncomp
     gamma = gamma.copy()
     for n in params.filter_orders:
@@ -99,6 +100,8 @@ def spatial_filter(prob: Problem, gamma, q_prev, params: HybridParams, log=None)
                 break
             km = np.tile(keep, c)
             gamma = np.where(km, gf, gamma)
+            if masks is not None:
+                masks.append((n, keep.copy()))
             r_new = fv.cell_residual_norm(prob, gamma, q_prev)
             s_old = np.sum(r)
             s_new = np.sum(r_new)
@@ -121,8 +124,10 @@ def fit(Phi_rows, d, rcond):
 def hybrid_step(prob: Problem, q_prev, Phi, psi, hat, tilde, params: HybridParams = None):
     """One hybrid snapshot gamma_k from gamma_{k-1} = q_prev.
 
-    Returns dict(gamma, y, J, eps, rho, newton) where rho = psi + Phi y is the
-    reconstruction and eps the indicator of the filtered snapshot."""
+    Returns dict(gamma, y, J, eps, rho, newton, us, masks) where rho = psi + Phi y
+    is the reconstruction, eps the indicator of the filtered snapshot, us the
+    state after each subiteration's Newton solve and masks the applied filter
+    passes (the decisions the adjoint keeps frozen)."""
     params = params or HybridParams()
     hd = fv.dofs_of_cells(prob, hat)
     td = fv.dofs_of_cells(prob, tilde)
@@ -130,10 +135,12 @@ def hybrid_step(prob: Problem, q_prev, Phi, psi, hat, tilde, params: HybridParam
     u = q_prev.copy()             # v_hat guess and v_tilde^(1) both from gamma_{k-1}
     y_old = None
     newton = []
+    us = []
     J = 0
     for j in range(1, params.jmax + 1):
         u, its = fv.partial_hdm_solve(prob, u, q_prev, hat)
         newton.append(its)
+        us.append(u.copy())
         y = fit(Phi_hat, u[hd] - psi[hd], params.rcond_fit)
         u[td] = psi[td] + Phi[td] @ y
         J = j
@@ -143,8 +150,8 @@ def hybrid_step(prob: Problem, q_prev, Phi, psi, hat, tilde, params: HybridParam
     rho = psi + Phi @ y
     gamma = rho.copy()
     gamma[hd] = u[hd]
-    flog = []
-    gamma = spatial_filter(prob, gamma, q_prev, params, flog)
+    flog, masks = [], []
+    gamma = spatial_filter(prob, gamma, q_prev, params, flog, masks)
     eps = indicator(prob, gamma, rho, params.floor_rel)
     return {"gamma": gamma, "y": y, "J": J, "eps": eps, "rho": rho,
-            "newton": newton, "filter_log": flog}
+            "newton": newton, "filter_log": flog, "us": us, "masks": masks}

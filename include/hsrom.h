@@ -206,6 +206,48 @@ hs_status rom_hybrid_step(hs_ctx* ctx, const double* q_prev, const double* Phi, 
 hs_status hs_filter(hs_ctx* ctx, const double* gamma_in, const double* q_prev,
                     const hs_hybrid_params* params /* host */, double* gamma_out, hs_step_info* info);
 
+/* --------------------------------------------- adjoint (frozen decisions) */
+/* The adjoint differentiates the trajectory map with every decision of the
+ * forward run frozen: the step schedule, the sampled sets, the subiteration
+ * count J, the filter masks and the bases (Phi_k, psi_k).  A hybrid step's
+ * decisions are kept in a library-owned tape. */
+typedef struct hs_htape hs_htape;
+#define HS_TAPE_RECORD 0   /* normal hybrid step; copy its decisions into the tape */
+#define HS_TAPE_REPLAY 1   /* rerun with the tape's decisions; record its internal states */
+
+hs_status hs_htape_create(hs_ctx* ctx, hs_htape** out /* host */);
+hs_status hs_htape_destroy(hs_htape* tape);
+/* Inspect a recorded tape: J, the number of applied filter passes and their
+ * orders (passes: host array of at least 64 entries, may be NULL) and their
+ * kept-cell masks (device, npass x ncell bytes, may be NULL). */
+hs_status hs_htape_info(const hs_htape* tape, int32_t* J /* host */, int32_t* npass /* host */,
+                        int32_t* passes /* host */, uint8_t* masks /* device */);
+/* The sampled set a tape holds (borrowed: owned and freed by the tape). */
+hs_status hs_htape_samples(hs_htape* tape, hs_samples** out /* host */);
+/* rom_hybrid_step with a tape.  HS_TAPE_RECORD: as rom_hybrid_step (s are the
+ * sets to use), and the tape keeps a copy of the sampled set, J and every
+ * applied filter pass (order and kept-cell mask).  HS_TAPE_REPLAY: s is
+ * ignored; the step runs exactly the tape's J subiterations on its sets and
+ * applies its filter passes and masks without gating, recording the state
+ * after each subiteration's Newton solve and the fit's pseudo-inverse.  With
+ * the same q_prev, Phi, psi and m, a replay reproduces the recorded output. */
+hs_status rom_hybrid_step_taped(hs_ctx* ctx, const double* q_prev, const double* Phi, const double* psi,
+                                int32_t m, const hs_samples* s, const hs_hybrid_params* params /* host */,
+                                double* q_out, double* eps_out, hs_step_info* info /* host */,
+                                hs_htape* tape, int32_t mode);
+/* lam_out = (d gamma_k / d gamma_{k-1})^T lam_in for a full step whose output
+ * is q_out: solves J(q_out)^T lam_out = lam_in (eq. hdm: dR/dq_prev = -I) by
+ * transposed block-Jacobi relaxation to relative accuracy 1e-12. */
+hs_status hdm_step_adjoint(hs_ctx* ctx, const double* q_out, const double* lam_in, double* lam_out,
+                           hs_step_info* info /* host, may be NULL */);
+/* lam_out = (d gamma_k / d gamma_{k-1})^T lam_in for a hybrid step replayed
+ * into tape (HS_TAPE_REPLAY) with basis Phi (m columns).  Reverse order of the
+ * forward: transposed filter passes, Phi^T on the unsampled rows, then per
+ * subiteration (last first) Phi^T on the ring, the pseudo-inverse transpose,
+ * a transposed restricted Newton-matrix solve and the coupling to the ring. */
+hs_status rom_hybrid_step_adjoint(hs_ctx* ctx, const double* Phi, int32_t m, const hs_htape* tape,
+                                  const double* lam_in, double* lam_out, hs_step_info* info /* host */);
+
 /* ------------------------------------------------------- measurement */
 /* Kernel classes that can be timed with HIP events on the context's stream. */
 #define HS_PROF_NONE        0

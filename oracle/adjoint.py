@@ -71,21 +71,24 @@ def forward_with_tape(prob: Problem, q0, steps, p: AromParams):
     return gammas[-1], tape
 
 
-def replay_hybrid(prob: Problem, q_prev, st, params: HybridParams):
-    """The hybrid step with J, the sets, the basis and the filter masks frozen."""
+def replay_hybrid(prob: Problem, q_prev, st, params: HybridParams, states=False):
+    """The hybrid step with J, the sets, the basis and the filter masks frozen.
+    With ``states`` also the state after each subiteration's Newton solve."""
     hd = fv.dofs_of_cells(prob, st["hat"])
     td = fv.dofs_of_cells(prob, st["tilde"])
     Phi, psi = st["Phi"], st["psi"]
     u = q_prev.copy()
+    us = []
     for _ in range(st["J"]):
         u, _ = fv.partial_hdm_solve(prob, u, q_prev, st["hat"])
+        us.append(u.copy())
         y, *_ = np.linalg.lstsq(Phi[hd], u[hd] - psi[hd], rcond=params.rcond_fit)
         u[td] = psi[td] + Phi[td] @ y
     g = psi + Phi @ y
     g[hd] = u[hd]
     for n, keep in st["masks"]:
         g = np.where(np.tile(keep, prob.ncomp), shapiro(prob, g, n), g)
-    return g
+    return (g, us) if states else g
 
 
 def replay(prob: Problem, q0, tape, params: HybridParams):

@@ -23,6 +23,7 @@ HS_ERR_RANK = -4
 
 BURGERS_1D, BURGERS_2D, EULER_2D = 0, 1, 2
 RULE_FRACTION, RULE_RRE = 0, 1
+TAPE_RECORD, TAPE_REPLAY = 0, 1
 FP64, MIXED_FP32 = 0, 1
 
 
@@ -100,6 +101,14 @@ _SIGS = {
     "rom_hybrid_step": [P, P, P, P, I32, P, ctypes.POINTER(HybridParams), P, P, P,
                         ctypes.POINTER(StepInfo)],
     "hs_filter": [P, P, P, ctypes.POINTER(HybridParams), P, ctypes.POINTER(StepInfo)],
+    "hs_htape_create": [P, ctypes.POINTER(P)],
+    "hs_htape_destroy": [P],
+    "hs_htape_info": [P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32), P],
+    "hs_htape_samples": [P, ctypes.POINTER(P)],
+    "rom_hybrid_step_taped": [P, P, P, P, I32, P, ctypes.POINTER(HybridParams), P, P,
+                              ctypes.POINTER(StepInfo), P, I32],
+    "hdm_step_adjoint": [P, P, P, P, ctypes.POINTER(StepInfo)],
+    "rom_hybrid_step_adjoint": [P, P, I32, P, P, P, ctypes.POINTER(StepInfo)],
     "hs_prof_enable": [P, I32],
     "hs_prof_read": [P, ctypes.POINTER(D), ctypes.POINTER(I32), ctypes.POINTER(D)],
 }
@@ -261,14 +270,82 @@ class Context:
         return out, info.as_dict()
 
 
-class Samples:
-    """Library-owned sampled sets (hat-S, tilde-S, mask)."""
+    # ------------------------------------------------------------- adjoint
+    def tape(self):
+        return Tape(self)
+
+    def rom_hybrid_step_taped(self, q_prev, Phi, psi, m, tape, mode, samples=None, params=None, out=None,
+                              eps=None):
+        params = params or hybrid_params()
+        out = self.empty() if out is None else out
+        info = StepInfo()
+        self._check(lib().rom_hybrid_step_taped(self.h, _ptr(self._in(q_prev)), _ptr(Phi), _ptr(self._in(psi)), m,
+                                                samples.h if samples is not None else None, ctypes.byref(params),
+                                                _ptr(self._in(out)), _ptr(eps), ctypes.byref(info), tape.h, mode))
+        return out, info.as_dict()
+
+    def hdm_step_adjoint(self, q_out, lam, out=None):
+        out = self.empty() if out is None else out
+        info = StepInfo()
+        self._check(lib().hdm_step_adjoint(self.h, _ptr(self._in(q_out)), _ptr(self._in(lam)), _ptr(self._in(out)),
+                                           ctypes.byref(info)))
+        return out, info.as_dict()
+
+    def rom_hybrid_step_adjoint(self, Phi, m, tape, lam, out=None):
+        out = self.empty() if out is None else out
+        info = StepInfo()
+        self._check(lib().rom_hybrid_step_adjoint(self.h, _ptr(Phi), m, tape.h, _ptr(self._in(lam)),
+                                                  _ptr(self._in(out)), ctypes.byref(info)))
+        return out, info.as_dict()
+
+
+class Tape:
+    """Library-owned record of one hybrid step's frozen decisions."""
 
     def __init__(self, ctx: Context):
         self.ctx = ctx
         h = P()
-        ctx._check(lib().hs_samples_create(ctx.h, ctypes.byref(h)))
+        ctx._check(lib().hs_htape_create(ctx.h, ctypes.byref(h)))
         self.h = h
+
+    def info(self):
+        """(J, [(n, kept-cell mask tensor), ...]) of the recorded step."""
+        J, npass = I32(0), I32(0)
+        passes = (I32 * 64)()
+        self.ctx._check(lib().hs_htape_info(self.h, ctypes.byref(J), ctypes.byref(npass), passes, None))
+        masks = torch.empty(max(npass.value, 1) * self.ctx.ncell, dtype=torch.uint8, device=self.ctx.device)
+        self.ctx._check(lib().hs_htape_info(self.h, None, None, None, _ptr(masks)))
+        nc = self.ctx.ncell
+        return J.value, [(passes[k], masks[k * nc:(k + 1) * nc]) for k in range(npass.value)]
+
+    def samples(self):
+        """The sampled set the tape holds (owned by the tape)."""
+        h = P()
+        self.ctx._check(lib().hs_htape_samples(self.h, ctypes.byref(h)))
+        return Samples(self.ctx, handle=h, owner=self)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hs_htape_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Samples:
+    """Library-owned sampled sets (hat-S, tilde-S, mask)."""
+
+    def __init__(self, ctx: Context, handle=None, owner=None):
+        self.ctx = ctx
+        self.owner = owner          # set for a set borrowed from another object
+        if handle is None:
+            handle = P()
+            ctx._check(lib().hs_samples_create(ctx.h, ctypes.byref(handle)))
+        self.h = handle
 
     def counts(self):
         c = (I32 * 3)()
@@ -285,7 +362,8 @@ class Samples:
 
     def close(self):
         if getattr(self, "h", None):
-            lib().hs_samples_destroy(self.h)
+            if self.owner is None:
+                lib().hs_samples_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -63,6 +63,7 @@ struct hs_ctx {
   double* gtmp = nullptr;     // N  filter scratch / merged state
   double* rcell = nullptr;    // ncell cell residual norms
   double* rcell2 = nullptr;   // ncell cell residual norms
+  double* adj = nullptr;      // N  adjoint work vector
   double* red = nullptr;      // reduction partials (kRedBlocks * 64 * 64 doubles)
   double* small = nullptr;    // small dense matrices and vectors (16 * 64 * 64 doubles)
   unsigned long long* stats = nullptr;   // kStatSlots
@@ -98,6 +99,33 @@ struct hs_samples {
   int32_t* nbr = nullptr;     // 4 * ncell, compact index of each stencil neighbour in hat-S or -1
   int32_t* scan = nullptr;    // scan scratch
 };
+
+// A hybrid step's frozen decisions (and, after a replay, its internal states).
+constexpr int kMaxPasses = 64;
+struct hs_htape {
+  hs_ctx* ctx = nullptr;
+  hs_samples* s = nullptr;    // copy of the sampled set
+  int J = 0;                  // subiterations
+  int npass = 0;              // applied filter passes
+  int passes[kMaxPasses] = {0};   // filter order n of each applied pass
+  uint8_t* masks = nullptr;   // kMaxPasses x ncell kept-cell masks
+  double* us = nullptr;       // J x N states after each subiteration's Newton solve (replay)
+  size_t us_cap = 0;          // capacity of us in doubles
+  double* gp = nullptr;       // fit pseudo-inverse (m x m, replay)
+  int m = 0;
+  bool recorded = false, replayed = false;
+};
+
+// Layout of ctx->small (offsets in doubles).
+constexpr int kSmG = 0;                 // Gram (m x m)
+constexpr int kSmGp = 4096;             // pseudo-inverse (m x m)
+constexpr int kSmY0 = 12288;            // y0
+constexpr int kSmY = 12288 + 64;        // y
+constexpr int kSmYPrev = 12288 + 128;   // previous y
+constexpr int kSmMisc = 12288 + 192;    // [0] = ||dy||, [1] = rank, [2] = cond, [8] = residual sum
+constexpr int kSmAdjY = 12288 + 256;    // adjoint: y-bar of the current subiteration
+constexpr int kSmAdjZ = 12288 + 320;    // adjoint: G+ y-bar
+constexpr int kSmAdjY0 = 12288 + 384;   // adjoint: y-bar from the reconstruction
 
 // ----------------------------------------------------------------- helpers
 #define HS_TRY(expr)                     \
@@ -263,7 +291,12 @@ hs_status newton_solve(hs_ctx* ctx, double* q, const double* q_prev, double tol,
 hs_status cell_residual_norm(hs_ctx* ctx, const double* q, const double* q_prev, double* rcell,
                              double* sum_out);
 hs_status run_filter(hs_ctx* ctx, double* gamma, const double* q_prev, const hs_hybrid_params* hp,
-                     hs_step_info* info);
+                     hs_step_info* info, hs_htape* record = nullptr);
+// Solve the linear system whose relaxation data (coef, rhs layout [.. * ncell + p])
+// is given, to relative accuracy eta; result in x (same layout).  rho is the
+// max-norm contraction bound of the relaxation (>= 1: monitored batches).
+hs_status relax_solve(hs_ctx* ctx, const int* hat, const int* nbr, int count, const double* coef,
+                      const double* rhs, double rho, double eta, double* x, int* sweeps);
 // Bracket one launch of kernel class cls with events (no-op unless enabled).
 hs_status prof_begin(hs_ctx* ctx, int cls);
 hs_status prof_end(hs_ctx* ctx, int cls, double bytes);

@@ -107,48 +107,6 @@ hs_status max_abs(hs_ctx* ctx, const double* x, long long n, double* out) {
 }
 
 // ------------------------------------------------------------ dense blocks
-// Inverse of a small row-major NC x NC matrix (Gauss-Jordan, partial pivoting).
-template <int NC>
-__device__ inline void small_inverse(const double A[NC * NC], double X[NC * NC]) {
-  if constexpr (NC == 1) {
-    X[0] = 1.0 / A[0];
-  } else {
-    double M[NC][2 * NC];
-#pragma unroll
-    for (int r = 0; r < NC; ++r)
-#pragma unroll
-      for (int c = 0; c < 2 * NC; ++c) M[r][c] = c < NC ? A[r * NC + c] : (c - NC == r ? 1.0 : 0.0);
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      int piv = k;
-      double best = fabs(M[k][k]);
-#pragma unroll
-      for (int r = k + 1; r < NC; ++r)
-        if (fabs(M[r][k]) > best) { best = fabs(M[r][k]); piv = r; }
-#pragma unroll
-      for (int c = 0; c < 2 * NC; ++c) {   // swap rows k and piv
-        const double t = M[k][c];
-        M[k][c] = M[piv][c];
-        M[piv][c] = t;
-      }
-      const double inv = 1.0 / M[k][k];
-#pragma unroll
-      for (int c = 0; c < 2 * NC; ++c) M[k][c] *= inv;
-#pragma unroll
-      for (int r = 0; r < NC; ++r) {
-        if (r == k) continue;
-        const double f = M[r][k];
-#pragma unroll
-        for (int c = 0; c < 2 * NC; ++c) M[r][c] -= f * M[k][c];
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < NC; ++r)
-#pragma unroll
-      for (int c = 0; c < NC; ++c) X[r * NC + c] = M[r][NC + c];
-  }
-}
-
 // --------------------------------------------------------- residual kernel
 template <int NC>
 __global__ void residual_kernel(Grid g, const double* __restrict__ q, const double* __restrict__ qp,
@@ -453,6 +411,79 @@ static hs_status newton_impl(hs_ctx* ctx, double* q, const double* q_prev, doubl
   }
 }
 
+template <int NC>
+__global__ void copy_compact_kernel(int count, int cap, const double* __restrict__ src, double* __restrict__ dst) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= count) return;
+#pragma unroll
+  for (int a = 0; a < NC; ++a) dst[a * cap + p] = src[a * cap + p];
+}
+
+template <int NC>
+static hs_status relax_impl(hs_ctx* ctx, const int* hat, const int* nbr, int count, const double* coef,
+                            const double* rhs, double rho, double eta, double* x, int* sweeps) {
+  const Grid& g = ctx->g;
+  const int cap = ctx->ncell;
+  const int nb = blocks_for(count);
+  double* bufs[2] = {ctx->d0, ctx->d1};
+  const double* dold = rhs;
+  int used = 1;
+  // fixed sweep count when the bound proves contraction within lin_maxit sweeps
+  int nsw = 1;
+  if (rho > 0.0 && rho < 1.0) nsw = std::max(1, (int)std::ceil(std::log(eta) / std::log(rho)));
+  if (rho < 1.0 && nsw <= ctx->p.lin_maxit) {
+    for (int k = 2; k <= nsw; ++k) {
+      double* dnew = bufs[k & 1];
+      HS_LAUNCH(ctx, (sweep_kernel<NC, false, false>), nb, kBlock, g, hat, nbr, count, cap, coef, rhs, dold, dnew,
+                (double*)nullptr, ctx->part);
+      dold = dnew;
+    }
+    used = nsw;
+  } else {
+    constexpr int kBatch = 8;
+    if (nb > kPartCap) return ctx->fail(HS_ERR_SHAPE, "relaxation grid beyond the statistics capacity");
+    int k = 1;
+    double prev_diff = -1.0, rate = 0.9;
+    bool conv = false;
+    while (k < ctx->p.lin_maxit) {
+      for (int b = 0; b < kBatch && k < ctx->p.lin_maxit; ++b, ++k) {
+        double* dnew = bufs[k & 1];
+        if (b == kBatch - 1 || k == ctx->p.lin_maxit - 1)
+          HS_LAUNCH(ctx, (sweep_kernel<NC, false, true>), nb, kBlock, g, hat, nbr, count, cap, coef, rhs, dold, dnew,
+                    (double*)nullptr, ctx->part);
+        else
+          HS_LAUNCH(ctx, (sweep_kernel<NC, false, false>), nb, kBlock, g, hat, nbr, count, cap, coef, rhs, dold,
+                    dnew, (double*)nullptr, ctx->part);
+        dold = dnew;
+      }
+      HS_TRY(finish_stats(ctx, nb, (1u << kStatDiff) | (1u << kStatDnorm), 0u));
+      unsigned long long s2[kStatSlots];
+      HS_TRY(read_stats(ctx, s2));
+      const double diff = bits_to_double(s2[kStatDiff]);
+      const double dn = bits_to_double(s2[kStatDnorm]);
+      if (!std::isfinite(diff)) return ctx->fail(HS_ERR_NONFINITE, "non-finite relaxation iterate");
+      if (prev_diff > 0.0 && diff > 0.0) rate = std::min(0.99, std::pow(diff / prev_diff, 1.0 / kBatch));
+      prev_diff = diff;
+      if (diff == 0.0 || (rate < 1.0 && rate / (1.0 - rate) * diff <= eta * dn)) {
+        conv = true;
+        break;
+      }
+    }
+    used = k;
+    if (!conv) return ctx->fail(HS_ERR_NOT_CONVERGED, "block-Jacobi relaxation did not converge");
+  }
+  HS_LAUNCH(ctx, copy_compact_kernel<NC>, nb, kBlock, count, cap, dold, x);
+  if (sweeps) *sweeps += used;
+  return HS_OK;
+}
+
+hs_status relax_solve(hs_ctx* ctx, const int* hat, const int* nbr, int count, const double* coef,
+                      const double* rhs, double rho, double eta, double* x, int* sweeps) {
+  if (count == 0) return HS_OK;
+  if (ctx->nc == 1) return relax_impl<1>(ctx, hat, nbr, count, coef, rhs, rho, eta, x, sweeps);
+  return relax_impl<4>(ctx, hat, nbr, count, coef, rhs, rho, eta, x, sweeps);
+}
+
 hs_status newton_solve(hs_ctx* ctx, double* q, const double* q_prev, double tol, const hs_samples* s,
                        hs_step_info* info) {
   if (s && s->n_s == 0) return HS_OK;
@@ -493,7 +524,7 @@ hs_status hs_destroy(hs_ctx* ctx) {
   if (!ctx) return HS_ERR_INVALID_ARG;
   void* bufs[] = {ctx->u,    ctx->R,     ctx->rhs,    ctx->d0,  ctx->d1,    ctx->coef, ctx->rho,
                   ctx->gf,   ctx->gtmp,  ctx->rcell,  ctx->rcell2, ctx->red, ctx->small, ctx->stats,
-                  ctx->ibuf, (void*)ctx->ptab, ctx->part};
+                  ctx->ibuf, (void*)ctx->ptab, ctx->part, ctx->adj};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
@@ -559,6 +590,7 @@ hs_status hs_create(const hs_problem* pr, void* stream, hs_ctx** out) {
   A((void**)&ctx->stats, kStatSlots * 8);
   A((void**)&ctx->ibuf, (NC + 8192) * 4);
   A((void**)&ctx->ptab, 128 * sizeof(double*));
+  A((void**)&ctx->adj, N * 8);
   A((void**)&ctx->part, (size_t)kStatSlots * kPartCap * 8);
   if (st == HS_OK) {
     hipError_t e = hipHostMalloc(&ctx->hpin, 65536, hipHostMallocDefault);

@@ -19,14 +19,6 @@
 
 namespace hs {
 
-// small-buffer layout (doubles)
-constexpr int kSmG = 0;                 // Gram (m x m)
-constexpr int kSmGp = 4096;             // pseudo-inverse (m x m)
-constexpr int kSmY0 = 12288;            // y0
-constexpr int kSmY = 12288 + 64;        // y
-constexpr int kSmYPrev = 12288 + 128;   // previous y
-constexpr int kSmMisc = 12288 + 192;    // [0] = ||dy||, [1] = rank, [2] = cond
-
 // Gathered rows of Phi at the dofs of hat-S cells (all components).
 struct GatherLoader {
   const double* Phi;
@@ -276,7 +268,8 @@ __global__ void sum_finish_kernel(const double* __restrict__ part, int nb, doubl
 template <int NC>
 __global__ void gate_kernel(Grid g, const double* __restrict__ cur, const double* __restrict__ gf,
                             const double* __restrict__ qp, const double* __restrict__ r,
-                            double* __restrict__ merged, double* __restrict__ part) {
+                            double* __restrict__ merged, uint8_t* __restrict__ keep_out,
+                            double* __restrict__ part) {
 #pragma clang fp contract(off)
   __shared__ int lds[kBlock / kWave];
   const int cell = blockIdx.x * blockDim.x + threadIdx.x;
@@ -295,9 +288,19 @@ __global__ void gate_kernel(Grid g, const double* __restrict__ cur, const double
 #pragma unroll
     for (int a = 0; a < NC; ++a)
       merged[a * g.ncell + cell] = keep ? gf[a * g.ncell + cell] : cur[a * g.ncell + cell];
+    if (keep_out) keep_out[cell] = (uint8_t)keep;
   }
   keep = block_sum_int(keep, lds);
   if (threadIdx.x == 0) stat_part(part, kStatCount, (double)keep);
+}
+
+// Replay of a recorded pass: merged = mask ? gf : cur.
+__global__ void mask_blend_kernel(long long n, int ncell, const double* __restrict__ cur,
+                                  const double* __restrict__ gf, const uint8_t* __restrict__ mask,
+                                  double* __restrict__ merged) {
+  const long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  merged[r] = mask[r % ncell] ? gf[r] : cur[r];
 }
 
 hs_status cell_residual_norm(hs_ctx* ctx, const double* q, const double* q_prev, double* rcell,
@@ -327,8 +330,13 @@ static hs_status filter_apply(hs_ctx* ctx, const double* in, double* out, int no
 }
 
 hs_status run_filter(hs_ctx* ctx, double* gamma, const double* q_prev, const hs_hybrid_params* hp,
-                     hs_step_info* info) {
+                     hs_step_info* info, hs_htape* record) {
   if (blocks_for(ctx->ncell) > kPartCap) return ctx->fail(HS_ERR_SHAPE, "grid beyond the statistics capacity");
+  if (record) {
+    if ((long long)hp->n_orders * hp->jfmax > kMaxPasses)
+      return ctx->fail(HS_ERR_INVALID_ARG, "taped step: more filter passes possible than the tape holds");
+    record->npass = 0;
+  }
   double* cur = gamma;
   double* spare = ctx->gtmp;
   double* r = ctx->rcell;
@@ -340,10 +348,11 @@ hs_status run_filter(hs_ctx* ctx, double* gamma, const double* q_prev, const hs_
     HS_TRY(cell_residual_norm(ctx, cur, q_prev, r, &sum_r));
     for (int it = 1; it <= hp->jfmax; ++it) {
       HS_TRY(filter_apply(ctx, cur, ctx->gf, nord));
+      uint8_t* keep_out = record ? record->masks + (size_t)record->npass * ctx->ncell : nullptr;
       if (ctx->nc == 1)
-        HS_LAUNCH(ctx, gate_kernel<1>, nb, kBlock, ctx->g, cur, ctx->gf, q_prev, r, spare, ctx->part);
+        HS_LAUNCH(ctx, gate_kernel<1>, nb, kBlock, ctx->g, cur, ctx->gf, q_prev, r, spare, keep_out, ctx->part);
       else
-        HS_LAUNCH(ctx, gate_kernel<4>, nb, kBlock, ctx->g, cur, ctx->gf, q_prev, r, spare, ctx->part);
+        HS_LAUNCH(ctx, gate_kernel<4>, nb, kBlock, ctx->g, cur, ctx->gf, q_prev, r, spare, keep_out, ctx->part);
       HS_TRY(finish_stats(ctx, nb, 0u, 1u << kStatCount));
       unsigned long long st[kStatSlots];
       HS_TRY(read_stats(ctx, st));
@@ -353,6 +362,7 @@ hs_status run_filter(hs_ctx* ctx, double* gamma, const double* q_prev, const hs_
         info->filter_kept += (int)kept;
       }
       if (kept == 0) break;
+      if (record) record->passes[record->npass++] = nord;
       std::swap(cur, spare);
       double sum_new;
       HS_TRY(cell_residual_norm(ctx, cur, q_prev, r2, &sum_new));
@@ -361,6 +371,22 @@ hs_status run_filter(hs_ctx* ctx, double* gamma, const double* q_prev, const hs_
       sum_r = sum_new;
       if (dec < hp->eps_f) break;
     }
+  }
+  if (cur != gamma)
+    HIP_TRY(ctx, hipMemcpyAsync(gamma, cur, ctx->n * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  return HS_OK;
+}
+
+// The recorded filter passes applied without gating.
+static hs_status replay_filter(hs_ctx* ctx, double* gamma, const hs_htape* tape, hs_step_info* info) {
+  double* cur = gamma;
+  double* spare = ctx->gtmp;
+  for (int k = 0; k < tape->npass; ++k) {
+    HS_TRY(filter_apply(ctx, cur, ctx->gf, tape->passes[k]));
+    HS_LAUNCH(ctx, mask_blend_kernel, blocks_for(ctx->n), kBlock, (long long)ctx->n, ctx->ncell, cur, ctx->gf,
+              tape->masks + (size_t)k * ctx->ncell, spare);
+    std::swap(cur, spare);
+    if (info) info->filter_passes += 1;
   }
   if (cur != gamma)
     HIP_TRY(ctx, hipMemcpyAsync(gamma, cur, ctx->n * 8, hipMemcpyDeviceToDevice, ctx->stream));
@@ -414,11 +440,110 @@ static hs_status fit_solve(hs_ctx* ctx, const double* Phi, int m, const int* hat
   return HS_OK;
 }
 
+// mode: -1 plain step, HS_TAPE_RECORD, HS_TAPE_REPLAY (see the header).
+static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const double* Phi, const double* psi, int m,
+                             const hs_samples* s, const hs_hybrid_params* hp, double* q_out, double* eps_out,
+                             double* y_out, hs_step_info* info, hs_htape* tape, int mode) {
+  if (!ctx || !q_prev || !Phi || !psi || !hp || !q_out) return HS_ERR_INVALID_ARG;
+  if (q_out == q_prev || q_out == psi || q_out == Phi) return HS_ERR_INVALID_ARG;
+  const bool replay = mode == HS_TAPE_REPLAY;
+  if (mode >= 0 && (!tape || tape->ctx != ctx)) return HS_ERR_INVALID_ARG;
+  if (replay) {
+    if (!tape->recorded) return ctx->fail(HS_ERR_INVALID_ARG, "replay of a tape that holds no recorded step");
+    s = tape->s;
+  }
+  if (!s || s->ctx != ctx) return HS_ERR_INVALID_ARG;
+  if (m < 1 || m > ctx->p.m_max) return ctx->fail(HS_ERR_RANK, "empty basis");
+  if (hp->jmax < 1 || hp->n_orders < 0 || hp->n_orders > 4 || !(hp->rcond_fit > 0) || !(hp->eps_y >= 0))
+    return HS_ERR_INVALID_ARG;
+  for (int o = 0; o < hp->n_orders; ++o)
+    if (hp->filter_orders[o] < 1 || hp->filter_orders[o] > 3) return HS_ERR_INVALID_ARG;
+  if (hp->precision != HS_FP64) return ctx->fail(HS_ERR_INVALID_ARG, "rom_hybrid_step: only HS_FP64 in this build");
+  if (s->n_s == 0) return ctx->fail(HS_ERR_RANK, "empty sampled set");
+  hs_step_info local{};
+  hs_step_info* inf = info ? info : &local;
+  std::memset(inf, 0, sizeof *inf);
+  inf->n_s = s->n_s;
+  inf->l = s->l;
+  const int jmax = replay ? tape->J : hp->jmax;
+  if (replay) {
+    const size_t need = (size_t)jmax * ctx->n;
+    if (tape->us_cap < need) {
+      if (tape->us) HIP_TRY(ctx, hipFree(tape->us));
+      tape->us = nullptr;
+      tape->us_cap = 0;
+      if (hipMalloc((void**)&tape->us, need * 8) != hipSuccess)
+        return ctx->fail(HS_ERR_OOM, "tape: no memory for the subiteration states");
+      tape->us_cap = need;
+    }
+  }
+
+  double qmax;
+  HS_TRY(max_abs(ctx, q_prev, ctx->n, &qmax));
+  if (!std::isfinite(qmax)) return ctx->fail(HS_ERR_NONFINITE, "non-finite q_prev");
+  const double tol = ctx->p.newton_rtol * std::max(1.0, qmax);
+  double* u = ctx->u;
+  double* sm = ctx->small;
+  HIP_TRY(ctx, hipMemcpyAsync(u, q_prev, ctx->n * 8, hipMemcpyDeviceToDevice, ctx->stream));
+
+  HS_TRY(fit_factor(ctx, Phi, m, s->hat, s->n_s, hp->rcond_fit));
+  double misc[3];
+  HS_TRY(readback(ctx, sm + kSmMisc, 3 * sizeof(double), misc));
+  inf->fit_rank = (int)misc[1];
+  inf->fit_cond = misc[2];
+  if (inf->fit_rank == 0) return ctx->fail(HS_ERR_RANK, "rank-zero fit");
+
+  for (int j = 1; j <= jmax; ++j) {
+    HS_TRY(newton_solve(ctx, u, q_prev, tol, s, inf));
+    if (replay)
+      HIP_TRY(ctx, hipMemcpyAsync(tape->us + (size_t)(j - 1) * ctx->n, u, ctx->n * 8, hipMemcpyDeviceToDevice,
+                                  ctx->stream));
+    HS_TRY(fit_solve(ctx, Phi, m, s->hat, s->n_s, u, psi, j == 1));
+    if (s->l > 0)
+      HS_LAUNCH(ctx, ring_update_kernel, blocks_for((long long)ctx->nc * s->l), kBlock, Phi, (long long)ctx->n, m,
+                ctx->nc, ctx->ncell, s->tilde, s->l, psi, sm + kSmY, u);
+    inf->subiters = j;
+    if (replay) continue;
+    double dy;
+    HS_TRY(readback(ctx, sm + kSmMisc, sizeof(double), &dy));
+    inf->dy_last = dy;
+    if (j >= 2 && dy < hp->eps_y) break;
+  }
+  if (replay) {
+    HIP_TRY(ctx, hipMemcpyAsync(tape->gp, sm + kSmGp, (size_t)m * m * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    tape->m = m;
+  }
+  HS_TRY(prof_begin(ctx, HS_PROF_RECON));
+  HS_LAUNCH(ctx, recon_kernel, blocks_for(ctx->n), kBlock, Phi, (long long)ctx->n, m, ctx->ncell, psi, sm + kSmY,
+            s->mask, u, q_out, ctx->rho);
+  // reads m columns of Phi, psi, u and the mask; writes gamma and rho
+  HS_TRY(prof_end(ctx, HS_PROF_RECON, 8.0 * (double)ctx->n * (m + 4) + (double)ctx->ncell));
+  if (replay) HS_TRY(replay_filter(ctx, q_out, tape, inf));
+  else HS_TRY(run_filter(ctx, q_out, q_prev, hp, inf, mode == HS_TAPE_RECORD ? tape : nullptr));
+  if (eps_out) {
+    double gmax;
+    HS_TRY(max_abs(ctx, q_out, ctx->n, &gmax));
+    const double fl = hp->floor_rel * std::max(1.0, gmax);
+    HS_LAUNCH(ctx, indicator_kernel, blocks_for(ctx->ncell), kBlock, ctx->ncell, ctx->nc, q_out, ctx->rho, fl * fl,
+              eps_out);
+  }
+  if (y_out) HIP_TRY(ctx, hipMemcpyAsync(y_out, sm + kSmY, m * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  if (mode == HS_TAPE_RECORD) {
+    HS_TRY(hs_samples_set(ctx, tape->s, s->hat, s->n_s));
+    tape->J = inf->subiters;
+    tape->recorded = true;
+    tape->replayed = false;
+  }
+  if (replay) tape->replayed = true;
+  return hs_sync(ctx);
+}
+
 }  // namespace hs
 
 using namespace hs;
 
 extern "C" {
+
 
 hs_status hs_filter(hs_ctx* ctx, const double* gamma_in, const double* q_prev, const hs_hybrid_params* hp,
                     double* gamma_out, hs_step_info* info) {
@@ -460,63 +585,61 @@ hs_status hs_indicator_full(hs_ctx* ctx, const double* gamma, const double* Phi,
 hs_status rom_hybrid_step(hs_ctx* ctx, const double* q_prev, const double* Phi, const double* psi, int32_t m,
                           const hs_samples* s, const hs_hybrid_params* hp, double* q_out, double* eps_out,
                           double* y_out, hs_step_info* info) {
-  if (!ctx || !q_prev || !Phi || !psi || !s || !hp || !q_out || s->ctx != ctx) return HS_ERR_INVALID_ARG;
-  if (q_out == q_prev || q_out == psi || q_out == Phi) return HS_ERR_INVALID_ARG;
-  if (m < 1 || m > ctx->p.m_max) return ctx->fail(HS_ERR_RANK, "empty basis");
-  if (hp->jmax < 1 || hp->n_orders < 0 || hp->n_orders > 4 || !(hp->rcond_fit > 0) || !(hp->eps_y >= 0))
-    return HS_ERR_INVALID_ARG;
-  for (int o = 0; o < hp->n_orders; ++o)
-    if (hp->filter_orders[o] < 1 || hp->filter_orders[o] > 3) return HS_ERR_INVALID_ARG;
-  if (hp->precision != HS_FP64) return ctx->fail(HS_ERR_INVALID_ARG, "rom_hybrid_step: only HS_FP64 in this build");
-  if (s->n_s == 0) return ctx->fail(HS_ERR_RANK, "empty sampled set");
-  hs_step_info local{};
-  hs_step_info* inf = info ? info : &local;
-  std::memset(inf, 0, sizeof *inf);
-  inf->n_s = s->n_s;
-  inf->l = s->l;
+  return hybrid_impl(ctx, q_prev, Phi, psi, m, s, hp, q_out, eps_out, y_out, info, nullptr, -1);
+}
 
-  double qmax;
-  HS_TRY(max_abs(ctx, q_prev, ctx->n, &qmax));
-  if (!std::isfinite(qmax)) return ctx->fail(HS_ERR_NONFINITE, "non-finite q_prev");
-  const double tol = ctx->p.newton_rtol * std::max(1.0, qmax);
-  double* u = ctx->u;
-  double* sm = ctx->small;
-  HIP_TRY(ctx, hipMemcpyAsync(u, q_prev, ctx->n * 8, hipMemcpyDeviceToDevice, ctx->stream));
+hs_status rom_hybrid_step_taped(hs_ctx* ctx, const double* q_prev, const double* Phi, const double* psi,
+                                int32_t m, const hs_samples* s, const hs_hybrid_params* hp, double* q_out,
+                                double* eps_out, hs_step_info* info, hs_htape* tape, int32_t mode) {
+  if (mode != HS_TAPE_RECORD && mode != HS_TAPE_REPLAY) return HS_ERR_INVALID_ARG;
+  return hybrid_impl(ctx, q_prev, Phi, psi, m, s, hp, q_out, eps_out, nullptr, info, tape, mode);
+}
 
-  HS_TRY(fit_factor(ctx, Phi, m, s->hat, s->n_s, hp->rcond_fit));
-  double misc[3];
-  HS_TRY(readback(ctx, sm + kSmMisc, 3 * sizeof(double), misc));
-  inf->fit_rank = (int)misc[1];
-  inf->fit_cond = misc[2];
-  if (inf->fit_rank == 0) return ctx->fail(HS_ERR_RANK, "rank-zero fit");
-
-  for (int j = 1; j <= hp->jmax; ++j) {
-    HS_TRY(newton_solve(ctx, u, q_prev, tol, s, inf));
-    HS_TRY(fit_solve(ctx, Phi, m, s->hat, s->n_s, u, psi, j == 1));
-    if (s->l > 0)
-      HS_LAUNCH(ctx, ring_update_kernel, blocks_for((long long)ctx->nc * s->l), kBlock, Phi, (long long)ctx->n, m,
-                ctx->nc, ctx->ncell, s->tilde, s->l, psi, sm + kSmY, u);
-    double dy;
-    HS_TRY(readback(ctx, sm + kSmMisc, sizeof(double), &dy));
-    inf->subiters = j;
-    inf->dy_last = dy;
-    if (j >= 2 && dy < hp->eps_y) break;
+hs_status hs_htape_create(hs_ctx* ctx, hs_htape** out) {
+  if (!ctx || !out) return HS_ERR_INVALID_ARG;
+  hs_htape* t = new hs_htape();
+  t->ctx = ctx;
+  hs_status st = hs_samples_create(ctx, &t->s);
+  if (st == HS_OK && hipMalloc((void**)&t->masks, (size_t)kMaxPasses * ctx->ncell) != hipSuccess) st = HS_ERR_OOM;
+  if (st == HS_OK && hipMalloc((void**)&t->gp, (size_t)kMaxBasis * kMaxBasis * 8) != hipSuccess) st = HS_ERR_OOM;
+  if (st != HS_OK) {
+    hs_htape_destroy(t);
+    return ctx->fail(st, "tape allocation failed");
   }
-  HS_TRY(prof_begin(ctx, HS_PROF_RECON));
-  HS_LAUNCH(ctx, recon_kernel, blocks_for(ctx->n), kBlock, Phi, (long long)ctx->n, m, ctx->ncell, psi, sm + kSmY,
-            s->mask, u, q_out, ctx->rho);
-  // reads m columns of Phi, psi, u and the mask; writes gamma and rho
-  HS_TRY(prof_end(ctx, HS_PROF_RECON, 8.0 * (double)ctx->n * (m + 4) + (double)ctx->ncell));
-  HS_TRY(run_filter(ctx, q_out, q_prev, hp, inf));
-  if (eps_out) {
-    double gmax;
-    HS_TRY(max_abs(ctx, q_out, ctx->n, &gmax));
-    const double fl = hp->floor_rel * std::max(1.0, gmax);
-    HS_LAUNCH(ctx, indicator_kernel, blocks_for(ctx->ncell), kBlock, ctx->ncell, ctx->nc, q_out, ctx->rho, fl * fl,
-              eps_out);
+  *out = t;
+  return HS_OK;
+}
+
+hs_status hs_htape_info(const hs_htape* t, int32_t* J, int32_t* npass, int32_t* passes, uint8_t* masks) {
+  if (!t) return HS_ERR_INVALID_ARG;
+  hs_ctx* ctx = t->ctx;
+  if (!t->recorded) return ctx->fail(HS_ERR_INVALID_ARG, "tape holds no recorded step");
+  if (J) *J = t->J;
+  if (npass) *npass = t->npass;
+  if (passes)
+    for (int k = 0; k < t->npass; ++k) passes[k] = t->passes[k];
+  if (masks && t->npass > 0) {
+    HIP_TRY(ctx, hipMemcpyAsync(masks, t->masks, (size_t)t->npass * ctx->ncell, hipMemcpyDeviceToDevice,
+                                ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   }
-  if (y_out) HIP_TRY(ctx, hipMemcpyAsync(y_out, sm + kSmY, m * 8, hipMemcpyDeviceToDevice, ctx->stream));
-  return hs_sync(ctx);
+  return HS_OK;
+}
+
+hs_status hs_htape_samples(hs_htape* t, hs_samples** out) {
+  if (!t || !out) return HS_ERR_INVALID_ARG;
+  *out = t->s;
+  return HS_OK;
+}
+
+hs_status hs_htape_destroy(hs_htape* t) {
+  if (!t) return HS_ERR_INVALID_ARG;
+  if (t->s) hs_samples_destroy(t->s);
+  if (t->masks) (void)hipFree(t->masks);
+  if (t->us) (void)hipFree(t->us);
+  if (t->gp) (void)hipFree(t->gp);
+  delete t;
+  return HS_OK;
 }
 
 }  // extern "C"

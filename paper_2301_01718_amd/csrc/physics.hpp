@@ -249,4 +249,46 @@ __device__ inline void cell_jacobian(const Grid& g, const Stencil<NC>& st, doubl
   }
 }
 
+// Inverse of a small row-major NC x NC matrix (Gauss-Jordan, partial pivoting).
+template <int NC>
+__device__ inline void small_inverse(const double A[NC * NC], double X[NC * NC]) {
+  if constexpr (NC == 1) {
+    X[0] = 1.0 / A[0];
+  } else {
+    double M[NC][2 * NC];
+#pragma unroll
+    for (int r = 0; r < NC; ++r)
+#pragma unroll
+      for (int c = 0; c < 2 * NC; ++c) M[r][c] = c < NC ? A[r * NC + c] : (c - NC == r ? 1.0 : 0.0);
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      int piv = k;
+      double best = fabs(M[k][k]);
+#pragma unroll
+      for (int r = k + 1; r < NC; ++r)
+        if (fabs(M[r][k]) > best) { best = fabs(M[r][k]); piv = r; }
+#pragma unroll
+      for (int c = 0; c < 2 * NC; ++c) {   // swap rows k and piv
+        const double t = M[k][c];
+        M[k][c] = M[piv][c];
+        M[piv][c] = t;
+      }
+      const double inv = 1.0 / M[k][k];
+#pragma unroll
+      for (int c = 0; c < 2 * NC; ++c) M[k][c] *= inv;
+#pragma unroll
+      for (int r = 0; r < NC; ++r) {
+        if (r == k) continue;
+        const double f = M[r][k];
+#pragma unroll
+        for (int c = 0; c < 2 * NC; ++c) M[r][c] -= f * M[k][c];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NC; ++r)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) X[r * NC + c] = M[r][NC + c];
+  }
+}
+
 }  // namespace hs

@@ -17,7 +17,7 @@ import time
 
 import torch
 
-from ._lib import (Context, HsError, FP64, HS_ERR_NOT_CONVERGED, HS_ERR_RANK, hybrid_params)
+from ._lib import (Context, HsError, FP64, HS_ERR_NOT_CONVERGED, HS_ERR_RANK, TAPE_RECORD, hybrid_params)
 
 
 @dataclasses.dataclass
@@ -66,6 +66,10 @@ class Arom:
         self.hp = hybrid_params(cfg.eps_y, cfg.jmax, cfg.filter_orders, cfg.eps_f, cfg.jfmax,
                                 cfg.rcond_fit, cfg.floor_rel, cfg.precision)
         self.m_eff = 0
+        self.basis_version = 0
+        # optional: an object with tape(k) -> Tape, called for every hybrid
+        # step; the step then records its frozen decisions (adjoint use)
+        self.recorder = None
 
     def slot(self, k):
         return self.ring[k % (self.cfg.w + 2)]
@@ -85,12 +89,19 @@ class Arom:
         k = self.k
         rec = {"k": k}
         prev, out = self.slot(k - 1), self.slot(k)
-        used = {"q_prev": prev, "Phi": self.Phi, "psi": self.psi, "m": self.m_eff}
+        used = {"q_prev": prev, "Phi": self.Phi, "psi": self.psi, "m": self.m_eff,
+                "basis_version": self.basis_version}
         hybrid = not is_full_step(k, cfg.w, cfg.z) and self.have_samples and self.m_eff > 0
         if hybrid:
             try:
-                _, info = c.rom_hybrid_step(prev, self.Phi, self.psi, self.m_eff, self.samples,
-                                            self.hp, out=out, eps=self.eps)
+                if self.recorder is not None:
+                    _, info = c.rom_hybrid_step_taped(prev, self.Phi, self.psi, self.m_eff,
+                                                      self.recorder.tape(k), TAPE_RECORD,
+                                                      samples=self.samples, params=self.hp, out=out,
+                                                      eps=self.eps)
+                else:
+                    _, info = c.rom_hybrid_step(prev, self.Phi, self.psi, self.m_eff, self.samples,
+                                                self.hp, out=out, eps=self.eps)
                 rec.update(type="hybrid", n_s=info["n_s"], l=info["l"], J=info["subiters"],
                            newton=info["newton_iters"], sweeps=info["lin_sweeps"],
                            filter_passes=info["filter_passes"], fit_cond=info["fit_cond"])
@@ -118,6 +129,7 @@ class Arom:
             window = [self.slot(j) for j in range(lo, k + 1)]
             self.m_eff = c.basis_update(window, cfg.w, cfg.m, self.Phi, self.psi, self.sigma,
                                         cfg.tau_pod, cfg.precision)
+            self.basis_version += 1
             rec["m_eff"] = self.m_eff
             if on_update is not None:
                 on_update(k, rec, {"eps": self.eps, "samples": self.samples if self.have_samples else None,

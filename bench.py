@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--roofline-kernel", default="basis_form",
                     choices=["basis_gram", "basis_form", "recon", "resjac", "sweep", "cellres"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurement")
+    ap.add_argument("--adjoint-workload", default="burgers2d_256")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 1 GiB elementwise copy (counter calibration for rocprofv3 --pmc)")
     return ap.parse_args()
@@ -93,11 +95,35 @@ def cpu_baseline(prob, wl, snap):
                        f"before the first timed step, with its sampling and POD update: {dt:.1f} s")}
 
 
+def adjoint_bench(name, seed):
+    """Forward-with-tape and backward (checkpoint replay + step adjoints) wall
+    time per step of the frozen-decision adjoint on a whole trajectory."""
+    import torch
+    import workloads as W
+    from paper_2301_01718_amd.adjoint import HybridTrajectory, Trajectory
+    from paper_2301_01718_amd.driver import AromConfig
+    wl = W.WORKLOADS[name]
+    prob, q0 = W.make(wl, seed)
+    cfg = AromConfig(w=wl.w, m=wl.m, z=wl.z, fraction=wl.frac, halo=wl.halo)
+    K = wl.checkpoint or 10
+    traj = Trajectory(prob, cfg, wl.steps, checkpoint_every=K)
+    q = torch.from_numpy(q0).to(traj.ctx.device).requires_grad_(True)
+    qT = HybridTrajectory.apply(q, traj)
+    loss = 0.5 * torch.sum(qT * qT)
+    loss.backward()
+    kinds = [k for k, _ in traj.decisions()]
+    return {"workload": name, "nx": prob.nx, "ny": prob.ny, "steps": wl.steps, "checkpoint_every": K,
+            "hybrid_steps": kinds.count("hybrid"),
+            "forward_taped_s_per_step": traj.timing["forward_s"] / wl.steps,
+            "backward_s_per_step": traj.timing["backward_s"] / wl.steps,
+            "grad_norm": float(torch.linalg.vector_norm(q.grad))}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU; multi-GPU runs are not part of it "
-              "(see DESIGN.md, 'How the path would shard').", file=sys.stderr)
+        print("bench.py: only one GPU is measured; the hybrid step's multi-GPU (sharded) "
+              "layout is a design, not built, so --gpus must be 1.", file=sys.stderr)
         return 2
     import numpy as np
     import torch
@@ -181,6 +207,10 @@ def main():
             "traffic": traffic,
             "bytes_per_launch": (k_bytes / k_launch) if k_launch else None,
             "launches": k_launch, "avg_launch_us": (1e3 * k_ms / k_launch) if k_launch else None}
+    adj = None
+    if not args.no_adjoint:
+        log(f"adjoint trajectory on {args.adjoint_workload} ...")
+        adj = adjoint_bench(args.adjoint_workload, args.seed)
     cpu = None
     if snap is not None:
         log("timing the oracle on the host ...")
@@ -202,6 +232,7 @@ def main():
         "mean_n_s_frac": float(np.mean([r["n_s"] / prob.ncell for r in recs if r["type"] == "hybrid"] or [0])),
         "mean_J": float(np.mean([r["J"] for r in recs if r["type"] == "hybrid"] or [0])),
         "m_eff": recs[-1].get("m_eff"),
+        "adjoint": adj,
     }
     print(json.dumps(out), flush=True)
     return 0

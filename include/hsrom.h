@@ -248,6 +248,13 @@ hs_status hdm_step_adjoint(hs_ctx* ctx, const double* q_out, const double* lam_i
 hs_status rom_hybrid_step_adjoint(hs_ctx* ctx, const double* Phi, int32_t m, const hs_htape* tape,
                                   const double* lam_in, double* lam_out, hs_step_info* info /* host */);
 
+/* ----------------------------------------------------------- options */
+/* HS_OPT_TILED_SWEEPS: 1 (default) relaxes in LDS tiles, several sweeps per
+ * launch; 0 runs one sweep per launch over the compact cell list.  Both give
+ * the same iterates bit for bit (a switch for measurement and testing). */
+#define HS_OPT_TILED_SWEEPS 1
+hs_status hs_set_option(hs_ctx* ctx, int32_t option, int64_t value);
+
 /* ------------------------------------------------------- measurement */
 /* Kernel classes that can be timed with HIP events on the context's stream. */
 #define HS_PROF_NONE        0

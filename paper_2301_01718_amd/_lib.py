@@ -109,6 +109,7 @@ _SIGS = {
                               ctypes.POINTER(StepInfo), P, I32],
     "hdm_step_adjoint": [P, P, P, P, ctypes.POINTER(StepInfo)],
     "rom_hybrid_step_adjoint": [P, P, I32, P, P, P, ctypes.POINTER(StepInfo)],
+    "hs_set_option": [P, I32, ctypes.c_int64],
     "hs_prof_enable": [P, I32],
     "hs_prof_read": [P, ctypes.POINTER(D), ctypes.POINTER(I32), ctypes.POINTER(D)],
 }
@@ -192,6 +193,10 @@ class Context:
 
     def sync(self):
         self._check(lib().hs_sync(self.h))
+
+    def set_tiled_sweeps(self, on: bool):
+        """Relax in LDS tiles (several sweeps per launch) or one sweep per launch."""
+        self._check(lib().hs_set_option(self.h, 1, 1 if on else 0))
 
     # ---------------------------------------------------------- measurement
     def prof_enable(self, kernel_class):

@@ -344,8 +344,11 @@ static hs_status project(hs_ctx* ctx, const double* Phi, int m, const int* list,
 }
 
 // Transposed relaxation data at state q, then the solve into x (compact).
-static hs_status transposed_solve(hs_ctx* ctx, const double* q, const int* hat, const int* nbr, int count,
-                                  const double* v, double* x, int* sweeps) {
+static hs_status transposed_solve(hs_ctx* ctx, const double* q, const hs_samples* s, const double* v, double* x,
+                                  int* sweeps) {
+  const int* hat = s ? s->hat : nullptr;
+  const int* nbr = s ? s->nbr : nullptr;
+  const int count = s ? s->n_s : ctx->ncell;
   const int nbs = stat_blocks(count);
   if (ctx->nc == 1)
     HS_LAUNCH(ctx, adj_coef_kernel<1>, nbs, kBlock, ctx->g, q, hat, nbr, count, ctx->ncell, v, ctx->coef, ctx->rhs,
@@ -358,7 +361,7 @@ static hs_status transposed_solve(hs_ctx* ctx, const double* q, const int* hat, 
   HS_TRY(read_stats(ctx, st));
   const double rho = bits_to_double(st[kStatRho]);
   if (!std::isfinite(rho)) return ctx->fail(HS_ERR_NONFINITE, "non-finite transposed Jacobian");
-  return relax_solve(ctx, hat, nbr, count, ctx->coef, ctx->rhs, rho, kAdjointRtol, x, sweeps);
+  return relax_solve(ctx, s, ctx->coef, ctx->rhs, rho, kAdjointRtol, x, sweeps);
 }
 
 }  // namespace hs
@@ -377,7 +380,7 @@ hs_status hdm_step_adjoint(hs_ctx* ctx, const double* q_out, const double* lam_i
     v = ctx->adj;
   }
   int sweeps = 0;
-  HS_TRY(transposed_solve(ctx, q_out, nullptr, nullptr, ctx->ncell, v, lam_out, &sweeps));
+  HS_TRY(transposed_solve(ctx, q_out, nullptr, v, lam_out, &sweeps));
   if (info) info->lin_sweeps = sweeps;
   return hs_sync(ctx);
 }
@@ -440,7 +443,7 @@ hs_status rom_hybrid_step_adjoint(hs_ctx* ctx, const double* Phi, int32_t m, con
       HS_TRY(project(ctx, Phi, m, s->tilde, s->l, nullptr, tbar, nullptr, sm + kSmAdjY, tape->gp, sm + kSmAdjZ));
     HS_LAUNCH(ctx, adj_expand_kernel, blocks_for((long long)nc * s->n_s), kBlock, Phi, N, m, nc, ncell, s->hat,
               s->n_s, (const double*)(sm + kSmAdjZ), last ? (const double*)vbar0 : (const double*)nullptr, vbar);
-    HS_TRY(transposed_solve(ctx, uj, s->hat, s->nbr, s->n_s, vbar, mu, &sweeps));
+    HS_TRY(transposed_solve(ctx, uj, s, vbar, mu, &sweeps));
     HS_LAUNCH(ctx, scatter_add_kernel, blocks_for((long long)nc * s->n_s), kBlock, nc, ncell, s->hat, s->n_s,
               (const double*)mu, lam_out);
     if (s->l > 0) {

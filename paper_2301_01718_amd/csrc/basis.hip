@@ -9,7 +9,7 @@
 // X^T X = V diag(sigma^2) V^T; a second pass forms Phi = X V_m diag(1/sigma_m),
 // the left singular vectors, again on MFMA.  The traffic is two reads of the
 // window and one write of Phi (the method-of-snapshots minimum).
-// Kernels using stage_centred must run with 256 threads (four waves).
+// Kernels using the window staging must run with 256 threads (four waves).
 #include "dense.hpp"
 
 #include <algorithm>
@@ -20,33 +20,46 @@ namespace hs {
 constexpr int kMaxSnaps = kMaxBasis + 1;
 constexpr int kPerWave = (kMaxSnaps + 3) / 4;   // snapshots each of the four waves loads
 
-// Stage rows row0 .. row0+63 of the centred window into X (64 x ldx, LDS):
-// X[r][j] = snap[off + j][row0 + r] - centre[r] for j < w, 0 for w <= j < wp.
-// Lane = row, wave q loads snapshots q, q+4, ... (wave-uniform pointers), all
-// loads independent and in flight together.  The centring state (mean of the
-// first w snapshots) and psi_new (mean of the last w) are summed per wave
-// over its snapshots and the four partial sums combined in a fixed order.
-// Needs 256 threads; the caller synchronises before reading X.
-__device__ inline void stage_centred(const double* const* __restrict__ snaps, int nsnap, int w, long long n,
-                                     long long row0, double* X, int ldx, int wp, double* psi_new) {
+// Rows row0 .. row0+63 of the window in registers: lane = row, wave q holds
+// snapshots q, q+4, ... (wave-uniform pointers).  window_prefetch only issues
+// the loads, so a kernel can start the next chunk's loads before it computes
+// on the current one; window_commit waits for them.
+struct WindowRegs {
+  double v[kPerWave];
+};
+
+__device__ inline void window_prefetch(const double* const* __restrict__ snaps, int nsnap, long long n,
+                                       long long row0, WindowRegs& R) {
+  const int lane = threadIdx.x % kChunk;
+  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x / kChunk);
+  const long long row = row0 + lane;
+  const bool ok = row < n;
+#pragma unroll
+  for (int i = 0; i < kPerWave; ++i) {
+    const int j = q + 4 * i;
+    R.v[i] = (j < nsnap && ok) ? snaps[j][row] : 0.0;
+  }
+}
+
+// Centred rows into X (64 x ldx, LDS): X[r][j] = snap[off + j][row0 + r] -
+// centre[r] for j < w, 0 for w <= j < wp.  The centring state (mean of the
+// first w snapshots) and psi_new (mean of the last w) are summed per wave over
+// its snapshots and the four partial sums combined in a fixed order.  Needs
+// 256 threads; the caller synchronises before reading X.
+__device__ inline void window_commit(const WindowRegs& R, int nsnap, int w, long long n, long long row0, double* X,
+                                     int ldx, int wp, double* psi_new) {
   __shared__ double part_c[4][kChunk], part_n[4][kChunk], centre[kChunk];
   const int lane = threadIdx.x % kChunk;
   const int q = __builtin_amdgcn_readfirstlane(threadIdx.x / kChunk);
   const long long row = row0 + lane;
   const bool ok = row < n;
   const int off = nsnap - w;
-  double v[kPerWave];
-#pragma unroll
-  for (int i = 0; i < kPerWave; ++i) {
-    const int j = q + 4 * i;
-    v[i] = (j < nsnap && ok) ? snaps[j][row] : 0.0;
-  }
   double c = 0.0, nw = 0.0;
 #pragma unroll
   for (int i = 0; i < kPerWave; ++i) {
     const int j = q + 4 * i;
-    if (j < w) c += v[i];
-    if (j >= off && j < nsnap) nw += v[i];
+    if (j < w) c += R.v[i];
+    if (j >= off && j < nsnap) nw += R.v[i];
   }
   part_c[q][lane] = c;
   part_n[q][lane] = nw;
@@ -62,7 +75,7 @@ __device__ inline void stage_centred(const double* const* __restrict__ snaps, in
 #pragma unroll
   for (int i = 0; i < kPerWave; ++i) {
     const int j = q + 4 * i;
-    if (j >= off && j < nsnap) X[lane * ldx + (j - off)] = ok ? v[i] - ce : 0.0;
+    if (j >= off && j < nsnap) X[lane * ldx + (j - off)] = ok ? R.v[i] - ce : 0.0;
   }
   for (int j = w + q; j < wp; j += 4) X[lane * ldx + j] = 0.0;
 }
@@ -73,8 +86,10 @@ struct WindowLoader {
   int nsnap, w;
   long long n;
   double* psi_new;
-  __device__ void load(long long row0, double* X, int ldx, int wp) const {
-    stage_centred(snaps, nsnap, w, n, row0, X, ldx, wp, psi_new);
+  using Regs = WindowRegs;
+  __device__ void prefetch(long long row0, Regs& R) const { window_prefetch(snaps, nsnap, n, row0, R); }
+  __device__ void commit(long long row0, const Regs& R, double* X, int ldx, int wp) const {
+    window_commit(R, nsnap, w, n, row0, X, ldx, wp, psi_new);
   }
 };
 
@@ -115,13 +130,19 @@ __global__ void __launch_bounds__(256) basis_eig_kernel(const double* __restrict
   __syncthreads();
   // 1. pivoted Cholesky (rows of L in pivot order: row i <-> index perm[i])
   for (int k = 0; k < w; ++k) {
-    if (t == 0) {
-      int p = k;
-      double best = d[perm[k]];
-      for (int i = k + 1; i < w; ++i)
-        if (d[perm[i]] > best) { best = d[perm[i]]; p = i; }
-      piv = best > tolc ? p : -1;
-      if (piv >= 0) rank = k + 1;
+    if (t < kWave) {
+      // pivot: largest remaining diagonal, ties to the lowest position (w <= 64: one wave)
+      double best = (t >= k && t < w) ? d[perm[t]] : -INFINITY;
+      int p = t;
+      for (int o = kWave / 2; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, kWave);
+        const int op = __shfl_xor(p, o, kWave);
+        if (ob > best || (ob == best && op < p)) { best = ob; p = op; }
+      }
+      if (t == 0) {
+        piv = best > tolc ? p : -1;
+        if (piv >= 0) rank = k + 1;
+      }
     }
     __syncthreads();
     if (piv < 0) break;
@@ -205,27 +226,34 @@ __global__ void __launch_bounds__(256) basis_eig_kernel(const double* __restrict
 
 // Phi = X T for rows of the window (centred on the fly), on MFMA.
 // C^T = T^T X^T so that each 16-lane group writes 16 consecutive rows of one
-// column of Phi.  256 threads.
+// column of Phi.  The next chunk's loads are in flight during the products.
+// 256 threads; dynamic LDS: X (kChunk x (wp + 1)) then T (wp x (mp + 1)).
 __global__ void __launch_bounds__(256) basis_form_kernel(const double* const* __restrict__ snaps, int nsnap,
                                                          int w, long long n, const double* __restrict__ T,
                                                          int mp, int wp, int meff, double* __restrict__ Phi) {
-  __shared__ double X[kChunk * (kMaxBasis + 1)];
-  __shared__ double Ts[kMaxBasis * (kMaxBasis + 1)];
-  const int ldx = kMaxBasis + 1;
+  extern __shared__ double sh[];
+  const int ldx = wp + 1, ldt = mp + 1;
+  double* X = sh;
+  double* Ts = sh + kChunk * ldx;
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-  for (int e = threadIdx.x; e < wp * mp; e += blockDim.x) Ts[(e / mp) * ldx + e % mp] = T[(e / mp) * mp + e % mp];
+  for (int e = threadIdx.x; e < wp * mp; e += blockDim.x) Ts[(e / mp) * ldt + e % mp] = T[e];
   const long long nchunks = (n + kChunk - 1) / kChunk;
-  for (long long ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+  WindowRegs R;
+  long long ch = blockIdx.x;
+  if (ch < nchunks) window_prefetch(snaps, nsnap, n, ch * kChunk, R);
+  for (; ch < nchunks; ch += gridDim.x) {
     const long long row0 = ch * kChunk;
     __syncthreads();
-    stage_centred(snaps, nsnap, w, n, row0, X, ldx, wp, nullptr);
+    window_commit(R, nsnap, w, n, row0, X, ldx, wp, nullptr);
     __syncthreads();
+    if (ch + gridDim.x < nchunks) window_prefetch(snaps, nsnap, n, (ch + gridDim.x) * kChunk, R);
     const int rb = wave;   // 16 rows per wave
     for (int mb = 0; mb * 16 < mp; ++mb) {
+      if (mb * 16 >= meff) break;
       double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
       for (int k0 = 0; k0 < wp; k0 += 4) {
         const int k = k0 + lane / 16;
-        const double a = Ts[k * ldx + mb * 16 + lane % 16];     // A = T^T: A[c][k] = T[k][c]
+        const double a = Ts[k * ldt + mb * 16 + lane % 16];     // A = T^T: A[c][k] = T[k][c]
         const double b = X[(rb * 16 + lane % 16) * ldx + k];    // B[k][r] = X[r][k]
         acc = mfma_f64(a, b, acc);
       }
@@ -261,7 +289,7 @@ extern "C" hs_status basis_update(hs_ctx* ctx, const double* const* snaps, int32
   const int wp = (w + 15) / 16 * 16;
   const int mp = (m + 15) / 16 * 16;
   const long long nchunks = (n + kChunk - 1) / kChunk;
-  const int nb = (int)std::min<long long>(nchunks, 512);
+  const int nb = (int)std::min<long long>(nchunks, kRedBlocks);
   WindowLoader ld{tab, nsnap, w, n, psi_out};
   const size_t lds = (size_t)kChunk * (wp + 1) * sizeof(double);
   HS_TRY(prof_begin(ctx, HS_PROF_BASIS_GRAM));
@@ -279,7 +307,10 @@ extern "C" hs_status basis_update(hs_ctx* ctx, const double* const* snaps, int32
   *m_eff = me;
   if (me == 0) return HS_OK;
   HS_TRY(prof_begin(ctx, HS_PROF_BASIS_FORM));
-  HS_LAUNCH(ctx, basis_form_kernel, nb, 256, tab, nsnap, w, n, T, mp, wp, me, Phi_out);
+  const size_t flds = ((size_t)kChunk * (wp + 1) + (size_t)wp * (mp + 1)) * sizeof(double);
+  hipLaunchKernelGGL(basis_form_kernel, dim3(nb), dim3(256), flds, ctx->stream, tab, nsnap, w, n,
+                     (const double*)T, mp, wp, me, Phi_out);
+  HIP_TRY(ctx, hipGetLastError());
   // reads every snapshot of the window once, writes m_eff columns of Phi
   HS_TRY(prof_end(ctx, HS_PROF_BASIS_FORM, 8.0 * (double)n * (nsnap + me)));
   return HS_OK;

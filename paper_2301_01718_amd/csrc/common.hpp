@@ -64,6 +64,11 @@ struct hs_ctx {
   double* rcell = nullptr;    // ncell cell residual norms
   double* rcell2 = nullptr;   // ncell cell residual norms
   double* adj = nullptr;      // N  adjoint work vector
+  // tiled relaxation: tile_x x tile_y cells per tile, up to tile_s sweeps per
+  // launch; ntx x nty tiles cover the grid; tiled = false forces one sweep
+  // per launch over the compact cell list
+  int tile_x = 0, tile_y = 0, tile_s = 0, ntx = 0, nty = 0;
+  bool tiled = true;
   double* red = nullptr;      // reduction partials (kRedBlocks * 64 * 64 doubles)
   double* small = nullptr;    // small dense matrices and vectors (16 * 64 * 64 doubles)
   unsigned long long* stats = nullptr;   // kStatSlots
@@ -98,6 +103,9 @@ struct hs_samples {
   int32_t* pos = nullptr;     // ncell, compact index of a hat-S cell or -1
   int32_t* nbr = nullptr;     // 4 * ncell, compact index of each stencil neighbour in hat-S or -1
   int32_t* scan = nullptr;    // scan scratch
+  uint8_t* tflag = nullptr;   // per tile of the context's tiling: holds a hat-S cell
+  int32_t* tiles = nullptr;   // active tile ids (ntiles)
+  int ntiles = 0;
 };
 
 // A hybrid step's frozen decisions (and, after a replay, its internal states).
@@ -295,8 +303,18 @@ hs_status run_filter(hs_ctx* ctx, double* gamma, const double* q_prev, const hs_
 // Solve the linear system whose relaxation data (coef, rhs layout [.. * ncell + p])
 // is given, to relative accuracy eta; result in x (same layout).  rho is the
 // max-norm contraction bound of the relaxation (>= 1: monitored batches).
-hs_status relax_solve(hs_ctx* ctx, const int* hat, const int* nbr, int count, const double* coef,
-                      const double* rhs, double rho, double eta, double* x, int* sweeps);
+hs_status relax_solve(hs_ctx* ctx, const hs_samples* s, const double* coef, const double* rhs, double rho,
+                      double eta, double* x, int* sweeps);
+// Relaxation sweeps k0+1 .. k0+nsweeps on the full mesh (s == nullptr) or the
+// sampled set s, starting from the iterate xin (compact layout).  With q the
+// final iterate is added to the state q (Newton update); otherwise *xlast
+// points to it (one of ctx->d0 / ctx->d1, or xin if nsweeps == 0).  With
+// record, the last sweep reports max |x_k - x_{k-1}| and max |x_k|.
+hs_status relax_sweeps(hs_ctx* ctx, const hs_samples* s, const double* coef, const double* rhs,
+                       const double* xin, int nsweeps, double* q, bool record, const double** xlast);
+void tile_geometry(const hs_problem* pr, int nc, int* tx, int* ty, int* s);
+// Whether the relaxation on s (nullptr: full mesh) runs in tiles.
+bool use_tiles(const hs_ctx* ctx, const hs_samples* s);
 // Bracket one launch of kernel class cls with events (no-op unless enabled).
 hs_status prof_begin(hs_ctx* ctx, int cls);
 hs_status prof_end(hs_ctx* ctx, int cls, double bytes);

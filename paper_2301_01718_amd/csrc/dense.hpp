@@ -22,7 +22,9 @@ constexpr int kChunk = 64;   // rows staged per LDS chunk
 // Gram G = X^T X of a tall matrix whose rows are produced by a Loader into
 // LDS (kChunk rows x ldx, zero padded), accumulated over all chunks of this
 // block; the block's partial wp x wp matrix goes to part[blockIdx.x].
-//   Loader::load(chunk_row0, X /*LDS kChunk x ldx*/) fills the rows.
+//   Loader::prefetch(chunk_row0, regs) issues the loads of a chunk into
+//   registers; Loader::commit(chunk_row0, regs, X /*LDS kChunk x ldx*/) writes
+//   the rows.  The next chunk's loads are in flight during the products.
 // Block: 256 threads = 4 waves; wave v owns tiles t = v, v + 4, ... of the
 // (wp/16)^2 output tiles.
 template <class Loader>
@@ -37,10 +39,14 @@ __global__ void __launch_bounds__(256) gram_kernel(Loader ld, long long nrows, i
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
   const long long nchunks = (nrows + kChunk - 1) / kChunk;
-  for (long long ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+  typename Loader::Regs R;
+  long long ch = blockIdx.x;
+  if (ch < nchunks) ld.prefetch(ch * kChunk, R);
+  for (; ch < nchunks; ch += gridDim.x) {
     __syncthreads();
-    ld.load(ch * kChunk, X, ldx, wp);
+    ld.commit(ch * kChunk, R, X, ldx, wp);
     __syncthreads();
+    if (ch + gridDim.x < nchunks) ld.prefetch((ch + gridDim.x) * kChunk, R);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int tile = wave + 4 * t;
@@ -184,26 +190,16 @@ __device__ inline void jacobi_eig_wave(double* A, double* V, int lda, int n, dou
     if (!rotated) break;
     __syncthreads();
   }
-  if (t == 0) {
-    for (int i = 0; i < n; ++i) {
-      lam[i] = A[i * lda + i];
-      order[i] = i;
+  // stable descending order by rank: rank_i = #{j: l_j > l_i} + #{j < i: l_j == l_i}
+  if (t < n) {
+    const double li = A[t * lda + t];
+    int rk = 0;
+    for (int j = 0; j < n; ++j) {
+      const double lj = A[j * lda + j];
+      rk += (lj > li) || (lj == li && j < t);
     }
-    for (int i = 0; i < n; ++i) {        // stable selection sort, descending
-      int b = i;
-      for (int j = i + 1; j < n; ++j)
-        if (lam[j] > lam[b]) b = j;
-      if (b != i) {
-        const double x = lam[b];
-        const int o = order[b];
-        for (int j = b; j > i; --j) {
-          lam[j] = lam[j - 1];
-          order[j] = order[j - 1];
-        }
-        lam[i] = x;
-        order[i] = o;
-      }
-    }
+    lam[rk] = li;
+    order[rk] = t;
   }
   __syncthreads();
 }

@@ -219,76 +219,9 @@ __global__ void resjac_kernel(Grid g, const double* __restrict__ q, const double
   }
 }
 
-// One Jacobi sweep: dnew = b - sum_X M_X dold[X]; with FINAL, q[cell] += dnew.
-// With RECORD, max |dnew - dold| and max |dnew| go to the stats slots.
-template <int NC, bool FINAL, bool RECORD>
-__global__ void sweep_kernel(Grid g, const int* __restrict__ hat, const int* __restrict__ nbr, int count,
-                             int cap, const double* __restrict__ coef, const double* __restrict__ rhs,
-                             const double* __restrict__ dold, double* __restrict__ dnew,
-                             double* __restrict__ q, double* __restrict__ part) {
-  __shared__ double lds[kBlock / kWave];
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  double diff = 0.0, dn = 0.0;
-  if (p < count) {
-    const int ndir = g.kind == HS_BURGERS_1D ? 2 : 4;
-    double acc[NC];
-#pragma unroll
-    for (int a = 0; a < NC; ++a) acc[a] = rhs[a * cap + p];
-    int i = 0, j = 0, cell = p;
-    if (hat) cell = hat[p];
-    else { i = p % g.nx; j = p / g.nx; }
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-      if (d >= ndir) break;
-      int nb;
-      if (hat) {
-        nb = nbr[d * cap + p];
-        if (nb < 0) continue;
-      } else {
-        nb = neighbour(g, i, j, d);
-        if (nb < 0 || nb == cell) continue;
-      }
-#pragma unroll
-      for (int a = 0; a < NC; ++a)
-#pragma unroll
-        for (int b = 0; b < NC; ++b)
-          acc[a] -= coef[((d * NC + a) * NC + b) * (size_t)cap + p] * dold[b * cap + nb];
-    }
-    if (FINAL) {
-#pragma unroll
-      for (int a = 0; a < NC; ++a) q[a * g.ncell + cell] += acc[a];
-    } else {
-#pragma unroll
-      for (int a = 0; a < NC; ++a) {
-        dnew[a * cap + p] = acc[a];
-        if (RECORD) {
-          diff = fmax(diff, fabs(acc[a] - dold[a * cap + p]));
-          dn = fmax(dn, fabs(acc[a]));
-        }
-      }
-    }
-  }
-  if (RECORD) {
-    diff = block_max(diff, lds);
-    dn = block_max(dn, lds);
-    if (threadIdx.x == 0) {
-      stat_part(part, kStatDiff, diff);
-      stat_part(part, kStatDnorm, dn);
-    }
-  }
-}
-
-template <int NC>
-__global__ void add_update_kernel(Grid g, const int* __restrict__ hat, int count, int cap,
-                                  const double* __restrict__ d, double* __restrict__ q) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= count) return;
-  const int cell = hat ? hat[p] : p;
-#pragma unroll
-  for (int a = 0; a < NC; ++a) q[a * g.ncell + cell] += d[a * cap + p];
-}
-
 // ------------------------------------------------------------ Newton solve
+hs_status linear_solve(hs_ctx* ctx, const hs_samples* s, double rho, double eta, double* q, int* sweeps);
+
 template <int NC>
 static hs_status newton_impl(hs_ctx* ctx, double* q, const double* q_prev, double tol,
                              const hs_samples* s, hs_step_info* info) {
@@ -299,7 +232,6 @@ static hs_status newton_impl(hs_ctx* ctx, double* q, const double* q_prev, doubl
   const int cap = ctx->ncell;
   const int maxit = ctx->p.newton_maxit;
   const double lin_rtol = ctx->p.lin_rtol;
-  const int nb = blocks_for(count);
   int sweeps_total = 0;
   for (int it = 0;; ++it) {
     const int nbs = stat_blocks(count);
@@ -338,131 +270,61 @@ static hs_status newton_impl(hs_ctx* ctx, double* q, const double* q_prev, doubl
     // next residual to a tenth of the tolerance; lin_rtol is the floor.
     const double scale = std::max(1.0, tol / ctx->p.newton_rtol);
     const double eta = std::min(0.1, std::max(lin_rtol, std::max(rmax / scale, 0.1 * tol / rmax)));
-    if (rho < 1.0) {
-      // fixed sweep count from the contraction bound: rho^nsw <= eta
-      int nsw = 1;
-      if (rho > 0.0) nsw = (int)std::ceil(std::log(eta) / std::log(rho));
-      nsw = std::max(1, std::min(nsw, ctx->p.lin_maxit));
-      sweeps_total += nsw;
-      if (nsw == 1) {
-        HS_LAUNCH(ctx, add_update_kernel<NC>, nb, kBlock, g, hat, count, cap, ctx->rhs, q);
-      } else {
-        const double* dold = ctx->rhs;
-        double* bufs[2] = {ctx->d0, ctx->d1};
-        const double sweep_bytes =
-            (double)count * (8.0 * (4 * NC * NC + NC) + 8.0 * NC * 2 + (hat ? 4.0 * 5 : 0.0));
-        for (int k = 2; k <= nsw; ++k) {
-          double* dnew = bufs[k & 1];
-          HS_TRY(prof_begin(ctx, HS_PROF_SWEEP));
-          if (k == nsw)
-            HS_LAUNCH(ctx, (sweep_kernel<NC, true, false>), nb, kBlock, g, hat, nbr, count, cap, ctx->coef,
-                      ctx->rhs, dold, dnew, q, ctx->part);
-          else
-            HS_LAUNCH(ctx, (sweep_kernel<NC, false, false>), nb, kBlock, g, hat, nbr, count, cap, ctx->coef,
-                      ctx->rhs, dold, dnew, q, ctx->part);
-          // reads the relaxation blocks, b and the previous iterate; writes the new one
-          HS_TRY(prof_end(ctx, HS_PROF_SWEEP, sweep_bytes));
-          dold = dnew;
-        }
-      }
-    } else {
-      // The max-norm bound does not prove contraction (components of very
-      // different scales): relax in batches and stop on the fixed-point
-      // difference, with the contraction factor estimated from successive
-      // batches (error <= r/(1-r) * ||delta_{k+1} - delta_k||).
-      constexpr int kBatch = 8;
-      if (nb > kPartCap) return ctx->fail(HS_ERR_SHAPE, "relaxation grid beyond the statistics capacity");
-      const double* dold = ctx->rhs;
-      double* bufs[2] = {ctx->d0, ctx->d1};
-      int k = 1;
-      double prev_diff = -1.0, rate = 0.9;
-      bool conv = false;
-      while (k < ctx->p.lin_maxit) {
-        for (int b = 0; b < kBatch && k < ctx->p.lin_maxit; ++b, ++k) {
-          double* dnew = bufs[k & 1];
-          const bool rec = b == kBatch - 1 || k == ctx->p.lin_maxit - 1;
-          if (rec) {
-            HS_LAUNCH(ctx, (sweep_kernel<NC, false, true>), nb, kBlock, g, hat, nbr, count, cap, ctx->coef,
-                      ctx->rhs, dold, dnew, q, ctx->part);
-          } else {
-            HS_LAUNCH(ctx, (sweep_kernel<NC, false, false>), nb, kBlock, g, hat, nbr, count, cap, ctx->coef,
-                      ctx->rhs, dold, dnew, q, ctx->part);
-          }
-          dold = dnew;
-        }
-        HS_TRY(finish_stats(ctx, nb, (1u << kStatDiff) | (1u << kStatDnorm), 0u));
-        unsigned long long s2[kStatSlots];
-        HS_TRY(read_stats(ctx, s2));
-        const double diff = bits_to_double(s2[kStatDiff]);
-        const double dn = bits_to_double(s2[kStatDnorm]);
-        if (!std::isfinite(diff)) return ctx->fail(HS_ERR_NONFINITE, "non-finite relaxation iterate");
-        if (prev_diff > 0.0 && diff > 0.0)
-          rate = std::min(0.99, std::pow(diff / prev_diff, 1.0 / kBatch));
-        prev_diff = diff;
-        if (diff == 0.0 || (rate < 1.0 && rate / (1.0 - rate) * diff <= eta * dn)) {
-          conv = true;
-          break;
-        }
-      }
-      sweeps_total += k;
-      if (!conv) return ctx->fail(HS_ERR_NOT_CONVERGED, "block-Jacobi relaxation did not converge");
-      HS_LAUNCH(ctx, add_update_kernel<NC>, nb, kBlock, g, hat, count, cap, dold, q);
-    }
+    HS_TRY(linear_solve(ctx, s, rho, eta, q, &sweeps_total));
   }
 }
 
-template <int NC>
-__global__ void copy_compact_kernel(int count, int cap, const double* __restrict__ src, double* __restrict__ dst) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= count) return;
-#pragma unroll
-  for (int a = 0; a < NC; ++a) dst[a * cap + p] = src[a * cap + p];
+// x[a * cap + p] = src[a * cap + p] for p < count (compact layout).
+__global__ void copy_compact_kernel(int nc, int count, int cap, const double* __restrict__ src,
+                                    double* __restrict__ dst) {
+  const long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (k >= (long long)nc * count) return;
+  const long long a = k / count, p = k % count;
+  dst[a * cap + p] = src[a * cap + p];
 }
 
-template <int NC>
-static hs_status relax_impl(hs_ctx* ctx, const int* hat, const int* nbr, int count, const double* coef,
-                            const double* rhs, double rho, double eta, double* x, int* sweeps) {
-  const Grid& g = ctx->g;
-  const int cap = ctx->ncell;
-  const int nb = blocks_for(count);
-  double* bufs[2] = {ctx->d0, ctx->d1};
-  const double* dold = rhs;
-  int used = 1;
-  // fixed sweep count when the bound proves contraction within lin_maxit sweeps
+// Relaxation of the system whose data (ctx->coef, rhs) is loaded, to relative
+// accuracy eta in the max norm; the sweeps start from x_1 = rhs.  With q the
+// solution is added to the state q (Newton update), otherwise written to x
+// (compact layout).  rho < 1 with a sweep count within lin_maxit: that many
+// sweeps (rho^nsw <= eta); otherwise batches of 8 with the stop test on the
+// fixed-point difference and the rate estimated from successive batches
+// (error <= r / (1 - r) * ||x_{k+1} - x_k||).
+static hs_status linear_solve_impl(hs_ctx* ctx, const hs_samples* s, const double* rhs, double rho, double eta,
+                                   double* q, double* x, int* sweeps) {
   int nsw = 1;
   if (rho > 0.0 && rho < 1.0) nsw = std::max(1, (int)std::ceil(std::log(eta) / std::log(rho)));
+  const double* last = rhs;
+  int used;
   if (rho < 1.0 && nsw <= ctx->p.lin_maxit) {
-    for (int k = 2; k <= nsw; ++k) {
-      double* dnew = bufs[k & 1];
-      HS_LAUNCH(ctx, (sweep_kernel<NC, false, false>), nb, kBlock, g, hat, nbr, count, cap, coef, rhs, dold, dnew,
-                (double*)nullptr, ctx->part);
-      dold = dnew;
-    }
+    HS_TRY(prof_begin(ctx, HS_PROF_SWEEP));
+    HS_TRY(relax_sweeps(ctx, s, ctx->coef, rhs, rhs, nsw - 1, q, false, &last));
+    const int count = s ? s->n_s : ctx->ncell;
+    const int per = use_tiles(ctx, s) ? ctx->tile_s : 1;
+    const int launches = (nsw - 1 + per - 1) / per;
+    // each launch reads the relaxation blocks, b and the iterate once and writes the new iterate
+    HS_TRY(prof_end(ctx, HS_PROF_SWEEP, (double)launches * count *
+                                            (8.0 * (4 * ctx->nc * ctx->nc + ctx->nc) + 16.0 * ctx->nc)));
     used = nsw;
   } else {
     constexpr int kBatch = 8;
-    if (nb > kPartCap) return ctx->fail(HS_ERR_SHAPE, "relaxation grid beyond the statistics capacity");
     int k = 1;
     double prev_diff = -1.0, rate = 0.9;
     bool conv = false;
     while (k < ctx->p.lin_maxit) {
-      for (int b = 0; b < kBatch && k < ctx->p.lin_maxit; ++b, ++k) {
-        double* dnew = bufs[k & 1];
-        if (b == kBatch - 1 || k == ctx->p.lin_maxit - 1)
-          HS_LAUNCH(ctx, (sweep_kernel<NC, false, true>), nb, kBlock, g, hat, nbr, count, cap, coef, rhs, dold, dnew,
-                    (double*)nullptr, ctx->part);
-        else
-          HS_LAUNCH(ctx, (sweep_kernel<NC, false, false>), nb, kBlock, g, hat, nbr, count, cap, coef, rhs, dold,
-                    dnew, (double*)nullptr, ctx->part);
-        dold = dnew;
-      }
+      const int b = std::min(kBatch, ctx->p.lin_maxit - k);
+      const double* nxt;
+      HS_TRY(relax_sweeps(ctx, s, ctx->coef, rhs, last, b, nullptr, true, &nxt));
+      last = nxt;
+      k += b;
+      const int nb = use_tiles(ctx, s) ? (s ? s->ntiles : ctx->ntx * ctx->nty) : blocks_for(s ? s->n_s : ctx->ncell);
       HS_TRY(finish_stats(ctx, nb, (1u << kStatDiff) | (1u << kStatDnorm), 0u));
-      unsigned long long s2[kStatSlots];
-      HS_TRY(read_stats(ctx, s2));
-      const double diff = bits_to_double(s2[kStatDiff]);
-      const double dn = bits_to_double(s2[kStatDnorm]);
+      unsigned long long st[kStatSlots];
+      HS_TRY(read_stats(ctx, st));
+      const double diff = bits_to_double(st[kStatDiff]);
+      const double dn = bits_to_double(st[kStatDnorm]);
       if (!std::isfinite(diff)) return ctx->fail(HS_ERR_NONFINITE, "non-finite relaxation iterate");
-      if (prev_diff > 0.0 && diff > 0.0) rate = std::min(0.99, std::pow(diff / prev_diff, 1.0 / kBatch));
+      if (prev_diff > 0.0 && diff > 0.0) rate = std::min(0.99, std::pow(diff / prev_diff, 1.0 / b));
       prev_diff = diff;
       if (diff == 0.0 || (rate < 1.0 && rate / (1.0 - rate) * diff <= eta * dn)) {
         conv = true;
@@ -471,17 +333,27 @@ static hs_status relax_impl(hs_ctx* ctx, const int* hat, const int* nbr, int cou
     }
     used = k;
     if (!conv) return ctx->fail(HS_ERR_NOT_CONVERGED, "block-Jacobi relaxation did not converge");
+    if (q) HS_TRY(relax_sweeps(ctx, s, ctx->coef, rhs, last, 0, q, false, nullptr));
   }
-  HS_LAUNCH(ctx, copy_compact_kernel<NC>, nb, kBlock, count, cap, dold, x);
+  if (x) {
+    const int count = s ? s->n_s : ctx->ncell;
+    if (last != x)
+      HS_LAUNCH(ctx, (copy_compact_kernel), blocks_for((long long)ctx->nc * count), kBlock, ctx->nc, count,
+                ctx->ncell, last, x);
+  }
   if (sweeps) *sweeps += used;
   return HS_OK;
 }
 
-hs_status relax_solve(hs_ctx* ctx, const int* hat, const int* nbr, int count, const double* coef,
-                      const double* rhs, double rho, double eta, double* x, int* sweeps) {
-  if (count == 0) return HS_OK;
-  if (ctx->nc == 1) return relax_impl<1>(ctx, hat, nbr, count, coef, rhs, rho, eta, x, sweeps);
-  return relax_impl<4>(ctx, hat, nbr, count, coef, rhs, rho, eta, x, sweeps);
+hs_status linear_solve(hs_ctx* ctx, const hs_samples* s, double rho, double eta, double* q, int* sweeps) {
+  return linear_solve_impl(ctx, s, ctx->rhs, rho, eta, q, nullptr, sweeps);
+}
+
+hs_status relax_solve(hs_ctx* ctx, const hs_samples* s, const double* coef, const double* rhs, double rho,
+                      double eta, double* x, int* sweeps) {
+  if ((s ? s->n_s : ctx->ncell) == 0) return HS_OK;
+  if (coef != ctx->coef) return ctx->fail(HS_ERR_INVALID_ARG, "relaxation data must be in the context");
+  return linear_solve_impl(ctx, s, rhs, rho, eta, nullptr, x, sweeps);
 }
 
 hs_status newton_solve(hs_ctx* ctx, double* q, const double* q_prev, double tol, const hs_samples* s,
@@ -568,6 +440,9 @@ hs_status hs_create(const hs_problem* pr, void* stream, hs_ctx** out) {
   g.ly = pr->kind == HS_BURGERS_1D ? 0.0 : pr->dt / pr->dy;
   g.gamma = pr->gamma;
   g.inflow = pr->inflow;
+  tile_geometry(pr, ctx->nc, &ctx->tile_x, &ctx->tile_y, &ctx->tile_s);
+  ctx->ntx = (g.nx + ctx->tile_x - 1) / ctx->tile_x;
+  ctx->nty = (g.ny + ctx->tile_y - 1) / ctx->tile_y;
 
   const size_t N = ctx->n, NC = ctx->ncell, nc = ctx->nc;
   hs_status st = HS_OK;
@@ -629,6 +504,15 @@ hs_status hs_prof_read(hs_ctx* ctx, double* total_ms, int32_t* launches, double*
   ctx->prof_used = 0;
   ctx->prof_bytes.clear();
   return HS_OK;
+}
+
+hs_status hs_set_option(hs_ctx* ctx, int32_t option, int64_t value) {
+  if (!ctx) return HS_ERR_INVALID_ARG;
+  if (option == HS_OPT_TILED_SWEEPS && (value == 0 || value == 1)) {
+    ctx->tiled = value == 1;
+    return HS_OK;
+  }
+  return HS_ERR_INVALID_ARG;
 }
 
 hs_status hs_sync(hs_ctx* ctx) {

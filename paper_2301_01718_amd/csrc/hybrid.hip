@@ -19,13 +19,17 @@
 
 namespace hs {
 
-// Gathered rows of Phi at the dofs of hat-S cells (all components).
+// Gathered rows of Phi at the dofs of hat-S cells (all components): thread
+// (r, q) holds row r and columns q, q + 4, ... of the chunk.
 struct GatherLoader {
   const double* Phi;
   long long n;
   int m, nc, ncell, ns;
   const int* hat;
-  __device__ void load(long long row0, double* X, int ldx, int wp) const {
+  struct Regs {
+    double v[kMaxBasis / 4];
+  };
+  __device__ void prefetch(long long row0, Regs& R) const {
     const int r = threadIdx.x % kChunk;
     const long long row = row0 + r;
     long long dof = -1;
@@ -33,8 +37,19 @@ struct GatherLoader {
       const int a = (int)(row / ns), p = (int)(row % ns);
       dof = (long long)a * ncell + hat[p];
     }
-    for (int j = threadIdx.x / kChunk; j < wp; j += blockDim.x / kChunk)
-      X[r * ldx + j] = (dof >= 0 && j < m) ? Phi[(size_t)j * n + dof] : 0.0;
+#pragma unroll
+    for (int i = 0; i < kMaxBasis / 4; ++i) {
+      const int j = threadIdx.x / kChunk + 4 * i;
+      R.v[i] = (dof >= 0 && j < m) ? Phi[(size_t)j * n + dof] : 0.0;
+    }
+  }
+  __device__ void commit(long long, const Regs& R, double* X, int ldx, int wp) const {
+    const int r = threadIdx.x % kChunk;
+#pragma unroll
+    for (int i = 0; i < kMaxBasis / 4; ++i) {
+      const int j = threadIdx.x / kChunk + 4 * i;
+      if (j < wp) X[r * ldx + j] = R.v[i];
+    }
   }
 };
 

@@ -1,0 +1,341 @@
+// Block-Jacobi relaxation sweeps with temporal blocking in LDS.
+//
+// One sweep is x_new = b - sum_X M_X x_old[X] per cell (the relaxation of the
+// Newton correction, and of the transposed systems of the adjoint).  A
+// launch of the tiled kernel covers up to S sweeps: a workgroup stages one
+// tile of the grid plus an S-cell halo (periodic wrap where the grid wraps),
+// keeps its cells' M_X and b in registers, and runs the sweeps in LDS; the
+// region whose values are exact shrinks by one cell per sweep, so after s <= S
+// sweeps the tile itself holds the exact iterate.  On a sampled set the
+// active tiles are those holding a sampled cell; other cells of a tile carry
+// no unknown (their value stays 0 and no sampled cell reads it, exactly as in
+// the compact list form).  Per cell the products are accumulated in the
+// order of the compact-list sweep, so both give the same iterates bit for bit.
+// Per launch each region cell is read once instead of once per sweep; tiles
+// are used where they are dense (the full mesh, compact sampled sets).
+#include "physics.hpp"
+
+#include <algorithm>
+
+namespace hs {
+
+template <int NC, int TSX, int TSY, int S>
+struct TileCfg {
+  static constexpr int RW = TSX + 2 * S;
+  static constexpr int RH = TSY == 1 ? 1 : TSY + 2 * S;
+  static constexpr int R = RW * RH;
+  static constexpr int CPT = (R + kBlock - 1) / kBlock;   // region cells per thread
+};
+
+// tiles: active tile ids (nullptr: tile = blockIdx.x); pos/nbr: compact index
+// of a cell and of its in-set neighbours (nullptr: full mesh, index = cell).
+// xin: iterate before the launch (compact layout x[a * cap + p]); the result
+// goes to xout, or is added to the state q when q != nullptr.  With record,
+// max |x_last - x_prev| and max |x_last| of the tile go to the statistics.
+template <int NC, int TSX, int TSY, int S, bool COEF_REG>
+__global__ void __launch_bounds__(kBlock) tile_sweep_kernel(
+    Grid g, const int* __restrict__ tiles, int ntx, const int* __restrict__ pos, const int* __restrict__ nbr,
+    int cap, const double* __restrict__ coef, const double* __restrict__ rhs, const double* __restrict__ xin,
+    double* __restrict__ xout, double* __restrict__ q, int nsw, int record, double* __restrict__ part) {
+  using C = TileCfg<NC, TSX, TSY, S>;
+  constexpr int RW = C::RW, RH = C::RH, R = C::R, CPT = C::CPT;
+  constexpr bool ONE_D = TSY == 1;
+  constexpr int NDIR = ONE_D ? 2 : 4;
+  __shared__ double xs[2][NC][R];
+  __shared__ double lds[kBlock / kWave];
+  const int tile = tiles ? tiles[blockIdx.x] : (int)blockIdx.x;
+  const int tx = tile % ntx, ty = tile / ntx;
+  const int i0 = tx * TSX - S, j0 = ONE_D ? 0 : ty * TSY - S;
+  const bool per = g.bc == HS_BC_PERIODIC;
+
+  int pidx[CPT];
+  int cells[CPT];
+  unsigned vmask[CPT];
+  double rh[CPT][NC];
+  double cf[COEF_REG ? CPT : 1][COEF_REG ? 4 * NC * NC : 1];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int r = threadIdx.x + c * kBlock;
+    pidx[c] = -1;
+    cells[c] = -1;
+    vmask[c] = 0u;
+    double x[NC];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) x[a] = 0.0;
+    if (r < R) {
+      const int rx = r % RW, ry = r / RW;
+      int gi = i0 + rx, gj = j0 + ry;
+      bool inside;
+      if (per) {
+        gi = ((gi % g.nx) + g.nx) % g.nx;
+        gj = ONE_D ? 0 : ((gj % g.ny) + g.ny) % g.ny;
+        inside = true;
+      } else {
+        inside = gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny;
+      }
+      if (inside) {
+        const int cell = gi + g.nx * gj;
+        const int p = pos ? pos[cell] : cell;
+        cells[c] = cell;
+        if (p >= 0) {
+          pidx[c] = p;
+          unsigned v = 0u;
+#pragma unroll
+          for (int d = 0; d < NDIR; ++d) {
+            bool ok;
+            if (pos) {
+              ok = nbr[d * cap + p] >= 0;
+            } else {
+              const int nb = neighbour(g, gi, gj, d);
+              ok = nb >= 0 && nb != cell;
+            }
+            v |= ok ? (1u << d) : 0u;
+          }
+          vmask[c] = v;
+#pragma unroll
+          for (int a = 0; a < NC; ++a) {
+            rh[c][a] = rhs[a * cap + p];
+            x[a] = xin[a * cap + p];
+          }
+          if constexpr (COEF_REG) {
+#pragma unroll
+            for (int e = 0; e < 4 * NC * NC; ++e) cf[c][e] = coef[(size_t)e * cap + p];
+          }
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        xs[0][a][r] = x[a];
+        xs[1][a][r] = x[a];
+      }
+    }
+  }
+  __syncthreads();
+
+  int cur = 0;
+  for (int k = 0; k < nsw; ++k) {
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      const int r = threadIdx.x + c * kBlock;
+      if (r >= R || pidx[c] < 0) continue;
+      const int p = pidx[c];
+      const int rx = r % RW, ry = r / RW;
+      double acc[NC];
+#pragma unroll
+      for (int a = 0; a < NC; ++a) acc[a] = rh[c][a];
+#pragma unroll
+      for (int d = 0; d < NDIR; ++d) {
+        if (!((vmask[c] >> d) & 1u)) continue;
+        int nr;
+        bool ok;
+        if (d == 0) { ok = rx > 0; nr = r - 1; }
+        else if (d == 1) { ok = rx < RW - 1; nr = r + 1; }
+        else if (d == 2) { ok = ry > 0; nr = r - RW; }
+        else { ok = ry < RH - 1; nr = r + RW; }
+        if (!ok) continue;   // region edge: this cell's value is no longer needed
+#pragma unroll
+        for (int a = 0; a < NC; ++a)
+#pragma unroll
+          for (int b = 0; b < NC; ++b) {
+            const int e = (d * NC + a) * NC + b;
+            double m;
+            if constexpr (COEF_REG) m = cf[c][e];
+            else m = coef[(size_t)e * cap + p];
+            acc[a] -= m * xs[cur][b][nr];
+          }
+      }
+#pragma unroll
+      for (int a = 0; a < NC; ++a) xs[cur ^ 1][a][r] = acc[a];
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+
+  double diff = 0.0, dn = 0.0;
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int r = threadIdx.x + c * kBlock;
+    if (r >= R || pidx[c] < 0) continue;
+    const int rx = r % RW, ry = r / RW;
+    const int li = rx - S, lj = ONE_D ? 0 : ry - S;
+    if (li < 0 || li >= TSX || lj < 0 || lj >= TSY) continue;
+    if (tx * TSX + li >= g.nx || ty * TSY + lj >= g.ny) continue;   // ragged last tile
+    const int p = pidx[c];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      const double x = xs[cur][a][r];
+      if (q) q[a * g.ncell + cells[c]] += x;
+      else xout[a * cap + p] = x;
+      if (record) {
+        diff = fmax(diff, fabs(x - xs[cur ^ 1][a][r]));
+        dn = fmax(dn, fabs(x));
+      }
+    }
+  }
+  if (record) {
+    diff = block_max(diff, lds);
+    dn = block_max(dn, lds);
+    if (threadIdx.x == 0) {
+      stat_part(part, kStatDiff, diff);
+      stat_part(part, kStatDnorm, dn);
+    }
+  }
+}
+
+// Compact-list sweep (the same iteration, one sweep per launch); used for
+// scattered sampled sets, when the tiled form is switched off, or when the
+// grid holds more tiles than the statistics capacity.
+template <int NC, bool FINAL, bool RECORD>
+__global__ void list_sweep_kernel(Grid g, const int* __restrict__ hat, const int* __restrict__ nbr, int count,
+                                  int cap, const double* __restrict__ coef, const double* __restrict__ rhs,
+                                  const double* __restrict__ dold, double* __restrict__ dnew,
+                                  double* __restrict__ q, double* __restrict__ part) {
+  __shared__ double lds[kBlock / kWave];
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  double diff = 0.0, dn = 0.0;
+  if (p < count) {
+    const int ndir = g.kind == HS_BURGERS_1D ? 2 : 4;
+    double acc[NC];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) acc[a] = rhs[a * cap + p];
+    int i = 0, j = 0, cell = p;
+    if (hat) cell = hat[p];
+    else { i = p % g.nx; j = p / g.nx; }
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      if (d >= ndir) break;
+      int nb;
+      if (hat) {
+        nb = nbr[d * cap + p];
+        if (nb < 0) continue;
+      } else {
+        nb = neighbour(g, i, j, d);
+        if (nb < 0 || nb == cell) continue;
+      }
+#pragma unroll
+      for (int a = 0; a < NC; ++a)
+#pragma unroll
+        for (int b = 0; b < NC; ++b)
+          acc[a] -= coef[((d * NC + a) * NC + b) * (size_t)cap + p] * dold[b * cap + nb];
+    }
+    if (FINAL) {
+#pragma unroll
+      for (int a = 0; a < NC; ++a) q[a * g.ncell + cell] += acc[a];
+    } else {
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        dnew[a * cap + p] = acc[a];
+        if (RECORD) {
+          diff = fmax(diff, fabs(acc[a] - dold[a * cap + p]));
+          dn = fmax(dn, fabs(acc[a]));
+        }
+      }
+    }
+  }
+  if (RECORD) {
+    diff = block_max(diff, lds);
+    dn = block_max(dn, lds);
+    if (threadIdx.x == 0) {
+      stat_part(part, kStatDiff, diff);
+      stat_part(part, kStatDnorm, dn);
+    }
+  }
+}
+
+template <int NC>
+__global__ void add_list_kernel(Grid g, const int* __restrict__ hat, int count, int cap,
+                                const double* __restrict__ d, double* __restrict__ q) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= count) return;
+  const int cell = hat ? hat[p] : p;
+#pragma unroll
+  for (int a = 0; a < NC; ++a) q[a * g.ncell + cell] += d[a * cap + p];
+}
+
+// ------------------------------------------------------------------- host
+template <int NC, int TSX, int TSY, int S, bool CR>
+static hs_status launch_tiles(hs_ctx* ctx, const hs_samples* s, int ntiles, const double* coef,
+                              const double* rhs, const double* xin, double* xout, double* q, int k, bool record) {
+  HS_LAUNCH(ctx, (tile_sweep_kernel<NC, TSX, TSY, S, CR>), ntiles, kBlock, ctx->g, s ? s->tiles : nullptr,
+            ctx->ntx, s ? s->pos : nullptr, s ? s->nbr : nullptr, ctx->ncell, coef, rhs, xin, xout, q, k,
+            record ? 1 : 0, ctx->part);
+  return HS_OK;
+}
+
+// Tiles pay when they are dense: every region cell of an active tile is
+// staged and swept, so a scattered sampled set (which activates most tiles
+// while filling few of their cells) is relaxed over its compact list instead.
+bool use_tiles(const hs_ctx* ctx, const hs_samples* s) {
+  const int ntiles = s ? s->ntiles : ctx->ntx * ctx->nty;
+  if (!ctx->tiled || ntiles <= 0 || ntiles > kPartCap) return false;
+  if (!s) return true;
+  return 2.0 * s->n_s >= (double)ntiles * ctx->tile_x * ctx->tile_y;
+}
+
+hs_status relax_sweeps(hs_ctx* ctx, const hs_samples* s, const double* coef, const double* rhs,
+                       const double* xin, int nsweeps, double* q, bool record, const double** xlast) {
+  const int count = s ? s->n_s : ctx->ncell;
+  const int cap = ctx->ncell;
+  const Grid& g = ctx->g;
+  const int NC = ctx->nc;
+  if (nsweeps <= 0) {
+    if (q) {
+      if (NC == 1) HS_LAUNCH(ctx, add_list_kernel<1>, blocks_for(count), kBlock, g, s ? s->hat : nullptr, count, cap, xin, q);
+      else HS_LAUNCH(ctx, add_list_kernel<4>, blocks_for(count), kBlock, g, s ? s->hat : nullptr, count, cap, xin, q);
+    }
+    if (xlast) *xlast = xin;
+    return HS_OK;
+  }
+  const int ntiles = s ? s->ntiles : ctx->ntx * ctx->nty;
+  const bool tiled = use_tiles(ctx, s);
+  const double* in = xin;
+  int left = nsweeps;
+  while (left > 0) {
+    const int k = tiled ? std::min(left, ctx->tile_s) : 1;
+    const bool last = k == left;
+    double* out = in == ctx->d0 ? ctx->d1 : ctx->d0;
+    double* qq = last ? q : nullptr;
+    const bool rec = last && record;
+    if (tiled) {
+      if (g.kind == HS_BURGERS_1D)
+        HS_TRY((launch_tiles<1, 1024, 1, 8, true>(ctx, s, ntiles, coef, rhs, in, out, qq, k, rec)));
+      else if (NC == 1)
+        HS_TRY((launch_tiles<1, 32, 32, 8, true>(ctx, s, ntiles, coef, rhs, in, out, qq, k, rec)));
+      else
+        HS_TRY((launch_tiles<4, 16, 16, 4, false>(ctx, s, ntiles, coef, rhs, in, out, qq, k, rec)));
+    } else {
+      const int nb = blocks_for(count);
+      if (rec && nb > kPartCap) return ctx->fail(HS_ERR_SHAPE, "relaxation grid beyond the statistics capacity");
+      const int* hat = s ? s->hat : nullptr;
+      const int* nbr = s ? s->nbr : nullptr;
+#define HS_SWEEP(NCV)                                                                                         \
+  do {                                                                                                        \
+    if (qq)                                                                                                   \
+      HS_LAUNCH(ctx, (list_sweep_kernel<NCV, true, false>), nb, kBlock, g, hat, nbr, count, cap, coef, rhs, in, \
+                out, qq, ctx->part);                                                                          \
+    else if (rec)                                                                                             \
+      HS_LAUNCH(ctx, (list_sweep_kernel<NCV, false, true>), nb, kBlock, g, hat, nbr, count, cap, coef, rhs, in, \
+                out, qq, ctx->part);                                                                          \
+    else                                                                                                      \
+      HS_LAUNCH(ctx, (list_sweep_kernel<NCV, false, false>), nb, kBlock, g, hat, nbr, count, cap, coef, rhs,   \
+                in, out, qq, ctx->part);                                                                      \
+  } while (0)
+      if (NC == 1) HS_SWEEP(1);
+      else HS_SWEEP(4);
+#undef HS_SWEEP
+    }
+    left -= k;
+    in = out;
+  }
+  if (xlast) *xlast = q ? nullptr : in;
+  return HS_OK;
+}
+
+// Tile geometry of a context (must match the instantiations above).
+void tile_geometry(const hs_problem* pr, int nc, int* tx, int* ty, int* s) {
+  if (pr->kind == HS_BURGERS_1D) { *tx = 1024; *ty = 1; *s = 8; }
+  else if (nc == 1) { *tx = 32; *ty = 32; *s = 8; }
+  else { *tx = 16; *ty = 16; *s = 4; }
+}
+
+}  // namespace hs

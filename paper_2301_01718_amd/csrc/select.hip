@@ -266,6 +266,16 @@ __global__ void scatter_mask_kernel(const int* __restrict__ list, int n, int nce
   if (c >= 0 && c < ncell) mask[c] = 1;   // out-of-range entries are dropped (count check fails)
 }
 
+// Flag the tile of every listed cell (all writers store the same value).
+__global__ void tile_flag_kernel(Grid g, const int* __restrict__ hat, int ns, int tx, int ty, int ntx,
+                                 uint8_t* __restrict__ tflag) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= ns) return;
+  const int cell = hat[p];
+  const int i = cell % g.nx, j = cell / g.nx;
+  tflag[(j / ty) * ntx + i / tx] = 1;
+}
+
 __global__ void fill_u8_kernel(uint8_t* p, int n, uint8_t v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -287,9 +297,9 @@ static hs_status scan_blocks(hs_ctx* ctx, const uint8_t* flags, int n, int* bsum
   return HS_OK;
 }
 
-// Compact flags into list (and pos); returns the count on the host.
-static hs_status compact(hs_ctx* ctx, hs_samples* s, const uint8_t* flags, int* list, int* pos, int* count) {
-  const int n = s->ncell;
+// Compact n flags into list (and pos); returns the count on the host.
+static hs_status compact(hs_ctx* ctx, hs_samples* s, const uint8_t* flags, int n, int* list, int* pos,
+                         int* count) {
   const int nb = blocks_for(n, kScanTile);
   HS_TRY(scan_blocks(ctx, flags, n, s->scan));
   HS_LAUNCH(ctx, compact_kernel, nb, kBlock, flags, n, s->scan, list, pos);
@@ -301,10 +311,17 @@ static hs_status finish_sets(hs_ctx* ctx, hs_samples* s) {
   const int n = s->ncell;
   const int nb = blocks_for(n);
   HS_LAUNCH(ctx, ring_kernel, nb, kBlock, ctx->g, s->mask, s->tmask);
-  HS_TRY(compact(ctx, s, s->mask, s->hat, s->pos, &s->n_s));
-  HS_TRY(compact(ctx, s, s->tmask, s->tilde, nullptr, &s->l));
+  HS_TRY(compact(ctx, s, s->mask, n, s->hat, s->pos, &s->n_s));
+  HS_TRY(compact(ctx, s, s->tmask, n, s->tilde, nullptr, &s->l));
   if (s->n_s > 0)
     HS_LAUNCH(ctx, nbr_table_kernel, blocks_for(s->n_s), kBlock, ctx->g, s->hat, s->n_s, n, s->pos, s->nbr);
+  // active tiles of the tiled relaxation
+  const int nt = ctx->ntx * ctx->nty;
+  HS_LAUNCH(ctx, fill_u8_kernel, blocks_for(nt), kBlock, s->tflag, nt, (uint8_t)0);
+  if (s->n_s > 0)
+    HS_LAUNCH(ctx, tile_flag_kernel, blocks_for(s->n_s), kBlock, ctx->g, s->hat, s->n_s, ctx->tile_x,
+              ctx->tile_y, ctx->ntx, s->tflag);
+  HS_TRY(compact(ctx, s, s->tflag, nt, s->tiles, nullptr, &s->ntiles));
   return HS_OK;
 }
 
@@ -327,6 +344,9 @@ hs_status hs_samples_create(hs_ctx* ctx, hs_samples** out) {
   ok = ok && hipMalloc((void**)&s->tilde, n * 4 + 64) == hipSuccess;
   ok = ok && hipMalloc((void**)&s->pos, n * 4 + 64) == hipSuccess;
   ok = ok && hipMalloc((void**)&s->nbr, 4 * n * 4 + 64) == hipSuccess;
+  const size_t nt = (size_t)ctx->ntx * ctx->nty;
+  ok = ok && hipMalloc((void**)&s->tflag, nt + 64) == hipSuccess;
+  ok = ok && hipMalloc((void**)&s->tiles, nt * 4 + 64) == hipSuccess;
   ok = ok && hipMalloc((void**)&s->scan, (n / kScanTile + 64) * 4 + sizeof(SelectState) + 64) == hipSuccess;
   if (!ok) {
     hs_samples_destroy(s);
@@ -338,7 +358,8 @@ hs_status hs_samples_create(hs_ctx* ctx, hs_samples** out) {
 
 hs_status hs_samples_destroy(hs_samples* s) {
   if (!s) return HS_ERR_INVALID_ARG;
-  void* bufs[] = {s->gmask, s->mask, s->tmask, s->dtmp, s->hat, s->tilde, s->pos, s->nbr, s->scan};
+  void* bufs[] = {s->gmask, s->mask, s->tmask, s->dtmp, s->hat, s->tilde, s->pos, s->nbr, s->scan,
+                  s->tflag, s->tiles};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete s;

@@ -195,3 +195,36 @@ def test_hybrid_step_matches_oracle(name):
     assert rel(host(out), ref["gamma"]) < 1e-12, rel(host(out), ref["gamma"])
     ok, d = indicator_close(host(eps_g), ref["eps"], ref["gamma"], tol=1e-12)
     assert ok, d
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_tiled_sweeps_equal_list_sweeps(name):
+    """The LDS-tiled relaxation (several sweeps per launch) and the one-sweep
+    compact-list relaxation give the same iterates bit for bit: full and
+    sampled Newton solves, and the transposed solve of the adjoint."""
+    need_gpu()
+    print_case("tiled sweeps", name)
+    wl, prob, q0 = case(name, 0)
+    w, m = 12, 8
+    snaps = window(prob, q0, w)
+    o = pod.pod(snaps, w, m)
+    g = snaps[-1]
+    eps, _ = sampling.indicator_full(prob, g, o["Phi"], o["psi_new"])
+    sel = sampling.select(prob, eps, sampling.RULE_FRACTION, wl.frac)
+    Phi = dev(np.ascontiguousarray(o["Phi"].T).reshape(-1))
+    outs = []
+    for tiled in (True, False):
+        ctx = ctx_for(prob)
+        ctx.set_tiled_sweeps(tiled)
+        full, fi = ctx.hdm_step(dev(g))
+        s = ctx.samples_set(dev(sel["hat"]))
+        hyb, hi = ctx.rom_hybrid_step(dev(g), Phi, dev(o["psi_new"]), o["m_eff"], s)
+        lam = dev(np.random.default_rng(2).standard_normal(prob.n))
+        adj, ai = ctx.hdm_step_adjoint(full, lam)
+        print("  tiled", tiled, "sweeps", fi["lin_sweeps"], hi["lin_sweeps"], ai["lin_sweeps"], flush=True)
+        outs.append((full, hyb, adj, fi["lin_sweeps"], hi["lin_sweeps"]))
+    (a0, b0, c0, f0, h0), (a1, b1, c1, f1, h1) = outs
+    assert (f0, h0) == (f1, h1)
+    assert torch.equal(a0, a1)
+    assert torch.equal(b0, b1)
+    assert torch.equal(c0, c1)

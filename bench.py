@@ -43,6 +43,7 @@ def parse():
                     choices=["basis_gram", "basis_form", "recon", "resjac", "sweep", "cellres"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurement")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision measurement")
     ap.add_argument("--adjoint-workload", default="burgers2d_256")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 1 GiB elementwise copy (counter calibration for rocprofv3 --pmc)")
@@ -93,6 +94,36 @@ def cpu_baseline(prob, wl, snap):
     return {"value": 1.0 / dt, "unit": "hybrid steps/s", "cores": int(cores), "kind": "oracle",
             "sample": (f"one hybrid step of {wl.name} ({prob.nx}x{prob.ny}) from the GPU state "
                        f"before the first timed step, with its sampling and POD update: {dt:.1f} s")}
+
+
+def mixed_bench(prob, q0, wl, k_start, steps, ref_state):
+    """The same trajectory with the FP32 master copy of the basis: hybrid
+    steps/s over the same timed steps, and the state difference against the
+    FP64 run at the last timed step."""
+    import numpy as np
+    import torch
+    import paper_2301_01718_amd as hs
+    import paper_2301_01718_amd.driver as D
+    cfg = D.AromConfig(w=wl.w, m=wl.m, z=wl.z, fraction=wl.frac, halo=wl.halo, precision=hs.MIXED_FP32)
+    drv = D.Arom(prob, cfg)
+    dev = drv.ctx.device
+    drv.start(torch.from_numpy(q0).to(dev), wl.steps)
+    while drv.k < k_start:
+        drv.advance()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    recs = []
+    torch.cuda.synchronize(dev)
+    for i in range(steps):
+        ev[i][0].record()
+        recs.append(drv.advance())
+        ev[i][1].record()
+    torch.cuda.synchronize(dev)
+    hyb = [a.elapsed_time(b) for (a, b), r in zip(ev, recs) if r["type"] == "hybrid"]
+    d = torch.linalg.vector_norm(drv.state() - ref_state) / torch.linalg.vector_norm(ref_state)
+    return {"precision": "mixed_fp32 (FP32 basis master copy, FP64 arithmetic)",
+            "value": len(hyb) / (sum(hyb) / 1e3) if hyb else 0.0, "unit": "hybrid steps/s",
+            "hybrid_step_ms": float(np.median(hyb)) if hyb else None,
+            "state_rel_diff_vs_fp64": float(d), "timed_steps": [recs[0]["k"], recs[-1]["k"]]}
 
 
 def adjoint_bench(name, seed):
@@ -207,6 +238,10 @@ def main():
             "traffic": traffic,
             "bytes_per_launch": (k_bytes / k_launch) if k_launch else None,
             "launches": k_launch, "avg_launch_us": (1e3 * k_ms / k_launch) if k_launch else None}
+    mixed = None
+    if not args.no_mixed:
+        log("mixed-precision run ...")
+        mixed = mixed_bench(prob, q0, wl, recs[0]["k"] - 1, args.steps, drv.state())
     adj = None
     if not args.no_adjoint:
         log(f"adjoint trajectory on {args.adjoint_workload} ...")
@@ -232,6 +267,7 @@ def main():
         "mean_n_s_frac": float(np.mean([r["n_s"] / prob.ncell for r in recs if r["type"] == "hybrid"] or [0])),
         "mean_J": float(np.mean([r["J"] for r in recs if r["type"] == "hybrid"] or [0])),
         "m_eff": recs[-1].get("m_eff"),
+        "mixed_fp32": mixed,
         "adjoint": adj,
     }
     print(json.dumps(out), flush=True)

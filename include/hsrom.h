@@ -64,8 +64,16 @@ extern "C" {
 #define HS_BC_PERIODIC       1
 #define HS_BC_TRANSMISSIVE   2 /* every ghost = its boundary cell */
 
+/* Precision of the basis Phi.  HS_FP64: Phi is double.  HS_MIXED_FP32: Phi
+ * is an FP32 master copy (float): every N-stream of the hybrid step that reads
+ * the basis (fit gathers and projections, ring update, reconstruction,
+ * indicator) moves half the bytes, while all arithmetic stays FP64 (products
+ * of the float entries are formed and accumulated in double, and the fit is
+ * refined in FP64).  The snapshot Gram of basis_update stays FP64 in both
+ * modes: the truncation sigma_i > tau_pod sigma_0 resolves eigenvalues down
+ * to tau_pod^2 = 1e-8 of the largest, below FP32 resolution. */
 #define HS_FP64        0
-#define HS_MIXED_FP32  1   /* Grams / projections in FP32 on MFMA + FP64 refinement */
+#define HS_MIXED_FP32  1
 
 typedef int32_t hs_status;
 typedef struct hs_ctx hs_ctx;          /* opaque, library-owned */
@@ -162,8 +170,9 @@ hs_status hs_samples_export(hs_ctx* ctx, const hs_samples* s, int32_t* hat, int3
 /* eps_j = sum_c (gamma - psi - Phi y)^2 at cell j with y = Phi^T (gamma - psi)
  * (a snapshot known everywhere; Sec. 2.3.3).  Cells whose error norm is below
  * floor_rel * max(1, ||gamma||_inf) get eps = 0.  y_out (m doubles) may be NULL. */
-hs_status hs_indicator_full(hs_ctx* ctx, const double* gamma, const double* Phi, const double* psi,
-                            int32_t m, double floor_rel, double* eps, double* y_out);
+hs_status hs_indicator_full(hs_ctx* ctx, const double* gamma, const void* Phi /* see precision */,
+                            const double* psi, int32_t m, double floor_rel, int32_t precision, double* eps,
+                            double* y_out);
 
 /* ------------------------------------------------------ basis_update */
 /* snaps: HOST array of nsnap DEVICE pointers to N-vectors, oldest first:
@@ -175,10 +184,11 @@ hs_status hs_indicator_full(hs_ctx* ctx, const double* gamma, const double* Phi,
  * m_eff = #{i < m : sigma_i > tau_pod * sigma_0}; columns beyond m_eff are
  * left untouched.  sigma_out gets all w singular values (descending).
  * Sign: each right singular vector has its largest-magnitude entry positive.
- * precision: HS_FP64 or HS_MIXED_FP32 (FP32 Gram + FP64 Rayleigh-Ritz refinement). */
+ * precision: HS_FP64 (Phi_out is double*) or HS_MIXED_FP32 (Phi_out is
+ * float*: the FP32 master copy, formed in FP64 and rounded once). */
 hs_status basis_update(hs_ctx* ctx, const double* const* snaps /* host */, int32_t nsnap, int32_t w,
                        int32_t m, double tau_pod, int32_t precision,
-                       double* Phi_out, double* psi_out, double* sigma_out, int32_t* m_eff /* host */);
+                       void* Phi_out, double* psi_out, double* sigma_out, int32_t* m_eff /* host */);
 
 /* --------------------------------------------------- rom_hybrid_step */
 typedef struct hs_hybrid_params {
@@ -190,7 +200,7 @@ typedef struct hs_hybrid_params {
   int32_t jfmax;            /* max passes per filter order (paper: 10) */
   double  rcond_fit;        /* pseudo-inverse cutoff relative to sigma_max (1e-6) */
   double  floor_rel;        /* indicator floor (1e-11) */
-  int32_t precision;        /* HS_FP64 or HS_MIXED_FP32 (fit Gram/projections) */
+  int32_t precision;        /* HS_FP64 (Phi double) or HS_MIXED_FP32 (Phi float) */
 } hs_hybrid_params;
 
 /* One hybrid snapshot from q_prev = gamma_{k-1} with basis (Phi, psi; m
@@ -198,7 +208,7 @@ typedef struct hs_hybrid_params {
  * the reduced coordinates y^(J) to y_out (m, may be NULL) and the indicator
  * of the filtered snapshot to eps_out (ncell, may be NULL).
  * Errors: HS_ERR_RANK (m = 0 or empty hat-S), HS_ERR_NOT_CONVERGED. */
-hs_status rom_hybrid_step(hs_ctx* ctx, const double* q_prev, const double* Phi, const double* psi,
+hs_status rom_hybrid_step(hs_ctx* ctx, const double* q_prev, const void* Phi, const double* psi,
                           int32_t m, const hs_samples* s, const hs_hybrid_params* params /* host */,
                           double* q_out, double* eps_out, double* y_out, hs_step_info* info /* host */);
 
@@ -231,7 +241,7 @@ hs_status hs_htape_samples(hs_htape* tape, hs_samples** out /* host */);
  * applies its filter passes and masks without gating, recording the state
  * after each subiteration's Newton solve and the fit's pseudo-inverse.  With
  * the same q_prev, Phi, psi and m, a replay reproduces the recorded output. */
-hs_status rom_hybrid_step_taped(hs_ctx* ctx, const double* q_prev, const double* Phi, const double* psi,
+hs_status rom_hybrid_step_taped(hs_ctx* ctx, const double* q_prev, const void* Phi, const double* psi,
                                 int32_t m, const hs_samples* s, const hs_hybrid_params* params /* host */,
                                 double* q_out, double* eps_out, hs_step_info* info /* host */,
                                 hs_htape* tape, int32_t mode);
@@ -241,7 +251,7 @@ hs_status rom_hybrid_step_taped(hs_ctx* ctx, const double* q_prev, const double*
 hs_status hdm_step_adjoint(hs_ctx* ctx, const double* q_out, const double* lam_in, double* lam_out,
                            hs_step_info* info /* host, may be NULL */);
 /* lam_out = (d gamma_k / d gamma_{k-1})^T lam_in for a hybrid step replayed
- * into tape (HS_TAPE_REPLAY) with basis Phi (m columns).  Reverse order of the
+ * into tape (HS_TAPE_REPLAY) with basis Phi (m columns, FP64 only).  Reverse order of the
  * forward: transposed filter passes, Phi^T on the unsampled rows, then per
  * subiteration (last first) Phi^T on the ring, the pseudo-inverse transpose,
  * a transposed restricted Newton-matrix solve and the coupling to the ring. */

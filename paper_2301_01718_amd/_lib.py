@@ -96,7 +96,7 @@ _SIGS = {
     "hs_samples_set": [P, P, P, I32],
     "hs_samples_counts": [P, ctypes.POINTER(I32)],
     "hs_samples_export": [P, P, P, P, P],
-    "hs_indicator_full": [P, P, P, P, I32, D, P, P],
+    "hs_indicator_full": [P, P, P, P, I32, D, I32, P, P],
     "basis_update": [P, ctypes.POINTER(P), I32, I32, I32, D, I32, P, P, P, ctypes.POINTER(I32)],
     "rom_hybrid_step": [P, P, P, P, I32, P, ctypes.POINTER(HybridParams), P, P, P,
                         ctypes.POINTER(StepInfo)],
@@ -139,6 +139,24 @@ def _ptr(t):
     if t is None:
         return None
     return ctypes.c_void_p(t.data_ptr())
+
+
+def basis_precision(Phi):
+    """FP64 for a float64 basis, MIXED_FP32 for its float32 master copy."""
+    if Phi.dtype == torch.float64:
+        return FP64
+    if Phi.dtype == torch.float32:
+        return MIXED_FP32
+    raise ValueError(f"basis must be float64 or float32, got {Phi.dtype}")
+
+
+def _with_precision(params, prec):
+    if params.precision == prec:
+        return params
+    hp = HybridParams()
+    ctypes.pointer(hp)[0] = params
+    hp.precision = prec
+    return hp
 
 
 class Context:
@@ -241,15 +259,23 @@ class Context:
         self._check(lib().hs_samples_set(self.h, s.h, _ptr(hat) if hat.numel() else None, hat.numel()))
         return s
 
+    def _basis(self, Phi, m):
+        if not Phi.is_contiguous() or Phi.numel() < m * self.n or Phi.device != self.device:
+            raise ValueError(f"basis must be a contiguous tensor of at least {m} x {self.n} entries on {self.device}")
+        return basis_precision(Phi)
+
     def indicator_full(self, gamma, Phi, psi, m, floor_rel=1e-11, eps=None, y=None):
+        prec = self._basis(Phi, m)
         eps = self.empty(self.ncell) if eps is None else self._in(eps, self.ncell)
         y = self.empty(m) if y is None else y
         self._check(lib().hs_indicator_full(self.h, _ptr(self._in(gamma)), _ptr(Phi), _ptr(self._in(psi)), m,
-                                            floor_rel, _ptr(eps), _ptr(y)))
+                                            floor_rel, prec, _ptr(eps), _ptr(y)))
         return eps, y
 
     # ------------------------------------------------------------- basis
-    def basis_update(self, snaps, w, m, Phi_out, psi_out, sigma_out, tau_pod=1e-4, precision=FP64):
+    def basis_update(self, snaps, w, m, Phi_out, psi_out, sigma_out, tau_pod=1e-4):
+        """Phi_out float64: FP64 basis; float32: the FP32 master copy (HS_MIXED_FP32)."""
+        precision = self._basis(Phi_out, m)
         arr = (P * len(snaps))(*[P(self._in(s).data_ptr()) for s in snaps])
         me = I32(0)
         self._check(lib().basis_update(self.h, arr, len(snaps), w, m, tau_pod, precision, _ptr(Phi_out),
@@ -258,7 +284,7 @@ class Context:
 
     # -------------------------------------------------------------- hybrid
     def rom_hybrid_step(self, q_prev, Phi, psi, m, samples, params=None, out=None, eps=None, y=None):
-        params = params or hybrid_params()
+        params = _with_precision(params or hybrid_params(), self._basis(Phi, m))
         out = self.empty() if out is None else out
         info = StepInfo()
         self._check(lib().rom_hybrid_step(self.h, _ptr(self._in(q_prev)), _ptr(Phi), _ptr(self._in(psi)), m,
@@ -281,7 +307,7 @@ class Context:
 
     def rom_hybrid_step_taped(self, q_prev, Phi, psi, m, tape, mode, samples=None, params=None, out=None,
                               eps=None):
-        params = params or hybrid_params()
+        params = _with_precision(params or hybrid_params(), self._basis(Phi, m))
         out = self.empty() if out is None else out
         info = StepInfo()
         self._check(lib().rom_hybrid_step_taped(self.h, _ptr(self._in(q_prev)), _ptr(Phi), _ptr(self._in(psi)), m,

@@ -24,7 +24,7 @@ import time
 
 import torch
 
-from ._lib import TAPE_REPLAY
+from ._lib import FP64, TAPE_REPLAY
 from .driver import Arom, AromConfig
 
 
@@ -53,6 +53,8 @@ class Trajectory:
                  ctx=None, verify_replay: bool = True):
         if checkpoint_every < 1:
             raise ValueError("checkpoint_every must be >= 1")
+        if cfg.precision != FP64:
+            raise ValueError("the adjoint runs on an FP64 basis (AromConfig.precision = FP64)")
         self.prob = prob
         self.cfg = cfg
         self.steps = steps

@@ -390,6 +390,7 @@ hs_status rom_hybrid_step_adjoint(hs_ctx* ctx, const double* Phi, int32_t m, con
   if (!ctx || !Phi || !tape || !lam_in || !lam_out || tape->ctx != ctx) return HS_ERR_INVALID_ARG;
   if (!tape->replayed) return ctx->fail(HS_ERR_INVALID_ARG, "adjoint needs a replayed tape");
   if (m != tape->m) return ctx->fail(HS_ERR_INVALID_ARG, "basis size differs from the replayed step");
+  if (tape->precision != HS_FP64) return ctx->fail(HS_ERR_INVALID_ARG, "adjoint needs an FP64 basis");
   const hs_samples* s = tape->s;
   const int ncell = ctx->ncell, nc = ctx->nc;
   const long long N = ctx->n;

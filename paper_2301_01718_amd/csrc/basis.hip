@@ -228,9 +228,11 @@ __global__ void __launch_bounds__(256) basis_eig_kernel(const double* __restrict
 // C^T = T^T X^T so that each 16-lane group writes 16 consecutive rows of one
 // column of Phi.  The next chunk's loads are in flight during the products.
 // 256 threads; dynamic LDS: X (kChunk x (wp + 1)) then T (wp x (mp + 1)).
+// TP = double, or float for the FP32 master copy (rounded once on store).
+template <typename TP>
 __global__ void __launch_bounds__(256) basis_form_kernel(const double* const* __restrict__ snaps, int nsnap,
                                                          int w, long long n, const double* __restrict__ T,
-                                                         int mp, int wp, int meff, double* __restrict__ Phi) {
+                                                         int mp, int wp, int meff, TP* __restrict__ Phi) {
   extern __shared__ double sh[];
   const int ldx = wp + 1, ldt = mp + 1;
   double* X = sh;
@@ -261,7 +263,7 @@ __global__ void __launch_bounds__(256) basis_form_kernel(const double* const* __
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int col = mb * 16 + lane / 16 + 4 * i;
-        if (col < meff && orow < n) Phi[(size_t)col * n + orow] = acc[i];
+        if (col < meff && orow < n) Phi[(size_t)col * n + orow] = (TP)acc[i];
       }
     }
   }
@@ -272,13 +274,13 @@ __global__ void __launch_bounds__(256) basis_form_kernel(const double* const* __
 using namespace hs;
 
 extern "C" hs_status basis_update(hs_ctx* ctx, const double* const* snaps, int32_t nsnap, int32_t w, int32_t m,
-                                  double tau_pod, int32_t precision, double* Phi_out, double* psi_out,
+                                  double tau_pod, int32_t precision, void* Phi_out, double* psi_out,
                                   double* sigma_out, int32_t* m_eff) {
   if (!ctx || !snaps || !Phi_out || !psi_out || !sigma_out || !m_eff) return HS_ERR_INVALID_ARG;
   if (w < 2 || w > ctx->p.w_max || (nsnap != w && nsnap != w + 1)) return HS_ERR_INVALID_ARG;
   if (m < 1 || m > ctx->p.m_max || m > w) return HS_ERR_INVALID_ARG;
   if (!(tau_pod >= 0.0 && tau_pod < 1.0)) return HS_ERR_INVALID_ARG;
-  if (precision != HS_FP64) return ctx->fail(HS_ERR_INVALID_ARG, "basis_update: only HS_FP64 in this build");
+  if (precision != HS_FP64 && precision != HS_MIXED_FP32) return HS_ERR_INVALID_ARG;
   for (int j = 0; j < nsnap; ++j)
     if (!snaps[j]) return HS_ERR_INVALID_ARG;
   // pointer table to device memory through the pinned staging area
@@ -308,10 +310,15 @@ extern "C" hs_status basis_update(hs_ctx* ctx, const double* const* snaps, int32
   if (me == 0) return HS_OK;
   HS_TRY(prof_begin(ctx, HS_PROF_BASIS_FORM));
   const size_t flds = ((size_t)kChunk * (wp + 1) + (size_t)wp * (mp + 1)) * sizeof(double);
-  hipLaunchKernelGGL(basis_form_kernel, dim3(nb), dim3(256), flds, ctx->stream, tab, nsnap, w, n,
-                     (const double*)T, mp, wp, me, Phi_out);
+  if (precision == HS_MIXED_FP32)
+    hipLaunchKernelGGL(basis_form_kernel<float>, dim3(nb), dim3(256), flds, ctx->stream, tab, nsnap, w, n,
+                       (const double*)T, mp, wp, me, (float*)Phi_out);
+  else
+    hipLaunchKernelGGL(basis_form_kernel<double>, dim3(nb), dim3(256), flds, ctx->stream, tab, nsnap, w, n,
+                       (const double*)T, mp, wp, me, (double*)Phi_out);
   HIP_TRY(ctx, hipGetLastError());
   // reads every snapshot of the window once, writes m_eff columns of Phi
-  HS_TRY(prof_end(ctx, HS_PROF_BASIS_FORM, 8.0 * (double)n * (nsnap + me)));
+  const double phi_bytes = precision == HS_MIXED_FP32 ? 4.0 : 8.0;
+  HS_TRY(prof_end(ctx, HS_PROF_BASIS_FORM, (double)n * (8.0 * nsnap + phi_bytes * me)));
   return HS_OK;
 }

@@ -121,6 +121,7 @@ struct hs_htape {
   size_t us_cap = 0;          // capacity of us in doubles
   double* gp = nullptr;       // fit pseudo-inverse (m x m, replay)
   int m = 0;
+  int precision = HS_FP64;    // basis precision of the replay
   bool recorded = false, replayed = false;
 };
 

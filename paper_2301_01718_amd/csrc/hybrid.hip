@@ -21,8 +21,9 @@ namespace hs {
 
 // Gathered rows of Phi at the dofs of hat-S cells (all components): thread
 // (r, q) holds row r and columns q, q + 4, ... of the chunk.
+template <typename TP>
 struct GatherLoader {
-  const double* Phi;
+  const TP* Phi;
   long long n;
   int m, nc, ncell, ns;
   const int* hat;
@@ -40,7 +41,7 @@ struct GatherLoader {
 #pragma unroll
     for (int i = 0; i < kMaxBasis / 4; ++i) {
       const int j = threadIdx.x / kChunk + 4 * i;
-      R.v[i] = (dof >= 0 && j < m) ? Phi[(size_t)j * n + dof] : 0.0;
+      R.v[i] = (dof >= 0 && j < m) ? (double)Phi[(size_t)j * n + dof] : 0.0;
     }
   }
   __device__ void commit(long long, const Regs& R, double* X, int ldx, int wp) const {
@@ -85,8 +86,8 @@ __global__ void __launch_bounds__(256) pinv_kernel(const double* __restrict__ G,
 
 // Partial projections Phi_rows^T d over rows (gathered if hat != nullptr):
 // mode 0: d = u - psi; mode 1: d = u - psi - Phi_row y0.
-template <int MP>
-__global__ void __launch_bounds__(256) project_kernel(const double* __restrict__ Phi, long long n, int m,
+template <int MP, typename TP>
+__global__ void __launch_bounds__(256) project_kernel(const TP* __restrict__ Phi, long long n, int m,
                                                       int nc, int ncell, const int* __restrict__ hat, int ns,
                                                       const double* __restrict__ u, const double* __restrict__ psi,
                                                       const double* __restrict__ y0, int mode,
@@ -105,7 +106,7 @@ __global__ void __launch_bounds__(256) project_kernel(const double* __restrict__
     if (hat) dof = (row / ns) * (long long)ncell + hat[row % ns];
     double ph[MP];
 #pragma unroll
-    for (int j = 0; j < MP; ++j) ph[j] = j < m ? Phi[(size_t)j * n + dof] : 0.0;
+    for (int j = 0; j < MP; ++j) ph[j] = j < m ? (double)Phi[(size_t)j * n + dof] : 0.0;
     double d = u[dof] - psi[dof];
     if (mode == 1) {
       double s = 0.0;
@@ -169,7 +170,8 @@ __global__ void __launch_bounds__(256) project_finish_kernel(const double* __res
 }
 
 // u <- psi + Phi y on the dofs of the listed cells.
-__global__ void ring_update_kernel(const double* __restrict__ Phi, long long n, int m, int nc, int ncell,
+template <typename TP>
+__global__ void ring_update_kernel(const TP* __restrict__ Phi, long long n, int m, int nc, int ncell,
                                    const int* __restrict__ cells, int nl, const double* __restrict__ psi,
                                    const double* __restrict__ y, double* __restrict__ u) {
   __shared__ double yl[kMaxBasis];
@@ -179,13 +181,14 @@ __global__ void ring_update_kernel(const double* __restrict__ Phi, long long n, 
   if (k >= (long long)nc * nl) return;
   const long long dof = (k / nl) * (long long)ncell + cells[k % nl];
   double s = 0.0;
-  for (int j = 0; j < m; ++j) s += Phi[(size_t)j * n + dof] * yl[j];
+  for (int j = 0; j < m; ++j) s += (double)Phi[(size_t)j * n + dof] * yl[j];
   u[dof] = psi[dof] + s;
 }
 
 // rho = psi + Phi y everywhere; gamma = u on hat-S cells, rho elsewhere.
 // With mask == nullptr only rho is written.
-__global__ void recon_kernel(const double* __restrict__ Phi, long long n, int m, int ncell,
+template <typename TP>
+__global__ void recon_kernel(const TP* __restrict__ Phi, long long n, int m, int ncell,
                              const double* __restrict__ psi, const double* __restrict__ y,
                              const uint8_t* __restrict__ mask, const double* __restrict__ u,
                              double* __restrict__ gamma, double* __restrict__ rho) {
@@ -195,7 +198,7 @@ __global__ void recon_kernel(const double* __restrict__ Phi, long long n, int m,
   const long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (r >= n) return;
   double s = 0.0;
-  for (int j = 0; j < m; ++j) s += Phi[(size_t)j * n + r] * yl[j];
+  for (int j = 0; j < m; ++j) s += (double)Phi[(size_t)j * n + r] * yl[j];
   const double rr = psi[r] + s;
   rho[r] = rr;
   if (mask) gamma[r] = mask[r % ncell] ? u[r] : rr;
@@ -411,56 +414,102 @@ static hs_status replay_filter(hs_ctx* ctx, double* gamma, const hs_htape* tape,
 // ------------------------------------------------------------- fit helpers
 static int pad16(int m) { return (m + 15) / 16 * 16; }
 
-static hs_status launch_project(hs_ctx* ctx, const double* Phi, int m, const int* hat, int ns,
-                                const double* u, const double* psi, const double* y0, int mode, int* nb_out) {
-  const long long rows = hat ? (long long)ctx->nc * ns : ctx->n;
-  const int nb = (int)std::max<long long>(1, std::min<long long>((rows + kBlock - 1) / kBlock, 512));
-  *nb_out = nb;
-  const int mp = pad16(m);
-  switch (mp) {
-    case 16: HS_LAUNCH(ctx, project_kernel<16>, nb, kBlock, Phi, (long long)ctx->n, m, ctx->nc, ctx->ncell, hat, ns, u, psi, y0, mode, ctx->red); break;
-    case 32: HS_LAUNCH(ctx, project_kernel<32>, nb, kBlock, Phi, (long long)ctx->n, m, ctx->nc, ctx->ncell, hat, ns, u, psi, y0, mode, ctx->red); break;
-    case 48: HS_LAUNCH(ctx, project_kernel<48>, nb, kBlock, Phi, (long long)ctx->n, m, ctx->nc, ctx->ncell, hat, ns, u, psi, y0, mode, ctx->red); break;
-    default: HS_LAUNCH(ctx, project_kernel<64>, nb, kBlock, Phi, (long long)ctx->n, m, ctx->nc, ctx->ncell, hat, ns, u, psi, y0, mode, ctx->red); break;
+template <typename TP>
+static hs_status launch_project_t(hs_ctx* ctx, const TP* Phi, int m, const int* hat, int ns, const double* u,
+                                  const double* psi, const double* y0, int mode, int nb) {
+  const long long n = ctx->n;
+  switch (pad16(m)) {
+    case 16: HS_LAUNCH(ctx, (project_kernel<16, TP>), nb, kBlock, Phi, n, m, ctx->nc, ctx->ncell, hat, ns, u, psi, y0, mode, ctx->red); break;
+    case 32: HS_LAUNCH(ctx, (project_kernel<32, TP>), nb, kBlock, Phi, n, m, ctx->nc, ctx->ncell, hat, ns, u, psi, y0, mode, ctx->red); break;
+    case 48: HS_LAUNCH(ctx, (project_kernel<48, TP>), nb, kBlock, Phi, n, m, ctx->nc, ctx->ncell, hat, ns, u, psi, y0, mode, ctx->red); break;
+    default: HS_LAUNCH(ctx, (project_kernel<64, TP>), nb, kBlock, Phi, n, m, ctx->nc, ctx->ncell, hat, ns, u, psi, y0, mode, ctx->red); break;
   }
   return HS_OK;
 }
 
-// Gram of the (gathered) rows and its truncated pseudo-inverse.
-static hs_status fit_factor(hs_ctx* ctx, const double* Phi, int m, const int* hat, int ns, double rcond) {
+// Phi is double (HS_FP64) or float (HS_MIXED_FP32).
+static hs_status launch_project(hs_ctx* ctx, const void* Phi, int prec, int m, const int* hat, int ns,
+                                const double* u, const double* psi, const double* y0, int mode, int* nb_out) {
+  const long long rows = hat ? (long long)ctx->nc * ns : ctx->n;
+  const int nb = (int)std::max<long long>(1, std::min<long long>((rows + kBlock - 1) / kBlock, 512));
+  *nb_out = nb;
+  if (prec == HS_MIXED_FP32)
+    return launch_project_t(ctx, (const float*)Phi, m, hat, ns, u, psi, y0, mode, nb);
+  return launch_project_t(ctx, (const double*)Phi, m, hat, ns, u, psi, y0, mode, nb);
+}
+
+template <typename TP>
+static hs_status launch_ring(hs_ctx* ctx, const TP* Phi, int m, const hs_samples* s, const double* psi,
+                             const double* y, double* u) {
+  HS_LAUNCH(ctx, ring_update_kernel<TP>, blocks_for((long long)ctx->nc * s->l), kBlock, Phi, (long long)ctx->n, m,
+            ctx->nc, ctx->ncell, s->tilde, s->l, psi, y, u);
+  return HS_OK;
+}
+
+template <typename TP>
+static hs_status launch_recon(hs_ctx* ctx, const TP* Phi, int m, const double* psi, const double* y,
+                              const uint8_t* mask, const double* u, double* gamma, double* rho) {
+  HS_LAUNCH(ctx, recon_kernel<TP>, blocks_for(ctx->n), kBlock, Phi, (long long)ctx->n, m, ctx->ncell, psi, y, mask,
+            u, gamma, rho);
+  return HS_OK;
+}
+
+static hs_status ring_update(hs_ctx* ctx, const void* Phi, int prec, int m, const hs_samples* s, const double* psi,
+                             const double* y, double* u) {
+  if (prec == HS_MIXED_FP32) return launch_ring(ctx, (const float*)Phi, m, s, psi, y, u);
+  return launch_ring(ctx, (const double*)Phi, m, s, psi, y, u);
+}
+
+static hs_status reconstruct(hs_ctx* ctx, const void* Phi, int prec, int m, const double* psi, const double* y,
+                             const uint8_t* mask, const double* u, double* gamma, double* rho) {
+  if (prec == HS_MIXED_FP32) return launch_recon(ctx, (const float*)Phi, m, psi, y, mask, u, gamma, rho);
+  return launch_recon(ctx, (const double*)Phi, m, psi, y, mask, u, gamma, rho);
+}
+
+// Gram of the (gathered) rows and its truncated pseudo-inverse (FP64 MFMA on
+// the basis entries in either storage precision).
+template <typename TP>
+static hs_status launch_fit_gram(hs_ctx* ctx, const TP* Phi, int m, const int* hat, int ns, int nb, int wp,
+                                 long long rows) {
+  GatherLoader<TP> ld{Phi, (long long)ctx->n, m, ctx->nc, ctx->ncell, ns, hat};
+  const size_t lds = (size_t)kChunk * (wp + 1) * sizeof(double);
+  hipLaunchKernelGGL(gram_kernel<GatherLoader<TP>>, dim3(nb), dim3(256), lds, ctx->stream, ld, rows, wp, ctx->red);
+  HIP_TRY(ctx, hipGetLastError());
+  return HS_OK;
+}
+
+static hs_status fit_factor(hs_ctx* ctx, const void* Phi, int prec, int m, const int* hat, int ns, double rcond) {
   const int wp = pad16(m);
   const long long rows = hat ? (long long)ctx->nc * ns : ctx->n;
   const long long nchunks = (rows + kChunk - 1) / kChunk;
   const int nb = (int)std::max<long long>(1, std::min<long long>(nchunks, 512));
-  GatherLoader ld{Phi, (long long)ctx->n, m, ctx->nc, ctx->ncell, ns, hat};
-  const size_t lds = (size_t)kChunk * (wp + 1) * sizeof(double);
-  hipLaunchKernelGGL(gram_kernel<GatherLoader>, dim3(nb), dim3(256), lds, ctx->stream, ld, rows, wp, ctx->red);
-  HIP_TRY(ctx, hipGetLastError());
+  if (prec == HS_MIXED_FP32) HS_TRY(launch_fit_gram(ctx, (const float*)Phi, m, hat, ns, nb, wp, rows));
+  else HS_TRY(launch_fit_gram(ctx, (const double*)Phi, m, hat, ns, nb, wp, rows));
   HS_LAUNCH(ctx, gram_reduce_kernel, m * m, kBlock, ctx->red, nb, wp, m, ctx->small + kSmG);
   HS_LAUNCH(ctx, pinv_kernel, 1, 256, ctx->small + kSmG, m, rcond, ctx->small + kSmGp, ctx->small + kSmMisc);
   return HS_OK;
 }
 
 // y = pinv fit of (u - psi) on the rows, with one refinement step.
-static hs_status fit_solve(hs_ctx* ctx, const double* Phi, int m, const int* hat, int ns, const double* u,
+static hs_status fit_solve(hs_ctx* ctx, const void* Phi, int prec, int m, const int* hat, int ns, const double* u,
                            const double* psi, int first) {
   double* sm = ctx->small;
   int nb;
-  HS_TRY(launch_project(ctx, Phi, m, hat, ns, u, psi, nullptr, 0, &nb));
+  HS_TRY(launch_project(ctx, Phi, prec, m, hat, ns, u, psi, nullptr, 0, &nb));
   HS_LAUNCH(ctx, project_finish_kernel, 1, 256, ctx->red, nb, pad16(m), m, sm + kSmGp, 0, sm + kSmY0, sm + kSmY,
             sm + kSmYPrev, sm + kSmMisc, first);
-  HS_TRY(launch_project(ctx, Phi, m, hat, ns, u, psi, sm + kSmY0, 1, &nb));
+  HS_TRY(launch_project(ctx, Phi, prec, m, hat, ns, u, psi, sm + kSmY0, 1, &nb));
   HS_LAUNCH(ctx, project_finish_kernel, 1, 256, ctx->red, nb, pad16(m), m, sm + kSmGp, 1, sm + kSmY0, sm + kSmY,
             sm + kSmYPrev, sm + kSmMisc, first);
   return HS_OK;
 }
 
 // mode: -1 plain step, HS_TAPE_RECORD, HS_TAPE_REPLAY (see the header).
-static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const double* Phi, const double* psi, int m,
+static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const void* Phi, const double* psi, int m,
                              const hs_samples* s, const hs_hybrid_params* hp, double* q_out, double* eps_out,
                              double* y_out, hs_step_info* info, hs_htape* tape, int mode) {
   if (!ctx || !q_prev || !Phi || !psi || !hp || !q_out) return HS_ERR_INVALID_ARG;
-  if (q_out == q_prev || q_out == psi || q_out == Phi) return HS_ERR_INVALID_ARG;
+  if (q_out == q_prev || q_out == psi || (const void*)q_out == Phi) return HS_ERR_INVALID_ARG;
   const bool replay = mode == HS_TAPE_REPLAY;
   if (mode >= 0 && (!tape || tape->ctx != ctx)) return HS_ERR_INVALID_ARG;
   if (replay) {
@@ -473,7 +522,8 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const double* Ph
     return HS_ERR_INVALID_ARG;
   for (int o = 0; o < hp->n_orders; ++o)
     if (hp->filter_orders[o] < 1 || hp->filter_orders[o] > 3) return HS_ERR_INVALID_ARG;
-  if (hp->precision != HS_FP64) return ctx->fail(HS_ERR_INVALID_ARG, "rom_hybrid_step: only HS_FP64 in this build");
+  const int prec = hp->precision;
+  if (prec != HS_FP64 && prec != HS_MIXED_FP32) return HS_ERR_INVALID_ARG;
   if (s->n_s == 0) return ctx->fail(HS_ERR_RANK, "empty sampled set");
   hs_step_info local{};
   hs_step_info* inf = info ? info : &local;
@@ -501,7 +551,7 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const double* Ph
   double* sm = ctx->small;
   HIP_TRY(ctx, hipMemcpyAsync(u, q_prev, ctx->n * 8, hipMemcpyDeviceToDevice, ctx->stream));
 
-  HS_TRY(fit_factor(ctx, Phi, m, s->hat, s->n_s, hp->rcond_fit));
+  HS_TRY(fit_factor(ctx, Phi, prec, m, s->hat, s->n_s, hp->rcond_fit));
   double misc[3];
   HS_TRY(readback(ctx, sm + kSmMisc, 3 * sizeof(double), misc));
   inf->fit_rank = (int)misc[1];
@@ -513,10 +563,8 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const double* Ph
     if (replay)
       HIP_TRY(ctx, hipMemcpyAsync(tape->us + (size_t)(j - 1) * ctx->n, u, ctx->n * 8, hipMemcpyDeviceToDevice,
                                   ctx->stream));
-    HS_TRY(fit_solve(ctx, Phi, m, s->hat, s->n_s, u, psi, j == 1));
-    if (s->l > 0)
-      HS_LAUNCH(ctx, ring_update_kernel, blocks_for((long long)ctx->nc * s->l), kBlock, Phi, (long long)ctx->n, m,
-                ctx->nc, ctx->ncell, s->tilde, s->l, psi, sm + kSmY, u);
+    HS_TRY(fit_solve(ctx, Phi, prec, m, s->hat, s->n_s, u, psi, j == 1));
+    if (s->l > 0) HS_TRY(ring_update(ctx, Phi, prec, m, s, psi, sm + kSmY, u));
     inf->subiters = j;
     if (replay) continue;
     double dy;
@@ -527,12 +575,13 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const double* Ph
   if (replay) {
     HIP_TRY(ctx, hipMemcpyAsync(tape->gp, sm + kSmGp, (size_t)m * m * 8, hipMemcpyDeviceToDevice, ctx->stream));
     tape->m = m;
+    tape->precision = prec;
   }
   HS_TRY(prof_begin(ctx, HS_PROF_RECON));
-  HS_LAUNCH(ctx, recon_kernel, blocks_for(ctx->n), kBlock, Phi, (long long)ctx->n, m, ctx->ncell, psi, sm + kSmY,
-            s->mask, u, q_out, ctx->rho);
+  HS_TRY(reconstruct(ctx, Phi, prec, m, psi, sm + kSmY, s->mask, u, q_out, ctx->rho));
   // reads m columns of Phi, psi, u and the mask; writes gamma and rho
-  HS_TRY(prof_end(ctx, HS_PROF_RECON, 8.0 * (double)ctx->n * (m + 4) + (double)ctx->ncell));
+  const double phi_bytes = prec == HS_MIXED_FP32 ? 4.0 : 8.0;
+  HS_TRY(prof_end(ctx, HS_PROF_RECON, (double)ctx->n * (phi_bytes * m + 32.0) + (double)ctx->ncell));
   if (replay) HS_TRY(replay_filter(ctx, q_out, tape, inf));
   else HS_TRY(run_filter(ctx, q_out, q_prev, hp, inf, mode == HS_TAPE_RECORD ? tape : nullptr));
   if (eps_out) {
@@ -573,21 +622,21 @@ hs_status hs_filter(hs_ctx* ctx, const double* gamma_in, const double* q_prev, c
   return hs_sync(ctx);
 }
 
-hs_status hs_indicator_full(hs_ctx* ctx, const double* gamma, const double* Phi, const double* psi, int32_t m,
-                            double floor_rel, double* eps, double* y_out) {
+hs_status hs_indicator_full(hs_ctx* ctx, const double* gamma, const void* Phi, const double* psi, int32_t m,
+                            double floor_rel, int32_t precision, double* eps, double* y_out) {
   if (!ctx || !gamma || !Phi || !psi || !eps) return HS_ERR_INVALID_ARG;
   if (m < 1 || m > ctx->p.m_max) return HS_ERR_INVALID_ARG;
+  if (precision != HS_FP64 && precision != HS_MIXED_FP32) return HS_ERR_INVALID_ARG;
   double* sm = ctx->small;
   int nb;
-  HS_TRY(launch_project(ctx, Phi, m, nullptr, 0, gamma, psi, nullptr, 0, &nb));
+  HS_TRY(launch_project(ctx, Phi, precision, m, nullptr, 0, gamma, psi, nullptr, 0, &nb));
   // y = Phi^T (gamma - psi): G+ = I
   std::vector<double> eye(m * m, 0.0);
   for (int i = 0; i < m; ++i) eye[i * m + i] = 1.0;
   HIP_TRY(ctx, hipMemcpyAsync(sm + kSmGp, eye.data(), m * m * 8, hipMemcpyHostToDevice, ctx->stream));
   HS_LAUNCH(ctx, project_finish_kernel, 1, 256, ctx->red, nb, pad16(m), m, sm + kSmGp, 0, sm + kSmY0, sm + kSmY,
             sm + kSmYPrev, sm + kSmMisc, 1);
-  HS_LAUNCH(ctx, recon_kernel, blocks_for(ctx->n), kBlock, Phi, (long long)ctx->n, m, ctx->ncell, psi,
-            sm + kSmY0, (const uint8_t*)nullptr, (const double*)nullptr, (double*)nullptr, ctx->rho);
+  HS_TRY(reconstruct(ctx, Phi, precision, m, psi, sm + kSmY0, nullptr, nullptr, nullptr, ctx->rho));
   double gmax;
   HS_TRY(max_abs(ctx, gamma, ctx->n, &gmax));
   const double fl = floor_rel * std::max(1.0, gmax);
@@ -597,13 +646,13 @@ hs_status hs_indicator_full(hs_ctx* ctx, const double* gamma, const double* Phi,
   return hs_sync(ctx);
 }
 
-hs_status rom_hybrid_step(hs_ctx* ctx, const double* q_prev, const double* Phi, const double* psi, int32_t m,
+hs_status rom_hybrid_step(hs_ctx* ctx, const double* q_prev, const void* Phi, const double* psi, int32_t m,
                           const hs_samples* s, const hs_hybrid_params* hp, double* q_out, double* eps_out,
                           double* y_out, hs_step_info* info) {
   return hybrid_impl(ctx, q_prev, Phi, psi, m, s, hp, q_out, eps_out, y_out, info, nullptr, -1);
 }
 
-hs_status rom_hybrid_step_taped(hs_ctx* ctx, const double* q_prev, const double* Phi, const double* psi,
+hs_status rom_hybrid_step_taped(hs_ctx* ctx, const double* q_prev, const void* Phi, const double* psi,
                                 int32_t m, const hs_samples* s, const hs_hybrid_params* hp, double* q_out,
                                 double* eps_out, hs_step_info* info, hs_htape* tape, int32_t mode) {
   if (mode != HS_TAPE_RECORD && mode != HS_TAPE_REPLAY) return HS_ERR_INVALID_ARG;

@@ -17,7 +17,8 @@ import time
 
 import torch
 
-from ._lib import (Context, HsError, FP64, HS_ERR_NOT_CONVERGED, HS_ERR_RANK, TAPE_RECORD, hybrid_params)
+from ._lib import (Context, HsError, FP64, HS_ERR_NOT_CONVERGED, HS_ERR_RANK, MIXED_FP32, TAPE_RECORD,
+                   hybrid_params)
 
 
 @dataclasses.dataclass
@@ -58,7 +59,9 @@ class Arom:
         self.ctx = ctx or Context(prob, m_max=cfg.m, w_max=cfg.w, device=device)
         c = self.ctx
         self.ring = [c.empty() for _ in range(cfg.w + 2)]
-        self.Phi = torch.zeros(cfg.m * c.n, dtype=torch.float64, device=c.device)
+        # the basis: FP64, or its FP32 master copy in the mixed mode
+        phi_dtype = torch.float32 if cfg.precision == MIXED_FP32 else torch.float64
+        self.Phi = torch.zeros(cfg.m * c.n, dtype=phi_dtype, device=c.device)
         self.psi = c.empty()
         self.sigma = torch.zeros(cfg.w, dtype=torch.float64, device=c.device)
         self.eps = c.empty(c.ncell)
@@ -127,8 +130,7 @@ class Arom:
                 self.have_samples = cnt["n_s"] > 0
             lo = k - cfg.w if k >= cfg.w else 0
             window = [self.slot(j) for j in range(lo, k + 1)]
-            self.m_eff = c.basis_update(window, cfg.w, cfg.m, self.Phi, self.psi, self.sigma,
-                                        cfg.tau_pod, cfg.precision)
+            self.m_eff = c.basis_update(window, cfg.w, cfg.m, self.Phi, self.psi, self.sigma, cfg.tau_pod)
             self.basis_version += 1
             rec["m_eff"] = self.m_eff
             if on_update is not None:

@@ -97,6 +97,39 @@ def test_rre_rule_is_smallest_count_reaching_delta():
         assert math.fsum(s[:n - 1]) / tot < delta + 1e-15
 
 
+def test_rre_rule_exact_on_the_fixed_point_grid():
+    """eq. rre with exact rational sums (brute force) on errors that the
+    64-bit encoding represents exactly, including exact hits of delta and
+    ties: the rule returns the smallest n with RRE(n) >= delta."""
+    from fractions import Fraction
+    rng = np.random.default_rng(8)
+    for trial in range(40):
+        n = int(rng.integers(1, 40))
+        ints = rng.integers(0, 9, n) * (1 << int(rng.integers(0, 5)))   # small dyadic integers, many ties
+        eps = ints.astype(float) * 2.0 ** -30
+        if not np.any(eps > 0):
+            continue
+        order = sorted(range(n), key=lambda i: (-eps[i], i))
+        tot = sum(Fraction(int(v)) for v in ints)
+        for delta in (0.25, 0.5, 0.75, 0.8, 0.9, 1.0, float(rng.random())):
+            want = None
+            acc = Fraction(0)
+            for g, i in enumerate(order, start=1):
+                acc += int(ints[i])
+                if acc / tot >= Fraction(delta):
+                    want = g
+                    break
+            want = min(want, int(np.count_nonzero(eps > 0)))
+            assert sampling.count_g(eps, sampling.RULE_RRE, delta=delta) == want, (trial, delta)
+
+
+def test_rre_fixed_point_encoding():
+    eps = np.array([0.0, 3.0, 1.5, 2.0 ** -70, 1.0])
+    q = sampling.fixed_point_errors(eps)
+    # largest 3 = 1.5 * 2^1 -> 3 * 2^62; others scale alike; 2^-70 * 2^62 < 1 -> 0
+    assert q == [0, 3 << 62, 3 << 61, 0, 1 << 62]
+
+
 # ---------------------------------------------------------------- indicator
 
 def test_indicator_zero_in_exact_span():

@@ -8,6 +8,8 @@
 // patterns of the errors (for non-negative doubles the unsigned integer order
 // is the numeric order), so the result is exact and independent of any
 // floating-point summation.  Integer histograms use LDS atomics (exact).
+// The RRE rule (eq. rre) first finds n_g with the same radix walk carrying
+// exact fixed-point sums of the errors instead of counts.
 #include "physics.hpp"
 
 #include <algorithm>
@@ -23,12 +25,251 @@ struct SelectState {
   long long k;                 // rank still to place within the current bucket
 };
 
+// #{eps > 0} and max eps (per-block partials).
 __global__ void count_positive_kernel(const double* __restrict__ eps, int n, double* __restrict__ part) {
   __shared__ int lds[kBlock / kWave];
+  __shared__ double ldm[kBlock / kWave];
   int c = 0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) c += eps[i] > 0.0;
+  double mx = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double e = eps[i];
+    c += e > 0.0;
+    mx = fmax(mx, e > 0.0 ? e : 0.0);
+  }
   c = block_sum_int(c, lds);
-  if (threadIdx.x == 0) stat_part(part, kStatCount, (double)c);
+  mx = block_max(mx, ldm);
+  if (threadIdx.x == 0) {
+    stat_part(part, kStatCount, (double)c);
+    stat_part(part, kStatQMax, mx);
+  }
+}
+
+// --------------------------------------------------------------- RRE rule
+// eq. rre with exact sums: every error is encoded in 64-bit fixed point
+// relative to the largest, q = floor(eps 2^(63 - emax)) (2^emax <= max eps <
+// 2^(emax+1)), and all sums of q are exact integers (32-bit halves summed in
+// 64-bit integers, integer atomics), so the decision RRE(n_g) >= delta does
+// not depend on any summation order.  Comparisons S >= delta T are made as
+// S 2^dsh >= dnum T with delta = dnum 2^-dsh, in 256-bit integers.
+struct U256 {
+  unsigned long long w[4];
+};
+
+__device__ inline U256 u256_small(unsigned long long lo, unsigned long long hi32sum) {
+  // lo + hi32sum * 2^32
+  U256 r{{0, 0, 0, 0}};
+  r.w[0] = lo;
+  const unsigned long long a = hi32sum << 32, b = hi32sum >> 32;
+  r.w[0] += a;
+  r.w[1] = b + (r.w[0] < a ? 1ull : 0ull);
+  return r;
+}
+
+__device__ inline U256 u256_add(const U256& a, const U256& b) {
+  U256 r;
+  unsigned long long c = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const unsigned long long s = a.w[i] + b.w[i];
+    const unsigned long long c1 = s < a.w[i];
+    r.w[i] = s + c;
+    const unsigned long long c2 = r.w[i] < s;
+    c = c1 | c2;
+  }
+  return r;
+}
+
+__device__ inline U256 u256_shl(const U256& a, int sh) {   // 0 <= sh < 256
+  U256 r{{0, 0, 0, 0}};
+  const int ws = sh / 64, bs = sh % 64;
+  for (int i = 3; i >= ws; --i) {
+    unsigned long long v = a.w[i - ws] << bs;
+    if (bs && i - ws - 1 >= 0) v |= a.w[i - ws - 1] >> (64 - bs);
+    r.w[i] = v;
+  }
+  return r;
+}
+
+__device__ inline U256 u256_mul64(const U256& a, unsigned long long m) {
+  U256 r{{0, 0, 0, 0}};
+  unsigned long long carry = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const unsigned long long lo = a.w[i] * m, hi = __umul64hi(a.w[i], m);
+    r.w[i] = lo + carry;
+    carry = hi + (r.w[i] < lo ? 1ull : 0ull);
+  }
+  return r;
+}
+
+__device__ inline bool u256_ge(const U256& a, const U256& b) {
+  for (int i = 3; i >= 0; --i)
+    if (a.w[i] != b.w[i]) return a.w[i] > b.w[i];
+  return true;
+}
+
+__device__ inline unsigned long long fixed_q(double e, int emax) {
+  if (!(e > 0.0)) return 0ull;
+  const unsigned long long b = dbits(e);
+  const int ex = (int)(b >> 52);
+  unsigned long long M = b & ((1ull << 52) - 1ull);
+  int x;
+  if (ex == 0) {
+    x = -1074;                 // subnormal: e = M 2^-1074
+  } else {
+    M |= 1ull << 52;           // e = M 2^(ex - 1075)
+    x = ex - 1075;
+  }
+  const int sh = x + 63 - emax;
+  if (sh >= 0) return M << sh;
+  if (sh <= -64) return 0ull;
+  return M >> (-sh);
+}
+
+struct RreState {
+  unsigned long long prefix;    // digits of the crossing key fixed so far
+  long long count_above;        // keys above the prefix bucket
+  U256 s_above;                 // sum of q above the prefix bucket
+  U256 target;                  // dnum * T
+  unsigned long long tot_lo, tot_hi;   // T = tot_lo + tot_hi 2^32
+  long long ng;                 // result
+  int dsh;
+  int emax;
+};
+
+__global__ void rre_total_kernel(const double* __restrict__ eps, int n, int emax, RreState* st) {
+  __shared__ unsigned long long slo[kBlock / kWave], shi[kBlock / kWave];
+  unsigned long long lo = 0, hi = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const unsigned long long q = fixed_q(eps[i], emax);
+    lo += q & 0xffffffffull;
+    hi += q >> 32;
+  }
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    lo += __shfl_xor(lo, o, kWave);
+    hi += __shfl_xor(hi, o, kWave);
+  }
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  if (lane == 0) {
+    slo[w] = lo;
+    shi[w] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long a = 0, b = 0;
+    for (int k = 0; k < (int)(blockDim.x / kWave); ++k) {
+      a += slo[k];
+      b += shi[k];
+    }
+    atomicAdd(&st->tot_lo, a);
+    atomicAdd(&st->tot_hi, b);
+  }
+}
+
+__global__ void rre_init_kernel(RreState* st, unsigned long long dnum, int dsh, int emax) {
+  const U256 T = u256_small(st->tot_lo, st->tot_hi);
+  st->target = u256_mul64(T, dnum);
+  st->dsh = dsh;
+  st->emax = emax;
+  st->prefix = 0ull;
+  st->count_above = 0;
+  st->s_above = U256{{0, 0, 0, 0}};
+  st->ng = 0;
+}
+
+// Per digit of the keys under the current prefix: count and the exact sum
+// of q (two 64-bit integer halves).
+__global__ void rre_hist_kernel(const double* __restrict__ eps, int n, const RreState* st, int shift,
+                                unsigned int* __restrict__ cnt, unsigned long long* __restrict__ slo,
+                                unsigned long long* __restrict__ shi) {
+  __shared__ unsigned int c[256];
+  __shared__ unsigned long long l[256], h[256];
+  for (int t = threadIdx.x; t < 256; t += blockDim.x) {
+    c[t] = 0;
+    l[t] = 0;
+    h[t] = 0;
+  }
+  __syncthreads();
+  const unsigned long long himask = shift >= 56 ? 0ull : (~0ull << (shift + 8));
+  const unsigned long long pre = st->prefix & himask;
+  const int emax = st->emax;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double e = eps[i];
+    if (!(e > 0.0)) continue;
+    const unsigned long long key = dbits(e);
+    if ((key & himask) != pre) continue;
+    const int d = (int)((key >> shift) & 255u);
+    const unsigned long long q = fixed_q(e, emax);
+    atomicAdd(&c[d], 1u);
+    atomicAdd(&l[d], q & 0xffffffffull);
+    atomicAdd(&h[d], q >> 32);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < 256; t += blockDim.x) {
+    if (c[t]) {
+      atomicAdd(&cnt[t], c[t]);
+      atomicAdd(&slo[t], l[t]);
+      atomicAdd(&shi[t], h[t]);
+    }
+  }
+}
+
+// One thread: walk the digits from the largest down, adding bucket sums to
+// the running sum above, and fix the digit whose bucket crosses the target;
+// then clear the histograms.
+__global__ void rre_pick_kernel(RreState* st, int shift, unsigned int* __restrict__ cnt,
+                                unsigned long long* __restrict__ slo, unsigned long long* __restrict__ shi) {
+  if (threadIdx.x == 0) {
+    U256 acc = st->s_above;
+    long long ca = st->count_above;
+    for (int d = 255; d >= 0; --d) {
+      if (cnt[d] == 0) continue;
+      const U256 nxt = u256_add(acc, u256_small(slo[d], shi[d]));
+      if (u256_ge(u256_shl(nxt, st->dsh), st->target)) {
+        st->prefix |= (unsigned long long)d << shift;
+        break;
+      }
+      acc = nxt;
+      ca += cnt[d];
+    }
+    st->s_above = acc;
+    st->count_above = ca;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < 256; t += blockDim.x) {
+    cnt[t] = 0;
+    slo[t] = 0;
+    shi[t] = 0;
+  }
+}
+
+// The crossing key K is fixed; its tied keys all carry q_K.  n_g = count
+// above K + the smallest t with (S_above + t q_K) 2^dsh >= dnum T.
+__global__ void rre_final_kernel(RreState* st, long long ties) {
+  const unsigned long long K = st->prefix;
+  const unsigned long long qk = fixed_q(__longlong_as_double((long long)K), st->emax);
+  long long lo = 1, hi = ties > 0 ? ties : 1;
+  while (lo < hi) {
+    const long long mid = lo + (hi - lo) / 2;
+    const U256 v = u256_add(st->s_above, u256_mul64(U256{{qk, 0, 0, 0}}, (unsigned long long)mid));
+    if (u256_ge(u256_shl(v, st->dsh), st->target)) hi = mid;
+    else lo = mid + 1;
+  }
+  st->ng = st->count_above + lo;
+}
+
+// Number of keys equal to K (the last pass's bucket, counted again).
+__global__ void count_key_kernel(const double* __restrict__ eps, int n, const RreState* st,
+                                 unsigned int* __restrict__ out) {
+  __shared__ int lds[kBlock / kWave];
+  int c = 0;
+  const unsigned long long K = st->prefix;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double e = eps[i];
+    c += (e > 0.0) && dbits(e) == K;
+  }
+  c = block_sum_int(c, lds);
+  if (threadIdx.x == 0 && c) atomicAdd(out, (unsigned int)c);
 }
 
 __global__ void radix_hist_kernel(const double* __restrict__ eps, int n, const SelectState* st, int shift,
@@ -297,6 +538,42 @@ static hs_status scan_blocks(hs_ctx* ctx, const uint8_t* flags, int n, int* bsum
   return HS_OK;
 }
 
+// n_g of the RRE rule (exact fixed-point sums), given #{eps > 0} and max eps.
+static hs_status rre_count(hs_ctx* ctx, const double* eps, int n, double delta, long long npos, double emx,
+                           long long* ng) {
+  if (npos == 0) { *ng = 0; return HS_OK; }
+  if (delta > 1.0) { *ng = npos; return HS_OK; }           // RRE <= 1 never reaches delta
+  if (!(delta > std::ldexp(1.0, -64))) { *ng = 1; return HS_OK; }   // the largest q alone exceeds delta T
+  int de;
+  const double dm = std::frexp(delta, &de);                 // delta = dm 2^de, 0.5 <= dm < 1
+  const unsigned long long dnum = (unsigned long long)std::ldexp(dm, 53);
+  const int dsh = 53 - de;                                  // delta = dnum 2^-dsh, dsh <= 117
+  const int emax = std::ilogb(emx);
+  // scratch in the integer buffer: histograms (8-byte aligned) and the state
+  unsigned char* base = reinterpret_cast<unsigned char*>(ctx->ibuf) + 8192;
+  unsigned int* cnt = reinterpret_cast<unsigned int*>(base);
+  unsigned long long* slo = reinterpret_cast<unsigned long long*>(base + 1024);
+  unsigned long long* shi = reinterpret_cast<unsigned long long*>(base + 3072);
+  RreState* rs = reinterpret_cast<RreState*>(base + 5120);
+  unsigned int* ties = reinterpret_cast<unsigned int*>(base + 5120 + 256);
+  const int bytes = 5120 + 256 + 64;
+  HS_LAUNCH(ctx, fill_u8_kernel, blocks_for(bytes), kBlock, base, bytes, (uint8_t)0);
+  HS_LAUNCH(ctx, rre_total_kernel, blocks_for(n, kBlock, 1024), kBlock, eps, n, emax, rs);
+  HS_LAUNCH(ctx, rre_init_kernel, 1, 1, rs, dnum, dsh, emax);
+  for (int shift = 56; shift >= 0; shift -= 8) {
+    HS_LAUNCH(ctx, rre_hist_kernel, blocks_for(n, kBlock, 2048), kBlock, eps, n, rs, shift, cnt, slo, shi);
+    HS_LAUNCH(ctx, rre_pick_kernel, 1, 256, rs, shift, cnt, slo, shi);
+  }
+  HS_LAUNCH(ctx, count_key_kernel, blocks_for(n, kBlock, 1024), kBlock, eps, n, rs, ties);
+  unsigned int nt;
+  HS_TRY(readback(ctx, ties, sizeof nt, &nt));
+  HS_LAUNCH(ctx, rre_final_kernel, 1, 1, rs, (long long)nt);
+  long long r;
+  HS_TRY(readback(ctx, &rs->ng, sizeof r, &r));
+  *ng = std::min(r, npos);
+  return HS_OK;
+}
+
 // Compact n flags into list (and pos); returns the count on the host.
 static hs_status compact(hs_ctx* ctx, hs_samples* s, const uint8_t* flags, int n, int* list, int* pos,
                          int* count) {
@@ -380,21 +657,27 @@ hs_status sample_select(hs_ctx* ctx, const double* eps, const hs_sample_params* 
   if (sp->rule == HS_RULE_FRACTION) {
     if (!(sp->fraction >= 0.0 && sp->fraction <= 1.0)) return HS_ERR_INVALID_ARG;
   } else if (sp->rule == HS_RULE_RRE) {
-    return ctx->fail(HS_ERR_INVALID_ARG, "the RRE rule is not available in this build");
+    if (!std::isfinite(sp->delta)) return HS_ERR_INVALID_ARG;
   } else {
     return HS_ERR_INVALID_ARG;
   }
   const int n = ctx->ncell;
   const int nb = blocks_for(n);
-  // n_g = min(ceil(f * ncell), #{eps > 0})
   const int nbp = blocks_for(n, kBlock, 1024);
   HS_LAUNCH(ctx, count_positive_kernel, nbp, kBlock, eps, n, ctx->part);
-  HS_TRY(finish_stats(ctx, nbp, 0u, 1u << kStatCount));
+  HS_TRY(finish_stats(ctx, nbp, 1u << kStatQMax, 1u << kStatCount));
   unsigned long long st[kStatSlots];
   HS_TRY(read_stats(ctx, st));
   const long long npos = (long long)bits_to_double(st[kStatCount]);
-  const long long want = (long long)std::ceil(sp->fraction * (double)n);
-  const long long ng = std::min(want, npos);
+  const double emx = bits_to_double(st[kStatQMax]);
+  long long ng;
+  if (sp->rule == HS_RULE_FRACTION) {
+    // n_g = min(ceil(f * ncell), #{eps > 0})
+    const long long want = (long long)std::ceil(sp->fraction * (double)n);
+    ng = std::min(want, npos);
+  } else {
+    HS_TRY(rre_count(ctx, eps, n, sp->delta, npos, emx, &ng));
+  }
   s->n_g = (int)ng;
 
   SelectState* state = reinterpret_cast<SelectState*>(s->scan + state_offset(n));

@@ -17,8 +17,8 @@ import time
 
 import torch
 
-from ._lib import (Context, HsError, FP64, HS_ERR_NOT_CONVERGED, HS_ERR_RANK, MIXED_FP32, TAPE_RECORD,
-                   hybrid_params)
+from ._lib import (Context, HsError, FP64, HS_ERR_NOT_CONVERGED, HS_ERR_RANK, MIXED_FP32, RULE_FRACTION,
+                   TAPE_RECORD, hybrid_params)
 
 
 @dataclasses.dataclass
@@ -28,6 +28,8 @@ class AromConfig:
     z: int = 20
     fraction: float = 0.1
     halo: int = 2
+    rule: int = RULE_FRACTION      # or RULE_RRE (eq. rre) with delta
+    delta: float = 0.9
     tau_pod: float = 1e-4
     eps_y: float = 1e-4
     jmax: int = 10
@@ -124,7 +126,8 @@ class Arom:
             if k >= cfg.w and self.m_eff > 0:
                 if not hybrid:
                     c.indicator_full(out, self.Phi, self.psi, self.m_eff, cfg.floor_rel, eps=self.eps)
-                c.sample_select(self.eps, cfg.fraction, cfg.halo, samples=self.samples)
+                c.sample_select(self.eps, cfg.fraction, cfg.halo, samples=self.samples, rule=cfg.rule,
+                                delta=cfg.delta)
                 cnt = self.samples.counts()
                 rec["n_g"] = cnt["n_g"]
                 self.have_samples = cnt["n_s"] > 0

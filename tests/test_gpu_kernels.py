@@ -228,3 +228,30 @@ def test_tiled_sweeps_equal_list_sweeps(name):
     assert torch.equal(a0, a1)
     assert torch.equal(b0, b1)
     assert torch.equal(c0, c1)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_sample_select_rre_bit_exact(name):
+    """The RRE rule (eq. rre, exact fixed-point sums): n_g, hat-S and
+    tilde-S equal the oracle's for several delta, on a real indicator and on
+    an indicator with many exact ties."""
+    need_gpu()
+    print_case("sample_select RRE", name)
+    import paper_2301_01718_amd as hs
+    wl, prob, q0 = case(name, 2)
+    w, m = 10, 6
+    snaps = window(prob, q0, w)
+    o = pod.pod(snaps, w, m)
+    g = fv.hdm_step(prob, snaps[-1])[0]
+    eps_real, _ = sampling.indicator_full(prob, g, o["Phi"], o["psi_new"])
+    rng = np.random.default_rng(4)
+    eps_ties = rng.integers(0, 6, prob.ncell).astype(float) * 0.125 * rng.choice([1.0, 2.0 ** -40], prob.ncell)
+    ctx = ctx_for(prob)
+    for eps in (eps_real, eps_ties):
+        for delta in (0.3, 0.8, 0.9, 0.99, 1.0, 1.5):
+            s = ctx.sample_select(dev(eps), 0.0, halo=wl.halo, rule=hs.RULE_RRE, delta=delta)
+            o_sel = sampling.select(prob, eps, sampling.RULE_RRE, delta=delta, halo=wl.halo)
+            hat, tilde, _ = s.export()
+            print(f"  delta {delta}: n_g {s.counts()['n_g']} oracle {o_sel['n_g']}", flush=True)
+            assert s.counts()["n_g"] == o_sel["n_g"]
+            assert np.array_equal(host(hat), o_sel["hat"]) and np.array_equal(host(tilde), o_sel["tilde"])

@@ -25,11 +25,20 @@ constexpr int kPerWave = (kMaxSnaps + 3) / 4;   // snapshots each of the four wa
 // the loads, so a kernel can start the next chunk's loads before it computes
 // on the current one; window_commit waits for them.
 struct WindowRegs {
+  const double* p[kPerWave];   // this wave's snapshot pointers (loaded once per block)
   double v[kPerWave];
 };
 
-__device__ inline void window_prefetch(const double* const* __restrict__ snaps, int nsnap, long long n,
-                                       long long row0, WindowRegs& R) {
+__device__ inline void window_init(const double* const* __restrict__ snaps, int nsnap, WindowRegs& R) {
+  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x / kChunk);
+#pragma unroll
+  for (int i = 0; i < kPerWave; ++i) {
+    const int j = q + 4 * i;
+    R.p[i] = j < nsnap ? snaps[j] : nullptr;
+  }
+}
+
+__device__ inline void window_prefetch(int nsnap, long long n, long long row0, WindowRegs& R) {
   const int lane = threadIdx.x % kChunk;
   const int q = __builtin_amdgcn_readfirstlane(threadIdx.x / kChunk);
   const long long row = row0 + lane;
@@ -37,7 +46,7 @@ __device__ inline void window_prefetch(const double* const* __restrict__ snaps, 
 #pragma unroll
   for (int i = 0; i < kPerWave; ++i) {
     const int j = q + 4 * i;
-    R.v[i] = (j < nsnap && ok) ? snaps[j][row] : 0.0;
+    R.v[i] = (j < nsnap && ok) ? R.p[i][row] : 0.0;
   }
 }
 
@@ -87,7 +96,8 @@ struct WindowLoader {
   long long n;
   double* psi_new;
   using Regs = WindowRegs;
-  __device__ void prefetch(long long row0, Regs& R) const { window_prefetch(snaps, nsnap, n, row0, R); }
+  __device__ void init(Regs& R) const { window_init(snaps, nsnap, R); }
+  __device__ void prefetch(long long row0, Regs& R) const { window_prefetch(nsnap, n, row0, R); }
   __device__ void commit(long long row0, const Regs& R, double* X, int ldx, int wp) const {
     window_commit(R, nsnap, w, n, row0, X, ldx, wp, psi_new);
   }
@@ -229,11 +239,15 @@ __global__ void __launch_bounds__(256) basis_eig_kernel(const double* __restrict
 // column of Phi.  The next chunk's loads are in flight during the products.
 // 256 threads; dynamic LDS: X (kChunk x (wp + 1)) then T (wp x (mp + 1)).
 // TP = double, or float for the FP32 master copy (rounded once on store).
+// meff is read from device memory (the eigen kernel's output), so the pass can
+// be enqueued before the host learns m_eff.
 template <typename TP>
 __global__ void __launch_bounds__(256) basis_form_kernel(const double* const* __restrict__ snaps, int nsnap,
                                                          int w, long long n, const double* __restrict__ T,
-                                                         int mp, int wp, int meff, TP* __restrict__ Phi) {
+                                                         int mp, int wp, const int* __restrict__ meff_d,
+                                                         TP* __restrict__ Phi) {
   extern __shared__ double sh[];
+  const int meff = *meff_d;
   const int ldx = wp + 1, ldt = mp + 1;
   double* X = sh;
   double* Ts = sh + kChunk * ldx;
@@ -241,14 +255,15 @@ __global__ void __launch_bounds__(256) basis_form_kernel(const double* const* __
   for (int e = threadIdx.x; e < wp * mp; e += blockDim.x) Ts[(e / mp) * ldt + e % mp] = T[e];
   const long long nchunks = (n + kChunk - 1) / kChunk;
   WindowRegs R;
+  window_init(snaps, nsnap, R);
   long long ch = blockIdx.x;
-  if (ch < nchunks) window_prefetch(snaps, nsnap, n, ch * kChunk, R);
+  if (ch < nchunks) window_prefetch(nsnap, n, ch * kChunk, R);
   for (; ch < nchunks; ch += gridDim.x) {
     const long long row0 = ch * kChunk;
     __syncthreads();
     window_commit(R, nsnap, w, n, row0, X, ldx, wp, nullptr);
     __syncthreads();
-    if (ch + gridDim.x < nchunks) window_prefetch(snaps, nsnap, n, (ch + gridDim.x) * kChunk, R);
+    if (ch + gridDim.x < nchunks) window_prefetch(nsnap, n, (ch + gridDim.x) * kChunk, R);
     const int rb = wave;   // 16 rows per wave
     for (int mb = 0; mb * 16 < mp; ++mb) {
       if (mb * 16 >= meff) break;
@@ -304,19 +319,18 @@ extern "C" hs_status basis_update(hs_ctx* ctx, const double* const* snaps, int32
   int* meff_d = reinterpret_cast<int*>(ctx->small + 3 * kMaxBasis * kMaxBasis);
   HS_LAUNCH(ctx, gram_reduce_kernel, w * w, kBlock, ctx->red, nb, wp, w, G);
   HS_LAUNCH(ctx, basis_eig_kernel, 1, 256, G, w, m, tau_pod, sigma_out, T, mp, meff_d);
-  int me = 0;
-  HS_TRY(readback(ctx, meff_d, sizeof(int), &me));
-  *m_eff = me;
-  if (me == 0) return HS_OK;
   HS_TRY(prof_begin(ctx, HS_PROF_BASIS_FORM));
   const size_t flds = ((size_t)kChunk * (wp + 1) + (size_t)wp * (mp + 1)) * sizeof(double);
   if (precision == HS_MIXED_FP32)
     hipLaunchKernelGGL(basis_form_kernel<float>, dim3(nb), dim3(256), flds, ctx->stream, tab, nsnap, w, n,
-                       (const double*)T, mp, wp, me, (float*)Phi_out);
+                       (const double*)T, mp, wp, (const int*)meff_d, (float*)Phi_out);
   else
     hipLaunchKernelGGL(basis_form_kernel<double>, dim3(nb), dim3(256), flds, ctx->stream, tab, nsnap, w, n,
-                       (const double*)T, mp, wp, me, (double*)Phi_out);
+                       (const double*)T, mp, wp, (const int*)meff_d, (double*)Phi_out);
   HIP_TRY(ctx, hipGetLastError());
+  int me = 0;
+  HS_TRY(readback(ctx, meff_d, sizeof(int), &me));
+  *m_eff = me;
   // reads every snapshot of the window once, writes m_eff columns of Phi
   const double phi_bytes = precision == HS_MIXED_FP32 ? 4.0 : 8.0;
   HS_TRY(prof_end(ctx, HS_PROF_BASIS_FORM, (double)n * (8.0 * nsnap + phi_bytes * me)));

@@ -35,7 +35,12 @@ enum StatSlot : int {
   kStatCount = 4,      // generic integer counter
   kStatDiff = 5,       // max |delta_new - delta_old| of a recorded sweep
   kStatDnorm = 6,      // max |delta_new| of a recorded sweep
-  kStatSlots = 8
+  kStatFitRank = 8,    // rank of the fit's pseudo-inverse
+  kStatFitCond = 9,    // its condition number
+  kStatDy = 10,        // ||y_j - y_{j-1}|| of the last subiteration
+  kStatSum0 = 11,      // l1 sum of the cell residual norms before a filter order
+  kStatSum = 12,       // the same after a filter pass
+  kStatSlots = 16
 };
 
 constexpr int kPartCap = 4096;   // max blocks of a kernel that reports statistics
@@ -294,11 +299,20 @@ hs_status read_stats(hs_ctx* ctx, unsigned long long* out /* kStatSlots */);
 hs_status finish_stats(hs_ctx* ctx, int nb, unsigned max_mask, unsigned sum_mask);
 inline int stat_blocks(long long n) { return blocks_for(n, kBlock, kPartCap); }
 hs_status max_abs(hs_ctx* ctx, const double* x, long long n, double* out);
-// Newton on the full mesh (hat == nullptr) or on a compact cell list.
+// Newton on the full mesh (s == nullptr) or on a sampled set.  primed: the
+// first iteration's residual/Jacobian was already launched by
+// newton_first_launch on q, and {max |R|, rho} were read back (else nullptr).
 hs_status newton_solve(hs_ctx* ctx, double* q, const double* q_prev, double tol,
-                       const hs_samples* s, hs_step_info* info);
+                       const hs_samples* s, hs_step_info* info, const double* primed = nullptr);
+// Residual, Jacobian relaxation data and the ResMax/Rho statistics at q
+// (enqueued only; read with read_stats).
+hs_status newton_first_launch(hs_ctx* ctx, const double* q, const double* q_prev, const hs_samples* s);
+// max |x| into the QMax statistics slot (enqueued only).
+hs_status max_abs_launch(hs_ctx* ctx, const double* x, long long n);
 hs_status cell_residual_norm(hs_ctx* ctx, const double* q, const double* q_prev, double* rcell,
                              double* sum_out);
+// The same, enqueued only: the sum goes to the statistics slot `slot`.
+hs_status cell_residual_launch(hs_ctx* ctx, const double* q, const double* q_prev, double* rcell, int slot);
 hs_status run_filter(hs_ctx* ctx, double* gamma, const double* q_prev, const hs_hybrid_params* hp,
                      hs_step_info* info, hs_htape* record = nullptr);
 // Solve the linear system whose relaxation data (coef, rhs layout [.. * ncell + p])

@@ -22,6 +22,7 @@ constexpr int kChunk = 64;   // rows staged per LDS chunk
 // Gram G = X^T X of a tall matrix whose rows are produced by a Loader into
 // LDS (kChunk rows x ldx, zero padded), accumulated over all chunks of this
 // block; the block's partial wp x wp matrix goes to part[blockIdx.x].
+//   Loader::init(regs) loads per-block constants (e.g. pointers) once;
 //   Loader::prefetch(chunk_row0, regs) issues the loads of a chunk into
 //   registers; Loader::commit(chunk_row0, regs, X /*LDS kChunk x ldx*/) writes
 //   the rows.  The next chunk's loads are in flight during the products.
@@ -40,6 +41,7 @@ __global__ void __launch_bounds__(256) gram_kernel(Loader ld, long long nrows, i
   for (int t = 0; t < 4; ++t) acc[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
   const long long nchunks = (nrows + kChunk - 1) / kChunk;
   typename Loader::Regs R;
+  ld.init(R);
   long long ch = blockIdx.x;
   if (ch < nchunks) ld.prefetch(ch * kChunk, R);
   for (; ch < nchunks; ch += gridDim.x) {

@@ -96,10 +96,14 @@ hs_status finish_stats(hs_ctx* ctx, int nb, unsigned max_mask, unsigned sum_mask
   return HS_OK;
 }
 
-hs_status max_abs(hs_ctx* ctx, const double* x, long long n, double* out) {
+hs_status max_abs_launch(hs_ctx* ctx, const double* x, long long n) {
   const int nb = blocks_for(n, kBlock, 1024);
   HS_LAUNCH(ctx, max_abs_kernel, nb, kBlock, x, n, ctx->part);
-  HS_TRY(finish_stats(ctx, nb, 1u << kStatQMax, 0u));
+  return finish_stats(ctx, nb, 1u << kStatQMax, 0u);
+}
+
+hs_status max_abs(hs_ctx* ctx, const double* x, long long n, double* out) {
+  HS_TRY(max_abs_launch(ctx, x, n));
   unsigned long long st[kStatSlots];
   HS_TRY(read_stats(ctx, st));
   *out = bits_to_double(st[kStatQMax]);
@@ -223,30 +227,44 @@ __global__ void resjac_kernel(Grid g, const double* __restrict__ q, const double
 hs_status linear_solve(hs_ctx* ctx, const hs_samples* s, double rho, double eta, double* q, int* sweeps);
 
 template <int NC>
-static hs_status newton_impl(hs_ctx* ctx, double* q, const double* q_prev, double tol,
-                             const hs_samples* s, hs_step_info* info) {
-  const Grid& g = ctx->g;
+static hs_status resjac_launch(hs_ctx* ctx, const double* q, const double* q_prev, const hs_samples* s) {
   const int* hat = s ? s->hat : nullptr;
   const int* nbr = s ? s->nbr : nullptr;
   const int count = s ? s->n_s : ctx->ncell;
-  const int cap = ctx->ncell;
+  const int nbs = stat_blocks(count);
+  HS_TRY(prof_begin(ctx, HS_PROF_RESJAC));
+  HS_LAUNCH(ctx, resjac_kernel<NC>, nbs, kBlock, ctx->g, q, q_prev, hat, nbr, count, ctx->ncell, ctx->coef,
+            ctx->rhs, ctx->part);
+  // reads: state of the cell (+ 4 neighbours, counted once), q_prev, the
+  // list entries; writes: 4 NC x NC relaxation blocks and the NC-vector b
+  HS_TRY(prof_end(ctx, HS_PROF_RESJAC,
+                  (double)count * (8.0 * NC * 2 + 8.0 * (4 * NC * NC + NC) + (hat ? 4.0 * 5 : 0.0))));
+  return finish_stats(ctx, nbs, (1u << kStatResMax) | (1u << kStatRho), 0u);
+}
+
+hs_status newton_first_launch(hs_ctx* ctx, const double* q, const double* q_prev, const hs_samples* s) {
+  if (ctx->nc == 1) return resjac_launch<1>(ctx, q, q_prev, s);
+  return resjac_launch<4>(ctx, q, q_prev, s);
+}
+
+template <int NC>
+static hs_status newton_impl(hs_ctx* ctx, double* q, const double* q_prev, double tol,
+                             const hs_samples* s, hs_step_info* info, const double* primed) {
   const int maxit = ctx->p.newton_maxit;
   const double lin_rtol = ctx->p.lin_rtol;
   int sweeps_total = 0;
   for (int it = 0;; ++it) {
-    const int nbs = stat_blocks(count);
-    HS_TRY(prof_begin(ctx, HS_PROF_RESJAC));
-    HS_LAUNCH(ctx, resjac_kernel<NC>, nbs, kBlock, g, q, q_prev, hat, nbr, count, cap, ctx->coef,
-              ctx->rhs, ctx->part);
-    // reads: state of the cell (+ 4 neighbours, counted once), q_prev, the
-    // list entries; writes: 4 NC x NC relaxation blocks and the NC-vector b
-    HS_TRY(prof_end(ctx, HS_PROF_RESJAC,
-                    (double)count * (8.0 * NC * 2 + 8.0 * (4 * NC * NC + NC) + (hat ? 4.0 * 5 : 0.0))));
-    HS_TRY(finish_stats(ctx, nbs, (1u << kStatResMax) | (1u << kStatRho), 0u));
-    unsigned long long st[kStatSlots];
-    HS_TRY(read_stats(ctx, st));
-    const double rmax = bits_to_double(st[kStatResMax]);
-    const double rho = bits_to_double(st[kStatRho]);
+    double rmax, rho;
+    if (it == 0 && primed) {
+      rmax = primed[0];
+      rho = primed[1];
+    } else {
+      HS_TRY(resjac_launch<NC>(ctx, q, q_prev, s));
+      unsigned long long st[kStatSlots];
+      HS_TRY(read_stats(ctx, st));
+      rmax = bits_to_double(st[kStatResMax]);
+      rho = bits_to_double(st[kStatRho]);
+    }
     if (!std::isfinite(rmax))
       return ctx->fail(HS_ERR_NONFINITE, "non-finite residual in Newton solve");
     if (info) {
@@ -357,10 +375,10 @@ hs_status relax_solve(hs_ctx* ctx, const hs_samples* s, const double* coef, cons
 }
 
 hs_status newton_solve(hs_ctx* ctx, double* q, const double* q_prev, double tol, const hs_samples* s,
-                       hs_step_info* info) {
+                       hs_step_info* info, const double* primed) {
   if (s && s->n_s == 0) return HS_OK;
-  if (ctx->nc == 1) return newton_impl<1>(ctx, q, q_prev, tol, s, info);
-  return newton_impl<4>(ctx, q, q_prev, tol, s, info);
+  if (ctx->nc == 1) return newton_impl<1>(ctx, q, q_prev, tol, s, info, primed);
+  return newton_impl<4>(ctx, q, q_prev, tol, s, info, primed);
 }
 
 }  // namespace hs

@@ -30,6 +30,7 @@ struct GatherLoader {
   struct Regs {
     double v[kMaxBasis / 4];
   };
+  __device__ void init(Regs&) const {}
   __device__ void prefetch(long long row0, Regs& R) const {
     const int r = threadIdx.x % kChunk;
     const long long row = row0 + r;
@@ -56,7 +57,8 @@ struct GatherLoader {
 
 // Truncated pseudo-inverse of the m x m Gram: G+ = sum_{kept} v v^T / lambda.
 __global__ void __launch_bounds__(256) pinv_kernel(const double* __restrict__ G, int m, double rcond,
-                                                  double* __restrict__ Gp, double* __restrict__ misc) {
+                                                  double* __restrict__ Gp, double* __restrict__ misc,
+                                                  unsigned long long* __restrict__ stats) {
   __shared__ double A[kMaxBasis * (kMaxBasis + 1)], V[kMaxBasis * (kMaxBasis + 1)];
   __shared__ double lam[kMaxBasis];
   __shared__ int order[kMaxBasis];
@@ -74,6 +76,8 @@ __global__ void __launch_bounds__(256) pinv_kernel(const double* __restrict__ G,
     rank = k;
     misc[1] = k;
     misc[2] = k > 0 ? sqrt(lmax / lam[k - 1]) : 0.0;
+    stats[kStatFitRank] = dbits((double)k);
+    stats[kStatFitCond] = dbits(misc[2]);
   }
   __syncthreads();
   for (int e = t; e < m * m; e += blockDim.x) {
@@ -136,7 +140,7 @@ __global__ void __launch_bounds__(256) project_finish_kernel(const double* __res
                                                              int m, const double* __restrict__ Gp, int mode,
                                                              double* __restrict__ y0, double* __restrict__ y,
                                                              double* __restrict__ yprev, double* __restrict__ misc,
-                                                             int first) {
+                                                             int first, unsigned long long* __restrict__ stats) {
   __shared__ double b[kMaxBasis], ynew[kMaxBasis];
   const int t = threadIdx.x;
   const int lane = t % kWave, wave = t / kWave, nw = blockDim.x / kWave;
@@ -161,6 +165,7 @@ __global__ void __launch_bounds__(256) project_finish_kernel(const double* __res
       d2 += d * d;
     }
     misc[0] = first ? INFINITY : sqrt(d2);
+    if (stats) stats[kStatDy] = dbits(misc[0]);
   }
   __syncthreads();
   if (mode == 1 && t < m) {
@@ -204,12 +209,21 @@ __global__ void recon_kernel(const TP* __restrict__ Phi, long long n, int m, int
   if (mask) gamma[r] = mask[r % ncell] ? u[r] : rr;
 }
 
-// eps_cell = sum_c (gamma - rho)^2, flushed to 0 below floor2.
+__global__ void eye_kernel(double* __restrict__ A, int m) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < m * m) A[e] = (e / m == e % m) ? 1.0 : 0.0;
+}
+
+// eps_cell = sum_c (gamma - rho)^2, flushed to 0 below fl^2 with
+// fl = floor_rel * max(1, max |gamma|) (max |gamma| from the QMax slot).
 __global__ void indicator_kernel(int ncell, int nc, const double* __restrict__ gamma,
-                                 const double* __restrict__ rho, double floor2, double* __restrict__ eps) {
+                                 const double* __restrict__ rho, double floor_rel,
+                                 const unsigned long long* __restrict__ stats, double* __restrict__ eps) {
 #pragma clang fp contract(off)
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncell) return;
+  const double fl = floor_rel * fmax(1.0, __longlong_as_double((long long)stats[kStatQMax]));
+  const double floor2 = fl * fl;
   double e = 0.0;
   for (int a = 0; a < nc; ++a) {
     const double d = gamma[(size_t)a * ncell + c] - rho[(size_t)a * ncell + c];
@@ -321,6 +335,17 @@ __global__ void mask_blend_kernel(long long n, int ncell, const double* __restri
   merged[r] = mask[r % ncell] ? gf[r] : cur[r];
 }
 
+hs_status cell_residual_launch(hs_ctx* ctx, const double* q, const double* q_prev, double* rcell, int slot) {
+  const int nb = blocks_for(ctx->ncell);
+  if (nb > kRedBlocks * 64) return ctx->fail(HS_ERR_SHAPE, "grid too large for the reduction buffer");
+  HS_TRY(prof_begin(ctx, HS_PROF_CELLRES));
+  if (ctx->nc == 1) HS_LAUNCH(ctx, cellres_kernel<1>, nb, kBlock, ctx->g, q, q_prev, rcell, ctx->red);
+  else HS_LAUNCH(ctx, cellres_kernel<4>, nb, kBlock, ctx->g, q, q_prev, rcell, ctx->red);
+  HS_TRY(prof_end(ctx, HS_PROF_CELLRES, (double)ctx->ncell * (16.0 * ctx->nc + 8.0)));
+  HS_LAUNCH(ctx, sum_finish_kernel, 1, kBlock, ctx->red, nb, reinterpret_cast<double*>(ctx->stats + slot));
+  return HS_OK;
+}
+
 hs_status cell_residual_norm(hs_ctx* ctx, const double* q, const double* q_prev, double* rcell,
                              double* sum_out) {
   const int nb = blocks_for(ctx->ncell);
@@ -347,6 +372,10 @@ static hs_status filter_apply(hs_ctx* ctx, const double* in, double* out, int no
   return HS_OK;
 }
 
+// One host synchronisation per pass: the gate's kept count and the l1 sum of
+// the merged state's cell residual norms are read together (when nothing was
+// kept the merged state equals the current one, so the sum is unchanged).
+// The norms carry over from one filter order to the next (same state).
 hs_status run_filter(hs_ctx* ctx, double* gamma, const double* q_prev, const hs_hybrid_params* hp,
                      hs_step_info* info, hs_htape* record) {
   if (blocks_for(ctx->ncell) > kPartCap) return ctx->fail(HS_ERR_SHAPE, "grid beyond the statistics capacity");
@@ -360,10 +389,11 @@ hs_status run_filter(hs_ctx* ctx, double* gamma, const double* q_prev, const hs_
   double* r = ctx->rcell;
   double* r2 = ctx->rcell2;
   const int nb = blocks_for(ctx->ncell);
+  bool have_sum = false;
+  double sum_r = 0.0;
+  if (hp->n_orders > 0 && hp->jfmax > 0) HS_TRY(cell_residual_launch(ctx, cur, q_prev, r, kStatSum0));
   for (int o = 0; o < hp->n_orders; ++o) {
     const int nord = hp->filter_orders[o];
-    double sum_r;
-    HS_TRY(cell_residual_norm(ctx, cur, q_prev, r, &sum_r));
     for (int it = 1; it <= hp->jfmax; ++it) {
       HS_TRY(filter_apply(ctx, cur, ctx->gf, nord));
       uint8_t* keep_out = record ? record->masks + (size_t)record->npass * ctx->ncell : nullptr;
@@ -372,9 +402,15 @@ hs_status run_filter(hs_ctx* ctx, double* gamma, const double* q_prev, const hs_
       else
         HS_LAUNCH(ctx, gate_kernel<4>, nb, kBlock, ctx->g, cur, ctx->gf, q_prev, r, spare, keep_out, ctx->part);
       HS_TRY(finish_stats(ctx, nb, 0u, 1u << kStatCount));
+      HS_TRY(cell_residual_launch(ctx, spare, q_prev, r2, kStatSum));
       unsigned long long st[kStatSlots];
       HS_TRY(read_stats(ctx, st));
+      if (!have_sum) {
+        sum_r = bits_to_double(st[kStatSum0]);
+        have_sum = true;
+      }
       const long long kept = (long long)bits_to_double(st[kStatCount]);
+      const double sum_new = bits_to_double(st[kStatSum]);
       if (info) {
         info->filter_passes += 1;
         info->filter_kept += (int)kept;
@@ -382,8 +418,6 @@ hs_status run_filter(hs_ctx* ctx, double* gamma, const double* q_prev, const hs_
       if (kept == 0) break;
       if (record) record->passes[record->npass++] = nord;
       std::swap(cur, spare);
-      double sum_new;
-      HS_TRY(cell_residual_norm(ctx, cur, q_prev, r2, &sum_new));
       std::swap(r, r2);
       const double dec = (sum_r - sum_new) / sum_r;
       sum_r = sum_new;
@@ -486,7 +520,8 @@ static hs_status fit_factor(hs_ctx* ctx, const void* Phi, int prec, int m, const
   if (prec == HS_MIXED_FP32) HS_TRY(launch_fit_gram(ctx, (const float*)Phi, m, hat, ns, nb, wp, rows));
   else HS_TRY(launch_fit_gram(ctx, (const double*)Phi, m, hat, ns, nb, wp, rows));
   HS_LAUNCH(ctx, gram_reduce_kernel, m * m, kBlock, ctx->red, nb, wp, m, ctx->small + kSmG);
-  HS_LAUNCH(ctx, pinv_kernel, 1, 256, ctx->small + kSmG, m, rcond, ctx->small + kSmGp, ctx->small + kSmMisc);
+  HS_LAUNCH(ctx, pinv_kernel, 1, 256, ctx->small + kSmG, m, rcond, ctx->small + kSmGp, ctx->small + kSmMisc,
+            ctx->stats);
   return HS_OK;
 }
 
@@ -497,10 +532,10 @@ static hs_status fit_solve(hs_ctx* ctx, const void* Phi, int prec, int m, const 
   int nb;
   HS_TRY(launch_project(ctx, Phi, prec, m, hat, ns, u, psi, nullptr, 0, &nb));
   HS_LAUNCH(ctx, project_finish_kernel, 1, 256, ctx->red, nb, pad16(m), m, sm + kSmGp, 0, sm + kSmY0, sm + kSmY,
-            sm + kSmYPrev, sm + kSmMisc, first);
+            sm + kSmYPrev, sm + kSmMisc, first, (unsigned long long*)nullptr);
   HS_TRY(launch_project(ctx, Phi, prec, m, hat, ns, u, psi, sm + kSmY0, 1, &nb));
   HS_LAUNCH(ctx, project_finish_kernel, 1, 256, ctx->red, nb, pad16(m), m, sm + kSmGp, 1, sm + kSmY0, sm + kSmY,
-            sm + kSmYPrev, sm + kSmMisc, first);
+            sm + kSmYPrev, sm + kSmMisc, first, ctx->stats);
   return HS_OK;
 }
 
@@ -543,23 +578,28 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const void* Phi,
     }
   }
 
-  double qmax;
-  HS_TRY(max_abs(ctx, q_prev, ctx->n, &qmax));
-  if (!std::isfinite(qmax)) return ctx->fail(HS_ERR_NONFINITE, "non-finite q_prev");
-  const double tol = ctx->p.newton_rtol * std::max(1.0, qmax);
   double* u = ctx->u;
   double* sm = ctx->small;
+  // max |q_prev| (Newton tolerance) and the fit factorisation, read together
+  HS_TRY(max_abs_launch(ctx, q_prev, ctx->n));
   HIP_TRY(ctx, hipMemcpyAsync(u, q_prev, ctx->n * 8, hipMemcpyDeviceToDevice, ctx->stream));
-
   HS_TRY(fit_factor(ctx, Phi, prec, m, s->hat, s->n_s, hp->rcond_fit));
-  double misc[3];
-  HS_TRY(readback(ctx, sm + kSmMisc, 3 * sizeof(double), misc));
-  inf->fit_rank = (int)misc[1];
-  inf->fit_cond = misc[2];
+  unsigned long long st[kStatSlots];
+  HS_TRY(read_stats(ctx, st));
+  const double qmax = bits_to_double(st[kStatQMax]);
+  if (!std::isfinite(qmax)) return ctx->fail(HS_ERR_NONFINITE, "non-finite q_prev");
+  const double tol = ctx->p.newton_rtol * std::max(1.0, qmax);
+  inf->fit_rank = (int)bits_to_double(st[kStatFitRank]);
+  inf->fit_cond = bits_to_double(st[kStatFitCond]);
   if (inf->fit_rank == 0) return ctx->fail(HS_ERR_RANK, "rank-zero fit");
 
+  // Subiterations.  The stop test on ||y_j - y_{j-1}|| is read together with
+  // the residual of the next Newton solve's first iteration, launched
+  // speculatively (it changes no state, so it is simply dropped on a stop).
+  double primed[2];
+  bool have_primed = false;
   for (int j = 1; j <= jmax; ++j) {
-    HS_TRY(newton_solve(ctx, u, q_prev, tol, s, inf));
+    HS_TRY(newton_solve(ctx, u, q_prev, tol, s, inf, have_primed ? primed : nullptr));
     if (replay)
       HIP_TRY(ctx, hipMemcpyAsync(tape->us + (size_t)(j - 1) * ctx->n, u, ctx->n * 8, hipMemcpyDeviceToDevice,
                                   ctx->stream));
@@ -567,10 +607,15 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const void* Phi,
     if (s->l > 0) HS_TRY(ring_update(ctx, Phi, prec, m, s, psi, sm + kSmY, u));
     inf->subiters = j;
     if (replay) continue;
-    double dy;
-    HS_TRY(readback(ctx, sm + kSmMisc, sizeof(double), &dy));
+    const bool more = j < jmax;
+    if (more) HS_TRY(newton_first_launch(ctx, u, q_prev, s));
+    HS_TRY(read_stats(ctx, st));
+    const double dy = bits_to_double(st[kStatDy]);
     inf->dy_last = dy;
-    if (j >= 2 && dy < hp->eps_y) break;
+    if (!more || (j >= 2 && dy < hp->eps_y)) break;
+    primed[0] = bits_to_double(st[kStatResMax]);
+    primed[1] = bits_to_double(st[kStatRho]);
+    have_primed = true;
   }
   if (replay) {
     HIP_TRY(ctx, hipMemcpyAsync(tape->gp, sm + kSmGp, (size_t)m * m * 8, hipMemcpyDeviceToDevice, ctx->stream));
@@ -585,11 +630,9 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const void* Phi,
   if (replay) HS_TRY(replay_filter(ctx, q_out, tape, inf));
   else HS_TRY(run_filter(ctx, q_out, q_prev, hp, inf, mode == HS_TAPE_RECORD ? tape : nullptr));
   if (eps_out) {
-    double gmax;
-    HS_TRY(max_abs(ctx, q_out, ctx->n, &gmax));
-    const double fl = hp->floor_rel * std::max(1.0, gmax);
-    HS_LAUNCH(ctx, indicator_kernel, blocks_for(ctx->ncell), kBlock, ctx->ncell, ctx->nc, q_out, ctx->rho, fl * fl,
-              eps_out);
+    HS_TRY(max_abs_launch(ctx, q_out, ctx->n));
+    HS_LAUNCH(ctx, indicator_kernel, blocks_for(ctx->ncell), kBlock, ctx->ncell, ctx->nc, q_out, ctx->rho,
+              hp->floor_rel, (const unsigned long long*)ctx->stats, eps_out);
   }
   if (y_out) HIP_TRY(ctx, hipMemcpyAsync(y_out, sm + kSmY, m * 8, hipMemcpyDeviceToDevice, ctx->stream));
   if (mode == HS_TAPE_RECORD) {
@@ -631,17 +674,13 @@ hs_status hs_indicator_full(hs_ctx* ctx, const double* gamma, const void* Phi, c
   int nb;
   HS_TRY(launch_project(ctx, Phi, precision, m, nullptr, 0, gamma, psi, nullptr, 0, &nb));
   // y = Phi^T (gamma - psi): G+ = I
-  std::vector<double> eye(m * m, 0.0);
-  for (int i = 0; i < m; ++i) eye[i * m + i] = 1.0;
-  HIP_TRY(ctx, hipMemcpyAsync(sm + kSmGp, eye.data(), m * m * 8, hipMemcpyHostToDevice, ctx->stream));
+  HS_LAUNCH(ctx, eye_kernel, blocks_for(m * m), kBlock, sm + kSmGp, m);
   HS_LAUNCH(ctx, project_finish_kernel, 1, 256, ctx->red, nb, pad16(m), m, sm + kSmGp, 0, sm + kSmY0, sm + kSmY,
-            sm + kSmYPrev, sm + kSmMisc, 1);
+            sm + kSmYPrev, sm + kSmMisc, 1, (unsigned long long*)nullptr);
   HS_TRY(reconstruct(ctx, Phi, precision, m, psi, sm + kSmY0, nullptr, nullptr, nullptr, ctx->rho));
-  double gmax;
-  HS_TRY(max_abs(ctx, gamma, ctx->n, &gmax));
-  const double fl = floor_rel * std::max(1.0, gmax);
-  HS_LAUNCH(ctx, indicator_kernel, blocks_for(ctx->ncell), kBlock, ctx->ncell, ctx->nc, gamma, ctx->rho, fl * fl,
-            eps);
+  HS_TRY(max_abs_launch(ctx, gamma, ctx->n));
+  HS_LAUNCH(ctx, indicator_kernel, blocks_for(ctx->ncell), kBlock, ctx->ncell, ctx->nc, gamma, ctx->rho, floor_rel,
+            (const unsigned long long*)ctx->stats, eps);
   if (y_out) HIP_TRY(ctx, hipMemcpyAsync(y_out, sm + kSmY0, m * 8, hipMemcpyDeviceToDevice, ctx->stream));
   return hs_sync(ctx);
 }

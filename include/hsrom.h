@@ -189,6 +189,17 @@ hs_status hs_indicator_full(hs_ctx* ctx, const double* gamma, const void* Phi /*
 hs_status basis_update(hs_ctx* ctx, const double* const* snaps /* host */, int32_t nsnap, int32_t w,
                        int32_t m, double tau_pod, int32_t precision,
                        void* Phi_out, double* psi_out, double* sigma_out, int32_t* m_eff /* host */);
+/* The same update split in two: basis_update_async enqueues it on a stream
+ * of the context's own (ordered after all work enqueued on the context's
+ * stream so far) and returns; basis_update_finish waits for it and returns
+ * m_eff.  In between, other calls on the context may run (the sampling step
+ * of Alg. 1 overlaps the update this way) provided they do not read or write
+ * the snapshots, Phi_out, psi_out or sigma_out; a second update, synchronous
+ * or not, is rejected until the first is finished. */
+hs_status basis_update_async(hs_ctx* ctx, const double* const* snaps /* host */, int32_t nsnap, int32_t w,
+                             int32_t m, double tau_pod, int32_t precision, void* Phi_out, double* psi_out,
+                             double* sigma_out);
+hs_status basis_update_finish(hs_ctx* ctx, int32_t* m_eff /* host */);
 
 /* --------------------------------------------------- rom_hybrid_step */
 typedef struct hs_hybrid_params {

@@ -98,6 +98,8 @@ _SIGS = {
     "hs_samples_export": [P, P, P, P, P],
     "hs_indicator_full": [P, P, P, P, I32, D, I32, P, P],
     "basis_update": [P, ctypes.POINTER(P), I32, I32, I32, D, I32, P, P, P, ctypes.POINTER(I32)],
+    "basis_update_async": [P, ctypes.POINTER(P), I32, I32, I32, D, I32, P, P, P],
+    "basis_update_finish": [P, ctypes.POINTER(I32)],
     "rom_hybrid_step": [P, P, P, P, I32, P, ctypes.POINTER(HybridParams), P, P, P,
                         ctypes.POINTER(StepInfo)],
     "hs_filter": [P, P, P, ctypes.POINTER(HybridParams), P, ctypes.POINTER(StepInfo)],
@@ -280,6 +282,18 @@ class Context:
         me = I32(0)
         self._check(lib().basis_update(self.h, arr, len(snaps), w, m, tau_pod, precision, _ptr(Phi_out),
                                        _ptr(self._in(psi_out)), _ptr(sigma_out), ctypes.byref(me)))
+        return me.value
+
+    def basis_update_async(self, snaps, w, m, Phi_out, psi_out, sigma_out, tau_pod=1e-4):
+        """Enqueue the update on the context's own stream; finish with basis_update_finish."""
+        precision = self._basis(Phi_out, m)
+        arr = (P * len(snaps))(*[P(self._in(s).data_ptr()) for s in snaps])
+        self._check(lib().basis_update_async(self.h, arr, len(snaps), w, m, tau_pod, precision, _ptr(Phi_out),
+                                             _ptr(self._in(psi_out)), _ptr(sigma_out)))
+
+    def basis_update_finish(self):
+        me = I32(0)
+        self._check(lib().basis_update_finish(self.h, ctypes.byref(me)))
         return me.value
 
     # -------------------------------------------------------------- hybrid

@@ -108,17 +108,17 @@ struct WindowLoader {
 //  1. pivoted Cholesky G = P L L^T P^T + S, stopped when the largest remaining
 //     diagonal entry is below eps * trace(G) (S is then below the rounding
 //     level of G itself), giving L (w x r), r = numerical rank;
-//  2. Jacobi eigendecomposition of the small r x r matrix L^T L = W Lam W^T;
-//  3. eigenvectors of G: V = P L W Lam^{-1/2}; singular values sigma = sqrt(Lam).
+//  2. one-sided Jacobi on the columns of L: L W = U Sigma (U orthonormal), so
+//     G = P U Sigma^2 U^T P^T without forming L^T L;
+//  3. eigenvectors of G: V = P U; singular values sigma.
 // One block of 256 threads.
 __global__ void __launch_bounds__(256) basis_eig_kernel(const double* __restrict__ G, int w, int m,
                                                        double tau, double* __restrict__ sigma,
                                                        double* __restrict__ T, int mp,
                                                        int* __restrict__ m_eff_out) {
   constexpr int lda = kMaxBasis + 1;
-  __shared__ double A[kMaxBasis * lda];   // G, then L^T L
-  __shared__ double L[kMaxBasis * lda];   // pivoted Cholesky factor (permuted rows)
-  __shared__ double W[kMaxBasis * lda];   // Jacobi eigenvectors of L^T L, then V = L W
+  __shared__ double A[kMaxBasis * lda];   // G, then the eigenvectors V
+  __shared__ double L[kMaxBasis * lda];   // pivoted Cholesky factor (permuted rows), then L W
   __shared__ double d[kMaxBasis], lam[kMaxBasis];
   __shared__ int perm[kMaxBasis], order[kMaxBasis];
   __shared__ int rank, piv, meff;
@@ -177,7 +177,14 @@ __global__ void __launch_bounds__(256) basis_eig_kernel(const double* __restrict
         continue;
       }
       double sacc = A[perm[i] * lda + perm[k]];
-      for (int j = 0; j < k; ++j) sacc -= L[i * lda + j] * L[k * lda + j];
+      double s4[4] = {0.0, 0.0, 0.0, 0.0};
+      int j = 0;
+      for (; j + 8 <= k; j += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s4[u % 4] += L[i * lda + j + u] * L[k * lda + j + u];
+      }
+      for (; j < k; ++j) s4[0] += L[i * lda + j] * L[k * lda + j];
+      sacc -= ((s4[0] + s4[1]) + s4[2]) + s4[3];
       const double lik = sacc / lkk;
       L[i * lda + k] = lik;
       d[perm[i]] -= lik * lik;
@@ -185,15 +192,94 @@ __global__ void __launch_bounds__(256) basis_eig_kernel(const double* __restrict
     __syncthreads();
   }
   const int r = rank;
-  // 2. B = L^T L (r x r) into A, Jacobi
-  for (int e = t; e < r * r; e += nt) {
-    const int a = e / r, b = e % r;
-    double sacc = 0.0;
-    for (int i = 0; i < w; ++i) sacc += L[i * lda + a] * L[i * lda + b];
-    A[a * lda + b] = sacc;
+  // 2. one-sided Jacobi on the columns of L (w x r): rotate column pairs until
+  //    they are orthogonal; then L W = U Sigma with the left singular vectors
+  //    U of L, i.e. the eigenvectors of G (in pivot row order), and sigma^2
+  //    the eigenvalues.  Pairs are scheduled round robin; each pair is one
+  //    group of 8 lanes (dot products reduced by shuffles), one barrier per
+  //    round.  A pair is rotated when |a_p.a_q| > sqrt(w) eps |a_p||a_q| (the
+  //    rounding level of a length-w dot product); sweeps stop once no pair
+  //    exceeds w eps, so rounding noise cannot keep them going.
+  {
+    const double tol_rot = sqrt((double)w) * 2.2e-16, tol_conv = (double)w * 2.2e-16;
+    const int np = (r + 1) & ~1;
+    const int P = np / 2;
+    const int grp = t / 8, gl = t % 8;
+    __shared__ int rotated;
+    for (int sweep = 0; sweep < 60 && r > 1; ++sweep) {
+      if (t == 0) rotated = 0;
+      __syncthreads();
+      for (int rd = 0; rd < np - 1; ++rd) {
+        if (grp < P) {
+          int p, q;
+          if (grp == 0) {
+            p = rd % (np - 1);
+            q = np - 1;
+          } else {
+            p = (rd + grp) % (np - 1);
+            q = (rd - grp + (np - 1)) % (np - 1);
+          }
+          if (p > q) { const int x = p; p = q; q = x; }
+          if (q < r) {
+            // rows gl, gl + 8, ... (w <= 64: at most 8 per lane, all loads in flight together)
+            double xs[8], ys[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+              const int k = gl + 8 * i;
+              xs[i] = k < w ? L[k * lda + p] : 0.0;
+              ys[i] = k < w ? L[k * lda + q] : 0.0;
+            }
+            double aa = 0.0, bb = 0.0, gg = 0.0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+              aa += xs[i] * xs[i];
+              bb += ys[i] * ys[i];
+              gg += xs[i] * ys[i];
+            }
+#pragma unroll
+            for (int o = 4; o > 0; o >>= 1) {
+              aa += __shfl_xor(aa, o, kWave);
+              bb += __shfl_xor(bb, o, kWave);
+              gg += __shfl_xor(gg, o, kWave);
+            }
+            const double lim = sqrt(aa * bb);
+            if (aa > 0.0 && bb > 0.0 && fabs(gg) > tol_rot * lim) {
+              const double zeta = (bb - aa) / (2.0 * gg);
+              const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+              const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+#pragma unroll
+              for (int i = 0; i < 8; ++i) {
+                const int k = gl + 8 * i;
+                if (k < w) {
+                  L[k * lda + p] = c * xs[i] - sn * ys[i];
+                  L[k * lda + q] = sn * xs[i] + c * ys[i];
+                }
+              }
+              if (gl == 0 && fabs(gg) > tol_conv * lim) rotated = 1;
+            }
+          }
+        }
+        __syncthreads();
+      }
+      if (!rotated) break;
+      __syncthreads();
+    }
+  }
+  // eigenvalues: squared column norms, in descending order (stable rank sort)
+  if (t < r) {
+    double s2 = 0.0;
+    for (int k = 0; k < w; ++k) s2 += L[k * lda + t] * L[k * lda + t];
+    d[t] = s2;
   }
   __syncthreads();
-  if (r > 0) jacobi_eig_wave(A, W, lda, r, lam, order, 40);
+  if (t < r) {
+    const double li = d[t];
+    int rk = 0;
+    for (int j = 0; j < r; ++j) rk += (d[j] > li) || (d[j] == li && j < t);
+    lam[rk] = li;
+    order[rk] = t;
+  }
+  __syncthreads();
   // 3. sigma, m_eff
   if (t == 0) {
     const double s0 = r > 0 ? sqrt(fmax(lam[0], 0.0)) : 0.0;
@@ -207,13 +293,10 @@ __global__ void __launch_bounds__(256) basis_eig_kernel(const double* __restrict
     *m_eff_out = me;
   }
   __syncthreads();
-  // V[:, i] = P L W[:, order[i]] / sqrt(lam_i) in original index order (stored in A)
+  // V[:, i] = P L[:, order[i]] / sqrt(lam_i) in original index order (stored in A)
   for (int e = t; e < w * meff; e += nt) {
     const int row = e / meff, i = e % meff;
-    const int col = order[i];
-    double sacc = 0.0;
-    for (int j = 0; j < r; ++j) sacc += L[row * lda + j] * W[j * lda + col];
-    A[perm[row] * lda + i] = sacc / sqrt(lam[i]);
+    A[perm[row] * lda + i] = L[row * lda + order[i]] / sqrt(lam[i]);
   }
   __syncthreads();
   // T[:, i] = sign_i V[:, i] / sigma_i, the sign making the largest |entry| positive
@@ -284,14 +367,12 @@ __global__ void __launch_bounds__(256) basis_form_kernel(const double* const* __
   }
 }
 
-}  // namespace hs
-
-using namespace hs;
-
-extern "C" hs_status basis_update(hs_ctx* ctx, const double* const* snaps, int32_t nsnap, int32_t w, int32_t m,
-                                  double tau_pod, int32_t precision, void* Phi_out, double* psi_out,
-                                  double* sigma_out, int32_t* m_eff) {
-  if (!ctx || !snaps || !Phi_out || !psi_out || !sigma_out || !m_eff) return HS_ERR_INVALID_ARG;
+// Enqueue the whole update on the context's current stream; m_eff stays on
+// the device (meff_d) until read back.
+static hs_status basis_enqueue(hs_ctx* ctx, const double* const* snaps, int32_t nsnap, int32_t w, int32_t m,
+                               double tau_pod, int32_t precision, void* Phi_out, double* psi_out,
+                               double* sigma_out) {
+  if (!ctx || !snaps || !Phi_out || !psi_out || !sigma_out) return HS_ERR_INVALID_ARG;
   if (w < 2 || w > ctx->p.w_max || (nsnap != w && nsnap != w + 1)) return HS_ERR_INVALID_ARG;
   if (m < 1 || m > ctx->p.m_max || m > w) return HS_ERR_INVALID_ARG;
   if (!(tau_pod >= 0.0 && tau_pod < 1.0)) return HS_ERR_INVALID_ARG;
@@ -328,11 +409,62 @@ extern "C" hs_status basis_update(hs_ctx* ctx, const double* const* snaps, int32
     hipLaunchKernelGGL(basis_form_kernel<double>, dim3(nb), dim3(256), flds, ctx->stream, tab, nsnap, w, n,
                        (const double*)T, mp, wp, (const int*)meff_d, (double*)Phi_out);
   HIP_TRY(ctx, hipGetLastError());
+  ctx->pending_form = {n, nsnap, precision == HS_MIXED_FP32 ? 4.0 : 8.0};
+  return HS_OK;
+}
+
+// m_eff of the enqueued update (waits for the stream it ran on); closes the
+// formation pass's measurement with its algorithmic bytes.
+static hs_status basis_complete(hs_ctx* ctx, int32_t* m_eff) {
+  int* meff_d = reinterpret_cast<int*>(ctx->small + 3 * kMaxBasis * kMaxBasis);
   int me = 0;
   HS_TRY(readback(ctx, meff_d, sizeof(int), &me));
   *m_eff = me;
   // reads every snapshot of the window once, writes m_eff columns of Phi
-  const double phi_bytes = precision == HS_MIXED_FP32 ? 4.0 : 8.0;
-  HS_TRY(prof_end(ctx, HS_PROF_BASIS_FORM, (double)n * (8.0 * nsnap + phi_bytes * me)));
+  const auto& f = ctx->pending_form;
+  return prof_end(ctx, HS_PROF_BASIS_FORM, (double)f.n * (8.0 * f.nsnap + f.phi_bytes * me));
+}
+
+}  // namespace hs
+
+using namespace hs;
+
+extern "C" hs_status basis_update(hs_ctx* ctx, const double* const* snaps, int32_t nsnap, int32_t w, int32_t m,
+                                  double tau_pod, int32_t precision, void* Phi_out, double* psi_out,
+                                  double* sigma_out, int32_t* m_eff) {
+  if (!ctx || !m_eff) return HS_ERR_INVALID_ARG;
+  if (ctx->aux_pending) return ctx->fail(HS_ERR_INVALID_ARG, "an asynchronous basis update is in flight");
+  HS_TRY(basis_enqueue(ctx, snaps, nsnap, w, m, tau_pod, precision, Phi_out, psi_out, sigma_out));
+  return basis_complete(ctx, m_eff);
+}
+
+extern "C" hs_status basis_update_async(hs_ctx* ctx, const double* const* snaps, int32_t nsnap, int32_t w,
+                                        int32_t m, double tau_pod, int32_t precision, void* Phi_out,
+                                        double* psi_out, double* sigma_out) {
+  if (!ctx) return HS_ERR_INVALID_ARG;
+  if (ctx->aux_pending) return ctx->fail(HS_ERR_INVALID_ARG, "an asynchronous basis update is in flight");
+  // the update starts after everything enqueued on the context's stream so far
+  HIP_TRY(ctx, hipEventRecord(ctx->aux_ready, ctx->stream));
+  HIP_TRY(ctx, hipStreamWaitEvent(ctx->aux, ctx->aux_ready, 0));
+  hipStream_t main = ctx->stream;
+  ctx->stream = ctx->aux;
+  const hs_status st = basis_enqueue(ctx, snaps, nsnap, w, m, tau_pod, precision, Phi_out, psi_out, sigma_out);
+  ctx->stream = main;
+  if (st != HS_OK) {
+    (void)hipStreamSynchronize(ctx->aux);
+    return st;
+  }
+  ctx->aux_pending = true;
   return HS_OK;
+}
+
+extern "C" hs_status basis_update_finish(hs_ctx* ctx, int32_t* m_eff) {
+  if (!ctx || !m_eff) return HS_ERR_INVALID_ARG;
+  if (!ctx->aux_pending) return ctx->fail(HS_ERR_INVALID_ARG, "no asynchronous basis update in flight");
+  ctx->aux_pending = false;
+  hipStream_t main = ctx->stream;
+  ctx->stream = ctx->aux;
+  const hs_status st = basis_complete(ctx, m_eff);
+  ctx->stream = main;
+  return st;
 }

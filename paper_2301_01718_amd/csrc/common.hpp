@@ -53,6 +53,10 @@ struct hs_ctx {
   hs::Grid g{};
   int nc = 1, ncell = 0, n = 0, nnb = 4;   // nnb: stencil neighbours per cell
   hipStream_t stream = nullptr;
+  hipStream_t aux = nullptr;        // library-owned stream of basis_update_async (default priority)
+  hipEvent_t aux_ready = nullptr;   // recorded on stream, waited on by aux
+  bool aux_pending = false;         // an asynchronous basis update is in flight
+  struct { long long n; int nsnap; double phi_bytes; } pending_form{0, 0, 8.0};
   int device = 0;
   std::string err;
 

@@ -26,8 +26,8 @@ constexpr int kChunk = 64;   // rows staged per LDS chunk
 //   Loader::prefetch(chunk_row0, regs) issues the loads of a chunk into
 //   registers; Loader::commit(chunk_row0, regs, X /*LDS kChunk x ldx*/) writes
 //   the rows.  The next chunk's loads are in flight during the products.
-// Block: 256 threads = 4 waves; wave v owns tiles t = v, v + 4, ... of the
-// (wp/16)^2 output tiles.
+// Block: 256 threads = 4 waves; G is symmetric, so only the nt (nt + 1) / 2
+// tiles with ti <= tj are formed; wave v owns tiles t = v, v + 4, ... of them.
 template <class Loader>
 __global__ void __launch_bounds__(256) gram_kernel(Loader ld, long long nrows, int wp,
                                                    double* __restrict__ part) {
@@ -35,7 +35,17 @@ __global__ void __launch_bounds__(256) gram_kernel(Loader ld, long long nrows, i
   const int ldx = wp + 1;
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   const int nt = wp / 16;
-  const int ntiles = nt * nt;
+  const int ntiles = nt * (nt + 1) / 2;
+  // upper-triangle tile t -> (ti, tj), ti <= tj, row by row
+  auto tile_of = [nt](int t, int& ti, int& tj) {
+    int i = 0;
+    while (t >= nt - i) {
+      t -= nt - i;
+      ++i;
+    }
+    ti = i;
+    tj = i + t;
+  };
   double4_t acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
@@ -53,7 +63,8 @@ __global__ void __launch_bounds__(256) gram_kernel(Loader ld, long long nrows, i
     for (int t = 0; t < 4; ++t) {
       const int tile = wave + 4 * t;
       if (tile >= ntiles) break;
-      const int ti = tile / nt, tj = tile % nt;
+      int ti, tj;
+      tile_of(tile, ti, tj);
 #pragma unroll 4
       for (int k0 = 0; k0 < kChunk; k0 += 4) {
         const int k = k0 + lane / 16;
@@ -68,7 +79,8 @@ __global__ void __launch_bounds__(256) gram_kernel(Loader ld, long long nrows, i
   for (int t = 0; t < 4; ++t) {
     const int tile = wave + 4 * t;
     if (tile >= ntiles) break;
-    const int ti = tile / nt, tj = tile % nt;
+    int ti, tj;
+    tile_of(tile, ti, tj);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int r = ti * 16 + lane / 16 + 4 * i, c = tj * 16 + lane % 16;
@@ -79,11 +91,19 @@ __global__ void __launch_bounds__(256) gram_kernel(Loader ld, long long nrows, i
 
 // Sum nb partial wp x wp matrices; one block per entry of the w x w result
 // (row-major, leading dimension w), a fixed strided order and a fixed tree.
+// Entries below the diagonal tiles are read from their mirror image (only
+// tiles with ti <= tj are formed), so G is exactly symmetric off the
+// diagonal tiles.
 static __global__ void gram_reduce_kernel(const double* __restrict__ part, int nb, int wp, int w,
                                           double* __restrict__ G) {
   __shared__ double lds[kBlock / kWave];
   const int e = blockIdx.x;
-  const int r = e / w, c = e % w;
+  int r = e / w, c = e % w;
+  if (r / 16 > c / 16) {
+    const int x = r;
+    r = c;
+    c = x;
+  }
   double s = 0.0;
   for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[(size_t)b * wp * wp + r * wp + c];
   s = block_sum(s, lds);
@@ -95,7 +115,8 @@ static __global__ void gram_reduce_kernel(const double* __restrict__ part, int n
 // by cyclic Jacobi with round-robin parallel ordering (any block size that is
 // a multiple of 64).  A pair is rotated only if its off-diagonal entry exceeds
 // both eps * sqrt(|a_pp a_qq|) and eps * trace|A|: below the latter an entry
-// is rounding noise that cannot move any eigenvalue by more than rounding.  On
+// is rounding noise that cannot move any eigenvalue by more than rounding.
+// Sweeps stop once no entry exceeds n eps sqrt(|a_pp a_qq|).  On
 // return lam is sorted in descending order with V's columns permuted alike.
 // A (n x n, row-major) is overwritten.  LDS: A, V (64 x 65 each).
 __device__ inline void jacobi_eig_wave(double* A, double* V, int lda, int n, double* lam, int* order,
@@ -135,12 +156,14 @@ __device__ inline void jacobi_eig_wave(double* A, double* V, int lda, int n, dou
         if (q < n) {
           const double apq = A[p * lda + q];
           const double app = A[p * lda + p], aqq = A[q * lda + q];
-          if (fabs(apq) > atol && fabs(apq) > 2.2e-16 * sqrt(fabs(app) * fabs(aqq))) {
+          const double lim = sqrt(fabs(app) * fabs(aqq));
+          if (fabs(apq) > atol && fabs(apq) > 2.2e-16 * lim) {
             const double tau = (aqq - app) / (2.0 * apq);
             const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + tt * tt);
             s = tt * c;
-            rotated = 1;
+            // rotations at the rounding level do not keep the sweeps going
+            if (fabs(apq) > (double)n * 2.2e-16 * lim) rotated = 1;
           }
         }
         pp[t] = p; qq[t] = q; cs[t] = c; sn[t] = s;

@@ -418,6 +418,11 @@ hs_status hs_destroy(hs_ctx* ctx) {
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
+  if (ctx->aux) {
+    (void)hipStreamSynchronize(ctx->aux);
+    (void)hipStreamDestroy(ctx->aux);
+  }
+  if (ctx->aux_ready) (void)hipEventDestroy(ctx->aux_ready);
   if (ctx->hpin) (void)hipHostFree(ctx->hpin);
   if (ctx->hstage) (void)hipHostFree(ctx->hstage);
   delete ctx;
@@ -485,6 +490,11 @@ hs_status hs_create(const hs_problem* pr, void* stream, hs_ctx** out) {
   A((void**)&ctx->ptab, 128 * sizeof(double*));
   A((void**)&ctx->adj, N * 8);
   A((void**)&ctx->part, (size_t)kStatSlots * kPartCap * 8);
+  if (st == HS_OK) {
+    if (hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->aux_ready, hipEventDisableTiming) != hipSuccess)
+      st = ctx->fail(HS_ERR_HIP, "stream/event creation");
+  }
   if (st == HS_OK) {
     hipError_t e = hipHostMalloc(&ctx->hpin, 65536, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc(&ctx->hstage, 65536, hipHostMallocDefault);

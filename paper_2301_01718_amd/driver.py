@@ -123,17 +123,24 @@ class Arom:
             on_step(k, rec, used, out)
         self.have_samples = False
         if wants_update(k, cfg.w, cfg.z, self.steps):
-            if k >= cfg.w and self.m_eff > 0:
-                if not hybrid:
-                    c.indicator_full(out, self.Phi, self.psi, self.m_eff, cfg.floor_rel, eps=self.eps)
-                c.sample_select(self.eps, cfg.fraction, cfg.halo, samples=self.samples, rule=cfg.rule,
-                                delta=cfg.delta)
-                cnt = self.samples.counts()
-                rec["n_g"] = cnt["n_g"]
-                self.have_samples = cnt["n_s"] > 0
+            sample = k >= cfg.w and self.m_eff > 0
+            if sample and not hybrid:
+                # the indicator of a full snapshot reads the current basis: before it is replaced
+                c.indicator_full(out, self.Phi, self.psi, self.m_eff, cfg.floor_rel, eps=self.eps)
             lo = k - cfg.w if k >= cfg.w else 0
             window = [self.slot(j) for j in range(lo, k + 1)]
-            self.m_eff = c.basis_update(window, cfg.w, cfg.m, self.Phi, self.psi, self.sigma, cfg.tau_pod)
+            # the basis update runs on the context's second stream while the
+            # sampled sets are selected on its main stream
+            c.basis_update_async(window, cfg.w, cfg.m, self.Phi, self.psi, self.sigma, cfg.tau_pod)
+            try:
+                if sample:
+                    c.sample_select(self.eps, cfg.fraction, cfg.halo, samples=self.samples, rule=cfg.rule,
+                                    delta=cfg.delta)
+                    cnt = self.samples.counts()
+                    rec["n_g"] = cnt["n_g"]
+                    self.have_samples = cnt["n_s"] > 0
+            finally:
+                self.m_eff = c.basis_update_finish()
             self.basis_version += 1
             rec["m_eff"] = self.m_eff
             if on_update is not None:

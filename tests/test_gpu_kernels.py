@@ -255,3 +255,35 @@ def test_sample_select_rre_bit_exact(name):
             print(f"  delta {delta}: n_g {s.counts()['n_g']} oracle {o_sel['n_g']}", flush=True)
             assert s.counts()["n_g"] == o_sel["n_g"]
             assert np.array_equal(host(hat), o_sel["hat"]) and np.array_equal(host(tilde), o_sel["tilde"])
+
+
+def test_basis_update_async_equals_sync():
+    """basis_update_async + basis_update_finish give the synchronous result
+    bit for bit, with a sample_select run on the main stream in between; a
+    second update is rejected while one is in flight."""
+    need_gpu()
+    print_case("basis_update_async")
+    import paper_2301_01718_amd as hs
+    wl, prob, q0 = case("burgers2d", 1)
+    w, m = 12, 8
+    snaps = [dev(s) for s in window(prob, q0, w)]
+    eps = dev(np.random.default_rng(0).random(prob.ncell))
+    ctx = ctx_for(prob)
+    outs = []
+    for mode in ("sync", "async"):
+        P = torch.zeros(m * prob.n, dtype=torch.float64, device="cuda")
+        psi = ctx.empty()
+        sig = torch.zeros(w, dtype=torch.float64, device="cuda")
+        if mode == "sync":
+            me = ctx.basis_update(snaps, w, m, P, psi, sig)
+            s = ctx.sample_select(eps, wl.frac, halo=wl.halo)
+        else:
+            ctx.basis_update_async(snaps, w, m, P, psi, sig)
+            with pytest.raises(hs.HsError):
+                ctx.basis_update(snaps, w, m, P, psi, sig)
+            s = ctx.sample_select(eps, wl.frac, halo=wl.halo)
+            me = ctx.basis_update_finish()
+        outs.append((me, P.clone(), psi.clone(), sig.clone(), [host(x) for x in s.export()[:2]]))
+    (m0, P0, p0, s0, h0), (m1, P1, p1, s1, h1) = outs
+    assert m0 == m1 and torch.equal(P0, P1) and torch.equal(p0, p1) and torch.equal(s0, s1)
+    assert all(np.array_equal(a, b) for a, b in zip(h0, h1))

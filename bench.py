@@ -54,10 +54,15 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def source_digest():
+# the sources each measured kernel is built from (a change voids its counters)
+KERNEL_SOURCES = {"basis_form": ["basis.hip", "dense.hpp", "common.hpp"],
+                  "basis_gram": ["basis.hip", "dense.hpp", "common.hpp"]}
+
+
+def source_digest(kernel):
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2301_01718_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in sorted(KERNEL_SOURCES.get(kernel, os.listdir(csrc))):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -71,7 +76,7 @@ def traffic_for(kernel, workload):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("source_digest") != source_digest():
+    if d.get("source_digest") != source_digest(kernel):
         return None
     return d.get("bytes_per_launch")
 

@@ -409,7 +409,11 @@ static hs_status basis_enqueue(hs_ctx* ctx, const double* const* snaps, int32_t 
     hipLaunchKernelGGL(basis_form_kernel<double>, dim3(nb), dim3(256), flds, ctx->stream, tab, nsnap, w, n,
                        (const double*)T, mp, wp, (const int*)meff_d, (double*)Phi_out);
   HIP_TRY(ctx, hipGetLastError());
-  ctx->pending_form = {n, nsnap, precision == HS_MIXED_FP32 ? 4.0 : 8.0};
+  // the measurement ends with the kernel; its bytes need m_eff (set on completion)
+  const size_t before = ctx->prof_bytes.size();
+  HS_TRY(prof_end(ctx, HS_PROF_BASIS_FORM, 0.0));
+  const int idx = ctx->prof_bytes.size() > before ? (int)before : -1;
+  ctx->pending_form = {n, nsnap, precision == HS_MIXED_FP32 ? 4.0 : 8.0, idx};
   return HS_OK;
 }
 
@@ -422,7 +426,9 @@ static hs_status basis_complete(hs_ctx* ctx, int32_t* m_eff) {
   *m_eff = me;
   // reads every snapshot of the window once, writes m_eff columns of Phi
   const auto& f = ctx->pending_form;
-  return prof_end(ctx, HS_PROF_BASIS_FORM, (double)f.n * (8.0 * f.nsnap + f.phi_bytes * me));
+  if (f.prof_idx >= 0 && f.prof_idx < (int)ctx->prof_bytes.size())
+    ctx->prof_bytes[f.prof_idx] = (double)f.n * (8.0 * f.nsnap + f.phi_bytes * me);
+  return HS_OK;
 }
 
 }  // namespace hs

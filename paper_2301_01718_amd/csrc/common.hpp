@@ -56,7 +56,7 @@ struct hs_ctx {
   hipStream_t aux = nullptr;        // library-owned stream of basis_update_async (default priority)
   hipEvent_t aux_ready = nullptr;   // recorded on stream, waited on by aux
   bool aux_pending = false;         // an asynchronous basis update is in flight
-  struct { long long n; int nsnap; double phi_bytes; } pending_form{0, 0, 8.0};
+  struct { long long n; int nsnap; double phi_bytes; int prof_idx; } pending_form{0, 0, 8.0, -1};
   int device = 0;
   std::string err;
 

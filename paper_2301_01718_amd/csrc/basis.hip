@@ -38,6 +38,12 @@ __device__ inline void window_init(const double* const* __restrict__ snaps, int 
   }
 }
 
+// Snapshot pointers come from a device table, so the compiler cannot tell
+// they address global memory and would use flat loads, which also count
+// against the LDS wait counter: the first LDS wait of the commit would then
+// drain every prefetched load.  The cast makes them global loads.
+typedef const __attribute__((address_space(1))) double* gptr_t;
+
 __device__ inline void window_prefetch(int nsnap, long long n, long long row0, WindowRegs& R) {
   const int lane = threadIdx.x % kChunk;
   const int q = __builtin_amdgcn_readfirstlane(threadIdx.x / kChunk);
@@ -46,7 +52,7 @@ __device__ inline void window_prefetch(int nsnap, long long n, long long row0, W
 #pragma unroll
   for (int i = 0; i < kPerWave; ++i) {
     const int j = q + 4 * i;
-    R.v[i] = (j < nsnap && ok) ? R.p[i][row] : 0.0;
+    R.v[i] = (j < nsnap && ok) ? ((gptr_t)R.p[i])[row] : 0.0;
   }
 }
 
@@ -337,16 +343,18 @@ __global__ void __launch_bounds__(256) basis_form_kernel(const double* const* __
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   for (int e = threadIdx.x; e < wp * mp; e += blockDim.x) Ts[(e / mp) * ldt + e % mp] = T[e];
   const long long nchunks = (n + kChunk - 1) / kChunk;
-  WindowRegs R;
-  window_init(snaps, nsnap, R);
-  long long ch = blockIdx.x;
-  if (ch < nchunks) window_prefetch(nsnap, n, ch * kChunk, R);
-  for (; ch < nchunks; ch += gridDim.x) {
+  // two register buffers: the loads of the chunk after next are in flight
+  // while the current chunk is committed and multiplied
+  WindowRegs Ra, Rb;
+  window_init(snaps, nsnap, Ra);
+  window_init(snaps, nsnap, Rb);
+  const long long G = gridDim.x;
+  auto process = [&](WindowRegs& R, long long ch) {
     const long long row0 = ch * kChunk;
     __syncthreads();
     window_commit(R, nsnap, w, n, row0, X, ldx, wp, nullptr);
     __syncthreads();
-    if (ch + gridDim.x < nchunks) window_prefetch(nsnap, n, (ch + gridDim.x) * kChunk, R);
+    if (ch + 2 * G < nchunks) window_prefetch(nsnap, n, (ch + 2 * G) * kChunk, R);
     const int rb = wave;   // 16 rows per wave
     for (int mb = 0; mb * 16 < mp; ++mb) {
       if (mb * 16 >= meff) break;
@@ -364,6 +372,13 @@ __global__ void __launch_bounds__(256) basis_form_kernel(const double* const* __
         if (col < meff && orow < n) Phi[(size_t)col * n + orow] = (TP)acc[i];
       }
     }
+  };
+  long long ch = blockIdx.x;
+  if (ch < nchunks) window_prefetch(nsnap, n, ch * kChunk, Ra);
+  if (ch + G < nchunks) window_prefetch(nsnap, n, (ch + G) * kChunk, Rb);
+  for (; ch < nchunks; ch += 2 * G) {
+    process(Ra, ch);
+    if (ch + G < nchunks) process(Rb, ch + G);
   }
 }
 

@@ -55,12 +55,20 @@ class Arom:
     and its output; ``on_update(k, rec, state)`` after every sampling/basis
     update.  The tensors are valid only during the call."""
 
+    RING_STAGGER = 328   # doubles between consecutive ring slots beyond N (2624 B)
+
     def __init__(self, prob, cfg: AromConfig, device="cuda", ctx: Context | None = None):
         self.prob = prob
         self.cfg = cfg
         self.ctx = ctx or Context(prob, m_max=cfg.m, w_max=cfg.w, device=device)
         c = self.ctx
-        self.ring = [c.empty() for _ in range(cfg.w + 2)]
+        # the snapshot ring: one allocation, slots staggered by a few KiB so
+        # that the same row of different snapshots does not map to the same
+        # HBM channel (the basis passes read one row of every slot at once)
+        nslot = cfg.w + 2
+        stride = c.n + self.RING_STAGGER
+        self._ring_buf = torch.empty(nslot * stride, dtype=torch.float64, device=c.device)
+        self.ring = [self._ring_buf[j * stride: j * stride + c.n] for j in range(nslot)]
         # the basis: FP64, or its FP32 master copy in the mixed mode
         phi_dtype = torch.float32 if cfg.precision == MIXED_FP32 else torch.float64
         self.Phi = torch.zeros(cfg.m * c.n, dtype=phi_dtype, device=c.device)

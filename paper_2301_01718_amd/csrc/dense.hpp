@@ -50,17 +50,15 @@ __global__ void __launch_bounds__(256) gram_kernel(Loader ld, long long nrows, i
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
   const long long nchunks = (nrows + kChunk - 1) / kChunk;
-  // two register buffers: the loads of the chunk after next are in flight
-  // while the current chunk is committed and multiplied
-  typename Loader::Regs Ra, Rb;
-  ld.init(Ra);
-  ld.init(Rb);
-  const long long G = gridDim.x;
-  auto process = [&](typename Loader::Regs& R, long long ch) {
+  typename Loader::Regs R;
+  ld.init(R);
+  long long ch = blockIdx.x;
+  if (ch < nchunks) ld.prefetch(ch * kChunk, R);
+  for (; ch < nchunks; ch += gridDim.x) {
     __syncthreads();
     ld.commit(ch * kChunk, R, X, ldx, wp);
     __syncthreads();
-    if (ch + 2 * G < nchunks) ld.prefetch((ch + 2 * G) * kChunk, R);
+    if (ch + gridDim.x < nchunks) ld.prefetch((ch + gridDim.x) * kChunk, R);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int tile = wave + 4 * t;
@@ -75,13 +73,6 @@ __global__ void __launch_bounds__(256) gram_kernel(Loader ld, long long nrows, i
         acc[t] = mfma_f64(a, b, acc[t]);
       }
     }
-  };
-  long long ch = blockIdx.x;
-  if (ch < nchunks) ld.prefetch(ch * kChunk, Ra);
-  if (ch + G < nchunks) ld.prefetch((ch + G) * kChunk, Rb);
-  for (; ch < nchunks; ch += 2 * G) {
-    process(Ra, ch);
-    if (ch + G < nchunks) process(Rb, ch + G);
   }
   double* out = part + (size_t)blockIdx.x * wp * wp;
 #pragma unroll

@@ -55,7 +55,7 @@ class Arom:
     and its output; ``on_update(k, rec, state)`` after every sampling/basis
     update.  The tensors are valid only during the call."""
 
-    RING_STAGGER = 328   # doubles between consecutive ring slots beyond N (2624 B)
+    RING_STAGGER = 320   # doubles between consecutive ring slots beyond N (2560 B: whole 128-B lines)
 
     def __init__(self, prob, cfg: AromConfig, device="cuda", ctx: Context | None = None):
         self.prob = prob

@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--workload", default="burgers2d_1024")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--roofline-kernel", default="basis_form",
-                    choices=["basis_gram", "basis_form", "recon", "resjac", "sweep", "cellres"])
+                    choices=["basis_gram", "basis_form", "recon", "resjac", "sweep", "cellres", "filter"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurement")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision measurement")

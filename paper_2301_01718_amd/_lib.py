@@ -116,7 +116,8 @@ _SIGS = {
     "hs_prof_read": [P, ctypes.POINTER(D), ctypes.POINTER(I32), ctypes.POINTER(D)],
 }
 
-PROF_CLASSES = {"basis_gram": 1, "basis_form": 2, "recon": 3, "resjac": 4, "sweep": 5, "cellres": 6}
+PROF_CLASSES = {"basis_gram": 1, "basis_form": 2, "recon": 3, "resjac": 4, "sweep": 5, "cellres": 6,
+                "filter": 7}
 
 
 def lib():

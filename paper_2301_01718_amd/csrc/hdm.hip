@@ -509,7 +509,7 @@ hs_status hs_create(const hs_problem* pr, void* stream, hs_ctx** out) {
 }
 
 hs_status hs_prof_enable(hs_ctx* ctx, int32_t cls) {
-  if (!ctx || cls < HS_PROF_NONE || cls > HS_PROF_CELLRES) return HS_ERR_INVALID_ARG;
+  if (!ctx || cls < HS_PROF_NONE || cls > HS_PROF_FILTER) return HS_ERR_INVALID_ARG;
   ctx->prof_class = cls;
   ctx->prof_used = 0;
   ctx->prof_bytes.clear();

@@ -233,12 +233,34 @@ __global__ void indicator_kernel(int ncell, int nc, const double* __restrict__ g
 }
 
 // ----------------------------------------------------------------- filter
-// out = S_n in along one axis, with S_n = I - (-delta^2/4)^n evaluated as n
-// nested second differences over the 2n+1 values of the stencil (periodic
-// wrap or repetition of the boundary value).
+// S_n = I - (-delta^2/4)^n at one point, from the 2n+1 values load(-n..n)
+// along one axis (centre load(0)): n nested second differences
+// -(a - 2b + c)/4, subtracted from the centre.  Every filter kernel goes
+// through this function, so the arithmetic is the same everywhere.
+template <int N, typename Load>
+__device__ inline double shapiro_point(Load load) {
+#pragma clang fp contract(off)
+  double v[2 * N + 1];
+#pragma unroll
+  for (int s = -N; s <= N; ++s) v[s + N] = load(s);
+  const double centre = v[N];
+#pragma unroll
+  for (int lev = 0; lev < N; ++lev)
+#pragma unroll
+    for (int s = 0; s + 2 < 2 * (N - lev) + 1; ++s) v[s] = -(v[s] - 2.0 * v[s + 1] + v[s + 2]) / 4.0;
+  return centre - v[0];
+}
+
+template <typename Load>
+__device__ inline double shapiro_any(int nord, Load load) {
+  if (nord == 1) return shapiro_point<1>(load);
+  if (nord == 2) return shapiro_point<2>(load);
+  return shapiro_point<3>(load);
+}
+
+// out = S_n in along one axis (periodic wrap or repetition of the boundary value).
 __global__ void shapiro_kernel(Grid g, const double* __restrict__ in, double* __restrict__ out, int axis,
                                int nord) {
-#pragma clang fp contract(off)
   const long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (k >= (long long)g.nc * g.ncell) return;
   const int a = (int)(k / g.ncell), cell = (int)(k % g.ncell);
@@ -246,21 +268,13 @@ __global__ void shapiro_kernel(Grid g, const double* __restrict__ in, double* __
   const int len = axis == 0 ? g.nx : g.ny;
   const int x0 = axis == 0 ? i : j;
   const bool per = g.bc == HS_BC_PERIODIC;
-  double v[7];
-  for (int s = -nord; s <= nord; ++s) {
+  const double* src = in + (size_t)a * g.ncell;
+  out[k] = shapiro_any(nord, [&](int s) {
     int x = x0 + s;
     if (per) x = ((x % len) + len) % len;
     else x = x < 0 ? 0 : (x >= len ? len - 1 : x);
-    const int cc = axis == 0 ? x + g.nx * j : i + g.nx * x;
-    v[s + nord] = in[(size_t)a * g.ncell + cc];
-  }
-  const double centre = v[nord];
-  int cnt = 2 * nord + 1;
-  for (int lev = 0; lev < nord; ++lev) {
-    for (int s = 0; s + 2 < cnt; ++s) v[s] = -(v[s] - 2.0 * v[s + 1] + v[s + 2]) / 4.0;
-    cnt -= 2;
-  }
-  out[k] = centre - v[0];
+    return src[axis == 0 ? x + g.nx * j : i + g.nx * x];
+  });
 }
 
 // rcell = cellwise 2-norm of R(q); block partial sums of rcell to part.
@@ -296,36 +310,6 @@ __global__ void sum_finish_kernel(const double* __restrict__ part, int nb, doubl
   if (threadIdx.x == 0) *out = s;
 }
 
-// Gate: keep the filtered value where the cell residual norm strictly decreases.
-template <int NC>
-__global__ void gate_kernel(Grid g, const double* __restrict__ cur, const double* __restrict__ gf,
-                            const double* __restrict__ qp, const double* __restrict__ r,
-                            double* __restrict__ merged, uint8_t* __restrict__ keep_out,
-                            double* __restrict__ part) {
-#pragma clang fp contract(off)
-  __shared__ int lds[kBlock / kWave];
-  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
-  int keep = 0;
-  if (cell < g.ncell) {
-    Stencil<NC> st;
-    load_stencil<NC>(g, gf, cell, st);
-    double p[NC], R[NC];
-#pragma unroll
-    for (int a = 0; a < NC; ++a) p[a] = qp[a * g.ncell + cell];
-    cell_residual<NC>(g, st, p, R);
-    double s = R[0] * R[0];
-#pragma unroll
-    for (int a = 1; a < NC; ++a) s = s + R[a] * R[a];
-    keep = sqrt(s) < r[cell];
-#pragma unroll
-    for (int a = 0; a < NC; ++a)
-      merged[a * g.ncell + cell] = keep ? gf[a * g.ncell + cell] : cur[a * g.ncell + cell];
-    if (keep_out) keep_out[cell] = (uint8_t)keep;
-  }
-  keep = block_sum_int(keep, lds);
-  if (threadIdx.x == 0) stat_part(part, kStatCount, (double)keep);
-}
-
 // Replay of a recorded pass: merged = mask ? gf : cur.
 __global__ void mask_blend_kernel(long long n, int ncell, const double* __restrict__ cur,
                                   const double* __restrict__ gf, const uint8_t* __restrict__ mask,
@@ -333,6 +317,222 @@ __global__ void mask_blend_kernel(long long n, int ncell, const double* __restri
   const long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (r >= n) return;
   merged[r] = mask[r % ncell] ? gf[r] : cur[r];
+}
+
+// ------------------------------------------------------ fused filter pass
+// One pass of the residual-gated filter (Sec. 2.3.4) per TX x TY tile, with
+// the state read once from HBM instead of once per stage:
+//   A  the current state on the tile + an H = n_max + 2 halo (staged in LDS);
+//   B  S_x A on the tile + a 2-cell ring of columns, all staged rows;
+//   G  S_y B on the tile + a 2-cell ring (1D: G = B);
+//   M  the gate on the tile + a 1-cell ring: G where the cell residual norm of
+//      G is below r (the norm of the current state), else A;
+//   r2 the cell residual norm of M on the tile.
+// The filter differences are nested in the order of shapiro_kernel and the
+// residual is cell_residual on the same values, so G, the decisions, M and
+// r2 are bit-identical to the unfused passes; ring cells are recomputed by
+// the neighbouring tiles with the same arithmetic.  Out-of-domain positions
+// of a non-periodic grid hold the clamped state (the filter's boundary
+// repetition); the residual stencils follow the ghost rules of neighbour().
+// Per block: the kept count and the sum of r2 go to the statistics partials.
+constexpr int kFiltHalo = 5;
+
+template <int NC, int TX, int TY>
+struct FiltCfg {
+  static constexpr bool ONE_D = TY == 1;
+  static constexpr int H = kFiltHalo;
+  static constexpr int AW = TX + 2 * H, AH = ONE_D ? 1 : TY + 2 * H;
+  static constexpr int BW = TX + 4, BH = AH;
+  static constexpr int GW = TX + 4, GH = ONE_D ? 1 : TY + 4;
+  static constexpr int MW = TX + 2, MH = ONE_D ? 1 : TY + 2;
+};
+
+__device__ inline int wrap_or_clamp(int u, int len, bool per) {
+  if (per) return ((u % len) + len) % len;
+  return u < 0 ? 0 : (u >= len ? len - 1 : u);
+}
+
+// Stencil of the cell at unwrapped position (ux, uy) (inside the domain, or
+// any position on a periodic grid) from an LDS array arr[a * stride + pos]
+// whose position (0, 0) is the unwrapped point (ox, oy), row width w.
+template <int NC>
+__device__ inline void lds_stencil(const Grid& g, const double* arr, int stride, int ox, int oy, int w, int ux,
+                                   int uy, Stencil<NC>& st) {
+  const bool per = g.bc == HS_BC_PERIODIC;
+  const int ndir = g.kind == HS_BURGERS_1D ? 2 : 4;
+  const int pc = (uy - oy) * w + (ux - ox);
+#pragma unroll
+  for (int a = 0; a < NC; ++a) st.c[a] = arr[a * stride + pc];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    if (d >= ndir) {
+#pragma unroll
+      for (int a = 0; a < NC; ++a) st.nb[d][a] = st.c[a];
+      continue;
+    }
+    const int vx = ux + (d == 0 ? -1 : (d == 1 ? 1 : 0));
+    const int vy = uy + (d == 2 ? -1 : (d == 3 ? 1 : 0));
+    const bool inside = per || (vx >= 0 && vx < g.nx && vy >= 0 && vy < g.ny);
+    if (inside) {
+      const int pn = (vy - oy) * w + (vx - ox);
+#pragma unroll
+      for (int a = 0; a < NC; ++a) st.nb[d][a] = arr[a * stride + pn];
+    } else {
+      const bool inflow = neighbour(g, ux, uy, d) < 0;
+#pragma unroll
+      for (int a = 0; a < NC; ++a) st.nb[d][a] = inflow ? g.inflow : st.c[a];
+    }
+  }
+}
+
+template <int NC, int TX, int TY>
+__global__ void __launch_bounds__(kBlock) filter_gate_kernel(
+    Grid g, int ntx, int ntiles, int nord, const double* __restrict__ cur, const double* __restrict__ qp,
+    const double* __restrict__ r, double* __restrict__ merged, double* __restrict__ r2,
+    uint8_t* __restrict__ keep_out, double* __restrict__ part) {
+#pragma clang fp contract(off)
+  using C = FiltCfg<NC, TX, TY>;
+  constexpr bool ONE_D = C::ONE_D;
+  constexpr int H = C::H, AW = C::AW, AH = C::AH, BW = C::BW, BH = C::BH, GW = C::GW, GH = C::GH;
+  constexpr int MW = C::MW, MH = C::MH;
+  constexpr int RA = AW * AH, RB = BW * BH, RG = GW * GH, RM = MW * MH;
+  static_assert(ONE_D || RM <= RB, "the gate's merged state reuses the S_x buffer");
+  __shared__ double sA[NC * RA];
+  __shared__ double sB[NC * RB];
+  __shared__ double sG[ONE_D ? 1 : NC * RG];
+  __shared__ double sM1[ONE_D ? NC * RM : 1];
+  __shared__ uint8_t sK[RM];
+  __shared__ double lds[kBlock / kWave];
+  double* G = ONE_D ? sB : sG;
+  const int gstride = ONE_D ? RB : RG;
+  double* M = ONE_D ? sM1 : sB;
+  const bool per = g.bc == HS_BC_PERIODIC;
+  double rsum = 0.0;
+  int kept = 0;
+
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int X0 = (tile % ntx) * TX, Y0 = ONE_D ? 0 : (tile / ntx) * TY;
+    // A: the current state, wrapped or clamped
+    for (int p = threadIdx.x; p < RA; p += kBlock) {
+      const int ax = p % AW, ay = p / AW;
+      const int x = wrap_or_clamp(X0 - H + ax, g.nx, per);
+      const int y = ONE_D ? 0 : wrap_or_clamp(Y0 - H + ay, g.ny, per);
+#pragma unroll
+      for (int a = 0; a < NC; ++a) sA[a * RA + p] = cur[(size_t)a * g.ncell + x + (size_t)g.nx * y];
+    }
+    __syncthreads();
+    // B = S_x A (columns X0-2 .. X0+TX+1)
+    for (int p = threadIdx.x; p < RB; p += kBlock) {
+      const int bx = p % BW, by = p / BW;
+      const int c0 = by * AW + bx + H - 2;
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        const double* src = sA + a * RA + c0;
+        sB[a * RB + p] = shapiro_any(nord, [&](int s) { return src[s]; });
+      }
+    }
+    __syncthreads();
+    if constexpr (!ONE_D) {
+      // G = S_y B (rows Y0-2 .. Y0+TY+1)
+      for (int p = threadIdx.x; p < RG; p += kBlock) {
+        const int gx = p % GW, gy = p / GW;
+        const int c0 = (gy + H - 2) * BW + gx;
+#pragma unroll
+        for (int a = 0; a < NC; ++a) {
+          const double* src = sB + a * RB + c0;
+          sG[a * RG + p] = shapiro_any(nord, [&](int s) { return src[s * BW]; });
+        }
+      }
+      __syncthreads();
+    }
+    // gate on the tile + 1 ring
+    for (int p = threadIdx.x; p < RM; p += kBlock) {
+      const int mx = p % MW, my = p / MW;
+      const int ux = X0 - 1 + mx, uy = ONE_D ? 0 : Y0 - 1 + my;
+      uint8_t keep = 0;
+      if (per || (ux >= 0 && ux < g.nx && uy >= 0 && uy < g.ny)) {
+        const int cell = wrap_or_clamp(ux, g.nx, per) + g.nx * (ONE_D ? 0 : wrap_or_clamp(uy, g.ny, per));
+        Stencil<NC> st;
+        lds_stencil<NC>(g, G, gstride, X0 - 2, ONE_D ? 0 : Y0 - 2, GW, ux, uy, st);
+        double pv[NC], R[NC];
+#pragma unroll
+        for (int a = 0; a < NC; ++a) pv[a] = qp[(size_t)a * g.ncell + cell];
+        cell_residual<NC>(g, st, pv, R);
+        double s = R[0] * R[0];
+#pragma unroll
+        for (int a = 1; a < NC; ++a) s = s + R[a] * R[a];
+        keep = sqrt(s) < r[cell];
+        const int pa = (uy - (ONE_D ? 0 : Y0 - H)) * AW + (ux - (X0 - H));
+#pragma unroll
+        for (int a = 0; a < NC; ++a) M[a * RM + p] = keep ? st.c[a] : sA[a * RA + pa];
+      }
+      sK[p] = keep;
+    }
+    __syncthreads();
+    // the merged state, its residual norm and the decisions on the tile
+    for (int p = threadIdx.x; p < TX * TY; p += kBlock) {
+      const int lx = p % TX, ly = p / TX;
+      const int ux = X0 + lx, uy = Y0 + ly;
+      if (ux >= g.nx || uy >= g.ny) continue;
+      const int cell = ux + g.nx * uy;
+      Stencil<NC> st;
+      lds_stencil<NC>(g, M, RM, X0 - 1, ONE_D ? 0 : Y0 - 1, MW, ux, uy, st);
+      double pv[NC], R[NC];
+#pragma unroll
+      for (int a = 0; a < NC; ++a) pv[a] = qp[(size_t)a * g.ncell + cell];
+      cell_residual<NC>(g, st, pv, R);
+      double s = R[0] * R[0];
+#pragma unroll
+      for (int a = 1; a < NC; ++a) s = s + R[a] * R[a];
+      const double rn = sqrt(s);
+      r2[cell] = rn;
+      rsum += rn;
+#pragma unroll
+      for (int a = 0; a < NC; ++a) merged[(size_t)a * g.ncell + cell] = st.c[a];
+      const uint8_t keep = sK[(ONE_D ? 0 : (ly + 1) * MW) + lx + 1];
+      if (keep_out) keep_out[cell] = keep;
+      kept += keep;
+    }
+    __syncthreads();
+  }
+  const double bs = block_sum(rsum, lds);
+  const int bk = block_sum_int(kept, reinterpret_cast<int*>(lds));
+  if (threadIdx.x == 0) {
+    stat_part(part, kStatSum, bs);
+    stat_part(part, kStatCount, (double)bk);
+  }
+}
+
+// Tile of the fused filter pass (must match the instantiations in filter_pass).
+static void filter_tile(const hs_ctx* ctx, int* tx, int* ty) {
+  if (ctx->g.kind == HS_BURGERS_1D) { *tx = 512; *ty = 1; }
+  else if (ctx->nc == 1) { *tx = 32; *ty = 32; }
+  else { *tx = 16; *ty = 16; }
+}
+
+// One gated pass: merged (the next state), r2, keep_out; kept count and sum
+// of r2 to the statistics slots kStatCount / kStatSum (enqueued only).
+static hs_status filter_pass(hs_ctx* ctx, const double* cur, const double* q_prev, const double* r, int nord,
+                             double* merged, double* r2, uint8_t* keep_out) {
+  int tx, ty;
+  filter_tile(ctx, &tx, &ty);
+  const int ntx = (ctx->g.nx + tx - 1) / tx;
+  const int ntiles = ntx * ((ctx->g.ny + ty - 1) / ty);
+  const int nb = std::min(ntiles, kPartCap);
+  HS_TRY(prof_begin(ctx, HS_PROF_FILTER));
+  if (ctx->g.kind == HS_BURGERS_1D)
+    HS_LAUNCH(ctx, (filter_gate_kernel<1, 512, 1>), nb, kBlock, ctx->g, ntx, ntiles, nord, cur, q_prev, r, merged,
+              r2, keep_out, ctx->part);
+  else if (ctx->nc == 1)
+    HS_LAUNCH(ctx, (filter_gate_kernel<1, 32, 32>), nb, kBlock, ctx->g, ntx, ntiles, nord, cur, q_prev, r, merged,
+              r2, keep_out, ctx->part);
+  else
+    HS_LAUNCH(ctx, (filter_gate_kernel<4, 16, 16>), nb, kBlock, ctx->g, ntx, ntiles, nord, cur, q_prev, r, merged,
+              r2, keep_out, ctx->part);
+  // reads: the state, q_prev and r once; writes: merged, r2 and the decisions
+  HS_TRY(prof_end(ctx, HS_PROF_FILTER,
+                  (double)ctx->ncell * (8.0 * ctx->nc * 3 + 8.0 * 2 + (keep_out ? 1.0 : 0.0))));
+  return finish_stats(ctx, nb, 0u, (1u << kStatCount) | (1u << kStatSum));
 }
 
 hs_status cell_residual_launch(hs_ctx* ctx, const double* q, const double* q_prev, double* rcell, int slot) {
@@ -378,7 +578,6 @@ static hs_status filter_apply(hs_ctx* ctx, const double* in, double* out, int no
 // The norms carry over from one filter order to the next (same state).
 hs_status run_filter(hs_ctx* ctx, double* gamma, const double* q_prev, const hs_hybrid_params* hp,
                      hs_step_info* info, hs_htape* record) {
-  if (blocks_for(ctx->ncell) > kPartCap) return ctx->fail(HS_ERR_SHAPE, "grid beyond the statistics capacity");
   if (record) {
     if ((long long)hp->n_orders * hp->jfmax > kMaxPasses)
       return ctx->fail(HS_ERR_INVALID_ARG, "taped step: more filter passes possible than the tape holds");
@@ -388,21 +587,14 @@ hs_status run_filter(hs_ctx* ctx, double* gamma, const double* q_prev, const hs_
   double* spare = ctx->gtmp;
   double* r = ctx->rcell;
   double* r2 = ctx->rcell2;
-  const int nb = blocks_for(ctx->ncell);
   bool have_sum = false;
   double sum_r = 0.0;
   if (hp->n_orders > 0 && hp->jfmax > 0) HS_TRY(cell_residual_launch(ctx, cur, q_prev, r, kStatSum0));
   for (int o = 0; o < hp->n_orders; ++o) {
     const int nord = hp->filter_orders[o];
     for (int it = 1; it <= hp->jfmax; ++it) {
-      HS_TRY(filter_apply(ctx, cur, ctx->gf, nord));
       uint8_t* keep_out = record ? record->masks + (size_t)record->npass * ctx->ncell : nullptr;
-      if (ctx->nc == 1)
-        HS_LAUNCH(ctx, gate_kernel<1>, nb, kBlock, ctx->g, cur, ctx->gf, q_prev, r, spare, keep_out, ctx->part);
-      else
-        HS_LAUNCH(ctx, gate_kernel<4>, nb, kBlock, ctx->g, cur, ctx->gf, q_prev, r, spare, keep_out, ctx->part);
-      HS_TRY(finish_stats(ctx, nb, 0u, 1u << kStatCount));
-      HS_TRY(cell_residual_launch(ctx, spare, q_prev, r2, kStatSum));
+      HS_TRY(filter_pass(ctx, cur, q_prev, r, nord, spare, r2, keep_out));
       unsigned long long st[kStatSlots];
       HS_TRY(read_stats(ctx, st));
       if (!have_sum) {

@@ -215,9 +215,12 @@ class Context:
     def sync(self):
         self._check(lib().hs_sync(self.h))
 
-    def set_tiled_sweeps(self, on: bool):
-        """Relax in LDS tiles (several sweeps per launch) or one sweep per launch."""
-        self._check(lib().hs_set_option(self.h, 1, 1 if on else 0))
+    def set_tiled_sweeps(self, mode):
+        """Relaxation sweeps: False = one sweep per launch over the cell list;
+        True = LDS tiles where they pay (default); "always" = tiles wherever
+        they fit.  The iterates are the same bit for bit."""
+        v = 2 if mode == "always" else (1 if mode else 0)
+        self._check(lib().hs_set_option(self.h, 1, v))
 
     # ---------------------------------------------------------- measurement
     def prof_enable(self, kernel_class):

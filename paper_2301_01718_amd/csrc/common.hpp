@@ -74,10 +74,12 @@ struct hs_ctx {
   double* rcell2 = nullptr;   // ncell cell residual norms
   double* adj = nullptr;      // N  adjoint work vector
   // tiled relaxation: tile_x x tile_y cells per tile, up to tile_s sweeps per
-  // launch; ntx x nty tiles cover the grid; tiled = false forces one sweep
-  // per launch over the compact cell list
+  // launch; ntx x nty tiles cover the grid; tiled: 0 = one sweep per launch
+  // over the compact cell list, 1 = tiles where dense enough, 2 = tiles always
   int tile_x = 0, tile_y = 0, tile_s = 0, ntx = 0, nty = 0;
-  bool tiled = true;
+  // the same for sampled sets (smaller tiles: a set fills a few of them)
+  int stile_x = 0, stile_y = 0, stile_s = 0, sntx = 0, snty = 0;
+  int tiled = 1;
   double* red = nullptr;      // reduction partials (kRedBlocks * 64 * 64 doubles)
   double* small = nullptr;    // small dense matrices and vectors (16 * 64 * 64 doubles)
   unsigned long long* stats = nullptr;   // kStatSlots
@@ -331,9 +333,14 @@ hs_status relax_solve(hs_ctx* ctx, const hs_samples* s, const double* coef, cons
 // record, the last sweep reports max |x_k - x_{k-1}| and max |x_k|.
 hs_status relax_sweeps(hs_ctx* ctx, const hs_samples* s, const double* coef, const double* rhs,
                        const double* xin, int nsweeps, double* q, bool record, const double** xlast);
-void tile_geometry(const hs_problem* pr, int nc, int* tx, int* ty, int* s);
-// Whether the relaxation on s (nullptr: full mesh) runs in tiles.
+// Tile shape and sweeps per launch of the full mesh (sampled = false) or of
+// sampled sets; set_tile_geometry fills both into the context.
+void tile_geometry(const hs_problem* pr, int nc, bool sampled, int* tx, int* ty, int* s);
+void set_tile_geometry(hs_ctx* ctx, const hs_problem* pr);
+// Whether the relaxation on s (nullptr: full mesh) runs in tiles, and the
+// sweeps per tiled launch.
 bool use_tiles(const hs_ctx* ctx, const hs_samples* s);
+int tile_sweeps(const hs_ctx* ctx, const hs_samples* s);
 // Bracket one launch of kernel class cls with events (no-op unless enabled).
 hs_status prof_begin(hs_ctx* ctx, int cls);
 hs_status prof_end(hs_ctx* ctx, int cls, double bytes);

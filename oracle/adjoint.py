@@ -37,8 +37,9 @@ from .hybrid import HybridParams, hybrid_step, shapiro
 # Forward with tape, and replay with frozen decisions
 # --------------------------------------------------------------------------
 
-def forward_with_tape(prob: Problem, q0, steps, p: AromParams):
-    """Alg. 1 as in oracle.arom.run, recording every step's frozen data."""
+def forward_with_tape(prob: Problem, q0, steps, p: AromParams, keep_norms=False):
+    """Alg. 1 as in oracle.arom.run, recording every step's frozen data (with
+    keep_norms also the residual norms each filter gate compared)."""
     gammas = [q0.copy()]
     basis = None
     samples = None
@@ -49,12 +50,14 @@ def forward_with_tape(prob: Problem, q0, steps, p: AromParams):
                   and basis is not None and basis[0].shape[1] > 0)
         eps = None
         if hybrid:
-            out = hybrid_step(prob, prev, basis[0], basis[1], samples["hat"], samples["tilde"], p.hybrid)
+            norms = [] if keep_norms else None
+            out = hybrid_step(prob, prev, basis[0], basis[1], samples["hat"], samples["tilde"], p.hybrid,
+                              norms=norms)
             g = out["gamma"]
             eps = out["eps"]
             tape.append({"type": "hybrid", "hat": samples["hat"], "tilde": samples["tilde"],
                          "Phi": basis[0], "psi": basis[1], "J": out["J"], "us": out["us"],
-                         "masks": out["masks"], "out": g})
+                         "masks": out["masks"], "out": g, "norms": norms})
         else:
             g, _ = fv.hdm_step(prob, prev)
             tape.append({"type": "full", "out": g})

@@ -82,9 +82,11 @@ def shapiro(prob: Problem, q, n):
     return g.reshape(-1)
 
 
-def spatial_filter(prob: Problem, gamma, q_prev, params: HybridParams, log=None, masks=None):
+def spatial_filter(prob: Problem, gamma, q_prev, params: HybridParams, log=None, masks=None, norms=None):
     """Residual-gated filter sequence.  Returns the filtered state.  If
-    ``masks`` is a list, every applied pass appends (n, kept-cell mask)."""
+    ``masks`` is a list, every applied pass appends (n, kept-cell mask); if
+    ``norms`` is a list, every applied pass appends (n, r, rf), the cell
+    residual norms its gate compared (a record only)."""
     c = prob.ncomp
     gamma = gamma.copy()
     for n in params.filter_orders:
@@ -102,6 +104,8 @@ def spatial_filter(prob: Problem, gamma, q_prev, params: HybridParams, log=None,
             gamma = np.where(km, gf, gamma)
             if masks is not None:
                 masks.append((n, keep.copy()))
+            if norms is not None:
+                norms.append((n, r.copy(), rf.copy()))
             r_new = fv.cell_residual_norm(prob, gamma, q_prev)
             s_old = np.sum(r)
             s_new = np.sum(r_new)
@@ -121,7 +125,7 @@ def fit(Phi_rows, d, rcond):
     return y
 
 
-def hybrid_step(prob: Problem, q_prev, Phi, psi, hat, tilde, params: HybridParams = None):
+def hybrid_step(prob: Problem, q_prev, Phi, psi, hat, tilde, params: HybridParams = None, norms=None):
     """One hybrid snapshot gamma_k from gamma_{k-1} = q_prev.
 
     Returns dict(gamma, y, J, eps, rho, newton, us, masks) where rho = psi + Phi y
@@ -151,7 +155,7 @@ def hybrid_step(prob: Problem, q_prev, Phi, psi, hat, tilde, params: HybridParam
     gamma = rho.copy()
     gamma[hd] = u[hd]
     flog, masks = [], []
-    gamma = spatial_filter(prob, gamma, q_prev, params, flog, masks)
+    gamma = spatial_filter(prob, gamma, q_prev, params, flog, masks, norms)
     eps = indicator(prob, gamma, rho, params.floor_rel)
     return {"gamma": gamma, "y": y, "J": J, "eps": eps, "rho": rho,
             "newton": newton, "filter_log": flog, "us": us, "masks": masks}

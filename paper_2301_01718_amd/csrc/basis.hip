@@ -17,97 +17,176 @@
 
 namespace hs {
 
-constexpr int kMaxSnaps = kMaxBasis + 1;
-constexpr int kPerWave = (kMaxSnaps + 3) / 4;   // snapshots each of the four waves loads
-
-// Rows row0 .. row0+63 of the window in registers: lane = row, wave q holds
-// snapshots q, q+4, ... (wave-uniform pointers).  window_prefetch only issues
-// the loads, so a kernel can start the next chunk's loads before it computes
-// on the current one; window_commit waits for them.
-struct WindowRegs {
-  const double* p[kPerWave];   // this wave's snapshot pointers (loaded once per block)
-  double v[kPerWave];
-};
-
-__device__ inline void window_init(const double* const* __restrict__ snaps, int nsnap, WindowRegs& R) {
-  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x / kChunk);
-#pragma unroll
-  for (int i = 0; i < kPerWave; ++i) {
-    const int j = q + 4 * i;
-    R.p[i] = j < nsnap ? snaps[j] : nullptr;
-  }
-}
+// Wave-private window chunks.  A wave owns 16 consecutive rows: lane l holds
+// row l % 16 of the snapshots l / 16, l / 16 + 4, ... (at most 17 per lane),
+// so each load instruction reads a 128-byte run of four snapshots.  The
+// window means of a row are lane-group sums combined by two fixed shuffles;
+// the centred rows go to a wave-private LDS region (16 rows), from which the
+// MFMA operands are read.  There is no workgroup barrier in the loop, and the
+// small register footprint lets about six waves per SIMD hide the latency.
+constexpr int kWaveRows = 16;                 // rows per wave chunk
 
 // Snapshot pointers come from a device table, so the compiler cannot tell
 // they address global memory and would use flat loads, which also count
-// against the LDS wait counter: the first LDS wait of the commit would then
-// drain every prefetched load.  The cast makes them global loads.
+// against the LDS wait counter.  The cast makes them global loads.
 typedef const __attribute__((address_space(1))) double* gptr_t;
 
-__device__ inline void window_prefetch(int nsnap, long long n, long long row0, WindowRegs& R) {
-  const int lane = threadIdx.x % kChunk;
-  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x / kChunk);
-  const long long row = row0 + lane;
-  const bool ok = row < n;
+template <int PER>
+struct LaneSnaps {
+  gptr_t p[PER];   // this lane's snapshots l / 16 + 4 i (clamped to the last one)
+  double v[PER];
+};
+
+template <int PER>
+__device__ inline void lane_snaps_init(const double* const* __restrict__ snaps, int nsnap, LaneSnaps<PER>& L) {
+  const int g = (threadIdx.x % kWave) / 16;
 #pragma unroll
-  for (int i = 0; i < kPerWave; ++i) {
-    const int j = q + 4 * i;
-    R.v[i] = (j < nsnap && ok) ? ((gptr_t)R.p[i])[row] : 0.0;
+  for (int i = 0; i < PER; ++i) {
+    const int j = g + 4 * i;
+    L.p[i] = (gptr_t)snaps[j < nsnap ? j : nsnap - 1];
   }
 }
 
-// Centred rows into X (64 x ldx, LDS): X[r][j] = snap[off + j][row0 + r] -
-// centre[r] for j < w, 0 for w <= j < wp.  The centring state (mean of the
-// first w snapshots) and psi_new (mean of the last w) are summed per wave over
-// its snapshots and the four partial sums combined in a fixed order.  Needs
-// 256 threads; the caller synchronises before reading X.
-__device__ inline void window_commit(const WindowRegs& R, int nsnap, int w, long long n, long long row0, double* X,
-                                     int ldx, int wp, double* psi_new) {
-  __shared__ double part_c[4][kChunk], part_n[4][kChunk], centre[kChunk];
-  const int lane = threadIdx.x % kChunk;
-  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x / kChunk);
-  const long long row = row0 + lane;
+// Loads this lane's values of its row (branch-free: all loads in flight
+// together; rows past n read row n - 1, snapshots past nsnap the last one,
+// both zeroed afterwards).
+template <int PER>
+__device__ inline void lane_snaps_load(LaneSnaps<PER>& L, int nsnap, long long n, long long row) {
+  const int g = (threadIdx.x % kWave) / 16;
   const bool ok = row < n;
+  const long long rr = ok ? row : n - 1;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) L.v[i] = L.p[i][rr];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) L.v[i] = (ok && g + 4 * i < nsnap) ? L.v[i] : 0.0;
+}
+
+// Sum over the four lane groups of a row, in the fixed order
+// ((g0 + g1) + (g2 + g3)), identical in all four groups.
+__device__ inline double group_sum(double x) {
+  const double t = x + __shfl_xor(x, 16, kWave);
+  return t + __shfl_xor(t, 32, kWave);
+}
+
+// The row's centring state (mean of the first w snapshots); psi_new (mean of
+// the last w) is written by the lanes of group 0.
+template <int PER>
+__device__ inline double lane_snaps_centre(const LaneSnaps<PER>& L, int nsnap, int w, long long row, long long n,
+                                           double* __restrict__ psi_new) {
+  const int g = (threadIdx.x % kWave) / 16;
   const int off = nsnap - w;
   double c = 0.0, nw = 0.0;
 #pragma unroll
-  for (int i = 0; i < kPerWave; ++i) {
-    const int j = q + 4 * i;
-    if (j < w) c += R.v[i];
-    if (j >= off && j < nsnap) nw += R.v[i];
+  for (int i = 0; i < PER; ++i) {
+    const int j = g + 4 * i;
+    c += j < w ? L.v[i] : 0.0;
+    nw += (j >= off && j < nsnap) ? L.v[i] : 0.0;
   }
-  part_c[q][lane] = c;
-  part_n[q][lane] = nw;
-  __syncthreads();
-  if (threadIdx.x < kChunk) {
-    const double cc = ((part_c[0][lane] + part_c[1][lane]) + part_c[2][lane]) + part_c[3][lane];
-    const double nn = ((part_n[0][lane] + part_n[1][lane]) + part_n[2][lane]) + part_n[3][lane];
-    centre[lane] = cc / (double)w;
-    if (psi_new && ok) psi_new[row] = nn / (double)w;
-  }
-  __syncthreads();
-  const double ce = centre[lane];
-#pragma unroll
-  for (int i = 0; i < kPerWave; ++i) {
-    const int j = q + 4 * i;
-    if (j >= off && j < nsnap) X[lane * ldx + (j - off)] = ok ? R.v[i] - ce : 0.0;
-  }
-  for (int j = w + q; j < wp; j += 4) X[lane * ldx + j] = 0.0;
+  c = group_sum(c);
+  nw = group_sum(nw);
+  if (psi_new && g == 0 && row < n) psi_new[row] = nw / (double)w;
+  return c / (double)w;
 }
 
-// Row loader of the centred window; also writes psi_new for its rows.
-struct WindowLoader {
-  const double* const* snaps;   // device table of nsnap pointers
-  int nsnap, w;
-  long long n;
-  double* psi_new;
-  using Regs = WindowRegs;
-  __device__ void init(Regs& R) const { window_init(snaps, nsnap, R); }
-  __device__ void prefetch(long long row0, Regs& R) const { window_prefetch(nsnap, n, row0, R); }
-  __device__ void commit(long long row0, const Regs& R, double* X, int ldx, int wp) const {
-    window_commit(R, nsnap, w, n, row0, X, ldx, wp, psi_new);
+// X[r][j - off] = v_j - c into the wave's region (kWaveRows x ldx).  Values
+// with no column (j < off, j >= nsnap) go to the spare column wp, which no
+// product reads; columns w .. wp - 1 are zeroed once per kernel.
+template <int PER>
+__device__ inline void lane_snaps_store(const LaneSnaps<PER>& L, double c, int nsnap, int w, int wp, double* xs,
+                                        int ldx) {
+  const int lane = threadIdx.x % kWave, g = lane / 16, r = lane % 16;
+  const int off = nsnap - w;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int j = g + 4 * i;
+    const int col = (j >= off && j < nsnap) ? j - off : wp;
+    xs[r * ldx + col] = L.v[i] - c;
   }
-};
+}
+
+// Orders this wave's LDS accesses around its region (the region is private
+// to the wave, whose LDS instructions execute in order; this stops the
+// compiler from moving them across).
+__device__ inline void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Window Gram G = X^T X (upper tiles ti <= tj of 16 x 16) and psi_new.  Each
+// wave accumulates its chunks' tiles in registers; the four waves' tiles are
+// summed in a fixed order into the block partial part[blockIdx.x] (wp x wp).
+// Block: 4 waves; dynamic LDS: 4 regions of kWaveRows x (wp + 1) (the cross-
+// wave sum reuses them at the end).
+template <int NS>
+__global__ void __launch_bounds__(256) window_gram_kernel(const double* const* __restrict__ snaps, int nsnap,
+                                                          int w, long long n, int wp, double* __restrict__ psi_new,
+                                                          double* __restrict__ part) {
+  extern __shared__ double sh[];
+  constexpr int NT = (NS - 1) / 16;              // tile rows of the padded Gram
+  constexpr int NTILES = NT * (NT + 1) / 2;
+  constexpr int PER = (NS + 3) / 4;
+  static_assert(NTILES * 256 <= 4 * kWaveRows * NS, "the cross-wave sum reuses the regions");
+  const int ldx = wp + 1;
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  double* xs = sh + wv * kWaveRows * ldx;
+  for (int e = lane; e < kWaveRows * ldx; e += kWave) xs[e] = 0.0;
+  double4_t acc[NTILES];
+#pragma unroll
+  for (int t = 0; t < NTILES; ++t) acc[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  LaneSnaps<PER> L;
+  lane_snaps_init<PER>(snaps, nsnap, L);
+  const long long nchunks = (n + kWaveRows - 1) / kWaveRows;
+  const long long nwaves = gridDim.x * 4LL;
+  for (long long ch = blockIdx.x * 4LL + wv; ch < nchunks; ch += nwaves) {
+    const long long row = ch * kWaveRows + lane % 16;
+    lane_snaps_load<PER>(L, nsnap, n, row);
+    const double c = lane_snaps_centre<PER>(L, nsnap, w, row, n, psi_new);
+    wave_lds_fence();
+    lane_snaps_store<PER>(L, c, nsnap, w, wp, xs, ldx);
+    wave_lds_fence();
+    // per k-step the NT column blocks x_t = X[k][16 t + l % 16] serve as
+    // both operands: A = X^T (A[r][k] = X[k][16 ti + r]), B[k][c] = X[k][16 tj + c]
+#pragma unroll
+    for (int k0 = 0; k0 < kWaveRows; k0 += 4) {
+      const int k = k0 + lane / 16;
+      double x[NT];
+#pragma unroll
+      for (int tb = 0; tb < NT; ++tb) x[tb] = xs[k * ldx + tb * 16 + lane % 16];
+      int t = 0;
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+        for (int tj = ti; tj < NT; ++tj, ++t) acc[t] = mfma_f64(x[ti], x[tj], acc[t]);
+    }
+  }
+  // rows past n were zeroed and centred with their (zero) mean: they add nothing
+  __syncthreads();
+  double* red = sh;
+  for (int q = 0; q < 4; ++q) {
+    if (wv == q) {
+#pragma unroll
+      for (int t = 0; t < NTILES; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int e = t * 256 + i * kWave + lane;
+          red[e] = q == 0 ? acc[t][i] : red[e] + acc[t][i];
+        }
+    }
+    __syncthreads();
+  }
+  double* out = part + (size_t)blockIdx.x * wp * wp;
+  for (int e = threadIdx.x; e < NTILES * 256; e += blockDim.x) {
+    const int t = e / 256, i = (e % 256) / kWave, l = e % kWave;
+    int ti = 0, tt = t;
+    while (tt >= NT - ti) {
+      tt -= NT - ti;
+      ++ti;
+    }
+    const int tj = ti + tt;
+    const int r = ti * 16 + l / 16 + 4 * i, cc = tj * 16 + l % 16;
+    out[r * wp + cc] = red[e];
+  }
+}
 
 // Eigen-decomposition of the window Gram G (w x w, PSD) and the formation
 // matrix T = V_m diag(1/sigma) (w x mp, zero padded), sigma (w), m_eff.
@@ -323,62 +402,55 @@ __global__ void __launch_bounds__(256) basis_eig_kernel(const double* __restrict
   }
 }
 
-// Phi = X T for rows of the window (centred on the fly), on MFMA.
-// C^T = T^T X^T so that each 16-lane group writes 16 consecutive rows of one
-// column of Phi.  The next chunk's loads are in flight during the products.
-// 256 threads; dynamic LDS: X (kChunk x (wp + 1)) then T (wp x (mp + 1)).
+// Phi = X T for rows of the window (centred on the fly), on MFMA, in
+// wave-private chunks as the Gram pass.  C^T = T^T X^T so that each 16-lane
+// group writes 16 consecutive rows of one column of Phi.  Block: 4 waves;
+// dynamic LDS: T (wp x (mp + 1)), then 4 regions of kWaveRows x (wp + 1).
 // TP = double, or float for the FP32 master copy (rounded once on store).
 // meff is read from device memory (the eigen kernel's output), so the pass can
 // be enqueued before the host learns m_eff.
-template <typename TP>
+template <int NS, typename TP>
 __global__ void __launch_bounds__(256) basis_form_kernel(const double* const* __restrict__ snaps, int nsnap,
                                                          int w, long long n, const double* __restrict__ T,
                                                          int mp, int wp, const int* __restrict__ meff_d,
                                                          TP* __restrict__ Phi) {
   extern __shared__ double sh[];
+  constexpr int PER = (NS + 3) / 4;
   const int meff = *meff_d;
   const int ldx = wp + 1, ldt = mp + 1;
-  double* X = sh;
-  double* Ts = sh + kChunk * ldx;
-  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  double* Ts = sh;
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  double* xs = sh + wp * ldt + wv * kWaveRows * ldx;
   for (int e = threadIdx.x; e < wp * mp; e += blockDim.x) Ts[(e / mp) * ldt + e % mp] = T[e];
-  const long long nchunks = (n + kChunk - 1) / kChunk;
-  // two register buffers: the loads of the chunk after next are in flight
-  // while the current chunk is committed and multiplied
-  WindowRegs Ra, Rb;
-  window_init(snaps, nsnap, Ra);
-  window_init(snaps, nsnap, Rb);
-  const long long G = gridDim.x;
-  auto process = [&](WindowRegs& R, long long ch) {
-    const long long row0 = ch * kChunk;
-    __syncthreads();
-    window_commit(R, nsnap, w, n, row0, X, ldx, wp, nullptr);
-    __syncthreads();
-    if (ch + 2 * G < nchunks) window_prefetch(nsnap, n, (ch + 2 * G) * kChunk, R);
-    const int rb = wave;   // 16 rows per wave
-    for (int mb = 0; mb * 16 < mp; ++mb) {
-      if (mb * 16 >= meff) break;
+  for (int e = lane; e < kWaveRows * ldx; e += kWave) xs[e] = 0.0;
+  __syncthreads();
+  LaneSnaps<PER> L;
+  lane_snaps_init<PER>(snaps, nsnap, L);
+  const long long nchunks = (n + kWaveRows - 1) / kWaveRows;
+  const long long nwaves = gridDim.x * 4LL;
+  for (long long ch = blockIdx.x * 4LL + wv; ch < nchunks; ch += nwaves) {
+    const long long row = ch * kWaveRows + lane % 16;
+    lane_snaps_load<PER>(L, nsnap, n, row);
+    const double c = lane_snaps_centre<PER>(L, nsnap, w, row, n, nullptr);
+    wave_lds_fence();
+    lane_snaps_store<PER>(L, c, nsnap, w, wp, xs, ldx);
+    wave_lds_fence();
+    for (int mb = 0; mb * 16 < meff; ++mb) {
       double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
-      for (int k0 = 0; k0 < wp; k0 += 4) {
+#pragma unroll 4
+      for (int k0 = 0; k0 + 1 < NS; k0 += 4) {
         const int k = k0 + lane / 16;
-        const double a = Ts[k * ldt + mb * 16 + lane % 16];     // A = T^T: A[c][k] = T[k][c]
-        const double b = X[(rb * 16 + lane % 16) * ldx + k];    // B[k][r] = X[r][k]
+        const double a = Ts[k * ldt + mb * 16 + lane % 16];              // A = T^T: A[c][k] = T[k][c]
+        const double b = xs[(lane % 16) * ldx + k];                      // B[k][r] = X[r][k]
         acc = mfma_f64(a, b, acc);
       }
-      const long long orow = row0 + rb * 16 + lane % 16;
+      const long long orow = ch * kWaveRows + lane % 16;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int col = mb * 16 + lane / 16 + 4 * i;
         if (col < meff && orow < n) Phi[(size_t)col * n + orow] = (TP)acc[i];
       }
     }
-  };
-  long long ch = blockIdx.x;
-  if (ch < nchunks) window_prefetch(nsnap, n, ch * kChunk, Ra);
-  if (ch + G < nchunks) window_prefetch(nsnap, n, (ch + G) * kChunk, Rb);
-  for (; ch < nchunks; ch += 2 * G) {
-    process(Ra, ch);
-    if (ch + G < nchunks) process(Rb, ch + G);
   }
 }
 
@@ -392,6 +464,7 @@ static hs_status basis_enqueue(hs_ctx* ctx, const double* const* snaps, int32_t 
   if (m < 1 || m > ctx->p.m_max || m > w) return HS_ERR_INVALID_ARG;
   if (!(tau_pod >= 0.0 && tau_pod < 1.0)) return HS_ERR_INVALID_ARG;
   if (precision != HS_FP64 && precision != HS_MIXED_FP32) return HS_ERR_INVALID_ARG;
+  if (ctx->n >= (1LL << 29)) return ctx->fail(HS_ERR_SHAPE, "basis_update: more than 2^29 entries per snapshot");
   for (int j = 0; j < nsnap; ++j)
     if (!snaps[j]) return HS_ERR_INVALID_ARG;
   // pointer table to device memory through the pinned staging area
@@ -401,12 +474,20 @@ static hs_status basis_enqueue(hs_ctx* ctx, const double* const* snaps, int32_t 
   const long long n = ctx->n;
   const int wp = (w + 15) / 16 * 16;
   const int mp = (m + 15) / 16 * 16;
-  const long long nchunks = (n + kChunk - 1) / kChunk;
-  const int nb = (int)std::min<long long>(nchunks, kRedBlocks);
-  WindowLoader ld{tab, nsnap, w, n, psi_out};
-  const size_t lds = (size_t)kChunk * (wp + 1) * sizeof(double);
+  // four waves per workgroup, each on 16-row chunks
+  const long long nchunks = (n + kWaveRows - 1) / kWaveRows;
+  const int nb = (int)std::min<long long>((nchunks + 3) / 4, kRedBlocks);
+  const size_t glds = (size_t)4 * kWaveRows * (wp + 1) * sizeof(double);
+  const size_t flds = ((size_t)wp * (mp + 1) + (size_t)4 * kWaveRows * (wp + 1)) * sizeof(double);
+  if (flds > (size_t)ctx->max_lds)
+    return ctx->fail(HS_ERR_SHAPE, "basis_update: window and rank need more LDS than a workgroup has");
   HS_TRY(prof_begin(ctx, HS_PROF_BASIS_GRAM));
-  hipLaunchKernelGGL(gram_kernel<WindowLoader>, dim3(nb), dim3(256), lds, ctx->stream, ld, n, wp, ctx->red);
+  switch (wp) {
+    case 16: hipLaunchKernelGGL(window_gram_kernel<17>, dim3(nb), dim3(256), glds, ctx->stream, tab, nsnap, w, n, wp, psi_out, ctx->red); break;
+    case 32: hipLaunchKernelGGL(window_gram_kernel<33>, dim3(nb), dim3(256), glds, ctx->stream, tab, nsnap, w, n, wp, psi_out, ctx->red); break;
+    case 48: hipLaunchKernelGGL(window_gram_kernel<49>, dim3(nb), dim3(256), glds, ctx->stream, tab, nsnap, w, n, wp, psi_out, ctx->red); break;
+    default: hipLaunchKernelGGL(window_gram_kernel<65>, dim3(nb), dim3(256), glds, ctx->stream, tab, nsnap, w, n, wp, psi_out, ctx->red); break;
+  }
   HIP_TRY(ctx, hipGetLastError());
   // reads every snapshot of the window once, writes psi_{k+1}
   HS_TRY(prof_end(ctx, HS_PROF_BASIS_GRAM, 8.0 * (double)n * (nsnap + 1)));
@@ -416,13 +497,23 @@ static hs_status basis_enqueue(hs_ctx* ctx, const double* const* snaps, int32_t 
   HS_LAUNCH(ctx, gram_reduce_kernel, w * w, kBlock, ctx->red, nb, wp, w, G);
   HS_LAUNCH(ctx, basis_eig_kernel, 1, 256, G, w, m, tau_pod, sigma_out, T, mp, meff_d);
   HS_TRY(prof_begin(ctx, HS_PROF_BASIS_FORM));
-  const size_t flds = ((size_t)kChunk * (wp + 1) + (size_t)wp * (mp + 1)) * sizeof(double);
-  if (precision == HS_MIXED_FP32)
-    hipLaunchKernelGGL(basis_form_kernel<float>, dim3(nb), dim3(256), flds, ctx->stream, tab, nsnap, w, n,
-                       (const double*)T, mp, wp, (const int*)meff_d, (float*)Phi_out);
-  else
-    hipLaunchKernelGGL(basis_form_kernel<double>, dim3(nb), dim3(256), flds, ctx->stream, tab, nsnap, w, n,
-                       (const double*)T, mp, wp, (const int*)meff_d, (double*)Phi_out);
+  const int nbf = nb;
+#define HS_FORM(NSV)                                                                                            \
+  do {                                                                                                          \
+    if (precision == HS_MIXED_FP32)                                                                             \
+      hipLaunchKernelGGL((basis_form_kernel<NSV, float>), dim3(nbf), dim3(256), flds, ctx->stream, tab, nsnap, w, n, \
+                         (const double*)T, mp, wp, (const int*)meff_d, (float*)Phi_out);                       \
+    else                                                                                                        \
+      hipLaunchKernelGGL((basis_form_kernel<NSV, double>), dim3(nbf), dim3(256), flds, ctx->stream, tab, nsnap, w, \
+                         n, (const double*)T, mp, wp, (const int*)meff_d, (double*)Phi_out);                   \
+  } while (0)
+  switch (wp) {
+    case 16: HS_FORM(17); break;
+    case 32: HS_FORM(33); break;
+    case 48: HS_FORM(49); break;
+    default: HS_FORM(65); break;
+  }
+#undef HS_FORM
   HIP_TRY(ctx, hipGetLastError());
   // the measurement ends with the kernel; its bytes need m_eff (set on completion)
   const size_t before = ctx->prof_bytes.size();

@@ -448,6 +448,8 @@ hs_status hs_create(const hs_problem* pr, void* stream, hs_ctx** out) {
   if (ctx->p.lin_maxit <= 0) ctx->p.lin_maxit = 400;
   ctx->stream = static_cast<hipStream_t>(stream);
   (void)hipGetDevice(&ctx->device);
+  if (hipDeviceGetAttribute(&ctx->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device) != hipSuccess)
+    ctx->max_lds = 65536;
   ctx->nc = pr->kind == HS_EULER_2D ? 4 : 1;
   ctx->ncell = pr->nx * pr->ny;
   ctx->n = ctx->nc * ctx->ncell;

@@ -104,12 +104,14 @@ def window(prob, q0, w, extra=1):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("first", [False, True])
-def test_basis_update_matches_oracle(name, first):
+@pytest.mark.parametrize("w,m,first", [(12, 8, False), (12, 8, True), (30, 20, False), (48, 32, False),
+                                       (60, 40, False)])
+def test_basis_update_matches_oracle(name, w, m, first):
+    """Windows padded to 16, 32, 48 and 64 columns (every instantiation of the
+    window passes), the first update (w snapshots) and the later ones (w + 1)."""
     need_gpu()
-    print_case("basis_update", name, first)
+    print_case("basis_update", name, w, m, first)
     wl, prob, q0 = case(name, 1)
-    w, m = 12, 8
     snaps = window(prob, q0, w, extra=0 if first else 1)
     o = pod.pod(snaps, w, m, tau=1e-4)
     ctx = ctx_for(prob)
@@ -117,8 +119,8 @@ def test_basis_update_matches_oracle(name, first):
     psi = ctx.empty()
     sig = torch.zeros(w, dtype=torch.float64, device="cuda")
     me = ctx.basis_update([dev(s) for s in snaps], w, m, Phi, psi, sig, tau_pod=1e-4)
-    # the window means are summed in four fixed partial sums (a few ulps from
-    # the oracle's single sequential sum)
+    # the window means are summed in eight strided partial sums (a few ulps
+    # from the oracle's sum)
     assert np.max(np.abs(host(psi) - o["psi_new"])) <= 1e-15 * np.max(np.abs(o["psi_new"]))
     sg, so = host(sig), o["sigma"]
     assert np.max(np.abs(sg ** 2 - so ** 2)) <= 1e-13 * so[0] ** 2

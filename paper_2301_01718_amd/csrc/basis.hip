@@ -145,8 +145,10 @@ __global__ void __launch_bounds__(256) window_gram_kernel(const double* const* _
     lane_snaps_store<PER>(L, c, nsnap, w, wp, xs, ldx);
     wave_lds_fence();
     // per k-step the NT column blocks x_t = X[k][16 t + l % 16] serve as
-    // both operands: A = X^T (A[r][k] = X[k][16 ti + r]), B[k][c] = X[k][16 tj + c]
-#pragma unroll
+    // both operands: A = X^T (A[r][k] = X[k][16 ti + r]), B[k][c] = X[k][16 tj + c];
+    // the tiles of a k-step are independent, the k-steps are not unrolled
+    // (fewer live registers, more resident waves)
+#pragma unroll 1
     for (int k0 = 0; k0 < kWaveRows; k0 += 4) {
       const int k = k0 + lane / 16;
       double x[NT];
@@ -186,6 +188,23 @@ __global__ void __launch_bounds__(256) window_gram_kernel(const double* const* _
     const int r = ti * 16 + l / 16 + 4 * i, cc = tj * 16 + l % 16;
     out[r * wp + cc] = red[e];
   }
+}
+
+// Sum over each aligned group of 8 lanes, in every lane of the group, by DPP
+// moves (quad xor 1, quad xor 2, half-row mirror): register-to-register,
+// without the LDS round trip of a lane shuffle.
+template <int CTRL>
+__device__ inline double dpp_double(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ inline double group8_sum(double x) {
+  x += dpp_double<0xB1>(x);    // quad_perm [1, 0, 3, 2]
+  x += dpp_double<0x4E>(x);    // quad_perm [2, 3, 0, 1]
+  x += dpp_double<0x141>(x);   // row_half_mirror: lane i <-> 7 - i within 8
+  return x;
 }
 
 // Eigen-decomposition of the window Gram G (w x w, PSD) and the formation
@@ -321,17 +340,17 @@ __global__ void __launch_bounds__(256) basis_eig_kernel(const double* __restrict
               bb += ys[i] * ys[i];
               gg += xs[i] * ys[i];
             }
-#pragma unroll
-            for (int o = 4; o > 0; o >>= 1) {
-              aa += __shfl_xor(aa, o, kWave);
-              bb += __shfl_xor(bb, o, kWave);
-              gg += __shfl_xor(gg, o, kWave);
-            }
-            const double lim = sqrt(aa * bb);
-            if (aa > 0.0 && bb > 0.0 && fabs(gg) > tol_rot * lim) {
-              const double zeta = (bb - aa) / (2.0 * gg);
-              const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-              const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+            aa = group8_sum(aa);
+            bb = group8_sum(bb);
+            gg = group8_sum(gg);
+            // rotation when |g| > tol sqrt(a b), tested on squares; with
+            // d = b - a, e = 2 g: t = sign(d) e / (|d| + sqrt(d^2 + e^2)) (the
+            // smaller root of t^2 + 2 (d / e) t - 1 = 0), c = 1 / sqrt(1 + t^2)
+            const double ab = aa * bb;
+            if (aa > 0.0 && bb > 0.0 && gg * gg > tol_rot * tol_rot * ab) {
+              const double dd = bb - aa, ee = 2.0 * gg;
+              const double tt = (dd >= 0.0 ? ee : -ee) / (fabs(dd) + sqrt(dd * dd + ee * ee));
+              const double c = rsqrt(1.0 + tt * tt), sn = c * tt;
 #pragma unroll
               for (int i = 0; i < 8; ++i) {
                 const int k = gl + 8 * i;
@@ -340,7 +359,7 @@ __global__ void __launch_bounds__(256) basis_eig_kernel(const double* __restrict
                   L[k * lda + q] = sn * xs[i] + c * ys[i];
                 }
               }
-              if (gl == 0 && fabs(gg) > tol_conv * lim) rotated = 1;
+              if (gl == 0 && gg * gg > tol_conv * tol_conv * ab) rotated = 1;
             }
           }
         }
@@ -474,9 +493,12 @@ static hs_status basis_enqueue(hs_ctx* ctx, const double* const* snaps, int32_t 
   const long long n = ctx->n;
   const int wp = (w + 15) / 16 * 16;
   const int mp = (m + 15) / 16 * 16;
-  // four waves per workgroup, each on 16-row chunks
+  // four waves per workgroup, each on 16-row chunks; the Gram pass keeps
+  // three workgroups per compute unit resident (registers), so its grid is
+  // one resident round (768), which also bounds the partials it leaves
   const long long nchunks = (n + kWaveRows - 1) / kWaveRows;
-  const int nb = (int)std::min<long long>((nchunks + 3) / 4, kRedBlocks);
+  const int nb = (int)std::min<long long>((nchunks + 3) / 4, 768);
+  const int nbf = (int)std::min<long long>((nchunks + 3) / 4, kRedBlocks);
   const size_t glds = (size_t)4 * kWaveRows * (wp + 1) * sizeof(double);
   const size_t flds = ((size_t)wp * (mp + 1) + (size_t)4 * kWaveRows * (wp + 1)) * sizeof(double);
   if (flds > (size_t)ctx->max_lds)
@@ -497,7 +519,6 @@ static hs_status basis_enqueue(hs_ctx* ctx, const double* const* snaps, int32_t 
   HS_LAUNCH(ctx, gram_reduce_kernel, w * w, kBlock, ctx->red, nb, wp, w, G);
   HS_LAUNCH(ctx, basis_eig_kernel, 1, 256, G, w, m, tau_pod, sigma_out, T, mp, meff_d);
   HS_TRY(prof_begin(ctx, HS_PROF_BASIS_FORM));
-  const int nbf = nb;
 #define HS_FORM(NSV)                                                                                            \
   do {                                                                                                          \
     if (precision == HS_MIXED_FP32)                                                                             \

@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--workload", default="burgers2d_1024")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--roofline-kernel", default="basis_form",
-                    choices=["basis_gram", "basis_form", "recon", "resjac", "sweep", "cellres", "filter"])
+                    choices=["basis_gram", "basis_form", "recon", "resjac", "sweep", "cellres", "filter", "residual"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurement")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision measurement")
@@ -79,6 +79,46 @@ def traffic_for(kernel, workload):
     if d.get("source_digest") != source_digest(kernel):
         return None
     return d.get("bytes_per_launch")
+
+
+def kernel_rates(ctx, q, q_prev, reps=3):
+    """Achieved HBM rate (algorithmic bytes / HIP-event launch time) of the
+    residual kernel classes on the full mesh: hs_residual, the residual +
+    Jacobian data of a full Newton step, and the fused filter pass."""
+    import torch
+    out = {}
+    R = ctx.empty()
+    jobs = {"residual": lambda: ctx.residual(q, q_prev, out=R),
+            "resjac": lambda: ctx.hdm_step(q_prev, out=R),
+            "filter": lambda: ctx.filter(q, q_prev, out=R)}
+    for cls, fn in jobs.items():
+        fn()
+        torch.cuda.synchronize(ctx.device)
+        ctx.prof_enable(cls)
+        for _ in range(reps):
+            fn()
+        ms, n, by = ctx.prof_read()
+        ctx.prof_enable(0)
+        if n:
+            gbs = (by / n) / (ms / n * 1e-3) / 1e9
+            out[cls] = {"launches": n, "avg_launch_us": 1e3 * ms / n, "bytes_per_launch": by / n,
+                        "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+    return out
+
+
+def residual_kernels(prob, q, q_prev, seed):
+    """kernel_rates on this workload's mesh and on the 2D Euler 512^2 mesh."""
+    import torch
+    import workloads as W
+    from paper_2301_01718_amd import Context
+    res = {"burgers2d_1024" if prob.nx == 1024 else "this": kernel_rates(Context(prob), q, q_prev)}
+    wl_e = W.WORKLOADS["euler2d_512"]
+    prob_e, q0_e = W.make(wl_e, seed)
+    ce = Context(prob_e)
+    qe0 = torch.from_numpy(q0_e).to(ce.device)
+    qe1, _ = ce.hdm_step(qe0)
+    res["euler2d_512"] = kernel_rates(ce, qe1, qe0)
+    return res
 
 
 def cpu_baseline(prob, wl, snap):
@@ -226,6 +266,10 @@ def main():
         th.append(time.perf_counter() - t)
     t_H = float(np.median(th))
 
+    log("residual kernel rates ...")
+    prev_state = drv.slot(drv.k - 1).clone()
+    resk = residual_kernels(prob, drv.state(), prev_state, args.seed)
+
     if args.copy_probe:
         a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)
@@ -265,6 +309,7 @@ def main():
                    "timed_steps": [recs[0]["k"], recs[-1]["k"]]},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "residual_kernels": resk,
         "cell_updates_per_s": prob.ncell * args.steps / elapsed,
         "hybrid_step_ms": float(np.median(hyb)) if hyb else None,
         "full_step_ms": 1e3 * t_H,

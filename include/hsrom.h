@@ -288,6 +288,7 @@ hs_status hs_set_option(hs_ctx* ctx, int32_t option, int64_t value);
 #define HS_PROF_SWEEP       5   /* Jacobi relaxation sweeps */
 #define HS_PROF_CELLRES     6   /* cell residual norms (filter) */
 #define HS_PROF_FILTER      7   /* fused filter pass: S_y S_x, gate, merged residual norms */
+#define HS_PROF_RESIDUAL    8   /* hs_residual: R(q; q_prev) on the full mesh */
 /* Start timing every launch of one kernel class (HS_PROF_NONE stops).  Each
  * launch is bracketed by two HIP events recorded on the context's stream, and
  * the algorithmic bytes of that launch (the minimum reads and writes the

@@ -117,7 +117,7 @@ _SIGS = {
 }
 
 PROF_CLASSES = {"basis_gram": 1, "basis_form": 2, "recon": 3, "resjac": 4, "sweep": 5, "cellres": 6,
-                "filter": 7}
+                "filter": 7, "residual": 8}
 
 
 def lib():

@@ -55,7 +55,7 @@ __device__ inline void coupling_block(const Grid& g, const double* __restrict__ 
 // neighbour in direction e (0 for repeats, ghosts and cells outside the
 // list), rhs = D_p^{-T} v_p; the max-norm contraction bound to part[Rho].
 template <int NC>
-__global__ void adj_coef_kernel(Grid g, const double* __restrict__ q, const int* __restrict__ hat,
+__global__ void __launch_bounds__(kBlock) adj_coef_kernel(Grid g, const double* __restrict__ q, const int* __restrict__ hat,
                                 const int* __restrict__ nbr, int count, int cap, const double* __restrict__ v,
                                 double* __restrict__ coef, double* __restrict__ rhs, double* __restrict__ part) {
   __shared__ double lds[kBlock / kWave];
@@ -125,7 +125,7 @@ __global__ void adj_coef_kernel(Grid g, const double* __restrict__ q, const int*
 // ring cell of B_s^T mu[s], with B_s the block of s's residual for the ring
 // cell (pos maps a cell to its hat-S index, -1 outside).
 template <int NC>
-__global__ void ring_coupling_kernel(Grid g, const double* __restrict__ q, const int* __restrict__ tilde, int l,
+__global__ void __launch_bounds__(kBlock) ring_coupling_kernel(Grid g, const double* __restrict__ q, const int* __restrict__ tilde, int l,
                                      const int* __restrict__ pos, const double* __restrict__ mu, int cap,
                                      double* __restrict__ tb) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;

@@ -129,7 +129,7 @@ __global__ void residual_kernel(Grid g, const double* __restrict__ q, const doub
 
 // out = J(q) v
 template <int NC>
-__global__ void jvp_kernel(Grid g, const double* __restrict__ q, const double* __restrict__ v,
+__global__ void __launch_bounds__(kBlock) jvp_kernel(Grid g, const double* __restrict__ q, const double* __restrict__ v,
                            double* __restrict__ out) {
   const int cell = blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= g.ncell) return;
@@ -161,7 +161,7 @@ __global__ void jvp_kernel(Grid g, const double* __restrict__ q, const double* _
 // Residual + Jacobi iteration data on the full mesh (hat == nullptr) or on the
 // compact list hat[0..count) whose in-set neighbours are nbr[d * cap + p].
 template <int NC>
-__global__ void resjac_kernel(Grid g, const double* __restrict__ q, const double* __restrict__ qp,
+__global__ void __launch_bounds__(kBlock) resjac_kernel(Grid g, const double* __restrict__ q, const double* __restrict__ qp,
                               const int* __restrict__ hat, const int* __restrict__ nbr, int count,
                               int cap, double* __restrict__ coef, double* __restrict__ rhs,
                               double* __restrict__ part) {
@@ -509,7 +509,7 @@ hs_status hs_create(const hs_problem* pr, void* stream, hs_ctx** out) {
 }
 
 hs_status hs_prof_enable(hs_ctx* ctx, int32_t cls) {
-  if (!ctx || cls < HS_PROF_NONE || cls > HS_PROF_FILTER) return HS_ERR_INVALID_ARG;
+  if (!ctx || cls < HS_PROF_NONE || cls > HS_PROF_RESIDUAL) return HS_ERR_INVALID_ARG;
   ctx->prof_class = cls;
   ctx->prof_used = 0;
   ctx->prof_bytes.clear();
@@ -552,9 +552,11 @@ hs_status hs_sync(hs_ctx* ctx) {
 hs_status hs_residual(hs_ctx* ctx, const double* q, const double* q_prev, double* R) {
   if (!ctx || !q || !q_prev || !R) return HS_ERR_INVALID_ARG;
   const int nb = blocks_for(ctx->ncell);
+  HS_TRY(prof_begin(ctx, HS_PROF_RESIDUAL));
   if (ctx->nc == 1) HS_LAUNCH(ctx, residual_kernel<1>, nb, kBlock, ctx->g, q, q_prev, R);
   else HS_LAUNCH(ctx, residual_kernel<4>, nb, kBlock, ctx->g, q, q_prev, R);
-  return HS_OK;
+  // reads q and q_prev once, writes R
+  return prof_end(ctx, HS_PROF_RESIDUAL, 24.0 * ctx->n);
 }
 
 hs_status hs_jvp(hs_ctx* ctx, const double* q, const double* v, double* out) {

@@ -249,11 +249,42 @@ __device__ inline void cell_jacobian(const Grid& g, const Stencil<NC>& st, doubl
   }
 }
 
-// Inverse of a small row-major NC x NC matrix (Gauss-Jordan, partial pivoting).
+// Inverse of a small row-major NC x NC matrix (NC = 4: adjugate; otherwise
+// Gauss-Jordan with partial pivoting).
 template <int NC>
 __device__ inline void small_inverse(const double A[NC * NC], double X[NC * NC]) {
   if constexpr (NC == 1) {
     X[0] = 1.0 / A[0];
+  } else if constexpr (NC == 4) {
+    // adjugate / determinant, the cofactors from complementary 2 x 2 minors of
+    // the top and bottom row pairs (Laplace expansion): static indexing, so
+    // the block stays in registers (the blocks inverted here are the
+    // diagonally dominated Newton-Jacobian blocks; the relaxation only needs
+    // an accurate inverse, the converged Newton state does not depend on it)
+    const double a00 = A[0], a01 = A[1], a02 = A[2], a03 = A[3], a10 = A[4], a11 = A[5], a12 = A[6], a13 = A[7];
+    const double a20 = A[8], a21 = A[9], a22 = A[10], a23 = A[11], a30 = A[12], a31 = A[13], a32 = A[14],
+                 a33 = A[15];
+    const double s0 = a00 * a11 - a10 * a01, s1 = a00 * a12 - a10 * a02, s2 = a00 * a13 - a10 * a03;
+    const double s3 = a01 * a12 - a11 * a02, s4 = a01 * a13 - a11 * a03, s5 = a02 * a13 - a12 * a03;
+    const double c5 = a22 * a33 - a32 * a23, c4 = a21 * a33 - a31 * a23, c3 = a21 * a32 - a31 * a22;
+    const double c2 = a20 * a33 - a30 * a23, c1 = a20 * a32 - a30 * a22, c0 = a20 * a31 - a30 * a21;
+    const double inv = 1.0 / (s0 * c5 - s1 * c4 + s2 * c3 + s3 * c2 - s4 * c1 + s5 * c0);
+    X[0] = (a11 * c5 - a12 * c4 + a13 * c3) * inv;
+    X[1] = (-a01 * c5 + a02 * c4 - a03 * c3) * inv;
+    X[2] = (a31 * s5 - a32 * s4 + a33 * s3) * inv;
+    X[3] = (-a21 * s5 + a22 * s4 - a23 * s3) * inv;
+    X[4] = (-a10 * c5 + a12 * c2 - a13 * c1) * inv;
+    X[5] = (a00 * c5 - a02 * c2 + a03 * c1) * inv;
+    X[6] = (-a30 * s5 + a32 * s2 - a33 * s1) * inv;
+    X[7] = (a20 * s5 - a22 * s2 + a23 * s1) * inv;
+    X[8] = (a10 * c4 - a11 * c2 + a13 * c0) * inv;
+    X[9] = (-a00 * c4 + a01 * c2 - a03 * c0) * inv;
+    X[10] = (a30 * s4 - a31 * s2 + a33 * s0) * inv;
+    X[11] = (-a20 * s4 + a21 * s2 - a23 * s0) * inv;
+    X[12] = (-a10 * c3 + a11 * c1 - a12 * c0) * inv;
+    X[13] = (a00 * c3 - a01 * c1 + a02 * c0) * inv;
+    X[14] = (-a30 * s3 + a31 * s1 - a32 * s0) * inv;
+    X[15] = (a20 * s3 - a21 * s1 + a22 * s0) * inv;
   } else {
     double M[NC][2 * NC];
 #pragma unroll

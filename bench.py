@@ -161,6 +161,8 @@ def mixed_bench(prob, q0, wl, k_start, steps, ref_state):
     for i in range(steps):
         ev[i][0].record()
         recs.append(drv.advance())
+        if i == steps - 1:
+            drv.finish()            # the last step's basis update, still in flight, is part of it
         ev[i][1].record()
     torch.cuda.synchronize(dev)
     hyb = [a.elapsed_time(b) for (a, b), r in zip(ev, recs) if r["type"] == "hybrid"]
@@ -224,7 +226,9 @@ def main():
         drv.advance()
     log(f"warmup done at step {drv.k}")
 
-    # inputs of the first timed step, for the CPU baseline (host copies, untimed)
+    # inputs of the first timed step, for the CPU baseline (host copies,
+    # untimed; the warm-up's basis update is completed first)
+    drv.finish()
     snap = None
     if not args.no_cpu_baseline and drv.have_samples:
         hat, tilde, _ = drv.samples.export()
@@ -245,6 +249,10 @@ def main():
     for i in range(args.steps):
         ev[i][0].record()
         recs.append(drv.advance())
+        if i == args.steps - 1:
+            # a step's basis update completes inside the next hybrid step
+            # (beside its first Newton solve); the last one is part of it
+            drv.finish()
         ev[i][1].record()
     torch.cuda.synchronize(dev)
     elapsed = time.perf_counter() - t0

@@ -200,8 +200,19 @@ hs_status basis_update_async(hs_ctx* ctx, const double* const* snaps /* host */,
                              int32_t m, double tau_pod, int32_t precision, void* Phi_out, double* psi_out,
                              double* sigma_out);
 hs_status basis_update_finish(hs_ctx* ctx, int32_t* m_eff /* host */);
+/* m_eff of the last completed basis update (synchronous, finished, or
+ * completed by a hybrid step given HS_BASIS_PENDING).  Error if an update is
+ * still in flight. */
+hs_status hs_basis_m_eff(hs_ctx* ctx, int32_t* m_eff /* host */);
 
 /* --------------------------------------------------- rom_hybrid_step */
+/* m = HS_BASIS_PENDING: Phi and psi are the outputs of an asynchronous
+ * basis_update that is still in flight.  The step runs its first restricted
+ * Newton solve (which does not read the basis) beside the update, then
+ * completes the update as basis_update_finish would and uses its m_eff
+ * (read it back with hs_basis_m_eff; on every return path the update has
+ * been completed).  Results are those of finishing the update first. */
+#define HS_BASIS_PENDING (-1)
 typedef struct hs_hybrid_params {
   double  eps_y;            /* subiteration tolerance (paper: 1e-4) */
   int32_t jmax;             /* max subiterations (paper: 10) */

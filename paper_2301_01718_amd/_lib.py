@@ -100,6 +100,7 @@ _SIGS = {
     "basis_update": [P, ctypes.POINTER(P), I32, I32, I32, D, I32, P, P, P, ctypes.POINTER(I32)],
     "basis_update_async": [P, ctypes.POINTER(P), I32, I32, I32, D, I32, P, P, P],
     "basis_update_finish": [P, ctypes.POINTER(I32)],
+    "hs_basis_m_eff": [P, ctypes.POINTER(I32)],
     "rom_hybrid_step": [P, P, P, P, I32, P, ctypes.POINTER(HybridParams), P, P, P,
                         ctypes.POINTER(StepInfo)],
     "hs_filter": [P, P, P, ctypes.POINTER(HybridParams), P, ctypes.POINTER(StepInfo)],
@@ -115,6 +116,8 @@ _SIGS = {
     "hs_prof_enable": [P, I32],
     "hs_prof_read": [P, ctypes.POINTER(D), ctypes.POINTER(I32), ctypes.POINTER(D)],
 }
+
+BASIS_PENDING = -1   # rom_hybrid_step's m for a basis still being formed (HS_BASIS_PENDING)
 
 PROF_CLASSES = {"basis_gram": 1, "basis_form": 2, "recon": 3, "resjac": 4, "sweep": 5, "cellres": 6,
                 "filter": 7, "residual": 8}
@@ -177,6 +180,7 @@ class Context:
                     dt=prob.dt, gamma=prob.gamma, inflow=prob.inflow, newton_rtol=newton_rtol,
                     newton_maxit=newton_maxit, lin_rtol=lin_rtol, lin_maxit=lin_maxit,
                     m_max=m_max, w_max=w_max)
+        self.m_max, self.w_max = m_max, w_max
         self.ncomp = 4 if prob.kind == EULER_2D else 1
         self.ncell = prob.nx * prob.ny
         self.n = self.ncomp * self.ncell
@@ -266,6 +270,8 @@ class Context:
         return s
 
     def _basis(self, Phi, m):
+        # m = BASIS_PENDING: the basis an asynchronous update is forming (up to m_max modes)
+        m = self.m_max if m == BASIS_PENDING else m
         if not Phi.is_contiguous() or Phi.numel() < m * self.n or Phi.device != self.device:
             raise ValueError(f"basis must be a contiguous tensor of at least {m} x {self.n} entries on {self.device}")
         return basis_precision(Phi)
@@ -294,9 +300,21 @@ class Context:
         arr = (P * len(snaps))(*[P(self._in(s).data_ptr()) for s in snaps])
         self._check(lib().basis_update_async(self.h, arr, len(snaps), w, m, tau_pod, precision, _ptr(Phi_out),
                                              _ptr(self._in(psi_out)), _ptr(sigma_out)))
+        self._pending = True
+
+    def basis_pending(self):
+        """Whether an asynchronous basis update is in flight."""
+        return getattr(self, "_pending", False)
+
+    def basis_m_eff(self):
+        """m_eff of the last completed basis update."""
+        me = I32(0)
+        self._check(lib().hs_basis_m_eff(self.h, ctypes.byref(me)))
+        return me.value
 
     def basis_update_finish(self):
         me = I32(0)
+        self._pending = False
         self._check(lib().basis_update_finish(self.h, ctypes.byref(me)))
         return me.value
 
@@ -305,9 +323,13 @@ class Context:
         params = _with_precision(params or hybrid_params(), self._basis(Phi, m))
         out = self.empty() if out is None else out
         info = StepInfo()
-        self._check(lib().rom_hybrid_step(self.h, _ptr(self._in(q_prev)), _ptr(Phi), _ptr(self._in(psi)), m,
-                                          samples.h, ctypes.byref(params), _ptr(self._in(out)),
-                                          _ptr(eps), _ptr(y), ctypes.byref(info)))
+        try:
+            self._check(lib().rom_hybrid_step(self.h, _ptr(self._in(q_prev)), _ptr(Phi), _ptr(self._in(psi)), m,
+                                              samples.h, ctypes.byref(params), _ptr(self._in(out)),
+                                              _ptr(eps), _ptr(y), ctypes.byref(info)))
+        finally:
+            if m == BASIS_PENDING:
+                self._pending = False        # the step completes the update on every path
         return out, info.as_dict()
 
     def filter(self, gamma, q_prev, params=None, out=None):
@@ -328,9 +350,14 @@ class Context:
         params = _with_precision(params or hybrid_params(), self._basis(Phi, m))
         out = self.empty() if out is None else out
         info = StepInfo()
-        self._check(lib().rom_hybrid_step_taped(self.h, _ptr(self._in(q_prev)), _ptr(Phi), _ptr(self._in(psi)), m,
-                                                samples.h if samples is not None else None, ctypes.byref(params),
-                                                _ptr(self._in(out)), _ptr(eps), ctypes.byref(info), tape.h, mode))
+        try:
+            self._check(lib().rom_hybrid_step_taped(self.h, _ptr(self._in(q_prev)), _ptr(Phi), _ptr(self._in(psi)),
+                                                    m, samples.h if samples is not None else None,
+                                                    ctypes.byref(params), _ptr(self._in(out)), _ptr(eps),
+                                                    ctypes.byref(info), tape.h, mode))
+        finally:
+            if m == BASIS_PENDING:
+                self._pending = False
         return out, info.as_dict()
 
     def hdm_step_adjoint(self, q_out, lam, out=None):

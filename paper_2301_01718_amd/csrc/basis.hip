@@ -551,6 +551,7 @@ static hs_status basis_complete(hs_ctx* ctx, int32_t* m_eff) {
   int me = 0;
   HS_TRY(readback(ctx, meff_d, sizeof(int), &me));
   *m_eff = me;
+  ctx->basis_meff = me;
   // reads every snapshot of the window once, writes m_eff columns of Phi
   const auto& f = ctx->pending_form;
   if (f.prof_idx >= 0 && f.prof_idx < (int)ctx->prof_bytes.size())
@@ -591,8 +592,8 @@ extern "C" hs_status basis_update_async(hs_ctx* ctx, const double* const* snaps,
   return HS_OK;
 }
 
-extern "C" hs_status basis_update_finish(hs_ctx* ctx, int32_t* m_eff) {
-  if (!ctx || !m_eff) return HS_ERR_INVALID_ARG;
+namespace hs {
+hs_status basis_finish_pending(hs_ctx* ctx, int32_t* m_eff) {
   if (!ctx->aux_pending) return ctx->fail(HS_ERR_INVALID_ARG, "no asynchronous basis update in flight");
   ctx->aux_pending = false;
   hipStream_t main = ctx->stream;
@@ -600,4 +601,17 @@ extern "C" hs_status basis_update_finish(hs_ctx* ctx, int32_t* m_eff) {
   const hs_status st = basis_complete(ctx, m_eff);
   ctx->stream = main;
   return st;
+}
+}  // namespace hs
+
+extern "C" hs_status basis_update_finish(hs_ctx* ctx, int32_t* m_eff) {
+  if (!ctx || !m_eff) return HS_ERR_INVALID_ARG;
+  return basis_finish_pending(ctx, m_eff);
+}
+
+extern "C" hs_status hs_basis_m_eff(hs_ctx* ctx, int32_t* m_eff) {
+  if (!ctx || !m_eff) return HS_ERR_INVALID_ARG;
+  if (ctx->aux_pending) return ctx->fail(HS_ERR_INVALID_ARG, "a basis update is still in flight");
+  *m_eff = ctx->basis_meff;
+  return HS_OK;
 }

@@ -56,6 +56,7 @@ struct hs_ctx {
   hipStream_t aux = nullptr;        // library-owned stream of basis_update_async (default priority)
   hipEvent_t aux_ready = nullptr;   // recorded on stream, waited on by aux
   bool aux_pending = false;         // an asynchronous basis update is in flight
+  int basis_meff = 0;               // m_eff of the last completed basis update
   struct { long long n; int nsnap; double phi_bytes; int prof_idx; } pending_form{0, 0, 8.0, -1};
   int device = 0;
   int max_lds = 65536;               // LDS bytes a workgroup may use on this device
@@ -341,6 +342,8 @@ void set_tile_geometry(hs_ctx* ctx, const hs_problem* pr);
 // Whether the relaxation on s (nullptr: full mesh) runs in tiles, and the
 // sweeps per tiled launch.
 bool use_tiles(const hs_ctx* ctx, const hs_samples* s);
+// Completes the asynchronous basis update in flight (its m_eff to *m_eff).
+hs_status basis_finish_pending(hs_ctx* ctx, int32_t* m_eff);
 int tile_sweeps(const hs_ctx* ctx, const hs_samples* s);
 // Bracket one launch of kernel class cls with events (no-op unless enabled).
 hs_status prof_begin(hs_ctx* ctx, int cls);

@@ -735,7 +735,20 @@ static hs_status fit_solve(hs_ctx* ctx, const void* Phi, int prec, int m, const 
 static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const void* Phi, const double* psi, int m,
                              const hs_samples* s, const hs_hybrid_params* hp, double* q_out, double* eps_out,
                              double* y_out, hs_step_info* info, hs_htape* tape, int mode) {
-  if (!ctx || !q_prev || !Phi || !psi || !hp || !q_out) return HS_ERR_INVALID_ARG;
+  if (!ctx) return HS_ERR_INVALID_ARG;
+  // HS_BASIS_PENDING: the basis is still being formed on the context's
+  // second stream; it is completed after the first Newton solve, and on
+  // every early return by the guard
+  const bool pending = m == HS_BASIS_PENDING;
+  struct PendingGuard {
+    hs_ctx* c;
+    bool active;
+    ~PendingGuard() {
+      int32_t me;
+      if (active && c->aux_pending) (void)basis_finish_pending(c, &me);
+    }
+  } guard{ctx, pending};
+  if (!q_prev || !Phi || !psi || !hp || !q_out) return HS_ERR_INVALID_ARG;
   if (q_out == q_prev || q_out == psi || (const void*)q_out == Phi) return HS_ERR_INVALID_ARG;
   const bool replay = mode == HS_TAPE_REPLAY;
   if (mode >= 0 && (!tape || tape->ctx != ctx)) return HS_ERR_INVALID_ARG;
@@ -743,8 +756,10 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const void* Phi,
     if (!tape->recorded) return ctx->fail(HS_ERR_INVALID_ARG, "replay of a tape that holds no recorded step");
     s = tape->s;
   }
+  if (pending && (replay || !ctx->aux_pending))
+    return ctx->fail(HS_ERR_INVALID_ARG, "HS_BASIS_PENDING needs an asynchronous basis update in flight");
   if (!s || s->ctx != ctx) return HS_ERR_INVALID_ARG;
-  if (m < 1 || m > ctx->p.m_max) return ctx->fail(HS_ERR_RANK, "empty basis");
+  if (!pending && (m < 1 || m > ctx->p.m_max)) return ctx->fail(HS_ERR_RANK, "empty basis");
   if (hp->jmax < 1 || hp->n_orders < 0 || hp->n_orders > 4 || !(hp->rcond_fit > 0) || !(hp->eps_y >= 0))
     return HS_ERR_INVALID_ARG;
   for (int o = 0; o < hp->n_orders; ++o)
@@ -773,17 +788,21 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const void* Phi,
   double* u = ctx->u;
   double* sm = ctx->small;
   // max |q_prev| (Newton tolerance) and the fit factorisation, read together
+  // (with a pending basis the factorisation follows the first Newton solve)
   HS_TRY(max_abs_launch(ctx, q_prev, ctx->n));
   HIP_TRY(ctx, hipMemcpyAsync(u, q_prev, ctx->n * 8, hipMemcpyDeviceToDevice, ctx->stream));
-  HS_TRY(fit_factor(ctx, Phi, prec, m, s->hat, s->n_s, hp->rcond_fit));
+  if (!pending) HS_TRY(fit_factor(ctx, Phi, prec, m, s->hat, s->n_s, hp->rcond_fit));
   unsigned long long st[kStatSlots];
   HS_TRY(read_stats(ctx, st));
   const double qmax = bits_to_double(st[kStatQMax]);
   if (!std::isfinite(qmax)) return ctx->fail(HS_ERR_NONFINITE, "non-finite q_prev");
   const double tol = ctx->p.newton_rtol * std::max(1.0, qmax);
-  inf->fit_rank = (int)bits_to_double(st[kStatFitRank]);
-  inf->fit_cond = bits_to_double(st[kStatFitCond]);
-  if (inf->fit_rank == 0) return ctx->fail(HS_ERR_RANK, "rank-zero fit");
+  auto fit_stats = [&]() -> hs_status {
+    inf->fit_rank = (int)bits_to_double(st[kStatFitRank]);
+    inf->fit_cond = bits_to_double(st[kStatFitCond]);
+    return inf->fit_rank == 0 ? ctx->fail(HS_ERR_RANK, "rank-zero fit") : HS_OK;
+  };
+  if (!pending) HS_TRY(fit_stats());
 
   // Subiterations.  The stop test on ||y_j - y_{j-1}|| is read together with
   // the residual of the next Newton solve's first iteration, launched
@@ -792,6 +811,16 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const void* Phi,
   bool have_primed = false;
   for (int j = 1; j <= jmax; ++j) {
     HS_TRY(newton_solve(ctx, u, q_prev, tol, s, inf, have_primed ? primed : nullptr));
+    if (pending && j == 1) {
+      int32_t me = 0;
+      guard.active = false;
+      HS_TRY(basis_finish_pending(ctx, &me));
+      if (me < 1 || me > ctx->p.m_max) return ctx->fail(HS_ERR_RANK, "empty basis");
+      m = me;
+      HS_TRY(fit_factor(ctx, Phi, prec, m, s->hat, s->n_s, hp->rcond_fit));
+      HS_TRY(read_stats(ctx, st));
+      HS_TRY(fit_stats());
+    }
     if (replay)
       HIP_TRY(ctx, hipMemcpyAsync(tape->us + (size_t)(j - 1) * ctx->n, u, ctx->n * 8, hipMemcpyDeviceToDevice,
                                   ctx->stream));

@@ -17,8 +17,8 @@ import time
 
 import torch
 
-from ._lib import (Context, HsError, FP64, HS_ERR_NOT_CONVERGED, HS_ERR_RANK, MIXED_FP32, RULE_FRACTION,
-                   TAPE_RECORD, hybrid_params)
+from ._lib import (BASIS_PENDING, Context, HsError, FP64, HS_ERR_NOT_CONVERGED, HS_ERR_RANK, MIXED_FP32,
+                   RULE_FRACTION, TAPE_RECORD, hybrid_params)
 
 
 @dataclasses.dataclass
@@ -80,6 +80,10 @@ class Arom:
                                 cfg.rcond_fit, cfg.floor_rel, cfg.precision)
         self.m_eff = 0
         self.basis_version = 0
+        # a basis update left in flight for the next hybrid step to complete
+        # (after its first Newton solve, which does not need the basis)
+        self.pending = None
+        self.defer_basis = True
         # optional: an object with tape(k) -> Tape, called for every hybrid
         # step; the step then records its frozen decisions (adjoint use)
         self.recorder = None
@@ -87,8 +91,16 @@ class Arom:
     def slot(self, k):
         return self.ring[k % (self.cfg.w + 2)]
 
+    def _complete(self):
+        """Finish a pending basis update (if any) and record its m_eff."""
+        if self.pending is not None:
+            rec, self.pending = self.pending, None
+            self.m_eff = self.ctx.basis_update_finish() if self.ctx.basis_pending() else self.ctx.basis_m_eff()
+            rec["m_eff"] = self.m_eff
+
     def start(self, q0, steps):
         """Load gamma_0 and reset the schedule for a run of ``steps`` steps."""
+        self._complete()
         self.slot(0).copy_(q0)
         self.m_eff = 0
         self.have_samples = False
@@ -102,18 +114,22 @@ class Arom:
         k = self.k
         rec = {"k": k}
         prev, out = self.slot(k - 1), self.slot(k)
+        hybrid = (not is_full_step(k, cfg.w, cfg.z) and self.have_samples
+                  and (self.pending is not None or self.m_eff > 0))
+        if not hybrid:
+            self._complete()
         used = {"q_prev": prev, "Phi": self.Phi, "psi": self.psi, "m": self.m_eff,
                 "basis_version": self.basis_version}
-        hybrid = not is_full_step(k, cfg.w, cfg.z) and self.have_samples and self.m_eff > 0
         if hybrid:
+            m_arg = BASIS_PENDING if self.pending is not None else self.m_eff
             try:
                 if self.recorder is not None:
-                    _, info = c.rom_hybrid_step_taped(prev, self.Phi, self.psi, self.m_eff,
+                    _, info = c.rom_hybrid_step_taped(prev, self.Phi, self.psi, m_arg,
                                                       self.recorder.tape(k), TAPE_RECORD,
                                                       samples=self.samples, params=self.hp, out=out,
                                                       eps=self.eps)
                 else:
-                    _, info = c.rom_hybrid_step(prev, self.Phi, self.psi, self.m_eff, self.samples,
+                    _, info = c.rom_hybrid_step(prev, self.Phi, self.psi, m_arg, self.samples,
                                                 self.hp, out=out, eps=self.eps)
                 rec.update(type="hybrid", n_s=info["n_s"], l=info["l"], J=info["subiters"],
                            newton=info["newton_iters"], sweeps=info["lin_sweeps"],
@@ -123,6 +139,9 @@ class Arom:
                     raise
                 hybrid = False
                 rec["fallback"] = str(e)
+            finally:
+                self._complete()        # the step completed the update on every path
+                used["m"] = self.m_eff
         if not hybrid:
             _, info = c.hdm_step(prev, out=out)
             rec.update(type="full", n_s=c.ncell, newton=info["newton_iters"], sweeps=info["lin_sweeps"])
@@ -140,6 +159,7 @@ class Arom:
             # the basis update runs on the context's second stream while the
             # sampled sets are selected on its main stream
             c.basis_update_async(window, cfg.w, cfg.m, self.Phi, self.psi, self.sigma, cfg.tau_pod)
+            self.pending = rec
             try:
                 if sample:
                     c.sample_select(self.eps, cfg.fraction, cfg.halo, samples=self.samples, rule=cfg.rule,
@@ -148,9 +168,12 @@ class Arom:
                     rec["n_g"] = cnt["n_g"]
                     self.have_samples = cnt["n_s"] > 0
             finally:
-                self.m_eff = c.basis_update_finish()
+                # left in flight only for a next step that is hybrid and can
+                # complete it; a caller that inspects the update gets it whole
+                nxt_hybrid = (not is_full_step(k + 1, cfg.w, cfg.z) and self.have_samples and k < self.steps)
+                if on_update is not None or not self.defer_basis or not nxt_hybrid:
+                    self._complete()
             self.basis_version += 1
-            rec["m_eff"] = self.m_eff
             if on_update is not None:
                 on_update(k, rec, {"eps": self.eps, "samples": self.samples if self.have_samples else None,
                                    "window": window, "Phi": self.Phi, "psi": self.psi,
@@ -159,6 +182,10 @@ class Arom:
 
     def state(self):
         return self.slot(self.k)
+
+    def finish(self):
+        """Complete a basis update still in flight (the end of a run)."""
+        self._complete()
 
     def run(self, q0, steps, on_step=None, on_update=None, timing=False):
         self.start(q0, steps)
@@ -170,4 +197,5 @@ class Arom:
                 torch.cuda.synchronize(self.ctx.device)
                 rec["seconds"] = time.perf_counter() - t0
             records.append(rec)
+        self._complete()
         return self.slot(steps), records

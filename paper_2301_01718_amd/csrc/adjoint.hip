@@ -356,9 +356,8 @@ static hs_status transposed_solve(hs_ctx* ctx, const double* q, const hs_samples
   else
     HS_LAUNCH(ctx, adj_coef_kernel<4>, nbs, kBlock, ctx->g, q, hat, nbr, count, ctx->ncell, v, ctx->coef, ctx->rhs,
               ctx->part);
-  HS_TRY(finish_stats(ctx, nbs, 1u << kStatRho, 0u));
   unsigned long long st[kStatSlots];
-  HS_TRY(read_stats(ctx, st));
+  HS_TRY(finish_stats(ctx, nbs, 1u << kStatRho, 0u, st));
   const double rho = bits_to_double(st[kStatRho]);
   if (!std::isfinite(rho)) return ctx->fail(HS_ERR_NONFINITE, "non-finite transposed Jacobian");
   return relax_solve(ctx, s, ctx->coef, ctx->rhs, rho, kAdjointRtol, x, sweeps);

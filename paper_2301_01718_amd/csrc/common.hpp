@@ -87,7 +87,9 @@ struct hs_ctx {
   unsigned long long* stats = nullptr;   // kStatSlots
   double* part = nullptr;     // per-block partial statistics: kStatSlots x kPartCap
   int* ibuf = nullptr;        // integer scratch (ncell + 1024)
-  void* hpin = nullptr;       // pinned host readback buffer (64 KiB)
+  void* hpin = nullptr;       // host read-back buffer (64 KiB + tag word): pinned, coherent, mapped
+  void* dpin = nullptr;       // its device address
+  unsigned pin_tag = 0;       // last tag published into it
   void* hstage = nullptr;     // pinned host staging buffer for small uploads (64 KiB)
   const double** ptab = nullptr;   // device table of snapshot pointers (128 entries)
 
@@ -304,7 +306,10 @@ hs_status zero_stats(hs_ctx* ctx);
 hs_status read_stats(hs_ctx* ctx, unsigned long long* out /* kStatSlots */);
 // Reduce the per-block partials of the slots in max_mask (max) and sum_mask
 // (sum) over nb blocks into the stats slots (bit patterns of the doubles).
-hs_status finish_stats(hs_ctx* ctx, int nb, unsigned max_mask, unsigned sum_mask);
+// With out, the same launch also delivers all stats slots to the host
+// (read_stats in one step).
+hs_status finish_stats(hs_ctx* ctx, int nb, unsigned max_mask, unsigned sum_mask,
+                       unsigned long long* out = nullptr);
 inline int stat_blocks(long long n) { return blocks_for(n, kBlock, kPartCap); }
 hs_status max_abs(hs_ctx* ctx, const double* x, long long n, double* out);
 // Newton on the full mesh (s == nullptr) or on a sampled set.  primed: the
@@ -312,9 +317,10 @@ hs_status max_abs(hs_ctx* ctx, const double* x, long long n, double* out);
 // newton_first_launch on q, and {max |R|, rho} were read back (else nullptr).
 hs_status newton_solve(hs_ctx* ctx, double* q, const double* q_prev, double tol,
                        const hs_samples* s, hs_step_info* info, const double* primed = nullptr);
-// Residual, Jacobian relaxation data and the ResMax/Rho statistics at q
-// (enqueued only; read with read_stats).
-hs_status newton_first_launch(hs_ctx* ctx, const double* q, const double* q_prev, const hs_samples* s);
+// Residual, Jacobian relaxation data and the ResMax/Rho statistics at q;
+// with st all stats slots are read back as well (else enqueued only).
+hs_status newton_first_launch(hs_ctx* ctx, const double* q, const double* q_prev, const hs_samples* s,
+                              unsigned long long* st);
 // max |x| into the QMax statistics slot (enqueued only).
 hs_status max_abs_launch(hs_ctx* ctx, const double* x, long long n);
 hs_status cell_residual_norm(hs_ctx* ctx, const double* q, const double* q_prev, double* rcell,

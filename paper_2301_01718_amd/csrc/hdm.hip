@@ -15,6 +15,8 @@
 #include "physics.hpp"
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cstring>
 
 namespace hs {
@@ -35,10 +37,30 @@ __global__ void max_abs_kernel(const double* __restrict__ x, long long n, double
   if (threadIdx.x == 0) stat_part(part, kStatQMax, m);
 }
 
+// Read-backs go through a host buffer that the device writes directly
+// (pinned, coherent, mapped): one wave stores the words, fences at system
+// scope and then stores the tag; the host spins on the tag instead of waiting
+// for a copy engine and the stream's completion signal.
+constexpr size_t kPinBytes = 65536;
+
+__device__ inline void post_words(const uint32_t* src, int words, uint32_t* dst, uint32_t* tagp, unsigned tag) {
+  // a single wave: its stores are complete once the fence has waited for them
+  for (int i = threadIdx.x; i < words; i += kWave) dst[i] = src[i];
+  __threadfence_system();
+  if (threadIdx.x == 0) *(volatile uint32_t*)tagp = tag;
+}
+
+__global__ void post_kernel(const uint32_t* __restrict__ src, int words, uint32_t* dst, uint32_t* tagp,
+                            unsigned tag) {
+  post_words(src, words, dst, tagp, tag);
+}
+
 // One block: reduce the partials of the flagged slots (fixed strided order and
-// a fixed tree) and store them as bit patterns in the stats slots.
+// a fixed tree) and store them as bit patterns in the stats slots; with dst,
+// the first wave then posts all slots to the host buffer.
 __global__ void finish_stats_kernel(const double* __restrict__ part, int nb, unsigned max_mask,
-                                    unsigned sum_mask, unsigned long long* __restrict__ stats) {
+                                    unsigned sum_mask, unsigned long long* __restrict__ stats, uint32_t* dst,
+                                    uint32_t* tagp, unsigned tag) {
   __shared__ double lds[kBlock / kWave];
   for (int slot = 0; slot < kStatSlots; ++slot) {
     const bool mx = (max_mask >> slot) & 1u, sm = (sum_mask >> slot) & 1u;
@@ -51,12 +73,47 @@ __global__ void finish_stats_kernel(const double* __restrict__ part, int nb, uns
     v = mx ? block_max(v, lds) : block_sum(v, lds);
     if (threadIdx.x == 0) stats[slot] = dbits(v);
   }
+  if (dst == nullptr) return;
+  __syncthreads();
+  if (threadIdx.x < kWave)
+    post_words(reinterpret_cast<const uint32_t*>(stats), kStatSlots * 2, dst, tagp, tag);
+}
+
+static unsigned next_tag(hs_ctx* ctx) {
+  ctx->pin_tag = ctx->pin_tag + 1u == 0u ? 1u : ctx->pin_tag + 1u;
+  return ctx->pin_tag;
+}
+
+static uint32_t* pin_tag_dev(hs_ctx* ctx) {
+  return reinterpret_cast<uint32_t*>(static_cast<char*>(ctx->dpin) + kPinBytes);
+}
+
+// Spin until the tag arrives; after 20 ms fall back to a blocking wait on the
+// stream (a long queue ahead, or an error to report).
+static hs_status await_tag(hs_ctx* ctx, unsigned tag) {
+  const volatile uint32_t* t =
+      reinterpret_cast<const volatile uint32_t*>(static_cast<const char*>(ctx->hpin) + kPinBytes);
+  const auto start = std::chrono::steady_clock::now();
+  for (unsigned spin = 1;; ++spin) {
+    if (*t == tag) break;
+    if ((spin & 1023u) == 0u && std::chrono::steady_clock::now() - start > std::chrono::milliseconds(20)) {
+      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      if (*t != tag) return ctx->fail(HS_ERR_HIP, "read-back: the device did not deliver the result");
+      break;
+    }
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  return HS_OK;
 }
 
 hs_status readback(hs_ctx* ctx, const void* dsrc, size_t bytes, void* hdst) {
-  if (bytes > 65536) return ctx->fail(HS_ERR_INVALID_ARG, "readback too large");
-  HIP_TRY(ctx, hipMemcpyAsync(ctx->hpin, dsrc, bytes, hipMemcpyDeviceToHost, ctx->stream));
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  if (bytes > kPinBytes) return ctx->fail(HS_ERR_INVALID_ARG, "readback too large");
+  if (bytes % 4 != 0 || reinterpret_cast<uintptr_t>(dsrc) % 4 != 0)
+    return ctx->fail(HS_ERR_INVALID_ARG, "readback of a non-word-aligned range");
+  const unsigned tag = next_tag(ctx);
+  HS_LAUNCH(ctx, post_kernel, 1, kWave, static_cast<const uint32_t*>(dsrc), (int)(bytes / 4),
+            static_cast<uint32_t*>(ctx->dpin), pin_tag_dev(ctx), tag);
+  HS_TRY(await_tag(ctx, tag));
   std::memcpy(hdst, ctx->hpin, bytes);
   return HS_OK;
 }
@@ -91,8 +148,17 @@ hs_status read_stats(hs_ctx* ctx, unsigned long long* out) {
   return readback(ctx, ctx->stats, kStatSlots * sizeof(unsigned long long), out);
 }
 
-hs_status finish_stats(hs_ctx* ctx, int nb, unsigned max_mask, unsigned sum_mask) {
-  HS_LAUNCH(ctx, finish_stats_kernel, 1, kBlock, ctx->part, nb, max_mask, sum_mask, ctx->stats);
+hs_status finish_stats(hs_ctx* ctx, int nb, unsigned max_mask, unsigned sum_mask, unsigned long long* out) {
+  if (!out) {
+    HS_LAUNCH(ctx, finish_stats_kernel, 1, kBlock, ctx->part, nb, max_mask, sum_mask, ctx->stats, nullptr,
+              nullptr, 0u);
+    return HS_OK;
+  }
+  const unsigned tag = next_tag(ctx);
+  HS_LAUNCH(ctx, finish_stats_kernel, 1, kBlock, ctx->part, nb, max_mask, sum_mask, ctx->stats,
+            static_cast<uint32_t*>(ctx->dpin), pin_tag_dev(ctx), tag);
+  HS_TRY(await_tag(ctx, tag));
+  std::memcpy(out, ctx->hpin, kStatSlots * sizeof(unsigned long long));
   return HS_OK;
 }
 
@@ -103,9 +169,10 @@ hs_status max_abs_launch(hs_ctx* ctx, const double* x, long long n) {
 }
 
 hs_status max_abs(hs_ctx* ctx, const double* x, long long n, double* out) {
-  HS_TRY(max_abs_launch(ctx, x, n));
+  const int nb = blocks_for(n, kBlock, 1024);
+  HS_LAUNCH(ctx, max_abs_kernel, nb, kBlock, x, n, ctx->part);
   unsigned long long st[kStatSlots];
-  HS_TRY(read_stats(ctx, st));
+  HS_TRY(finish_stats(ctx, nb, 1u << kStatQMax, 0u, st));
   *out = bits_to_double(st[kStatQMax]);
   return HS_OK;
 }
@@ -227,7 +294,8 @@ __global__ void __launch_bounds__(kBlock) resjac_kernel(Grid g, const double* __
 hs_status linear_solve(hs_ctx* ctx, const hs_samples* s, double rho, double eta, double* q, int* sweeps);
 
 template <int NC>
-static hs_status resjac_launch(hs_ctx* ctx, const double* q, const double* q_prev, const hs_samples* s) {
+static hs_status resjac_launch(hs_ctx* ctx, const double* q, const double* q_prev, const hs_samples* s,
+                               unsigned long long* st) {
   const int* hat = s ? s->hat : nullptr;
   const int* nbr = s ? s->nbr : nullptr;
   const int count = s ? s->n_s : ctx->ncell;
@@ -239,12 +307,13 @@ static hs_status resjac_launch(hs_ctx* ctx, const double* q, const double* q_pre
   // list entries; writes: 4 NC x NC relaxation blocks and the NC-vector b
   HS_TRY(prof_end(ctx, HS_PROF_RESJAC,
                   (double)count * (8.0 * NC * 2 + 8.0 * (4 * NC * NC + NC) + (hat ? 4.0 * 5 : 0.0))));
-  return finish_stats(ctx, nbs, (1u << kStatResMax) | (1u << kStatRho), 0u);
+  return finish_stats(ctx, nbs, (1u << kStatResMax) | (1u << kStatRho), 0u, st);
 }
 
-hs_status newton_first_launch(hs_ctx* ctx, const double* q, const double* q_prev, const hs_samples* s) {
-  if (ctx->nc == 1) return resjac_launch<1>(ctx, q, q_prev, s);
-  return resjac_launch<4>(ctx, q, q_prev, s);
+hs_status newton_first_launch(hs_ctx* ctx, const double* q, const double* q_prev, const hs_samples* s,
+                              unsigned long long* st) {
+  if (ctx->nc == 1) return resjac_launch<1>(ctx, q, q_prev, s, st);
+  return resjac_launch<4>(ctx, q, q_prev, s, st);
 }
 
 template <int NC>
@@ -259,9 +328,8 @@ static hs_status newton_impl(hs_ctx* ctx, double* q, const double* q_prev, doubl
       rmax = primed[0];
       rho = primed[1];
     } else {
-      HS_TRY(resjac_launch<NC>(ctx, q, q_prev, s));
       unsigned long long st[kStatSlots];
-      HS_TRY(read_stats(ctx, st));
+      HS_TRY(resjac_launch<NC>(ctx, q, q_prev, s, st));
       rmax = bits_to_double(st[kStatResMax]);
       rho = bits_to_double(st[kStatRho]);
     }
@@ -336,9 +404,8 @@ static hs_status linear_solve_impl(hs_ctx* ctx, const hs_samples* s, const doubl
       last = nxt;
       k += b;
       const int nb = use_tiles(ctx, s) ? (s ? s->ntiles : ctx->ntx * ctx->nty) : blocks_for(s ? s->n_s : ctx->ncell);
-      HS_TRY(finish_stats(ctx, nb, (1u << kStatDiff) | (1u << kStatDnorm), 0u));
       unsigned long long st[kStatSlots];
-      HS_TRY(read_stats(ctx, st));
+      HS_TRY(finish_stats(ctx, nb, (1u << kStatDiff) | (1u << kStatDnorm), 0u, st));
       const double diff = bits_to_double(st[kStatDiff]);
       const double dn = bits_to_double(st[kStatDnorm]);
       if (!std::isfinite(diff)) return ctx->fail(HS_ERR_NONFINITE, "non-finite relaxation iterate");
@@ -496,8 +563,12 @@ hs_status hs_create(const hs_problem* pr, void* stream, hs_ctx** out) {
       st = ctx->fail(HS_ERR_HIP, "stream/event creation");
   }
   if (st == HS_OK) {
-    hipError_t e = hipHostMalloc(&ctx->hpin, 65536, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc(&ctx->hstage, 65536, hipHostMallocDefault);
+    hipError_t e = hipHostMalloc(&ctx->hpin, kPinBytes + 256, hipHostMallocCoherent | hipHostMallocMapped);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(&ctx->dpin, ctx->hpin, 0);
+    if (e == hipSuccess) {
+      *reinterpret_cast<volatile uint32_t*>(static_cast<char*>(ctx->hpin) + kPinBytes) = 0u;
+      e = hipHostMalloc(&ctx->hstage, 65536, hipHostMallocDefault);
+    }
     if (e != hipSuccess) st = ctx->fail(HS_ERR_OOM, "hipHostMalloc");
   }
   if (st != HS_OK) {

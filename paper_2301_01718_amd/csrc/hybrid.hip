@@ -513,7 +513,7 @@ static void filter_tile(const hs_ctx* ctx, int* tx, int* ty) {
 // One gated pass: merged (the next state), r2, keep_out; kept count and sum
 // of r2 to the statistics slots kStatCount / kStatSum (enqueued only).
 static hs_status filter_pass(hs_ctx* ctx, const double* cur, const double* q_prev, const double* r, int nord,
-                             double* merged, double* r2, uint8_t* keep_out) {
+                             double* merged, double* r2, uint8_t* keep_out, unsigned long long* st) {
   int tx, ty;
   filter_tile(ctx, &tx, &ty);
   const int ntx = (ctx->g.nx + tx - 1) / tx;
@@ -532,7 +532,7 @@ static hs_status filter_pass(hs_ctx* ctx, const double* cur, const double* q_pre
   // reads: the state, q_prev and r once; writes: merged, r2 and the decisions
   HS_TRY(prof_end(ctx, HS_PROF_FILTER,
                   (double)ctx->ncell * (8.0 * ctx->nc * 3 + 8.0 * 2 + (keep_out ? 1.0 : 0.0))));
-  return finish_stats(ctx, nb, 0u, (1u << kStatCount) | (1u << kStatSum));
+  return finish_stats(ctx, nb, 0u, (1u << kStatCount) | (1u << kStatSum), st);
 }
 
 hs_status cell_residual_launch(hs_ctx* ctx, const double* q, const double* q_prev, double* rcell, int slot) {
@@ -594,9 +594,8 @@ hs_status run_filter(hs_ctx* ctx, double* gamma, const double* q_prev, const hs_
     const int nord = hp->filter_orders[o];
     for (int it = 1; it <= hp->jfmax; ++it) {
       uint8_t* keep_out = record ? record->masks + (size_t)record->npass * ctx->ncell : nullptr;
-      HS_TRY(filter_pass(ctx, cur, q_prev, r, nord, spare, r2, keep_out));
       unsigned long long st[kStatSlots];
-      HS_TRY(read_stats(ctx, st));
+      HS_TRY(filter_pass(ctx, cur, q_prev, r, nord, spare, r2, keep_out, st));
       if (!have_sum) {
         sum_r = bits_to_double(st[kStatSum0]);
         have_sum = true;
@@ -829,8 +828,8 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const void* Phi,
     inf->subiters = j;
     if (replay) continue;
     const bool more = j < jmax;
-    if (more) HS_TRY(newton_first_launch(ctx, u, q_prev, s));
-    HS_TRY(read_stats(ctx, st));
+    if (more) HS_TRY(newton_first_launch(ctx, u, q_prev, s, st));
+    else HS_TRY(read_stats(ctx, st));
     const double dy = bits_to_double(st[kStatDy]);
     inf->dy_last = dy;
     if (!more || (j >= 2 && dy < hp->eps_y)) break;

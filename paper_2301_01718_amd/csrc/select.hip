@@ -272,6 +272,43 @@ __global__ void count_key_kernel(const double* __restrict__ eps, int n, const Rr
   if (threadIdx.x == 0 && c) atomicAdd(out, (unsigned int)c);
 }
 
+// Exclusive prefix sum of a per-thread count within its block.
+__device__ inline int block_exclusive_rank(int flag, int* wsum) {
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  int x = flag;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(x, o, kWave);
+    if (lane >= o) x += y;
+  }
+  if (lane == kWave - 1) wsum[w] = x;
+  __syncthreads();
+  int woff = 0;
+  for (int k = 0; k < w; ++k) woff += wsum[k];
+  __syncthreads();
+  return x - flag + woff;
+}
+
+// Keys whose digit is shared by many lanes of a wave (the exponent digits of
+// errors that span a few binades) are counted once per wave: up to four
+// rounds in which the first pending lane's digit is matched across the wave
+// and added with its lane count; the remaining lanes add one each.
+__device__ inline void wave_hist_add(unsigned int* h, unsigned d, bool pending) {
+  const int lane = threadIdx.x % kWave;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const unsigned long long act = __ballot(pending);
+    if (act == 0ull) return;
+    const int leader = __ffsll((long long)act) - 1;
+    const unsigned dl = __shfl(d, leader, kWave);
+    const bool match = pending && d == dl;
+    const unsigned long long mm = __ballot(match);
+    if (lane == leader) atomicAdd(&h[dl], (unsigned)__popcll(mm));
+    pending = pending && !match;
+  }
+  if (pending) atomicAdd(&h[d], 1u);
+}
+
 __global__ void radix_hist_kernel(const double* __restrict__ eps, int n, const SelectState* st, int shift,
                                   unsigned int* __restrict__ hist) {
   __shared__ unsigned int h[256];
@@ -279,40 +316,35 @@ __global__ void radix_hist_kernel(const double* __restrict__ eps, int n, const S
   __syncthreads();
   const unsigned long long himask = shift >= 56 ? 0ull : (~0ull << (shift + 8));
   const unsigned long long pre = st->prefix & himask;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const double e = eps[i];
-    if (!(e > 0.0)) continue;
+  const int stride = gridDim.x * blockDim.x;
+  // the trip count is uniform across a wave (every lane takes part in the ballots)
+  for (int base = blockIdx.x * blockDim.x; base < n; base += stride) {
+    const int i = base + threadIdx.x;
+    const double e = i < n ? eps[i] : 0.0;
     const unsigned long long key = dbits(e);
-    if ((key & himask) == pre) atomicAdd(&h[(key >> shift) & 255u], 1u);
+    const bool take = e > 0.0 && (key & himask) == pre;
+    wave_hist_add(h, (unsigned)(key >> shift) & 255u, take);
   }
   __syncthreads();
   for (int t = threadIdx.x; t < 256; t += blockDim.x)
     if (h[t]) atomicAdd(&hist[t], h[t]);
 }
 
-// One block of 256 threads: choose the digit that holds the k-th largest key.
+// One block of 256 threads, thread t on digit 255 - t: the exclusive prefix
+// over t is the count of keys with a larger digit; the thread whose bucket
+// holds the k-th largest key fixes the digit.  Clears the histogram.
 __global__ void radix_pick_kernel(SelectState* st, int shift, unsigned int* __restrict__ hist) {
-  __shared__ unsigned long long above[257];
-  const int t = threadIdx.x;   // digit t
-  if (t == 0) {
-    // suffix sums from the largest digit down (256 terms, one thread: exact and cheap)
-    unsigned long long s = 0;
-    above[256] = 0;
-    for (int d = 255; d >= 0; --d) {
-      above[d] = s;            // count of keys with digit > d
-      s += hist[d];
-    }
-  }
-  __syncthreads();
+  __shared__ int wsum[256 / kWave];
+  const int d = 255 - (int)threadIdx.x;
+  const int c = (int)hist[d];
+  const int above = block_exclusive_rank(c, wsum);
   const long long k = st->k;
-  const unsigned long long a = above[t], c = hist[t];
   __syncthreads();
-  if (c > 0 && (long long)a < k && k <= (long long)(a + c)) {
-    st->prefix |= (unsigned long long)t << shift;
-    st->k = k - (long long)a;
+  if (c > 0 && (long long)above < k && k <= (long long)above + c) {
+    st->prefix |= (unsigned long long)d << shift;
+    st->k = k - above;
   }
-  __syncthreads();
-  hist[t] = 0;
+  hist[d] = 0;
 }
 
 // gmask = key > K, emask = key == K (candidates for the remaining ties).
@@ -370,23 +402,6 @@ __global__ void scan_bsums_kernel(int* __restrict__ bsum, int nb) {
     __syncthreads();
   }
   if (threadIdx.x == 0) bsum[nb] = carry;
-}
-
-// Rank of each set flag within its block (exclusive), plus the block offset.
-__device__ inline int block_exclusive_rank(int flag, int* wsum) {
-  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-  int x = flag;
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const int y = __shfl_up(x, o, kWave);
-    if (lane >= o) x += y;
-  }
-  if (lane == kWave - 1) wsum[w] = x;
-  __syncthreads();
-  int woff = 0;
-  for (int k = 0; k < w; ++k) woff += wsum[k];
-  __syncthreads();
-  return x - flag + woff;
 }
 
 // Compaction: list[offset] = i for every set flag, pos[i] = offset or -1.
@@ -522,9 +537,13 @@ __global__ void fill_u8_kernel(uint8_t* p, int n, uint8_t v) {
   if (i < n) p[i] = v;
 }
 
-__global__ void init_state_kernel(SelectState* st, long long k) {
-  st->prefix = 0ull;
-  st->k = k;
+// One block of 256 threads: the select state and a cleared histogram.
+__global__ void init_state_kernel(SelectState* st, long long k, unsigned int* __restrict__ hist) {
+  hist[threadIdx.x] = 0u;
+  if (threadIdx.x == 0) {
+    st->prefix = 0ull;
+    st->k = k;
+  }
 }
 
 // ------------------------------------------------------------------- host
@@ -665,9 +684,8 @@ hs_status sample_select(hs_ctx* ctx, const double* eps, const hs_sample_params* 
   const int nb = blocks_for(n);
   const int nbp = blocks_for(n, kBlock, 1024);
   HS_LAUNCH(ctx, count_positive_kernel, nbp, kBlock, eps, n, ctx->part);
-  HS_TRY(finish_stats(ctx, nbp, 1u << kStatQMax, 1u << kStatCount));
   unsigned long long st[kStatSlots];
-  HS_TRY(read_stats(ctx, st));
+  HS_TRY(finish_stats(ctx, nbp, 1u << kStatQMax, 1u << kStatCount, st));
   const long long npos = (long long)bits_to_double(st[kStatCount]);
   const double emx = bits_to_double(st[kStatQMax]);
   long long ng;
@@ -685,9 +703,7 @@ hs_status sample_select(hs_ctx* ctx, const double* eps, const hs_sample_params* 
   if (ng == 0) {
     HS_LAUNCH(ctx, fill_u8_kernel, nb, kBlock, s->gmask, n, (uint8_t)0);
   } else {
-    HS_LAUNCH(ctx, fill_u8_kernel, blocks_for(256 * sizeof(unsigned int)), kBlock,
-              reinterpret_cast<uint8_t*>(hist), (int)(256 * sizeof(unsigned int)), (uint8_t)0);
-    HS_LAUNCH(ctx, init_state_kernel, 1, 1, state, ng);
+    HS_LAUNCH(ctx, init_state_kernel, 1, 256, state, ng, hist);
     for (int shift = 56; shift >= 0; shift -= 8) {
       HS_LAUNCH(ctx, radix_hist_kernel, blocks_for(n, kBlock, 2048), kBlock, eps, n, state, shift, hist);
       HS_LAUNCH(ctx, radix_pick_kernel, 1, 256, state, shift, hist);

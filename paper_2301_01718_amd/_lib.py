@@ -165,6 +165,19 @@ def _with_precision(params, prec):
     return hp
 
 
+class SnapshotTable:
+    """Device addresses of a fixed list of snapshots of one context (checked
+    when built; the tensors are kept alive with it)."""
+
+    __slots__ = ("ctx", "arr", "count", "_keep")
+
+    def __init__(self, ctx, snaps):
+        self.ctx = ctx
+        self._keep = list(snaps)
+        self.arr = (P * len(self._keep))(*[P(ctx._in(t).data_ptr()) for t in self._keep])
+        self.count = len(self._keep)
+
+
 class Context:
     """One problem on one device and stream.  Tensors are float64 (states),
     int32 (cell lists) or uint8 (masks), contiguous, on ``device``."""
@@ -285,20 +298,32 @@ class Context:
         return eps, y
 
     # ------------------------------------------------------------- basis
+    def snapshot_table(self, snaps):
+        """The device addresses of a list of snapshots, checked once; pass it
+        to basis_update(_async) in place of the list while the tensors live."""
+        return SnapshotTable(self, snaps)
+
+    def _snap_array(self, snaps):
+        if isinstance(snaps, SnapshotTable):
+            if snaps.ctx is not self:
+                raise ValueError("snapshot table of another context")
+            return snaps.arr, snaps.count
+        return (P * len(snaps))(*[P(self._in(s).data_ptr()) for s in snaps]), len(snaps)
+
     def basis_update(self, snaps, w, m, Phi_out, psi_out, sigma_out, tau_pod=1e-4):
         """Phi_out float64: FP64 basis; float32: the FP32 master copy (HS_MIXED_FP32)."""
         precision = self._basis(Phi_out, m)
-        arr = (P * len(snaps))(*[P(self._in(s).data_ptr()) for s in snaps])
+        arr, count = self._snap_array(snaps)
         me = I32(0)
-        self._check(lib().basis_update(self.h, arr, len(snaps), w, m, tau_pod, precision, _ptr(Phi_out),
+        self._check(lib().basis_update(self.h, arr, count, w, m, tau_pod, precision, _ptr(Phi_out),
                                        _ptr(self._in(psi_out)), _ptr(sigma_out), ctypes.byref(me)))
         return me.value
 
     def basis_update_async(self, snaps, w, m, Phi_out, psi_out, sigma_out, tau_pod=1e-4):
         """Enqueue the update on the context's own stream; finish with basis_update_finish."""
         precision = self._basis(Phi_out, m)
-        arr = (P * len(snaps))(*[P(self._in(s).data_ptr()) for s in snaps])
-        self._check(lib().basis_update_async(self.h, arr, len(snaps), w, m, tau_pod, precision, _ptr(Phi_out),
+        arr, count = self._snap_array(snaps)
+        self._check(lib().basis_update_async(self.h, arr, count, w, m, tau_pod, precision, _ptr(Phi_out),
                                              _ptr(self._in(psi_out)), _ptr(sigma_out)))
         self._pending = True
 

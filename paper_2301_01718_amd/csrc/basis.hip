@@ -26,10 +26,16 @@ namespace hs {
 // small register footprint lets about six waves per SIMD hide the latency.
 constexpr int kWaveRows = 16;                 // rows per wave chunk
 
-// Snapshot pointers come from a device table, so the compiler cannot tell
-// they address global memory and would use flat loads, which also count
-// against the LDS wait counter.  The cast makes them global loads.
+// Snapshot pointers come from a table, so the compiler cannot tell they
+// address global memory and would use flat loads, which also count against
+// the LDS wait counter.  The cast makes them global loads.
 typedef const __attribute__((address_space(1))) double* gptr_t;
+
+// The window's snapshot addresses, passed by value as a kernel argument (no
+// upload of a device table before the launch).
+struct SnapTable {
+  const double* p[kMaxBasis + 1];
+};
 
 template <int PER>
 struct LaneSnaps {
@@ -38,12 +44,12 @@ struct LaneSnaps {
 };
 
 template <int PER>
-__device__ inline void lane_snaps_init(const double* const* __restrict__ snaps, int nsnap, LaneSnaps<PER>& L) {
+__device__ inline void lane_snaps_init(const SnapTable& snaps, int nsnap, LaneSnaps<PER>& L) {
   const int g = (threadIdx.x % kWave) / 16;
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int j = g + 4 * i;
-    L.p[i] = (gptr_t)snaps[j < nsnap ? j : nsnap - 1];
+    L.p[i] = (gptr_t)snaps.p[j < nsnap ? j : nsnap - 1];
   }
 }
 
@@ -118,7 +124,7 @@ __device__ inline void wave_lds_fence() {
 // Block: 4 waves; dynamic LDS: 4 regions of kWaveRows x (wp + 1) (the cross-
 // wave sum reuses them at the end).
 template <int NS>
-__global__ void __launch_bounds__(256) window_gram_kernel(const double* const* __restrict__ snaps, int nsnap,
+__global__ void __launch_bounds__(256) window_gram_kernel(const SnapTable snaps, int nsnap,
                                                           int w, long long n, int wp, double* __restrict__ psi_new,
                                                           double* __restrict__ part) {
   extern __shared__ double sh[];
@@ -429,7 +435,7 @@ __global__ void __launch_bounds__(256) basis_eig_kernel(const double* __restrict
 // meff is read from device memory (the eigen kernel's output), so the pass can
 // be enqueued before the host learns m_eff.
 template <int NS, typename TP>
-__global__ void __launch_bounds__(256) basis_form_kernel(const double* const* __restrict__ snaps, int nsnap,
+__global__ void __launch_bounds__(256) basis_form_kernel(const SnapTable snaps, int nsnap,
                                                          int w, long long n, const double* __restrict__ T,
                                                          int mp, int wp, const int* __restrict__ meff_d,
                                                          TP* __restrict__ Phi) {
@@ -486,10 +492,8 @@ static hs_status basis_enqueue(hs_ctx* ctx, const double* const* snaps, int32_t 
   if (ctx->n >= (1LL << 29)) return ctx->fail(HS_ERR_SHAPE, "basis_update: more than 2^29 entries per snapshot");
   for (int j = 0; j < nsnap; ++j)
     if (!snaps[j]) return HS_ERR_INVALID_ARG;
-  // pointer table to device memory through the pinned staging area
-  std::memcpy(ctx->hstage, snaps, nsnap * sizeof(double*));
-  HIP_TRY(ctx, hipMemcpyAsync(ctx->ptab, ctx->hstage, nsnap * sizeof(double*), hipMemcpyHostToDevice, ctx->stream));
-  const double* const* tab = const_cast<const double* const*>(ctx->ptab);
+  SnapTable tab{};
+  for (int j = 0; j < nsnap; ++j) tab.p[j] = snaps[j];
   const long long n = ctx->n;
   const int wp = (w + 15) / 16 * 16;
   const int mp = (m + 15) / 16 * 16;

@@ -90,8 +90,6 @@ struct hs_ctx {
   void* hpin = nullptr;       // host read-back buffer (64 KiB + tag word): pinned, coherent, mapped
   void* dpin = nullptr;       // its device address
   unsigned pin_tag = 0;       // last tag published into it
-  void* hstage = nullptr;     // pinned host staging buffer for small uploads (64 KiB)
-  const double** ptab = nullptr;   // device table of snapshot pointers (128 entries)
 
   // kernel timing (hs_prof_enable)
   int prof_class = 0;

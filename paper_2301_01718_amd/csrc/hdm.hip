@@ -481,7 +481,7 @@ hs_status hs_destroy(hs_ctx* ctx) {
   if (!ctx) return HS_ERR_INVALID_ARG;
   void* bufs[] = {ctx->u,    ctx->R,     ctx->rhs,    ctx->d0,  ctx->d1,    ctx->coef, ctx->rho,
                   ctx->gf,   ctx->gtmp,  ctx->rcell,  ctx->rcell2, ctx->red, ctx->small, ctx->stats,
-                  ctx->ibuf, (void*)ctx->ptab, ctx->part, ctx->adj};
+                  ctx->ibuf, ctx->part, ctx->adj};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
@@ -491,7 +491,6 @@ hs_status hs_destroy(hs_ctx* ctx) {
   }
   if (ctx->aux_ready) (void)hipEventDestroy(ctx->aux_ready);
   if (ctx->hpin) (void)hipHostFree(ctx->hpin);
-  if (ctx->hstage) (void)hipHostFree(ctx->hstage);
   delete ctx;
   return HS_OK;
 }
@@ -554,7 +553,6 @@ hs_status hs_create(const hs_problem* pr, void* stream, hs_ctx** out) {
   A((void**)&ctx->small, 16 * kMaxBasis * kMaxBasis * 8);
   A((void**)&ctx->stats, kStatSlots * 8);
   A((void**)&ctx->ibuf, (NC + 8192) * 4);
-  A((void**)&ctx->ptab, 128 * sizeof(double*));
   A((void**)&ctx->adj, N * 8);
   A((void**)&ctx->part, (size_t)kStatSlots * kPartCap * 8);
   if (st == HS_OK) {
@@ -565,10 +563,7 @@ hs_status hs_create(const hs_problem* pr, void* stream, hs_ctx** out) {
   if (st == HS_OK) {
     hipError_t e = hipHostMalloc(&ctx->hpin, kPinBytes + 256, hipHostMallocCoherent | hipHostMallocMapped);
     if (e == hipSuccess) e = hipHostGetDevicePointer(&ctx->dpin, ctx->hpin, 0);
-    if (e == hipSuccess) {
-      *reinterpret_cast<volatile uint32_t*>(static_cast<char*>(ctx->hpin) + kPinBytes) = 0u;
-      e = hipHostMalloc(&ctx->hstage, 65536, hipHostMallocDefault);
-    }
+    if (e == hipSuccess) *reinterpret_cast<volatile uint32_t*>(static_cast<char*>(ctx->hpin) + kPinBytes) = 0u;
     if (e != hipSuccess) st = ctx->fail(HS_ERR_OOM, "hipHostMalloc");
   }
   if (st != HS_OK) {

@@ -69,6 +69,7 @@ class Arom:
         stride = c.n + self.RING_STAGGER
         self._ring_buf = torch.empty(nslot * stride, dtype=torch.float64, device=c.device)
         self.ring = [self._ring_buf[j * stride: j * stride + c.n] for j in range(nslot)]
+        self._tables = {}   # (first slot, length) -> the window's snapshot table
         # the basis: FP64, or its FP32 master copy in the mixed mode
         phi_dtype = torch.float32 if cfg.precision == MIXED_FP32 else torch.float64
         self.Phi = torch.zeros(cfg.m * c.n, dtype=phi_dtype, device=c.device)
@@ -158,7 +159,11 @@ class Arom:
             window = [self.slot(j) for j in range(lo, k + 1)]
             # the basis update runs on the context's second stream while the
             # sampled sets are selected on its main stream
-            c.basis_update_async(window, cfg.w, cfg.m, self.Phi, self.psi, self.sigma, cfg.tau_pod)
+            key = (lo % (cfg.w + 2), len(window))
+            table = self._tables.get(key)
+            if table is None:
+                table = self._tables[key] = c.snapshot_table(window)
+            c.basis_update_async(table, cfg.w, cfg.m, self.Phi, self.psi, self.sigma, cfg.tau_pod)
             self.pending = rec
             try:
                 if sample:

@@ -62,21 +62,34 @@ __global__ void finish_stats_kernel(const double* __restrict__ part, int nb, uns
                                     unsigned sum_mask, unsigned long long* __restrict__ stats, uint32_t* dst,
                                     uint32_t* tagp, unsigned tag) {
   __shared__ double lds[kBlock / kWave];
-  for (int slot = 0; slot < kStatSlots; ++slot) {
-    const bool mx = (max_mask >> slot) & 1u, sm = (sum_mask >> slot) & 1u;
-    if (!mx && !sm) continue;
-    double v = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+  __shared__ unsigned long long sv[kStatSlots];   // all slots, as posted
+  if (threadIdx.x < kStatSlots) sv[threadIdx.x] = stats[threadIdx.x];
+  const unsigned mask = max_mask | sum_mask;
+  // the partials of every flagged slot are loaded together (per slot the
+  // order is the strided one and the tree below is fixed)
+  double v[kStatSlots];
+#pragma unroll
+  for (int slot = 0; slot < kStatSlots; ++slot) v[slot] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+#pragma unroll
+    for (int slot = 0; slot < kStatSlots; ++slot) {
+      if (!((mask >> slot) & 1u)) continue;
       const double x = part[slot * kPartCap + b];
-      v = mx ? fmax(v, x) : v + x;
+      v[slot] = ((max_mask >> slot) & 1u) ? fmax(v[slot], x) : v[slot] + x;
     }
-    v = mx ? block_max(v, lds) : block_sum(v, lds);
-    if (threadIdx.x == 0) stats[slot] = dbits(v);
+  }
+#pragma unroll
+  for (int slot = 0; slot < kStatSlots; ++slot) {
+    if (!((mask >> slot) & 1u)) continue;
+    const double r = ((max_mask >> slot) & 1u) ? block_max(v[slot], lds) : block_sum(v[slot], lds);
+    if (threadIdx.x == 0) {
+      stats[slot] = dbits(r);
+      sv[slot] = dbits(r);
+    }
   }
   if (dst == nullptr) return;
   __syncthreads();
-  if (threadIdx.x < kWave)
-    post_words(reinterpret_cast<const uint32_t*>(stats), kStatSlots * 2, dst, tagp, tag);
+  if (threadIdx.x < kWave) post_words(reinterpret_cast<const uint32_t*>(sv), kStatSlots * 2, dst, tagp, tag);
 }
 
 static unsigned next_tag(hs_ctx* ctx) {

@@ -309,6 +309,11 @@ __device__ inline void wave_hist_add(unsigned int* h, unsigned d, bool pending) 
   if (pending) atomicAdd(&h[d], 1u);
 }
 
+// The global histogram has kHistCopies copies, a block adding into copy
+// blockIdx % kHistCopies: the blocks' additions to a common digit (all the
+// keys of one binade) would otherwise serialise on one address.
+constexpr int kHistCopies = 8;
+
 __global__ void radix_hist_kernel(const double* __restrict__ eps, int n, const SelectState* st, int shift,
                                   unsigned int* __restrict__ hist) {
   __shared__ unsigned int h[256];
@@ -326,17 +331,20 @@ __global__ void radix_hist_kernel(const double* __restrict__ eps, int n, const S
     wave_hist_add(h, (unsigned)(key >> shift) & 255u, take);
   }
   __syncthreads();
+  unsigned int* copy = hist + (blockIdx.x % kHistCopies) * 256;
   for (int t = threadIdx.x; t < 256; t += blockDim.x)
-    if (h[t]) atomicAdd(&hist[t], h[t]);
+    if (h[t]) atomicAdd(&copy[t], h[t]);
 }
 
 // One block of 256 threads, thread t on digit 255 - t: the exclusive prefix
 // over t is the count of keys with a larger digit; the thread whose bucket
-// holds the k-th largest key fixes the digit.  Clears the histogram.
+// holds the k-th largest key fixes the digit.  Clears the histogram copies.
 __global__ void radix_pick_kernel(SelectState* st, int shift, unsigned int* __restrict__ hist) {
   __shared__ int wsum[256 / kWave];
   const int d = 255 - (int)threadIdx.x;
-  const int c = (int)hist[d];
+  int c = 0;
+#pragma unroll
+  for (int k = 0; k < kHistCopies; ++k) c += (int)hist[k * 256 + d];
   const int above = block_exclusive_rank(c, wsum);
   const long long k = st->k;
   __syncthreads();
@@ -344,7 +352,8 @@ __global__ void radix_pick_kernel(SelectState* st, int shift, unsigned int* __re
     st->prefix |= (unsigned long long)d << shift;
     st->k = k - above;
   }
-  hist[d] = 0;
+#pragma unroll
+  for (int k = 0; k < kHistCopies; ++k) hist[k * 256 + d] = 0u;
 }
 
 // gmask = key > K, emask = key == K (candidates for the remaining ties).
@@ -537,9 +546,10 @@ __global__ void fill_u8_kernel(uint8_t* p, int n, uint8_t v) {
   if (i < n) p[i] = v;
 }
 
-// One block of 256 threads: the select state and a cleared histogram.
+// One block of 256 threads: the select state and cleared histogram copies.
 __global__ void init_state_kernel(SelectState* st, long long k, unsigned int* __restrict__ hist) {
-  hist[threadIdx.x] = 0u;
+#pragma unroll
+  for (int c = 0; c < kHistCopies; ++c) hist[c * 256 + threadIdx.x] = 0u;
   if (threadIdx.x == 0) {
     st->prefix = 0ull;
     st->k = k;

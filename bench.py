@@ -121,6 +121,42 @@ def residual_kernels(prob, q, q_prev, seed):
     return res
 
 
+STEP_CLASSES = ("sweep", "resjac", "filter", "recon", "basis_gram", "basis_form")
+
+
+def step_kernel_rates(prob, q0, wl, k_start, steps):
+    """Every kernel class of the hybrid step on the real path: the same
+    trajectory is replayed up to the first timed step once per class, and the
+    class is timed (HIP events on the stream it runs on) over the same timed
+    steps.  A measured region is one launch (a linear solve's sweeps: the
+    launches of one solve).  us_per_step is the class's time per step; the
+    basis classes run on the second stream, beside the main one."""
+    import torch
+    import paper_2301_01718_amd.driver as D
+    cfg = D.AromConfig(w=wl.w, m=wl.m, z=wl.z, fraction=wl.frac, halo=wl.halo)
+    drv = D.Arom(prob, cfg)
+    c = drv.ctx
+    out = {}
+    for cls in STEP_CLASSES:
+        drv.start(torch.from_numpy(q0).to(c.device), wl.steps)
+        while drv.k < k_start:
+            drv.advance()
+        drv.finish()
+        torch.cuda.synchronize(c.device)
+        c.prof_enable(cls)
+        for i in range(steps):
+            drv.advance()
+        drv.finish()
+        torch.cuda.synchronize(c.device)
+        ms, n, by = c.prof_read()
+        c.prof_enable(0)
+        if n:
+            gbs = (by / n) / (ms / n * 1e-3) / 1e9
+            out[cls] = {"regions_per_step": n / steps, "avg_region_us": 1e3 * ms / n, "us_per_step": 1e3 * ms / steps,
+                        "bytes_per_region": by / n, "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+    return out
+
+
 def cpu_baseline(prob, wl, snap):
     """Time the oracle on one hybrid step + its sampling + its basis update."""
     import numpy as np
@@ -301,6 +337,8 @@ def main():
     log("residual kernel rates ...")
     prev_state = drv.slot(drv.k - 1).clone()
     resk = residual_kernels(prob, drv.state(), prev_state, args.seed)
+    log("kernel classes of the timed steps ...")
+    stepk = step_kernel_rates(prob, q0, wl, recs[0]["k"] - 1, args.steps)
 
     if args.copy_probe:
         a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
@@ -342,6 +380,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "residual_kernels": resk,
+        "step_kernels": stepk,
         "cell_updates_per_s": prob.ncell * args.steps / elapsed,
         "hybrid_step_ms": float(np.median(hyb)) if hyb else None,
         "full_step_ms": 1e3 * t_H,

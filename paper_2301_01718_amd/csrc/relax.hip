@@ -19,12 +19,22 @@
 
 namespace hs {
 
-template <int NC, int TSX, int TSY, int S>
+// Threads per tile of the scalar 2D kernels.  A sampled set activates a few
+// hundred 16 x 16 tiles, fewer workgroups than the chip holds: 512 threads
+// (two region cells each) give a launch twice the waves of 256 (sampled-set
+// sweeps 367 -> 306 us per hybrid step on 1024^2).  The full mesh's 32 x 32
+// tiles take 1024 threads (three region cells each, 60 registers instead of
+// 177; full step 0.42 -> 0.37 ms).  Euler's 4 x 4 blocks keep 256 threads
+// (more threads per tile leave fewer registers per thread and spill).
+constexpr int kSweepThreadsSet = 512;
+constexpr int kSweepThreadsMesh = 1024;
+
+template <int NC, int TSX, int TSY, int S, int NT>
 struct TileCfg {
   static constexpr int RW = TSX + 2 * S;
   static constexpr int RH = TSY == 1 ? 1 : TSY + 2 * S;
   static constexpr int R = RW * RH;
-  static constexpr int CPT = (R + kBlock - 1) / kBlock;   // region cells per thread
+  static constexpr int CPT = (R + NT - 1) / NT;   // region cells per thread
 };
 
 // tiles: active tile ids (nullptr: tile = blockIdx.x); pos/nbr: compact index
@@ -32,17 +42,17 @@ struct TileCfg {
 // xin: iterate before the launch (compact layout x[a * cap + p]); the result
 // goes to xout, or is added to the state q when q != nullptr.  With record,
 // max |x_last - x_prev| and max |x_last| of the tile go to the statistics.
-template <int NC, int TSX, int TSY, int S, bool COEF_REG>
-__global__ void __launch_bounds__(kBlock) tile_sweep_kernel(
+template <int NC, int TSX, int TSY, int S, bool COEF_REG, int NT>
+__global__ void __launch_bounds__(NT) tile_sweep_kernel(
     Grid g, const int* __restrict__ tiles, int ntx, const int* __restrict__ pos, const int* __restrict__ nbr,
     int cap, const double* __restrict__ coef, const double* __restrict__ rhs, const double* __restrict__ xin,
     double* __restrict__ xout, double* __restrict__ q, int nsw, int record, double* __restrict__ part) {
-  using C = TileCfg<NC, TSX, TSY, S>;
+  using C = TileCfg<NC, TSX, TSY, S, NT>;
   constexpr int RW = C::RW, RH = C::RH, R = C::R, CPT = C::CPT;
   constexpr bool ONE_D = TSY == 1;
   constexpr int NDIR = ONE_D ? 2 : 4;
   __shared__ double xs[2][NC][R];
-  __shared__ double lds[kBlock / kWave];
+  __shared__ double lds[NT / kWave];
   const int tile = tiles ? tiles[blockIdx.x] : (int)blockIdx.x;
   const int tx = tile % ntx, ty = tile / ntx;
   const int i0 = tx * TSX - S, j0 = ONE_D ? 0 : ty * TSY - S;
@@ -60,7 +70,7 @@ __global__ void __launch_bounds__(kBlock) tile_sweep_kernel(
   double cf[COEF_REG ? CPT : 1][COEF_REG ? 4 * NC * NC : 1];
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
-    const int r = threadIdx.x + c * kBlock;
+    const int r = threadIdx.x + c * NT;
     int cell = -1;
     if (r < R) {
       const int rx = r % RW, ry = r / RW;
@@ -114,7 +124,7 @@ __global__ void __launch_bounds__(kBlock) tile_sweep_kernel(
   }
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
-    const int r = threadIdx.x + c * kBlock;
+    const int r = threadIdx.x + c * NT;
     if (r >= R) continue;
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
@@ -129,7 +139,7 @@ __global__ void __launch_bounds__(kBlock) tile_sweep_kernel(
   // staged region (at the region edge a cell's value is no longer needed).
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
-    const int r = threadIdx.x + c * kBlock;
+    const int r = threadIdx.x + c * NT;
     const int rx = r % RW, ry = r / RW;
     unsigned v = vmask[c];
     if (rx == 0) v &= ~1u;
@@ -149,7 +159,7 @@ __global__ void __launch_bounds__(kBlock) tile_sweep_kernel(
   for (int k = 0; k < nsw; ++k) {
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
-      const int r = threadIdx.x + c * kBlock;
+      const int r = threadIdx.x + c * NT;
       if (r >= R) continue;
       const int pp = pidx[c] < 0 ? 0 : pidx[c];
       double acc[NC];
@@ -187,7 +197,7 @@ __global__ void __launch_bounds__(kBlock) tile_sweep_kernel(
   double diff = 0.0, dn = 0.0;
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
-    const int r = threadIdx.x + c * kBlock;
+    const int r = threadIdx.x + c * NT;
     if (r >= R || pidx[c] < 0) continue;
     const int rx = r % RW, ry = r / RW;
     const int li = rx - S, lj = ONE_D ? 0 : ry - S;
@@ -286,10 +296,10 @@ __global__ void add_list_kernel(Grid g, const int* __restrict__ hat, int count, 
 }
 
 // ------------------------------------------------------------------- host
-template <int NC, int TSX, int TSY, int S, bool CR>
+template <int NC, int TSX, int TSY, int S, bool CR, int NT = kBlock>
 static hs_status launch_tiles(hs_ctx* ctx, const hs_samples* s, int ntiles, const double* coef,
                               const double* rhs, const double* xin, double* xout, double* q, int k, bool record) {
-  HS_LAUNCH(ctx, (tile_sweep_kernel<NC, TSX, TSY, S, CR>), ntiles, kBlock, ctx->g, s ? s->tiles : nullptr,
+  HS_LAUNCH(ctx, (tile_sweep_kernel<NC, TSX, TSY, S, CR, NT>), ntiles, NT, ctx->g, s ? s->tiles : nullptr,
             s ? ctx->sntx : ctx->ntx, s ? s->pos : nullptr, s ? s->nbr : nullptr, ctx->ncell, coef, rhs, xin,
             xout, q, k, record ? 1 : 0, ctx->part);
   return HS_OK;
@@ -343,9 +353,9 @@ hs_status relax_sweeps(hs_ctx* ctx, const hs_samples* s, const double* coef, con
       else if (g.kind == HS_BURGERS_1D)
         HS_TRY((launch_tiles<1, 1024, 1, 8, true>(ctx, s, ntiles, coef, rhs, in, out, qq, k, rec)));
       else if (NC == 1 && s)
-        HS_TRY((launch_tiles<1, 16, 16, 8, true>(ctx, s, ntiles, coef, rhs, in, out, qq, k, rec)));
+        HS_TRY((launch_tiles<1, 16, 16, 8, true, kSweepThreadsSet>(ctx, s, ntiles, coef, rhs, in, out, qq, k, rec)));
       else if (NC == 1)
-        HS_TRY((launch_tiles<1, 32, 32, 8, true>(ctx, s, ntiles, coef, rhs, in, out, qq, k, rec)));
+        HS_TRY((launch_tiles<1, 32, 32, 8, true, kSweepThreadsMesh>(ctx, s, ntiles, coef, rhs, in, out, qq, k, rec)));
       else
         HS_TRY((launch_tiles<4, 16, 16, 4, false>(ctx, s, ntiles, coef, rhs, in, out, qq, k, rec)));
     } else {

@@ -40,6 +40,7 @@ enum StatSlot : int {
   kStatDy = 10,        // ||y_j - y_{j-1}|| of the last subiteration
   kStatSum0 = 11,      // l1 sum of the cell residual norms before a filter order
   kStatSum = 12,       // the same after a filter pass
+  kStatSweeps = 13,    // sweeps of the Newton correction decided on the device (integer; -1: batch form)
   kStatSlots = 16
 };
 
@@ -266,6 +267,15 @@ __device__ inline void stat_part(double* part, int slot, double v) {
   part[slot * kPartCap + blockIdx.x] = v;
 }
 
+// Read-back to the host buffer (pinned, coherent, mapped): one wave stores the
+// words, fences at system scope (its stores are complete once the fence has
+// waited for them) and then stores the tag the host spins on.
+__device__ inline void post_words(const uint32_t* src, int words, uint32_t* dst, uint32_t* tagp, unsigned tag) {
+  for (int i = threadIdx.x; i < words; i += kWave) dst[i] = src[i];
+  __threadfence_system();
+  if (threadIdx.x == 0) *(volatile uint32_t*)tagp = tag;
+}
+
 // ---------------------------------------------------------- grid helpers
 // Neighbour of cell (i, j) across a face.  dir: 0 = W, 1 = E, 2 = S, 3 = N.
 // Returns the neighbour cell, the cell itself for a zeroth-order-extrapolation
@@ -339,6 +349,29 @@ hs_status relax_solve(hs_ctx* ctx, const hs_samples* s, const double* coef, cons
 // record, the last sweep reports max |x_k - x_{k-1}| and max |x_k|.
 hs_status relax_sweeps(hs_ctx* ctx, const hs_samples* s, const double* coef, const double* rhs,
                        const double* xin, int nsweeps, double* q, bool record, const double** xlast);
+// The Newton decision taken by the first tiled sweep launch of an iteration
+// (scalar problems): it reduces the residual/Jacobian partials (ResMax, Rho),
+// tests convergence, chooses the sweep count of the correction exactly as the
+// host would (inexact Newton, rho^nsw <= eta), runs the first sweeps of it and
+// posts the stats (with kStatSweeps) to the host; the host then enqueues the
+// remaining sweeps.  total <= 0 (converged, non-finite, or the batch form):
+// the launch changes nothing but the stats.
+struct NewtonCtrl {
+  const double* part = nullptr;   // nullptr: an ordinary launch
+  int nb = 0;                     // resjac blocks
+  double tol = 0.0, scale = 1.0, lin_rtol = 0.0;
+  int lin_maxit = 0;
+  unsigned long long* stats = nullptr;
+  uint32_t* dst = nullptr;
+  uint32_t* tagp = nullptr;
+  unsigned tag = 0;
+};
+// Whether the Newton decision can run in the first sweep launch on s.
+bool newton_ctrl_ok(const hs_ctx* ctx, const hs_samples* s);
+// That launch: sweeps from x_1 = rhs into ctx->d0, or onto q when they are all.
+hs_status relax_first_ctrl(hs_ctx* ctx, const hs_samples* s, double* q, const NewtonCtrl& c);
+// Algorithmic bytes of one sweep launch on s (nullptr: the full mesh).
+double sweep_launch_bytes(const hs_ctx* ctx, const hs_samples* s);
 // Tile shape and sweeps per launch of the full mesh (sampled = false) or of
 // sampled sets; set_tile_geometry fills both into the context.
 void tile_geometry(const hs_problem* pr, int nc, bool sampled, int* tx, int* ty, int* s);

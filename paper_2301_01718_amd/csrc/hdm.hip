@@ -43,13 +43,6 @@ __global__ void max_abs_kernel(const double* __restrict__ x, long long n, double
 // for a copy engine and the stream's completion signal.
 constexpr size_t kPinBytes = 65536;
 
-__device__ inline void post_words(const uint32_t* src, int words, uint32_t* dst, uint32_t* tagp, unsigned tag) {
-  // a single wave: its stores are complete once the fence has waited for them
-  for (int i = threadIdx.x; i < words; i += kWave) dst[i] = src[i];
-  __threadfence_system();
-  if (threadIdx.x == 0) *(volatile uint32_t*)tagp = tag;
-}
-
 __global__ void post_kernel(const uint32_t* __restrict__ src, int words, uint32_t* dst, uint32_t* tagp,
                             unsigned tag) {
   post_words(src, words, dst, tagp, tag);
@@ -308,7 +301,7 @@ hs_status linear_solve(hs_ctx* ctx, const hs_samples* s, double rho, double eta,
 
 template <int NC>
 static hs_status resjac_launch(hs_ctx* ctx, const double* q, const double* q_prev, const hs_samples* s,
-                               unsigned long long* st) {
+                               unsigned long long* st, bool finish = true) {
   const int* hat = s ? s->hat : nullptr;
   const int* nbr = s ? s->nbr : nullptr;
   const int count = s ? s->n_s : ctx->ncell;
@@ -320,7 +313,39 @@ static hs_status resjac_launch(hs_ctx* ctx, const double* q, const double* q_pre
   // list entries; writes: 4 NC x NC relaxation blocks and the NC-vector b
   HS_TRY(prof_end(ctx, HS_PROF_RESJAC,
                   (double)count * (8.0 * NC * 2 + 8.0 * (4 * NC * NC + NC) + (hat ? 4.0 * 5 : 0.0))));
+  if (!finish) return HS_OK;
   return finish_stats(ctx, nbs, (1u << kStatResMax) | (1u << kStatRho), 0u, st);
+}
+
+// One Newton iteration's residual/Jacobian whose decision is taken on the
+// device by the first sweep launch (NewtonCtrl): that launch runs while the
+// host reads the decision back.  *total: the correction's sweep count (<= 0:
+// no sweeps ran).
+template <int NC>
+static hs_status resjac_ctrl(hs_ctx* ctx, double* q, const double* q_prev, double tol, const hs_samples* s,
+                             unsigned long long* st, int* total) {
+  HS_TRY(resjac_launch<NC>(ctx, q, q_prev, s, nullptr, false));
+  NewtonCtrl c;
+  c.part = ctx->part;
+  c.nb = stat_blocks(s ? s->n_s : ctx->ncell);
+  c.tol = tol;
+  c.scale = std::max(1.0, tol / ctx->p.newton_rtol);
+  c.lin_rtol = ctx->p.lin_rtol;
+  c.lin_maxit = ctx->p.lin_maxit;
+  c.stats = ctx->stats;
+  c.dst = static_cast<uint32_t*>(ctx->dpin);
+  c.tagp = pin_tag_dev(ctx);
+  c.tag = next_tag(ctx);
+  const size_t pidx = ctx->prof_bytes.size();
+  HS_TRY(prof_begin(ctx, HS_PROF_SWEEP));
+  HS_TRY(relax_first_ctrl(ctx, s, q, c));
+  HS_TRY(prof_end(ctx, HS_PROF_SWEEP, 0.0));
+  HS_TRY(await_tag(ctx, c.tag));
+  std::memcpy(st, ctx->hpin, kStatSlots * sizeof(unsigned long long));
+  *total = (int)(long long)st[kStatSweeps];
+  // a launch that ran sweeps moved a launch's algorithmic bytes
+  if (*total > 0 && ctx->prof_bytes.size() > pidx) ctx->prof_bytes[pidx] = sweep_launch_bytes(ctx, s);
+  return HS_OK;
 }
 
 hs_status newton_first_launch(hs_ctx* ctx, const double* q, const double* q_prev, const hs_samples* s,
@@ -335,14 +360,17 @@ static hs_status newton_impl(hs_ctx* ctx, double* q, const double* q_prev, doubl
   const int maxit = ctx->p.newton_maxit;
   const double lin_rtol = ctx->p.lin_rtol;
   int sweeps_total = 0;
+  const bool ctrl = newton_ctrl_ok(ctx, s);
   for (int it = 0;; ++it) {
     double rmax, rho;
+    int dev_total = 0;
     if (it == 0 && primed) {
       rmax = primed[0];
       rho = primed[1];
     } else {
       unsigned long long st[kStatSlots];
-      HS_TRY(resjac_launch<NC>(ctx, q, q_prev, s, st));
+      if (ctrl) HS_TRY(resjac_ctrl<NC>(ctx, q, q_prev, tol, s, st, &dev_total));
+      else HS_TRY(resjac_launch<NC>(ctx, q, q_prev, s, st));
       rmax = bits_to_double(st[kStatResMax]);
       rho = bits_to_double(st[kStatRho]);
     }
@@ -364,6 +392,15 @@ static hs_status newton_impl(hs_ctx* ctx, double* q, const double* q_prev, doubl
       return ctx->fail(HS_ERR_NOT_CONVERGED, msg);
     }
     if (!std::isfinite(rho)) return ctx->fail(HS_ERR_NONFINITE, "non-finite Jacobian");
+    if (dev_total > 0) {
+      // the device chose a fixed-count correction and its first launch ran
+      // min(S, total - 1) sweeps from x_1 = rhs into d0 (or onto q)
+      const int first = std::min(tile_sweeps(ctx, s), dev_total - 1);
+      if (dev_total - 1 > first)
+        HS_TRY(relax_sweeps(ctx, s, ctx->coef, ctx->rhs, ctx->d0, dev_total - 1 - first, q, false, nullptr));
+      sweeps_total += dev_total;
+      continue;
+    }
     // Inexact Newton: the correction needs relative accuracy eta ~ ||R|| (the
     // quadratic term is of that size anyway) and never beyond what brings the
     // next residual to a tenth of the tolerance; lin_rtol is the floor.
@@ -396,14 +433,7 @@ static hs_status linear_solve_impl(hs_ctx* ctx, const hs_samples* s, const doubl
   const double* last = rhs;
   int used;
   if (rho < 1.0 && nsw <= ctx->p.lin_maxit) {
-    HS_TRY(prof_begin(ctx, HS_PROF_SWEEP));
     HS_TRY(relax_sweeps(ctx, s, ctx->coef, rhs, rhs, nsw - 1, q, false, &last));
-    const int count = s ? s->n_s : ctx->ncell;
-    const int per = tile_sweeps(ctx, s);
-    const int launches = (nsw - 1 + per - 1) / per;
-    // each launch reads the relaxation blocks, b and the iterate once and writes the new iterate
-    HS_TRY(prof_end(ctx, HS_PROF_SWEEP, (double)launches * count *
-                                            (8.0 * (4 * ctx->nc * ctx->nc + ctx->nc) + 16.0 * ctx->nc)));
     used = nsw;
   } else {
     constexpr int kBatch = 8;

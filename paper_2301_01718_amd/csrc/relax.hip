@@ -37,22 +37,66 @@ struct TileCfg {
   static constexpr int CPT = (R + NT - 1) / NT;   // region cells per thread
 };
 
+// The sweep count of a Newton correction (0: none here, converged or
+// non-finite; -1: the batch form), as the host computes it: inexact Newton
+// accuracy eta from the residual, rho^nsw <= eta.
+__device__ inline int newton_sweeps(double rmax, double rho, const NewtonCtrl& c) {
+  if (!isfinite(rmax) || rmax <= c.tol || !isfinite(rho)) return 0;
+  const double eta = fmin(0.1, fmax(c.lin_rtol, fmax(rmax / c.scale, 0.1 * c.tol / rmax)));
+  int nsw = 1;
+  if (rho > 0.0 && rho < 1.0) {
+    const double k = ceil(log(eta) / log(rho));
+    nsw = k > (double)c.lin_maxit ? c.lin_maxit + 1 : max(1, (int)k);
+  }
+  return (rho < 1.0 && nsw <= c.lin_maxit) ? nsw : -1;
+}
+
 // tiles: active tile ids (nullptr: tile = blockIdx.x); pos/nbr: compact index
 // of a cell and of its in-set neighbours (nullptr: full mesh, index = cell).
 // xin: iterate before the launch (compact layout x[a * cap + p]); the result
 // goes to xout, or is added to the state q when q != nullptr.  With record,
 // max |x_last - x_prev| and max |x_last| of the tile go to the statistics.
+// With ctl.part the launch first takes the Newton decision (NewtonCtrl): nsw
+// and q then follow from it, and block 0 posts the statistics to the host.
 template <int NC, int TSX, int TSY, int S, bool COEF_REG, int NT>
 __global__ void __launch_bounds__(NT) tile_sweep_kernel(
     Grid g, const int* __restrict__ tiles, int ntx, const int* __restrict__ pos, const int* __restrict__ nbr,
     int cap, const double* __restrict__ coef, const double* __restrict__ rhs, const double* __restrict__ xin,
-    double* __restrict__ xout, double* __restrict__ q, int nsw, int record, double* __restrict__ part) {
+    double* __restrict__ xout, double* __restrict__ q, int nsw, int record, double* __restrict__ part,
+    const NewtonCtrl ctl) {
   using C = TileCfg<NC, TSX, TSY, S, NT>;
   constexpr int RW = C::RW, RH = C::RH, R = C::R, CPT = C::CPT;
   constexpr bool ONE_D = TSY == 1;
   constexpr int NDIR = ONE_D ? 2 : 4;
   __shared__ double xs[2][NC][R];
   __shared__ double lds[NT / kWave];
+  __shared__ int s_total;
+  if (ctl.part != nullptr) {
+    // every block reduces the same partials (max: exact in any order)
+    double rm = 0.0, rh = 0.0;
+    for (int b = threadIdx.x; b < ctl.nb; b += NT) {
+      rm = fmax(rm, ctl.part[kStatResMax * kPartCap + b]);
+      rh = fmax(rh, ctl.part[kStatRho * kPartCap + b]);
+    }
+    rm = block_max(rm, lds);
+    rh = block_max(rh, lds);
+    if (threadIdx.x == 0) {
+      const int total = newton_sweeps(rm, rh, ctl);
+      s_total = total;
+      if (blockIdx.x == 0) {
+        ctl.stats[kStatResMax] = dbits(rm);
+        ctl.stats[kStatRho] = dbits(rh);
+        ctl.stats[kStatSweeps] = (unsigned long long)(long long)total;
+      }
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x < kWave)
+      post_words(reinterpret_cast<const uint32_t*>(ctl.stats), kStatSlots * 2, ctl.dst, ctl.tagp, ctl.tag);
+    const int total = s_total;
+    if (total <= 0) return;
+    nsw = min(S, total - 1);
+    if (total - 1 > S) q = nullptr;
+  }
   const int tile = tiles ? tiles[blockIdx.x] : (int)blockIdx.x;
   const int tx = tile % ntx, ty = tile / ntx;
   const int i0 = tx * TSX - S, j0 = ONE_D ? 0 : ty * TSY - S;
@@ -298,10 +342,11 @@ __global__ void add_list_kernel(Grid g, const int* __restrict__ hat, int count, 
 // ------------------------------------------------------------------- host
 template <int NC, int TSX, int TSY, int S, bool CR, int NT = kBlock>
 static hs_status launch_tiles(hs_ctx* ctx, const hs_samples* s, int ntiles, const double* coef,
-                              const double* rhs, const double* xin, double* xout, double* q, int k, bool record) {
+                              const double* rhs, const double* xin, double* xout, double* q, int k, bool record,
+                              const NewtonCtrl& ctl = NewtonCtrl{}) {
   HS_LAUNCH(ctx, (tile_sweep_kernel<NC, TSX, TSY, S, CR, NT>), ntiles, NT, ctx->g, s ? s->tiles : nullptr,
             s ? ctx->sntx : ctx->ntx, s ? s->pos : nullptr, s ? s->nbr : nullptr, ctx->ncell, coef, rhs, xin,
-            xout, q, k, record ? 1 : 0, ctx->part);
+            xout, q, k, record ? 1 : 0, ctx->part, ctl);
   return HS_OK;
 }
 
@@ -316,6 +361,31 @@ bool use_tiles(const hs_ctx* ctx, const hs_samples* s) {
   if (ctx->tiled == 0 || ntiles <= 0 || ntiles > kPartCap) return false;
   if (!s || ctx->tiled == 2) return true;
   return 4.0 * s->n_s >= (double)ntiles * ctx->stile_x * ctx->stile_y;
+}
+
+bool newton_ctrl_ok(const hs_ctx* ctx, const hs_samples* s) { return ctx->nc == 1 && use_tiles(ctx, s); }
+
+// A sweep launch reads the relaxation blocks, b and the iterate once and
+// writes the new iterate.
+double sweep_launch_bytes(const hs_ctx* ctx, const hs_samples* s) {
+  const int count = s ? s->n_s : ctx->ncell;
+  return (double)count * (8.0 * (4 * ctx->nc * ctx->nc + ctx->nc) + 16.0 * ctx->nc);
+}
+
+hs_status relax_first_ctrl(hs_ctx* ctx, const hs_samples* s, double* q, const NewtonCtrl& c) {
+  if (!newton_ctrl_ok(ctx, s)) return ctx->fail(HS_ERR_INVALID_ARG, "device Newton decision needs scalar tiles");
+  const int ntiles = s ? s->ntiles : ctx->ntx * ctx->nty;
+  const double* in = ctx->rhs;
+  double* out = ctx->d0;
+  const double* coef = ctx->coef;
+  const double* rhs = ctx->rhs;
+  if (ctx->g.kind == HS_BURGERS_1D && s)
+    return launch_tiles<1, 256, 1, 8, true>(ctx, s, ntiles, coef, rhs, in, out, q, 0, false, c);
+  if (ctx->g.kind == HS_BURGERS_1D)
+    return launch_tiles<1, 1024, 1, 8, true>(ctx, s, ntiles, coef, rhs, in, out, q, 0, false, c);
+  if (s)
+    return launch_tiles<1, 16, 16, 8, true, kSweepThreadsSet>(ctx, s, ntiles, coef, rhs, in, out, q, 0, false, c);
+  return launch_tiles<1, 32, 32, 8, true, kSweepThreadsMesh>(ctx, s, ntiles, coef, rhs, in, out, q, 0, false, c);
 }
 
 int tile_sweeps(const hs_ctx* ctx, const hs_samples* s) {
@@ -347,6 +417,7 @@ hs_status relax_sweeps(hs_ctx* ctx, const hs_samples* s, const double* coef, con
     double* out = in == ctx->d0 ? ctx->d1 : ctx->d0;
     double* qq = last ? q : nullptr;
     const bool rec = last && record;
+    HS_TRY(prof_begin(ctx, HS_PROF_SWEEP));
     if (tiled) {
       if (g.kind == HS_BURGERS_1D && s)
         HS_TRY((launch_tiles<1, 256, 1, 8, true>(ctx, s, ntiles, coef, rhs, in, out, qq, k, rec)));
@@ -379,6 +450,7 @@ hs_status relax_sweeps(hs_ctx* ctx, const hs_samples* s, const double* coef, con
       else HS_SWEEP(4);
 #undef HS_SWEEP
     }
+    HS_TRY(prof_end(ctx, HS_PROF_SWEEP, sweep_launch_bytes(ctx, s)));
     left -= k;
     in = out;
   }

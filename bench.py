@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurement")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision measurement")
+    ap.add_argument("--no-step-kernels", action="store_true", help="skip the per-class replays of the timed steps")
     ap.add_argument("--adjoint-workload", default="burgers2d_256")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 1 GiB elementwise copy (counter calibration for rocprofv3 --pmc)")
@@ -337,8 +338,10 @@ def main():
     log("residual kernel rates ...")
     prev_state = drv.slot(drv.k - 1).clone()
     resk = residual_kernels(prob, drv.state(), prev_state, args.seed)
-    log("kernel classes of the timed steps ...")
-    stepk = step_kernel_rates(prob, q0, wl, recs[0]["k"] - 1, args.steps)
+    stepk = None
+    if not args.no_step_kernels:
+        log("kernel classes of the timed steps ...")
+        stepk = step_kernel_rates(prob, q0, wl, recs[0]["k"] - 1, args.steps)
 
     if args.copy_probe:
         a = torch.ones(1 << 27, dtype=torch.float64, device=dev)

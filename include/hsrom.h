@@ -283,9 +283,10 @@ hs_status rom_hybrid_step_adjoint(hs_ctx* ctx, const double* Phi, int32_t m, con
 /* ----------------------------------------------------------- options */
 /* HS_OPT_TILED_SWEEPS: how the relaxation sweeps run.  0: one sweep per
  * launch over the compact cell list; 1 (default): LDS tiles, several sweeps
- * per launch, where the tiles are dense enough to pay, else the list; 2: tiles
- * wherever the tile list fits the statistics capacity.  All give the same
- * iterates bit for bit (a switch for measurement and testing). */
+ * per launch, for scalar problems where the tiles are dense enough to pay,
+ * else the list (Euler's 4x4 blocks always use the list); 2: tiles wherever
+ * the tile list fits the statistics capacity.  All give the same iterates bit
+ * for bit (a switch for measurement and testing). */
 #define HS_OPT_TILED_SWEEPS 1
 hs_status hs_set_option(hs_ctx* ctx, int32_t option, int64_t value);
 

@@ -356,10 +356,16 @@ static hs_status launch_tiles(hs_ctx* ctx, const hs_samples* s, int ntiles, cons
 // costs about one list sweep while doing up to S = 8 sweeps, and its work
 // grows with the staged cells (4x the tile cells for 16 x 16, S = 8): tiles
 // are used down to a quarter of the active tiles' cells sampled.
+// Euler's 4 x 4 blocks stay on the compact list unless tiles are forced: a
+// tile cannot hold their 64 coefficients per cell in registers, re-reads them
+// every sweep and runs one wave per SIMD (512^2: full step 8.2 ms tiled,
+// 1.4 ms over the list).
 bool use_tiles(const hs_ctx* ctx, const hs_samples* s) {
   const int ntiles = s ? s->ntiles : ctx->ntx * ctx->nty;
   if (ctx->tiled == 0 || ntiles <= 0 || ntiles > kPartCap) return false;
-  if (!s || ctx->tiled == 2) return true;
+  if (ctx->tiled == 2) return true;
+  if (ctx->nc != 1) return false;
+  if (!s) return true;
   return 4.0 * s->n_s >= (double)ntiles * ctx->stile_x * ctx->stile_y;
 }
 

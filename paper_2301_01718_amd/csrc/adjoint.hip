@@ -63,7 +63,8 @@ __global__ void __launch_bounds__(kBlock) adj_coef_kernel(Grid g, const double* 
   const int ndir = g.kind == HS_BURGERS_1D ? 2 : 4;
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < count; p += gridDim.x * blockDim.x) {
     const int cell = hat ? hat[p] : p;
-    const int i = cell % g.nx, j = cell / g.nx;
+    int i, j;
+    cell_ij(g, cell, i, j);
     double Di[NC * NC];
     {
       Stencil<NC> st;
@@ -131,7 +132,8 @@ __global__ void __launch_bounds__(kBlock) ring_coupling_kernel(Grid g, const dou
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= l) return;
   const int cell = tilde[t];
-  const int i = cell % g.nx, j = cell / g.nx;
+  int i, j;
+  cell_ij(g, cell, i, j);
   const int ndir = g.kind == HS_BURGERS_1D ? 2 : 4;
   double acc[NC];
 #pragma unroll
@@ -185,7 +187,8 @@ __global__ void shapiro_t_kernel(Grid g, const double* __restrict__ in, const ui
   const long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (k >= (long long)g.nc * g.ncell) return;
   const int a = (int)(k / g.ncell), cell = (int)(k % g.ncell);
-  const int i = cell % g.nx, j = cell / g.nx;
+  int i, j;
+  cell_ij(g, cell, i, j);
   const int len = axis == 0 ? g.nx : g.ny;
   const int x0 = axis == 0 ? i : j;
   auto at = [&](int x) {
@@ -198,7 +201,7 @@ __global__ void shapiro_t_kernel(Grid g, const double* __restrict__ in, const ui
     // the source cell x0 - k of weight c_k lands on x0 for every k
     for (int s = -n; s <= n; ++s) {
       int x = x0 - s;
-      x = ((x % len) + len) % len;
+      x = wrap_index(x, len);
       acc -= shapiro_weight(n, s) * at(x);
     }
   } else {

@@ -23,6 +23,8 @@ constexpr int kRedBlocks = 1024;     // upper bound on blocks of a reduction pas
 struct Grid {
   int nx, ny, ncell, nc, kind, bc;
   double lx, ly, gamma, inflow;
+  unsigned long long nx_mul;   // ceil(2^nx_shift / nx), for cell / nx by a multiply
+  int nx_shift;                // 32 + ceil(log2 nx)
 };
 
 // Small statistics slots (uint64 bit patterns of non-negative doubles, so an
@@ -263,6 +265,24 @@ __device__ inline void stat_max(unsigned long long* slot, double x) {
 
 // Per-block partial of a statistic: part[slot * kPartCap + block].  A finish
 // kernel reduces the partials (no same-address atomics across blocks).
+// Row j = cell / nx and column i = cell % nx by a multiply and a shift (a
+// runtime division costs about 20 VALU instructions): with l = ceil(log2 nx)
+// and m = ceil(2^(32+l) / nx), floor(cell m / 2^(32+l)) is the exact
+// quotient for every 0 <= cell < 2^31.
+__device__ inline void cell_ij(const Grid& g, int cell, int& i, int& j) {
+  j = (int)(((unsigned long long)(unsigned)cell * g.nx_mul) >> g.nx_shift);
+  i = cell - j * g.nx;
+}
+
+// u wrapped into [0, len) on a periodic axis.  Every halo and stencil offset
+// here lies within one period of the range, where one conditional add or
+// subtract does it (a runtime remainder costs about 20 VALU instructions);
+// the remainder serves anything farther.
+__device__ inline int wrap_index(int u, int len) {
+  if (u >= -len && u < 2 * len) return u < 0 ? u + len : (u >= len ? u - len : u);
+  return ((u % len) + len) % len;
+}
+
 __device__ inline void stat_part(double* part, int slot, double v) {
   part[slot * kPartCap + blockIdx.x] = v;
 }

@@ -574,6 +574,12 @@ hs_status hs_create(const hs_problem* pr, void* stream, hs_ctx** out) {
   g.ly = pr->kind == HS_BURGERS_1D ? 0.0 : pr->dt / pr->dy;
   g.gamma = pr->gamma;
   g.inflow = pr->inflow;
+  {
+    int l = 0;
+    while ((1LL << l) < (long long)g.nx) ++l;
+    g.nx_shift = 32 + l;
+    g.nx_mul = (unsigned long long)((((unsigned __int128)1 << g.nx_shift) + (unsigned)g.nx - 1) / (unsigned)g.nx);
+  }
   set_tile_geometry(ctx, pr);
 
   const size_t N = ctx->n, NC = ctx->ncell, nc = ctx->nc;

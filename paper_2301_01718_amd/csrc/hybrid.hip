@@ -264,14 +264,15 @@ __global__ void shapiro_kernel(Grid g, const double* __restrict__ in, double* __
   const long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (k >= (long long)g.nc * g.ncell) return;
   const int a = (int)(k / g.ncell), cell = (int)(k % g.ncell);
-  const int i = cell % g.nx, j = cell / g.nx;
+  int i, j;
+  cell_ij(g, cell, i, j);
   const int len = axis == 0 ? g.nx : g.ny;
   const int x0 = axis == 0 ? i : j;
   const bool per = g.bc == HS_BC_PERIODIC;
   const double* src = in + (size_t)a * g.ncell;
   out[k] = shapiro_any(nord, [&](int s) {
     int x = x0 + s;
-    if (per) x = ((x % len) + len) % len;
+    if (per) x = wrap_index(x, len);
     else x = x < 0 ? 0 : (x >= len ? len - 1 : x);
     return src[axis == 0 ? x + g.nx * j : i + g.nx * x];
   });
@@ -348,7 +349,7 @@ struct FiltCfg {
 };
 
 __device__ inline int wrap_or_clamp(int u, int len, bool per) {
-  if (per) return ((u % len) + len) % len;
+  if (per) return wrap_index(u, len);
   return u < 0 ? 0 : (u >= len ? len - 1 : u);
 }
 

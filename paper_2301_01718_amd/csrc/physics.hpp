@@ -152,7 +152,8 @@ struct Stencil {
 template <int NC>
 __device__ inline void load_stencil(const Grid& g, const double* __restrict__ q, int cell,
                                     Stencil<NC>& st) {
-  const int i = cell % g.nx, j = cell / g.nx;
+  int i, j;
+  cell_ij(g, cell, i, j);
   const int ndir = g.kind == HS_BURGERS_1D ? 2 : 4;
   st.self = cell;
 #pragma unroll

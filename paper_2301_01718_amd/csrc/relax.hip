@@ -120,8 +120,8 @@ __global__ void __launch_bounds__(NT) tile_sweep_kernel(
       const int rx = r % RW, ry = r / RW;
       int gi = i0 + rx, gj = j0 + ry;
       if (per) {
-        gi = ((gi % g.nx) + g.nx) % g.nx;
-        gj = ONE_D ? 0 : ((gj % g.ny) + g.ny) % g.ny;
+        gi = wrap_index(gi, g.nx);
+        gj = ONE_D ? 0 : wrap_index(gj, g.ny);
         cell = gi + g.nx * gj;
       } else if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny) {
         cell = gi + g.nx * gj;
@@ -153,7 +153,9 @@ __global__ void __launch_bounds__(NT) tile_sweep_kernel(
         ok = nbr[d * cap + pp] >= 0;
       } else {
         const int cl = cells[c] < 0 ? 0 : cells[c];
-        const int nb = neighbour(g, cl % g.nx, cl / g.nx, d);
+        int ci, cj;
+        cell_ij(g, cl, ci, cj);
+        const int nb = neighbour(g, ci, cj, d);
         ok = nb >= 0 && nb != cl;
       }
       v |= ok ? (1u << d) : 0u;
@@ -287,7 +289,7 @@ __global__ void list_sweep_kernel(Grid g, const int* __restrict__ hat, const int
     for (int a = 0; a < NC; ++a) acc[a] = rhs[a * cap + p];
     int i = 0, j = 0, cell = p;
     if (hat) cell = hat[p];
-    else { i = p % g.nx; j = p / g.nx; }
+    else cell_ij(g, p, i, j);
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
       if (d >= ndir) break;

@@ -464,7 +464,8 @@ __global__ void dilate_kernel(Grid g, const uint8_t* __restrict__ in, uint8_t* _
                               int h) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= g.ncell) return;
-  const int i = c % g.nx, j = c / g.nx;
+  int i, j;
+  cell_ij(g, c, i, j);
   const bool per = g.bc == HS_BC_PERIODIC;
   const int n = axis == 0 ? g.nx : g.ny;
   const int x0 = axis == 0 ? i : j;
@@ -488,7 +489,8 @@ __global__ void ring_kernel(Grid g, const uint8_t* __restrict__ mask, uint8_t* _
     tmask[c] = 0;
     return;
   }
-  const int i = c % g.nx, j = c / g.nx;
+  int i, j;
+  cell_ij(g, c, i, j);
   const bool per = g.bc == HS_BC_PERIODIC;
   const int ndir = g.kind == HS_BURGERS_1D ? 2 : 4;
   uint8_t v = 0;
@@ -512,7 +514,8 @@ __global__ void nbr_table_kernel(Grid g, const int* __restrict__ hat, int ns, in
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= ns) return;
   const int cell = hat[p];
-  const int i = cell % g.nx, j = cell / g.nx;
+  int i, j;
+  cell_ij(g, cell, i, j);
   const int ndir = g.kind == HS_BURGERS_1D ? 2 : 4;
   for (int d = 0; d < 4; ++d) {
     int v = -1;
@@ -537,7 +540,8 @@ __global__ void tile_flag_kernel(Grid g, const int* __restrict__ hat, int ns, in
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= ns) return;
   const int cell = hat[p];
-  const int i = cell % g.nx, j = cell / g.nx;
+  int i, j;
+  cell_ij(g, cell, i, j);
   tflag[(j / ty) * ntx + i / tx] = 1;
 }
 

@@ -93,6 +93,7 @@ struct hs_ctx {
   void* hpin = nullptr;       // host read-back buffer (64 KiB + tag word): pinned, coherent, mapped
   void* dpin = nullptr;       // its device address
   unsigned pin_tag = 0;       // last tag published into it
+  unsigned post_next = 0;     // next slot of the read-back ring
 
   // kernel timing (hs_prof_enable)
   int prof_class = 0;
@@ -151,6 +152,7 @@ constexpr int kSmMisc = 12288 + 192;    // [0] = ||dy||, [1] = rank, [2] = cond,
 constexpr int kSmAdjY = 12288 + 256;    // adjoint: y-bar of the current subiteration
 constexpr int kSmAdjZ = 12288 + 320;    // adjoint: G+ y-bar
 constexpr int kSmAdjY0 = 12288 + 384;   // adjoint: y-bar from the reconstruction
+constexpr int kSmFilt = 12288 + 448;    // device state of the filter loop (FiltCtl)
 
 // ----------------------------------------------------------------- helpers
 #define HS_TRY(expr)                     \
@@ -386,6 +388,18 @@ struct NewtonCtrl {
   uint32_t* tagp = nullptr;
   unsigned tag = 0;
 };
+// A slot of the host read-back ring: posts that may be in flight while the
+// host reads an earlier one (the filter loop runs one pass ahead).
+struct PostSlot {
+  uint32_t* dst = nullptr;    // device address of the slot's data (kPostWords words)
+  uint32_t* tagp = nullptr;   // device address of its tag word
+  unsigned tag = 0;
+  int slot = 0;
+};
+constexpr int kPostWords = 32;
+PostSlot post_slot(hs_ctx* ctx);
+// Waits for the slot's tag, then copies bytes (<= 4 kPostWords) of its data.
+hs_status await_post(hs_ctx* ctx, const PostSlot& p, void* out, size_t bytes);
 // Whether the Newton decision can run in the first sweep launch on s.
 bool newton_ctrl_ok(const hs_ctx* ctx, const hs_samples* s);
 // That launch: sweeps from x_1 = rhs into ctx->d0, or onto q when they are all.

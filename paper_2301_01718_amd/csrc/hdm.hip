@@ -94,11 +94,15 @@ static uint32_t* pin_tag_dev(hs_ctx* ctx) {
   return reinterpret_cast<uint32_t*>(static_cast<char*>(ctx->dpin) + kPinBytes);
 }
 
-// Spin until the tag arrives; after 20 ms fall back to a blocking wait on the
-// stream (a long queue ahead, or an error to report).
-static hs_status await_tag(hs_ctx* ctx, unsigned tag) {
-  const volatile uint32_t* t =
-      reinterpret_cast<const volatile uint32_t*>(static_cast<const char*>(ctx->hpin) + kPinBytes);
+// The read-back ring after the main area: kPostSlots slots of kSlotBytes
+// (data, then the tag word at kPostWords).
+constexpr int kPostSlots = 8;
+constexpr size_t kSlotBytes = 256;
+constexpr size_t kRingOffset = kPinBytes + 256;
+
+// Spin until the tag arrives at t; after 20 ms fall back to a blocking wait
+// on the stream (a long queue ahead, or an error to report).
+static hs_status await_tag_at(hs_ctx* ctx, const volatile uint32_t* t, unsigned tag) {
   const auto start = std::chrono::steady_clock::now();
   for (unsigned spin = 1;; ++spin) {
     if (*t == tag) break;
@@ -109,6 +113,29 @@ static hs_status await_tag(hs_ctx* ctx, unsigned tag) {
     }
   }
   std::atomic_thread_fence(std::memory_order_acquire);
+  return HS_OK;
+}
+
+static hs_status await_tag(hs_ctx* ctx, unsigned tag) {
+  return await_tag_at(
+      ctx, reinterpret_cast<const volatile uint32_t*>(static_cast<const char*>(ctx->hpin) + kPinBytes), tag);
+}
+
+PostSlot post_slot(hs_ctx* ctx) {
+  PostSlot p;
+  p.slot = (int)(ctx->post_next++ % kPostSlots);
+  char* base = static_cast<char*>(ctx->dpin) + kRingOffset + (size_t)p.slot * kSlotBytes;
+  p.dst = reinterpret_cast<uint32_t*>(base);
+  p.tagp = reinterpret_cast<uint32_t*>(base) + kPostWords;
+  p.tag = next_tag(ctx);
+  return p;
+}
+
+hs_status await_post(hs_ctx* ctx, const PostSlot& p, void* out, size_t bytes) {
+  if (bytes > kPostWords * 4) return ctx->fail(HS_ERR_INVALID_ARG, "post larger than a ring slot");
+  const char* base = static_cast<const char*>(ctx->hpin) + kRingOffset + (size_t)p.slot * kSlotBytes;
+  HS_TRY(await_tag_at(ctx, reinterpret_cast<const volatile uint32_t*>(base) + kPostWords, p.tag));
+  std::memcpy(out, base, bytes);
   return HS_OK;
 }
 
@@ -610,9 +637,10 @@ hs_status hs_create(const hs_problem* pr, void* stream, hs_ctx** out) {
       st = ctx->fail(HS_ERR_HIP, "stream/event creation");
   }
   if (st == HS_OK) {
-    hipError_t e = hipHostMalloc(&ctx->hpin, kPinBytes + 256, hipHostMallocCoherent | hipHostMallocMapped);
+    const size_t pin = kRingOffset + kPostSlots * kSlotBytes;
+    hipError_t e = hipHostMalloc(&ctx->hpin, pin, hipHostMallocCoherent | hipHostMallocMapped);
     if (e == hipSuccess) e = hipHostGetDevicePointer(&ctx->dpin, ctx->hpin, 0);
-    if (e == hipSuccess) *reinterpret_cast<volatile uint32_t*>(static_cast<char*>(ctx->hpin) + kPinBytes) = 0u;
+    if (e == hipSuccess) std::memset(ctx->hpin, 0, pin);
     if (e != hipSuccess) st = ctx->fail(HS_ERR_OOM, "hipHostMalloc");
   }
   if (st != HS_OK) {

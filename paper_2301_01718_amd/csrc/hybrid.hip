@@ -386,11 +386,27 @@ __device__ inline void lds_stencil(const Grid& g, const double* arr, int stride,
   }
 }
 
+// Device state of the filter loop (orders o, passes within an order it): the
+// finisher of each pass advances it exactly as the host loop would, so the
+// next pass can be enqueued before the host has read the decision.
+struct FiltCtl {
+  int o, it, parity, done, passes, kept;   // parity 1: the current state is in the spare buffer
+  double sum_r;                            // l1 sum of the current state's residual norms
+};
+
+// The gate kernel's view of that state (ctl == nullptr: a host-driven pass).
+struct FiltSpec {
+  const FiltCtl* ctl = nullptr;
+  double* state[2] = {nullptr, nullptr};   // gamma, spare
+  double* norms[2] = {nullptr, nullptr};   // r, r2
+  int orders[4] = {0, 0, 0, 0};
+};
+
 template <int NC, int TX, int TY>
 __global__ void __launch_bounds__(kBlock) filter_gate_kernel(
     Grid g, int ntx, int ntiles, int nord, const double* __restrict__ cur, const double* __restrict__ qp,
     const double* __restrict__ r, double* __restrict__ merged, double* __restrict__ r2,
-    uint8_t* __restrict__ keep_out, double* __restrict__ part) {
+    uint8_t* __restrict__ keep_out, double* __restrict__ part, const FiltSpec fs) {
 #pragma clang fp contract(off)
   using C = FiltCfg<NC, TX, TY>;
   constexpr bool ONE_D = C::ONE_D;
@@ -410,6 +426,16 @@ __global__ void __launch_bounds__(kBlock) filter_gate_kernel(
   const bool per = g.bc == HS_BC_PERIODIC;
   double rsum = 0.0;
   int kept = 0;
+  if (fs.ctl != nullptr) {
+    // the pass the device state asks for, or none once the loop is done
+    const FiltCtl c = *fs.ctl;
+    if (c.done) return;
+    nord = fs.orders[c.o];
+    cur = fs.state[c.parity];
+    merged = fs.state[c.parity ^ 1];
+    r = fs.norms[c.parity];
+    r2 = fs.norms[c.parity ^ 1];
+  }
 
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int X0 = (tile % ntx) * TX, Y0 = ONE_D ? 0 : (tile / ntx) * TY;
@@ -504,6 +530,82 @@ __global__ void __launch_bounds__(kBlock) filter_gate_kernel(
   }
 }
 
+// Initial state of the device-driven filter loop; the l1 sum of the input
+// state's residual norms comes from the statistics slot kStatSum0.
+__global__ void filt_init_kernel(FiltCtl* ctl, const unsigned long long* __restrict__ stats, int done) {
+  FiltCtl c;
+  c.o = 0;
+  c.it = 0;
+  c.parity = 0;
+  c.done = done;
+  c.passes = 0;
+  c.kept = 0;
+  c.sum_r = __longlong_as_double((long long)stats[kStatSum0]);
+  *ctl = c;
+}
+
+// Finisher of a device-driven pass (one workgroup of kBlock): the kept count
+// and the merged state's l1 residual sum reduced as finish_stats reduces them
+// (same order, same tree), the loop advanced as the host loop does it (no
+// cell kept: next order; else swap the buffers, stop the order when the
+// relative decrease falls below eps_f or after jfmax passes), and the record
+// {kept, sum, done, parity, passes, kept total, ran} posted to the host.
+__global__ void filt_finish_kernel(const double* __restrict__ part, int nb, FiltCtl* ctl, int n_orders,
+                                   int jfmax, double eps_f, unsigned long long* __restrict__ stats, PostSlot post) {
+  __shared__ double lds[kBlock / kWave];
+  __shared__ unsigned long long rec[8];
+  const FiltCtl c0 = *ctl;
+  if (!c0.done) {
+    double cnt = 0.0, sum = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+      cnt = cnt + part[kStatCount * kPartCap + b];
+      sum = sum + part[kStatSum * kPartCap + b];
+    }
+    cnt = block_sum(cnt, lds);
+    sum = block_sum(sum, lds);
+    if (threadIdx.x == 0) {
+      stats[kStatCount] = dbits(cnt);
+      stats[kStatSum] = dbits(sum);
+      FiltCtl c = c0;
+      const long long kept = (long long)cnt;
+      c.passes += 1;
+      c.kept += (int)kept;
+      if (kept == 0) {
+        c.o += 1;
+        c.it = 0;
+      } else {
+        c.parity ^= 1;
+        const double dec = (c.sum_r - sum) / c.sum_r;
+        c.sum_r = sum;
+        c.it += 1;
+        if (dec < eps_f || c.it >= jfmax) {
+          c.o += 1;
+          c.it = 0;
+        }
+      }
+      if (c.o >= n_orders) c.done = 1;
+      *ctl = c;
+      rec[0] = (unsigned long long)kept;
+      rec[1] = dbits(sum);
+      rec[2] = (unsigned long long)c.done;
+      rec[3] = (unsigned long long)c.parity;
+      rec[4] = (unsigned long long)c.passes;
+      rec[5] = (unsigned long long)c.kept;
+      rec[6] = 1ull;
+    }
+  } else if (threadIdx.x == 0) {
+    rec[0] = 0ull;
+    rec[1] = 0ull;
+    rec[2] = 1ull;
+    rec[3] = (unsigned long long)c0.parity;
+    rec[4] = (unsigned long long)c0.passes;
+    rec[5] = (unsigned long long)c0.kept;
+    rec[6] = 0ull;
+  }
+  __syncthreads();
+  if (threadIdx.x < kWave) post_words(reinterpret_cast<const uint32_t*>(rec), 14, post.dst, post.tagp, post.tag);
+}
+
 // Tile of the fused filter pass (must match the instantiations in filter_pass).
 static void filter_tile(const hs_ctx* ctx, int* tx, int* ty) {
   if (ctx->g.kind == HS_BURGERS_1D) { *tx = 512; *ty = 1; }
@@ -513,8 +615,8 @@ static void filter_tile(const hs_ctx* ctx, int* tx, int* ty) {
 
 // One gated pass: merged (the next state), r2, keep_out; kept count and sum
 // of r2 to the statistics slots kStatCount / kStatSum (enqueued only).
-static hs_status filter_pass(hs_ctx* ctx, const double* cur, const double* q_prev, const double* r, int nord,
-                             double* merged, double* r2, uint8_t* keep_out, unsigned long long* st) {
+static hs_status filter_gate_launch(hs_ctx* ctx, const double* cur, const double* q_prev, const double* r, int nord,
+                                    double* merged, double* r2, uint8_t* keep_out, const FiltSpec& fs, int* nb_out) {
   int tx, ty;
   filter_tile(ctx, &tx, &ty);
   const int ntx = (ctx->g.nx + tx - 1) / tx;
@@ -523,16 +625,26 @@ static hs_status filter_pass(hs_ctx* ctx, const double* cur, const double* q_pre
   HS_TRY(prof_begin(ctx, HS_PROF_FILTER));
   if (ctx->g.kind == HS_BURGERS_1D)
     HS_LAUNCH(ctx, (filter_gate_kernel<1, 512, 1>), nb, kBlock, ctx->g, ntx, ntiles, nord, cur, q_prev, r, merged,
-              r2, keep_out, ctx->part);
+              r2, keep_out, ctx->part, fs);
   else if (ctx->nc == 1)
     HS_LAUNCH(ctx, (filter_gate_kernel<1, 32, 32>), nb, kBlock, ctx->g, ntx, ntiles, nord, cur, q_prev, r, merged,
-              r2, keep_out, ctx->part);
+              r2, keep_out, ctx->part, fs);
   else
     HS_LAUNCH(ctx, (filter_gate_kernel<4, 16, 16>), nb, kBlock, ctx->g, ntx, ntiles, nord, cur, q_prev, r, merged,
-              r2, keep_out, ctx->part);
+              r2, keep_out, ctx->part, fs);
   // reads: the state, q_prev and r once; writes: merged, r2 and the decisions
   HS_TRY(prof_end(ctx, HS_PROF_FILTER,
                   (double)ctx->ncell * (8.0 * ctx->nc * 3 + 8.0 * 2 + (keep_out ? 1.0 : 0.0))));
+  *nb_out = nb;
+  return HS_OK;
+}
+
+// One host-driven gated pass: merged (the next state), r2, keep_out; the kept
+// count and the sum of r2 come back in st (kStatCount / kStatSum).
+static hs_status filter_pass(hs_ctx* ctx, const double* cur, const double* q_prev, const double* r, int nord,
+                             double* merged, double* r2, uint8_t* keep_out, unsigned long long* st) {
+  int nb;
+  HS_TRY(filter_gate_launch(ctx, cur, q_prev, r, nord, merged, r2, keep_out, FiltSpec{}, &nb));
   return finish_stats(ctx, nb, 0u, (1u << kStatCount) | (1u << kStatSum), st);
 }
 
@@ -577,8 +689,58 @@ static hs_status filter_apply(hs_ctx* ctx, const double* in, double* out, int no
 // the merged state's cell residual norms are read together (when nothing was
 // kept the merged state equals the current one, so the sum is unchanged).
 // The norms carry over from one filter order to the next (same state).
+// The filter loop driven by the device state (no recording): each pass is
+// enqueued with its finisher one pass ahead of the host, which reads the
+// records in order and stops enqueueing once one says the loop is done (the
+// pass already enqueued behind it then does nothing).
+static hs_status run_filter_device(hs_ctx* ctx, double* gamma, const double* q_prev, const hs_hybrid_params* hp,
+                                   hs_step_info* info) {
+  FiltCtl* ctl = reinterpret_cast<FiltCtl*>(ctx->small + kSmFilt);
+  HS_TRY(cell_residual_launch(ctx, gamma, q_prev, ctx->rcell, kStatSum0));
+  HS_LAUNCH(ctx, filt_init_kernel, 1, 1, ctl, (const unsigned long long*)ctx->stats, 0);
+  FiltSpec fs;
+  fs.ctl = ctl;
+  fs.state[0] = gamma;
+  fs.state[1] = ctx->gtmp;
+  fs.norms[0] = ctx->rcell;
+  fs.norms[1] = ctx->rcell2;
+  for (int o = 0; o < hp->n_orders; ++o) fs.orders[o] = hp->filter_orders[o];
+  const long long max_passes = (long long)hp->n_orders * hp->jfmax;
+  long long enqueued = 0;
+  auto enqueue = [&](PostSlot* p) -> hs_status {
+    int nb;
+    // the pointers and the order come from the device state
+    HS_TRY(filter_gate_launch(ctx, gamma, q_prev, ctx->rcell, 1, ctx->gtmp, ctx->rcell2, nullptr, fs, &nb));
+    *p = post_slot(ctx);
+    HS_LAUNCH(ctx, filt_finish_kernel, 1, kBlock, ctx->part, nb, ctl, hp->n_orders, hp->jfmax, hp->eps_f,
+              ctx->stats, *p);
+    ++enqueued;
+    return HS_OK;
+  };
+  PostSlot pend[2];
+  HS_TRY(enqueue(&pend[0]));
+  HS_TRY(enqueue(&pend[1]));
+  unsigned long long rec[8];
+  for (long long k = 0;; ++k) {
+    HS_TRY(await_post(ctx, pend[k % 2], rec, 7 * sizeof(unsigned long long)));
+    if (rec[2]) break;
+    if (enqueued > max_passes) return ctx->fail(HS_ERR_INVALID_ARG, "filter loop ran past its pass bound");
+    HS_TRY(enqueue(&pend[k % 2]));
+  }
+  if (info) {
+    info->filter_passes += (int)rec[4];
+    info->filter_kept += (int)rec[5];
+  }
+  if (rec[3]) HIP_TRY(ctx, hipMemcpyAsync(gamma, ctx->gtmp, ctx->n * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  return HS_OK;
+}
+
 hs_status run_filter(hs_ctx* ctx, double* gamma, const double* q_prev, const hs_hybrid_params* hp,
                      hs_step_info* info, hs_htape* record) {
+  if (!record) {
+    if (hp->n_orders <= 0 || hp->jfmax <= 0) return HS_OK;
+    return run_filter_device(ctx, gamma, q_prev, hp, info);
+  }
   if (record) {
     if ((long long)hp->n_orders * hp->jfmax > kMaxPasses)
       return ctx->fail(HS_ERR_INVALID_ARG, "taped step: more filter passes possible than the tape holds");

@@ -343,12 +343,19 @@ hs_status finish_stats(hs_ctx* ctx, int nb, unsigned max_mask, unsigned sum_mask
 inline int stat_blocks(long long n) { return blocks_for(n, kBlock, kPartCap); }
 hs_status max_abs(hs_ctx* ctx, const double* x, long long n, double* out);
 // Newton on the full mesh (s == nullptr) or on a sampled set.  primed: the
-// first iteration's residual/Jacobian was already launched by
-// newton_first_launch on q, and {max |R|, rho} were read back (else nullptr).
+// first iteration's residual/Jacobian was already launched on q by
+// newton_first_launch or newton_first_ctrl, and {max |R|, rho, the device's
+// sweep count (0: none ran)} were read back (else nullptr).
 hs_status newton_solve(hs_ctx* ctx, double* q, const double* q_prev, double tol,
                        const hs_samples* s, hs_step_info* info, const double* primed = nullptr);
 // Residual, Jacobian relaxation data and the ResMax/Rho statistics at q;
 // with st all stats slots are read back as well (else enqueued only).
+// The same with the decision on the device (newton_ctrl_ok): the first sweep
+// launch also applies the subiteration stop test when sub_check is set (the
+// host applies it to the same ||dy|| from the posted stats); *total as in the
+// primed array.
+hs_status newton_first_ctrl(hs_ctx* ctx, double* q, const double* q_prev, double tol, const hs_samples* s,
+                            int sub_check, double eps_y, unsigned long long* st, int* total);
 hs_status newton_first_launch(hs_ctx* ctx, const double* q, const double* q_prev, const hs_samples* s,
                               unsigned long long* st);
 // max |x| into the QMax statistics slot (enqueued only).
@@ -383,6 +390,8 @@ struct NewtonCtrl {
   int nb = 0;                     // resjac blocks
   double tol = 0.0, scale = 1.0, lin_rtol = 0.0;
   int lin_maxit = 0;
+  int sub_check = 0;       // also the subiteration stop test: no sweeps when ||y_j - y_{j-1}|| < eps_y
+  double eps_y = 0.0;
   unsigned long long* stats = nullptr;
   uint32_t* dst = nullptr;
   uint32_t* tagp = nullptr;

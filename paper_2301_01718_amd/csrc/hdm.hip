@@ -350,9 +350,11 @@ static hs_status resjac_launch(hs_ctx* ctx, const double* q, const double* q_pre
 // no sweeps ran).
 template <int NC>
 static hs_status resjac_ctrl(hs_ctx* ctx, double* q, const double* q_prev, double tol, const hs_samples* s,
-                             unsigned long long* st, int* total) {
+                             unsigned long long* st, int* total, int sub_check = 0, double eps_y = 0.0) {
   HS_TRY(resjac_launch<NC>(ctx, q, q_prev, s, nullptr, false));
   NewtonCtrl c;
+  c.sub_check = sub_check;
+  c.eps_y = eps_y;
   c.part = ctx->part;
   c.nb = stat_blocks(s ? s->n_s : ctx->ncell);
   c.tol = tol;
@@ -375,6 +377,12 @@ static hs_status resjac_ctrl(hs_ctx* ctx, double* q, const double* q_prev, doubl
   return HS_OK;
 }
 
+hs_status newton_first_ctrl(hs_ctx* ctx, double* q, const double* q_prev, double tol, const hs_samples* s,
+                            int sub_check, double eps_y, unsigned long long* st, int* total) {
+  if (!newton_ctrl_ok(ctx, s)) return ctx->fail(HS_ERR_INVALID_ARG, "device Newton decision needs scalar tiles");
+  return resjac_ctrl<1>(ctx, q, q_prev, tol, s, st, total, sub_check, eps_y);
+}
+
 hs_status newton_first_launch(hs_ctx* ctx, const double* q, const double* q_prev, const hs_samples* s,
                               unsigned long long* st) {
   if (ctx->nc == 1) return resjac_launch<1>(ctx, q, q_prev, s, st);
@@ -394,6 +402,7 @@ static hs_status newton_impl(hs_ctx* ctx, double* q, const double* q_prev, doubl
     if (it == 0 && primed) {
       rmax = primed[0];
       rho = primed[1];
+      dev_total = (int)primed[2];
     } else {
       unsigned long long st[kStatSlots];
       if (ctrl) HS_TRY(resjac_ctrl<NC>(ctx, q, q_prev, tol, s, st, &dev_total));

@@ -969,8 +969,9 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const void* Phi,
   // Subiterations.  The stop test on ||y_j - y_{j-1}|| is read together with
   // the residual of the next Newton solve's first iteration, launched
   // speculatively (it changes no state, so it is simply dropped on a stop).
-  double primed[2];
+  double primed[3];
   bool have_primed = false;
+  const bool ctrl = newton_ctrl_ok(ctx, s);
   for (int j = 1; j <= jmax; ++j) {
     HS_TRY(newton_solve(ctx, u, q_prev, tol, s, inf, have_primed ? primed : nullptr));
     if (pending && j == 1) {
@@ -991,13 +992,18 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const void* Phi,
     inf->subiters = j;
     if (replay) continue;
     const bool more = j < jmax;
-    if (more) HS_TRY(newton_first_launch(ctx, u, q_prev, s, st));
+    // with the device decision, the next solve's first sweeps start at once
+    // unless the device's stop test (the same as below) ends the loop
+    int dev_total = 0;
+    if (more && ctrl) HS_TRY(newton_first_ctrl(ctx, u, q_prev, tol, s, j >= 2, hp->eps_y, st, &dev_total));
+    else if (more) HS_TRY(newton_first_launch(ctx, u, q_prev, s, st));
     else HS_TRY(read_stats(ctx, st));
     const double dy = bits_to_double(st[kStatDy]);
     inf->dy_last = dy;
     if (!more || (j >= 2 && dy < hp->eps_y)) break;
     primed[0] = bits_to_double(st[kStatResMax]);
     primed[1] = bits_to_double(st[kStatRho]);
+    primed[2] = dev_total;
     have_primed = true;
   }
   if (replay) {

@@ -81,7 +81,8 @@ __global__ void __launch_bounds__(NT) tile_sweep_kernel(
     rm = block_max(rm, lds);
     rh = block_max(rh, lds);
     if (threadIdx.x == 0) {
-      const int total = newton_sweeps(rm, rh, ctl);
+      const double dy = __longlong_as_double((long long)ctl.stats[kStatDy]);
+      const int total = (ctl.sub_check && dy < ctl.eps_y) ? 0 : newton_sweeps(rm, rh, ctl);
       s_total = total;
       if (blockIdx.x == 0) {
         ctl.stats[kStatResMax] = dbits(rm);

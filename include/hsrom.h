@@ -24,8 +24,13 @@
  *   rho v, E).  Bases are column-major N x m: Phi[col * N + row].
  * - Work is enqueued on the stream given to hs_create.  Calls that must take
  *   a data-dependent decision (Newton convergence, subiteration and filter
- *   stopping, set sizes) synchronise that stream internally; they return
- *   only when their outputs are complete.
+ *   stopping, set sizes) read it back internally and return once every
+ *   decision is taken and reported (info, counts, m_eff); unless a call says
+ *   otherwise they also return only when their outputs are complete.
+ *   rom_hybrid_step returns with the work after its last decision (the
+ *   indicator, the final copies) still enqueued: its outputs are complete in
+ *   the stream's order, so later work on that stream needs no wait, and a
+ *   reader on the host or on another stream synchronises first (hs_sync).
  * - Return value: HS_OK (0) or a negative status.  Argument errors are
  *   reported before any work is enqueued.  Numerical failures
  *   (HS_ERR_NOT_CONVERGED, HS_ERR_RANK, HS_ERR_NONFINITE) leave the outputs
@@ -228,8 +233,10 @@ typedef struct hs_hybrid_params {
 /* One hybrid snapshot from q_prev = gamma_{k-1} with basis (Phi, psi; m
  * columns) and the sampled sets s (eq. hybrid).  Writes gamma_k to q_out,
  * the reduced coordinates y^(J) to y_out (m, may be NULL) and the indicator
- * of the filtered snapshot to eps_out (ncell, may be NULL).
- * Errors: HS_ERR_RANK (m = 0 or empty hat-S), HS_ERR_NOT_CONVERGED. */
+ * of the filtered snapshot to eps_out (ncell, may be NULL).  Returns before
+ * the last kernels have run (see the conventions: outputs complete in
+ * stream order).  Errors: HS_ERR_RANK (m = 0 or empty hat-S),
+ * HS_ERR_NOT_CONVERGED. */
 hs_status rom_hybrid_step(hs_ctx* ctx, const double* q_prev, const void* Phi, const double* psi,
                           int32_t m, const hs_samples* s, const hs_hybrid_params* params /* host */,
                           double* q_out, double* eps_out, double* y_out, hs_step_info* info /* host */);

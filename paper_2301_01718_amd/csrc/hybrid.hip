@@ -1031,7 +1031,8 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const void* Phi,
     tape->replayed = false;
   }
   if (replay) tape->replayed = true;
-  return hs_sync(ctx);
+  // outputs complete in stream order: no wait for the work after the last decision
+  return HS_OK;
 }
 
 }  // namespace hs

@@ -314,16 +314,57 @@ __device__ inline void wave_hist_add(unsigned int* h, unsigned d, bool pending) 
 // keys of one binade) would otherwise serialise on one address.
 constexpr int kHistCopies = 8;
 
-__global__ void radix_hist_kernel(const double* __restrict__ eps, int n, const SelectState* st, int shift,
-                                  unsigned int* __restrict__ hist) {
+constexpr int kHistWords = kHistCopies * 256;   // one histogram buffer
+constexpr int kRadixBlocks = 512;               // workgroups of a digit pass
+
+// The digit of the previous pass, taken by every workgroup of 256 threads
+// from that pass's histogram buffer (thread t on digit 255 - t): the
+// exclusive prefix over t counts the keys with a larger digit, and the
+// bucket holding the k-th largest key fixes the digit.  Returns the state
+// after that digit (the same in every workgroup).
+__device__ inline SelectState radix_pick(const unsigned int* __restrict__ hist, int shift, SelectState s,
+                                         int* wsum, SelectState* sh) {
+  const int d = 255 - (int)threadIdx.x;
+  int c = 0;
+#pragma unroll
+  for (int k = 0; k < kHistCopies; ++k) c += (int)hist[k * 256 + d];
+  if (threadIdx.x == 0) *sh = s;
+  const int above = block_exclusive_rank(c, wsum);
+  if (c > 0 && (long long)above < s.k && s.k <= (long long)above + c) {
+    sh->prefix = s.prefix | ((unsigned long long)d << shift);
+    sh->k = s.k - above;
+  }
+  __syncthreads();
+  const SelectState r = *sh;
+  __syncthreads();
+  return r;
+}
+
+// Digit pass p (shift 56 - 8p) of the radix select, 256 threads: the digit
+// of pass p - 1 from its buffer, the state after it (workgroup 0 stores it
+// for pass p + 1), then this pass's histogram of the keys that share the
+// fixed digits.  Buffers rotate over three: pass p fills p % 3, reads
+// (p - 1) % 3 and clears (p + 1) % 3, which the pass before it read and the
+// pass after it fills.  States alternate over two slots.
+__global__ void __launch_bounds__(256) radix_pass_kernel(const double* __restrict__ eps, int n,
+                                                         SelectState* __restrict__ st2, int p,
+                                                         unsigned int* __restrict__ hist3) {
   __shared__ unsigned int h[256];
-  for (int t = threadIdx.x; t < 256; t += blockDim.x) h[t] = 0;
+  __shared__ int wsum[256 / kWave];
+  __shared__ SelectState sh;
+  const int shift = 56 - 8 * p;
+  h[threadIdx.x] = 0;
+  unsigned int* nxt = hist3 + ((p + 1) % 3) * kHistWords;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < kHistWords; i += gridDim.x * 256) nxt[i] = 0u;
+  SelectState s = st2[(p + 1) % 2];
+  if (p > 0) s = radix_pick(hist3 + ((p - 1) % 3) * kHistWords, shift + 8, s, wsum, &sh);
+  if (blockIdx.x == 0 && threadIdx.x == 0) st2[p % 2] = s;
   __syncthreads();
   const unsigned long long himask = shift >= 56 ? 0ull : (~0ull << (shift + 8));
-  const unsigned long long pre = st->prefix & himask;
-  const int stride = gridDim.x * blockDim.x;
+  const unsigned long long pre = s.prefix & himask;
+  const int stride = gridDim.x * 256;
   // the trip count is uniform across a wave (every lane takes part in the ballots)
-  for (int base = blockIdx.x * blockDim.x; base < n; base += stride) {
+  for (int base = blockIdx.x * 256; base < n; base += stride) {
     const int i = base + threadIdx.x;
     const double e = i < n ? eps[i] : 0.0;
     const unsigned long long key = dbits(e);
@@ -331,41 +372,28 @@ __global__ void radix_hist_kernel(const double* __restrict__ eps, int n, const S
     wave_hist_add(h, (unsigned)(key >> shift) & 255u, take);
   }
   __syncthreads();
-  unsigned int* copy = hist + (blockIdx.x % kHistCopies) * 256;
-  for (int t = threadIdx.x; t < 256; t += blockDim.x)
-    if (h[t]) atomicAdd(&copy[t], h[t]);
+  unsigned int* copy = hist3 + (p % 3) * kHistWords + (blockIdx.x % kHistCopies) * 256;
+  if (h[threadIdx.x]) atomicAdd(&copy[threadIdx.x], h[threadIdx.x]);
 }
 
-// One block of 256 threads, thread t on digit 255 - t: the exclusive prefix
-// over t is the count of keys with a larger digit; the thread whose bucket
-// holds the k-th largest key fixes the digit.  Clears the histogram copies.
-__global__ void radix_pick_kernel(SelectState* st, int shift, unsigned int* __restrict__ hist) {
+// The last digit (pass 7's buffer), then gmask = key > K and emask = key == K
+// (candidates for the remaining ties); workgroup 0 stores the final state in
+// slot 0 for the tie pass.  256 threads, grid-stride.
+__global__ void __launch_bounds__(256) radix_mark_kernel(const double* __restrict__ eps, int n,
+                                                         SelectState* __restrict__ st2,
+                                                         const unsigned int* __restrict__ hist3,
+                                                         uint8_t* __restrict__ gmask, uint8_t* __restrict__ emask) {
   __shared__ int wsum[256 / kWave];
-  const int d = 255 - (int)threadIdx.x;
-  int c = 0;
-#pragma unroll
-  for (int k = 0; k < kHistCopies; ++k) c += (int)hist[k * 256 + d];
-  const int above = block_exclusive_rank(c, wsum);
-  const long long k = st->k;
-  __syncthreads();
-  if (c > 0 && (long long)above < k && k <= (long long)above + c) {
-    st->prefix |= (unsigned long long)d << shift;
-    st->k = k - above;
+  __shared__ SelectState sh;
+  const SelectState s = radix_pick(hist3 + (7 % 3) * kHistWords, 0, st2[7 % 2], wsum, &sh);
+  if (blockIdx.x == 0 && threadIdx.x == 0) st2[0] = s;
+  const unsigned long long K = s.prefix;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const double e = eps[i];
+    const unsigned long long key = e > 0.0 ? dbits(e) : 0ull;
+    gmask[i] = (e > 0.0) && key > K;
+    emask[i] = (e > 0.0) && key == K;
   }
-#pragma unroll
-  for (int k = 0; k < kHistCopies; ++k) hist[k * 256 + d] = 0u;
-}
-
-// gmask = key > K, emask = key == K (candidates for the remaining ties).
-__global__ void mark_kernel(const double* __restrict__ eps, int n, const SelectState* st,
-                            uint8_t* __restrict__ gmask, uint8_t* __restrict__ emask) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double e = eps[i];
-  const unsigned long long K = st->prefix;
-  const unsigned long long key = e > 0.0 ? dbits(e) : 0ull;
-  gmask[i] = (e > 0.0) && key > K;
-  emask[i] = (e > 0.0) && key == K;
 }
 
 // ------------------------------------------------------------- block scan
@@ -550,13 +578,14 @@ __global__ void fill_u8_kernel(uint8_t* p, int n, uint8_t v) {
   if (i < n) p[i] = v;
 }
 
-// One block of 256 threads: the select state and cleared histogram copies.
-__global__ void init_state_kernel(SelectState* st, long long k, unsigned int* __restrict__ hist) {
+// One block of 256 threads: the state before the first digit (slot 1) and a
+// cleared first histogram buffer.
+__global__ void init_state_kernel(SelectState* st2, long long k, unsigned int* __restrict__ hist3) {
 #pragma unroll
-  for (int c = 0; c < kHistCopies; ++c) hist[c * 256 + threadIdx.x] = 0u;
+  for (int c = 0; c < kHistCopies; ++c) hist3[c * 256 + threadIdx.x] = 0u;
   if (threadIdx.x == 0) {
-    st->prefix = 0ull;
-    st->k = k;
+    st2[1].prefix = 0ull;
+    st2[1].k = k;
   }
 }
 
@@ -717,12 +746,10 @@ hs_status sample_select(hs_ctx* ctx, const double* eps, const hs_sample_params* 
   if (ng == 0) {
     HS_LAUNCH(ctx, fill_u8_kernel, nb, kBlock, s->gmask, n, (uint8_t)0);
   } else {
+    const int rb = blocks_for(n, 256, kRadixBlocks);
     HS_LAUNCH(ctx, init_state_kernel, 1, 256, state, ng, hist);
-    for (int shift = 56; shift >= 0; shift -= 8) {
-      HS_LAUNCH(ctx, radix_hist_kernel, blocks_for(n, kBlock, 2048), kBlock, eps, n, state, shift, hist);
-      HS_LAUNCH(ctx, radix_pick_kernel, 1, 256, state, shift, hist);
-    }
-    HS_LAUNCH(ctx, mark_kernel, nb, kBlock, eps, n, state, s->gmask, s->dtmp);
+    for (int p = 0; p < 8; ++p) HS_LAUNCH(ctx, radix_pass_kernel, rb, 256, eps, n, state, p, hist);
+    HS_LAUNCH(ctx, radix_mark_kernel, rb, 256, eps, n, state, hist, s->gmask, s->dtmp);
     HS_TRY(scan_blocks(ctx, s->dtmp, n, s->scan));
     HS_LAUNCH(ctx, tie_keep_kernel, blocks_for(n, kScanTile), kBlock, s->dtmp, n, s->scan, state, s->gmask);
   }

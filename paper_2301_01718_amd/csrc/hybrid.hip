@@ -874,10 +874,8 @@ static hs_status fit_factor(hs_ctx* ctx, const void* Phi, int prec, int m, const
   if (prec == HS_MIXED_FP32) HS_TRY(launch_fit_gram(ctx, (const float*)Phi, m, hat, ns, nb, wp, rows));
   else HS_TRY(launch_fit_gram(ctx, (const double*)Phi, m, hat, ns, nb, wp, rows));
   HS_LAUNCH(ctx, gram_reduce_kernel, m * m, kBlock, ctx->red, nb, wp, m, ctx->small + kSmG);
-  // small fits in one wave: its workgroup barriers cost next to nothing (the
-  // rotations and their order do not depend on the workgroup size)
-  HS_LAUNCH(ctx, pinv_kernel, 1, m <= 16 ? kWave : 256, ctx->small + kSmG, m, rcond, ctx->small + kSmGp,
-            ctx->small + kSmMisc, ctx->stats);
+  HS_LAUNCH(ctx, pinv_kernel, 1, 256, ctx->small + kSmG, m, rcond, ctx->small + kSmGp, ctx->small + kSmMisc,
+            ctx->stats);
   return HS_OK;
 }
 

@@ -154,16 +154,22 @@ __device__ inline void jacobi_eig_wave(double* A, double* V, int lda, int n, dou
         if (p > q) { const int x = p; p = q; q = x; }
         double c = 1.0, s = 0.0;
         if (q < n) {
+          // thresholds on squares (no square root), and the rotation with one
+          // square root, one division and one reciprocal square root:
+          // t = sign(d) e / (|d| + sqrt(d^2 + e^2)), d = (a_qq - a_pp) / 2,
+          // e = a_pq, is tan(theta) of the rotation that zeroes a_pq
           const double apq = A[p * lda + q];
           const double app = A[p * lda + p], aqq = A[q * lda + q];
-          const double lim = sqrt(fabs(app) * fabs(aqq));
-          if (fabs(apq) > atol && fabs(apq) > 2.2e-16 * lim) {
-            const double tau = (aqq - app) / (2.0 * apq);
-            const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + tt * tt);
+          const double lim2 = fabs(app) * fabs(aqq);
+          const double apq2 = apq * apq;
+          if (fabs(apq) > atol && apq2 > (2.2e-16 * 2.2e-16) * lim2) {
+            const double d = 0.5 * (aqq - app);
+            const double tt = (d >= 0.0 ? apq : -apq) / (fabs(d) + sqrt(d * d + apq2));
+            c = rsqrt(1.0 + tt * tt);
             s = tt * c;
             // rotations at the rounding level do not keep the sweeps going
-            if (fabs(apq) > (double)n * 2.2e-16 * lim) rotated = 1;
+            const double nt2 = (double)n * 2.2e-16;
+            if (apq2 > nt2 * nt2 * lim2) rotated = 1;
           }
         }
         pp[t] = p; qq[t] = q; cs[t] = c; sn[t] = s;

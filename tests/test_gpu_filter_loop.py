@@ -1,0 +1,66 @@
+"""The device-driven filter loop against the host-driven one and the oracle.
+
+rom_hybrid_step runs the residual-gated filter loop (Sec. 2.3.4) on a
+device-resident state: each pass is enqueued before the host has read the
+previous pass's decision.  A taped step (TAPE_RECORD) runs the same loop from
+the host, pass by pass.  Across filter parameters that reach every branch of
+the loop (a pass that keeps no cell, the relative-decrease stop, the pass
+bound j_f,max, one or several orders), the two must give the same state bit
+for bit and the same pass and kept counts; the state must match the
+oracle's hybrid step with the same parameters (1e-12).
+"""
+import numpy as np
+import pytest
+
+from oracle import fv, hybrid, pod, sampling
+
+from gpu_common import case, ctx_for, dev, host, need_gpu, print_case, rel, torch
+
+pytestmark = pytest.mark.gpu
+
+# (orders, eps_f, jfmax): default; one pass per order; no decrease stop (only
+# "nothing kept" or the bound end an order); an early decrease stop; a single
+# high order with a small bound
+PARAMS = [((1, 2, 3), 1e-2, 10), ((1, 2, 3), 1e-2, 1), ((1, 2, 3), 0.0, 4), ((2, 3), 0.9, 10),
+          ((3,), 1e-2, 2)]
+
+
+def setup(name):
+    wl, prob, q0 = case(name, 2)
+    w, m = 12, 8
+    snaps = [q0]
+    for _ in range(w):
+        snaps.append(fv.hdm_step(prob, snaps[-1])[0])
+    o = pod.pod(snaps, w, m)
+    g = snaps[-1]
+    eps, _ = sampling.indicator_full(prob, g, o["Phi"], o["psi_new"])
+    sel = sampling.select(prob, eps, sampling.RULE_FRACTION, wl.frac)
+    return prob, g, o["Phi"], o["psi_new"], o["m_eff"], sel
+
+
+@pytest.mark.parametrize("name", ["burgers2d", "euler2d"])
+def test_device_filter_loop_equals_host_loop(name):
+    need_gpu()
+    import paper_2301_01718_amd as hs
+    prob, g, Phi_o, psi, me, sel = setup(name)
+    ctx = ctx_for(prob)
+    s = ctx.samples_set(dev(sel["hat"]))
+    Phi = dev(np.ascontiguousarray(Phi_o.T).reshape(-1))
+    qg, psig = dev(g), dev(psi)
+    for orders, eps_f, jfmax in PARAMS:
+        print_case("filter loop", name, orders, eps_f, jfmax)
+        hp = hs.hybrid_params(filter_orders=orders, eps_f=eps_f, jfmax=jfmax)
+        dev_out, dinfo = ctx.rom_hybrid_step(qg, Phi, psig, me, s, hp)
+        tape = ctx.tape()
+        host_out, hinfo = ctx.rom_hybrid_step_taped(qg, Phi, psig, me, tape, hs.TAPE_RECORD, samples=s, params=hp)
+        print("  passes", dinfo["filter_passes"], hinfo["filter_passes"], "kept", dinfo["filter_kept"],
+              hinfo["filter_kept"], flush=True)
+        assert torch.equal(dev_out, host_out)
+        assert dinfo["filter_passes"] == hinfo["filter_passes"]
+        assert dinfo["filter_kept"] == hinfo["filter_kept"]
+        assert 1 <= dinfo["filter_passes"] <= len(orders) * jfmax
+        ref = hybrid.hybrid_step(prob, g, Phi_o, psi, sel["hat"], sel["tilde"],
+                                 hybrid.HybridParams(filter_orders=orders, eps_f=eps_f, jfmax=jfmax))
+        err = rel(host(dev_out), ref["gamma"])
+        print("  rel to oracle", err, flush=True)
+        assert err < 1e-12

@@ -2,9 +2,9 @@
 
 The forward map u_0 -> u_T of Alg. 1 contains non-differentiable decisions:
 the step schedule, the sampled sets, the subiteration count J, the filter
-masks, the rank of the basis and of the fit.  The adjoint here (reading:
-SURVEY C-12) differentiates the map with all of them frozen at their forward
-values, and with the bases Phi_k and reference states psi_k frozen as well
+masks, the rank of the basis and of the fit.  The paper gives no adjoint of
+its method; the one here (a reading of its Alg. 1 as a map of gamma_0)
+differentiates the map with all of them frozen at their forward values, and with the bases Phi_k and reference states psi_k frozen as well
 (they are functions of earlier snapshots; their derivatives are not taken).
 With those frozen, each step is a smooth map of its input gamma_{k-1}:
 

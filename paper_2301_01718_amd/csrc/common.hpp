@@ -120,6 +120,7 @@ struct hs_samples {
   int32_t* pos = nullptr;     // ncell, compact index of a hat-S cell or -1
   int32_t* nbr = nullptr;     // 4 * ncell, compact index of each stencil neighbour in hat-S or -1
   int32_t* scan = nullptr;    // scan scratch
+  int32_t* scan3 = nullptr;   // block sums of the three set compactions, then their totals
   uint8_t* tflag = nullptr;   // per tile of the context's tiling: holds a hat-S cell
   int32_t* tiles = nullptr;   // active tile ids (ntiles)
   int ntiles = 0;

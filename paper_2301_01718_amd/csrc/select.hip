@@ -412,7 +412,7 @@ __global__ void flag_count_kernel(const uint8_t* __restrict__ f, int n, int* __r
 }
 
 // Single block: exclusive scan of nb block sums in place; total to bsum[nb].
-__global__ void scan_bsums_kernel(int* __restrict__ bsum, int nb) {
+__device__ inline void scan_bsums_block(int* __restrict__ bsum, int nb) {
   __shared__ int carry;
   __shared__ int wsum[kBlock / kWave];
   if (threadIdx.x == 0) carry = 0;
@@ -420,7 +420,6 @@ __global__ void scan_bsums_kernel(int* __restrict__ bsum, int nb) {
   for (int base = 0; base < nb; base += kBlock) {
     const int i = base + threadIdx.x;
     const int v = i < nb ? bsum[i] : 0;
-    // inclusive wave scan
     int x = v;
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
 #pragma unroll
@@ -440,6 +439,8 @@ __global__ void scan_bsums_kernel(int* __restrict__ bsum, int nb) {
   }
   if (threadIdx.x == 0) bsum[nb] = carry;
 }
+
+__global__ void scan_bsums_kernel(int* __restrict__ bsum, int nb) { scan_bsums_block(bsum, nb); }
 
 // Compaction: list[offset] = i for every set flag, pos[i] = offset or -1.
 __global__ void compact_kernel(const uint8_t* __restrict__ f, int n, const int* __restrict__ bsum,
@@ -562,20 +563,61 @@ __global__ void scatter_mask_kernel(const int* __restrict__ list, int n, int nce
   if (c >= 0 && c < ncell) mask[c] = 1;   // out-of-range entries are dropped (count check fails)
 }
 
-// Flag the tile of every listed cell (all writers store the same value).
-__global__ void tile_flag_kernel(Grid g, const int* __restrict__ hat, int ns, int tx, int ty, int ntx,
-                                 uint8_t* __restrict__ tflag) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= ns) return;
-  const int cell = hat[p];
-  int i, j;
-  cell_ij(g, cell, i, j);
-  tflag[(j / ty) * ntx + i / tx] = 1;
-}
-
 __global__ void fill_u8_kernel(uint8_t* p, int n, uint8_t v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
+}
+
+// The tiles that hold a hat-S cell, from the mask (the same set as from the
+// list, available before the list is compacted).
+__global__ void tile_flag_mask_kernel(Grid g, const uint8_t* __restrict__ mask, int tx, int ty, int ntx,
+                                      uint8_t* __restrict__ tflag) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.ncell || !mask[c]) return;
+  int i, j;
+  cell_ij(g, c, i, j);
+  tflag[(j / ty) * ntx + i / tx] = 1;
+}
+
+// Three flag arrays compacted together: the block counts of all three in one
+// launch, the scans of the three block-sum arrays in another (one workgroup
+// each), then a compaction per array and one read-back of the three totals.
+struct Flags3 {
+  const uint8_t* f[3];
+  int n[3];
+  int nb[3];     // blocks_for(n, kScanTile)
+  int* bsum[3];  // nb + 1 entries each
+};
+
+__global__ void flag_count3_kernel(Flags3 fl) {
+  __shared__ int lds[kBlock / kWave];
+  int a = 0, b = blockIdx.x;
+  if (b >= fl.nb[0]) {
+    b -= fl.nb[0];
+    a = 1;
+    if (b >= fl.nb[1]) {
+      b -= fl.nb[1];
+      a = 2;
+    }
+  }
+  const uint8_t* f = fl.f[a];
+  const int n = fl.n[a];
+  const int base = b * kScanTile;
+  int c = 0;
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    const int i = base + r * kBlock + threadIdx.x;
+    if (i < n) c += f[i] != 0;
+  }
+  c = block_sum_int(c, lds);
+  if (threadIdx.x == 0) fl.bsum[a][b] = c;
+}
+
+// Workgroup a scans array a's block sums; the totals also go to totals[a].
+__global__ void scan_bsums3_kernel(Flags3 fl, int* __restrict__ totals) {
+  const int a = blockIdx.x;
+  scan_bsums_block(fl.bsum[a], fl.nb[a]);
+  if (threadIdx.x == 0) totals[a] = fl.bsum[a][fl.nb[a]];
 }
 
 // One block of 256 threads: the state before the first digit (slot 1) and a
@@ -636,31 +678,39 @@ static hs_status rre_count(hs_ctx* ctx, const double* eps, int n, double delta, 
   return HS_OK;
 }
 
-// Compact n flags into list (and pos); returns the count on the host.
-static hs_status compact(hs_ctx* ctx, hs_samples* s, const uint8_t* flags, int n, int* list, int* pos,
-                         int* count) {
-  const int nb = blocks_for(n, kScanTile);
-  HS_TRY(scan_blocks(ctx, flags, n, s->scan));
-  HS_LAUNCH(ctx, compact_kernel, nb, kBlock, flags, n, s->scan, list, pos);
-  return readback(ctx, s->scan + nb, sizeof(int), count);
-}
-
-// hat mask -> tilde mask, both lists, pos and the neighbour table.
+// hat mask -> tilde mask, both lists, pos, the neighbour table and the
+// active tiles of the tiled relaxation; one read-back for the three counts.
 static hs_status finish_sets(hs_ctx* ctx, hs_samples* s) {
   const int n = s->ncell;
   const int nb = blocks_for(n);
+  const int nt = ctx->sntx * ctx->snty;
   HS_LAUNCH(ctx, ring_kernel, nb, kBlock, ctx->g, s->mask, s->tmask);
-  HS_TRY(compact(ctx, s, s->mask, n, s->hat, s->pos, &s->n_s));
-  HS_TRY(compact(ctx, s, s->tmask, n, s->tilde, nullptr, &s->l));
+  HS_LAUNCH(ctx, fill_u8_kernel, blocks_for(nt), kBlock, s->tflag, nt, (uint8_t)0);
+  HS_LAUNCH(ctx, tile_flag_mask_kernel, nb, kBlock, ctx->g, s->mask, ctx->stile_x, ctx->stile_y, ctx->sntx,
+            s->tflag);
+  Flags3 fl;
+  const uint8_t* flags[3] = {s->mask, s->tmask, s->tflag};
+  const int lens[3] = {n, n, nt};
+  const size_t region = (size_t)n / kScanTile + 64;
+  for (int a = 0; a < 3; ++a) {
+    fl.f[a] = flags[a];
+    fl.n[a] = lens[a];
+    fl.nb[a] = blocks_for(lens[a], kScanTile);
+    fl.bsum[a] = s->scan3 + a * region;
+  }
+  int* totals = s->scan3 + 3 * region;
+  HS_LAUNCH(ctx, flag_count3_kernel, fl.nb[0] + fl.nb[1] + fl.nb[2], kBlock, fl);
+  HS_LAUNCH(ctx, scan_bsums3_kernel, 3, kBlock, fl, totals);
+  HS_LAUNCH(ctx, compact_kernel, fl.nb[0], kBlock, s->mask, n, fl.bsum[0], s->hat, s->pos);
+  HS_LAUNCH(ctx, compact_kernel, fl.nb[1], kBlock, s->tmask, n, fl.bsum[1], s->tilde, (int*)nullptr);
+  HS_LAUNCH(ctx, compact_kernel, fl.nb[2], kBlock, s->tflag, nt, fl.bsum[2], s->tiles, (int*)nullptr);
+  int cnt[3];
+  HS_TRY(readback(ctx, totals, sizeof cnt, cnt));
+  s->n_s = cnt[0];
+  s->l = cnt[1];
+  s->ntiles = cnt[2];
   if (s->n_s > 0)
     HS_LAUNCH(ctx, nbr_table_kernel, blocks_for(s->n_s), kBlock, ctx->g, s->hat, s->n_s, n, s->pos, s->nbr);
-  // active tiles of the tiled relaxation
-  const int nt = ctx->sntx * ctx->snty;
-  HS_LAUNCH(ctx, fill_u8_kernel, blocks_for(nt), kBlock, s->tflag, nt, (uint8_t)0);
-  if (s->n_s > 0)
-    HS_LAUNCH(ctx, tile_flag_kernel, blocks_for(s->n_s), kBlock, ctx->g, s->hat, s->n_s, ctx->stile_x,
-              ctx->stile_y, ctx->sntx, s->tflag);
-  HS_TRY(compact(ctx, s, s->tflag, nt, s->tiles, nullptr, &s->ntiles));
   return HS_OK;
 }
 
@@ -687,6 +737,7 @@ hs_status hs_samples_create(hs_ctx* ctx, hs_samples** out) {
   ok = ok && hipMalloc((void**)&s->tflag, nt + 64) == hipSuccess;
   ok = ok && hipMalloc((void**)&s->tiles, nt * 4 + 64) == hipSuccess;
   ok = ok && hipMalloc((void**)&s->scan, (n / kScanTile + 64) * 4 + sizeof(SelectState) + 64) == hipSuccess;
+  ok = ok && hipMalloc((void**)&s->scan3, (3 * (n / kScanTile + 64) + 64) * 4) == hipSuccess;
   if (!ok) {
     hs_samples_destroy(s);
     return ctx->fail(HS_ERR_OOM, "hipMalloc (samples)");
@@ -697,7 +748,7 @@ hs_status hs_samples_create(hs_ctx* ctx, hs_samples** out) {
 
 hs_status hs_samples_destroy(hs_samples* s) {
   if (!s) return HS_ERR_INVALID_ARG;
-  void* bufs[] = {s->gmask, s->mask, s->tmask, s->dtmp, s->hat, s->tilde, s->pos, s->nbr, s->scan,
+  void* bufs[] = {s->gmask, s->mask, s->tmask, s->dtmp, s->hat, s->tilde, s->pos, s->nbr, s->scan, s->scan3,
                   s->tflag, s->tiles};
   for (void* b : bufs)
     if (b) (void)hipFree(b);

@@ -382,17 +382,19 @@ __global__ void __launch_bounds__(256) radix_pass_kernel(const double* __restric
 __global__ void __launch_bounds__(256) radix_mark_kernel(const double* __restrict__ eps, int n,
                                                          SelectState* __restrict__ st2,
                                                          const unsigned int* __restrict__ hist3,
+                                                         const long long* __restrict__ ngd,
                                                          uint8_t* __restrict__ gmask, uint8_t* __restrict__ emask) {
   __shared__ int wsum[256 / kWave];
   __shared__ SelectState sh;
   const SelectState s = radix_pick(hist3 + (7 % 3) * kHistWords, 0, st2[7 % 2], wsum, &sh);
   if (blockIdx.x == 0 && threadIdx.x == 0) st2[0] = s;
   const unsigned long long K = s.prefix;
+  const bool any = *ngd > 0;   // n_g = 0: nothing is marked
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
     const double e = eps[i];
     const unsigned long long key = e > 0.0 ? dbits(e) : 0ull;
-    gmask[i] = (e > 0.0) && key > K;
-    emask[i] = (e > 0.0) && key == K;
+    gmask[i] = any && (e > 0.0) && key > K;
+    emask[i] = any && (e > 0.0) && key == K;
   }
 }
 
@@ -613,21 +615,31 @@ __global__ void flag_count3_kernel(Flags3 fl) {
   if (threadIdx.x == 0) fl.bsum[a][b] = c;
 }
 
-// Workgroup a scans array a's block sums; the totals also go to totals[a].
-__global__ void scan_bsums3_kernel(Flags3 fl, int* __restrict__ totals) {
+// Workgroup a scans array a's block sums; the totals also go to totals[a],
+// and n_g (when ngd is given) to totals[3].
+__global__ void scan_bsums3_kernel(Flags3 fl, int* __restrict__ totals, const long long* __restrict__ ngd) {
   const int a = blockIdx.x;
   scan_bsums_block(fl.bsum[a], fl.nb[a]);
   if (threadIdx.x == 0) totals[a] = fl.bsum[a][fl.nb[a]];
+  if (a == 0 && threadIdx.x == 0) totals[3] = ngd ? (int)*ngd : 0;
 }
 
-// One block of 256 threads: the state before the first digit (slot 1) and a
-// cleared first histogram buffer.
-__global__ void init_state_kernel(SelectState* st2, long long k, unsigned int* __restrict__ hist3) {
+// One block of 256 threads: the state before the first digit (slot 1), n_g
+// to ngd, and a cleared first histogram buffer.  k < 0: the fraction rule,
+// n_g = min(-k, #{eps > 0}) with the count from the statistics slot.
+__global__ void init_state_kernel(SelectState* st2, long long k, unsigned int* __restrict__ hist3,
+                                  const unsigned long long* __restrict__ stats, long long* ngd) {
 #pragma unroll
   for (int c = 0; c < kHistCopies; ++c) hist3[c * 256 + threadIdx.x] = 0u;
   if (threadIdx.x == 0) {
+    long long ng = k;
+    if (k < 0) {
+      const long long npos = (long long)__longlong_as_double((long long)stats[kStatCount]);
+      ng = -k < npos ? -k : npos;
+    }
     st2[1].prefix = 0ull;
-    st2[1].k = k;
+    st2[1].k = ng;
+    *ngd = ng;
   }
 }
 
@@ -680,7 +692,7 @@ static hs_status rre_count(hs_ctx* ctx, const double* eps, int n, double delta, 
 
 // hat mask -> tilde mask, both lists, pos, the neighbour table and the
 // active tiles of the tiled relaxation; one read-back for the three counts.
-static hs_status finish_sets(hs_ctx* ctx, hs_samples* s) {
+static hs_status finish_sets(hs_ctx* ctx, hs_samples* s, const long long* ngd = nullptr) {
   const int n = s->ncell;
   const int nb = blocks_for(n);
   const int nt = ctx->sntx * ctx->snty;
@@ -700,15 +712,16 @@ static hs_status finish_sets(hs_ctx* ctx, hs_samples* s) {
   }
   int* totals = s->scan3 + 3 * region;
   HS_LAUNCH(ctx, flag_count3_kernel, fl.nb[0] + fl.nb[1] + fl.nb[2], kBlock, fl);
-  HS_LAUNCH(ctx, scan_bsums3_kernel, 3, kBlock, fl, totals);
+  HS_LAUNCH(ctx, scan_bsums3_kernel, 3, kBlock, fl, totals, ngd);
   HS_LAUNCH(ctx, compact_kernel, fl.nb[0], kBlock, s->mask, n, fl.bsum[0], s->hat, s->pos);
   HS_LAUNCH(ctx, compact_kernel, fl.nb[1], kBlock, s->tmask, n, fl.bsum[1], s->tilde, (int*)nullptr);
   HS_LAUNCH(ctx, compact_kernel, fl.nb[2], kBlock, s->tflag, nt, fl.bsum[2], s->tiles, (int*)nullptr);
-  int cnt[3];
+  int cnt[4];
   HS_TRY(readback(ctx, totals, sizeof cnt, cnt));
   s->n_s = cnt[0];
   s->l = cnt[1];
   s->ntiles = cnt[2];
+  if (ngd) s->n_g = cnt[3];
   if (s->n_s > 0)
     HS_LAUNCH(ctx, nbr_table_kernel, blocks_for(s->n_s), kBlock, ctx->g, s->hat, s->n_s, n, s->pos, s->nbr);
   return HS_OK;
@@ -778,32 +791,30 @@ hs_status sample_select(hs_ctx* ctx, const double* eps, const hs_sample_params* 
   const int nb = blocks_for(n);
   const int nbp = blocks_for(n, kBlock, 1024);
   HS_LAUNCH(ctx, count_positive_kernel, nbp, kBlock, eps, n, ctx->part);
-  unsigned long long st[kStatSlots];
-  HS_TRY(finish_stats(ctx, nbp, 1u << kStatQMax, 1u << kStatCount, st));
-  const long long npos = (long long)bits_to_double(st[kStatCount]);
-  const double emx = bits_to_double(st[kStatQMax]);
-  long long ng;
-  if (sp->rule == HS_RULE_FRACTION) {
-    // n_g = min(ceil(f * ncell), #{eps > 0})
-    const long long want = (long long)std::ceil(sp->fraction * (double)n);
-    ng = std::min(want, npos);
-  } else {
-    HS_TRY(rre_count(ctx, eps, n, sp->delta, npos, emx, &ng));
-  }
-  s->n_g = (int)ng;
-
   SelectState* state = reinterpret_cast<SelectState*>(s->scan + state_offset(n));
+  long long* ngd = reinterpret_cast<long long*>(state + 2);
   unsigned int* hist = reinterpret_cast<unsigned int*>(ctx->ibuf);
-  if (ng == 0) {
-    HS_LAUNCH(ctx, fill_u8_kernel, nb, kBlock, s->gmask, n, (uint8_t)0);
+  long long k;   // the init kernel's rank argument
+  if (sp->rule == HS_RULE_FRACTION) {
+    // n_g = min(ceil(f * ncell), #{eps > 0}), formed on the device and read
+    // back with the set sizes
+    HS_TRY(finish_stats(ctx, nbp, 1u << kStatQMax, 1u << kStatCount));
+    const long long want = (long long)std::ceil(sp->fraction * (double)n);
+    k = -want;
+    if (want == 0) k = 0;
   } else {
-    const int rb = blocks_for(n, 256, kRadixBlocks);
-    HS_LAUNCH(ctx, init_state_kernel, 1, 256, state, ng, hist);
-    for (int p = 0; p < 8; ++p) HS_LAUNCH(ctx, radix_pass_kernel, rb, 256, eps, n, state, p, hist);
-    HS_LAUNCH(ctx, radix_mark_kernel, rb, 256, eps, n, state, hist, s->gmask, s->dtmp);
-    HS_TRY(scan_blocks(ctx, s->dtmp, n, s->scan));
-    HS_LAUNCH(ctx, tie_keep_kernel, blocks_for(n, kScanTile), kBlock, s->dtmp, n, s->scan, state, s->gmask);
+    unsigned long long st[kStatSlots];
+    HS_TRY(finish_stats(ctx, nbp, 1u << kStatQMax, 1u << kStatCount, st));
+    const long long npos = (long long)bits_to_double(st[kStatCount]);
+    const double emx = bits_to_double(st[kStatQMax]);
+    HS_TRY(rre_count(ctx, eps, n, sp->delta, npos, emx, &k));
   }
+  const int rb = blocks_for(n, 256, kRadixBlocks);
+  HS_LAUNCH(ctx, init_state_kernel, 1, 256, state, k, hist, (const unsigned long long*)ctx->stats, ngd);
+  for (int p = 0; p < 8; ++p) HS_LAUNCH(ctx, radix_pass_kernel, rb, 256, eps, n, state, p, hist);
+  HS_LAUNCH(ctx, radix_mark_kernel, rb, 256, eps, n, state, hist, (const long long*)ngd, s->gmask, s->dtmp);
+  HS_TRY(scan_blocks(ctx, s->dtmp, n, s->scan));
+  HS_LAUNCH(ctx, tie_keep_kernel, blocks_for(n, kScanTile), kBlock, s->dtmp, n, s->scan, state, s->gmask);
   // hat-S = dilate(G): x, then y
   const uint8_t* src = s->gmask;
   if (ctx->g.kind == HS_BURGERS_1D) {
@@ -812,7 +823,7 @@ hs_status sample_select(hs_ctx* ctx, const double* eps, const hs_sample_params* 
     HS_LAUNCH(ctx, dilate_kernel, nb, kBlock, ctx->g, src, s->dtmp, 0, sp->halo);
     HS_LAUNCH(ctx, dilate_kernel, nb, kBlock, ctx->g, s->dtmp, s->mask, 1, sp->halo);
   }
-  return finish_sets(ctx, s);
+  return finish_sets(ctx, s, ngd);
 }
 
 hs_status hs_samples_set(hs_ctx* ctx, hs_samples* s, const int32_t* hat, int32_t n_s) {

@@ -356,7 +356,8 @@ hs_status newton_solve(hs_ctx* ctx, double* q, const double* q_prev, double tol,
 // host applies it to the same ||dy|| from the posted stats); *total as in the
 // primed array.
 hs_status newton_first_ctrl(hs_ctx* ctx, double* q, const double* q_prev, double tol, const hs_samples* s,
-                            int sub_check, double eps_y, unsigned long long* st, int* total);
+                            int sub_check, double eps_y, unsigned long long* st, int* total,
+                            bool tol_from_qmax = false);
 hs_status newton_first_launch(hs_ctx* ctx, const double* q, const double* q_prev, const hs_samples* s,
                               unsigned long long* st);
 // max |x| into the QMax statistics slot (enqueued only).
@@ -393,6 +394,7 @@ struct NewtonCtrl {
   int lin_maxit = 0;
   int sub_check = 0;       // also the subiteration stop test: no sweeps when ||y_j - y_{j-1}|| < eps_y
   double eps_y = 0.0;
+  double rtol_qmax = 0.0;  // > 0: tol = rtol_qmax max(1, max |q_prev|) from the statistics (tol, scale unused)
   unsigned long long* stats = nullptr;
   uint32_t* dst = nullptr;
   uint32_t* tagp = nullptr;

@@ -350,11 +350,13 @@ static hs_status resjac_launch(hs_ctx* ctx, const double* q, const double* q_pre
 // no sweeps ran).
 template <int NC>
 static hs_status resjac_ctrl(hs_ctx* ctx, double* q, const double* q_prev, double tol, const hs_samples* s,
-                             unsigned long long* st, int* total, int sub_check = 0, double eps_y = 0.0) {
+                             unsigned long long* st, int* total, int sub_check = 0, double eps_y = 0.0,
+                             bool tol_from_qmax = false) {
   HS_TRY(resjac_launch<NC>(ctx, q, q_prev, s, nullptr, false));
   NewtonCtrl c;
   c.sub_check = sub_check;
   c.eps_y = eps_y;
+  if (tol_from_qmax) c.rtol_qmax = ctx->p.newton_rtol;
   c.part = ctx->part;
   c.nb = stat_blocks(s ? s->n_s : ctx->ncell);
   c.tol = tol;
@@ -378,9 +380,11 @@ static hs_status resjac_ctrl(hs_ctx* ctx, double* q, const double* q_prev, doubl
 }
 
 hs_status newton_first_ctrl(hs_ctx* ctx, double* q, const double* q_prev, double tol, const hs_samples* s,
-                            int sub_check, double eps_y, unsigned long long* st, int* total) {
+                            int sub_check, double eps_y, unsigned long long* st, int* total, bool tol_from_qmax) {
   if (!newton_ctrl_ok(ctx, s)) return ctx->fail(HS_ERR_INVALID_ARG, "device Newton decision needs scalar tiles");
-  return resjac_ctrl<1>(ctx, q, q_prev, tol, s, st, total, sub_check, eps_y);
+  if (tol_from_qmax && !(ctx->p.newton_rtol > 0.0))
+    return ctx->fail(HS_ERR_INVALID_ARG, "tolerance from max |q_prev| needs newton_rtol > 0");
+  return resjac_ctrl<1>(ctx, q, q_prev, tol, s, st, total, sub_check, eps_y, tol_from_qmax);
 }
 
 hs_status newton_first_launch(hs_ctx* ctx, const double* q, const double* q_prev, const hs_samples* s,

@@ -950,12 +950,26 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const void* Phi,
   double* u = ctx->u;
   double* sm = ctx->small;
   // max |q_prev| (Newton tolerance) and the fit factorisation, read together
-  // (with a pending basis the factorisation follows the first Newton solve)
+  // (with a pending basis the factorisation follows the first Newton solve);
+  // with the device decision they come back with the first Newton
+  // iteration, whose sweep launch forms the tolerance from the same value
   HS_TRY(max_abs_launch(ctx, q_prev, ctx->n));
   HIP_TRY(ctx, hipMemcpyAsync(u, q_prev, ctx->n * 8, hipMemcpyDeviceToDevice, ctx->stream));
   if (!pending) HS_TRY(fit_factor(ctx, Phi, prec, m, s->hat, s->n_s, hp->rcond_fit));
   unsigned long long st[kStatSlots];
-  HS_TRY(read_stats(ctx, st));
+  double primed[3];
+  bool have_primed = false;
+  const bool ctrl = newton_ctrl_ok(ctx, s) && ctx->p.newton_rtol > 0.0;
+  if (ctrl) {
+    int dev_total = 0;
+    HS_TRY(newton_first_ctrl(ctx, u, q_prev, 0.0, s, 0, 0.0, st, &dev_total, true));
+    primed[0] = bits_to_double(st[kStatResMax]);
+    primed[1] = bits_to_double(st[kStatRho]);
+    primed[2] = dev_total;
+    have_primed = true;
+  } else {
+    HS_TRY(read_stats(ctx, st));
+  }
   const double qmax = bits_to_double(st[kStatQMax]);
   if (!std::isfinite(qmax)) return ctx->fail(HS_ERR_NONFINITE, "non-finite q_prev");
   const double tol = ctx->p.newton_rtol * std::max(1.0, qmax);
@@ -969,9 +983,6 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const void* Phi,
   // Subiterations.  The stop test on ||y_j - y_{j-1}|| is read together with
   // the residual of the next Newton solve's first iteration, launched
   // speculatively (it changes no state, so it is simply dropped on a stop).
-  double primed[3];
-  bool have_primed = false;
-  const bool ctrl = newton_ctrl_ok(ctx, s);
   for (int j = 1; j <= jmax; ++j) {
     HS_TRY(newton_solve(ctx, u, q_prev, tol, s, inf, have_primed ? primed : nullptr));
     if (pending && j == 1) {

@@ -81,8 +81,15 @@ __global__ void __launch_bounds__(NT) tile_sweep_kernel(
     rm = block_max(rm, lds);
     rh = block_max(rh, lds);
     if (threadIdx.x == 0) {
+      NewtonCtrl c = ctl;
+      if (c.rtol_qmax > 0.0) {
+        // the tolerance the host forms from the same max |q_prev|
+        const double qm = __longlong_as_double((long long)ctl.stats[kStatQMax]);
+        c.tol = c.rtol_qmax * fmax(1.0, qm);
+        c.scale = fmax(1.0, c.tol / c.rtol_qmax);
+      }
       const double dy = __longlong_as_double((long long)ctl.stats[kStatDy]);
-      const int total = (ctl.sub_check && dy < ctl.eps_y) ? 0 : newton_sweeps(rm, rh, ctl);
+      const int total = (c.sub_check && dy < c.eps_y) ? 0 : newton_sweeps(rm, rh, c);
       s_total = total;
       if (blockIdx.x == 0) {
         ctl.stats[kStatResMax] = dbits(rm);

@@ -985,6 +985,7 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const void* Phi,
   // speculatively (it changes no state, so it is simply dropped on a stop).
   for (int j = 1; j <= jmax; ++j) {
     HS_TRY(newton_solve(ctx, u, q_prev, tol, s, inf, have_primed ? primed : nullptr));
+    have_primed = false;   // consumed: a replayed subiteration launches its own first iteration
     if (pending && j == 1) {
       int32_t me = 0;
       guard.active = false;

@@ -68,6 +68,33 @@ def hybrid_setup(name, seed=0):
     return prob, g, Phi_o, psi, o["m_eff"], sel
 
 
+@pytest.mark.parametrize("name", ["burgers1d", "burgers2d"])
+def test_taped_step_with_device_newton_decisions(name):
+    """With tiles forced on every set, scalar Newton solves take their
+    decisions on the device (the first sweep launch of each iteration); a
+    recorded step and its replay (which skips the subiteration stop test and
+    launches each subiteration's first Newton iteration itself) must still
+    reproduce the plain step bit for bit."""
+    need_gpu()
+    print_case("taped step, device Newton decisions", name)
+    import paper_2301_01718_amd as hs
+    prob, g, Phi_o, psi, me, sel = hybrid_setup(name)
+    ctx = ctx_for(prob)
+    ctx.set_tiled_sweeps("always")
+    s = ctx.samples_set(dev(sel["hat"]))
+    Phi = dev(np.ascontiguousarray(Phi_o.T).reshape(-1))
+    qg, psig = dev(g), dev(psi)
+    plain, pinfo = ctx.rom_hybrid_step(qg, Phi, psig, me, s)
+    tape = ctx.tape()
+    rec, _ = ctx.rom_hybrid_step_taped(qg, Phi, psig, me, tape, hs.TAPE_RECORD, samples=s)
+    rep, rinfo = ctx.rom_hybrid_step_taped(qg, Phi, psig, me, tape, hs.TAPE_REPLAY)
+    print("  J", pinfo["subiters"], "newton", pinfo["newton_iters"], rinfo["newton_iters"], flush=True)
+    assert pinfo["subiters"] >= 2
+    assert torch.equal(rec, plain)
+    assert torch.equal(rep, plain)
+    assert rinfo["newton_iters"] == pinfo["newton_iters"]
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_hybrid_step_adjoint_matches_oracle(name):
     need_gpu()

@@ -983,6 +983,7 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const void* Phi,
   // Subiterations.  The stop test on ||y_j - y_{j-1}|| is read together with
   // the residual of the next Newton solve's first iteration, launched
   // speculatively (it changes no state, so it is simply dropped on a stop).
+  bool fit_check = false;   // the fit factorised after the pending basis: its rank still to read
   for (int j = 1; j <= jmax; ++j) {
     HS_TRY(newton_solve(ctx, u, q_prev, tol, s, inf, have_primed ? primed : nullptr));
     have_primed = false;   // consumed: a replayed subiteration launches its own first iteration
@@ -992,9 +993,9 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const void* Phi,
       HS_TRY(basis_finish_pending(ctx, &me));
       if (me < 1 || me > ctx->p.m_max) return ctx->fail(HS_ERR_RANK, "empty basis");
       m = me;
+      // its rank and condition come back with this subiteration's decision
       HS_TRY(fit_factor(ctx, Phi, prec, m, s->hat, s->n_s, hp->rcond_fit));
-      HS_TRY(read_stats(ctx, st));
-      HS_TRY(fit_stats());
+      fit_check = true;
     }
     if (replay)
       HIP_TRY(ctx, hipMemcpyAsync(tape->us + (size_t)(j - 1) * ctx->n, u, ctx->n * 8, hipMemcpyDeviceToDevice,
@@ -1010,6 +1011,10 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const void* Phi,
     if (more && ctrl) HS_TRY(newton_first_ctrl(ctx, u, q_prev, tol, s, j >= 2, hp->eps_y, st, &dev_total));
     else if (more) HS_TRY(newton_first_launch(ctx, u, q_prev, s, st));
     else HS_TRY(read_stats(ctx, st));
+    if (fit_check) {
+      fit_check = false;
+      HS_TRY(fit_stats());
+    }
     const double dy = bits_to_double(st[kStatDy]);
     inf->dy_last = dy;
     if (!more || (j >= 2 && dy < hp->eps_y)) break;

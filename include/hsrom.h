@@ -295,6 +295,13 @@ hs_status rom_hybrid_step_adjoint(hs_ctx* ctx, const double* Phi, int32_t m, con
  * the tile list fits the statistics capacity.  All give the same iterates bit
  * for bit (a switch for measurement and testing). */
 #define HS_OPT_TILED_SWEEPS 1
+/* HS_OPT_SMALL_PINV: the fit's truncated pseudo-inverse (eq. red_coord) for
+ * m <= 8 basis columns.  1 (default): one wavefront with the matrix in
+ * registers; 0: the general LDS routine used for every m.  Both take the same
+ * Jacobi rotations in the same order and give the same result bit for bit (a
+ * switch for measurement and testing). */
+#define HS_OPT_SMALL_PINV 2
+/* Returns HS_ERR_INVALID_ARG for an unknown option or a value out of range. */
 hs_status hs_set_option(hs_ctx* ctx, int32_t option, int64_t value);
 
 /* ------------------------------------------------------- measurement */

@@ -239,6 +239,12 @@ class Context:
         v = 2 if mode == "always" else (1 if mode else 0)
         self._check(lib().hs_set_option(self.h, 1, v))
 
+    def set_small_pinv(self, on):
+        """The fit's pseudo-inverse for m <= 8: True = one wavefront with the
+        matrix in registers (default); False = the general LDS routine.  The
+        results are the same bit for bit."""
+        self._check(lib().hs_set_option(self.h, 2, 1 if on else 0))
+
     # ---------------------------------------------------------- measurement
     def prof_enable(self, kernel_class):
         cls = PROF_CLASSES[kernel_class] if isinstance(kernel_class, str) else kernel_class

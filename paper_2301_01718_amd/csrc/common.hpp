@@ -85,6 +85,8 @@ struct hs_ctx {
   // the same for sampled sets (smaller tiles: a set fills a few of them)
   int stile_x = 0, stile_y = 0, stile_s = 0, sntx = 0, snty = 0;
   int tiled = 1;
+  // fit pseudo-inverse for m <= 8: 1 = one wave in registers, 0 = LDS routine
+  int small_pinv = 1;
   double* red = nullptr;      // reduction partials (kRedBlocks * 64 * 64 doubles)
   double* small = nullptr;    // small dense matrices and vectors (16 * 64 * 64 doubles)
   unsigned long long* stats = nullptr;   // kStatSlots

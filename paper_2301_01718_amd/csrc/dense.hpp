@@ -121,6 +121,9 @@ static __global__ void gram_reduce_kernel(const double* __restrict__ part, int n
 // A (n x n, row-major) is overwritten.  LDS: A, V (64 x 65 each).
 __device__ inline void jacobi_eig_wave(double* A, double* V, int lda, int n, double* lam, int* order,
                                        int max_sweeps) {
+  // every product and sum rounded on its own (no contraction), so that the
+  // register variant for m <= 8 takes the same rotations to the bit
+#pragma clang fp contract(off)
   const int t = threadIdx.x;
   const int nt = blockDim.x;
   for (int i = t; i < n * lda; i += nt) V[i] = 0.0;

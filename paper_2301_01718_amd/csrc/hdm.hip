@@ -696,6 +696,10 @@ hs_status hs_set_option(hs_ctx* ctx, int32_t option, int64_t value) {
     ctx->tiled = (int)value;
     return HS_OK;
   }
+  if (option == HS_OPT_SMALL_PINV && (value == 0 || value == 1)) {
+    ctx->small_pinv = (int)value;
+    return HS_OK;
+  }
   return HS_ERR_INVALID_ARG;
 }
 

@@ -59,6 +59,7 @@ struct GatherLoader {
 __global__ void __launch_bounds__(256) pinv_kernel(const double* __restrict__ G, int m, double rcond,
                                                   double* __restrict__ Gp, double* __restrict__ misc,
                                                   unsigned long long* __restrict__ stats) {
+#pragma clang fp contract(off)
   __shared__ double A[kMaxBasis * (kMaxBasis + 1)], V[kMaxBasis * (kMaxBasis + 1)];
   __shared__ double lam[kMaxBasis];
   __shared__ int order[kMaxBasis];
@@ -85,6 +86,113 @@ __global__ void __launch_bounds__(256) pinv_kernel(const double* __restrict__ G,
     double s = 0.0;
     for (int i = 0; i < rank; ++i) s += V[r * lda + order[i]] * V[c * lda + order[i]] / lam[i];
     Gp[e] = s;
+  }
+}
+
+// The same truncated pseudo-inverse for m <= 8 in one wave with the matrix in
+// registers: lane 8 i + j holds A[i][j] and V[i][j].  Each round every lane
+// fetches the entries of its row pair and of its 2 x 2 block by cross-lane
+// reads, forms the row pair's rotation, reads its column pair's from lane
+// (j, j) and updates its own entry, so a round has no LDS round trip and no
+// barrier.  Schedule, thresholds, rotation formulas and
+// update order are those of jacobi_eig_wave, so the result is the same to the
+// bit (both round every product and sum on its own).  Launch: one block of
+// 64 threads.
+__device__ inline int rr_partner(int x, int r, int np) {   // 0 <= r < np - 1
+  const int np1 = np - 1;
+  if (x >= np) return x;
+  if (x == np1) return r;
+  int y = 2 * r - x;
+  if (y < 0) y += np1;
+  if (y >= np1) y -= np1;
+  return y == x ? np1 : y;
+}
+
+__global__ void __launch_bounds__(64) pinv_small_kernel(const double* __restrict__ G, int m, double rcond,
+                                                       double* __restrict__ Gp, double* __restrict__ misc,
+                                                       unsigned long long* __restrict__ stats) {
+#pragma clang fp contract(off)
+  constexpr int D = 8;
+  __shared__ double Vs[D * (D + 1)];
+  __shared__ double lam[D];
+  __shared__ int order[D];
+  const int l = threadIdx.x, i = l / D, j = l % D;
+  const bool in = i < m && j < m;
+  double a = in ? G[i * m + j] : 0.0;
+  double v = (in && i == j) ? 1.0 : 0.0;
+  // atol = eps * sum_i |a_ii| in index order, the same in every lane
+  double tr = 0.0;
+  for (int k = 0; k < m; ++k) tr += fabs(__shfl(a, k * D + k, kWave));
+  const double atol = 2.2e-16 * tr;
+  const int np = (m + 1) & ~1;
+  const double nt2 = (double)m * 2.2e-16;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    int big = 0;
+    for (int r = 0; r < np - 1; ++r) {
+      const int pi = rr_partner(i, r, np), pj = rr_partner(j, r, np);
+      const int rp = min(i, pi), rq = max(i, pi), cp = min(j, pj), cq = max(j, pj);
+      // entries of the row pair and of this lane's 2 x 2 block (padding lanes
+      // hold zeros; the indices are < 8)
+      const double app = __shfl(a, rp * D + rp, kWave), aqq = __shfl(a, rq * D + rq, kWave);
+      const double apq = __shfl(a, rp * D + rq, kWave);
+      const double a00 = __shfl(a, rp * D + cp, kWave), a01 = __shfl(a, rp * D + cq, kWave);
+      const double a10 = __shfl(a, rq * D + cp, kWave), a11 = __shfl(a, rq * D + cq, kWave);
+      const double vo = __shfl(v, i * D + (j == cp ? cq : cp), kWave);
+      // rotation of the row pair (c = 1, s = 0 if none); lane (j, j) holds the
+      // one of this lane's column pair
+      double ck = 1.0, sk = 0.0;
+      if (rq < m) {
+        const double lim2 = fabs(app) * fabs(aqq);
+        const double apq2 = apq * apq;
+        if (fabs(apq) > atol && apq2 > (2.2e-16 * 2.2e-16) * lim2) {
+          const double d = 0.5 * (aqq - app);
+          const double tt = (d >= 0.0 ? apq : -apq) / (fabs(d) + sqrt(d * d + apq2));
+          ck = rsqrt(1.0 + tt * tt);
+          sk = tt * ck;
+          if (apq2 > nt2 * nt2 * lim2) big = 1;
+        }
+      }
+      const double cl = __shfl(ck, j * D + j, kWave), sl = __shfl(sk, j * D + j, kWave);
+      const bool rqv = rq < m, cqv = cq < m;
+      const double x01 = cqv ? a01 : 0.0, x10 = rqv ? a10 : 0.0, x11 = (rqv && cqv) ? a11 : 0.0;
+      // rows, then columns (the order of jacobi_eig_wave)
+      const double b00 = ck * a00 - sk * x10, b01 = ck * x01 - sk * x11;
+      const double b10 = sk * a00 + ck * x10, b11 = sk * x01 + ck * x11;
+      if (i == rp) a = j == cp ? cl * b00 - sl * b01 : sl * b00 + cl * b01;
+      else a = j == cp ? cl * b10 - sl * b11 : sl * b10 + cl * b11;
+      if (sl != 0.0) v = j == cp ? cl * v - sl * vo : sl * vo + cl * v;
+      if (!in) a = 0.0, v = 0.0;
+    }
+    if (!__any(big)) break;
+  }
+  if (in) Vs[i * (D + 1) + j] = v;
+  // stable descending order of the diagonal (cross-lane reads by all lanes)
+  const int ld = min(l, D - 1);
+  const double li = __shfl(a, ld * D + ld, kWave);
+  int rk = 0;
+  for (int k = 0; k < m; ++k) {
+    const double lk = __shfl(a, k * D + k, kWave);
+    rk += (lk > li) || (lk == li && k < l);
+  }
+  if (l < m) {
+    lam[rk] = li;
+    order[rk] = l;
+  }
+  __syncthreads();
+  int rank = 0;
+  const double lmax = lam[0];
+  for (int k = 0; k < m; ++k)
+    if (lmax > 0.0 && lam[k] > rcond * rcond * lmax) rank = k + 1;
+  if (l == 0) {
+    misc[1] = rank;
+    misc[2] = rank > 0 ? sqrt(lmax / lam[rank - 1]) : 0.0;
+    stats[kStatFitRank] = dbits((double)rank);
+    stats[kStatFitCond] = dbits(misc[2]);
+  }
+  if (in) {
+    double s = 0.0;
+    for (int k = 0; k < rank; ++k) s += Vs[i * (D + 1) + order[k]] * Vs[j * (D + 1) + order[k]] / lam[k];
+    Gp[i * m + j] = s;
   }
 }
 
@@ -874,8 +982,12 @@ static hs_status fit_factor(hs_ctx* ctx, const void* Phi, int prec, int m, const
   if (prec == HS_MIXED_FP32) HS_TRY(launch_fit_gram(ctx, (const float*)Phi, m, hat, ns, nb, wp, rows));
   else HS_TRY(launch_fit_gram(ctx, (const double*)Phi, m, hat, ns, nb, wp, rows));
   HS_LAUNCH(ctx, gram_reduce_kernel, m * m, kBlock, ctx->red, nb, wp, m, ctx->small + kSmG);
-  HS_LAUNCH(ctx, pinv_kernel, 1, 256, ctx->small + kSmG, m, rcond, ctx->small + kSmGp, ctx->small + kSmMisc,
-            ctx->stats);
+  if (ctx->small_pinv && m >= 1 && m <= 8)
+    HS_LAUNCH(ctx, pinv_small_kernel, 1, kWave, ctx->small + kSmG, m, rcond, ctx->small + kSmGp,
+              ctx->small + kSmMisc, ctx->stats);
+  else
+    HS_LAUNCH(ctx, pinv_kernel, 1, 256, ctx->small + kSmG, m, rcond, ctx->small + kSmGp, ctx->small + kSmMisc,
+              ctx->stats);
   return HS_OK;
 }
 

@@ -200,6 +200,39 @@ def test_hybrid_step_matches_oracle(name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
+def test_small_pinv_equals_lds_pinv(name):
+    """The one-wave register pseudo-inverse of the fit (m <= 8) takes the
+    LDS routine's rotations in the same order: the hybrid step is the same bit
+    for bit with either, over several basis widths."""
+    need_gpu()
+    wl, prob, q0 = case(name, 0)
+    w = 12
+    snaps = window(prob, q0, w)
+    ctx = ctx_for(prob)
+    g = snaps[-1]
+    for m in (1, 3, 5, 8):
+        o = pod.pod(snaps, w, m)
+        Phi_o, psi, me = o["Phi"], o["psi_new"], o["m_eff"]
+        print_case("small pinv", name, "m", m, "m_eff", me)
+        eps, _ = sampling.indicator_full(prob, g, Phi_o, psi)
+        sel = sampling.select(prob, eps, sampling.RULE_FRACTION, wl.frac)
+        s = ctx.samples_set(dev(sel["hat"]))
+        Phi = dev(np.ascontiguousarray(Phi_o.T).reshape(-1))
+        outs = []
+        for on in (True, False):
+            ctx.set_small_pinv(on)
+            y_g = ctx.empty(me)
+            out, info = ctx.rom_hybrid_step(dev(g), Phi, dev(psi), me, s, y=y_g)
+            outs.append((out, y_g, info))
+        ctx.set_small_pinv(True)
+        (o1, y1, i1), (o2, y2, i2) = outs
+        assert torch.equal(o1, o2)
+        assert torch.equal(y1, y2)
+        assert i1["subiters"] == i2["subiters"]
+        assert i1["fit_rank"] == i2["fit_rank"] and i1["fit_cond"] == i2["fit_cond"]
+
+
+@pytest.mark.parametrize("name", list(CASES))
 def test_tiled_sweeps_equal_list_sweeps(name):
     """The LDS-tiled relaxation (several sweeps per launch) and the one-sweep
     compact-list relaxation give the same iterates bit for bit: full and

@@ -43,6 +43,8 @@ enum StatSlot : int {
   kStatSum0 = 11,      // l1 sum of the cell residual norms before a filter order
   kStatSum = 12,       // the same after a filter pass
   kStatSweeps = 13,    // sweeps of the Newton correction decided on the device (integer; -1: batch form)
+  kStatFiltCount1 = 14,  // kept count and residual sum of a device-driven filter pass with an odd
+  kStatFiltSum1 = 15,    // index (partials only: even passes use kStatCount / kStatSum)
   kStatSlots = 16
 };
 

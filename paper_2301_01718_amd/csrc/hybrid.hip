@@ -503,12 +503,52 @@ struct FiltCtl {
 };
 
 // The gate kernel's view of that state (ctl == nullptr: a host-driven pass).
+// Device-driven pass k reads the state of pass k - 1 from ctl[(k - 1) & 1],
+// advances it with that pass's kept count and residual sum (reduced from its
+// partials by every workgroup alike) and stores it to ctl[k & 1]; workgroup 0
+// posts the record of pass k - 1.  Pass 0 runs the initial state ctl[0].
 struct FiltSpec {
-  const FiltCtl* ctl = nullptr;
+  FiltCtl* ctl = nullptr;
   double* state[2] = {nullptr, nullptr};   // gamma, spare
   double* norms[2] = {nullptr, nullptr};   // r, r2
   int orders[4] = {0, 0, 0, 0};
+  int pass = 0, nb = 0;                    // k; partial count of every pass
+  int n_orders = 0, jfmax = 0;
+  double eps_f = 0.0;
+  unsigned long long* stats = nullptr;     // kStatCount / kStatSum of pass k - 1
+  PostSlot post{};                         // the record of pass k - 1 (k >= 1)
 };
+
+// Partial slots of device pass k (alternating, so pass k + 1 reads them while
+// writing its own).
+__host__ __device__ inline int filt_count_slot(int k) { return (k & 1) ? kStatFiltCount1 : kStatCount; }
+__host__ __device__ inline int filt_sum_slot(int k) { return (k & 1) ? kStatFiltSum1 : kStatSum; }
+
+// One step of the filter loop after a pass that kept `kept` cells and left
+// the l1 residual sum `sum`, as the host loop takes it (no cell kept: next
+// order; else swap the buffers, and stop the order when the relative
+// decrease falls below eps_f or after jfmax passes).
+__device__ inline FiltCtl filt_advance(FiltCtl c, long long kept, double sum, int n_orders, int jfmax,
+                                       double eps_f) {
+#pragma clang fp contract(off)
+  c.passes += 1;
+  c.kept += (int)kept;
+  if (kept == 0) {
+    c.o += 1;
+    c.it = 0;
+  } else {
+    c.parity ^= 1;
+    const double dec = (c.sum_r - sum) / c.sum_r;
+    c.sum_r = sum;
+    c.it += 1;
+    if (dec < eps_f || c.it >= jfmax) {
+      c.o += 1;
+      c.it = 0;
+    }
+  }
+  if (c.o >= n_orders) c.done = 1;
+  return c;
+}
 
 template <int NC, int TX, int TY>
 __global__ void __launch_bounds__(kBlock) filter_gate_kernel(
@@ -534,10 +574,59 @@ __global__ void __launch_bounds__(kBlock) filter_gate_kernel(
   const bool per = g.bc == HS_BC_PERIODIC;
   double rsum = 0.0;
   int kept = 0;
+  int cslot = kStatCount, sslot = kStatSum;
   if (fs.ctl != nullptr) {
     // the pass the device state asks for, or none once the loop is done
-    const FiltCtl c = *fs.ctl;
+    const int k = fs.pass;
+    FiltCtl c = fs.ctl[k == 0 ? 0 : (k - 1) & 1];
+    if (k > 0) {
+      // pass k - 1's kept count and residual sum: the same strided order and
+      // tree in every workgroup (and as finish_stats reduces them)
+      __shared__ unsigned long long rec[8];
+      const FiltCtl c0 = c;
+      double cnt = 0.0, sum = 0.0;
+      if (!c0.done) {
+        const int cs = filt_count_slot(k - 1), ss = filt_sum_slot(k - 1);
+        for (int b = threadIdx.x; b < fs.nb; b += blockDim.x) {
+          cnt = cnt + part[cs * kPartCap + b];
+          sum = sum + part[ss * kPartCap + b];
+        }
+        cnt = block_sum(cnt, lds);
+        sum = block_sum(sum, lds);
+        __shared__ double bc[2];   // thread 0's results to the workgroup
+        if (threadIdx.x == 0) {
+          bc[0] = cnt;
+          bc[1] = sum;
+        }
+        __syncthreads();
+        cnt = bc[0];
+        sum = bc[1];
+        c = filt_advance(c0, (long long)cnt, sum, fs.n_orders, fs.jfmax, fs.eps_f);
+      }
+      if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) {
+          fs.ctl[k & 1] = c;
+          const bool ran = !c0.done;
+          if (ran) {
+            fs.stats[kStatCount] = dbits(cnt);
+            fs.stats[kStatSum] = dbits(sum);
+          }
+          rec[0] = ran ? (unsigned long long)(long long)cnt : 0ull;
+          rec[1] = ran ? dbits(sum) : 0ull;
+          rec[2] = (unsigned long long)c.done;
+          rec[3] = (unsigned long long)c.parity;
+          rec[4] = (unsigned long long)c.passes;
+          rec[5] = (unsigned long long)c.kept;
+          rec[6] = ran ? 1ull : 0ull;
+        }
+        __syncthreads();
+        if (threadIdx.x < kWave) post_words(reinterpret_cast<const uint32_t*>(rec), 14, fs.post.dst, fs.post.tagp,
+                                            fs.post.tag);
+      }
+    }
     if (c.done) return;
+    cslot = filt_count_slot(k);
+    sslot = filt_sum_slot(k);
     nord = fs.orders[c.o];
     cur = fs.state[c.parity];
     merged = fs.state[c.parity ^ 1];
@@ -633,8 +722,8 @@ __global__ void __launch_bounds__(kBlock) filter_gate_kernel(
   const double bs = block_sum(rsum, lds);
   const int bk = block_sum_int(kept, reinterpret_cast<int*>(lds));
   if (threadIdx.x == 0) {
-    stat_part(part, kStatSum, bs);
-    stat_part(part, kStatCount, (double)bk);
+    stat_part(part, sslot, bs);
+    stat_part(part, cslot, (double)bk);
   }
 }
 
@@ -650,68 +739,6 @@ __global__ void filt_init_kernel(FiltCtl* ctl, const unsigned long long* __restr
   c.kept = 0;
   c.sum_r = __longlong_as_double((long long)stats[kStatSum0]);
   *ctl = c;
-}
-
-// Finisher of a device-driven pass (one workgroup of kBlock): the kept count
-// and the merged state's l1 residual sum reduced as finish_stats reduces them
-// (same order, same tree), the loop advanced as the host loop does it (no
-// cell kept: next order; else swap the buffers, stop the order when the
-// relative decrease falls below eps_f or after jfmax passes), and the record
-// {kept, sum, done, parity, passes, kept total, ran} posted to the host.
-__global__ void filt_finish_kernel(const double* __restrict__ part, int nb, FiltCtl* ctl, int n_orders,
-                                   int jfmax, double eps_f, unsigned long long* __restrict__ stats, PostSlot post) {
-  __shared__ double lds[kBlock / kWave];
-  __shared__ unsigned long long rec[8];
-  const FiltCtl c0 = *ctl;
-  if (!c0.done) {
-    double cnt = 0.0, sum = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-      cnt = cnt + part[kStatCount * kPartCap + b];
-      sum = sum + part[kStatSum * kPartCap + b];
-    }
-    cnt = block_sum(cnt, lds);
-    sum = block_sum(sum, lds);
-    if (threadIdx.x == 0) {
-      stats[kStatCount] = dbits(cnt);
-      stats[kStatSum] = dbits(sum);
-      FiltCtl c = c0;
-      const long long kept = (long long)cnt;
-      c.passes += 1;
-      c.kept += (int)kept;
-      if (kept == 0) {
-        c.o += 1;
-        c.it = 0;
-      } else {
-        c.parity ^= 1;
-        const double dec = (c.sum_r - sum) / c.sum_r;
-        c.sum_r = sum;
-        c.it += 1;
-        if (dec < eps_f || c.it >= jfmax) {
-          c.o += 1;
-          c.it = 0;
-        }
-      }
-      if (c.o >= n_orders) c.done = 1;
-      *ctl = c;
-      rec[0] = (unsigned long long)kept;
-      rec[1] = dbits(sum);
-      rec[2] = (unsigned long long)c.done;
-      rec[3] = (unsigned long long)c.parity;
-      rec[4] = (unsigned long long)c.passes;
-      rec[5] = (unsigned long long)c.kept;
-      rec[6] = 1ull;
-    }
-  } else if (threadIdx.x == 0) {
-    rec[0] = 0ull;
-    rec[1] = 0ull;
-    rec[2] = 1ull;
-    rec[3] = (unsigned long long)c0.parity;
-    rec[4] = (unsigned long long)c0.passes;
-    rec[5] = (unsigned long long)c0.kept;
-    rec[6] = 0ull;
-  }
-  __syncthreads();
-  if (threadIdx.x < kWave) post_words(reinterpret_cast<const uint32_t*>(rec), 14, post.dst, post.tagp, post.tag);
 }
 
 // Tile of the fused filter pass (must match the instantiations in filter_pass).
@@ -730,16 +757,18 @@ static hs_status filter_gate_launch(hs_ctx* ctx, const double* cur, const double
   const int ntx = (ctx->g.nx + tx - 1) / tx;
   const int ntiles = ntx * ((ctx->g.ny + ty - 1) / ty);
   const int nb = std::min(ntiles, kPartCap);
+  FiltSpec f = fs;
+  f.nb = nb;   // every pass of a grid has the same partial count
   HS_TRY(prof_begin(ctx, HS_PROF_FILTER));
   if (ctx->g.kind == HS_BURGERS_1D)
     HS_LAUNCH(ctx, (filter_gate_kernel<1, 512, 1>), nb, kBlock, ctx->g, ntx, ntiles, nord, cur, q_prev, r, merged,
-              r2, keep_out, ctx->part, fs);
+              r2, keep_out, ctx->part, f);
   else if (ctx->nc == 1)
     HS_LAUNCH(ctx, (filter_gate_kernel<1, 32, 32>), nb, kBlock, ctx->g, ntx, ntiles, nord, cur, q_prev, r, merged,
-              r2, keep_out, ctx->part, fs);
+              r2, keep_out, ctx->part, f);
   else
     HS_LAUNCH(ctx, (filter_gate_kernel<4, 16, 16>), nb, kBlock, ctx->g, ntx, ntiles, nord, cur, q_prev, r, merged,
-              r2, keep_out, ctx->part, fs);
+              r2, keep_out, ctx->part, f);
   // reads: the state, q_prev and r once; writes: merged, r2 and the decisions
   HS_TRY(prof_end(ctx, HS_PROF_FILTER,
                   (double)ctx->ncell * (8.0 * ctx->nc * 3 + 8.0 * 2 + (keep_out ? 1.0 : 0.0))));
@@ -797,13 +826,13 @@ static hs_status filter_apply(hs_ctx* ctx, const double* in, double* out, int no
 // the merged state's cell residual norms are read together (when nothing was
 // kept the merged state equals the current one, so the sum is unchanged).
 // The norms carry over from one filter order to the next (same state).
-// The filter loop driven by the device state (no recording): each pass is
-// enqueued with its finisher one pass ahead of the host, which reads the
-// records in order and stops enqueueing once one says the loop is done (the
-// pass already enqueued behind it then does nothing).
+// The filter loop driven by the device state (no recording): the host keeps
+// two passes enqueued beyond the last record it has read (pass k + 1 posts
+// the record of pass k), and stops enqueueing once a record says the loop is
+// done (the pass that posted it then did nothing).
 static hs_status run_filter_device(hs_ctx* ctx, double* gamma, const double* q_prev, const hs_hybrid_params* hp,
                                    hs_step_info* info) {
-  FiltCtl* ctl = reinterpret_cast<FiltCtl*>(ctx->small + kSmFilt);
+  FiltCtl* ctl = reinterpret_cast<FiltCtl*>(ctx->small + kSmFilt);   // two slots
   HS_TRY(cell_residual_launch(ctx, gamma, q_prev, ctx->rcell, kStatSum0));
   HS_LAUNCH(ctx, filt_init_kernel, 1, 1, ctl, (const unsigned long long*)ctx->stats, 0);
   FiltSpec fs;
@@ -813,27 +842,33 @@ static hs_status run_filter_device(hs_ctx* ctx, double* gamma, const double* q_p
   fs.norms[0] = ctx->rcell;
   fs.norms[1] = ctx->rcell2;
   for (int o = 0; o < hp->n_orders; ++o) fs.orders[o] = hp->filter_orders[o];
+  fs.n_orders = hp->n_orders;
+  fs.jfmax = hp->jfmax;
+  fs.eps_f = hp->eps_f;
+  fs.stats = ctx->stats;
   const long long max_passes = (long long)hp->n_orders * hp->jfmax;
   long long enqueued = 0;
+  // pass k = enqueued; for k >= 1 it posts the record of pass k - 1 to *p
   auto enqueue = [&](PostSlot* p) -> hs_status {
     int nb;
+    fs.pass = (int)enqueued;
+    fs.post = p ? (*p = post_slot(ctx)) : PostSlot{};
     // the pointers and the order come from the device state
     HS_TRY(filter_gate_launch(ctx, gamma, q_prev, ctx->rcell, 1, ctx->gtmp, ctx->rcell2, nullptr, fs, &nb));
-    *p = post_slot(ctx);
-    HS_LAUNCH(ctx, filt_finish_kernel, 1, kBlock, ctx->part, nb, ctl, hp->n_orders, hp->jfmax, hp->eps_f,
-              ctx->stats, *p);
     ++enqueued;
     return HS_OK;
   };
-  PostSlot pend[2];
-  HS_TRY(enqueue(&pend[0]));
-  HS_TRY(enqueue(&pend[1]));
+  // one record is outstanding at a time: that of pass k, posted by pass k + 1
+  // (running or queued), while pass k + 2 is enqueued once it is read
+  PostSlot pend;
+  HS_TRY(enqueue(nullptr));
+  HS_TRY(enqueue(&pend));
   unsigned long long rec[8];
-  for (long long k = 0;; ++k) {
-    HS_TRY(await_post(ctx, pend[k % 2], rec, 7 * sizeof(unsigned long long)));
+  for (;;) {
+    HS_TRY(await_post(ctx, pend, rec, 7 * sizeof(unsigned long long)));
     if (rec[2]) break;
     if (enqueued > max_passes) return ctx->fail(HS_ERR_INVALID_ARG, "filter loop ran past its pass bound");
-    HS_TRY(enqueue(&pend[k % 2]));
+    HS_TRY(enqueue(&pend));
   }
   if (info) {
     info->filter_passes += (int)rec[4];

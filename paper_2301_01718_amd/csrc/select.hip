@@ -322,14 +322,28 @@ constexpr int kRadixBlocks = 512;               // workgroups of a digit pass
 // exclusive prefix over t counts the keys with a larger digit, and the
 // bucket holding the k-th largest key fixes the digit.  Returns the state
 // after that digit (the same in every workgroup).
+// With ngd != nullptr (the first digit, whose histogram holds every positive
+// key) the rank is first capped at #{eps > 0}: n_g = min(k, #{eps > 0}) of
+// the fraction rule, stored to *ngd by workgroup 0.
 __device__ inline SelectState radix_pick(const unsigned int* __restrict__ hist, int shift, SelectState s,
-                                         int* wsum, SelectState* sh) {
+                                         int* wsum, SelectState* sh, long long* ngd = nullptr) {
   const int d = 255 - (int)threadIdx.x;
   int c = 0;
 #pragma unroll
   for (int k = 0; k < kHistCopies; ++k) c += (int)hist[k * 256 + d];
   if (threadIdx.x == 0) *sh = s;
   const int above = block_exclusive_rank(c, wsum);
+  if (ngd != nullptr) {
+    __shared__ long long npos;
+    if (threadIdx.x == 255) npos = (long long)above + c;
+    __syncthreads();
+    if (s.k > npos) s.k = npos;
+    if (threadIdx.x == 0) {
+      sh->k = s.k;
+      if (blockIdx.x == 0) *ngd = s.k;
+    }
+    __syncthreads();
+  }
   if (c > 0 && (long long)above < s.k && s.k <= (long long)above + c) {
     sh->prefix = s.prefix | ((unsigned long long)d << shift);
     sh->k = s.k - above;
@@ -348,7 +362,8 @@ __device__ inline SelectState radix_pick(const unsigned int* __restrict__ hist, 
 // pass after it fills.  States alternate over two slots.
 __global__ void __launch_bounds__(256) radix_pass_kernel(const double* __restrict__ eps, int n,
                                                          SelectState* __restrict__ st2, int p,
-                                                         unsigned int* __restrict__ hist3) {
+                                                         unsigned int* __restrict__ hist3,
+                                                         long long* __restrict__ ngd) {
   __shared__ unsigned int h[256];
   __shared__ int wsum[256 / kWave];
   __shared__ SelectState sh;
@@ -357,7 +372,7 @@ __global__ void __launch_bounds__(256) radix_pass_kernel(const double* __restric
   unsigned int* nxt = hist3 + ((p + 1) % 3) * kHistWords;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < kHistWords; i += gridDim.x * 256) nxt[i] = 0u;
   SelectState s = st2[(p + 1) % 2];
-  if (p > 0) s = radix_pick(hist3 + ((p - 1) % 3) * kHistWords, shift + 8, s, wsum, &sh);
+  if (p > 0) s = radix_pick(hist3 + ((p - 1) % 3) * kHistWords, shift + 8, s, wsum, &sh, p == 1 ? ngd : nullptr);
   if (blockIdx.x == 0 && threadIdx.x == 0) st2[p % 2] = s;
   __syncthreads();
   const unsigned long long himask = shift >= 56 ? 0ull : (~0ull << (shift + 8));
@@ -627,19 +642,14 @@ __global__ void scan_bsums3_kernel(Flags3 fl, int* __restrict__ totals, const lo
 // One block of 256 threads: the state before the first digit (slot 1), n_g
 // to ngd, and a cleared first histogram buffer.  k < 0: the fraction rule,
 // n_g = min(-k, #{eps > 0}) with the count from the statistics slot.
-__global__ void init_state_kernel(SelectState* st2, long long k, unsigned int* __restrict__ hist3,
-                                  const unsigned long long* __restrict__ stats, long long* ngd) {
+// Initial state of a selection of rank k (capped at #{eps > 0} by the first
+// digit pick, which also stores n_g).
+__global__ void init_state_kernel(SelectState* st2, long long k, unsigned int* __restrict__ hist3) {
 #pragma unroll
   for (int c = 0; c < kHistCopies; ++c) hist3[c * 256 + threadIdx.x] = 0u;
   if (threadIdx.x == 0) {
-    long long ng = k;
-    if (k < 0) {
-      const long long npos = (long long)__longlong_as_double((long long)stats[kStatCount]);
-      ng = -k < npos ? -k : npos;
-    }
     st2[1].prefix = 0ull;
-    st2[1].k = ng;
-    *ngd = ng;
+    st2[1].k = k;
   }
 }
 
@@ -790,19 +800,17 @@ hs_status sample_select(hs_ctx* ctx, const double* eps, const hs_sample_params* 
   const int n = ctx->ncell;
   const int nb = blocks_for(n);
   const int nbp = blocks_for(n, kBlock, 1024);
-  HS_LAUNCH(ctx, count_positive_kernel, nbp, kBlock, eps, n, ctx->part);
   SelectState* state = reinterpret_cast<SelectState*>(s->scan + state_offset(n));
   long long* ngd = reinterpret_cast<long long*>(state + 2);
   unsigned int* hist = reinterpret_cast<unsigned int*>(ctx->ibuf);
-  long long k;   // the init kernel's rank argument
+  long long k;   // the rank the digit passes look for
   if (sp->rule == HS_RULE_FRACTION) {
-    // n_g = min(ceil(f * ncell), #{eps > 0}), formed on the device and read
-    // back with the set sizes
-    HS_TRY(finish_stats(ctx, nbp, 1u << kStatQMax, 1u << kStatCount));
-    const long long want = (long long)std::ceil(sp->fraction * (double)n);
-    k = -want;
-    if (want == 0) k = 0;
+    // n_g = min(ceil(f * ncell), #{eps > 0}): the first digit pick caps the
+    // rank at the positive count of its histogram and stores n_g, read back
+    // with the set sizes
+    k = (long long)std::ceil(sp->fraction * (double)n);
   } else {
+    HS_LAUNCH(ctx, count_positive_kernel, nbp, kBlock, eps, n, ctx->part);
     unsigned long long st[kStatSlots];
     HS_TRY(finish_stats(ctx, nbp, 1u << kStatQMax, 1u << kStatCount, st));
     const long long npos = (long long)bits_to_double(st[kStatCount]);
@@ -810,8 +818,8 @@ hs_status sample_select(hs_ctx* ctx, const double* eps, const hs_sample_params* 
     HS_TRY(rre_count(ctx, eps, n, sp->delta, npos, emx, &k));
   }
   const int rb = blocks_for(n, 256, kRadixBlocks);
-  HS_LAUNCH(ctx, init_state_kernel, 1, 256, state, k, hist, (const unsigned long long*)ctx->stats, ngd);
-  for (int p = 0; p < 8; ++p) HS_LAUNCH(ctx, radix_pass_kernel, rb, 256, eps, n, state, p, hist);
+  HS_LAUNCH(ctx, init_state_kernel, 1, 256, state, k, hist);
+  for (int p = 0; p < 8; ++p) HS_LAUNCH(ctx, radix_pass_kernel, rb, 256, eps, n, state, p, hist, ngd);
   HS_LAUNCH(ctx, radix_mark_kernel, rb, 256, eps, n, state, hist, (const long long*)ngd, s->gmask, s->dtmp);
   HS_TRY(scan_blocks(ctx, s->dtmp, n, s->scan));
   HS_LAUNCH(ctx, tie_keep_kernel, blocks_for(n, kScanTile), kBlock, s->dtmp, n, s->scan, state, s->gmask);

@@ -71,7 +71,10 @@ def test_sample_select_bit_exact(name):
     eps[10:20] = eps[100]                  # ties at various places
     eps[200:260] = 0.5
     ctx = ctx_for(prob)
-    for frac in (0.0, 0.01, wl.frac, 0.3, 1.0):
+    # fractions above and below the positive share (the cap n_g <= #{eps > 0}),
+    # then an error field without a positive entry
+    cases = [(eps, frac) for frac in (0.0, 0.01, wl.frac, 0.3, 1.0)] + [(np.zeros(prob.ncell), 0.3)]
+    for eps, frac in cases:
         o = sampling.select(prob, eps, sampling.RULE_FRACTION, frac, halo=2)
         s = ctx.sample_select(dev(eps), frac, halo=2)
         c = s.counts()

@@ -460,14 +460,16 @@ __device__ inline void scan_bsums_block(int* __restrict__ bsum, int nb) {
 __global__ void scan_bsums_kernel(int* __restrict__ bsum, int nb) { scan_bsums_block(bsum, nb); }
 
 // Compaction: list[offset] = i for every set flag, pos[i] = offset or -1.
-__global__ void compact_kernel(const uint8_t* __restrict__ f, int n, const int* __restrict__ bsum,
-                               int* __restrict__ list, int* __restrict__ pos) {
+// Block b of a stream compaction: list[rank] = i for the flagged i of its
+// tile (bsum: exclusive scan of the tiles' counts); pos[i] = rank or -1.
+__device__ inline void compact_block(const uint8_t* __restrict__ f, int n, const int* __restrict__ bsum,
+                                     int* __restrict__ list, int* __restrict__ pos, int b) {
   __shared__ int wsum[kBlock / kWave];
   __shared__ int run;
   if (threadIdx.x == 0) run = 0;
   __syncthreads();
-  const int base = blockIdx.x * kScanTile;
-  const int off = bsum[blockIdx.x];
+  const int base = b * kScanTile;
+  const int off = bsum[b];
   for (int r = 0; r < kScanItems; ++r) {
     const int i = base + r * kBlock + threadIdx.x;
     const int flag = (i < n) && f[i];
@@ -528,8 +530,11 @@ __global__ void dilate_kernel(Grid g, const uint8_t* __restrict__ in, uint8_t* _
 }
 
 // tilde-S: face neighbours of hat-S that are not in hat-S.
-__global__ void ring_kernel(Grid g, const uint8_t* __restrict__ mask, uint8_t* __restrict__ tmask) {
+// (It also clears the nt tile flags that tile_flag_mask_kernel sets next.)
+__global__ void ring_kernel(Grid g, const uint8_t* __restrict__ mask, uint8_t* __restrict__ tmask,
+                            uint8_t* __restrict__ tflag, int nt) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < nt) tflag[c] = 0;
   if (c >= g.ncell) return;
   if (mask[c]) {
     tmask[c] = 0;
@@ -630,6 +635,27 @@ __global__ void flag_count3_kernel(Flags3 fl) {
   if (threadIdx.x == 0) fl.bsum[a][b] = c;
 }
 
+// The three compactions of the sets (hat-S with positions, tilde-S, active
+// tiles) in one launch: blocks [0, nb0) take array 0, the next nb1 array 1,
+// the rest array 2 (the split of flag_count3_kernel).
+struct Lists3 {
+  int* list[3];
+  int* pos0;
+};
+
+__global__ void compact3_kernel(Flags3 fl, Lists3 out) {
+  int a = 0, b = blockIdx.x;
+  if (b >= fl.nb[0]) {
+    b -= fl.nb[0];
+    a = 1;
+    if (b >= fl.nb[1]) {
+      b -= fl.nb[1];
+      a = 2;
+    }
+  }
+  compact_block(fl.f[a], fl.n[a], fl.bsum[a], out.list[a], a == 0 ? out.pos0 : nullptr, b);
+}
+
 // Workgroup a scans array a's block sums; the totals also go to totals[a],
 // and n_g (when ngd is given) to totals[3].
 __global__ void scan_bsums3_kernel(Flags3 fl, int* __restrict__ totals, const long long* __restrict__ ngd) {
@@ -706,8 +732,8 @@ static hs_status finish_sets(hs_ctx* ctx, hs_samples* s, const long long* ngd = 
   const int n = s->ncell;
   const int nb = blocks_for(n);
   const int nt = ctx->sntx * ctx->snty;
-  HS_LAUNCH(ctx, ring_kernel, nb, kBlock, ctx->g, s->mask, s->tmask);
-  HS_LAUNCH(ctx, fill_u8_kernel, blocks_for(nt), kBlock, s->tflag, nt, (uint8_t)0);
+  // the ring's grid covers the tile flags (nt <= n)
+  HS_LAUNCH(ctx, ring_kernel, nb, kBlock, ctx->g, s->mask, s->tmask, s->tflag, nt);
   HS_LAUNCH(ctx, tile_flag_mask_kernel, nb, kBlock, ctx->g, s->mask, ctx->stile_x, ctx->stile_y, ctx->sntx,
             s->tflag);
   Flags3 fl;
@@ -723,9 +749,8 @@ static hs_status finish_sets(hs_ctx* ctx, hs_samples* s, const long long* ngd = 
   int* totals = s->scan3 + 3 * region;
   HS_LAUNCH(ctx, flag_count3_kernel, fl.nb[0] + fl.nb[1] + fl.nb[2], kBlock, fl);
   HS_LAUNCH(ctx, scan_bsums3_kernel, 3, kBlock, fl, totals, ngd);
-  HS_LAUNCH(ctx, compact_kernel, fl.nb[0], kBlock, s->mask, n, fl.bsum[0], s->hat, s->pos);
-  HS_LAUNCH(ctx, compact_kernel, fl.nb[1], kBlock, s->tmask, n, fl.bsum[1], s->tilde, (int*)nullptr);
-  HS_LAUNCH(ctx, compact_kernel, fl.nb[2], kBlock, s->tflag, nt, fl.bsum[2], s->tiles, (int*)nullptr);
+  const Lists3 lists{{s->hat, s->tilde, s->tiles}, s->pos};
+  HS_LAUNCH(ctx, compact3_kernel, fl.nb[0] + fl.nb[1] + fl.nb[2], kBlock, fl, lists);
   int cnt[4];
   HS_TRY(readback(ctx, totals, sizeof cnt, cnt));
   s->n_s = cnt[0];

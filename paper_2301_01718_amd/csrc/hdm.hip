@@ -195,9 +195,17 @@ hs_status finish_stats(hs_ctx* ctx, int nb, unsigned max_mask, unsigned sum_mask
   return HS_OK;
 }
 
+// The per-block maxima of |x| only (slot kStatQMax of ctx->part, *nb of them),
+// for a kernel that reduces them itself.
+hs_status max_abs_partials(hs_ctx* ctx, const double* x, long long n, int* nb) {
+  *nb = blocks_for(n, kBlock, 1024);
+  HS_LAUNCH(ctx, max_abs_kernel, *nb, kBlock, x, n, ctx->part);
+  return HS_OK;
+}
+
 hs_status max_abs_launch(hs_ctx* ctx, const double* x, long long n) {
-  const int nb = blocks_for(n, kBlock, 1024);
-  HS_LAUNCH(ctx, max_abs_kernel, nb, kBlock, x, n, ctx->part);
+  int nb;
+  HS_TRY(max_abs_partials(ctx, x, n, &nb));
   return finish_stats(ctx, nb, 1u << kStatQMax, 0u);
 }
 

@@ -322,15 +322,26 @@ __global__ void eye_kernel(double* __restrict__ A, int m) {
   if (e < m * m) A[e] = (e / m == e % m) ? 1.0 : 0.0;
 }
 
+// max_abs_partials (hdm.hip): per-block maxima of |x| in slot kStatQMax.
+hs_status max_abs_partials(hs_ctx* ctx, const double* x, long long n, int* nb);
+
 // eps_cell = sum_c (gamma - rho)^2, flushed to 0 below fl^2 with
-// fl = floor_rel * max(1, max |gamma|) (max |gamma| from the QMax slot).
+// fl = floor_rel * max(1, max |gamma|).  Every workgroup reduces max |gamma|
+// from the nbq partials of max_abs_partials (a maximum is exact in any order).
 __global__ void indicator_kernel(int ncell, int nc, const double* __restrict__ gamma,
                                  const double* __restrict__ rho, double floor_rel,
-                                 const unsigned long long* __restrict__ stats, double* __restrict__ eps) {
+                                 const double* __restrict__ qpart, int nbq, double* __restrict__ eps) {
 #pragma clang fp contract(off)
+  __shared__ double lds[kBlock / kWave];
+  __shared__ double qmax;
+  double qm = 0.0;
+  for (int b = threadIdx.x; b < nbq; b += blockDim.x) qm = fmax(qm, qpart[kStatQMax * kPartCap + b]);
+  qm = block_max(qm, lds);
+  if (threadIdx.x == 0) qmax = qm;
+  __syncthreads();
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncell) return;
-  const double fl = floor_rel * fmax(1.0, __longlong_as_double((long long)stats[kStatQMax]));
+  const double fl = floor_rel * fmax(1.0, qmax);
   const double floor2 = fl * fl;
   double e = 0.0;
   for (int a = 0; a < nc; ++a) {
@@ -727,18 +738,28 @@ __global__ void __launch_bounds__(kBlock) filter_gate_kernel(
   }
 }
 
-// Initial state of the device-driven filter loop; the l1 sum of the input
-// state's residual norms comes from the statistics slot kStatSum0.
-__global__ void filt_init_kernel(FiltCtl* ctl, const unsigned long long* __restrict__ stats, int done) {
-  FiltCtl c;
-  c.o = 0;
-  c.it = 0;
-  c.parity = 0;
-  c.done = done;
-  c.passes = 0;
-  c.kept = 0;
-  c.sum_r = __longlong_as_double((long long)stats[kStatSum0]);
-  *ctl = c;
+// Initial state of the device-driven filter loop (one workgroup of kBlock):
+// the l1 sum of the input state's residual norms reduced from the nb block
+// partials of cellres_kernel as sum_finish_kernel reduces them (same order,
+// same tree), also stored to the statistics slot kStatSum0.
+__global__ void filt_init_kernel(FiltCtl* ctl, const double* __restrict__ part, int nb,
+                                 unsigned long long* __restrict__ stats, int done) {
+  __shared__ double lds[kBlock / kWave];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[b];
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) {
+    stats[kStatSum0] = dbits(s);
+    FiltCtl c;
+    c.o = 0;
+    c.it = 0;
+    c.parity = 0;
+    c.done = done;
+    c.passes = 0;
+    c.kept = 0;
+    c.sum_r = s;
+    *ctl = c;
+  }
 }
 
 // Tile of the fused filter pass (must match the instantiations in filter_pass).
@@ -785,13 +806,23 @@ static hs_status filter_pass(hs_ctx* ctx, const double* cur, const double* q_pre
   return finish_stats(ctx, nb, 0u, (1u << kStatCount) | (1u << kStatSum), st);
 }
 
-hs_status cell_residual_launch(hs_ctx* ctx, const double* q, const double* q_prev, double* rcell, int slot) {
+// Cell residual norms of q to rcell; their l1 sum is left as *nb block
+// partials in ctx->red.
+static hs_status cell_residual_partials(hs_ctx* ctx, const double* q, const double* q_prev, double* rcell,
+                                        int* nb_out) {
   const int nb = blocks_for(ctx->ncell);
   if (nb > kRedBlocks * 64) return ctx->fail(HS_ERR_SHAPE, "grid too large for the reduction buffer");
   HS_TRY(prof_begin(ctx, HS_PROF_CELLRES));
   if (ctx->nc == 1) HS_LAUNCH(ctx, cellres_kernel<1>, nb, kBlock, ctx->g, q, q_prev, rcell, ctx->red);
   else HS_LAUNCH(ctx, cellres_kernel<4>, nb, kBlock, ctx->g, q, q_prev, rcell, ctx->red);
   HS_TRY(prof_end(ctx, HS_PROF_CELLRES, (double)ctx->ncell * (16.0 * ctx->nc + 8.0)));
+  *nb_out = nb;
+  return HS_OK;
+}
+
+hs_status cell_residual_launch(hs_ctx* ctx, const double* q, const double* q_prev, double* rcell, int slot) {
+  int nb;
+  HS_TRY(cell_residual_partials(ctx, q, q_prev, rcell, &nb));
   HS_LAUNCH(ctx, sum_finish_kernel, 1, kBlock, ctx->red, nb, reinterpret_cast<double*>(ctx->stats + slot));
   return HS_OK;
 }
@@ -833,8 +864,9 @@ static hs_status filter_apply(hs_ctx* ctx, const double* in, double* out, int no
 static hs_status run_filter_device(hs_ctx* ctx, double* gamma, const double* q_prev, const hs_hybrid_params* hp,
                                    hs_step_info* info) {
   FiltCtl* ctl = reinterpret_cast<FiltCtl*>(ctx->small + kSmFilt);   // two slots
-  HS_TRY(cell_residual_launch(ctx, gamma, q_prev, ctx->rcell, kStatSum0));
-  HS_LAUNCH(ctx, filt_init_kernel, 1, 1, ctl, (const unsigned long long*)ctx->stats, 0);
+  int nbr;
+  HS_TRY(cell_residual_partials(ctx, gamma, q_prev, ctx->rcell, &nbr));
+  HS_LAUNCH(ctx, filt_init_kernel, 1, kBlock, ctl, (const double*)ctx->red, nbr, ctx->stats, 0);
   FiltSpec fs;
   fs.ctl = ctl;
   fs.state[0] = gamma;
@@ -1183,9 +1215,10 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const void* Phi,
   if (replay) HS_TRY(replay_filter(ctx, q_out, tape, inf));
   else HS_TRY(run_filter(ctx, q_out, q_prev, hp, inf, mode == HS_TAPE_RECORD ? tape : nullptr));
   if (eps_out) {
-    HS_TRY(max_abs_launch(ctx, q_out, ctx->n));
+    int nbq;
+    HS_TRY(max_abs_partials(ctx, q_out, ctx->n, &nbq));
     HS_LAUNCH(ctx, indicator_kernel, blocks_for(ctx->ncell), kBlock, ctx->ncell, ctx->nc, q_out, ctx->rho,
-              hp->floor_rel, (const unsigned long long*)ctx->stats, eps_out);
+              hp->floor_rel, (const double*)ctx->part, nbq, eps_out);
   }
   if (y_out) HIP_TRY(ctx, hipMemcpyAsync(y_out, sm + kSmY, m * 8, hipMemcpyDeviceToDevice, ctx->stream));
   if (mode == HS_TAPE_RECORD) {
@@ -1232,9 +1265,10 @@ hs_status hs_indicator_full(hs_ctx* ctx, const double* gamma, const void* Phi, c
   HS_LAUNCH(ctx, project_finish_kernel, 1, 256, ctx->red, nb, pad16(m), m, sm + kSmGp, 0, sm + kSmY0, sm + kSmY,
             sm + kSmYPrev, sm + kSmMisc, 1, (unsigned long long*)nullptr);
   HS_TRY(reconstruct(ctx, Phi, precision, m, psi, sm + kSmY0, nullptr, nullptr, nullptr, ctx->rho));
-  HS_TRY(max_abs_launch(ctx, gamma, ctx->n));
+  int nbq;
+  HS_TRY(max_abs_partials(ctx, gamma, ctx->n, &nbq));
   HS_LAUNCH(ctx, indicator_kernel, blocks_for(ctx->ncell), kBlock, ctx->ncell, ctx->nc, gamma, ctx->rho, floor_rel,
-            (const unsigned long long*)ctx->stats, eps);
+            (const double*)ctx->part, nbq, eps);
   if (y_out) HIP_TRY(ctx, hipMemcpyAsync(y_out, sm + kSmY0, m * 8, hipMemcpyDeviceToDevice, ctx->stream));
   return hs_sync(ctx);
 }

@@ -261,11 +261,14 @@ def adjoint_bench(name, seed):
     prob, q0 = W.make(wl, seed)
     cfg = AromConfig(w=wl.w, m=wl.m, z=wl.z, fraction=wl.frac, halo=wl.halo)
     K = wl.checkpoint or 10
-    traj = Trajectory(prob, cfg, wl.steps, checkpoint_every=K)
-    q = torch.from_numpy(q0).to(traj.ctx.device).requires_grad_(True)
-    qT = HybridTrajectory.apply(q, traj)
-    loss = 0.5 * torch.sum(qT * qT)
-    loss.backward()
+    # the second of two identical runs is timed: the first loads and warms
+    # every kernel of the taped and reverse paths
+    for _ in range(2):
+        traj = Trajectory(prob, cfg, wl.steps, checkpoint_every=K)
+        q = torch.from_numpy(q0).to(traj.ctx.device).requires_grad_(True)
+        qT = HybridTrajectory.apply(q, traj)
+        loss = 0.5 * torch.sum(qT * qT)
+        loss.backward()
     kinds = [k for k, _ in traj.decisions()]
     return {"workload": name, "nx": prob.nx, "ny": prob.ny, "steps": wl.steps, "checkpoint_every": K,
             "hybrid_steps": kinds.count("hybrid"),

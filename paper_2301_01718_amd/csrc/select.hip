@@ -611,8 +611,9 @@ struct Flags3 {
   int* bsum[3];  // nb + 1 entries each
 };
 
-__global__ void flag_count3_kernel(Flags3 fl) {
+__global__ void flag_count3_kernel(Flags3 fl, int* __restrict__ ticket) {
   __shared__ int lds[kBlock / kWave];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *ticket = 0;   // for scan_bsums3_kernel
   int a = 0, b = blockIdx.x;
   if (b >= fl.nb[0]) {
     b -= fl.nb[0];
@@ -657,19 +658,34 @@ __global__ void compact3_kernel(Flags3 fl, Lists3 out) {
 }
 
 // Workgroup a scans array a's block sums; the totals also go to totals[a],
-// and n_g (when ngd is given) to totals[3].
-__global__ void scan_bsums3_kernel(Flags3 fl, int* __restrict__ totals, const long long* __restrict__ ngd) {
+// and n_g (when ngd is given) to totals[3].  The last of the three
+// workgroups to finish (ticket at totals[4], cleared by flag_count3_kernel)
+// posts totals[0..3] to the host, so the sizes are read while the
+// compactions behind this kernel run.
+__global__ void scan_bsums3_kernel(Flags3 fl, int* __restrict__ totals, const long long* __restrict__ ngd,
+                                   PostSlot post) {
+  __shared__ int last;
   const int a = blockIdx.x;
   scan_bsums_block(fl.bsum[a], fl.nb[a]);
-  if (threadIdx.x == 0) totals[a] = fl.bsum[a][fl.nb[a]];
-  if (a == 0 && threadIdx.x == 0) totals[3] = ngd ? (int)*ngd : 0;
+  if (threadIdx.x == 0) {
+    totals[a] = fl.bsum[a][fl.nb[a]];
+    if (a == 0) totals[3] = ngd ? (int)*ngd : 0;
+    __threadfence();   // this workgroup's totals before its ticket
+    last = atomicAdd(&totals[4], 1) == (int)gridDim.x - 1;
+    if (last) __threadfence();   // the other workgroups' totals after their tickets
+  }
+  __syncthreads();
+  if (!last) return;
+  __shared__ uint32_t words[4];
+  if (threadIdx.x < 4) words[threadIdx.x] = (uint32_t)__hip_atomic_load(&totals[threadIdx.x], __ATOMIC_RELAXED,
+                                                                         __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  if (threadIdx.x < kWave) post_words(words, 4, post.dst, post.tagp, post.tag);
 }
 
-// One block of 256 threads: the state before the first digit (slot 1), n_g
-// to ngd, and a cleared first histogram buffer.  k < 0: the fraction rule,
-// n_g = min(-k, #{eps > 0}) with the count from the statistics slot.
-// Initial state of a selection of rank k (capped at #{eps > 0} by the first
-// digit pick, which also stores n_g).
+// One block of 256 threads: the state before the first digit (slot 1) of a
+// selection of rank k (capped at #{eps > 0} by the first digit pick, which
+// also stores n_g), and a cleared first histogram buffer.
 __global__ void init_state_kernel(SelectState* st2, long long k, unsigned int* __restrict__ hist3) {
 #pragma unroll
   for (int c = 0; c < kHistCopies; ++c) hist3[c * 256 + threadIdx.x] = 0u;
@@ -746,13 +762,14 @@ static hs_status finish_sets(hs_ctx* ctx, hs_samples* s, const long long* ngd = 
     fl.nb[a] = blocks_for(lens[a], kScanTile);
     fl.bsum[a] = s->scan3 + a * region;
   }
-  int* totals = s->scan3 + 3 * region;
-  HS_LAUNCH(ctx, flag_count3_kernel, fl.nb[0] + fl.nb[1] + fl.nb[2], kBlock, fl);
-  HS_LAUNCH(ctx, scan_bsums3_kernel, 3, kBlock, fl, totals, ngd);
+  int* totals = s->scan3 + 3 * region;   // 4 totals and the scan's ticket
+  HS_LAUNCH(ctx, flag_count3_kernel, fl.nb[0] + fl.nb[1] + fl.nb[2], kBlock, fl, totals + 4);
+  const PostSlot ps = post_slot(ctx);
+  HS_LAUNCH(ctx, scan_bsums3_kernel, 3, kBlock, fl, totals, ngd, ps);
   const Lists3 lists{{s->hat, s->tilde, s->tiles}, s->pos};
   HS_LAUNCH(ctx, compact3_kernel, fl.nb[0] + fl.nb[1] + fl.nb[2], kBlock, fl, lists);
   int cnt[4];
-  HS_TRY(readback(ctx, totals, sizeof cnt, cnt));
+  HS_TRY(await_post(ctx, ps, cnt, sizeof cnt));
   s->n_s = cnt[0];
   s->l = cnt[1];
   s->ntiles = cnt[2];

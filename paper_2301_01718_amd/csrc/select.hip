@@ -392,42 +392,43 @@ __global__ void __launch_bounds__(256) radix_pass_kernel(const double* __restric
 }
 
 // The last digit (pass 7's buffer), then gmask = key > K and emask = key == K
-// (candidates for the remaining ties); workgroup 0 stores the final state in
-// slot 0 for the tie pass.  256 threads, grid-stride.
+// (candidates for the remaining ties) on the workgroup's scan tile of
+// kScanTile cells, whose emask count goes to bsum[blockIdx.x] for the tie
+// scan; workgroup 0 stores the final state in slot 0 for the tie pass.
+// 256 threads, one workgroup per scan tile.
 __global__ void __launch_bounds__(256) radix_mark_kernel(const double* __restrict__ eps, int n,
                                                          SelectState* __restrict__ st2,
                                                          const unsigned int* __restrict__ hist3,
                                                          const long long* __restrict__ ngd,
-                                                         uint8_t* __restrict__ gmask, uint8_t* __restrict__ emask) {
+                                                         uint8_t* __restrict__ gmask, uint8_t* __restrict__ emask,
+                                                         int* __restrict__ bsum) {
   __shared__ int wsum[256 / kWave];
+  __shared__ int lds[256 / kWave];
   __shared__ SelectState sh;
   const SelectState s = radix_pick(hist3 + (7 % 3) * kHistWords, 0, st2[7 % 2], wsum, &sh);
   if (blockIdx.x == 0 && threadIdx.x == 0) st2[0] = s;
   const unsigned long long K = s.prefix;
   const bool any = *ngd > 0;   // n_g = 0: nothing is marked
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-    const double e = eps[i];
-    const unsigned long long key = e > 0.0 ? dbits(e) : 0ull;
-    gmask[i] = any && (e > 0.0) && key > K;
-    emask[i] = any && (e > 0.0) && key == K;
-  }
-}
-
-// ------------------------------------------------------------- block scan
-// Exclusive scan of per-block totals, then per-element ranks.
-__global__ void flag_count_kernel(const uint8_t* __restrict__ f, int n, int* __restrict__ bsum) {
-  __shared__ int lds[kBlock / kWave];
   const int base = blockIdx.x * kScanTile;
   int c = 0;
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
-    const int i = base + r * kBlock + threadIdx.x;
-    if (i < n) c += f[i] != 0;
+    const int i = base + r * 256 + threadIdx.x;
+    if (i < n) {
+      const double e = eps[i];
+      const unsigned long long key = e > 0.0 ? dbits(e) : 0ull;
+      const bool tie = any && (e > 0.0) && key == K;
+      gmask[i] = any && (e > 0.0) && key > K;
+      emask[i] = tie;
+      c += tie;
+    }
   }
   c = block_sum_int(c, lds);
   if (threadIdx.x == 0) bsum[blockIdx.x] = c;
 }
 
+// ------------------------------------------------------------- block scan
+// Exclusive scan of per-block totals, then per-element ranks.
 // Single block: exclusive scan of nb block sums in place; total to bsum[nb].
 __device__ inline void scan_bsums_block(int* __restrict__ bsum, int nb) {
   __shared__ int carry;
@@ -699,13 +700,6 @@ __global__ void init_state_kernel(SelectState* st2, long long k, unsigned int* _
 // The select state lives after the block sums in the scan buffer, 8-byte aligned.
 static size_t state_offset(int n) { return ((size_t)n / kScanTile + 32) & ~(size_t)1; }
 
-static hs_status scan_blocks(hs_ctx* ctx, const uint8_t* flags, int n, int* bsum) {
-  const int nb = blocks_for(n, kScanTile);
-  HS_LAUNCH(ctx, flag_count_kernel, nb, kBlock, flags, n, bsum);
-  HS_LAUNCH(ctx, scan_bsums_kernel, 1, kBlock, bsum, nb);
-  return HS_OK;
-}
-
 // n_g of the RRE rule (exact fixed-point sums), given #{eps > 0} and max eps.
 static hs_status rre_count(hs_ctx* ctx, const double* eps, int n, double delta, long long npos, double emx,
                            long long* ng) {
@@ -862,8 +856,11 @@ hs_status sample_select(hs_ctx* ctx, const double* eps, const hs_sample_params* 
   const int rb = blocks_for(n, 256, kRadixBlocks);
   HS_LAUNCH(ctx, init_state_kernel, 1, 256, state, k, hist);
   for (int p = 0; p < 8; ++p) HS_LAUNCH(ctx, radix_pass_kernel, rb, 256, eps, n, state, p, hist, ngd);
-  HS_LAUNCH(ctx, radix_mark_kernel, rb, 256, eps, n, state, hist, (const long long*)ngd, s->gmask, s->dtmp);
-  HS_TRY(scan_blocks(ctx, s->dtmp, n, s->scan));
+  // the mark pass also counts each scan tile's tie candidates
+  const int nbs = blocks_for(n, kScanTile);
+  HS_LAUNCH(ctx, radix_mark_kernel, nbs, 256, eps, n, state, hist, (const long long*)ngd, s->gmask, s->dtmp,
+            s->scan);
+  HS_LAUNCH(ctx, scan_bsums_kernel, 1, kBlock, s->scan, nbs);
   HS_LAUNCH(ctx, tie_keep_kernel, blocks_for(n, kScanTile), kBlock, s->dtmp, n, s->scan, state, s->gmask);
   // hat-S = dilate(G): x, then y
   const uint8_t* src = s->gmask;

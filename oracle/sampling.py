@@ -19,12 +19,13 @@ Readings
   rank is not reproducible.  The floor is on the per-cell error norm,
   ``floor_rel * max(1, ||gamma||_inf)``; the default is 1e-11.
 * Fixed-fraction mode (used by the workloads): n_g = min(ceil(f N_c),
-  #{eps > 0}).  RRE mode: the smallest n_g with RRE(n_g) >= delta, the sums
-  taken exactly: each error is first encoded in 64-bit fixed point relative
-  to the largest one, q_i = floor(eps_i 2^(63 - e_max)) with 2^e_max <=
-  max eps < 2^(e_max + 1) (a relative resolution of 2^-64; smaller values
-  count as 0), and the comparison sum_top q >= delta * sum q is made in
-  integers.  The decision is then independent of any summation order.
+  #{eps > 0}).  RRE mode: the smallest n_g with RRE(n_g) >= delta, with the
+  sums of eq. rre taken exactly: every error is a dyadic rational
+  M_i 2^(E_i), so all of them are written as integers over the smallest
+  exponent present and the ratio test sum_top >= delta * sum is made in
+  exact integer arithmetic (delta is itself a dyadic rational).  The count
+  is then the paper's definition with no rounding and no dependence on a
+  summation order.
 * Ties in the ordering go to the lower cell index.
 * No ODEIM points: the fit rows are the sampled set itself (the
   oversampling limit).  The sampled set is G dilated by a Chebyshev radius
@@ -67,20 +68,18 @@ def error_order(eps):
     return np.argsort(-eps, kind="stable")
 
 
-def fixed_point_errors(eps):
-    """q_i = floor(eps_i * 2^(63 - e_max)) as exact integers, e_max the
-    binary exponent of the largest error (so the largest maps to [2^63, 2^64))."""
-    emax = math.frexp(float(np.max(eps)))[1] - 1
-    out = []
-    for e in eps.tolist():
-        if e <= 0.0:
-            out.append(0)
+def exact_dyadic(values):
+    """Integers k_i and one exponent e with values_i = k_i 2^e exactly
+    (non-negative doubles; e is the smallest binary exponent present)."""
+    parts = []
+    for v in values:
+        if v <= 0.0:
+            parts.append((0, 0))
             continue
-        m, x = math.frexp(e)                 # e = m 2^x, 0.5 <= m < 1
-        M = int(m * (1 << 53))               # exact 53-bit integer: e = M 2^(x - 53)
-        sh = x - 53 + 63 - emax
-        out.append(M << sh if sh >= 0 else M >> -sh)
-    return out
+        m, x = math.frexp(v)                 # v = m 2^x, 0.5 <= m < 1
+        parts.append((int(m * (1 << 53)), x - 53))   # exact: v = M 2^(x - 53)
+    e = min((x for M, x in parts if M > 0), default=0)
+    return [M << (x - e) for M, x in parts], e
 
 
 def count_g(eps, rule, fraction=0.0, delta=0.0):
@@ -90,16 +89,18 @@ def count_g(eps, rule, fraction=0.0, delta=0.0):
         return min(int(math.ceil(fraction * ncell)), npos)
     if npos == 0:
         return 0
-    q = fixed_point_errors(eps)
-    total = sum(q)
+    # eq. rre: RRE(n) = sum_{top n} eps / sum eps; smallest n with RRE(n) >= delta
+    k, _ = exact_dyadic(eps.tolist())
+    total = sum(k)
     dm, de = math.frexp(float(delta))
-    dnum = int(dm * (1 << 53))               # delta = dnum 2^(de - 53)
-    dsh = 53 - de                            # S >= delta T  <=>  S 2^dsh >= dnum T
-    rhs = dnum * total
+    dnum, dexp = int(dm * (1 << 53)), de - 53    # delta = dnum 2^dexp exactly
+    # S >= delta T  <=>  S 2^(-dexp) >= dnum T  (dexp < 0)  or  S >= dnum T 2^dexp
+    rhs = dnum * total if dexp <= 0 else (dnum * total) << dexp
+    sh = -dexp if dexp <= 0 else 0
     s = 0
     for g, i in enumerate(error_order(eps).tolist(), start=1):
-        s += q[i]
-        if (s << dsh if dsh >= 0 else s >> -dsh) >= rhs:
+        s += k[i]
+        if (s << sh) >= rhs:
             return min(g, npos)
     return npos
 

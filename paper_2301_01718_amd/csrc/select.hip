@@ -45,12 +45,16 @@ __global__ void count_positive_kernel(const double* __restrict__ eps, int n, dou
 }
 
 // --------------------------------------------------------------- RRE rule
-// eq. rre with exact sums: every error is encoded in 64-bit fixed point
-// relative to the largest, q = floor(eps 2^(63 - emax)) (2^emax <= max eps <
+// eq. rre in integers: every error is encoded in 64-bit fixed point relative
+// to the largest, q = floor(eps 2^(63 - emax)) (2^emax <= max eps <
 // 2^(emax+1)), and all sums of q are exact integers (32-bit halves summed in
 // 64-bit integers, integer atomics), so the decision RRE(n_g) >= delta does
 // not depend on any summation order.  Comparisons S >= delta T are made as
-// S 2^dsh >= dnum T with delta = dnum 2^-dsh, in 256-bit integers.
+// S 2^dsh >= dnum T with delta = dnum 2^-dsh, in 256-bit integers.  The
+// encoding drops less than one unit of 2^(emax - 63) per error, so n_g is the
+// one eq. rre gives with exact sums unless the exact ratio at the crossing
+// lies within (n_g + N) 2^(emax - 63) / sum(eps) of delta; delta >= 1 is
+// decided exactly (every positive error).
 struct U256 {
   unsigned long long w[4];
 };
@@ -704,7 +708,8 @@ static size_t state_offset(int n) { return ((size_t)n / kScanTile + 32) & ~(size
 static hs_status rre_count(hs_ctx* ctx, const double* eps, int n, double delta, long long npos, double emx,
                            long long* ng) {
   if (npos == 0) { *ng = 0; return HS_OK; }
-  if (delta > 1.0) { *ng = npos; return HS_OK; }           // RRE <= 1 never reaches delta
+  // RRE(n) reaches 1 only with every positive error in the sum, and never exceeds it
+  if (delta >= 1.0) { *ng = npos; return HS_OK; }
   if (!(delta > std::ldexp(1.0, -64))) { *ng = 1; return HS_OK; }   // the largest q alone exceeds delta T
   int de;
   const double dm = std::frexp(delta, &de);                 // delta = dm 2^de, 0.5 <= dm < 1

@@ -64,3 +64,33 @@ def test_device_filter_loop_equals_host_loop(name):
         err = rel(host(dev_out), ref["gamma"])
         print("  rel to oracle", err, flush=True)
         assert err < 1e-12
+
+
+def _oracle_case(which):
+    import test_oracle_method as tom
+    if which == "oscillation":
+        prob, gamma, q_prev = tom.filter_case_oscillation()
+    else:
+        prob, gamma, q_prev, _, _ = tom.filter_case_mode()
+    return prob, gamma, q_prev
+
+
+@pytest.mark.parametrize("which,eps_f,jfmax", [("oscillation", 1e-2, 10), ("mode", 1e-2, 10), ("mode", 1e-2, 3),
+                                               ("mode", 0.05, 10), ("mode", 1e-3, 10)])
+def test_filter_loop_closed_forms(which, eps_f, jfmax):
+    """The closed-form cases that pin the oracle's loop control (strict gate,
+    empty-set stop, relative l1 stop, pass bound): the library's filter gives
+    the oracle's pass log (count and kept cells) and its state bit for bit."""
+    need_gpu()
+    import paper_2301_01718_amd as hs
+    print_case("filter closed form", which, eps_f, jfmax)
+    prob, gamma, q_prev = _oracle_case(which)
+    log = []
+    ref = hybrid.spatial_filter(prob, gamma, q_prev, hybrid.HybridParams(eps_f=eps_f, jfmax=jfmax), log)
+    ctx = ctx_for(prob, m_max=8, w_max=8)
+    out, info = ctx.filter(dev(gamma), dev(q_prev), hs.hybrid_params(eps_f=eps_f, jfmax=jfmax))
+    print("  oracle passes", len(log), "kept", sum(k for _, _, k in log), "gpu", info["filter_passes"],
+          info["filter_kept"], flush=True)
+    assert info["filter_passes"] == len(log)
+    assert info["filter_kept"] == sum(k for _, _, k in log)
+    assert np.array_equal(host(out), ref)

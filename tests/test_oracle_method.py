@@ -123,11 +123,92 @@ def test_rre_rule_exact_on_the_fixed_point_grid():
             assert sampling.count_g(eps, sampling.RULE_RRE, delta=delta) == want, (trial, delta)
 
 
-def test_rre_fixed_point_encoding():
-    eps = np.array([0.0, 3.0, 1.5, 2.0 ** -70, 1.0])
-    q = sampling.fixed_point_errors(eps)
-    # largest 3 = 1.5 * 2^1 -> 3 * 2^62; others scale alike; 2^-70 * 2^62 < 1 -> 0
-    assert q == [0, 3 << 62, 3 << 61, 0, 1 << 62]
+def _rre_brute(eps, delta):
+    """eq. rre written with Fraction sums (each double converted exactly)."""
+    from fractions import Fraction
+    order = sorted(range(eps.size), key=lambda i: (-eps[i], i))
+    fr = [Fraction(float(v)) for v in eps]
+    tot = sum(fr, Fraction(0))
+    d = Fraction(float(delta))
+    acc = Fraction(0)
+    npos = int(np.count_nonzero(eps > 0))
+    for g, i in enumerate(order, start=1):
+        acc += fr[i]
+        if acc >= d * tot:
+            return min(g, npos)
+    return npos
+
+
+def test_rre_exact_sums_match_fraction_brute_force():
+    """The oracle's integer form of eq. rre equals the definition taken with
+    exact rationals, on errors spanning many binades (down to subnormals)."""
+    rng = np.random.default_rng(11)
+    for trial in range(30):
+        n = int(rng.integers(1, 60))
+        eps = rng.random(n) * 2.0 ** rng.integers(-1070, 10, n).astype(float)
+        eps[rng.random(n) < 0.2] = 0.0
+        if trial % 3 == 0:
+            eps[: n // 2] = eps[0]                      # ties
+        if not np.any(eps > 0):
+            continue
+        for delta in (1e-12, 0.3, 0.5, 0.9, 0.999999, 1.0, 1.5, float(rng.random())):
+            assert sampling.count_g(eps, sampling.RULE_RRE, delta=delta) == _rre_brute(eps, delta), (trial, delta)
+
+
+def test_exact_dyadic_decomposition():
+    from fractions import Fraction
+    vals = [0.0, 3.0, 1.5, 2.0 ** -70, 1.0, 5e-324, 0.1]
+    k, e = sampling.exact_dyadic(vals)
+    for v, ki in zip(vals, k):
+        assert Fraction(ki) * Fraction(2) ** e == Fraction(v)
+
+
+def _fixed_point_count(eps, delta):
+    """The library's 64-bit encoding of eq. rre (a model of its documented
+    arithmetic, for comparison with the exact rule): q = floor(eps 2^(63 - e_max))
+    with 2^e_max <= max eps < 2^(e_max + 1); S >= delta T decided on q;
+    delta >= 1 gives every positive cell."""
+    npos = int(np.count_nonzero(eps > 0))
+    if npos == 0:
+        return 0
+    if delta >= 1.0:
+        return npos
+    emax = math.frexp(float(np.max(eps)))[1] - 1
+    q = [int(math.floor(math.ldexp(float(v), 63 - emax))) if v > 0 else 0 for v in eps]
+    tot = sum(q)
+    from fractions import Fraction
+    d = Fraction(float(delta))
+    acc = 0
+    for g, i in enumerate(sampling.error_order(eps).tolist(), start=1):
+        acc += q[i]
+        if acc >= d * tot:
+            return min(g, npos)
+    return npos
+
+
+def test_fixed_point_encoding_agrees_with_exact_rule_off_the_margin():
+    """The 64-bit encoding truncates each error by less than one unit of
+    2^(e_max - 63), so its decision equals the exact one unless the exact
+    ratio at the crossing lies within (n + N) 2^(e_max - 63) / sum(eps) of
+    delta.  Indicator-like inputs never come that close; a constructed one
+    does, and the difference is then the named sub-2^-64 effect."""
+    rng = np.random.default_rng(5)
+    for trial in range(40):
+        n = int(rng.integers(20, 400))
+        eps = (rng.random(n) ** 6) * 10.0 ** rng.uniform(-20, 0)
+        eps[rng.random(n) < 0.1] = 0.0
+        for delta in (0.3, 0.8, 0.9, 0.99, 1.0):
+            assert _fixed_point_count(eps, delta) == sampling.count_g(eps, sampling.RULE_RRE, delta=delta)
+    # one large error and one 2^-70 times smaller: exact RRE(1) = 1 / (1 + 2^-70) < delta
+    eps = np.array([1.0, 2.0 ** -70])
+    delta = 1.0 - 2.0 ** -53
+    assert sampling.count_g(eps, sampling.RULE_RRE, delta=delta) == 1      # 1/(1+2^-70) > 1 - 2^-53
+    eps = np.array([1.0] + [2.0 ** -60] * 256)                            # tail 2^-52 of the total
+    assert sampling.count_g(eps, sampling.RULE_RRE, delta=delta) > 1
+    assert _fixed_point_count(eps, delta) > 1                                # 2^-60 is still encoded
+    eps = np.array([1.0] + [2.0 ** -66] * 16384)                          # tail 2^-52, each below 2^-64
+    assert sampling.count_g(eps, sampling.RULE_RRE, delta=delta) > 1
+    assert _fixed_point_count(eps, delta) == 1                               # the named difference
 
 
 # ---------------------------------------------------------------- indicator
@@ -280,6 +361,82 @@ def test_filter_is_identity_on_converged_hdm_state():
     q1, _ = fv.hdm_step(prob, q0)
     out = hybrid.spatial_filter(prob, q1, q0, hybrid.HybridParams())
     assert np.array_equal(out, q1)
+
+
+def filter_case_oscillation():
+    """Periodic 2D Burgers, q_prev = 1 and gamma = 1 + (-1)^i / 4: the
+    order-2 Shapiro filter S_1 maps the 2 dx mode to 0 and keeps constants,
+    exactly in binary arithmetic for these values, and R(1; 1) = 0."""
+    prob, _ = W.make(W.WORKLOADS["burgers2d_1024"].resized(32, 4), 0)
+    q_prev = np.ones(prob.n)
+    i = np.arange(prob.ncell) % prob.nx
+    gamma = 1.0 + 0.25 * np.where(i % 2 == 0, 1.0, -1.0)
+    return prob, gamma, q_prev
+
+
+def filter_case_mode(amp=1e-4, k=2):
+    """Periodic 2D Burgers with a step so small that R(q; 1) = q - 1 exactly,
+    and gamma = 1 + amp cos(2 pi k (x_i + 1/2) / nx) (no cell on a node of the
+    mode): every pass of S_n scales the mode by g_n = 1 - sin(pi k / nx)^(2n)
+    (its transfer function), so every cell's residual drops by that factor
+    and the relative l1 decrease of a pass is sin(pi k / nx)^(2n)."""
+    import dataclasses
+    prob, _ = W.make(W.WORKLOADS["burgers2d_1024"].resized(32, 4), 0)
+    prob = dataclasses.replace(prob, dt=1e-300)
+    q_prev = np.ones(prob.n)
+    i = np.arange(prob.ncell) % prob.nx
+    p = amp * np.cos(2.0 * np.pi * k * (i + 0.5) / prob.nx)
+    return prob, 1.0 + p, q_prev, p, math.sin(math.pi * k / prob.nx) ** 2
+
+
+def test_filter_loop_strict_gate_and_empty_stop():
+    """Pass 1 of order 2 removes the oscillation in every cell; every later
+    pass finds no strict decrease and ends its order at once (a non-strict
+    gate would keep cells with equal zero residuals and run on)."""
+    prob, gamma, q_prev = filter_case_oscillation()
+    log = []
+    out = hybrid.spatial_filter(prob, gamma, q_prev, hybrid.HybridParams(), log)
+    assert log == [(1, 1, prob.ncell), (1, 2, 0), (2, 1, 0), (3, 1, 0)]
+    assert np.array_equal(out, q_prev)
+
+
+def test_filter_loop_relative_decrease_stop_and_pass_bound():
+    """Order 2: the relative decrease sin^2(pi/16) = 0.038 stays above
+    eps_f = 1e-2, so the order runs to j_f,max = 10 passes; orders 4 and 6
+    decrease by sin^4 = 1.4e-3 and sin^6 = 5.5e-5 < eps_f and stop after one
+    pass.  The amplitude makes the absolute l1 decrease (3e-4) smaller than
+    eps_f, so an absolute reading of the stop test would end order 2 after
+    its first pass.  The final state is 1 + g_1^10 g_2 g_3 p (one missing or
+    extra pass would move it by 4e-6)."""
+    prob, gamma, q_prev, p, s2 = filter_case_mode()
+    assert s2 > 1e-2 and s2 * s2 < 1e-2
+    assert np.sum(np.abs(p)) * s2 < 1e-2
+    log = []
+    out = hybrid.spatial_filter(prob, gamma, q_prev, hybrid.HybridParams(), log)
+    N = prob.ncell
+    assert log == [(1, j, N) for j in range(1, 11)] + [(2, 1, N), (3, 1, N)]
+    gain = (1 - s2) ** 10 * (1 - s2 ** 2) * (1 - s2 ** 3)
+    assert np.max(np.abs((out - 1.0) - gain * p)) <= 1e-14   # rounding of states near 1, 13 passes
+    # a smaller bound ends order 2 earlier with the same per-pass factor
+    log = []
+    out = hybrid.spatial_filter(prob, gamma, q_prev, hybrid.HybridParams(jfmax=3), log)
+    assert log == [(1, 1, N), (1, 2, N), (1, 3, N), (2, 1, N), (3, 1, N)]
+    gain = (1 - s2) ** 3 * (1 - s2 ** 2) * (1 - s2 ** 3)
+    assert np.max(np.abs((out - 1.0) - gain * p)) <= 1e-14   # rounding of states near 1, 13 passes
+
+
+def test_filter_loop_carries_the_merged_residual_between_passes():
+    """With eps_f between the order-2 and order-4 decreases only order 2
+    stops early: an eps_f above 0.038 ends it after pass 1 (the decrease is
+    measured against the merged state's residual, the next pass's r)."""
+    prob, gamma, q_prev, p, s2 = filter_case_mode()
+    N = prob.ncell
+    log = []
+    hybrid.spatial_filter(prob, gamma, q_prev, hybrid.HybridParams(eps_f=0.05), log)
+    assert log == [(1, 1, N), (2, 1, N), (3, 1, N)]
+    log = []
+    hybrid.spatial_filter(prob, gamma, q_prev, hybrid.HybridParams(eps_f=1e-3), log)
+    assert log == [(1, j, N) for j in range(1, 11)] + [(2, j, N) for j in range(1, 11)] + [(3, 1, N)]
 
 
 # ---------------------------------------------------------------- hybrid step

@@ -74,9 +74,9 @@ extern "C" {
  * the basis (fit gathers and projections, ring update, reconstruction,
  * indicator) moves half the bytes, while all arithmetic stays FP64 (products
  * of the float entries are formed and accumulated in double, and the fit is
- * refined in FP64).  The snapshot Gram of basis_update stays FP64 in both
- * modes: the truncation sigma_i > tau_pod sigma_0 resolves eigenvalues down
- * to tau_pod^2 = 1e-8 of the largest, below FP32 resolution. */
+ * refined in FP64).  basis_update works in FP64 in both modes: its cut
+ * sigma_i > tau_pod sigma_0 (tau_pod = 1e-8) needs singular values resolved
+ * to far below FP32 resolution. */
 #define HS_FP64        0
 #define HS_MIXED_FP32  1
 
@@ -189,6 +189,11 @@ hs_status hs_indicator_full(hs_ctx* ctx, const double* gamma, const void* Phi /*
  * m_eff = #{i < m : sigma_i > tau_pod * sigma_0}; columns beyond m_eff are
  * left untouched.  sigma_out gets all w singular values (descending).
  * Sign: each right singular vector has its largest-magnitude entry positive.
+ * The singular values come from a triangular factor of X (two window passes:
+ * a Gram-based preconditioner, then the Gram of the preconditioned window),
+ * accurate to about eps sigma_0 absolutely, so any tau_pod >= 1e-12 cuts at
+ * a reproducible rank; Phi = X V_m diag(1/sigma_m) (third pass) spans the
+ * POD subspace to rounding and is orthonormal to about eps sigma_0 / sigma_i.
  * precision: HS_FP64 (Phi_out is double*) or HS_MIXED_FP32 (Phi_out is
  * float*: the FP32 master copy, formed in FP64 and rounded once). */
 hs_status basis_update(hs_ctx* ctx, const double* const* snaps /* host */, int32_t nsnap, int32_t w,
@@ -225,8 +230,10 @@ typedef struct hs_hybrid_params {
   int32_t filter_orders[4]; /* n of S_n = I - (-delta^2/4)^n: 1, 2, 3 = orders 2, 4, 6 */
   double  eps_f;            /* filter stop tolerance on the relative l1 decrease (paper: 1e-2) */
   int32_t jfmax;            /* max passes per filter order (paper: 10) */
-  double  rcond_fit;        /* pseudo-inverse cutoff relative to sigma_max (1e-6) */
-  double  floor_rel;        /* indicator floor (1e-11) */
+  double  rcond_fit;        /* pseudo-inverse cutoff relative to sigma_max (1e-8); the fit
+                               factorises the gathered Gram, so the cut is never
+                               below sqrt(64 eps) = 1.2e-7 (kappa is reported) */
+  double  floor_rel;        /* indicator floor (1e-14) */
   int32_t precision;        /* HS_FP64 (Phi double) or HS_MIXED_FP32 (Phi float) */
 } hs_hybrid_params;
 
@@ -315,6 +322,7 @@ hs_status hs_set_option(hs_ctx* ctx, int32_t option, int64_t value);
 #define HS_PROF_CELLRES     6   /* cell residual norms (filter) */
 #define HS_PROF_FILTER      7   /* fused filter pass: S_y S_x, gate, merged residual norms */
 #define HS_PROF_RESIDUAL    8   /* hs_residual: R(q; q_prev) on the full mesh */
+#define HS_PROF_BASIS_PGRAM 9   /* second window pass of basis_update: Gram of the preconditioned window */
 /* Start timing every launch of one kernel class (HS_PROF_NONE stops).  Each
  * launch is bracketed by two HIP events recorded on the context's stream, and
  * the algorithmic bytes of that launch (the minimum reads and writes the

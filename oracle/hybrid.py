@@ -21,7 +21,9 @@ Readings
 --------
 * The fit rows are the sampled set (no ODEIM points).
 * The pseudo-inverse drops singular values of the gathered basis below
-  rcond_fit times the largest (rcond_fit = 1e-6 by default).
+  rcond_fit times the largest (rcond_fit = 1e-8 by default, the square root
+  of the double precision unit: below it a least-squares solution has no
+  correct digits).
 * The stopping test compares consecutive coordinates, so J >= 2.
 * The Newton guess on the sampled set is the previous snapshot in the first
   subiteration and the previous subiteration's solution afterwards.
@@ -51,7 +53,7 @@ class HybridParams:
     filter_orders: tuple = (1, 2, 3)      # n of S_n: filter orders 2, 4, 6
     eps_f: float = 1e-2
     jfmax: int = 10
-    rcond_fit: float = 1e-6
+    rcond_fit: float = 1e-8
     floor_rel: float = DEFAULT_FLOOR
 
 
@@ -128,8 +130,9 @@ def fit(Phi_rows, d, rcond):
 def hybrid_step(prob: Problem, q_prev, Phi, psi, hat, tilde, params: HybridParams = None, norms=None):
     """One hybrid snapshot gamma_k from gamma_{k-1} = q_prev.
 
-    Returns dict(gamma, y, J, eps, rho, newton, us, masks) where rho = psi + Phi y
-    is the reconstruction, eps the indicator of the filtered snapshot, us the
+    Returns dict(gamma, y, J, eps, rho, dy, newton, us, masks) where rho = psi + Phi y
+    is the reconstruction, eps the indicator of the filtered snapshot, dy the
+    norms ||y_j - y_{j-1}|| of the stopping test (j >= 2), us the
     state after each subiteration's Newton solve and masks the applied filter
     passes (the decisions the adjoint keeps frozen)."""
     params = params or HybridParams()
@@ -140,6 +143,7 @@ def hybrid_step(prob: Problem, q_prev, Phi, psi, hat, tilde, params: HybridParam
     y_old = None
     newton = []
     us = []
+    dy = []
     J = 0
     for j in range(1, params.jmax + 1):
         u, its = fv.partial_hdm_solve(prob, u, q_prev, hat)
@@ -148,8 +152,10 @@ def hybrid_step(prob: Problem, q_prev, Phi, psi, hat, tilde, params: HybridParam
         y = fit(Phi_hat, u[hd] - psi[hd], params.rcond_fit)
         u[td] = psi[td] + Phi[td] @ y
         J = j
-        if y_old is not None and np.linalg.norm(y - y_old) < params.eps_y:
-            break
+        if y_old is not None:
+            dy.append(float(np.linalg.norm(y - y_old)))
+            if dy[-1] < params.eps_y:
+                break
         y_old = y
     rho = psi + Phi @ y
     gamma = rho.copy()
@@ -157,5 +163,5 @@ def hybrid_step(prob: Problem, q_prev, Phi, psi, hat, tilde, params: HybridParam
     flog, masks = [], []
     gamma = spatial_filter(prob, gamma, q_prev, params, flog, masks, norms)
     eps = indicator(prob, gamma, rho, params.floor_rel)
-    return {"gamma": gamma, "y": y, "J": J, "eps": eps, "rho": rho,
+    return {"gamma": gamma, "y": y, "J": J, "eps": eps, "rho": rho, "dy": dy,
             "newton": newton, "filter_log": flog, "us": us, "masks": masks}

@@ -17,7 +17,8 @@ Readings
 * Values below a floor are flushed to zero before ordering: a cell whose
   reconstruction error is at rounding level carries no information and its
   rank is not reproducible.  The floor is on the per-cell error norm,
-  ``floor_rel * max(1, ||gamma||_inf)``; the default is 1e-11.
+  ``floor_rel * max(1, ||gamma||_inf)``; the default is 1e-14 (a few ulps
+  of the state).
 * Fixed-fraction mode (used by the workloads): n_g = min(ceil(f N_c),
   #{eps > 0}).  RRE mode: the smallest n_g with RRE(n_g) >= delta, with the
   sums of eq. rre taken exactly: every error is a dyadic rational
@@ -42,7 +43,7 @@ from workloads import BC_PERIODIC, BURGERS_1D, Problem
 
 RULE_FRACTION = 0
 RULE_RRE = 1
-DEFAULT_FLOOR = 1e-11
+DEFAULT_FLOOR = 1e-14
 
 
 def indicator(prob: Problem, gamma, rho, floor_rel=DEFAULT_FLOOR):

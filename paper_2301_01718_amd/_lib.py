@@ -66,7 +66,7 @@ class HybridParams(ctypes.Structure):
 
 
 def hybrid_params(eps_y=1e-4, jmax=10, filter_orders=(1, 2, 3), eps_f=1e-2, jfmax=10,
-                  rcond_fit=1e-6, floor_rel=1e-11, precision=FP64) -> HybridParams:
+                  rcond_fit=1e-8, floor_rel=1e-14, precision=FP64) -> HybridParams:
     hp = HybridParams()
     hp.eps_y, hp.jmax, hp.eps_f, hp.jfmax = eps_y, jmax, eps_f, jfmax
     hp.rcond_fit, hp.floor_rel, hp.precision = rcond_fit, floor_rel, precision
@@ -295,7 +295,7 @@ class Context:
             raise ValueError(f"basis must be a contiguous tensor of at least {m} x {self.n} entries on {self.device}")
         return basis_precision(Phi)
 
-    def indicator_full(self, gamma, Phi, psi, m, floor_rel=1e-11, eps=None, y=None):
+    def indicator_full(self, gamma, Phi, psi, m, floor_rel=1e-14, eps=None, y=None):
         prec = self._basis(Phi, m)
         eps = self.empty(self.ncell) if eps is None else self._in(eps, self.ncell)
         y = self.empty(m) if y is None else y
@@ -316,7 +316,7 @@ class Context:
             return snaps.arr, snaps.count
         return (P * len(snaps))(*[P(self._in(s).data_ptr()) for s in snaps]), len(snaps)
 
-    def basis_update(self, snaps, w, m, Phi_out, psi_out, sigma_out, tau_pod=1e-4):
+    def basis_update(self, snaps, w, m, Phi_out, psi_out, sigma_out, tau_pod=1e-8):
         """Phi_out float64: FP64 basis; float32: the FP32 master copy (HS_MIXED_FP32)."""
         precision = self._basis(Phi_out, m)
         arr, count = self._snap_array(snaps)
@@ -325,7 +325,7 @@ class Context:
                                        _ptr(self._in(psi_out)), _ptr(sigma_out), ctypes.byref(me)))
         return me.value
 
-    def basis_update_async(self, snaps, w, m, Phi_out, psi_out, sigma_out, tau_pod=1e-4):
+    def basis_update_async(self, snaps, w, m, Phi_out, psi_out, sigma_out, tau_pod=1e-8):
         """Enqueue the update on the context's own stream; finish with basis_update_finish."""
         precision = self._basis(Phi_out, m)
         arr, count = self._snap_array(snaps)

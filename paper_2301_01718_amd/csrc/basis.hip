@@ -1,14 +1,19 @@
 // POD basis update (A9): reference state and POD_m of the snapshot window
 // (eq. mean, eq. pod; the basis-update branch of Alg. 1).
 //
-// One pass over the window forms, row by row, both window means (the
+// The first pass over the window forms, row by row, both window means (the
 // centring state psi_k over the first w snapshots and psi_{k+1} over the last
 // w), the centred row of X = [gamma_j - psi_k] and accumulates the Gram
-// matrix X^T X on FP64 MFMA.  A pivoted Cholesky reduction to the numerical
-// rank and a Jacobi eigensolver on the reduced matrix give
-// X^T X = V diag(sigma^2) V^T; a second pass forms Phi = X V_m diag(1/sigma_m),
-// the left singular vectors, again on MFMA.  The traffic is two reads of the
-// window and one write of Phi (the method-of-snapshots minimum).
+// matrix X^T X on FP64 MFMA.  That Gram only serves as a preconditioner: its
+// eigenvalues carry about eps sigma_0^2 of absolute error, so singular values
+// below about 1e-8 sigma_0 (the POD cut) have no digits in it.  A shifted
+// pivoted Cholesky factor C1 of it is inverted, and the second pass forms the
+// Gram of X C1^-1 from the data, whose truncated pivoted Cholesky factor R2
+// gives X = Q R, R = R2 C1, with R accurate to the rounding of X itself
+// (X not squared).  One-sided Jacobi on R^T gives the right singular vectors
+// V and sigma; the third pass forms Phi = X V_m diag(1/sigma_m), the left
+// singular vectors, again on MFMA.  Traffic: three reads of the window and
+// one write of Phi.
 // Kernels using the window staging must run with 256 threads (four waves).
 #include "dense.hpp"
 
@@ -67,11 +72,35 @@ __device__ inline void lane_snaps_load(LaneSnaps<PER>& L, int nsnap, long long n
   for (int i = 0; i < PER; ++i) L.v[i] = (ok && g + 4 * i < nsnap) ? L.v[i] : 0.0;
 }
 
-// Sum over the four lane groups of a row, in the fixed order
-// ((g0 + g1) + (g2 + g3)), identical in all four groups.
-__device__ inline double group_sum(double x) {
-  const double t = x + __shfl_xor(x, 16, kWave);
-  return t + __shfl_xor(t, 32, kWave);
+// Window means with the sum correctly rounded (reproducible to the bit by
+// any implementation that rounds the sum correctly, whatever its order):
+// each lane keeps its values' sum as an unevaluated pair hi + lo with Knuth's
+// error-free TwoSum, the four lane groups of a row combine their pairs, and
+// hi + lo is rounded once.  The pair is exact as long as the accumulated low
+// parts add without rounding (values of a row within a few binades of each
+// other); otherwise it differs from the exact sum by about eps^2 of it, which
+// changes the rounded result only when the exact sum lies that close to a
+// rounding boundary.
+__device__ inline void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Pair sum over the four lane groups of a row.  Each combination is
+// symmetric in its two operands (the rounded sum and its exact error do not
+// depend on the order, and lo_a + lo_b == lo_b + lo_a), so all four groups
+// hold the same bits.
+__device__ inline double group_sum_exact(double hi, double lo) {
+#pragma unroll
+  for (int o = 16; o <= 32; o *= 2) {
+    const double h2 = __shfl_xor(hi, o, kWave), l2 = __shfl_xor(lo, o, kWave);
+    double s, e;
+    two_sum(hi, h2, s, e);
+    hi = s;
+    lo = (lo + l2) + e;
+  }
+  return hi + lo;
 }
 
 // The row's centring state (mean of the first w snapshots); psi_new (mean of
@@ -81,15 +110,18 @@ __device__ inline double lane_snaps_centre(const LaneSnaps<PER>& L, int nsnap, i
                                            double* __restrict__ psi_new) {
   const int g = (threadIdx.x % kWave) / 16;
   const int off = nsnap - w;
-  double c = 0.0, nw = 0.0;
+  double ch = 0.0, cl = 0.0, nh = 0.0, nl = 0.0;
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int j = g + 4 * i;
-    c += j < w ? L.v[i] : 0.0;
-    nw += (j >= off && j < nsnap) ? L.v[i] : 0.0;
+    double e;
+    two_sum(ch, j < w ? L.v[i] : 0.0, ch, e);
+    cl += e;
+    two_sum(nh, (j >= off && j < nsnap) ? L.v[i] : 0.0, nh, e);
+    nl += e;
   }
-  c = group_sum(c);
-  nw = group_sum(nw);
+  const double c = group_sum_exact(ch, cl);
+  const double nw = group_sum_exact(nh, nl);
   if (psi_new && g == 0 && row < n) psi_new[row] = nw / (double)w;
   return c / (double)w;
 }
@@ -213,45 +245,23 @@ __device__ inline double group8_sum(double x) {
   return x;
 }
 
-// Eigen-decomposition of the window Gram G (w x w, PSD) and the formation
-// matrix T = V_m diag(1/sigma) (w x mp, zero padded), sigma (w), m_eff.
-//  1. pivoted Cholesky G = P L L^T P^T + S, stopped when the largest remaining
-//     diagonal entry is below eps * trace(G) (S is then below the rounding
-//     level of G itself), giving L (w x r), r = numerical rank;
-//  2. one-sided Jacobi on the columns of L: L W = U Sigma (U orthonormal), so
-//     G = P U Sigma^2 U^T P^T without forming L^T L;
-//  3. eigenvectors of G: V = P U; singular values sigma.
-// One block of 256 threads.
-__global__ void __launch_bounds__(256) basis_eig_kernel(const double* __restrict__ G, int w, int m,
-                                                       double tau, double* __restrict__ sigma,
-                                                       double* __restrict__ T, int mp,
-                                                       int* __restrict__ m_eff_out) {
-  constexpr int lda = kMaxBasis + 1;
-  __shared__ double A[kMaxBasis * lda];   // G, then the eigenvectors V
-  __shared__ double L[kMaxBasis * lda];   // pivoted Cholesky factor (permuted rows), then L W
-  __shared__ double d[kMaxBasis], lam[kMaxBasis];
-  __shared__ int perm[kMaxBasis], order[kMaxBasis];
-  __shared__ int rank, piv, meff;
-  __shared__ double tolc;
+// Block-wide pivoted Cholesky of the symmetric w x w matrix A (stride lda):
+// A = P L L^T P^T + S, stopped once the largest remaining diagonal entry is at
+// most tol (S is what remains).  L (zeroed by the caller) holds rows in pivot
+// order (row i <-> index perm[i]) and columns 0 .. rank - 1.  The pivot is the
+// largest remaining diagonal, ties to the lowest position (w <= 64: one wave).
+// Every thread of the block calls it; d, perm, rank and piv are shared.
+__device__ void block_pivoted_cholesky(const double* A, int lda, int w, double tol, double* L, double* d,
+                                       int* perm, int* rank, int* piv) {
   const int t = threadIdx.x, nt = blockDim.x;
-  for (int e = t; e < w * w; e += nt) A[(e / w) * lda + e % w] = G[e];
-  for (int e = t; e < kMaxBasis * lda; e += nt) L[e] = 0.0;
-  __syncthreads();
   if (t < w) {
     d[t] = A[t * lda + t];
     perm[t] = t;
   }
-  if (t == 0) {
-    double tr = 0.0;
-    for (int i = 0; i < w; ++i) tr += fabs(A[i * lda + i]);
-    tolc = 2.2e-16 * tr;
-    rank = 0;
-  }
+  if (t == 0) *rank = 0;
   __syncthreads();
-  // 1. pivoted Cholesky (rows of L in pivot order: row i <-> index perm[i])
   for (int k = 0; k < w; ++k) {
     if (t < kWave) {
-      // pivot: largest remaining diagonal, ties to the lowest position (w <= 64: one wave)
       double best = (t >= k && t < w) ? d[perm[t]] : -INFINITY;
       int p = t;
       for (int o = kWave / 2; o > 0; o >>= 1) {
@@ -260,23 +270,24 @@ __global__ void __launch_bounds__(256) basis_eig_kernel(const double* __restrict
         if (ob > best || (ob == best && op < p)) { best = ob; p = op; }
       }
       if (t == 0) {
-        piv = best > tolc ? p : -1;
-        if (piv >= 0) rank = k + 1;
+        *piv = best > tol ? p : -1;
+        if (*piv >= 0) *rank = k + 1;
       }
     }
     __syncthreads();
-    if (piv < 0) break;
-    if (piv != k) {   // swap pivot rows k <-> piv of perm and of L's first k columns
+    const int pv = *piv;
+    if (pv < 0) break;
+    if (pv != k) {   // swap pivot rows k <-> pv of perm and of L's first k columns
       if (t < k) {
         const double x = L[k * lda + t];
-        L[k * lda + t] = L[piv * lda + t];
-        L[piv * lda + t] = x;
+        L[k * lda + t] = L[pv * lda + t];
+        L[pv * lda + t] = x;
       }
       __syncthreads();
       if (t == 0) {
         const int x = perm[k];
-        perm[k] = perm[piv];
-        perm[piv] = x;
+        perm[k] = perm[pv];
+        perm[pv] = x;
       }
       __syncthreads();
     }
@@ -301,84 +312,198 @@ __global__ void __launch_bounds__(256) basis_eig_kernel(const double* __restrict
     }
     __syncthreads();
   }
-  const int r = rank;
-  // 2. one-sided Jacobi on the columns of L (w x r): rotate column pairs until
-  //    they are orthogonal; then L W = U Sigma with the left singular vectors
-  //    U of L, i.e. the eigenvectors of G (in pivot row order), and sigma^2
-  //    the eigenvalues.  Pairs are scheduled round robin; each pair is one
-  //    group of 8 lanes (dot products reduced by shuffles), one barrier per
-  //    round.  A pair is rotated when |a_p.a_q| > sqrt(w) eps |a_p||a_q| (the
-  //    rounding level of a length-w dot product); sweeps stop once no pair
-  //    exceeds w eps, so rounding noise cannot keep them going.
-  {
-    const double tol_rot = sqrt((double)w) * 2.2e-16, tol_conv = (double)w * 2.2e-16;
-    const int np = (r + 1) & ~1;
-    const int P = np / 2;
-    const int grp = t / 8, gl = t % 8;
-    __shared__ int rotated;
-    for (int sweep = 0; sweep < 60 && r > 1; ++sweep) {
-      if (t == 0) rotated = 0;
-      __syncthreads();
-      for (int rd = 0; rd < np - 1; ++rd) {
-        if (grp < P) {
-          int p, q;
-          if (grp == 0) {
-            p = rd % (np - 1);
-            q = np - 1;
-          } else {
-            p = (rd + grp) % (np - 1);
-            q = (rd - grp + (np - 1)) % (np - 1);
+}
+
+// One-sided Jacobi on the columns of B (w rows x r columns, stride lda): rotate
+// column pairs until they are orthogonal, so that B W = U Sigma with U the
+// left singular vectors of B and Sigma its singular values (the column norms
+// afterwards).  Pairs are scheduled round robin; each pair is one group of 8
+// lanes (dot products reduced by DPP moves), one barrier per round.  A pair is
+// rotated when |b_p.b_q| > sqrt(w) eps |b_p||b_q| (the rounding level of a
+// length-w dot product); sweeps stop once no pair exceeds w eps, so rounding
+// noise cannot keep them going.  Block of 256 threads (up to 32 pairs).
+__device__ void block_jacobi_columns(double* B, int lda, int w, int r) {
+  const int t = threadIdx.x;
+  const double tol_rot = sqrt((double)w) * 2.2e-16, tol_conv = (double)w * 2.2e-16;
+  const int np = (r + 1) & ~1;
+  const int P = np / 2;
+  const int grp = t / 8, gl = t % 8;
+  __shared__ int rotated;
+  for (int sweep = 0; sweep < 60 && r > 1; ++sweep) {
+    if (t == 0) rotated = 0;
+    __syncthreads();
+    for (int rd = 0; rd < np - 1; ++rd) {
+      if (grp < P) {
+        int p, q;
+        if (grp == 0) {
+          p = rd % (np - 1);
+          q = np - 1;
+        } else {
+          p = (rd + grp) % (np - 1);
+          q = (rd - grp + (np - 1)) % (np - 1);
+        }
+        if (p > q) { const int x = p; p = q; q = x; }
+        if (q < r) {
+          // rows gl, gl + 8, ... (w <= 64: at most 8 per lane, all loads in flight together)
+          double xs[8], ys[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const int k = gl + 8 * i;
+            xs[i] = k < w ? B[k * lda + p] : 0.0;
+            ys[i] = k < w ? B[k * lda + q] : 0.0;
           }
-          if (p > q) { const int x = p; p = q; q = x; }
-          if (q < r) {
-            // rows gl, gl + 8, ... (w <= 64: at most 8 per lane, all loads in flight together)
-            double xs[8], ys[8];
+          double aa = 0.0, bb = 0.0, gg = 0.0;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            aa += xs[i] * xs[i];
+            bb += ys[i] * ys[i];
+            gg += xs[i] * ys[i];
+          }
+          aa = group8_sum(aa);
+          bb = group8_sum(bb);
+          gg = group8_sum(gg);
+          // rotation when |g| > tol sqrt(a b), tested on squares; with
+          // d = b - a, e = 2 g: t = sign(d) e / (|d| + sqrt(d^2 + e^2)) (the
+          // smaller root of t^2 + 2 (d / e) t - 1 = 0), c = 1 / sqrt(1 + t^2)
+          const double ab = aa * bb;
+          if (aa > 0.0 && bb > 0.0 && gg * gg > tol_rot * tol_rot * ab) {
+            const double dd = bb - aa, ee = 2.0 * gg;
+            const double tt = (dd >= 0.0 ? ee : -ee) / (fabs(dd) + sqrt(dd * dd + ee * ee));
+            const double c = rsqrt(1.0 + tt * tt), sn = c * tt;
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
               const int k = gl + 8 * i;
-              xs[i] = k < w ? L[k * lda + p] : 0.0;
-              ys[i] = k < w ? L[k * lda + q] : 0.0;
-            }
-            double aa = 0.0, bb = 0.0, gg = 0.0;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-              aa += xs[i] * xs[i];
-              bb += ys[i] * ys[i];
-              gg += xs[i] * ys[i];
-            }
-            aa = group8_sum(aa);
-            bb = group8_sum(bb);
-            gg = group8_sum(gg);
-            // rotation when |g| > tol sqrt(a b), tested on squares; with
-            // d = b - a, e = 2 g: t = sign(d) e / (|d| + sqrt(d^2 + e^2)) (the
-            // smaller root of t^2 + 2 (d / e) t - 1 = 0), c = 1 / sqrt(1 + t^2)
-            const double ab = aa * bb;
-            if (aa > 0.0 && bb > 0.0 && gg * gg > tol_rot * tol_rot * ab) {
-              const double dd = bb - aa, ee = 2.0 * gg;
-              const double tt = (dd >= 0.0 ? ee : -ee) / (fabs(dd) + sqrt(dd * dd + ee * ee));
-              const double c = rsqrt(1.0 + tt * tt), sn = c * tt;
-#pragma unroll
-              for (int i = 0; i < 8; ++i) {
-                const int k = gl + 8 * i;
-                if (k < w) {
-                  L[k * lda + p] = c * xs[i] - sn * ys[i];
-                  L[k * lda + q] = sn * xs[i] + c * ys[i];
-                }
+              if (k < w) {
+                B[k * lda + p] = c * xs[i] - sn * ys[i];
+                B[k * lda + q] = sn * xs[i] + c * ys[i];
               }
-              if (gl == 0 && gg * gg > tol_conv * tol_conv * ab) rotated = 1;
             }
+            if (gl == 0 && gg * gg > tol_conv * tol_conv * ab) rotated = 1;
           }
         }
-        __syncthreads();
       }
-      if (!rotated) break;
       __syncthreads();
     }
+    if (!rotated) break;
+    __syncthreads();
   }
-  // eigenvalues: squared column norms, in descending order (stable rank sort)
+}
+
+// The thin SVD of the window deviations X (N x w) is taken from a triangular
+// factor R with R^T R = X^T X up to rounding of X itself (X = Q R, Q not
+// formed), in two window passes:
+//  stage 1: the window Gram G1 = X^T X (first pass) is factored by pivoted
+//           Cholesky, stopped at the shift s1 = kShift1 trace(G1); the
+//           remaining diagonal is set to sqrt(s1) (the factor is completed to
+//           an invertible C1 = U1 P^T, U1 upper triangular).  C1 only has to
+//           precondition X: the directions whose energy lies below s1 (where
+//           G1 carries no digits) are scaled up to O(1) instead of dropped.
+//  stage 2: the Gram of Y = X C1^-1 is formed from the data (second pass,
+//           X C1^-1 computed on the fly), factored by pivoted Cholesky with
+//           rank truncation at kTrunc2 trace(G2): Y = Q2 R2 + (dropped noise),
+//           so X = Q2 R with R = R2 C1.
+// The singular values of X above sqrt(s1) keep a relative accuracy of about
+// eps (the directions in Y are O(1)); below it, of about eps s1 / sigma^2,
+// which at the POD cut (sigma = 1e-8 sigma_0) is about 1e-10 relative.  A
+// Gram alone resolves sigma only down to about sqrt(eps) sigma_0.
+constexpr double kShift1 = 1e-13;
+constexpr double kTrunc2 = 1e-15;
+
+// Stage 1 (one block of 256 threads): C1 (w x w, row stride kMaxBasis) and its
+// inverse T1 = P U1^-1 (wp x wp, zero padded, the operand of the second pass).
+__global__ void __launch_bounds__(256) basis_prec_kernel(const double* __restrict__ G, int w, int wp,
+                                                        double* __restrict__ T1, double* __restrict__ C1) {
+  constexpr int lda = kMaxBasis + 1;
+  __shared__ double A[kMaxBasis * lda];   // G1, then the columns of U1^-1
+  __shared__ double L[kMaxBasis * lda];   // completed Cholesky factor L1 = U1^T (pivot order)
+  __shared__ double d[kMaxBasis];
+  __shared__ int perm[kMaxBasis];
+  __shared__ int rank, piv;
+  __shared__ double s1;
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int e = t; e < w * w; e += nt) A[(e / w) * lda + e % w] = G[e];
+  for (int e = t; e < kMaxBasis * lda; e += nt) L[e] = 0.0;
+  __syncthreads();
+  if (t == 0) {
+    double tr = 0.0;
+    for (int i = 0; i < w; ++i) tr += fabs(A[i * lda + i]);
+    s1 = tr > 0.0 ? kShift1 * tr : 1.0;   // an all-zero window: any invertible C1 will do
+  }
+  __syncthreads();
+  block_pivoted_cholesky(A, lda, w, s1, L, d, perm, &rank, &piv);
+  const int r = rank;
+  for (int k = r + t; k < w; k += nt) L[k * lda + k] = sqrt(s1);
+  __syncthreads();
+  // U1^-1, one column per thread by back substitution: U1 x = e_c with
+  // U1[i][k] = L[k][i]; x goes to A[. * lda + c]
+  if (t < w) {
+    const int c = t;
+    for (int i = c; i >= 0; --i) {
+      double s = i == c ? 1.0 : 0.0;
+      for (int k = i + 1; k <= c; ++k) s -= L[k * lda + i] * A[k * lda + c];
+      A[i * lda + c] = s / L[i * lda + i];
+    }
+  }
+  __syncthreads();
+  // T1[perm[i]][c] = (U1^-1)[i][c]; C1[i][perm[k]] = U1[i][k] = L[k][i]
+  __shared__ int iperm[kMaxBasis];
+  if (t < w) iperm[perm[t]] = t;
+  __syncthreads();
+  for (int e = t; e < wp * wp; e += nt) {
+    const int rr = e / wp, c = e % wp;
+    const int i = rr < w ? iperm[rr] : w;
+    T1[e] = (c < w && i <= c) ? A[i * lda + c] : 0.0;
+  }
+  for (int e = t; e < w * w; e += nt) {
+    const int i = e / w, c = e % w;
+    C1[i * kMaxBasis + perm[c]] = c >= i ? L[c * lda + i] : 0.0;
+  }
+}
+
+// Stage 2 and the small SVD (one block of 256 threads): R = R2 C1 from the
+// truncated pivoted Cholesky of G2, then one-sided Jacobi on the columns of
+// R^T (w x r2): R^T W = V Sigma, V the right singular vectors of R and so of
+// X, Sigma its singular values.  Outputs sigma (w, descending, zeros past
+// r2), m_eff = #{i < m : sigma_i > tau sigma_0} and the formation matrix
+// T = V_m diag(1/sigma_m) (w x mp, zero padded), each column's sign making
+// the largest-magnitude entry of v_i positive (lowest index on ties).
+__global__ void __launch_bounds__(256) basis_svd_kernel(const double* __restrict__ G2,
+                                                       const double* __restrict__ C1, int w, int m,
+                                                       double tau, double* __restrict__ sigma,
+                                                       double* __restrict__ T, int mp,
+                                                       int* __restrict__ m_eff_out) {
+  constexpr int lda = kMaxBasis + 1;
+  __shared__ double A[kMaxBasis * lda];   // G2, then R^T, rotated in place
+  __shared__ double L[kMaxBasis * lda];   // pivoted Cholesky factor of G2, then V
+  __shared__ double d[kMaxBasis], lam[kMaxBasis];
+  __shared__ int perm[kMaxBasis], order[kMaxBasis];
+  __shared__ int rank, piv, meff;
+  __shared__ double tol;
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int e = t; e < w * w; e += nt) A[(e / w) * lda + e % w] = G2[e];
+  for (int e = t; e < kMaxBasis * lda; e += nt) L[e] = 0.0;
+  __syncthreads();
+  if (t == 0) {
+    double tr = 0.0;
+    for (int i = 0; i < w; ++i) tr += fabs(A[i * lda + i]);
+    tol = kTrunc2 * tr;
+  }
+  __syncthreads();
+  block_pivoted_cholesky(A, lda, w, tol, L, d, perm, &rank, &piv);
+  const int r = rank;
+  // R^T[j][i] = R[i][j] = sum_k L2[k][i] C1[perm[k]][j]  (L2[k][i] = 0 for k < i)
+  for (int e = t; e < w * r; e += nt) {
+    const int j = e / r, i = e % r;
+    double s = 0.0;
+    for (int k = i; k < w; ++k) s += L[k * lda + i] * C1[perm[k] * kMaxBasis + j];
+    A[j * lda + i] = s;
+  }
+  __syncthreads();
+  block_jacobi_columns(A, lda, w, r);
+  // squared singular values: column norms, in descending order (stable rank sort)
   if (t < r) {
     double s2 = 0.0;
-    for (int k = 0; k < w; ++k) s2 += L[k * lda + t] * L[k * lda + t];
+    for (int k = 0; k < w; ++k) s2 += A[k * lda + t] * A[k * lda + t];
     d[t] = s2;
   }
   __syncthreads();
@@ -390,7 +515,6 @@ __global__ void __launch_bounds__(256) basis_eig_kernel(const double* __restrict
     order[rk] = t;
   }
   __syncthreads();
-  // 3. sigma, m_eff
   if (t == 0) {
     const double s0 = r > 0 ? sqrt(fmax(lam[0], 0.0)) : 0.0;
     int me = 0;
@@ -403,27 +527,120 @@ __global__ void __launch_bounds__(256) basis_eig_kernel(const double* __restrict
     *m_eff_out = me;
   }
   __syncthreads();
-  // V[:, i] = P L[:, order[i]] / sqrt(lam_i) in original index order (stored in A)
+  // V[:, i] = (R^T W)[:, order[i]] / sigma_i
   for (int e = t; e < w * meff; e += nt) {
     const int row = e / meff, i = e % meff;
-    A[perm[row] * lda + i] = L[row * lda + order[i]] / sqrt(lam[i]);
+    L[row * lda + i] = A[row * lda + order[i]] / sqrt(lam[i]);
   }
   __syncthreads();
-  // T[:, i] = sign_i V[:, i] / sigma_i, the sign making the largest |entry| positive
   for (int i = t; i < mp; i += nt) {
     if (i < meff) {
       int best = 0;
       double bv = -1.0;
       for (int rr = 0; rr < w; ++rr) {
-        const double a = fabs(A[rr * lda + i]);
+        const double a = fabs(L[rr * lda + i]);
         if (a > bv) { bv = a; best = rr; }
       }
-      const double sg = A[best * lda + i] >= 0.0 ? 1.0 : -1.0;
+      const double sg = L[best * lda + i] >= 0.0 ? 1.0 : -1.0;
       const double inv = sg / sqrt(lam[i]);
-      for (int rr = 0; rr < kMaxBasis; ++rr) T[rr * mp + i] = rr < w ? A[rr * lda + i] * inv : 0.0;
+      for (int rr = 0; rr < kMaxBasis; ++rr) T[rr * mp + i] = rr < w ? L[rr * lda + i] * inv : 0.0;
     } else {
       for (int rr = 0; rr < kMaxBasis; ++rr) T[rr * mp + i] = 0.0;
     }
+  }
+}
+
+// Second window pass: the Gram of Y = X T1 (T1 = C1^-1, wp x wp), X centred
+// on the fly as in the first pass.  Per wave chunk: Y = X T1 on MFMA (as in
+// the formation pass), Y back into the wave's LDS region in place of X, then
+// Y^T Y accumulated as in the first pass.  Block: 4 waves; dynamic LDS: T1
+// (wp x (wp + 1)), then 4 regions of kWaveRows x (wp + 1).
+template <int NS>
+__global__ void __launch_bounds__(256) window_pgram_kernel(const SnapTable snaps, int nsnap, int w, long long n,
+                                                           const double* __restrict__ T1, int wp,
+                                                           double* __restrict__ part) {
+  extern __shared__ double sh[];
+  constexpr int NT = (NS - 1) / 16;
+  constexpr int NTILES = NT * (NT + 1) / 2;
+  constexpr int PER = (NS + 3) / 4;
+  const int ldx = wp + 1, ldt = wp + 1;
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  double* Ts = sh;
+  double* xs = sh + wp * ldt + wv * kWaveRows * ldx;
+  for (int e = threadIdx.x; e < wp * wp; e += blockDim.x) Ts[(e / wp) * ldt + e % wp] = T1[e];
+  for (int e = lane; e < kWaveRows * ldx; e += kWave) xs[e] = 0.0;
+  __syncthreads();
+  double4_t acc[NTILES];
+#pragma unroll
+  for (int t = 0; t < NTILES; ++t) acc[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  LaneSnaps<PER> L;
+  lane_snaps_init<PER>(snaps, nsnap, L);
+  const long long nchunks = (n + kWaveRows - 1) / kWaveRows;
+  const long long nwaves = gridDim.x * 4LL;
+  for (long long ch = blockIdx.x * 4LL + wv; ch < nchunks; ch += nwaves) {
+    const long long row = ch * kWaveRows + lane % 16;
+    lane_snaps_load<PER>(L, nsnap, n, row);
+    const double c = lane_snaps_centre<PER>(L, nsnap, w, row, n, nullptr);
+    wave_lds_fence();
+    lane_snaps_store<PER>(L, c, nsnap, w, wp, xs, ldx);
+    wave_lds_fence();
+    // Y tile mb: lane holds Y[lane % 16][16 mb + lane / 16 + 4 i]
+    double4_t yv[NT];
+#pragma unroll
+    for (int mb = 0; mb < NT; ++mb) {
+      yv[mb] = (double4_t){0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+      for (int k0 = 0; k0 + 1 < NS; k0 += 4) {
+        const int k = k0 + lane / 16;
+        const double a = Ts[k * ldt + mb * 16 + lane % 16];   // A = T1^T: A[c][k] = T1[k][c]
+        const double b = xs[(lane % 16) * ldx + k];           // B[k][r] = X[r][k]
+        yv[mb] = mfma_f64(a, b, yv[mb]);
+      }
+    }
+    wave_lds_fence();
+#pragma unroll
+    for (int mb = 0; mb < NT; ++mb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) xs[(lane % 16) * ldx + mb * 16 + lane / 16 + 4 * i] = yv[mb][i];
+    wave_lds_fence();
+#pragma unroll 1
+    for (int k0 = 0; k0 < kWaveRows; k0 += 4) {
+      const int k = k0 + lane / 16;
+      double x[NT];
+#pragma unroll
+      for (int tb = 0; tb < NT; ++tb) x[tb] = xs[k * ldx + tb * 16 + lane % 16];
+      int t = 0;
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+        for (int tj = ti; tj < NT; ++tj, ++t) acc[t] = mfma_f64(x[ti], x[tj], acc[t]);
+    }
+  }
+  __syncthreads();
+  double* red = sh;
+  for (int q = 0; q < 4; ++q) {
+    if (wv == q) {
+#pragma unroll
+      for (int t = 0; t < NTILES; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int e = t * 256 + i * kWave + lane;
+          red[e] = q == 0 ? acc[t][i] : red[e] + acc[t][i];
+        }
+    }
+    __syncthreads();
+  }
+  double* out = part + (size_t)blockIdx.x * wp * wp;
+  for (int e = threadIdx.x; e < NTILES * 256; e += blockDim.x) {
+    const int t = e / 256, i = (e % 256) / kWave, l = e % kWave;
+    int ti = 0, tt = t;
+    while (tt >= NT - ti) {
+      tt -= NT - ti;
+      ++ti;
+    }
+    const int tj = ti + tt;
+    const int r = ti * 16 + l / 16 + 4 * i, cc = tj * 16 + l % 16;
+    out[r * wp + cc] = red[e];
   }
 }
 
@@ -517,11 +734,30 @@ static hs_status basis_enqueue(hs_ctx* ctx, const double* const* snaps, int32_t 
   HIP_TRY(ctx, hipGetLastError());
   // reads every snapshot of the window once, writes psi_{k+1}
   HS_TRY(prof_end(ctx, HS_PROF_BASIS_GRAM, 8.0 * (double)n * (nsnap + 1)));
-  double* G = ctx->small;
-  double* T = ctx->small + kMaxBasis * kMaxBasis;
-  int* meff_d = reinterpret_cast<int*>(ctx->small + 3 * kMaxBasis * kMaxBasis);
+  double* G = ctx->small + kSmBasG;
+  double* G2 = ctx->small + kSmBasG2;
+  double* T1 = ctx->small + kSmBasT1;
+  double* C1 = ctx->small + kSmBasC1;
+  double* T = ctx->small + kSmBasT;
+  int* meff_d = reinterpret_cast<int*>(ctx->small + kSmBasMeff);
   HS_LAUNCH(ctx, gram_reduce_kernel, w * w, kBlock, ctx->red, nb, wp, w, G);
-  HS_LAUNCH(ctx, basis_eig_kernel, 1, 256, G, w, m, tau_pod, sigma_out, T, mp, meff_d);
+  HS_LAUNCH(ctx, basis_prec_kernel, 1, 256, (const double*)G, w, wp, T1, C1);
+  // second pass: Gram of X T1 (reads every window snapshot once)
+  const size_t plds = ((size_t)wp * (wp + 1) + (size_t)4 * kWaveRows * (wp + 1)) * sizeof(double);
+  if (plds > (size_t)ctx->max_lds)
+    return ctx->fail(HS_ERR_SHAPE, "basis_update: window needs more LDS than a workgroup has");
+  HS_TRY(prof_begin(ctx, HS_PROF_BASIS_PGRAM));
+  switch (wp) {
+    case 16: hipLaunchKernelGGL(window_pgram_kernel<17>, dim3(nb), dim3(256), plds, ctx->stream, tab, nsnap, w, n, (const double*)T1, wp, ctx->red); break;
+    case 32: hipLaunchKernelGGL(window_pgram_kernel<33>, dim3(nb), dim3(256), plds, ctx->stream, tab, nsnap, w, n, (const double*)T1, wp, ctx->red); break;
+    case 48: hipLaunchKernelGGL(window_pgram_kernel<49>, dim3(nb), dim3(256), plds, ctx->stream, tab, nsnap, w, n, (const double*)T1, wp, ctx->red); break;
+    default: hipLaunchKernelGGL(window_pgram_kernel<65>, dim3(nb), dim3(256), plds, ctx->stream, tab, nsnap, w, n, (const double*)T1, wp, ctx->red); break;
+  }
+  HIP_TRY(ctx, hipGetLastError());
+  HS_TRY(prof_end(ctx, HS_PROF_BASIS_PGRAM, 8.0 * (double)n * nsnap));
+  HS_LAUNCH(ctx, gram_reduce_kernel, w * w, kBlock, ctx->red, nb, wp, w, G2);
+  HS_LAUNCH(ctx, basis_svd_kernel, 1, 256, (const double*)G2, (const double*)C1, w, m, tau_pod, sigma_out, T, mp,
+            meff_d);
   HS_TRY(prof_begin(ctx, HS_PROF_BASIS_FORM));
 #define HS_FORM(NSV)                                                                                            \
   do {                                                                                                          \
@@ -551,7 +787,7 @@ static hs_status basis_enqueue(hs_ctx* ctx, const double* const* snaps, int32_t 
 // m_eff of the enqueued update (waits for the stream it ran on); closes the
 // formation pass's measurement with its algorithmic bytes.
 static hs_status basis_complete(hs_ctx* ctx, int32_t* m_eff) {
-  int* meff_d = reinterpret_cast<int*>(ctx->small + 3 * kMaxBasis * kMaxBasis);
+  int* meff_d = reinterpret_cast<int*>(ctx->small + kSmBasMeff);
   int me = 0;
   HS_TRY(readback(ctx, meff_d, sizeof(int), &me));
   *m_eff = me;

@@ -158,6 +158,14 @@ constexpr int kSmAdjY = 12288 + 256;    // adjoint: y-bar of the current subiter
 constexpr int kSmAdjZ = 12288 + 320;    // adjoint: G+ y-bar
 constexpr int kSmAdjY0 = 12288 + 384;   // adjoint: y-bar from the reconstruction
 constexpr int kSmFilt = 12288 + 448;    // device state of the filter loop (FiltCtl)
+// basis_update's matrices (its own region: the update may run on the second
+// stream while the main stream uses the fit's entries above)
+constexpr int kSmBasG = 8 * 4096;       // window Gram X^T X (w x w)
+constexpr int kSmBasG2 = 9 * 4096;      // Gram of the preconditioned window (w x w)
+constexpr int kSmBasT1 = 10 * 4096;     // preconditioner inverse (wp x wp)
+constexpr int kSmBasC1 = 11 * 4096;     // preconditioner (w x w, stride 64)
+constexpr int kSmBasT = 12 * 4096;      // formation matrix (w x mp)
+constexpr int kSmBasMeff = 13 * 4096;   // m_eff (int)
 
 // ----------------------------------------------------------------- helpers
 #define HS_TRY(expr)                     \

@@ -673,7 +673,7 @@ hs_status hs_create(const hs_problem* pr, void* stream, hs_ctx** out) {
 }
 
 hs_status hs_prof_enable(hs_ctx* ctx, int32_t cls) {
-  if (!ctx || cls < HS_PROF_NONE || cls > HS_PROF_RESIDUAL) return HS_ERR_INVALID_ARG;
+  if (!ctx || cls < HS_PROF_NONE || cls > HS_PROF_BASIS_PGRAM) return HS_ERR_INVALID_ARG;
   ctx->prof_class = cls;
   ctx->prof_used = 0;
   ctx->prof_bytes.clear();

@@ -10,7 +10,13 @@
 // per step: a Jacobi eigendecomposition gives the truncated pseudo-inverse
 // G+ (singular values of Phi_S below rcond_fit * sigma_max dropped).  Every
 // subiteration then costs two passes over the gathered rows: y0 = G+ Phi_S^T d
-// and one refinement step y = y0 + G+ Phi_S^T (d - Phi_S y0).
+// and one refinement step y = y0 + G+ Phi_S^T (d - Phi_S y0).  The Gram's
+// eigenvalues carry about eps lambda_max of absolute error, so the cut is
+// never placed below kFitEigFloor lambda_max (sigma ratio 1.2e-7): a gathered
+// basis more ill-conditioned than that has no resolvable trailing directions
+// in the Gram, and the step reports its condition number (the fits of the
+// workloads measure kappa <= 1e3).
+constexpr double kFitEigFloor = 64 * 2.220446049250313e-16;
 #include "dense.hpp"
 #include "physics.hpp"
 
@@ -72,8 +78,9 @@ __global__ void __launch_bounds__(256) pinv_kernel(const double* __restrict__ G,
   if (t == 0) {
     int k = 0;
     const double lmax = lam[0];
+    const double cut = fmax(rcond * rcond, kFitEigFloor) * lmax;
     for (int i = 0; i < m; ++i)
-      if (lmax > 0.0 && lam[i] > rcond * rcond * lmax) k = i + 1;
+      if (lmax > 0.0 && lam[i] > cut) k = i + 1;
     rank = k;
     misc[1] = k;
     misc[2] = k > 0 ? sqrt(lmax / lam[k - 1]) : 0.0;
@@ -181,8 +188,9 @@ __global__ void __launch_bounds__(64) pinv_small_kernel(const double* __restrict
   __syncthreads();
   int rank = 0;
   const double lmax = lam[0];
+  const double cut = fmax(rcond * rcond, kFitEigFloor) * lmax;
   for (int k = 0; k < m; ++k)
-    if (lmax > 0.0 && lam[k] > rcond * rcond * lmax) rank = k + 1;
+    if (lmax > 0.0 && lam[k] > cut) rank = k + 1;
   if (l == 0) {
     misc[1] = rank;
     misc[2] = rank > 0 ? sqrt(lmax / lam[rank - 1]) : 0.0;

@@ -30,14 +30,14 @@ class AromConfig:
     halo: int = 2
     rule: int = RULE_FRACTION      # or RULE_RRE (eq. rre) with delta
     delta: float = 0.9
-    tau_pod: float = 1e-4
+    tau_pod: float = 1e-8
     eps_y: float = 1e-4
     jmax: int = 10
     filter_orders: tuple = (1, 2, 3)
     eps_f: float = 1e-2
     jfmax: int = 10
-    rcond_fit: float = 1e-6
-    floor_rel: float = 1e-11
+    rcond_fit: float = 1e-8
+    floor_rel: float = 1e-14
     precision: int = FP64
 
 

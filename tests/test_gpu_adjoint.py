@@ -223,8 +223,11 @@ def test_trajectory_gradient_matches_oracle(name):
             # (1e-10 + 10 eps) / gap (Davis-Kahan)
             assert np.max(np.abs(host(psi_g) - st["psi"])) <= 1e-10 * np.max(np.abs(st["psi"]))
             X = b["X"]
-            dp = np.linalg.norm(P @ (P.T @ X) - st["Phi"] @ (st["Phi"].T @ X)) / np.linalg.norm(X)
-            assert dp <= projector_tol(b["sigma"], m, c=10.0 + 1e-10 / 2.2e-16), (k, dp)
+            Q, _ = np.linalg.qr(P)             # orthogonal projector onto span(Phi_gpu)
+            dp = np.linalg.norm(Q @ (Q.T @ X) - st["Phi"] @ (st["Phi"].T @ X)) / np.linalg.norm(X)
+            # the windows agree to 1e-10 of the states, i.e. 1e-10 |window| / |X| of X
+            ratio = np.sqrt(sum(np.sum(o ** 2) for o in outs[max(0, kk - wl.w): kk + 1])) / np.linalg.norm(X)
+            assert dp <= projector_tol(b["sigma"], m, c=10.0 + 1e-10 * ratio / 2.2e-16), (k, dp)
             shared.append({"type": "hybrid", "hat": hat, "tilde": tilde, "Phi": P, "psi": host(psi_g), "J": J,
                            "masks": st["masks"]})
         q_prev = st["out"]
@@ -251,5 +254,7 @@ def test_trajectory_gradient_matches_oracle(name):
     e_shared = rel(g_gpu, lam)
     print(f"  gradient rel: own decisions and bases {e_own:.2e}, shared frozen bases {e_shared:.2e}", flush=True)
     assert e_shared < 1e-10
-    if name != "burgers1d":       # 1D: the fit amplifies trailing-mode differences (8e-7 measured)
-        assert e_own < 1e-9
+    # against the oracle's own run: its windows differ from the GPU's by the
+    # trajectory difference (1e-10), and the gathered fits amplify what that
+    # does to the bases (1D fits reach condition numbers near 1e3)
+    assert e_own < (1e-5 if name == "burgers1d" else 1e-9)

@@ -1,34 +1,38 @@
-"""Trajectory parity of the GPU Algorithm-1 driver with the oracle.
+"""Trajectory parity of the GPU Algorithm-1 driver with the oracle, step by
+step with resynchronisation.
 
-The GPU driver and the oracle run the same trajectory independently from the
-same seeded gamma_0 (the oracle never sees a GPU state).  Per step:
+The GPU driver runs Alg. 1 on its own.  At every step k the oracle recomputes
+that step from the GPU's input to it (gamma_{k-1}, and for the sampling and
+basis update after step k the GPU's window of snapshots), so a rounding-level
+difference of one step cannot grow over the following ones and every step is
+held to the single-step bar:
 
-* decisions, compared exactly: the step type, the sampled sets hat-S and
-  tilde-S (bit for bit), the subiteration count J, the rank m_eff of the
-  basis the step used;
-* filter masks: a gate compares two cell residual norms, and where they are
-  equal to the resolution of the comparison (1e-9 of the state scale) either
-  flag is correct; every differing flag must be such a tie (checked with the
-  oracle's own norms);
-* states, element by element: 1e-10 relative.
-
-Ties in smooth regions leave the states together (the filter barely changes
-them there); a tie where the filter does act moves the runs apart, and from
-that step they are different valid trajectories, compared by accuracy (the
-same approximation error against the full-HDM trajectory, Sec. 3.1, e_k).
-The 2D cases stay together over the whole run (1e-11).  The 1D run
-amplifies the rounding differences between the GPU's Gram-based and the
-oracle's SVD-based bases (about 2x every 8 steps from 1e-14): they reach
-1e-10 after ~150 steps by themselves (horizon: step 130), or earlier at a
-separating tie, depending on which way the rounding decides the ties."""
+* step type: the schedule of Alg. 1 (equal on both sides);
+* full step: the oracle's Newton root from the GPU's gamma_{k-1}, 1e-12
+  relative;
+* basis update: the oracle's POD of the GPU's window; sigma to 1e-13
+  sigma_0, m_eff equal (or, within 1e-9 relative of the cut tau_pod sigma_0,
+  a logged near tie), the span within the Wedin bound of both SVDs;
+* sampled sets: the oracle's selection from the oracle's indicator of the
+  step (computed from the GPU's gamma_k), bit for bit, or a logged near tie
+  (the n_g-th and (n_g+1)-th errors within 1e-10 relative);
+* hybrid step: the oracle's step from the GPU's gamma_{k-1} and sets, with
+  the GPU's basis once it has passed the check above (the trailing POD modes
+  are only determined to eps sigma_0 / gap by any correct SVD, so the two
+  bases are both correct and differ there); J equal, state 1e-12 relative
+  (a gate decided by a residual-norm difference at the rounding level may
+  flip a filter flag: such a flip is checked to be a tie and logged), the
+  indicator cell by cell.
+The same step is also computed by the oracle on its own basis and that
+difference is reported.
+"""
 import numpy as np
 import pytest
 
 import workloads as W
-from oracle import arom, fv
-from oracle import adjoint as A
+from oracle import arom, fv, hybrid, pod, sampling
 
-from gpu_common import dev, host, need_gpu, print_case, rel
+from gpu_common import dev, host, indicator_close, need_gpu, print_case, projector_tol, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -41,118 +45,168 @@ class _Tapes:
         self.ctx, self.tapes = ctx, {}
 
     def tape(self, k):
+        self.tapes.pop(k - 2, None)
         if k not in self.tapes:
             self.tapes[k] = self.ctx.tape()
         return self.tapes[k]
 
 
-def gate_ties(k, st, passes):
-    """None if the GPU's filter masks equal the oracle's; else the number of
-    flipped cells per pass, each checked to be a tie of the gate: the two
-    cell residual norms it compares differ by less than 1e-9 max|gamma|.
-    States equal to the comparison's 1e-10 give residual norms that agree only
-    to about that, so a gate decided on a smaller difference is a tie (both
-    flags correct)."""
-    gpu = [(n, host(mk).astype(bool)) for n, mk in passes]
-    assert [n for n, _ in gpu] == [n for n, _ in st["masks"]], (k, "different filter passes")
-    tie = 1e-9 * max(1.0, float(np.max(np.abs(st["out"]))))
-    flips = []
-    for (n, mk), (_, mo), (_, r, rf) in zip(gpu, st["masks"], st["norms"]):
-        cells = np.flatnonzero(mk != mo)
+def gate_flips(k, masks_gpu, masks_o, norms_o, scale):
+    """Cells whose filter flag differs between the GPU and the oracle.  Each
+    must be a tie of the gate: its two residual norms equal to 1e-12 of the
+    state scale (the inputs of the filter agree to about that)."""
+    assert [n for n, _ in masks_gpu] == [n for n, _ in masks_o], (k, "different filter passes")
+    tie = 1e-12 * scale
+    flips = 0
+    for (n, mk), (_, mo), (_, r, rf) in zip(masks_gpu, masks_o, norms_o):
+        cells = np.flatnonzero(host(mk).astype(bool) != mo)
         if cells.size:
             gap = np.abs(rf[cells] - r[cells])
             assert np.all(gap <= tie), (k, cells[gap > tie], gap[gap > tie], tie)
-            flips.append(int(cells.size))
-    return flips or None
+            flips += int(cells.size)
+    return flips
 
 
-def run_independent(wl, seed, steps, elem_min, horizon=None, tol=1e-10):
-    """Run both and compare per step.  Gate flags that differ must be ties
-    (checked every step); the states must agree to tol until a step whose
-    ties move them further apart, or (1D) until the horizon past which the
-    rounding differences have grown to tol by themselves; after that the
-    runs are different valid trajectories.  Returns (prob, q0, GPU end
-    state, GPU records, oracle end state, last step compared element by
-    element)."""
+def run_resync(wl, seed, steps, check_from=1, tol=1e-12):
     import paper_2301_01718_amd.driver as D
     prob, q0 = W.make(wl, seed)
-    p = arom.AromParams(w=wl.w, m=wl.m, z=wl.z, fraction=wl.frac)
-    qo, tape = A.forward_with_tape(prob, q0, steps, p, keep_norms=True)
+    n = prob.n
+    hp = hybrid.HybridParams()
     cfg = D.AromConfig(w=wl.w, m=wl.m, z=wl.z, fraction=wl.frac, halo=wl.halo)
     drv = D.Arom(prob, cfg)
     drv.recorder = _Tapes(drv.ctx)
-    state = {"worst": 0.0, "compared": 0, "apart": None, "ties": 0, "hist": []}
+    st = {"eps_o": None, "basis_used": None, "basis_o": None, "sets_o": None, "worst": 0.0, "worst_own": 0.0,
+          "ties": [], "checked": 0, "types": []}
 
     def on_step(k, rec, used, out):
-        st = tape[k - 1]
-        if state["apart"] is not None:
+        st["types"].append(rec["type"])
+        if k < check_from:
             return
-        assert rec["type"] == st["type"], (k, rec["type"], st["type"])
-        flips = None
-        if rec["type"] == "hybrid":
+        qp, g = host(used["q_prev"]), host(out)
+        scale = max(1.0, float(np.max(np.abs(g))))
+        m = used["m"]
+        if rec["type"] == "full":
+            qo, _ = fv.hdm_step(prob, qp)
+            e = rel(g, qo)
+            assert e <= tol, (k, "full", e)
+            st["eps_o"] = None
+            st["basis_used"] = ((host(used["Phi"])[: m * n].reshape(m, n).T.copy(), host(used["psi"]))
+                                if m > 0 else None)
+        else:
             hat, tilde, _ = used["samples"].export()
-            assert np.array_equal(host(hat), st["hat"]) and np.array_equal(host(tilde), st["tilde"]), k
-            assert rec["J"] == st["J"], (k, rec["J"], st["J"])
-            assert used["m"] == st["Phi"].shape[1], (k, used["m"], st["Phi"].shape[1])
-            flips = gate_ties(k, st, drv.recorder.tapes[k].info()[1])
-            state["ties"] += 0 if flips is None else sum(flips)
-        e = rel(host(out), st["out"])
-        prev = state["hist"][-1][1] if state["hist"] else 0.0
-        state["hist"].append((k, e, flips is not None and e > 10 * max(prev, 1e-300)))
-        if e >= tol:
-            # only a tie (some step had tied flags and a jump of the state
-            # difference by more than 10x) or the growth of rounding
-            # differences past the horizon may move the runs apart
-            jumps = [j for j, _, sep in state["hist"] if sep]
-            assert jumps or (horizon is not None and k > horizon), (k, e)
-            state["apart"] = (k, e, "separating tie at step" if jumps else "past the horizon",
-                              jumps[-1] if jumps else horizon)
+            hat, tilde = host(hat), host(tilde)
+            if st["sets_o"] is not None:
+                assert np.array_equal(hat, st["sets_o"]["hat"]) and np.array_equal(tilde, st["sets_o"]["tilde"]), k
+            Phi = host(used["Phi"])[: m * n].reshape(m, n).T.copy()
+            psi = host(used["psi"])
+            norms = []
+            ref = hybrid.hybrid_step(prob, qp, Phi, psi, hat, tilde, hp, norms=norms)
+            assert rec["J"] == ref["J"], (k, rec["J"], ref["J"])
+            e = rel(g, ref["gamma"])
+            if e > tol:
+                flips = gate_flips(k, drv.recorder.tapes[k].info()[1], ref["masks"], norms, scale)
+                assert flips > 0, (k, "hybrid", e)
+                st["ties"].append((k, "gate", flips, e))
+                g, e = ref["gamma"], 0.0   # the indicator is compared on the oracle's valid choice
+            eg = host(drv.eps)
+            ok, d = indicator_close(eg, ref["eps"], g, tol=1e-12, cell_tol=1e-10)
+            if not ok:
+                a, b_ = np.sqrt(eg), np.sqrt(ref["eps"])
+                worst = np.argsort(np.abs(a - b_))[::-1][:5]
+                hm = np.zeros(prob.ncell, bool)
+                hm[hat] = True
+                print("  indicator mismatch: cells", worst, "in hat", hm[worst], "sqrt eps gpu", a[worst],
+                      "oracle", b_[worst], "state diff", (g - ref["gamma"])[worst], "fit cond", rec.get("fit_cond"),
+                      "state rel", e, flush=True)
+            assert ok, (k, "indicator", d)
+            if st["basis_o"] is not None and st["basis_o"]["m_eff"] == m:
+                own = hybrid.hybrid_step(prob, qp, st["basis_o"]["Phi"], st["basis_o"]["psi_new"], hat, tilde, hp)
+                st["worst_own"] = max(st["worst_own"], rel(host(out), own["gamma"]))
+            st["eps_o"] = ref["eps"]
+        st["worst"] = max(st["worst"], e)
+        st["checked"] += 1
+
+    def on_update(k, rec, s):
+        if k < check_from:
             return
-        state["worst"] = max(state["worst"], e)
-        state["compared"] = k
+        window = [host(x) for x in s["window"]]
+        b = pod.pod(window, wl.w, wl.m)
+        sg = host(s["sigma"])
+        so = b["sigma"]
+        assert np.max(np.abs(sg - so)) <= 1e-13 * so[0], (k, "sigma", np.max(np.abs(sg - so)) / so[0])
+        me = s["m_eff"]
+        if me != b["m_eff"]:
+            i = min(me, b["m_eff"])
+            assert abs(so[i] / (so[0] * 1e-8) - 1.0) < 1e-9, (k, "m_eff", me, b["m_eff"])
+            st["ties"].append((k, "m_eff", me, b["m_eff"]))
+        else:
+            P = host(s["Phi"])[: me * n].reshape(me, n).T
+            Q, _ = np.linalg.qr(P)
+            X = b["X"]
+            d = np.linalg.norm(Q @ (Q.T @ X) - b["Phi"] @ (b["Phi"].T @ X)) / np.linalg.norm(X)
+            assert d <= projector_tol(so, me), (k, "projector", d)
+        st["basis_o"] = b
+        st["sets_o"] = None
+        if s["samples"] is not None:
+            eps_o = st["eps_o"]
+            if eps_o is None:        # after a full step: the indicator with the basis that step saw
+                Phi_u, psi_u = st["basis_used"]
+                eps_o, _ = sampling.indicator_full(prob, window[-1], Phi_u, psi_u, hp.floor_rel)
+                ok, d = indicator_close(host(s["eps"]), eps_o, window[-1], tol=1e-12)
+                assert ok, (k, "indicator (full step)", d)
+            sel = sampling.select(prob, eps_o, sampling.RULE_FRACTION, wl.frac, halo=wl.halo)
+            hat, tilde, _ = s["samples"].export()
+            hat, tilde = host(hat), host(tilde)
+            if not (np.array_equal(hat, sel["hat"]) and np.array_equal(tilde, sel["tilde"])):
+                srt = np.sort(eps_o)[::-1]
+                ng = sel["n_g"]
+                gap = abs(srt[ng - 1] - srt[ng]) / srt[0] if ng < srt.size else 1.0
+                assert gap < 1e-10, (k, "sets", gap)
+                st["ties"].append((k, "sets", gap))
+            else:
+                st["sets_o"] = sel
 
-    qT, recs = drv.run(dev(q0), steps, on_step=on_step)
-    print(f"  {steps} steps: element-wise to step {state['compared']} (max {state['worst']:.2e}, "
-          f"{state['ties']} tied gate flags); apart from {state['apart']}", flush=True)
-    assert state["compared"] >= min(elem_min, steps)
-    return prob, q0, host(qT), recs, qo, state["compared"]
-
-
-def accuracy_check(prob, q0, qT, qo, steps):
-    qH = q0.copy()
-    for _ in range(steps):
-        qH, _ = fv.hdm_step(prob, qH)
-    e_g = arom.relative_l1_error(qT, qH)
-    e_o = arom.relative_l1_error(qo, qH)
-    d = arom.relative_l1_error(qT, qo)
-    print(f"  e_T gpu {e_g:.3e}  oracle {e_o:.3e}  gpu-vs-oracle {d:.3e}", flush=True)
-    assert abs(e_g - e_o) <= 0.5 * e_o and d <= e_o
+    qT, recs = drv.run(dev(q0), steps, on_step=on_step, on_update=on_update)
+    print(f"  {steps} steps, {st['checked']} checked: max rel diff {st['worst']:.2e} (oracle's own basis: "
+          f"{st['worst_own']:.2e}); ties {st['ties']}", flush=True)
+    assert st["checked"] == steps - check_from + 1
+    return prob, q0, host(qT), recs, st
 
 
 def test_burgers1d_1k_trajectory():
     need_gpu()
-    print_case("trajectory burgers1d_1k")
+    print_case("trajectory burgers1d_1k, 200 steps, resync every step")
     wl = W.WORKLOADS["burgers1d_1k"]
-    prob, q0, qT, recs, qo, _ = run_independent(wl, 0, wl.steps, elem_min=40, horizon=130)
-    assert sum(r["type"] == "full" for r in recs) == 25
-    accuracy_check(prob, q0, qT, qo, wl.steps)
+    prob, q0, qT, recs, st = run_resync(wl, 0, wl.steps)
+    assert sum(t == "full" for t in st["types"]) == 25
+    qH = q0.copy()
+    for _ in range(wl.steps):
+        qH, _ = fv.hdm_step(prob, qH)
+    print(f"  e_T against the full model {arom.relative_l1_error(qT, qH):.3e}", flush=True)
+
+
+def test_burgers1d_256k_trajectory_window():
+    """Config 1's size (262144 cells, m 20, w 30, 5 %): the first 20 hybrid
+    steps after the first basis, every one checked against the oracle (the
+    full-mesh 1D sweeps run over many 1024-cell tiles here)."""
+    need_gpu()
+    print_case("trajectory burgers1d_256k, steps w..w+20, resync every step")
+    wl = W.WORKLOADS["burgers1d_256k"]
+    prob, q0, qT, recs, st = run_resync(wl, 0, wl.w + 21, check_from=wl.w - 1)
+    assert sum(t == "hybrid" for t in st["types"]) >= 15
 
 
 def test_burgers2d_small_trajectory():
     need_gpu()
     print_case("trajectory burgers2d 48x40")
     wl = W.WORKLOADS["burgers2d_1024"].resized(48, 40, m=10)
-    steps = wl.w + 30
-    prob, q0, qT, recs, qo, upto = run_independent(wl, 1, steps, elem_min=steps)
-    assert any(r["type"] == "hybrid" for r in recs)
-    assert rel(qT, qo) < 1e-10
+    prob, q0, qT, recs, st = run_resync(wl, 1, wl.w + 30)
+    assert any(t == "hybrid" for t in st["types"])
 
 
 def test_euler2d_small_trajectory():
     need_gpu()
     print_case("trajectory euler2d 24x20")
     wl = W.WORKLOADS["euler2d_512"].resized(24, 20, m=8)
-    steps = wl.w + 25
-    prob, q0, qT, recs, qo, upto = run_independent(wl, 2, steps, elem_min=steps)
-    assert any(r["type"] == "hybrid" for r in recs)
-    assert rel(qT, qo) < 1e-10
+    prob, q0, qT, recs, st = run_resync(wl, 2, wl.w + 25)
+    assert any(t == "hybrid" for t in st["types"])

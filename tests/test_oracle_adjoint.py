@@ -24,15 +24,19 @@ def test_shapiro_transpose_dot_product(name, nx, ny, n):
     assert abs(lhs - rhs) <= 1e-14 * max(abs(lhs), 1.0) * prob.n ** 0.5
 
 
-def small_case(name, nx, ny, m, seed):
+def small_case(name, nx, ny, m, seed, fraction=0.08):
     wl = W.WORKLOADS[name].resized(nx, ny, m=m)
     prob, q0 = W.make(wl, seed)
-    p = AromParams(w=wl.w, m=wl.m, z=wl.z, fraction=0.08, halo=1)
+    p = AromParams(w=wl.w, m=wl.m, z=wl.z, fraction=fraction, halo=1)
     return wl, prob, q0, p
 
 
+# On 96 cells a fraction of 8 % leaves about 11 fit rows for 6 modes; such
+# nearly square gathered bases reach condition numbers near 1e5, whose
+# kappa^2 eps rounding noise in the fit swamps a central difference at
+# h = 1e-6.  15 % keeps kappa below 200 (measured).
 CASES = {"burgers2d": ("burgers2d_1024", 18, 16, 6, 3), "euler2d": ("euler2d_512", 12, 10, 4, 1),
-         "burgers1d": ("burgers1d_1k", 96, 1, 6, 2)}
+         "burgers1d": ("burgers1d_1k", 96, 1, 6, 2, 0.15)}
 
 
 @pytest.fixture(scope="module", params=list(CASES))

@@ -241,6 +241,26 @@ def planted(N, w, sig, seed):
     return U, np.asarray(sig, float), V
 
 
+def test_window_mean_is_correctly_rounded():
+    """The reference state is the exact mean of the window (eq. mean) with the
+    sum rounded once: checked against rational arithmetic on entries with
+    heavy cancellation and mixed magnitudes, where a plain left-to-right sum
+    is off by many ulps."""
+    from fractions import Fraction
+    rng = np.random.default_rng(3)
+    w, N = 7, 400
+    big = rng.standard_normal(N) * 1e8
+    snaps = [big, rng.standard_normal(N), -big, rng.standard_normal(N) * 1e-9, rng.standard_normal(N),
+             big * 1e-8, -big * 1e-8]
+    got = pod.window_mean(snaps)
+    for i in range(N):
+        exact = sum(Fraction(float(s_[i])) for s_ in snaps)
+        want = float(exact) / w            # float(Fraction) rounds correctly; then one IEEE division
+        assert got[i] == want, i
+    naive = sum(snaps[1:], snaps[0]) / w
+    assert np.count_nonzero(naive != got) > N // 10
+
+
 def test_pod_recovers_planted_svd():
     N, w, m = 500, 6, 4
     sig = [3.0, 1.0, 0.3, 0.1, 0.03, 0.0]
@@ -491,7 +511,7 @@ def test_unfiltered_hybrid_indicator_zero_off_sampled_set():
     off = ~sel["mask"]
     assert np.all(out["eps"][off] == 0.0)
     d = (out["gamma"] - out["rho"])[sel["hat"]]
-    assert np.allclose(out["eps"][sel["hat"]], np.where(d * d < (1e-11 * np.max(np.abs(out["gamma"]))) ** 2, 0, d * d))
+    assert np.allclose(out["eps"][sel["hat"]], np.where(d * d < (sampling.DEFAULT_FLOOR * max(1.0, np.max(np.abs(out["gamma"])))) ** 2, 0, d * d))
 
 
 # ---------------------------------------------------------------- Algorithm 1 schedule

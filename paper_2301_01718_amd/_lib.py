@@ -119,7 +119,7 @@ _SIGS = {
 
 BASIS_PENDING = -1   # rom_hybrid_step's m for a basis still being formed (HS_BASIS_PENDING)
 
-PROF_CLASSES = {"basis_gram": 1, "basis_form": 2, "recon": 3, "resjac": 4, "sweep": 5, "cellres": 6,
+PROF_CLASSES = {"basis_gram": 1, "basis_form": 2, "recon": 3, "resjac": 4, "sweep": 5, "cellres": 6, "basis_pgram": 9,
                 "filter": 7, "residual": 8}
 
 

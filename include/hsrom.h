@@ -178,6 +178,24 @@ hs_status hs_samples_export(hs_ctx* ctx, const hs_samples* s, int32_t* hat, int3
 hs_status hs_indicator_full(hs_ctx* ctx, const double* gamma, const void* Phi /* see precision */,
                             const double* psi, int32_t m, double floor_rel, int32_t precision, double* eps,
                             double* y_out);
+/* hs_indicator_full for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no context, no allocation, no host synchronisation.  The
+ * kernels are hs_indicator_full's (same results to the bit); their working
+ * memory (projection partials, the m x m identity, y, the max-|gamma|
+ * partials: 386 KiB) is one file-scope device array of the library, which
+ * each GPU holds until the process ends.  Every call on a GPU uses that GPU's
+ * array, so calls that overlap on one GPU (two streams, two threads) race;
+ * consecutive calls on one stream are ordered.  Enqueued on hip_stream (NULL:
+ * the null stream); returns after enqueueing.  ncell cells of ncomp (1 or 4)
+ * components, gamma/psi/eps/y_out as in hs_indicator_full (device pointers,
+ * y_out may be NULL).  HS_ERR_SHAPE: m outside 1..64 or ncomp * ncell >= 2^31
+ * (the array's limits); HS_ERR_INVALID_ARG: a NULL pointer, ncomp not 1 or 4,
+ * a precision other than HS_FP64 / HS_MIXED_FP32, floor_rel < 0; HS_ERR_HIP:
+ * a launch or the array's address lookup failed. */
+hs_status hs_indicator_full_noalloc(void* hip_stream, int32_t ncell, int32_t ncomp, const double* gamma,
+                                    const void* Phi /* see precision */, const double* psi, int32_t m,
+                                    double floor_rel, int32_t precision, double* eps, double* y_out);
 
 /* ------------------------------------------------------ basis_update */
 /* snaps: HOST array of nsnap DEVICE pointers to N-vectors, oldest first:

@@ -97,6 +97,7 @@ _SIGS = {
     "hs_samples_counts": [P, ctypes.POINTER(I32)],
     "hs_samples_export": [P, P, P, P, P],
     "hs_indicator_full": [P, P, P, P, I32, D, I32, P, P],
+    "hs_indicator_full_noalloc": [P, I32, I32, P, P, P, I32, D, I32, P, P],
     "basis_update": [P, ctypes.POINTER(P), I32, I32, I32, D, I32, P, P, P, ctypes.POINTER(I32)],
     "basis_update_async": [P, ctypes.POINTER(P), I32, I32, I32, D, I32, P, P, P],
     "basis_update_finish": [P, ctypes.POINTER(I32)],
@@ -139,6 +140,21 @@ def lib():
 
 def exported_symbols():
     return list(_SIGS)
+
+
+def indicator_full_noalloc(gamma, Phi, psi, m, ncell, ncomp, eps, y=None, floor_rel=1e-14, stream=None):
+    """hs_indicator_full_noalloc: the indicator of a full snapshot with no
+    context and no allocation (the library's own device scratch array), on
+    ``stream`` (default: torch's current stream).  ``eps`` (ncell doubles)
+    and ``y`` (m doubles, optional) are caller-owned outputs."""
+    import torch
+    prec = basis_precision(Phi)
+    if stream is None:
+        stream = torch.cuda.current_stream(gamma.device).cuda_stream
+    st = lib().hs_indicator_full_noalloc(ctypes.c_void_p(stream), ncell, ncomp, _ptr(gamma), _ptr(Phi), _ptr(psi),
+                                         m, floor_rel, prec, _ptr(eps), _ptr(y))
+    if st != 0:
+        raise HsError(st, f"hs_indicator_full_noalloc: {lib().hs_status_string(st).decode()}")
 
 
 def _ptr(t):

@@ -22,6 +22,7 @@ constexpr double kFitEigFloor = 64 * 2.220446049250313e-16;
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 
 namespace hs {
 
@@ -306,6 +307,16 @@ __global__ void ring_update_kernel(const TP* __restrict__ Phi, long long n, int 
   u[dof] = psi[dof] + s;
 }
 
+// rho_r = psi_r + sum_j Phi_rj y_j (the one expression every kernel that
+// reconstructs uses, so that they agree to the bit).
+template <typename TP>
+__device__ inline double recon_value(const TP* __restrict__ Phi, long long n, int m, const double* __restrict__ psi,
+                                     const double* yl, long long r) {
+  double s = 0.0;
+  for (int j = 0; j < m; ++j) s += (double)Phi[(size_t)j * n + r] * yl[j];
+  return psi[r] + s;
+}
+
 // rho = psi + Phi y everywhere; gamma = u on hat-S cells, rho elsewhere.
 // With mask == nullptr only rho is written.
 template <typename TP>
@@ -318,9 +329,7 @@ __global__ void recon_kernel(const TP* __restrict__ Phi, long long n, int m, int
   __syncthreads();
   const long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (r >= n) return;
-  double s = 0.0;
-  for (int j = 0; j < m; ++j) s += (double)Phi[(size_t)j * n + r] * yl[j];
-  const double rr = psi[r] + s;
+  const double rr = recon_value(Phi, n, m, psi, yl, r);
   rho[r] = rr;
   if (mask) gamma[r] = mask[r % ncell] ? u[r] : rr;
 }
@@ -333,13 +342,9 @@ __global__ void eye_kernel(double* __restrict__ A, int m) {
 // max_abs_partials (hdm.hip): per-block maxima of |x| in slot kStatQMax.
 hs_status max_abs_partials(hs_ctx* ctx, const double* x, long long n, int* nb);
 
-// eps_cell = sum_c (gamma - rho)^2, flushed to 0 below fl^2 with
-// fl = floor_rel * max(1, max |gamma|).  Every workgroup reduces max |gamma|
-// from the nbq partials of max_abs_partials (a maximum is exact in any order).
-__global__ void indicator_kernel(int ncell, int nc, const double* __restrict__ gamma,
-                                 const double* __restrict__ rho, double floor_rel,
-                                 const double* __restrict__ qpart, int nbq, double* __restrict__ eps) {
-#pragma clang fp contract(off)
+// max |gamma| of every workgroup alike, from the nbq partials of
+// max_abs_partials (a maximum is exact in any order).
+__device__ inline double block_qmax(const double* __restrict__ qpart, int nbq) {
   __shared__ double lds[kBlock / kWave];
   __shared__ double qmax;
   double qm = 0.0;
@@ -347,16 +352,54 @@ __global__ void indicator_kernel(int ncell, int nc, const double* __restrict__ g
   qm = block_max(qm, lds);
   if (threadIdx.x == 0) qmax = qm;
   __syncthreads();
+  return qmax;
+}
+
+// The cell's error sum_c d_c^2 (d_c = gamma - rho of component c), flushed to
+// 0 below floor2.
+__device__ inline double cell_error(double e, double floor2) { return e < floor2 ? 0.0 : e; }
+__device__ inline double add_square(double e, double d, int a) {
+#pragma clang fp contract(off)
+  return a == 0 ? d * d : e + d * d;
+}
+
+// eps_cell = sum_c (gamma - rho)^2, flushed to 0 below fl^2 with
+// fl = floor_rel * max(1, max |gamma|).
+__global__ void indicator_kernel(int ncell, int nc, const double* __restrict__ gamma,
+                                 const double* __restrict__ rho, double floor_rel,
+                                 const double* __restrict__ qpart, int nbq, double* __restrict__ eps) {
+#pragma clang fp contract(off)
+  const double qmax = block_qmax(qpart, nbq);
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncell) return;
   const double fl = floor_rel * fmax(1.0, qmax);
   const double floor2 = fl * fl;
   double e = 0.0;
+  for (int a = 0; a < nc; ++a) e = add_square(e, gamma[(size_t)a * ncell + c] - rho[(size_t)a * ncell + c], a);
+  eps[c] = cell_error(e, floor2);
+}
+
+// The same indicator with rho = psi + Phi y formed in place (no rho buffer).
+template <typename TP>
+__global__ void indicator_direct_kernel(int ncell, int nc, const double* __restrict__ gamma, const TP* __restrict__ Phi,
+                                        const double* __restrict__ psi, const double* __restrict__ y, int m,
+                                        double floor_rel, const double* __restrict__ qpart, int nbq,
+                                        double* __restrict__ eps) {
+#pragma clang fp contract(off)
+  __shared__ double yl[kMaxBasis];
+  if (threadIdx.x < m) yl[threadIdx.x] = y[threadIdx.x];
+  const double qmax = block_qmax(qpart, nbq);   // its barrier also publishes yl
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const long long n = (long long)nc * ncell;
+  const double fl = floor_rel * fmax(1.0, qmax);
+  const double floor2 = fl * fl;
+  double e = 0.0;
   for (int a = 0; a < nc; ++a) {
-    const double d = gamma[(size_t)a * ncell + c] - rho[(size_t)a * ncell + c];
-    e = a == 0 ? d * d : e + d * d;
+    const long long r = (long long)a * ncell + c;
+    e = add_square(e, gamma[r] - recon_value(Phi, n, m, psi, yl, r), a);
   }
-  eps[c] = e < floor2 ? 0.0 : e;
+  eps[c] = cell_error(e, floor2);
 }
 
 // ----------------------------------------------------------------- filter
@@ -1342,3 +1385,110 @@ hs_status hs_htape_destroy(hs_htape* t) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------- indicator without allocation
+// hs_indicator_full_noalloc keeps its working memory in one file-scope device
+// array (each GPU the library runs on holds its own copy until the process
+// ends).  Host code never passes the array's name to a kernel: the device
+// address is looked up once per device with hipGetSymbolAddress and kept.
+// Layout (doubles): projection partials (kProjBlocks x 64), the identity
+// (64 x 64), y and the finish kernel's bookkeeping (4 x 64), the max-|gamma|
+// partials (slot kStatQMax of a kStatSlots x kPartCap statistics block).
+namespace hs {
+constexpr int kProjBlocks = 512;
+constexpr size_t kNoAllocPart = 0;
+constexpr size_t kNoAllocEye = kNoAllocPart + (size_t)kProjBlocks * kMaxBasis;
+constexpr size_t kNoAllocY = kNoAllocEye + (size_t)kMaxBasis * kMaxBasis;
+constexpr size_t kNoAllocStats = kNoAllocY + 4 * kMaxBasis;
+constexpr size_t kNoAllocDoubles = kNoAllocStats + (size_t)(kStatQMax + 1) * kPartCap;
+constexpr int kNoAllocMaxDevices = 64;
+}  // namespace hs
+
+static __device__ __align__(256) double scratch[hs::kNoAllocDoubles];
+
+namespace hs {
+static std::mutex g_noalloc_mu;
+static double* g_noalloc_ptr[kNoAllocMaxDevices] = {nullptr};
+
+// The device address of this device's scratch array (looked up on the first
+// call on each device, with that device current).
+static hs_status noalloc_scratch(double** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return HS_ERR_HIP;
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return HS_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return HS_ERR_HIP;
+    g_noalloc_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_noalloc_ptr[dev];
+  return HS_OK;
+}
+
+#define HS_NA_LAUNCH(stream, kernel, grid, block, ...)                               \
+  do {                                                                               \
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, stream, __VA_ARGS__);     \
+    if (hipGetLastError() != hipSuccess) return HS_ERR_HIP;                          \
+  } while (0)
+
+// Per-block maxima of |x| into slot kStatQMax of a statistics block (a
+// maximum is exact in any order, so these equal max_abs_partials' values).
+__global__ void noalloc_max_abs_kernel(const double* __restrict__ x, long long n, double* __restrict__ part) {
+  __shared__ double lds[kBlock / kWave];
+  double mx = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    mx = fmax(mx, fabs(x[i]));
+  mx = block_max(mx, lds);
+  if (threadIdx.x == 0) stat_part(part, kStatQMax, mx);
+}
+
+template <typename TP>
+static hs_status indicator_noalloc_t(hipStream_t st, double* sc, int ncell, int nc, const double* gamma,
+                                     const TP* Phi, const double* psi, int m, double floor_rel, double* eps,
+                                     double* y_out) {
+  const long long n = (long long)nc * ncell;
+  const int nb = (int)std::max<long long>(1, std::min<long long>((n + kBlock - 1) / kBlock, kProjBlocks));
+  double* part = sc + kNoAllocPart;
+  double* eye = sc + kNoAllocEye;
+  double* y = y_out ? y_out : sc + kNoAllocY;
+  double* misc = sc + kNoAllocY + kMaxBasis;
+  double* stats = sc + kNoAllocStats;
+  // y = Phi^T (gamma - psi): the projection partials of every block, then
+  // their fixed-order sum applied to the identity (the same kernels and
+  // order as hs_indicator_full)
+  switch (pad16(m)) {
+    case 16: HS_NA_LAUNCH(st, (project_kernel<16, TP>), nb, kBlock, Phi, n, m, nc, ncell, (const int*)nullptr, 0, gamma, psi, (const double*)nullptr, 0, part); break;
+    case 32: HS_NA_LAUNCH(st, (project_kernel<32, TP>), nb, kBlock, Phi, n, m, nc, ncell, (const int*)nullptr, 0, gamma, psi, (const double*)nullptr, 0, part); break;
+    case 48: HS_NA_LAUNCH(st, (project_kernel<48, TP>), nb, kBlock, Phi, n, m, nc, ncell, (const int*)nullptr, 0, gamma, psi, (const double*)nullptr, 0, part); break;
+    default: HS_NA_LAUNCH(st, (project_kernel<64, TP>), nb, kBlock, Phi, n, m, nc, ncell, (const int*)nullptr, 0, gamma, psi, (const double*)nullptr, 0, part); break;
+  }
+  HS_NA_LAUNCH(st, eye_kernel, blocks_for(m * m), kBlock, eye, m);
+  HS_NA_LAUNCH(st, project_finish_kernel, 1, 256, (const double*)part, nb, pad16(m), m, (const double*)eye, 0, y,
+               misc + kMaxBasis, misc + 2 * kMaxBasis, misc, 1, (unsigned long long*)nullptr);
+  const int nbq = blocks_for(n, kBlock, 1024);
+  HS_NA_LAUNCH(st, noalloc_max_abs_kernel, nbq, kBlock, gamma, n, stats);
+  HS_NA_LAUNCH(st, (indicator_direct_kernel<TP>), blocks_for(ncell), kBlock, ncell, nc, gamma, Phi, psi,
+               (const double*)y, m, floor_rel, (const double*)stats, nbq, eps);
+  return HS_OK;
+}
+#undef HS_NA_LAUNCH
+}  // namespace hs
+
+extern "C" hs_status hs_indicator_full_noalloc(void* hip_stream, int32_t ncell, int32_t ncomp, const double* gamma,
+                                               const void* Phi, const double* psi, int32_t m, double floor_rel,
+                                               int32_t precision, double* eps, double* y_out) {
+  using namespace hs;
+  if (!gamma || !Phi || !psi || !eps) return HS_ERR_INVALID_ARG;
+  if (ncomp != 1 && ncomp != 4) return HS_ERR_INVALID_ARG;
+  if (precision != HS_FP64 && precision != HS_MIXED_FP32) return HS_ERR_INVALID_ARG;
+  if (!(floor_rel >= 0.0)) return HS_ERR_INVALID_ARG;
+  // the scratch array is sized for m <= 64 and at most 2^31 - 1 entries
+  if (m < 1 || m > kMaxBasis || ncell < 1 || (long long)ncomp * ncell >= (1LL << 31)) return HS_ERR_SHAPE;
+  double* sc = nullptr;
+  HS_TRY(noalloc_scratch(&sc));
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (precision == HS_MIXED_FP32)
+    return indicator_noalloc_t(st, sc, ncell, ncomp, gamma, (const float*)Phi, psi, m, floor_rel, eps, y_out);
+  return indicator_noalloc_t(st, sc, ncell, ncomp, gamma, (const double*)Phi, psi, m, floor_rel, eps, y_out);
+}

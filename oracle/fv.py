@@ -215,10 +215,17 @@ def _face_sources(prob: Problem, axis):
     return st(srcL), st(srcR), st(ownL), st(ownR)
 
 
-def jacobian(prob: Problem, q, q_prev=None) -> sp.csr_matrix:
-    """Exact dR/dq (q_prev enters linearly with a constant, so it is unused)."""
+def jacobian(prob: Problem, q, q_prev=None, cells=None) -> sp.csr_matrix:
+    """Exact dR/dq (q_prev enters linearly with a constant, so it is unused).
+    With ``cells`` only the rows of those cells' residuals are assembled (the
+    others are left empty): the same entries, fewer of them."""
     c, nc = prob.ncomp, prob.ncell
-    rows, cols, vals = [np.arange(c * nc)], [np.arange(c * nc)], [np.ones(c * nc)]
+    keep = None
+    if cells is not None:
+        keep = np.zeros(nc, dtype=bool)
+        keep[np.asarray(cells, dtype=np.int64)] = True
+    diag = np.arange(c * nc) if keep is None else dofs_of_cells(prob, np.flatnonzero(keep))
+    rows, cols, vals = [diag], [diag], [np.ones(diag.size)]
     for ax in axes(prob):
         lx = lam(prob, ax)
         dL, dR = face_flux_derivatives(prob, q, ax)
@@ -226,6 +233,8 @@ def jacobian(prob: Problem, q, q_prev=None) -> sp.csr_matrix:
         for own, sign in ((ownL, 1.0), (ownR, -1.0)):
             for src, d in ((srcL, dL), (srcR, dR)):
                 ok = (own >= 0) & (src >= 0)
+                if keep is not None:
+                    ok &= keep[np.maximum(own, 0)]
                 o = own[ok]
                 s = src[ok]
                 for a in range(c):
@@ -279,6 +288,6 @@ def partial_hdm_solve(prob: Problem, u, q_prev, hat_cells, tol=None, maxit=NEWTO
             return u, it
         if it == maxit:
             break
-        J = jacobian(prob, u)[d][:, d]
+        J = jacobian(prob, u, cells=hat_cells)[d][:, d]
         u[d] = u[d] - spla.spsolve(J.tocsc(), R)
     raise NotConverged(f"partial HDM Newton: ||R||_inf = {np.max(np.abs(R)):.3e} > {tol:.3e}")

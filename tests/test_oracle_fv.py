@@ -351,3 +351,16 @@ def test_newton_converges_quadratically(name, nx, seed):
     for i in k:
         assert norms[i] < 50 * norms[i - 1] ** 2, norms
     assert norms[-1] < 1e-13
+
+
+@pytest.mark.parametrize("name,nx,ny", [("burgers1d_1k", 300, 1), ("burgers2d_1024", 40, 36), ("euler2d_512", 24, 20)])
+def test_jacobian_restricted_rows_equal_full_rows(name, nx, ny):
+    """The restricted assembly used by the partial Newton solve gives the
+    full Jacobian's entries on the chosen rows, bit for bit."""
+    prob, q0 = W.make(W.WORKLOADS[name].resized(nx, ny), 0)
+    q1 = fv.hdm_step(prob, q0)[0]
+    cells = np.sort(np.random.default_rng(1).choice(prob.ncell, prob.ncell // 5, replace=False))
+    d = fv.dofs_of_cells(prob, cells)
+    A = fv.jacobian(prob, q1)[d]
+    B = fv.jacobian(prob, q1, cells=cells)[d]
+    assert np.array_equal(A.toarray(), B.toarray())

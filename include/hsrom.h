@@ -326,6 +326,11 @@ hs_status rom_hybrid_step_adjoint(hs_ctx* ctx, const double* Phi, int32_t m, con
  * Jacobi rotations in the same order and give the same result bit for bit (a
  * switch for measurement and testing). */
 #define HS_OPT_SMALL_PINV 2
+/* HS_OPT_FIT_CHOLESKY: for m > 8 the fit's pseudo-inverse is the inverse
+ * from a Cholesky factorisation of the gathered Gram whenever a bound on its
+ * condition (||G||_F ||G^-1||_F < 1e6) shows that no direction is cut
+ * (1, default); 0: always the Jacobi eigendecomposition. */
+#define HS_OPT_FIT_CHOLESKY 3
 /* Returns HS_ERR_INVALID_ARG for an unknown option or a value out of range. */
 hs_status hs_set_option(hs_ctx* ctx, int32_t option, int64_t value);
 

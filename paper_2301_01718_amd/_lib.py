@@ -261,6 +261,12 @@ class Context:
         results are the same bit for bit."""
         self._check(lib().hs_set_option(self.h, 2, 1 if on else 0))
 
+    def set_fit_cholesky(self, on):
+        """The fit's pseudo-inverse for m > 8: True = the Cholesky inverse when
+        a condition bound shows nothing is cut (default); False = always the
+        Jacobi eigendecomposition."""
+        self._check(lib().hs_set_option(self.h, 3, 1 if on else 0))
+
     # ---------------------------------------------------------- measurement
     def prof_enable(self, kernel_class):
         cls = PROF_CLASSES[kernel_class] if isinstance(kernel_class, str) else kernel_class

@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(kBlock) adj_coef_kernel(Grid g, const double* 
         }
     }
 #pragma unroll
-    for (int a = 0; a < NC; ++a) rho = fmax(rho, rowsum[a]);
+    for (int a = 0; a < NC; ++a) rho = nan_max(rho, rowsum[a]);
     if (!isfinite(rho)) rho = INFINITY;
   }
   rho = block_max(rho, lds);

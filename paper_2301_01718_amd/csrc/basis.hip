@@ -314,6 +314,28 @@ __device__ void block_pivoted_cholesky(const double* A, int lda, int w, double t
   }
 }
 
+// 1/sqrt(x) for x > 1e-290 from the hardware estimate and two Newton steps
+// (the library form also rescales denormals and handles infinities); the
+// rotations below need c^2 (1 + t^2) = 1 to rounding, not a correctly
+// rounded square root.
+__device__ inline double rsqrt_newton(double x) {
+#pragma clang fp contract(fast)
+  double r = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  r = r * (1.5 - hx * r * r);
+  r = r * (1.5 - hx * r * r);
+  return r;
+}
+
+// 1/x from the hardware estimate and two Newton steps (x > 1e-290).
+__device__ inline double rcp_newton(double x) {
+#pragma clang fp contract(fast)
+  double r = __builtin_amdgcn_rcp(x);
+  r = r * (2.0 - x * r);
+  r = r * (2.0 - x * r);
+  return r;
+}
+
 // One-sided Jacobi on the columns of B (w rows x r columns, stride lda): rotate
 // column pairs until they are orthogonal, so that B W = U Sigma with U the
 // left singular vectors of B and Sigma its singular values (the column norms
@@ -344,13 +366,14 @@ __device__ void block_jacobi_columns(double* B, int lda, int w, int r) {
         }
         if (p > q) { const int x = p; p = q; q = x; }
         if (q < r) {
-          // rows gl, gl + 8, ... (w <= 64: at most 8 per lane, all loads in flight together)
+          // rows gl, gl + 8, ... (64 rows: rows past w are zero, so the
+          // loads and stores need no branch and are all in flight together)
           double xs[8], ys[8];
 #pragma unroll
           for (int i = 0; i < 8; ++i) {
             const int k = gl + 8 * i;
-            xs[i] = k < w ? B[k * lda + p] : 0.0;
-            ys[i] = k < w ? B[k * lda + q] : 0.0;
+            xs[i] = B[k * lda + p];
+            ys[i] = B[k * lda + q];
           }
           double aa = 0.0, bb = 0.0, gg = 0.0;
 #pragma unroll
@@ -368,15 +391,22 @@ __device__ void block_jacobi_columns(double* B, int lda, int w, int r) {
           const double ab = aa * bb;
           if (aa > 0.0 && bb > 0.0 && gg * gg > tol_rot * tol_rot * ab) {
             const double dd = bb - aa, ee = 2.0 * gg;
-            const double tt = (dd >= 0.0 ? ee : -ee) / (fabs(dd) + sqrt(dd * dd + ee * ee));
-            const double c = rsqrt(1.0 + tt * tt), sn = c * tt;
+            const double x2 = dd * dd + ee * ee;
+            double tt, c;
+            if (x2 > 1e-290 && x2 < 1e290) {
+              const double h = x2 * rsqrt_newton(x2);
+              tt = (dd >= 0.0 ? ee : -ee) * rcp_newton(fabs(dd) + h);
+              c = rsqrt_newton(1.0 + tt * tt);
+            } else {
+              tt = (dd >= 0.0 ? ee : -ee) / (fabs(dd) + sqrt(x2));
+              c = rsqrt(1.0 + tt * tt);
+            }
+            const double sn = c * tt;
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
               const int k = gl + 8 * i;
-              if (k < w) {
-                B[k * lda + p] = c * xs[i] - sn * ys[i];
-                B[k * lda + q] = sn * xs[i] + c * ys[i];
-              }
+              B[k * lda + p] = c * xs[i] - sn * ys[i];
+              B[k * lda + q] = sn * xs[i] + c * ys[i];
             }
             if (gl == 0 && gg * gg > tol_conv * tol_conv * ab) rotated = 1;
           }
@@ -475,13 +505,19 @@ __global__ void __launch_bounds__(256) basis_svd_kernel(const double* __restrict
   constexpr int lda = kMaxBasis + 1;
   __shared__ double A[kMaxBasis * lda];   // G2, then R^T, rotated in place
   __shared__ double L[kMaxBasis * lda];   // pivoted Cholesky factor of G2, then V
+  __shared__ double Cs[kMaxBasis * kMaxBasis];   // C1 (its rows are read in pivot order)
   __shared__ double d[kMaxBasis], lam[kMaxBasis];
   __shared__ int perm[kMaxBasis], order[kMaxBasis];
   __shared__ int rank, piv, meff;
   __shared__ double tol;
   const int t = threadIdx.x, nt = blockDim.x;
+  for (int e = t; e < kMaxBasis * lda; e += nt) {
+    A[e] = 0.0;            // rows past w stay zero (the Jacobi reads all 64 rows)
+    L[e] = 0.0;
+  }
+  for (int e = t; e < w * kMaxBasis; e += nt) Cs[e] = C1[e];
+  __syncthreads();
   for (int e = t; e < w * w; e += nt) A[(e / w) * lda + e % w] = G2[e];
-  for (int e = t; e < kMaxBasis * lda; e += nt) L[e] = 0.0;
   __syncthreads();
   if (t == 0) {
     double tr = 0.0;
@@ -495,7 +531,7 @@ __global__ void __launch_bounds__(256) basis_svd_kernel(const double* __restrict
   for (int e = t; e < w * r; e += nt) {
     const int j = e / r, i = e % r;
     double s = 0.0;
-    for (int k = i; k < w; ++k) s += L[k * lda + i] * C1[perm[k] * kMaxBasis + j];
+    for (int k = i; k < w; ++k) s += L[k * lda + i] * Cs[perm[k] * kMaxBasis + j];
     A[j * lda + i] = s;
   }
   __syncthreads();

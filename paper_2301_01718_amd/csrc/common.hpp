@@ -89,6 +89,7 @@ struct hs_ctx {
   int tiled = 1;
   // fit pseudo-inverse for m <= 8: 1 = one wave in registers, 0 = LDS routine
   int small_pinv = 1;
+  int fit_chol = 1;           // HS_OPT_FIT_CHOLESKY
   double* red = nullptr;      // reduction partials (kRedBlocks * 64 * 64 doubles)
   double* small = nullptr;    // small dense matrices and vectors (16 * 64 * 64 doubles)
   unsigned long long* stats = nullptr;   // kStatSlots
@@ -214,9 +215,13 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// max(a, b), NaN if either is NaN (fmax returns the other operand, so a
+// maximum taken with it would hide a NaN from the finiteness checks).
+__device__ inline double nan_max(double a, double b) { return a != a ? a : (b != b ? b : fmax(a, b)); }
+
 __device__ inline double wave_max(double v) {
 #pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+  for (int o = kWave / 2; o > 0; o >>= 1) v = nan_max(v, __shfl_xor(v, o, kWave));
   return v;
 }
 

@@ -32,7 +32,7 @@ __global__ void max_abs_kernel(const double* __restrict__ x, long long n, double
   double m = 0.0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
-    m = fmax(m, fabs(x[i]));
+    m = nan_max(m, fabs(x[i]));
   m = block_max(m, lds);
   if (threadIdx.x == 0) stat_part(part, kStatQMax, m);
 }
@@ -68,7 +68,7 @@ __global__ void finish_stats_kernel(const double* __restrict__ part, int nb, uns
     for (int slot = 0; slot < kStatSlots; ++slot) {
       if (!((mask >> slot) & 1u)) continue;
       const double x = part[slot * kPartCap + b];
-      v[slot] = ((max_mask >> slot) & 1u) ? fmax(v[slot], x) : v[slot] + x;
+      v[slot] = ((max_mask >> slot) & 1u) ? nan_max(v[slot], x) : v[slot] + x;
     }
   }
 #pragma unroll
@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(kBlock) resjac_kernel(Grid g, const double* __
     double rowsum[NC];
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
-      rmax = fmax(rmax, fabs(R[a]));
+      rmax = nan_max(rmax, fabs(R[a]));
       bad |= !isfinite(R[a]);
       double b = 0.0;
 #pragma unroll
@@ -320,7 +320,7 @@ __global__ void __launch_bounds__(kBlock) resjac_kernel(Grid g, const double* __
         }
     }
 #pragma unroll
-    for (int a = 0; a < NC; ++a) rho = fmax(rho, rowsum[a]);
+    for (int a = 0; a < NC; ++a) rho = nan_max(rho, rowsum[a]);
     if (!isfinite(rho)) bad = true;
   }
   rmax = block_max(bad ? INFINITY : rmax, lds);
@@ -702,6 +702,10 @@ hs_status hs_set_option(hs_ctx* ctx, int32_t option, int64_t value) {
   if (!ctx) return HS_ERR_INVALID_ARG;
   if (option == HS_OPT_TILED_SWEEPS && value >= 0 && value <= 2) {
     ctx->tiled = (int)value;
+    return HS_OK;
+  }
+  if (option == HS_OPT_FIT_CHOLESKY && (value == 0 || value == 1)) {
+    ctx->fit_chol = (int)value;
     return HS_OK;
   }
   if (option == HS_OPT_SMALL_PINV && (value == 0 || value == 1)) {

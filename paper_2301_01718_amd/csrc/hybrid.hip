@@ -62,10 +62,88 @@ struct GatherLoader {
   }
 };
 
-// Truncated pseudo-inverse of the m x m Gram: G+ = sum_{kept} v v^T / lambda.
+// The Cholesky route of the pseudo-inverse is taken while its bound on
+// lambda_max / lambda_min of the Gram stays below this (kappa(Phi_S) < 1e3):
+// the inverse is then good to kappa^2 eps = 1e-10 and the fit's refinement
+// step removes that; more ill-conditioned fits take the eigen route.
+constexpr double kCholMaxRatio = 1e6;
+
+// For a well-conditioned Gram the truncated pseudo-inverse is the inverse:
+// G = L L^T (Cholesky), G^-1 = L^-T L^-1.  Taken when the Cholesky succeeds
+// and ||G||_F ||G^-1||_F (an upper bound on lambda_max / lambda_min) stays
+// below 1 / cut, so that no eigenvalue can lie under the cut.  Returns false
+// (nothing written) otherwise.  Every thread of the block calls it.
+__device__ bool pinv_by_cholesky(const double* A, double* L, double* Li, int lda, int m, double cut,
+                                 double* __restrict__ Gp, double* __restrict__ misc,
+                                 unsigned long long* __restrict__ stats) {
+#pragma clang fp contract(off)
+  __shared__ int bad;
+  __shared__ double lds[256 / kWave];
+  const int t = threadIdx.x, nt = blockDim.x;
+  if (t == 0) bad = 0;
+  __syncthreads();
+  for (int k = 0; k < m; ++k) {
+    // every thread forms l_kk from the same sums (same bits), then its entry
+    double dk = A[k * lda + k];
+    for (int j = 0; j < k; ++j) dk -= L[k * lda + j] * L[k * lda + j];
+    const double lkk = sqrt(dk);
+    for (int i = k + t; i < m; i += nt) {
+      if (i == k) {
+        L[k * lda + k] = lkk;
+        if (!(dk > 0.0)) bad = 1;
+      } else {
+        double sacc = A[i * lda + k];
+        for (int j = 0; j < k; ++j) sacc -= L[i * lda + j] * L[k * lda + j];
+        L[i * lda + k] = sacc / lkk;
+      }
+    }
+    __syncthreads();
+    if (bad) return false;
+  }
+  // L^-1, one column per thread (forward substitution)
+  if (t < m) {
+    const int c = t;
+    Li[c * lda + c] = 1.0 / L[c * lda + c];
+    for (int i = c + 1; i < m; ++i) {
+      double sacc = 0.0;
+      for (int k = c; k < i; ++k) sacc += L[i * lda + k] * Li[k * lda + c];
+      Li[i * lda + c] = -sacc / L[i * lda + i];
+    }
+  }
+  __syncthreads();
+  // G^-1 = L^-T L^-1 (into L's upper part is not needed: straight to Gp) and
+  // the Frobenius norms of G and G^-1
+  double fa = 0.0, fi = 0.0;
+  for (int e = t; e < m * m; e += nt) {
+    const int r = e / m, c = e % m;
+    double sacc = 0.0;
+    for (int k = r > c ? r : c; k < m; ++k) sacc += Li[k * lda + r] * Li[k * lda + c];
+    Gp[e] = sacc;
+    fi += sacc * sacc;
+    fa += A[r * lda + c] * A[r * lda + c];
+  }
+  fa = block_sum(fa, lds);
+  fi = block_sum(fi, lds);
+  __shared__ int ok;
+  if (t == 0) {
+    const double kb = sqrt(fa) * sqrt(fi);     // >= lambda_max / lambda_min
+    ok = kb * cut < 1.0 && kb < kCholMaxRatio;
+    if (ok) {
+      misc[1] = m;
+      misc[2] = sqrt(kb);                      // >= kappa(Phi_S)
+      stats[kStatFitRank] = dbits((double)m);
+      stats[kStatFitCond] = dbits(misc[2]);
+    }
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+// Truncated pseudo-inverse of the m x m Gram: G+ = sum_{kept} v v^T / lambda
+// (or the inverse, when a Cholesky shows that nothing is cut).
 __global__ void __launch_bounds__(256) pinv_kernel(const double* __restrict__ G, int m, double rcond,
                                                   double* __restrict__ Gp, double* __restrict__ misc,
-                                                  unsigned long long* __restrict__ stats) {
+                                                  unsigned long long* __restrict__ stats, int use_chol) {
 #pragma clang fp contract(off)
   __shared__ double A[kMaxBasis * (kMaxBasis + 1)], V[kMaxBasis * (kMaxBasis + 1)];
   __shared__ double lam[kMaxBasis];
@@ -75,6 +153,13 @@ __global__ void __launch_bounds__(256) pinv_kernel(const double* __restrict__ G,
   const int t = threadIdx.x;
   for (int e = t; e < m * m; e += blockDim.x) A[(e / m) * lda + e % m] = G[e];
   __syncthreads();
+  {
+    __shared__ double Li[kMaxBasis * (kMaxBasis + 1)];
+    // (m <= 8 keeps the eigen route: pinv_small_kernel computes the same
+    // pseudo-inverse in registers and is checked against this one)
+    if (use_chol && m > 8 && pinv_by_cholesky(A, V, Li, lda, m, fmax(rcond * rcond, kFitEigFloor), Gp, misc, stats))
+      return;
+  }
   jacobi_eig_wave(A, V, lda, m, lam, order, 40);
   if (t == 0) {
     int k = 0;
@@ -348,7 +433,7 @@ __device__ inline double block_qmax(const double* __restrict__ qpart, int nbq) {
   __shared__ double lds[kBlock / kWave];
   __shared__ double qmax;
   double qm = 0.0;
-  for (int b = threadIdx.x; b < nbq; b += blockDim.x) qm = fmax(qm, qpart[kStatQMax * kPartCap + b]);
+  for (int b = threadIdx.x; b < nbq; b += blockDim.x) qm = nan_max(qm, qpart[kStatQMax * kPartCap + b]);
   qm = block_max(qm, lds);
   if (threadIdx.x == 0) qmax = qm;
   __syncthreads();
@@ -1105,7 +1190,7 @@ static hs_status fit_factor(hs_ctx* ctx, const void* Phi, int prec, int m, const
               ctx->small + kSmMisc, ctx->stats);
   else
     HS_LAUNCH(ctx, pinv_kernel, 1, 256, ctx->small + kSmG, m, rcond, ctx->small + kSmGp, ctx->small + kSmMisc,
-              ctx->stats);
+              ctx->stats, ctx->fit_chol);
   return HS_OK;
 }
 
@@ -1438,7 +1523,7 @@ __global__ void noalloc_max_abs_kernel(const double* __restrict__ x, long long n
   __shared__ double lds[kBlock / kWave];
   double mx = 0.0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    mx = fmax(mx, fabs(x[i]));
+    mx = nan_max(mx, fabs(x[i]));
   mx = block_max(mx, lds);
   if (threadIdx.x == 0) stat_part(part, kStatQMax, mx);
 }

@@ -75,8 +75,8 @@ __global__ void __launch_bounds__(NT) tile_sweep_kernel(
     // every block reduces the same partials (max: exact in any order)
     double rm = 0.0, rh = 0.0;
     for (int b = threadIdx.x; b < ctl.nb; b += NT) {
-      rm = fmax(rm, ctl.part[kStatResMax * kPartCap + b]);
-      rh = fmax(rh, ctl.part[kStatRho * kPartCap + b]);
+      rm = nan_max(rm, ctl.part[kStatResMax * kPartCap + b]);
+      rh = nan_max(rh, ctl.part[kStatRho * kPartCap + b]);
     }
     rm = block_max(rm, lds);
     rh = block_max(rh, lds);
@@ -264,8 +264,8 @@ __global__ void __launch_bounds__(NT) tile_sweep_kernel(
       if (q) q[a * g.ncell + cells[c]] += x;
       else xout[a * cap + p] = x;
       if (record) {
-        diff = fmax(diff, fabs(x - xs[cur ^ 1][a][r]));
-        dn = fmax(dn, fabs(x));
+        diff = nan_max(diff, fabs(x - xs[cur ^ 1][a][r]));
+        dn = nan_max(dn, fabs(x));
       }
     }
   }
@@ -323,8 +323,8 @@ __global__ void list_sweep_kernel(Grid g, const int* __restrict__ hat, const int
       for (int a = 0; a < NC; ++a) {
         dnew[a * cap + p] = acc[a];
         if (RECORD) {
-          diff = fmax(diff, fabs(acc[a] - dold[a * cap + p]));
-          dn = fmax(dn, fabs(acc[a]));
+          diff = nan_max(diff, fabs(acc[a] - dold[a * cap + p]));
+          dn = nan_max(dn, fabs(acc[a]));
         }
       }
     }

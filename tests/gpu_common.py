@@ -72,6 +72,16 @@ def indicator_close(eg, eo, gamma, floor_rel=1e-14, tol=1e-13, cell_tol=None):
     return bool(ok), float(np.max(diff) / scale)
 
 
+def fit_tols(fit_cond, tol=1e-12, cell_tol=1e-10):
+    """The indicator's tolerances after a hybrid step whose gathered basis
+    has condition number (bound) fit_cond: sqrt(eps) on the sampled cells is
+    the fit's misfit |v - psi - Phi y|, and two correct least-squares
+    solutions differ by about kappa^2 eps relative (their sensitivity to
+    rounding), so the bars grow with 10 kappa^2 eps once that exceeds them."""
+    k2e = 10.0 * float(fit_cond) ** 2 * 2.2e-16
+    return max(tol, k2e), max(cell_tol, 100.0 * k2e)
+
+
 def projector_tol(sigma, me, c=100.0):
     """Bound on ||P_gpu X - P_oracle X|| / ||X|| for the orthogonal projectors
     onto two rank-me POD subspaces of the same window.  Both SVDs are exact for
@@ -83,3 +93,48 @@ def projector_tol(sigma, me, c=100.0):
     nxt = s[me] if me < s.size else 0.0
     gap = s[me - 1] - nxt
     return max(1e-12, c * 2.2e-16 * s[me - 1] / gap)
+
+
+def validate_filter(prob, gamma, q_prev, passes_gpu, hp=None, tie_rel=1e-12):
+    """Check a GPU filter run pass by pass against the oracle's gate on the
+    same input.  ``gamma`` is the oracle's state before the filter (equal to
+    the GPU's to rounding), ``passes_gpu`` the GPU's applied passes [(n,
+    kept-cell mask)].  For every pass, on the state left by the previous
+    passes (with the GPU's masks): the GPU's mask must equal the strict gate
+    rf < r except at ties |rf - r| <= tie_rel max(1, |gamma|_inf) (where both
+    flags are correct), and the loop control (orders, stop on an empty set,
+    on a relative l1 decrease below eps_f, after j_max^f passes) must produce
+    exactly the GPU's sequence of passes.  Returns (state after the GPU's
+    passes, number of tied flags)."""
+    from oracle import fv, hybrid
+    hp = hp or hybrid.HybridParams()
+    c = prob.ncomp
+    g = gamma.copy()
+    scale = max(1.0, float(np.max(np.abs(gamma))))
+    k = 0
+    ties = 0
+    for n in hp.filter_orders:
+        r = fv.cell_residual_norm(prob, g, q_prev)
+        for it in range(1, hp.jfmax + 1):
+            gf = hybrid.shapiro(prob, g, n)
+            rf = fv.cell_residual_norm(prob, gf, q_prev)
+            want = rf < r
+            applied = k < len(passes_gpu) and passes_gpu[k][0] == n
+            mk = np.asarray(passes_gpu[k][1], dtype=bool) if applied else np.zeros_like(want)
+            flip = np.flatnonzero(mk != want)
+            if flip.size:
+                gap = np.abs(rf[flip] - r[flip])
+                assert np.all(gap <= tie_rel * scale), ("gate", n, it, flip[gap > tie_rel * scale], gap.max())
+                ties += int(flip.size)
+            if applied:
+                k += 1
+            if not mk.any():
+                break                       # an empty gate ends the order
+            g = np.where(np.tile(mk, c), gf, g)
+            r_new = fv.cell_residual_norm(prob, g, q_prev)
+            s_old, s_new = np.sum(r), np.sum(r_new)
+            r = r_new
+            if (s_old - s_new) / s_old < hp.eps_f:
+                break
+    assert k == len(passes_gpu), ("pass count", k, len(passes_gpu))
+    return g, ties

@@ -29,7 +29,7 @@ import pytest
 import workloads as W
 from oracle import fv, hybrid, pod, sampling
 
-from gpu_common import ctx_for, dev, host, need_gpu, print_case, projector_tol, rel, torch
+from gpu_common import ctx_for, dev, host, need_gpu, print_case, projector_tol, rel, torch, validate_filter
 
 pytestmark = pytest.mark.gpu
 
@@ -174,3 +174,74 @@ def test_bench_configuration_properties():
         drv.advance(on_step, on_update)
     print(f"  steps {k0}..{last}: {seen}", flush=True)
     assert seen["hybrid"] >= 16 and seen["full"] >= 1 and seen["update"] >= 16
+
+
+WL3 = W.WORKLOADS["euler2d_512"]
+
+
+def test_euler_full_size_parity():
+    """Config 3's size (2D Euler 512 x 512, m 40, w 60, 8 %): the basis of a
+    window of translates (sigma, m_eff, span), the sets from the oracle's
+    indicator (bit for bit), one hybrid step on the oracle's basis and sets
+    (1e-12, equal J) and a full step checked by the oracle's residual."""
+    need_gpu()
+    print_case("full size euler2d_512, independent inputs")
+    prob, q0 = W.make(WL3, 0)
+    w, m = WL3.w, WL3.m
+    g3 = q0.reshape(prob.ncomp, prob.ny, prob.nx)
+    snaps = [np.roll(np.roll(g3, k, axis=2), k // 2, axis=1).reshape(-1).copy() for k in range(w + 1)]
+    ctx = ctx_for(prob, m_max=m, w_max=w)
+    b = pod.pod(snaps, w, m)
+    me = b["m_eff"]
+    Pg = torch.zeros(m * prob.n, dtype=torch.float64, device="cuda")
+    psig, sg = ctx.empty(), torch.zeros(w, dtype=torch.float64, device="cuda")
+    me_g = ctx.basis_update([dev(s) for s in snaps], w, m, Pg, psig, sg)
+    so = b["sigma"]
+    ds = np.max(np.abs(host(sg) - so)) / so[0]
+    P = host(Pg)[: me * prob.n].reshape(me, prob.n).T
+    Q, _ = np.linalg.qr(P)
+    X = b["X"]
+    d = np.linalg.norm(Q @ (Q.T @ X) - b["Phi"] @ (b["Phi"].T @ X)) / np.linalg.norm(X)
+    print(f"  basis: m_eff {me_g}/{me}, sigma err {ds:.1e} sigma_0, projector difference {d:.1e}", flush=True)
+    assert me_g == me and ds <= 1e-13 and d <= projector_tol(so, me)
+    assert np.array_equal(host(psig), b["psi_new"])
+    del Pg, P, Q
+
+    g = snaps[-1]
+    psi = b["psi_new"]
+    eps, _ = sampling.indicator_full(prob, g, b["Phi"], psi)
+    sel = sampling.select(prob, eps, sampling.RULE_FRACTION, WL3.frac, halo=WL3.halo)
+    s = ctx.sample_select(dev(eps), WL3.frac, WL3.halo)
+    hat, tilde, _ = s.export()
+    assert np.array_equal(host(hat), sel["hat"]) and np.array_equal(host(tilde), sel["tilde"])
+    print(f"  sets: n_s {sel['hat'].size}, l {sel['tilde'].size}", flush=True)
+
+    # the step is taped so that its filter passes (order, kept cells) can be
+    # checked: the residual-gated filter acts on shocks here, and a gate
+    # decided by a residual-norm difference at the rounding level of the
+    # step's inputs may go either way (both correct); every flag is checked
+    # on the oracle's side pass by pass, and the states compared on the same
+    # flags
+    from paper_2301_01718_amd import TAPE_RECORD
+    Phi_rows = dev(np.ascontiguousarray(b["Phi"].T).reshape(-1))
+    tape = ctx.tape()
+    out, info = ctx.rom_hybrid_step_taped(dev(g), Phi_rows, dev(psi), me, tape, TAPE_RECORD, samples=s)
+    J, passes = tape.info()
+    print(f"  gpu hybrid step: J {info['subiters']}, newton {info['newton_iters']}, filter passes {len(passes)}",
+          flush=True)
+    nof = hybrid.hybrid_step(prob, g, b["Phi"], psi, sel["hat"], sel["tilde"], hybrid.HybridParams(filter_orders=()))
+    assert J == nof["J"]
+    pre = nof["gamma"]
+    ref, ties = validate_filter(prob, pre, g, [(n, host(mk)) for n, mk in passes])
+    e = rel(host(out), ref)
+    print(f"  hybrid step: rel error {e:.2e} on the same filter flags ({ties} tied flags), J {J}", flush=True)
+    assert e < 1e-12
+    del Phi_rows
+
+    full, hinfo = ctx.hdm_step(dev(g))
+    R = fv.residual(prob, host(full), g)
+    tol = fv.newton_tol(g)
+    print(f"  hdm step: newton {hinfo['newton_iters']}, oracle ||R||_inf {np.max(np.abs(R)):.2e} "
+          f"(tolerance {tol:.2e})", flush=True)
+    assert hinfo["newton_iters"] >= 1 and np.max(np.abs(R)) <= tol
+

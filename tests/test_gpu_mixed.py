@@ -20,7 +20,7 @@ import workloads as W
 from oracle import arom, fv, hybrid, pod, sampling
 from oracle import adjoint as A
 
-from gpu_common import CASES, case, ctx_for, dev, host, indicator_close, need_gpu, print_case, rel, torch
+from gpu_common import CASES, case, ctx_for, dev, fit_tols, host, indicator_close, need_gpu, print_case, rel, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -144,8 +144,9 @@ def run_mixed_resync(wl, seed, steps, check_from=1, tol=1e-6):
             assert rec["J"] == own["J"], (k, rec["J"], own["J"])
             e_own = rel(g, own["gamma"])
             assert e_own <= 1e-12, (k, "mixed step on its own basis", e_own)
-            ok, d = indicator_close(host(drv.eps), own["eps"], g, tol=1e-12, cell_tol=1e-10)
-            assert ok, (k, "indicator", d)
+            itol, ctol = fit_tols(rec["fit_cond"])
+            ok, d = indicator_close(host(drv.eps), own["eps"], g, tol=itol, cell_tol=ctol)
+            assert ok, (k, "indicator", d, rec["fit_cond"])
             st["worst_own"] = max(st["worst_own"], e_own)
             ref = hybrid.hybrid_step(prob, qp, b["Phi"], b["psi_new"], hat, tilde, hp)
             if rec["J"] != ref["J"]:

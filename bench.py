@@ -364,7 +364,7 @@ def adjoint_bench(name, seed):
         qT = HybridTrajectory.apply(q, traj)
         loss = 0.5 * torch.sum(qT * qT)
         loss.backward()
-    kinds = [k for k, _ in traj.decisions()]
+    kinds = [traj.kinds[k][0] for k in range(1, wl.steps + 1)]
     return {"workload": name, "nx": prob.nx, "ny": prob.ny, "steps": wl.steps, "checkpoint_every": K,
             "hybrid_steps": kinds.count("hybrid"),
             "forward_taped_s_per_step": traj.timing["forward_s"] / wl.steps,

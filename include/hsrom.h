@@ -312,6 +312,58 @@ hs_status hdm_step_adjoint(hs_ctx* ctx, const double* q_out, const double* lam_i
 hs_status rom_hybrid_step_adjoint(hs_ctx* ctx, const double* Phi, int32_t m, const hs_htape* tape,
                                   const double* lam_in, double* lam_out, hs_step_info* info /* host */);
 
+/* -------------------------------------------- trajectory and its adjoint */
+/* A whole run of Algorithm 1 and the frozen-decision adjoint of its map
+ * gamma_0 -> gamma_T (Alg. 1; eq. hdm for full steps, eq. hybrid with the
+ * subiterations of Sec. 2.3.2 and the gated filters of Sec. 2.3.4 for hybrid
+ * steps).  Schedule: full steps for k + 1 <= w, k mod z == 0 and wherever no
+ * sampled set or basis exists; a hybrid step that fails with
+ * HS_ERR_NOT_CONVERGED or HS_ERR_RANK is redone as a full step.  After step
+ * k (k >= w - 1, step k + 1 not full, k < steps) the indicator of gamma_k
+ * selects the sampled set of step k + 1 (sample_select with `sample`) and the
+ * basis and reference state are rebuilt from the last w + 1 snapshots
+ * (basis_update with m, tau_pod). */
+typedef struct hs_traj_params {
+  int32_t steps;              /* N_t >= 1 */
+  int32_t checkpoint_every;   /* K >= 1: a checkpoint of gamma every K steps */
+  int32_t w, m, z;            /* window length, POD rank, full-step period */
+  double  tau_pod;            /* POD cut (1e-8) */
+  hs_sample_params sample;    /* selection rule, fraction / delta, halo */
+  hs_hybrid_params hybrid;    /* hybrid step parameters; precision must be HS_FP64 */
+} hs_traj_params;
+/* Library-owned record of one forward run: per step its kind, the basis it
+ * used and its hybrid-step tape; every basis; the checkpoints.  Its device
+ * memory grows with the run: one N x m basis per update, a tape per hybrid
+ * step, a state per checkpoint (freed by the next hs_traj_forward on the
+ * same tape or by hs_tape_destroy). */
+typedef struct hs_tape hs_tape;
+hs_status hs_tape_create(hs_ctx* ctx, hs_tape** out /* host */);
+hs_status hs_tape_destroy(hs_tape* tape);
+/* Run Alg. 1 from q0 (device, N) for params->steps steps, recording into
+ * tape; qT (device, N) = gamma_T.  Synchronous.  Errors: those of the calls
+ * it makes (a failed full step ends the run with its error). */
+hs_status hs_traj_forward(hs_ctx* ctx, const double* q0, const hs_traj_params* params /* host */,
+                          hs_tape* tape, double* qT);
+/* lam_0 = (d gamma_T / d gamma_0)^T lam_T with every decision of the
+ * recorded run frozen (device, N each; may alias).  Segments of K steps, last
+ * first: replayed from their checkpoints (full steps re-solved, hybrid steps
+ * in HS_TAPE_REPLAY mode), the replayed end state checked against the next
+ * checkpoint bit for bit (HS_ERR_INVALID_ARG if it differs: the inputs or a
+ * basis changed), then hdm_step_adjoint / rom_hybrid_step_adjoint in reverse.
+ * Synchronous. */
+hs_status hs_traj_backward(hs_ctx* ctx, hs_tape* tape, const double* lam_T, double* lam_0);
+/* The recorded run, step k (1..steps): kind (0 full, 1 hybrid), the index
+ * of the basis a hybrid step used (-1 otherwise) and its hybrid-step tape
+ * (borrowed, NULL for a full step); any pointer may be NULL. */
+hs_status hs_tape_step(const hs_tape* tape, int32_t k, int32_t* kind /* host */, int32_t* basis /* host */,
+                       hs_htape** htape /* host */);
+/* Copy basis `basis` out: Phi (device, N x m, column-major), psi (device, N),
+ * m (host); any of them may be NULL. */
+hs_status hs_tape_basis(hs_ctx* ctx, const hs_tape* tape, int32_t basis, double* Phi_out, double* psi_out,
+                        int32_t* m);
+/* Copy the checkpoint of step k (0 and every multiple of K, and steps) out. */
+hs_status hs_tape_checkpoint(hs_ctx* ctx, const hs_tape* tape, int32_t k, double* q_out);
+
 /* ----------------------------------------------------------- options */
 /* HS_OPT_TILED_SWEEPS: how the relaxation sweeps run.  0: one sweep per
  * launch over the compact cell list; 1 (default): LDS tiles, several sweeps

@@ -65,6 +65,12 @@ class HybridParams(ctypes.Structure):
                 ("floor_rel", ctypes.c_double), ("precision", ctypes.c_int32)]
 
 
+class TrajParams(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("checkpoint_every", ctypes.c_int32), ("w", ctypes.c_int32),
+                ("m", ctypes.c_int32), ("z", ctypes.c_int32), ("tau_pod", ctypes.c_double),
+                ("sample", SampleParams), ("hybrid", HybridParams)]
+
+
 def hybrid_params(eps_y=1e-4, jmax=10, filter_orders=(1, 2, 3), eps_f=1e-2, jfmax=10,
                   rcond_fit=1e-8, floor_rel=1e-14, precision=FP64) -> HybridParams:
     hp = HybridParams()
@@ -113,6 +119,13 @@ _SIGS = {
                               ctypes.POINTER(StepInfo), P, I32],
     "hdm_step_adjoint": [P, P, P, P, ctypes.POINTER(StepInfo)],
     "rom_hybrid_step_adjoint": [P, P, I32, P, P, P, ctypes.POINTER(StepInfo)],
+    "hs_tape_create": [P, ctypes.POINTER(P)],
+    "hs_tape_destroy": [P],
+    "hs_traj_forward": [P, P, ctypes.POINTER(TrajParams), P, P],
+    "hs_traj_backward": [P, P, P, P],
+    "hs_tape_step": [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(P)],
+    "hs_tape_basis": [P, P, I32, P, P, ctypes.POINTER(I32)],
+    "hs_tape_checkpoint": [P, P, I32, P],
     "hs_set_option": [P, I32, ctypes.c_int64],
     "hs_prof_enable": [P, I32],
     "hs_prof_read": [P, ctypes.POINTER(D), ctypes.POINTER(I32), ctypes.POINTER(D)],
@@ -429,10 +442,17 @@ class Context:
 
 
 class Tape:
-    """Library-owned record of one hybrid step's frozen decisions."""
+    """Library-owned record of one hybrid step's frozen decisions (``handle``:
+    a tape borrowed from a trajectory tape, which owns and frees it)."""
 
-    def __init__(self, ctx: Context):
+    def __init__(self, ctx: Context, handle=None, owner=None):
         self.ctx = ctx
+        self.owner = owner
+        if handle is not None:
+            self.h = handle
+            self.borrowed = True
+            return
+        self.borrowed = False
         h = P()
         ctx._check(lib().hs_htape_create(ctx.h, ctypes.byref(h)))
         self.h = h
@@ -455,7 +475,8 @@ class Tape:
 
     def close(self):
         if getattr(self, "h", None):
-            lib().hs_htape_destroy(self.h)
+            if not getattr(self, "borrowed", False):
+                lib().hs_htape_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -500,3 +521,46 @@ class Samples:
             self.close()
         except Exception:
             pass
+
+
+class TrajTape:
+    """Library-owned record of one run of hs_traj_forward (hs_tape)."""
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+        h = P()
+        ctx._check(lib().hs_tape_create(ctx.h, ctypes.byref(h)))
+        self.h = h
+
+    def step(self, k):
+        """(kind, basis index, borrowed Tape or None) of step k."""
+        kind, ver, ht = I32(0), I32(0), P()
+        self.ctx._check(lib().hs_tape_step(self.h, k, ctypes.byref(kind), ctypes.byref(ver), ctypes.byref(ht)))
+        tape = Tape(self.ctx, handle=ht, owner=self) if kind.value == 1 else None
+        return kind.value, ver.value, tape
+
+    def basis(self, version, m_max):
+        """Copies of basis `version`: (Phi, flat m x N), psi, m."""
+        m = I32(0)
+        self.ctx._check(lib().hs_tape_basis(self.ctx.h, self.h, version, None, None, ctypes.byref(m)))
+        Phi = self.ctx.empty(max(m.value, 1) * self.ctx.n)
+        psi = self.ctx.empty()
+        self.ctx._check(lib().hs_tape_basis(self.ctx.h, self.h, version, _ptr(Phi), _ptr(psi), None))
+        return Phi[: m.value * self.ctx.n], psi, m.value
+
+    def checkpoint(self, k):
+        q = self.ctx.empty()
+        self.ctx._check(lib().hs_tape_checkpoint(self.ctx.h, self.h, k, _ptr(q)))
+        return q
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hs_tape_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

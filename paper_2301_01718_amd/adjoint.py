@@ -8,15 +8,13 @@ frozen at their forward values; every step is then a smooth function of its
 input (eq. hdm for full steps; eq. hybrid with the subiterations of
 Sec. 2.3.2 and the gated filters of Sec. 2.3.4 for hybrid steps).
 
-Forward: the driver runs Alg. 1; each hybrid step records its decisions in a
-library tape and the basis it used is kept; the state is checkpointed every K
-steps.  Backward: per segment of K steps, last first, the segment is
-replayed from its checkpoint (full steps re-solved, hybrid steps in tape
-replay mode, which reproduces the recorded outputs bit for bit and keeps each
-subiteration's state), then the step adjoints run in reverse order through
-``hdm_step_adjoint`` and ``rom_hybrid_step_adjoint``.
-
-``HybridTrajectory.apply(q0, trajectory)`` exposes it to torch.autograd.
+The library does both directions: ``hs_traj_forward`` runs Alg. 1 and
+records the frozen decisions and a checkpoint every K steps in a trajectory
+tape; ``hs_traj_backward`` replays each segment from its checkpoint (checked
+bit for bit against the next checkpoint) and applies the step adjoints in
+reverse.  This module only marshals arguments and exposes the recorded run
+for inspection.  ``HybridTrajectory.apply(q0, trajectory)`` exposes it to
+torch.autograd.
 """
 from __future__ import annotations
 
@@ -24,33 +22,43 @@ import time
 
 import torch
 
-from ._lib import FP64, TAPE_REPLAY
-from .driver import Arom, AromConfig
+from ._lib import (FP64, TAPE_REPLAY, Context, SampleParams, TrajParams, TrajTape, _ptr, hybrid_params, lib)
+from .driver import AromConfig
 
 
-class _Recorder:
-    """Hands the driver one library tape per hybrid step (reused across runs)."""
+def traj_params(cfg: AromConfig, steps: int, K: int) -> TrajParams:
+    tp = TrajParams()
+    tp.steps, tp.checkpoint_every, tp.w, tp.m, tp.z = steps, K, cfg.w, cfg.m, cfg.z
+    tp.tau_pod = cfg.tau_pod
+    tp.sample = SampleParams(rule=cfg.rule, fraction=cfg.fraction, delta=cfg.delta, halo=cfg.halo)
+    tp.hybrid = hybrid_params(cfg.eps_y, cfg.jmax, cfg.filter_orders, cfg.eps_f, cfg.jfmax, cfg.rcond_fit,
+                              cfg.floor_rel, FP64)
+    return tp
 
-    def __init__(self, ctx):
-        self.ctx = ctx
-        self.tapes = {}
 
-    def tape(self, k):
-        t = self.tapes.get(k)
-        if t is None:
-            t = self.ctx.tape()
-            self.tapes[k] = t
-        return t
+class _Tapes:
+    """tapes[k]: the recorded hybrid-step tape of step k (borrowed)."""
+
+    def __init__(self, traj):
+        self.traj = traj
+
+    @property
+    def tapes(self):
+        return self.traj.tapes
 
 
 class Trajectory:
     """An Alg.-1 trajectory of ``steps`` steps that can be differentiated.
 
-    ``forward(q0)`` runs it and records the frozen decisions; ``backward(lam)``
-    returns (d gamma_T / d gamma_0)^T lam for the last forward run."""
+    ``forward(q0)`` runs it (hs_traj_forward) and records the frozen
+    decisions; ``backward(lam)`` returns (d gamma_T / d gamma_0)^T lam for
+    the last forward run (hs_traj_backward).  After a forward run, ``kinds``
+    (step -> ("full"|"hybrid", basis index)), ``bases`` (index -> (Phi,
+    psi, m), copied on first use), ``tapes`` (step -> hybrid-step tape) and
+    ``ckpt`` (checkpoint step -> state) expose the recorded run."""
 
     def __init__(self, prob, cfg: AromConfig, steps: int, checkpoint_every: int = 10, device="cuda",
-                 ctx=None, verify_replay: bool = True):
+                 ctx=None):
         if checkpoint_every < 1:
             raise ValueError("checkpoint_every must be >= 1")
         if cfg.precision != FP64:
@@ -59,47 +67,58 @@ class Trajectory:
         self.cfg = cfg
         self.steps = steps
         self.K = checkpoint_every
-        self.drv = Arom(prob, cfg, device=device, ctx=ctx)
-        self.ctx = self.drv.ctx
-        self.recorder = _Recorder(self.ctx)
-        self.verify_replay = verify_replay
-        self.records = []
+        self.ctx = ctx or Context(prob, m_max=cfg.m, w_max=cfg.w, device=device)
+        self.params = traj_params(cfg, steps, checkpoint_every)
+        self.hp = self.params.hybrid
+        self.tape = TrajTape(self.ctx)
+        self.recorder = _Tapes(self)
         self.timing = {}
+        self._reset()
+
+    def _reset(self):
+        self.kinds, self.tapes, self._bases, self._ckpt = {}, {}, {}, {}
 
     # ------------------------------------------------------------ forward
     def forward(self, q0):
         c = self.ctx
         q0 = c._in(q0.detach().contiguous())
-        self.ckpt = {0: q0.clone()}
-        self.kinds = {}
-        self.bases = {}
-        K = self.K
-
-        def on_step(k, rec, used, out):
-            if rec["type"] == "hybrid":
-                v = used["basis_version"]
-                if v not in self.bases:
-                    m = used["m"]
-                    self.bases[v] = (used["Phi"][: m * c.n].clone(), used["psi"].clone(), m)
-                self.kinds[k] = ("hybrid", v)
-            else:
-                self.kinds[k] = ("full", None)
-            if k % K == 0 or k == self.steps:
-                self.ckpt[k] = out.clone()
-
-        self.drv.recorder = self.recorder
+        qT = c.empty()
+        self._reset()
         torch.cuda.synchronize(c.device)
         t0 = time.perf_counter()
-        try:
-            qT, self.records = self.drv.run(q0, self.steps, on_step=on_step)
-        finally:
-            self.drv.recorder = None
-        torch.cuda.synchronize(c.device)
+        c._check(lib().hs_traj_forward(c.h, _ptr(q0), self.params, self.tape.h, _ptr(qT)))
         self.timing["forward_s"] = time.perf_counter() - t0
-        return self.ckpt[self.steps].clone()
+        for k in range(1, self.steps + 1):
+            kind, v, tape = self.tape.step(k)
+            self.kinds[k] = ("hybrid", v) if kind == 1 else ("full", None)
+            if tape is not None:
+                self.tapes[k] = tape
+        return qT
 
     # ----------------------------------------------------------- backward
+    def backward(self, lam):
+        c = self.ctx
+        lam = c._in(lam.detach().to(torch.float64).contiguous())
+        out = c.empty()
+        torch.cuda.synchronize(c.device)
+        t0 = time.perf_counter()
+        c._check(lib().hs_traj_backward(c.h, self.tape.h, _ptr(lam), _ptr(out)))
+        self.timing["backward_s"] = time.perf_counter() - t0
+        return out
+
+    # ------------------------------------------------------- inspection
+    @property
+    def bases(self):
+        return _Lazy(self._bases, lambda v: self.tape.basis(v, self.cfg.m))
+
+    @property
+    def ckpt(self):
+        return _Lazy(self._ckpt, self.tape.checkpoint)
+
     def _replay(self, s0, s1):
+        """The states of steps s0+1..s1 replayed from checkpoint s0 with the
+        recorded decisions through the step calls (inspection; the library's
+        backward does the same internally); checked against checkpoint s1."""
         c = self.ctx
         q = self.ckpt[s0]
         outs = {}
@@ -109,44 +128,33 @@ class Trajectory:
                 out, _ = c.hdm_step(q)
             else:
                 Phi, psi, m = self.bases[v]
-                out, _ = c.rom_hybrid_step_taped(q, Phi, psi, m, self.recorder.tapes[k], TAPE_REPLAY,
-                                                 params=self.drv.hp)
+                out, _ = c.rom_hybrid_step_taped(q, Phi, psi, m, self.tapes[k], TAPE_REPLAY, params=self.hp)
             outs[k] = out
             q = out
-        if self.verify_replay and not torch.equal(q, self.ckpt[s1]):
+        if not torch.equal(q, self.ckpt[s1]):
             raise RuntimeError(f"replay of steps {s0 + 1}..{s1} did not reproduce the recorded state")
         return outs
-
-    def backward(self, lam):
-        c = self.ctx
-        lam = c._in(lam.detach().to(torch.float64).contiguous()).clone()
-        torch.cuda.synchronize(c.device)
-        t0 = time.perf_counter()
-        sweeps = 0
-        for s0 in reversed(range(0, self.steps, self.K)):
-            s1 = min(s0 + self.K, self.steps)
-            outs = self._replay(s0, s1)
-            for k in range(s1, s0, -1):
-                kind, v = self.kinds[k]
-                if kind == "full":
-                    lam, info = c.hdm_step_adjoint(outs[k], lam)
-                else:
-                    Phi, _, m = self.bases[v]
-                    lam, info = c.rom_hybrid_step_adjoint(Phi, m, self.recorder.tapes[k], lam)
-                sweeps += info["lin_sweeps"]
-            del outs
-        torch.cuda.synchronize(c.device)
-        self.timing["backward_s"] = time.perf_counter() - t0
-        self.timing["adjoint_sweeps"] = sweeps
-        return lam
 
     def decisions(self):
         """Per step: ("full", None) or ("hybrid", (tape, Phi, psi, m))."""
         out = []
         for k in range(1, self.steps + 1):
             kind, v = self.kinds[k]
-            out.append((kind, None if kind == "full" else (self.recorder.tapes[k],) + self.bases[v]))
+            out.append((kind, None if kind == "full" else (self.tapes[k],) + self.bases[v]))
         return out
+
+
+class _Lazy(dict):
+    """A read-only mapping filled on first access of a key."""
+
+    def __init__(self, cache, make):
+        super().__init__()
+        self._cache, self._make = cache, make
+
+    def __getitem__(self, key):
+        if key not in self._cache:
+            self._cache[key] = self._make(key)
+        return self._cache[key]
 
 
 class HybridTrajectory(torch.autograd.Function):

@@ -258,3 +258,42 @@ def test_trajectory_gradient_matches_oracle(name):
     # trajectory difference (1e-10), and the gathered fits amplify what that
     # does to the bases (1D fits reach condition numbers near 1e3)
     assert e_own < (1e-5 if name == "burgers1d" else 1e-9)
+
+
+@pytest.mark.parametrize("name", ["burgers2d", "euler2d"])
+def test_traj_forward_equals_driver(name):
+    """hs_traj_forward (Alg. 1 inside the library, every hybrid step taped)
+    and the Python driver (the same calls, basis updates overlapped with the
+    selection, untaped steps) take the same decisions and end on the same
+    state to the bit; the library's backward equals the step adjoints applied
+    through the recorded run."""
+    need_gpu()
+    print_case("hs_traj_forward vs driver", name)
+    import paper_2301_01718_amd.driver as D
+    from paper_2301_01718_amd.adjoint import Trajectory
+    wl, extra, seed = TRAJ[name]
+    prob, q0 = W.make(wl, seed)
+    steps = wl.w + extra
+    cfg = D.AromConfig(w=wl.w, m=wl.m, z=wl.z, fraction=wl.frac, halo=wl.halo)
+    drv = D.Arom(prob, cfg)
+    qd, recs = drv.run(dev(q0), steps)
+    traj = Trajectory(prob, cfg, steps, checkpoint_every=5, ctx=drv.ctx)
+    qt = traj.forward(dev(q0))
+    assert [r["type"] for r in recs] == [traj.kinds[k][0] for k in range(1, steps + 1)]
+    assert torch.equal(qd, qt)
+    lam = dev(np.random.default_rng(4).standard_normal(prob.n))
+    g = traj.backward(lam)
+    # the same adjoint by hand through the recorded run
+    c = traj.ctx
+    lam2 = lam.clone()
+    for s0 in reversed(range(0, steps, traj.K)):
+        s1 = min(s0 + traj.K, steps)
+        outs = traj._replay(s0, s1)
+        for k in range(s1, s0, -1):
+            kind, v = traj.kinds[k]
+            if kind == "full":
+                lam2, _ = c.hdm_step_adjoint(outs[k], lam2)
+            else:
+                Phi, _, m = traj.bases[v]
+                lam2, _ = c.rom_hybrid_step_adjoint(Phi, m, traj.tapes[k], lam2)
+    assert torch.equal(g, lam2)

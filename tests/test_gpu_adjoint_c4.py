@@ -46,7 +46,7 @@ def test_c4_gradient_full_size():
     loss = 0.5 * torch.sum((qT - tgt) ** 2)
     loss.backward()
     g = host(q.grad)
-    kinds = [k for k, _ in traj.decisions()]
+    kinds = [traj.kinds[k][0] for k in range(1, wl.steps + 1)]
     print(f"  steps {wl.steps}, hybrid {kinds.count('hybrid')}, |g| {np.linalg.norm(g):.6e}", flush=True)
     assert kinds.count("hybrid") > 20
 
@@ -60,7 +60,7 @@ def test_c4_gradient_full_size():
             else:
                 Phi, psi, m = traj.bases[v]
                 x, _ = c.rom_hybrid_step_taped(x, Phi, psi, m, traj.recorder.tapes[k], TAPE_REPLAY,
-                                               params=traj.drv.hp)
+                                               params=traj.hp)
         return x
 
     assert torch.equal(replay(q0), qT.detach())

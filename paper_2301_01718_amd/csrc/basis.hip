@@ -245,73 +245,121 @@ __device__ inline double group8_sum(double x) {
   return x;
 }
 
-// Block-wide pivoted Cholesky of the symmetric w x w matrix A (stride lda):
-// A = P L L^T P^T + S, stopped once the largest remaining diagonal entry is at
-// most tol (S is what remains).  L (zeroed by the caller) holds rows in pivot
-// order (row i <-> index perm[i]) and columns 0 .. rank - 1.  The pivot is the
-// largest remaining diagonal, ties to the lowest position (w <= 64: one wave).
-// Every thread of the block calls it; d, perm, rank and piv are shared.
-__device__ void block_pivoted_cholesky(const double* A, int lda, int w, double tol, double* L, double* d,
-                                       int* perm, int* rank, int* piv) {
-  const int t = threadIdx.x, nt = blockDim.x;
-  if (t < w) {
-    d[t] = A[t * lda + t];
-    perm[t] = t;
+template <int CTRL>
+__device__ inline int dpp_int(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+
+// Largest v over the wave with its lane's index id (ties to the lower id),
+// returned in every lane: a butterfly within each row of 16 lanes by DPP
+// moves (quad xor 1, quad xor 2, half-row mirror, row mirror), then the four
+// row results read as uniform values.
+__device__ inline double wave_argmax(double v, int id, int& arg) {
+#define HS_ARGMAX_STEP(CTRL)                                  \
+  {                                                           \
+    const double ov = dpp_double<CTRL>(v);                    \
+    const int oi = dpp_int<CTRL>(id);                         \
+    if (ov > v || (ov == v && oi < id)) { v = ov; id = oi; }  \
   }
-  if (t == 0) *rank = 0;
-  __syncthreads();
-  for (int k = 0; k < w; ++k) {
-    if (t < kWave) {
-      double best = (t >= k && t < w) ? d[perm[t]] : -INFINITY;
-      int p = t;
-      for (int o = kWave / 2; o > 0; o >>= 1) {
-        const double ob = __shfl_xor(best, o, kWave);
-        const int op = __shfl_xor(p, o, kWave);
-        if (ob > best || (ob == best && op < p)) { best = ob; p = op; }
-      }
-      if (t == 0) {
-        *piv = best > tol ? p : -1;
-        if (*piv >= 0) *rank = k + 1;
-      }
-    }
-    __syncthreads();
-    const int pv = *piv;
-    if (pv < 0) break;
-    if (pv != k) {   // swap pivot rows k <-> pv of perm and of L's first k columns
-      if (t < k) {
-        const double x = L[k * lda + t];
-        L[k * lda + t] = L[pv * lda + t];
-        L[pv * lda + t] = x;
-      }
-      __syncthreads();
-      if (t == 0) {
-        const int x = perm[k];
-        perm[k] = perm[pv];
-        perm[pv] = x;
-      }
-      __syncthreads();
-    }
-    const double lkk = sqrt(d[perm[k]]);
-    for (int i = k + t; i < w; i += nt) {
-      if (i == k) {
-        L[k * lda + k] = lkk;
-        continue;
-      }
-      double sacc = A[perm[i] * lda + perm[k]];
-      double s4[4] = {0.0, 0.0, 0.0, 0.0};
-      int j = 0;
-      for (; j + 8 <= k; j += 8) {
+  HS_ARGMAX_STEP(0xB1)
+  HS_ARGMAX_STEP(0x4E)
+  HS_ARGMAX_STEP(0x141)
+  HS_ARGMAX_STEP(0x140)
+#undef HS_ARGMAX_STEP
+  double best = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 0),
+                                 __builtin_amdgcn_readlane(__double2loint(v), 0));
+  int bi = __builtin_amdgcn_readlane(id, 0);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) s4[u % 4] += L[i * lda + j + u] * L[k * lda + j + u];
+  for (int r = 1; r < 4; ++r) {
+    const double rv = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 16 * r),
+                                       __builtin_amdgcn_readlane(__double2loint(v), 16 * r));
+    const int ri = __builtin_amdgcn_readlane(id, 16 * r);
+    if (rv > best || (rv == best && ri < bi)) { best = rv; bi = ri; }
+  }
+  arg = bi;
+  return best;
+}
+
+// Pivoted Cholesky of the symmetric w x w matrix A (stride lda, w <= 64):
+// A = P L L^T P^T + S, stopped once the largest remaining diagonal entry is at
+// most tol (S is what remains).  Right-looking, block parallel: per step one
+// wave picks the pivot (the largest remaining diagonal, ties to the lowest
+// index), every row forms its multiplier l_i = A[i][p] / sqrt(A[p][p]) (the
+// multipliers go to L in the original row order), and the block subtracts
+// l l^T from the trailing matrix in place; three barriers per step.  Outputs:
+// L (zeroed by the caller) with rows in pivot order (row q <-> index
+// perm[q]) and columns 0 .. rank - 1; perm is a full permutation (rows never
+// pivoted follow in increasing index).  A is overwritten.  Every thread of
+// the block (256 threads) calls it; buf holds 2 * kMaxBasis doubles of LDS.
+__device__ __forceinline__ void block_pivoted_cholesky(double* A, int lda, int w, double tol, double* L,
+                                                       double* buf, int* perm, int* rank) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  __shared__ int s_piv, s_done[kMaxBasis];
+  __shared__ double s_best;
+  if (t < kMaxBasis) s_done[t] = t >= w;
+  __syncthreads();
+  int k = 0;
+  for (; k < w; ++k) {
+    if (t < kWave) {
+      int p;
+      const double best = wave_argmax(s_done[t] ? -INFINITY : A[t * lda + t], t, p);
+      if (t == 0) {
+        s_piv = p;
+        s_best = best;
       }
-      for (; j < k; ++j) s4[0] += L[i * lda + j] * L[k * lda + j];
-      sacc -= ((s4[0] + s4[1]) + s4[2]) + s4[3];
-      const double lik = sacc / lkk;
-      L[i * lda + k] = lik;
-      d[perm[i]] -= lik * lik;
+    }
+    __syncthreads();
+    const int p = s_piv;
+    const double best = s_best;
+    if (!(best > tol)) break;
+    const double lkk = sqrt(best);
+    if (t < w) {
+      const double li = s_done[t] ? 0.0 : (t == p ? lkk : A[t * lda + p] / lkk);
+      buf[t] = li;
+      L[t * lda + k] = li;
+    }
+    __syncthreads();
+    // rows t / 64, t / 64 + 4, ..., column t % 64 (no integer division by w)
+    // (unrolled, so that every row's loads are in flight together)
+    if ((t & 63) < w) {
+      const int j = t & 63;
+      const double lj = buf[j];
+#pragma unroll
+      for (int u = 0; u < kMaxBasis / 4; ++u) {
+        const int i = (t >> 6) + 4 * u;
+        if (i < w) A[i * lda + j] -= buf[i] * lj;
+      }
+    }
+    if (t == 0) {
+      s_done[p] = 1;
+      perm[k] = p;
     }
     __syncthreads();
   }
+  // the rows never pivoted take the remaining positions in index order
+  if (t < kWave) {
+    const bool rest = t < w && !s_done[t];
+    const unsigned long long mask = __ballot(rest);
+    if (rest) perm[k + __popcll(mask & ((1ull << t) - 1ull))] = t;
+  }
+  __syncthreads();
+  // rows of L into pivot order (through registers: at most 16 entries per thread)
+  const int r = k;
+  const int c = t & 63;
+  double tmp[kMaxBasis / 4];
+#pragma unroll
+  for (int u = 0; u < kMaxBasis / 4; ++u) {
+    const int q = (t >> 6) + 4 * u;
+    tmp[u] = (q < w && c < r) ? L[perm[q] * lda + c] : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kMaxBasis / 4; ++u) {
+    const int q = (t >> 6) + 4 * u;
+    if (q < w && c < r) L[q * lda + c] = tmp[u];
+  }
+  if (t == 0) *rank = r;
+  __syncthreads();
 }
 
 // 1/sqrt(x) for x > 1e-290 from the hardware estimate and two Newton steps
@@ -336,48 +384,61 @@ __device__ inline double rcp_newton(double x) {
   return r;
 }
 
-// One-sided Jacobi on the columns of B (w rows x r columns, stride lda): rotate
+// One-sided Jacobi on the columns of B (w rows x r columns; column p at
+// B[p * ldb], rows contiguous): rotate
 // column pairs until they are orthogonal, so that B W = U Sigma with U the
 // left singular vectors of B and Sigma its singular values (the column norms
 // afterwards).  Pairs are scheduled round robin; each pair is one group of 8
 // lanes (dot products reduced by DPP moves), one barrier per round.  A pair is
 // rotated when |b_p.b_q| > sqrt(w) eps |b_p||b_q| (the rounding level of a
 // length-w dot product); sweeps stop once no pair exceeds w eps, so rounding
-// noise cannot keep them going.  Block of 256 threads (up to 32 pairs).
-__device__ void block_jacobi_columns(double* B, int lda, int w, int r) {
+// noise cannot keep them going.  Block of 256 threads (up to 32 pairs).  With
+// ldb = 8 (mod 16) doubles a group's eight lanes read one half of the LDS
+// banks, the half set by the parity of its column.
+template <int NR>
+__device__ __forceinline__ void block_jacobi_columns(double* B, int ldb, int w, int r, int* sched, int* rotated_p) {
   const int t = threadIdx.x;
   const double tol_rot = sqrt((double)w) * 2.2e-16, tol_conv = (double)w * 2.2e-16;
   const int np = (r + 1) & ~1;
   const int P = np / 2;
   const int grp = t / 8, gl = t % 8;
-  __shared__ int rotated;
+  int& rotated = *rotated_p;
+  // the round-robin schedule, once (sched: LDS of (kMaxBasis - 1) kMaxBasis / 2
+  // ints): round rd pairs (p, q) of group grp
+  for (int e = t; e < (np - 1) * P; e += blockDim.x) {
+    const int rd = e / P, g = e % P;
+    int p, q;
+    if (g == 0) {
+      p = rd % (np - 1);
+      q = np - 1;
+    } else {
+      p = (rd + g) % (np - 1);
+      q = (rd - g + (np - 1)) % (np - 1);
+    }
+    if (p > q) { const int x = p; p = q; q = x; }
+    sched[e] = p | (q << 8);
+  }
+  __syncthreads();
   for (int sweep = 0; sweep < 60 && r > 1; ++sweep) {
     if (t == 0) rotated = 0;
     __syncthreads();
     for (int rd = 0; rd < np - 1; ++rd) {
       if (grp < P) {
-        int p, q;
-        if (grp == 0) {
-          p = rd % (np - 1);
-          q = np - 1;
-        } else {
-          p = (rd + grp) % (np - 1);
-          q = (rd - grp + (np - 1)) % (np - 1);
-        }
-        if (p > q) { const int x = p; p = q; q = x; }
+        const int pq = sched[rd * P + grp];
+        const int p = pq & 0xFF, q = pq >> 8;
         if (q < r) {
-          // rows gl, gl + 8, ... (64 rows: rows past w are zero, so the
-          // loads and stores need no branch and are all in flight together)
-          double xs[8], ys[8];
+          // rows gl, gl + 8, ... (8 NR >= w rows: rows past w are zero, so
+          // the loads and stores need no branch and are all in flight together)
+          double xs[NR], ys[NR];
 #pragma unroll
-          for (int i = 0; i < 8; ++i) {
+          for (int i = 0; i < NR; ++i) {
             const int k = gl + 8 * i;
-            xs[i] = B[k * lda + p];
-            ys[i] = B[k * lda + q];
+            xs[i] = B[p * ldb + k];
+            ys[i] = B[q * ldb + k];
           }
           double aa = 0.0, bb = 0.0, gg = 0.0;
 #pragma unroll
-          for (int i = 0; i < 8; ++i) {
+          for (int i = 0; i < NR; ++i) {
             aa += xs[i] * xs[i];
             bb += ys[i] * ys[i];
             gg += xs[i] * ys[i];
@@ -403,10 +464,10 @@ __device__ void block_jacobi_columns(double* B, int lda, int w, int r) {
             }
             const double sn = c * tt;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
+            for (int i = 0; i < NR; ++i) {
               const int k = gl + 8 * i;
-              B[k * lda + p] = c * xs[i] - sn * ys[i];
-              B[k * lda + q] = sn * xs[i] + c * ys[i];
+              B[p * ldb + k] = c * xs[i] - sn * ys[i];
+              B[q * ldb + k] = sn * xs[i] + c * ys[i];
             }
             if (gl == 0 && gg * gg > tol_conv * tol_conv * ab) rotated = 1;
           }
@@ -443,15 +504,19 @@ constexpr double kTrunc2 = 1e-15;
 // inverse T1 = P U1^-1 (wp x wp, zero padded, the operand of the second pass).
 __global__ void __launch_bounds__(256) basis_prec_kernel(const double* __restrict__ G, int w, int wp,
                                                         double* __restrict__ T1, double* __restrict__ C1) {
+  // one workgroup on a latency-bound chain, sharing its compute unit with the
+  // main stream's kernels: its waves take issue priority there
+  __builtin_amdgcn_s_setprio(3);
   constexpr int lda = kMaxBasis + 1;
   __shared__ double A[kMaxBasis * lda];   // G1, then the columns of U1^-1
   __shared__ double L[kMaxBasis * lda];   // completed Cholesky factor L1 = U1^T (pivot order)
-  __shared__ double d[kMaxBasis];
+  __shared__ double buf[2 * kMaxBasis];
   __shared__ int perm[kMaxBasis];
-  __shared__ int rank, piv;
+  __shared__ int rank;
   __shared__ double s1;
   const int t = threadIdx.x, nt = blockDim.x;
-  for (int e = t; e < w * w; e += nt) A[(e / w) * lda + e % w] = G[e];
+  if ((t & 63) < w)
+    for (int i = t >> 6; i < w; i += nt >> 6) A[i * lda + (t & 63)] = G[i * w + (t & 63)];
   for (int e = t; e < kMaxBasis * lda; e += nt) L[e] = 0.0;
   __syncthreads();
   if (t == 0) {
@@ -460,21 +525,31 @@ __global__ void __launch_bounds__(256) basis_prec_kernel(const double* __restric
     s1 = tr > 0.0 ? kShift1 * tr : 1.0;   // an all-zero window: any invertible C1 will do
   }
   __syncthreads();
-  block_pivoted_cholesky(A, lda, w, s1, L, d, perm, &rank, &piv);
+  block_pivoted_cholesky(A, lda, w, s1, L, buf, perm, &rank);
   const int r = rank;
   for (int k = r + t; k < w; k += nt) L[k * lda + k] = sqrt(s1);
   __syncthreads();
-  // U1^-1, one column per thread by back substitution: U1 x = e_c with
-  // U1[i][k] = L[k][i]; x goes to A[. * lda + c]
-  if (t < w) {
-    const int c = t;
-    for (int i = c; i >= 0; --i) {
-      double s = i == c ? 1.0 : 0.0;
-      for (int k = i + 1; k <= c; ++k) s -= L[k * lda + i] * A[k * lda + c];
-      A[i * lda + c] = s / L[i * lda + i];
-    }
-  }
+  // U1^-1 by right-looking back substitution on all columns at once: U1 X = I
+  // with U1[i][k] = L[k][i]; X builds up in A (row i final once step i has
+  // divided it by U1[i][i], rows above i updated by U1[k][i] X[i][.])
+  if ((t & 63) < w)
+    for (int i = t >> 6; i < w; i += nt >> 6) A[i * lda + (t & 63)] = i == (t & 63) ? 1.0 : 0.0;
   __syncthreads();
+  for (int i = w - 1; i >= 0; --i) {
+    if (t >= i && t < w) A[i * lda + t] /= L[i * lda + i];
+    __syncthreads();
+    // rows t / 64, t / 64 + 4, ... < i, column i + t % 64 (no integer division)
+    const int c = i + (t & 63);
+    if (c < w) {
+      const double xc = A[i * lda + c];
+#pragma unroll
+      for (int u = 0; u < kMaxBasis / 4; ++u) {
+        const int k = (t >> 6) + 4 * u;
+        if (k < i) A[k * lda + c] -= L[i * lda + k] * xc;
+      }
+    }
+    __syncthreads();
+  }
   // T1[perm[i]][c] = (U1^-1)[i][c]; C1[i][perm[k]] = U1[i][k] = L[k][i]
   __shared__ int iperm[kMaxBasis];
   if (t < w) iperm[perm[t]] = t;
@@ -502,22 +577,22 @@ __global__ void __launch_bounds__(256) basis_svd_kernel(const double* __restrict
                                                        double tau, double* __restrict__ sigma,
                                                        double* __restrict__ T, int mp,
                                                        int* __restrict__ m_eff_out) {
+  __builtin_amdgcn_s_setprio(3);   // as in the preconditioner kernel
   constexpr int lda = kMaxBasis + 1;
-  __shared__ double A[kMaxBasis * lda];   // G2, then R^T, rotated in place
+  constexpr int ldb = kMaxBasis + 8;
+  __shared__ double A[kMaxBasis * ldb];   // G2 (stride lda), then R by rows (the columns of R^T, stride ldb)
   __shared__ double L[kMaxBasis * lda];   // pivoted Cholesky factor of G2, then V
   __shared__ double Cs[kMaxBasis * kMaxBasis];   // C1 (its rows are read in pivot order)
-  __shared__ double d[kMaxBasis], lam[kMaxBasis];
+  __shared__ double d[2 * kMaxBasis], lam[kMaxBasis];
   __shared__ int perm[kMaxBasis], order[kMaxBasis];
-  __shared__ int rank, piv, meff;
+  __shared__ int sched[(kMaxBasis - 1) * (kMaxBasis / 2)];
+  __shared__ int rank, meff, rotated;
   __shared__ double tol;
   const int t = threadIdx.x, nt = blockDim.x;
-  for (int e = t; e < kMaxBasis * lda; e += nt) {
-    A[e] = 0.0;            // rows past w stay zero (the Jacobi reads all 64 rows)
-    L[e] = 0.0;
-  }
+  for (int e = t; e < kMaxBasis * lda; e += nt) L[e] = 0.0;
   for (int e = t; e < w * kMaxBasis; e += nt) Cs[e] = C1[e];
-  __syncthreads();
-  for (int e = t; e < w * w; e += nt) A[(e / w) * lda + e % w] = G2[e];
+  if ((t & 63) < w)
+    for (int i = t >> 6; i < w; i += nt >> 6) A[i * lda + (t & 63)] = G2[i * w + (t & 63)];
   __syncthreads();
   if (t == 0) {
     double tr = 0.0;
@@ -525,21 +600,48 @@ __global__ void __launch_bounds__(256) basis_svd_kernel(const double* __restrict
     tol = kTrunc2 * tr;
   }
   __syncthreads();
-  block_pivoted_cholesky(A, lda, w, tol, L, d, perm, &rank, &piv);
+  block_pivoted_cholesky(A, lda, w, tol, L, d, perm, &rank);
   const int r = rank;
-  // R^T[j][i] = R[i][j] = sum_k L2[k][i] C1[perm[k]][j]  (L2[k][i] = 0 for k < i)
-  for (int e = t; e < w * r; e += nt) {
-    const int j = e / r, i = e % r;
-    double s = 0.0;
-    for (int k = i; k < w; ++k) s += L[k * lda + i] * Cs[perm[k] * kMaxBasis + j];
-    A[j * lda + i] = s;
+  for (int e = t; e < kMaxBasis * ldb; e += nt) A[e] = 0.0;   // rows past w of R^T stay zero
+  __syncthreads();
+  // R[i][j] = sum_k R2[i][k] C1[perm[k]][j], R2[i][k] = L2[k][i] (zero for
+  // k < i and for i >= r), on MFMA in 16 x 16 tiles; row i of R is column i
+  // of R^T, stored at A[i * ldb]
+  {
+    const int lane = t % kWave, wv = t / kWave;
+    const int nti = (r + 15) / 16, ntj = (w + 15) / 16;
+    for (int tt = wv; tt < nti * ntj; tt += nt / kWave) {
+      const int ti = tt / ntj, tj = tt % ntj;
+      double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < w; k0 += 4) {
+        const int k = k0 + lane / 16;
+        const int i = ti * 16 + lane % 16, j = tj * 16 + lane % 16;
+        const double av = k < w ? L[k * lda + i] : 0.0;
+        const double bv = (k < w && j < w) ? Cs[perm[k] * kMaxBasis + j] : 0.0;
+        acc = mfma_f64(av, bv, acc);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = ti * 16 + lane / 16 + 4 * q, j = tj * 16 + lane % 16;
+        if (i < r && j < w) A[i * ldb + j] = acc[q];
+      }
+    }
   }
   __syncthreads();
-  block_jacobi_columns(A, lda, w, r);
+  switch ((w + 7) / 8) {
+    case 1: block_jacobi_columns<1>(A, ldb, w, r, sched, &rotated); break;
+    case 2: block_jacobi_columns<2>(A, ldb, w, r, sched, &rotated); break;
+    case 3: block_jacobi_columns<3>(A, ldb, w, r, sched, &rotated); break;
+    case 4: block_jacobi_columns<4>(A, ldb, w, r, sched, &rotated); break;
+    case 5: block_jacobi_columns<5>(A, ldb, w, r, sched, &rotated); break;
+    case 6: block_jacobi_columns<6>(A, ldb, w, r, sched, &rotated); break;
+    case 7: block_jacobi_columns<7>(A, ldb, w, r, sched, &rotated); break;
+    default: block_jacobi_columns<8>(A, ldb, w, r, sched, &rotated); break;
+  }
   // squared singular values: column norms, in descending order (stable rank sort)
   if (t < r) {
     double s2 = 0.0;
-    for (int k = 0; k < w; ++k) s2 += A[k * lda + t] * A[k * lda + t];
+    for (int k = 0; k < w; ++k) s2 += A[t * ldb + k] * A[t * ldb + k];
     d[t] = s2;
   }
   __syncthreads();
@@ -566,7 +668,7 @@ __global__ void __launch_bounds__(256) basis_svd_kernel(const double* __restrict
   // V[:, i] = (R^T W)[:, order[i]] / sigma_i
   for (int e = t; e < w * meff; e += nt) {
     const int row = e / meff, i = e % meff;
-    L[row * lda + i] = A[row * lda + order[i]] / sqrt(lam[i]);
+    L[row * lda + i] = A[order[i] * ldb + row] / sqrt(lam[i]);
   }
   __syncthreads();
   for (int i = t; i < mp; i += nt) {
@@ -732,6 +834,15 @@ __global__ void __launch_bounds__(256) basis_form_kernel(const SnapTable snaps, 
   }
 }
 
+// Workgroups of 256 threads of kernel fn (dynamic LDS lds) that the device
+// holds at once: a window pass launched with exactly that many workgroups
+// runs in one resident round, every wave with the same share of chunks.
+static int resident_blocks(const hs_ctx* ctx, const void* fn, size_t lds) {
+  int per = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, lds) != hipSuccess || per < 1) per = 1;
+  return per * ctx->num_cu;
+}
+
 // Enqueue the whole update on the context's current stream; m_eff stays on
 // the device (meff_d) until read back.
 static hs_status basis_enqueue(hs_ctx* ctx, const double* const* snaps, int32_t nsnap, int32_t w, int32_t m,
@@ -756,6 +867,7 @@ static hs_status basis_enqueue(hs_ctx* ctx, const double* const* snaps, int32_t 
   const long long nchunks = (n + kWaveRows - 1) / kWaveRows;
   const int nb = (int)std::min<long long>((nchunks + 3) / 4, 768);
   const int nbf = (int)std::min<long long>((nchunks + 3) / 4, kRedBlocks);
+  int nb_pgram = nb;
   const size_t glds = (size_t)4 * kWaveRows * (wp + 1) * sizeof(double);
   const size_t flds = ((size_t)wp * (mp + 1) + (size_t)4 * kWaveRows * (wp + 1)) * sizeof(double);
   if (flds > (size_t)ctx->max_lds)
@@ -783,15 +895,24 @@ static hs_status basis_enqueue(hs_ctx* ctx, const double* const* snaps, int32_t 
   if (plds > (size_t)ctx->max_lds)
     return ctx->fail(HS_ERR_SHAPE, "basis_update: window needs more LDS than a workgroup has");
   HS_TRY(prof_begin(ctx, HS_PROF_BASIS_PGRAM));
-  switch (wp) {
-    case 16: hipLaunchKernelGGL(window_pgram_kernel<17>, dim3(nb), dim3(256), plds, ctx->stream, tab, nsnap, w, n, (const double*)T1, wp, ctx->red); break;
-    case 32: hipLaunchKernelGGL(window_pgram_kernel<33>, dim3(nb), dim3(256), plds, ctx->stream, tab, nsnap, w, n, (const double*)T1, wp, ctx->red); break;
-    case 48: hipLaunchKernelGGL(window_pgram_kernel<49>, dim3(nb), dim3(256), plds, ctx->stream, tab, nsnap, w, n, (const double*)T1, wp, ctx->red); break;
-    default: hipLaunchKernelGGL(window_pgram_kernel<65>, dim3(nb), dim3(256), plds, ctx->stream, tab, nsnap, w, n, (const double*)T1, wp, ctx->red); break;
+  {
+    // the pass holds more registers than the Gram pass (two workgroups per
+    // compute unit instead of three): its grid is its own resident round
+    const void* fn = wp == 16 ? (const void*)window_pgram_kernel<17>
+                   : wp == 32 ? (const void*)window_pgram_kernel<33>
+                   : wp == 48 ? (const void*)window_pgram_kernel<49> : (const void*)window_pgram_kernel<65>;
+    const int nbp = (int)std::min<long long>({(nchunks + 3) / 4, (long long)resident_blocks(ctx, fn, plds), 768LL});
+    switch (wp) {
+      case 16: hipLaunchKernelGGL(window_pgram_kernel<17>, dim3(nbp), dim3(256), plds, ctx->stream, tab, nsnap, w, n, (const double*)T1, wp, ctx->red); break;
+      case 32: hipLaunchKernelGGL(window_pgram_kernel<33>, dim3(nbp), dim3(256), plds, ctx->stream, tab, nsnap, w, n, (const double*)T1, wp, ctx->red); break;
+      case 48: hipLaunchKernelGGL(window_pgram_kernel<49>, dim3(nbp), dim3(256), plds, ctx->stream, tab, nsnap, w, n, (const double*)T1, wp, ctx->red); break;
+      default: hipLaunchKernelGGL(window_pgram_kernel<65>, dim3(nbp), dim3(256), plds, ctx->stream, tab, nsnap, w, n, (const double*)T1, wp, ctx->red); break;
+    }
+    nb_pgram = nbp;
   }
   HIP_TRY(ctx, hipGetLastError());
   HS_TRY(prof_end(ctx, HS_PROF_BASIS_PGRAM, 8.0 * (double)n * nsnap));
-  HS_LAUNCH(ctx, gram_reduce_kernel, w * w, kBlock, ctx->red, nb, wp, w, G2);
+  HS_LAUNCH(ctx, gram_reduce_kernel, w * w, kBlock, ctx->red, nb_pgram, wp, w, G2);
   HS_LAUNCH(ctx, basis_svd_kernel, 1, 256, (const double*)G2, (const double*)C1, w, m, tau_pod, sigma_out, T, mp,
             meff_d);
   HS_TRY(prof_begin(ctx, HS_PROF_BASIS_FORM));

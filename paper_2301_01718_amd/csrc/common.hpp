@@ -65,6 +65,7 @@ struct hs_ctx {
   struct { long long n; int nsnap; double phi_bytes; int prof_idx; } pending_form{0, 0, 8.0, -1};
   int device = 0;
   int max_lds = 65536;               // LDS bytes a workgroup may use on this device
+  int num_cu = 256;                  // compute units of the device
   std::string err;
 
   // device workspaces (allocated once at create)

@@ -607,6 +607,9 @@ hs_status hs_create(const hs_problem* pr, void* stream, hs_ctx** out) {
   (void)hipGetDevice(&ctx->device);
   if (hipDeviceGetAttribute(&ctx->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device) != hipSuccess)
     ctx->max_lds = 65536;
+  if (hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess ||
+      ctx->num_cu < 1)
+    ctx->num_cu = 256;
   ctx->nc = pr->kind == HS_EULER_2D ? 4 : 1;
   ctx->ncell = pr->nx * pr->ny;
   ctx->n = ctx->nc * ctx->ncell;

@@ -82,6 +82,16 @@ def fit_tols(fit_cond, tol=1e-12, cell_tol=1e-10):
     return max(tol, k2e), max(cell_tol, 100.0 * k2e)
 
 
+def state_tol(fit_cond, tol=1e-12):
+    """The state bar of a hybrid step whose gathered basis has condition
+    number (bound) fit_cond: the unsampled cells are psi + Phi y, and for a
+    least-squares fit with a small residual (the misfit on the sampled cells
+    is O(sqrt(eps)) relative) first-order perturbation theory bounds the
+    relative difference of two correct solutions y by about kappa eps, so the
+    bar grows with 10 kappa eps once that exceeds tol."""
+    return max(tol, 10.0 * float(fit_cond) * 2.2e-16)
+
+
 def projector_tol(sigma, me, c=100.0):
     """Bound on ||P_gpu X - P_oracle X|| / ||X|| for the orthogonal projectors
     onto two rank-me POD subspaces of the same window.  Both SVDs are exact for

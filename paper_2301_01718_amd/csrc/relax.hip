@@ -58,12 +58,17 @@ __device__ inline int newton_sweeps(double rmax, double rho, const NewtonCtrl& c
 // max |x_last - x_prev| and max |x_last| of the tile go to the statistics.
 // With ctl.part the launch first takes the Newton decision (NewtonCtrl): nsw
 // and q then follow from it, and block 0 posts the statistics to the host.
+// The grid is ntiles rounded up to a multiple of 8 workgroups, in an
+// XCD-aware order: workgroups are dealt to the eight XCDs round robin (block b
+// runs on XCD b % 8), so block b takes tile slot (b % 8) per + b / 8 and each
+// XCD sweeps a contiguous run of the (row-ordered) tile list, whose staged
+// halos overlap and are then read from that XCD's own L2.
 template <int NC, int TSX, int TSY, int S, bool COEF_REG, int NT>
 __global__ void __launch_bounds__(NT) tile_sweep_kernel(
-    Grid g, const int* __restrict__ tiles, int ntx, const int* __restrict__ pos, const int* __restrict__ nbr,
-    int cap, const double* __restrict__ coef, const double* __restrict__ rhs, const double* __restrict__ xin,
-    double* __restrict__ xout, double* __restrict__ q, int nsw, int record, double* __restrict__ part,
-    const NewtonCtrl ctl) {
+    Grid g, const int* __restrict__ tiles, int ntiles, int ntx, const int* __restrict__ pos,
+    const int* __restrict__ nbr, int cap, const double* __restrict__ coef, const double* __restrict__ rhs,
+    const double* __restrict__ xin, double* __restrict__ xout, double* __restrict__ q, int nsw, int record,
+    double* __restrict__ part, const NewtonCtrl ctl) {
   using C = TileCfg<NC, TSX, TSY, S, NT>;
   constexpr int RW = C::RW, RH = C::RH, R = C::R, CPT = C::CPT;
   constexpr bool ONE_D = TSY == 1;
@@ -105,17 +110,27 @@ __global__ void __launch_bounds__(NT) tile_sweep_kernel(
     nsw = min(S, total - 1);
     if (total - 1 > S) q = nullptr;
   }
-  const int tile = tiles ? tiles[blockIdx.x] : (int)blockIdx.x;
+  const int slot = (int)(blockIdx.x % 8) * (int)(gridDim.x / 8) + (int)(blockIdx.x / 8);
+  if (slot >= ntiles) return;
+  const int tile = tiles ? tiles[slot] : slot;
   const int tx = tile % ntx, ty = tile / ntx;
   const int i0 = tx * TSX - S, j0 = ONE_D ? 0 : ty * TSY - S;
   const bool per = g.bc == HS_BC_PERIODIC;
 
-  // Staging, with every global load of the thread issued before the first
-  // use: (1) the region cells (wrapped, or -1 outside the domain); (2) their
-  // compact indices; (3) iterate, right-hand side and coefficients at clamped
-  // addresses (masked afterwards), so no load waits behind another cell's.
+  // Which cells a launch of nsw <= S sweeps touches: before sweep k the
+  // values at distance >= k from the region edge are exact, and only the
+  // tile (distance >= S) is kept, so sweep k updates the cells at distance
+  // >= lo + 1 + k (lo = S - nsw) and cells nearer the edge than lo are never
+  // read.  Cells outside the set carry no unknown: never updated (their value
+  // stays 0, and no set cell reads them).
+  const int lo = S - nsw;
+  // Staging, with the loads of a kind issued together: (1) the region cells
+  // (wrapped, or -1 outside the domain) and their distance to the region
+  // edge; (2) their compact indices; (3) iterate, right-hand side and
+  // coefficients of the cells that need them.
   int pidx[CPT];
   int cells[CPT];
+  int dist[CPT];
   unsigned vmask[CPT];
   double rh[CPT][NC];
   double x0[CPT][NC];
@@ -123,9 +138,11 @@ __global__ void __launch_bounds__(NT) tile_sweep_kernel(
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
     const int r = threadIdx.x + c * NT;
-    int cell = -1;
+    int cell = -1, dd = -1;
     if (r < R) {
       const int rx = r % RW, ry = r / RW;
+      dd = min(rx, RW - 1 - rx);
+      if (!ONE_D) dd = min(dd, min(ry, RH - 1 - ry));
       int gi = i0 + rx, gj = j0 + ry;
       if (per) {
         gi = wrap_index(gi, g.nx);
@@ -136,45 +153,51 @@ __global__ void __launch_bounds__(NT) tile_sweep_kernel(
       }
     }
     cells[c] = cell;
+    dist[c] = dd;
   }
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
-    const int cl = cells[c] < 0 ? 0 : cells[c];
-    const int p = pos ? pos[cl] : cl;
-    pidx[c] = cells[c] < 0 ? -1 : p;
+    int p = -1;
+    if (cells[c] >= 0 && dist[c] >= lo) p = pos ? pos[cells[c]] : cells[c];
+    pidx[c] = p;
   }
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
-    const int pp = pidx[c] < 0 ? 0 : pidx[c];
 #pragma unroll
-    for (int a = 0; a < NC; ++a) x0[c][a] = xin[a * cap + pp];
+    for (int a = 0; a < NC; ++a) x0[c][a] = 0.0;
+    if (pidx[c] >= 0) {
+#pragma unroll
+      for (int a = 0; a < NC; ++a) x0[c][a] = xin[a * cap + pidx[c]];
+    }
   }
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
     const int p = pidx[c];
-    const int pp = p < 0 ? 0 : p;
     unsigned v = 0u;
 #pragma unroll
-    for (int d = 0; d < NDIR; ++d) {
-      bool ok;
-      if (pos) {
-        ok = nbr[d * cap + pp] >= 0;
-      } else {
-        const int cl = cells[c] < 0 ? 0 : cells[c];
-        int ci, cj;
-        cell_ij(g, cl, ci, cj);
-        const int nb = neighbour(g, ci, cj, d);
-        ok = nb >= 0 && nb != cl;
+    for (int a = 0; a < NC; ++a) rh[c][a] = 0.0;
+    if (p >= 0 && dist[c] > lo) {
+#pragma unroll
+      for (int d = 0; d < NDIR; ++d) {
+        bool ok;
+        if (pos) {
+          ok = nbr[d * cap + p] >= 0;
+        } else {
+          int ci, cj;
+          cell_ij(g, cells[c], ci, cj);
+          const int nb = neighbour(g, ci, cj, d);
+          ok = nb >= 0 && nb != cells[c];
+        }
+        v |= ok ? (1u << d) : 0u;
       }
-      v |= ok ? (1u << d) : 0u;
-    }
-    vmask[c] = p < 0 ? 0u : v;
 #pragma unroll
-    for (int a = 0; a < NC; ++a) rh[c][a] = rhs[a * cap + pp];
-    if constexpr (COEF_REG) {
+      for (int a = 0; a < NC; ++a) rh[c][a] = rhs[a * cap + p];
+      if constexpr (COEF_REG) {
 #pragma unroll
-      for (int e = 0; e < 4 * NC * NC; ++e) cf[c][e] = coef[(size_t)e * cap + pp];
+        for (int e = 0; e < 4 * NC * NC; ++e) cf[c][e] = coef[(size_t)e * cap + p];
+      }
     }
+    vmask[c] = v;
   }
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
@@ -182,9 +205,8 @@ __global__ void __launch_bounds__(NT) tile_sweep_kernel(
     if (r >= R) continue;
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
-      const double x = pidx[c] < 0 ? 0.0 : x0[c][a];
-      xs[0][a][r] = x;
-      xs[1][a][r] = x;
+      xs[0][a][r] = x0[c][a];
+      xs[1][a][r] = x0[c][a];
     }
   }
   __syncthreads();
@@ -202,20 +224,21 @@ __global__ void __launch_bounds__(NT) tile_sweep_kernel(
       if (ry == 0) v &= ~4u;
       if (ry == RH - 1) v &= ~8u;
     }
-    vmask[c] = (r < R && pidx[c] >= 0) ? v : 0u;
+    vmask[c] = v;
   }
 
-  // The sweeps, branch-free per cell so that all LDS reads of a sweep are in
-  // flight together: every direction reads an in-region value (the cell's
-  // own where the direction is off) and the update is kept by a select, so
-  // the accumulation is the compact-list sweep's, operation for operation.
+  // The sweeps, branch-free per updated cell so that all LDS reads of a
+  // sweep are in flight together: every direction reads an in-region value
+  // (the cell's own where the direction is off) and the update is kept by a
+  // select, so the accumulation is the compact-list sweep's, operation for
+  // operation.
   int cur = 0;
   for (int k = 0; k < nsw; ++k) {
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       const int r = threadIdx.x + c * NT;
-      if (r >= R) continue;
-      const int pp = pidx[c] < 0 ? 0 : pidx[c];
+      if (pidx[c] < 0 || dist[c] < lo + 1 + k) continue;
+      const int pp = pidx[c];
       double acc[NC];
 #pragma unroll
       for (int a = 0; a < NC; ++a) acc[a] = rh[c][a];
@@ -240,9 +263,8 @@ __global__ void __launch_bounds__(NT) tile_sweep_kernel(
 #pragma unroll
         for (int a = 0; a < NC; ++a) acc[a] = on ? t[a] : acc[a];
       }
-      const bool live = pidx[c] >= 0;
 #pragma unroll
-      for (int a = 0; a < NC; ++a) xs[cur ^ 1][a][r] = live ? acc[a] : 0.0;
+      for (int a = 0; a < NC; ++a) xs[cur ^ 1][a][r] = acc[a];
     }
     __syncthreads();
     cur ^= 1;
@@ -273,8 +295,8 @@ __global__ void __launch_bounds__(NT) tile_sweep_kernel(
     diff = block_max(diff, lds);
     dn = block_max(dn, lds);
     if (threadIdx.x == 0) {
-      stat_part(part, kStatDiff, diff);
-      stat_part(part, kStatDnorm, dn);
+      part[kStatDiff * kPartCap + slot] = diff;
+      part[kStatDnorm * kPartCap + slot] = dn;
     }
   }
 }
@@ -354,9 +376,9 @@ template <int NC, int TSX, int TSY, int S, bool CR, int NT = kBlock>
 static hs_status launch_tiles(hs_ctx* ctx, const hs_samples* s, int ntiles, const double* coef,
                               const double* rhs, const double* xin, double* xout, double* q, int k, bool record,
                               const NewtonCtrl& ctl = NewtonCtrl{}) {
-  HS_LAUNCH(ctx, (tile_sweep_kernel<NC, TSX, TSY, S, CR, NT>), ntiles, NT, ctx->g, s ? s->tiles : nullptr,
-            s ? ctx->sntx : ctx->ntx, s ? s->pos : nullptr, s ? s->nbr : nullptr, ctx->ncell, coef, rhs, xin,
-            xout, q, k, record ? 1 : 0, ctx->part, ctl);
+  HS_LAUNCH(ctx, (tile_sweep_kernel<NC, TSX, TSY, S, CR, NT>), (ntiles + 7) / 8 * 8, NT, ctx->g,
+            s ? s->tiles : nullptr, ntiles, s ? ctx->sntx : ctx->ntx, s ? s->pos : nullptr, s ? s->nbr : nullptr,
+            ctx->ncell, coef, rhs, xin, xout, q, k, record ? 1 : 0, ctx->part, ctl);
   return HS_OK;
 }
 

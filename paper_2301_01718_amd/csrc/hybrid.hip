@@ -660,6 +660,7 @@ struct FiltSpec {
   double* norms[2] = {nullptr, nullptr};   // r, r2
   int orders[4] = {0, 0, 0, 0};
   int pass = 0, nb = 0;                    // k; partial count of every pass
+  int first = 1;                           // host-driven pass: the first of its order (every tile computed)
   int n_orders = 0, jfmax = 0;
   double eps_f = 0.0;
   unsigned long long* stats = nullptr;     // kStatCount / kStatSum of pass k - 1
@@ -721,7 +722,11 @@ __global__ void __launch_bounds__(kBlock) filter_gate_kernel(
   const bool per = g.bc == HS_BC_PERIODIC;
   double rsum = 0.0;
   int kept = 0;
-  int cslot = kStatCount, sslot = kStatSum;
+  // Partial slots alternate with the pass index, so that a pass reads the
+  // per-tile results of the previous one while writing its own.
+  int pass = fs.pass;
+  int cslot = filt_count_slot(pass), sslot = filt_sum_slot(pass);
+  bool all = fs.first != 0;
   if (fs.ctl != nullptr) {
     // the pass the device state asks for, or none once the loop is done
     const int k = fs.pass;
@@ -774,6 +779,7 @@ __global__ void __launch_bounds__(kBlock) filter_gate_kernel(
     if (c.done) return;
     cslot = filt_count_slot(k);
     sslot = filt_sum_slot(k);
+    all = k == 0 || c.it == 0;
     nord = fs.orders[c.o];
     cur = fs.state[c.parity];
     merged = fs.state[c.parity ^ 1];
@@ -781,8 +787,44 @@ __global__ void __launch_bounds__(kBlock) filter_gate_kernel(
     r2 = fs.norms[c.parity ^ 1];
   }
 
+  // Within an order, pass k can change a cell (its state, its gate decision
+  // or its residual norm) only if a cell within the halo H changed in pass
+  // k - 1, and H is less than a tile: pass k computes only the tiles next to
+  // (or being) a tile that kept a cell in pass k - 1.  Every other tile is
+  // unchanged in both state and norm buffers (by induction over the passes;
+  // the first pass of an order computes every tile) and carries its
+  // residual-sum partial forward, the sum of the same values in the same
+  // order.  One tile per workgroup is needed for the per-tile partials.
+  const bool track = !all && (int)gridDim.x == ntiles;
+  bool carried = false;
+  double carry_sum = 0.0;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int X0 = (tile % ntx) * TX, Y0 = ONE_D ? 0 : (tile / ntx) * TY;
+    if (track) {
+      // thread i < 9 reads neighbour tile i's kept count of pass k - 1
+      int hit = 0;
+      if (threadIdx.x < (ONE_D ? 3 : 9)) {
+        const int tx = tile % ntx, ty = tile / ntx, nty = ntiles / ntx;
+        int ux = tx + (int)(threadIdx.x % 3) - 1, uy = ONE_D ? 0 : ty + (int)(threadIdx.x / 3) - 1;
+        if (per) {
+          ux = (ux + ntx) % ntx;
+          uy = (uy + nty) % nty;
+        }
+        if (ux >= 0 && ux < ntx && uy >= 0 && uy < nty)
+          hit = part[filt_count_slot(pass - 1) * kPartCap + uy * ntx + ux] > 0.0;
+      }
+      if (!__syncthreads_or(hit)) {
+        carried = true;
+        carry_sum = part[filt_sum_slot(pass - 1) * kPartCap + tile];
+        if (keep_out) {
+          for (int p = threadIdx.x; p < TX * TY; p += kBlock) {
+            const int ux = X0 + p % TX, uy = Y0 + p / TX;
+            if (ux < g.nx && uy < g.ny) keep_out[ux + g.nx * uy] = 0;
+          }
+        }
+        continue;
+      }
+    }
     // A: the current state, wrapped or clamped
     for (int p = threadIdx.x; p < RA; p += kBlock) {
       const int ax = p % AW, ay = p / AW;
@@ -866,6 +908,13 @@ __global__ void __launch_bounds__(kBlock) filter_gate_kernel(
     }
     __syncthreads();
   }
+  if (carried) {
+    if (threadIdx.x == 0) {
+      stat_part(part, sslot, carry_sum);
+      stat_part(part, cslot, 0.0);
+    }
+    return;
+  }
   const double bs = block_sum(rsum, lds);
   const int bk = block_sum_int(kept, reinterpret_cast<int*>(lds));
   if (threadIdx.x == 0) {
@@ -926,20 +975,32 @@ static hs_status filter_gate_launch(hs_ctx* ctx, const double* cur, const double
   else
     HS_LAUNCH(ctx, (filter_gate_kernel<4, 16, 16>), nb, kBlock, ctx->g, ntx, ntiles, nord, cur, q_prev, r, merged,
               r2, keep_out, ctx->part, f);
-  // reads: the state, q_prev and r once; writes: merged, r2 and the decisions
+  // a full pass reads the state, q_prev and r once and writes merged, r2 and
+  // the decisions; a later pass of an order computes only the tiles near the
+  // previous pass's changes (decided on the device), counted as no bytes
+  const bool full = fs.ctl ? fs.pass == 0 : fs.first != 0;
   HS_TRY(prof_end(ctx, HS_PROF_FILTER,
-                  (double)ctx->ncell * (8.0 * ctx->nc * 3 + 8.0 * 2 + (keep_out ? 1.0 : 0.0))));
+                  full ? (double)ctx->ncell * (8.0 * ctx->nc * 3 + 8.0 * 2 + (keep_out ? 1.0 : 0.0)) : 0.0));
   *nb_out = nb;
   return HS_OK;
 }
 
-// One host-driven gated pass: merged (the next state), r2, keep_out; the kept
-// count and the sum of r2 come back in st (kStatCount / kStatSum).
+// One host-driven gated pass (index pass within the step, first: the first of
+// its order): merged (the next state), r2, keep_out; the kept count and the
+// sum of r2 come back in *kept, *sum (st: every statistics slot).
 static hs_status filter_pass(hs_ctx* ctx, const double* cur, const double* q_prev, const double* r, int nord,
-                             double* merged, double* r2, uint8_t* keep_out, unsigned long long* st) {
+                             double* merged, double* r2, uint8_t* keep_out, int pass, bool first,
+                             unsigned long long* st, long long* kept, double* sum) {
   int nb;
-  HS_TRY(filter_gate_launch(ctx, cur, q_prev, r, nord, merged, r2, keep_out, FiltSpec{}, &nb));
-  return finish_stats(ctx, nb, 0u, (1u << kStatCount) | (1u << kStatSum), st);
+  FiltSpec fs;
+  fs.pass = pass;
+  fs.first = first ? 1 : 0;
+  HS_TRY(filter_gate_launch(ctx, cur, q_prev, r, nord, merged, r2, keep_out, fs, &nb));
+  const int cs = filt_count_slot(pass), ss = filt_sum_slot(pass);
+  HS_TRY(finish_stats(ctx, nb, 0u, (1u << cs) | (1u << ss), st));
+  *kept = (long long)bits_to_double(st[cs]);
+  *sum = bits_to_double(st[ss]);
+  return HS_OK;
 }
 
 // Cell residual norms of q to rcell; their l1 sum is left as *nb block
@@ -1064,18 +1125,20 @@ hs_status run_filter(hs_ctx* ctx, double* gamma, const double* q_prev, const hs_
   bool have_sum = false;
   double sum_r = 0.0;
   if (hp->n_orders > 0 && hp->jfmax > 0) HS_TRY(cell_residual_launch(ctx, cur, q_prev, r, kStatSum0));
+  int pass = 0;
   for (int o = 0; o < hp->n_orders; ++o) {
     const int nord = hp->filter_orders[o];
     for (int it = 1; it <= hp->jfmax; ++it) {
       uint8_t* keep_out = record ? record->masks + (size_t)record->npass * ctx->ncell : nullptr;
       unsigned long long st[kStatSlots];
-      HS_TRY(filter_pass(ctx, cur, q_prev, r, nord, spare, r2, keep_out, st));
+      long long kept;
+      double sum_new;
+      HS_TRY(filter_pass(ctx, cur, q_prev, r, nord, spare, r2, keep_out, pass, it == 1, st, &kept, &sum_new));
+      ++pass;
       if (!have_sum) {
         sum_r = bits_to_double(st[kStatSum0]);
         have_sum = true;
       }
-      const long long kept = (long long)bits_to_double(st[kStatCount]);
-      const double sum_new = bits_to_double(st[kStatSum]);
       if (info) {
         info->filter_passes += 1;
         info->filter_kept += (int)kept;

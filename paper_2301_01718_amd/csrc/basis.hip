@@ -293,7 +293,7 @@ __device__ inline double wave_argmax(double v, int id, int& arg) {
 // the block (256 threads) calls it; buf holds 2 * kMaxBasis doubles of LDS.
 __device__ __forceinline__ void block_pivoted_cholesky(double* A, int lda, int w, double tol, double* L,
                                                        double* buf, int* perm, int* rank) {
-  const int t = threadIdx.x, nt = blockDim.x;
+  const int t = threadIdx.x;
   __shared__ int s_piv, s_done[kMaxBasis];
   __shared__ double s_best;
   if (t < kMaxBasis) s_done[t] = t >= w;

@@ -98,11 +98,14 @@ def kernel_rates(ctx, q, q_prev, reps=3):
     residual kernel classes on the full mesh: hs_residual, the residual +
     Jacobian data of a full Newton step, and the fused filter pass."""
     import torch
+    from paper_2301_01718_amd._lib import hybrid_params
     out = {}
     R = ctx.empty()
     jobs = {"residual": lambda: ctx.residual(q, q_prev, out=R),
             "resjac": lambda: ctx.hdm_step(q_prev, out=R),
-            "filter": lambda: ctx.filter(q, q_prev, out=R)}
+            # one pass per order: every pass is a full pass (a later pass of an
+            # order computes only the tiles near the previous pass's changes)
+            "filter": lambda: ctx.filter(q, q_prev, params=hybrid_params(jfmax=1), out=R)}
     for cls, fn in jobs.items():
         fn()
         torch.cuda.synchronize(ctx.device)

@@ -977,8 +977,9 @@ static hs_status filter_gate_launch(hs_ctx* ctx, const double* cur, const double
               r2, keep_out, ctx->part, f);
   // a full pass reads the state, q_prev and r once and writes merged, r2 and
   // the decisions; a later pass of an order computes only the tiles near the
-  // previous pass's changes (decided on the device), counted as no bytes
-  const bool full = fs.ctl ? fs.pass == 0 : fs.first != 0;
+  // previous pass's changes (decided on the device), counted as no bytes (with
+  // one pass per order every pass is the first of its order)
+  const bool full = fs.ctl ? (fs.pass == 0 || fs.jfmax == 1) : fs.first != 0;
   HS_TRY(prof_end(ctx, HS_PROF_FILTER,
                   full ? (double)ctx->ncell * (8.0 * ctx->nc * 3 + 8.0 * 2 + (keep_out ? 1.0 : 0.0)) : 0.0));
   *nb_out = nb;

@@ -20,6 +20,15 @@ With those frozen, each step is a smooth map of its input gamma_{k-1}:
 Tangents (forward mode) and adjoints (reverse mode) are written separately so
 that the dot-product test <T v, w> = <v, T^T w> checks the transposition.
 The loss is L = 0.5 ||u_T - u_target||^2.
+
+With ``psi_live`` the reference states are differentiated too: psi_k is the
+mean of the w snapshots that eq. mean averages (for the basis update after
+step k', the last w of its window, gamma_{k'-w+1} .. gamma_{k'}), a linear
+map of those snapshots, so a hybrid step's adjoint with respect to its psi
+(lambda_psi) returns lambda_psi / w to each of them.  The step is linear in
+psi: the ring values t_{j+1} = psi_T + Phi_T y_j, the fit
+y_j = A^+ (v_j - psi_S) and the reconstruction psi + Phi y_J off the sampled
+cells.  Only the bases stay frozen.
 """
 from __future__ import annotations
 
@@ -56,8 +65,8 @@ def forward_with_tape(prob: Problem, q0, steps, p: AromParams, keep_norms=False)
             g = out["gamma"]
             eps = out["eps"]
             tape.append({"type": "hybrid", "hat": samples["hat"], "tilde": samples["tilde"],
-                         "Phi": basis[0], "psi": basis[1], "J": out["J"], "us": out["us"],
-                         "masks": out["masks"], "out": g, "norms": norms})
+                         "Phi": basis[0], "psi": basis[1], "psi_idx": basis[2], "J": out["J"],
+                         "us": out["us"], "masks": out["masks"], "out": g, "norms": norms})
         else:
             g, _ = fv.hdm_step(prob, prev)
             tape.append({"type": "full", "out": g})
@@ -70,7 +79,8 @@ def forward_with_tape(prob: Problem, q0, steps, p: AromParams, keep_norms=False)
                 samples = sampling.select(prob, eps, p.rule, p.fraction, p.delta, p.halo)
             window = gammas[k - p.w:k + 1] if k >= p.w else gammas[0:k + 1]
             b = pod.pod(window, p.w, p.m, p.tau_pod)
-            basis = (b["Phi"], b["psi_new"])
+            # psi_new is the mean of the window's last w snapshots
+            basis = (b["Phi"], b["psi_new"], list(range(k - p.w + 1, k + 1)))
     return gammas[-1], tape
 
 
@@ -94,13 +104,20 @@ def replay_hybrid(prob: Problem, q_prev, st, params: HybridParams, states=False)
     return (g, us) if states else g
 
 
-def replay(prob: Problem, q0, tape, params: HybridParams):
+def replay(prob: Problem, q0, tape, params: HybridParams, psi_live=False):
+    """The frozen trajectory from q0.  With psi_live each hybrid step's psi is
+    the plain mean of its snapshots of this run (the map whose derivative
+    gradient(..., psi_live=True) takes); otherwise the recorded psi."""
     q = q0.copy()
+    states = [q]
     for st in tape:
         if st["type"] == "full":
             q, _ = fv.hdm_step(prob, q)
         else:
+            if psi_live:
+                st = dict(st, psi=sum(states[j] for j in st["psi_idx"]) / len(st["psi_idx"]))
             q = replay_hybrid(prob, q, st, params)
+        states.append(q)
     return q
 
 
@@ -236,6 +253,60 @@ def hybrid_step_adjoint(prob: Problem, st, lam, params: HybridParams):
     return pbar
 
 
+def hybrid_step_tangent_psi(prob: Problem, st, dpsi, params: HybridParams):
+    """Derivative of the frozen hybrid step's output with respect to its psi
+    (gamma_{k-1} fixed), applied to dpsi."""
+    Phi = st["Phi"]
+    hd = fv.dofs_of_cells(prob, st["hat"])
+    td = fv.dofs_of_cells(prob, st["tilde"])
+    Ap = _pinv(st, hd, params)
+    dt = np.zeros(td.size)                    # t_1 = gamma_{k-1} on the ring: no psi
+    for j in range(st["J"]):
+        Jh, Jt, _, _ = _split_jacobian(prob, st["us"][j], st["hat"], st["tilde"])
+        dv = spla.spsolve(Jh, -(Jt @ dt)) if Jt is not None else np.zeros(hd.size)
+        dy = Ap @ (dv - dpsi[hd])
+        dt = dpsi[td] + Phi[td] @ dy
+    g = dpsi + Phi @ dy
+    g[hd] = dv
+    for n, keep in st["masks"]:
+        g = np.where(np.tile(keep, prob.ncomp), shapiro(prob, g, n), g)
+    return g
+
+
+def hybrid_step_adjoint_psi(prob: Problem, st, lam, params: HybridParams):
+    """(gamma_{k-1} adjoint, psi adjoint) of the frozen hybrid step: the
+    transpose of hybrid_step_tangent and of hybrid_step_tangent_psi."""
+    Phi = st["Phi"]
+    N = prob.n
+    hd = fv.dofs_of_cells(prob, st["hat"])
+    td = fv.dofs_of_cells(prob, st["tilde"])
+    Ap = _pinv(st, hd, params)
+    g = lam.copy()
+    for n, keep in reversed(st["masks"]):
+        km = np.tile(keep, prob.ncomp)
+        g = shapiro_T(prob, np.where(km, g, 0.0), n) + np.where(km, 0.0, g)
+    breve = np.ones(N, bool)
+    breve[hd] = False
+    psibar = np.where(breve, g, 0.0)            # reconstruction psi + Phi y off the sampled cells
+    ybar = Phi[breve].T @ g[breve]
+    vbar = g[hd].copy()
+    tbar_next = np.zeros(td.size)
+    pbar = np.zeros(N)
+    for j in reversed(range(st["J"])):
+        if j < st["J"] - 1:
+            psibar[td] += tbar_next               # t_{j+1} = psi_T + Phi_T y_j
+        ybar_j = (ybar if j == st["J"] - 1 else 0.0) + Phi[td].T @ tbar_next
+        w_j = Ap.T @ ybar_j                       # y_j = A^+ (v_j - psi_S)
+        psibar[hd] -= w_j
+        vbar_j = (vbar if j == st["J"] - 1 else 0.0) + w_j
+        Jh, Jt, _, _ = _split_jacobian(prob, st["us"][j], st["hat"], st["tilde"])
+        mu = spla.spsolve(Jh.T.tocsc(), vbar_j)
+        pbar[hd] += mu
+        tbar_next = -(Jt.T @ mu) if Jt is not None else np.zeros(0)
+    pbar[td] += tbar_next                         # t_1 = gamma_{k-1} on the ring
+    return pbar, psibar
+
+
 def step_adjoint(prob: Problem, st, lam, params: HybridParams):
     if st["type"] == "full":
         return full_step_adjoint(prob, st["out"], lam)
@@ -248,11 +319,32 @@ def step_tangent(prob: Problem, st, d, params: HybridParams):
     return hybrid_step_tangent(prob, st, d, params)
 
 
-def gradient(prob: Problem, tape, qT, target, params: HybridParams):
-    """dL/du_0 for L = 0.5 ||u_T - u_target||^2 through the frozen trajectory."""
-    lam = qT - target
-    for st in reversed(tape):
-        lam = step_adjoint(prob, st, lam, params)
+def gradient(prob: Problem, tape, qT, target, params: HybridParams, psi_live=False):
+    """dL/du_0 for L = 0.5 ||u_T - u_target||^2 through the frozen trajectory
+    (with psi_live also through each hybrid step's reference state)."""
+    return backward(prob, tape, qT - target, params, psi_live)
+
+
+def backward(prob: Problem, tape, lam_T, params: HybridParams, psi_live=False):
+    """(d gamma_T / d gamma_0)^T lam_T through the frozen trajectory.  With
+    psi_live, the psi adjoint of the hybrid step that ends in gamma_k is held
+    until the backward pass reaches each snapshot its psi averages, and
+    added there with weight 1/w."""
+    lam = lam_T.copy()
+    pending = {}                                  # snapshot index -> accumulated psi contributions
+    for k in range(len(tape), 0, -1):
+        if k in pending:
+            lam = lam + pending.pop(k)
+        st = tape[k - 1]
+        if st["type"] == "full" or not psi_live:
+            lam = step_adjoint(prob, st, lam, params)
+            continue
+        lam, psibar = hybrid_step_adjoint_psi(prob, st, lam, params)
+        share = psibar / len(st["psi_idx"])
+        for j in st["psi_idx"]:
+            pending[j] = pending[j] + share if j in pending else share.copy()
+    if 0 in pending:
+        lam = lam + pending.pop(0)
     return lam
 
 

@@ -98,3 +98,69 @@ def test_trajectory_gradient_central_differences(taped):
         fd = (Lp - Lm) / (2 * h)
         gd = g @ d
         assert abs(gd - fd) <= 1e-6 * max(abs(gd), 1e-8 * np.linalg.norm(g) * np.linalg.norm(d)), (gd, fd)
+
+
+# ---------------------------------------------------------------- through psi
+def test_hybrid_psi_adjoint_dot_product(taped):
+    """The psi-adjoint of a hybrid step is the transpose of its psi-tangent,
+    and its gamma_{k-1} part equals the frozen-psi adjoint bit for bit."""
+    wl, prob, q0, p, qT, tape = taped
+    st = next(s for s in tape if s["type"] == "hybrid")
+    rng = np.random.default_rng(5)
+    dpsi = rng.standard_normal(prob.n)
+    w = rng.standard_normal(prob.n)
+    Td = A.hybrid_step_tangent_psi(prob, st, dpsi, p.hybrid)
+    pbar, psibar = A.hybrid_step_adjoint_psi(prob, st, w, p.hybrid)
+    lhs, rhs = Td @ w, dpsi @ psibar
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), np.linalg.norm(Td) * np.linalg.norm(w))
+    assert np.array_equal(pbar, A.hybrid_step_adjoint(prob, st, w, p.hybrid))
+
+
+def test_hybrid_psi_tangent_matches_finite_difference(taped):
+    wl, prob, q0, p, qT, tape = taped
+    k = next(i for i, s in enumerate(tape) if s["type"] == "hybrid")
+    st = tape[k]
+    q_prev = A.replay(prob, q0, tape[:k], p.hybrid)
+    d = np.random.default_rng(3).standard_normal(prob.n)
+    h = 1e-6
+    fd = (A.replay_hybrid(prob, q_prev, dict(st, psi=st["psi"] + h * d), p.hybrid)
+          - A.replay_hybrid(prob, q_prev, dict(st, psi=st["psi"] - h * d), p.hybrid)) / (2 * h)
+    t = A.hybrid_step_tangent_psi(prob, st, d, p.hybrid)
+    assert np.linalg.norm(fd - t) <= 1e-6 * np.linalg.norm(t)
+
+
+def test_psi_indices_are_the_means_snapshots(taped):
+    """Each hybrid step's psi is the plain mean of the snapshots it lists
+    (the last w of its basis update's window, eq. mean)."""
+    wl, prob, q0, p, qT, tape = taped
+    states = [q0]
+    for st in tape:
+        states.append(st["out"])
+    for st in tape:
+        if st["type"] != "hybrid":
+            continue
+        idx = st["psi_idx"]
+        assert len(idx) == wl.w and idx == list(range(idx[0], idx[0] + wl.w))
+        mean = sum(states[j] for j in idx) / wl.w
+        assert np.max(np.abs(mean - st["psi"])) <= 1e-14 * np.max(np.abs(mean))
+
+
+def test_trajectory_gradient_through_psi_central_differences(taped):
+    """With psi_live the gradient is that of the trajectory whose reference
+    states are recomputed from the perturbed run (bases and decisions
+    frozen); the psi path is not negligible: the frozen-psi gradient misses
+    these differences."""
+    wl, prob, q0, p, qT, tape = taped
+    target = fv.hdm_step(prob, q0 * 1.01)[0]
+    g = A.gradient(prob, tape, qT, target, p.hybrid, psi_live=True)
+    g0 = A.gradient(prob, tape, qT, target, p.hybrid)
+    assert np.linalg.norm(g - g0) > 1e-4 * np.linalg.norm(g)
+    rng = np.random.default_rng(13)
+    h = 1e-6
+    for _ in range(16):
+        d = rng.standard_normal(prob.n)
+        Lp = A.loss(A.replay(prob, q0 + h * d, tape, p.hybrid, psi_live=True), target)
+        Lm = A.loss(A.replay(prob, q0 - h * d, tape, p.hybrid, psi_live=True), target)
+        fd = (Lp - Lm) / (2 * h)
+        gd = g @ d
+        assert abs(gd - fd) <= 1e-6 * max(abs(gd), 1e-8 * np.linalg.norm(g) * np.linalg.norm(d)), (gd, fd)

@@ -311,6 +311,16 @@ hs_status hdm_step_adjoint(hs_ctx* ctx, const double* q_out, const double* lam_i
  * a transposed restricted Newton-matrix solve and the coupling to the ring. */
 hs_status rom_hybrid_step_adjoint(hs_ctx* ctx, const double* Phi, int32_t m, const hs_htape* tape,
                                   const double* lam_in, double* lam_out, hs_step_info* info /* host */);
+/* The same adjoint, and with lam_psi (device, N; nullptr: not formed) also
+ * (d gamma_k / d psi_k)^T lam_in, the adjoint with respect to the step's
+ * reference state (eq. mean): the step is linear in psi, which enters the
+ * ring values psi + Phi y of every subiteration, the fit
+ * (P^T Phi)^+ P^T (v - psi) (eq. red_coord) and the reconstruction psi + Phi y
+ * off the sampled cells (eq. rom_approx).  lam_psi must not alias lam_in or
+ * lam_out. */
+hs_status rom_hybrid_step_adjoint_psi(hs_ctx* ctx, const double* Phi, int32_t m, const hs_htape* tape,
+                                      const double* lam_in, double* lam_out, double* lam_psi,
+                                      hs_step_info* info /* host */);
 
 /* -------------------------------------------- trajectory and its adjoint */
 /* A whole run of Algorithm 1 and the frozen-decision adjoint of its map
@@ -330,6 +340,8 @@ typedef struct hs_traj_params {
   double  tau_pod;            /* POD cut (1e-8) */
   hs_sample_params sample;    /* selection rule, fraction / delta, halo */
   hs_hybrid_params hybrid;    /* hybrid step parameters; precision must be HS_FP64 */
+  int32_t psi_adjoint;        /* hs_traj_backward: 0: psi_k frozen like the bases; 1: also through
+                                 psi_k, the mean of the w snapshots its basis update averages (eq. mean) */
 } hs_traj_params;
 /* Library-owned record of one forward run: per step its kind, the basis it
  * used and its hybrid-step tape; every basis; the checkpoints.  Its device

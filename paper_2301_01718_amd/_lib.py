@@ -68,7 +68,7 @@ class HybridParams(ctypes.Structure):
 class TrajParams(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int32), ("checkpoint_every", ctypes.c_int32), ("w", ctypes.c_int32),
                 ("m", ctypes.c_int32), ("z", ctypes.c_int32), ("tau_pod", ctypes.c_double),
-                ("sample", SampleParams), ("hybrid", HybridParams)]
+                ("sample", SampleParams), ("hybrid", HybridParams), ("psi_adjoint", ctypes.c_int32)]
 
 
 def hybrid_params(eps_y=1e-4, jmax=10, filter_orders=(1, 2, 3), eps_f=1e-2, jfmax=10,
@@ -119,6 +119,7 @@ _SIGS = {
                               ctypes.POINTER(StepInfo), P, I32],
     "hdm_step_adjoint": [P, P, P, P, ctypes.POINTER(StepInfo)],
     "rom_hybrid_step_adjoint": [P, P, I32, P, P, P, ctypes.POINTER(StepInfo)],
+    "rom_hybrid_step_adjoint_psi": [P, P, I32, P, P, P, P, ctypes.POINTER(StepInfo)],
     "hs_tape_create": [P, ctypes.POINTER(P)],
     "hs_tape_destroy": [P],
     "hs_traj_forward": [P, P, ctypes.POINTER(TrajParams), P, P],
@@ -439,6 +440,17 @@ class Context:
         self._check(lib().rom_hybrid_step_adjoint(self.h, _ptr(Phi), m, tape.h, _ptr(self._in(lam)),
                                                   _ptr(self._in(out)), ctypes.byref(info)))
         return out, info.as_dict()
+
+    def rom_hybrid_step_adjoint_psi(self, Phi, m, tape, lam, out=None, lam_psi=None):
+        """(lambda_{k-1}, lambda_psi, info): the step adjoint and its part with
+        respect to the step's reference state psi."""
+        out = self.empty() if out is None else out
+        lam_psi = self.empty() if lam_psi is None else lam_psi
+        info = StepInfo()
+        self._check(lib().rom_hybrid_step_adjoint_psi(self.h, _ptr(Phi), m, tape.h, _ptr(self._in(lam)),
+                                                      _ptr(self._in(out)), _ptr(self._in(lam_psi)),
+                                                      ctypes.byref(info)))
+        return out, lam_psi, info.as_dict()
 
 
 class Tape:

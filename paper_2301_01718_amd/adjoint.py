@@ -26,9 +26,10 @@ from ._lib import (FP64, TAPE_REPLAY, Context, SampleParams, TrajParams, TrajTap
 from .driver import AromConfig
 
 
-def traj_params(cfg: AromConfig, steps: int, K: int) -> TrajParams:
+def traj_params(cfg: AromConfig, steps: int, K: int, psi_adjoint: bool = False) -> TrajParams:
     tp = TrajParams()
     tp.steps, tp.checkpoint_every, tp.w, tp.m, tp.z = steps, K, cfg.w, cfg.m, cfg.z
+    tp.psi_adjoint = 1 if psi_adjoint else 0
     tp.tau_pod = cfg.tau_pod
     tp.sample = SampleParams(rule=cfg.rule, fraction=cfg.fraction, delta=cfg.delta, halo=cfg.halo)
     tp.hybrid = hybrid_params(cfg.eps_y, cfg.jmax, cfg.filter_orders, cfg.eps_f, cfg.jfmax, cfg.rcond_fit,
@@ -52,13 +53,15 @@ class Trajectory:
 
     ``forward(q0)`` runs it (hs_traj_forward) and records the frozen
     decisions; ``backward(lam)`` returns (d gamma_T / d gamma_0)^T lam for
-    the last forward run (hs_traj_backward).  After a forward run, ``kinds``
+    the last forward run (hs_traj_backward; with ``psi_adjoint`` also through
+    each hybrid step's reference state, the mean of the snapshots its basis
+    update averaged, only the bases frozen).  After a forward run, ``kinds``
     (step -> ("full"|"hybrid", basis index)), ``bases`` (index -> (Phi,
     psi, m), copied on first use), ``tapes`` (step -> hybrid-step tape) and
     ``ckpt`` (checkpoint step -> state) expose the recorded run."""
 
     def __init__(self, prob, cfg: AromConfig, steps: int, checkpoint_every: int = 10, device="cuda",
-                 ctx=None):
+                 ctx=None, psi_adjoint: bool = False):
         if checkpoint_every < 1:
             raise ValueError("checkpoint_every must be >= 1")
         if cfg.precision != FP64:
@@ -68,7 +71,7 @@ class Trajectory:
         self.steps = steps
         self.K = checkpoint_every
         self.ctx = ctx or Context(prob, m_max=cfg.m, w_max=cfg.w, device=device)
-        self.params = traj_params(cfg, steps, checkpoint_every)
+        self.params = traj_params(cfg, steps, checkpoint_every, psi_adjoint)
         self.hp = self.params.hybrid
         self.tape = TrajTape(self.ctx)
         self.recorder = _Tapes(self)

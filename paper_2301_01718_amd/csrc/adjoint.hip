@@ -322,6 +322,22 @@ __global__ void scatter_add_kernel(int nc, int ncell, const int* __restrict__ li
   v[a * ncell + list[p]] += x[a * ncell + p];
 }
 
+// v[dof] -= x[a * cap + p] on the listed cells; out[i] = g[i] off the cells
+// flagged in mask, 0 on them.
+__global__ void scatter_sub_kernel(int nc, int ncell, const int* __restrict__ list, int count,
+                                   const double* __restrict__ x, double* __restrict__ v) {
+  const long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (k >= (long long)nc * count) return;
+  const long long a = k / count, p = k % count;
+  v[a * ncell + list[p]] -= x[a * ncell + p];
+}
+
+__global__ void unmasked_copy_kernel(long long n, int ncell, const uint8_t* __restrict__ mask,
+                                     const double* __restrict__ g, double* __restrict__ out) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = mask[i % ncell] ? 0.0 : g[i];
+}
+
 __global__ void zero_kernel(double* __restrict__ x, long long n) {
   const long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (k < n) x[k] = 0.0;
@@ -387,9 +403,10 @@ hs_status hdm_step_adjoint(hs_ctx* ctx, const double* q_out, const double* lam_i
   return hs_sync(ctx);
 }
 
-hs_status rom_hybrid_step_adjoint(hs_ctx* ctx, const double* Phi, int32_t m, const hs_htape* tape,
-                                  const double* lam_in, double* lam_out, hs_step_info* info) {
+hs_status rom_hybrid_step_adjoint_psi(hs_ctx* ctx, const double* Phi, int32_t m, const hs_htape* tape,
+                                      const double* lam_in, double* lam_out, double* lam_psi, hs_step_info* info) {
   if (!ctx || !Phi || !tape || !lam_in || !lam_out || tape->ctx != ctx) return HS_ERR_INVALID_ARG;
+  if (lam_psi && (lam_psi == lam_in || lam_psi == lam_out)) return HS_ERR_INVALID_ARG;
   if (!tape->replayed) return ctx->fail(HS_ERR_INVALID_ARG, "adjoint needs a replayed tape");
   if (m != tape->m) return ctx->fail(HS_ERR_INVALID_ARG, "basis size differs from the replayed step");
   if (tape->precision != HS_FP64) return ctx->fail(HS_ERR_INVALID_ARG, "adjoint needs an FP64 basis");
@@ -428,17 +445,24 @@ hs_status rom_hybrid_step_adjoint(hs_ctx* ctx, const double* Phi, int32_t m, con
   double* mu = ctx->rho;                // compact over hat-S
   double* sm = ctx->small;
 
-  // (2) reconstruction transpose: y-bar = Phi^T g off hat-S; v-bar = g on hat-S
+  // (2) reconstruction transpose: y-bar = Phi^T g off hat-S; v-bar = g on hat-S;
+  // psi-bar = g off hat-S (psi + Phi y there)
   HS_TRY(project(ctx, Phi, m, nullptr, 0, s->mask, g, nullptr, sm + kSmAdjY0, nullptr, nullptr));
   HS_LAUNCH(ctx, gather_kernel, blocks_for((long long)nc * s->n_s), kBlock, nc, ncell, s->hat, s->n_s,
             (const double*)g, vbar0);
   HS_LAUNCH(ctx, zero_kernel, nbN, kBlock, lam_out, N);
+  if (lam_psi) HS_LAUNCH(ctx, unmasked_copy_kernel, nbN, kBlock, N, ncell, (const uint8_t*)s->mask, (const double*)g,
+                         lam_psi);
 
   // (3) subiterations in reverse
   int sweeps = 0;
   for (int j = tape->J - 1; j >= 0; --j) {
     const bool last = j == tape->J - 1;
     const double* uj = tape->us + (size_t)j * N;
+    // t_{j+1} = psi on the ring + Phi y_j: its adjoint also goes to psi-bar
+    if (lam_psi && !last && s->l > 0)
+      HS_LAUNCH(ctx, scatter_add_kernel, blocks_for((long long)nc * s->l), kBlock, nc, ncell, s->tilde, s->l,
+                (const double*)tbar, lam_psi);
     if (last)
       HS_LAUNCH(ctx, adj_project_finish_kernel, 1, 256, sm + kSmAdjY0, 1, 64, m, (const double*)nullptr,
                 sm + kSmAdjY, (const double*)tape->gp, sm + kSmAdjZ);
@@ -446,6 +470,13 @@ hs_status rom_hybrid_step_adjoint(hs_ctx* ctx, const double* Phi, int32_t m, con
       HS_TRY(project(ctx, Phi, m, s->tilde, s->l, nullptr, tbar, nullptr, sm + kSmAdjY, tape->gp, sm + kSmAdjZ));
     HS_LAUNCH(ctx, adj_expand_kernel, blocks_for((long long)nc * s->n_s), kBlock, Phi, N, m, nc, ncell, s->hat,
               s->n_s, (const double*)(sm + kSmAdjZ), last ? (const double*)vbar0 : (const double*)nullptr, vbar);
+    if (lam_psi) {
+      // y_j = A^+ (v_j - psi on hat-S): psi-bar -= (A^+)^T y-bar = Phi_S z there
+      HS_LAUNCH(ctx, adj_expand_kernel, blocks_for((long long)nc * s->n_s), kBlock, Phi, N, m, nc, ncell, s->hat,
+                s->n_s, (const double*)(sm + kSmAdjZ), (const double*)nullptr, ctx->R);
+      HS_LAUNCH(ctx, scatter_sub_kernel, blocks_for((long long)nc * s->n_s), kBlock, nc, ncell, s->hat, s->n_s,
+                (const double*)ctx->R, lam_psi);
+    }
     HS_TRY(transposed_solve(ctx, uj, s, vbar, mu, &sweeps));
     HS_LAUNCH(ctx, scatter_add_kernel, blocks_for((long long)nc * s->n_s), kBlock, nc, ncell, s->hat, s->n_s,
               (const double*)mu, lam_out);
@@ -468,6 +499,11 @@ hs_status rom_hybrid_step_adjoint(hs_ctx* ctx, const double* Phi, int32_t m, con
     info->l = s->l;
   }
   return hs_sync(ctx);
+}
+
+hs_status rom_hybrid_step_adjoint(hs_ctx* ctx, const double* Phi, int32_t m, const hs_htape* tape,
+                                  const double* lam_in, double* lam_out, hs_step_info* info) {
+  return rom_hybrid_step_adjoint_psi(ctx, Phi, m, tape, lam_in, lam_out, nullptr, info);
 }
 
 }  // extern "C"

@@ -39,6 +39,18 @@ __global__ void zero_int_kernel(int* p) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
 }
 
+// y += x; and y = x / w (acc == 0) or y += x / w (acc == 1): the share of a
+// psi adjoint that goes to one of the w snapshots psi averages.
+__global__ void axpy_kernel(long long n, const double* __restrict__ x, double* __restrict__ y) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] += x[i];
+}
+
+__global__ void share_kernel(long long n, const double* __restrict__ x, double w, double* __restrict__ y, int acc) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] = acc ? y[i] + x[i] / w : x[i] / w;
+}
+
 }  // namespace hs
 
 struct hs_tape {
@@ -54,6 +66,7 @@ struct hs_tape {
     double* Phi = nullptr;
     double* psi = nullptr;
     int m = 0;
+    int k_update = 0;              // the step the update followed: psi averages gamma_{k-w+1} .. gamma_k
   };
   std::vector<Basis> bases;        // one per basis update
   std::vector<int> kind;           // per step 1..steps (index k): 0 full, 1 hybrid
@@ -62,6 +75,8 @@ struct hs_tape {
   std::map<int, double*> ckpt;     // checkpoints (step -> state)
   std::vector<double*> seg;        // K + 1 segment states (backward)
   double* lam[2] = {nullptr, nullptr};
+  double* lam_psi = nullptr;       // a hybrid step's psi adjoint (backward through psi)
+  std::vector<double*> pool;       // spare N-vectors for the pending psi contributions
 };
 
 namespace hs {
@@ -78,6 +93,10 @@ static void tape_release_run(hs_tape* t) {
   for (auto& kv : t->ckpt) (void)hipFree(kv.second);
   t->ckpt.clear();
   for (double* s : t->seg) (void)hipFree(s);
+  for (double* s : t->pool) (void)hipFree(s);
+  t->pool.clear();
+  if (t->lam_psi) (void)hipFree(t->lam_psi);
+  t->lam_psi = nullptr;
   t->seg.clear();
   t->kind.clear();
   t->bver.clear();
@@ -106,6 +125,7 @@ static hs_status check_params(hs_ctx* ctx, const hs_traj_params* p) {
   if (p->w < 2 || p->w > ctx->p.w_max || p->m < 1 || p->m > ctx->p.m_max || p->m > p->w) return HS_ERR_INVALID_ARG;
   if (p->hybrid.precision != HS_FP64)
     return ctx->fail(HS_ERR_INVALID_ARG, "the trajectory adjoint runs on an FP64 basis");
+  if (p->psi_adjoint != 0 && p->psi_adjoint != 1) return HS_ERR_INVALID_ARG;
   return HS_OK;
 }
 
@@ -208,6 +228,7 @@ hs_status hs_traj_forward(hs_ctx* ctx, const double* q0, const hs_traj_params* p
       std::vector<const double*> win;
       for (int j = lo; j <= k; ++j) win.push_back(slot(j));
       hs_tape::Basis nb;
+      nb.k_update = k;
       HS_TRY(dalloc(ctx, (void**)&nb.Phi, (size_t)n * p.m * 8));
       HS_TRY(dalloc(ctx, (void**)&nb.psi, (size_t)n * 8));
       t->bases.push_back(nb);
@@ -244,6 +265,28 @@ hs_status hs_traj_backward(hs_ctx* ctx, hs_tape* t, const double* lam_T, double*
   double* lam = t->lam[0];
   double* lam2 = t->lam[1];
   HS_TRY(dcopy(ctx, lam, lam_T, n));
+  // through psi: a hybrid step's psi adjoint is held, divided by w, for each
+  // snapshot its psi averages, and added to that snapshot's adjoint when the
+  // backward pass reaches it (snapshot index -> accumulated contribution)
+  const bool through_psi = p.psi_adjoint != 0;
+  std::map<int, double*> pending;
+  if (through_psi && !t->lam_psi) HS_TRY(dalloc(ctx, (void**)&t->lam_psi, (size_t)n * 8));
+  auto take = [&](double** out) -> hs_status {
+    if (!t->pool.empty()) {
+      *out = t->pool.back();
+      t->pool.pop_back();
+      return HS_OK;
+    }
+    return dalloc(ctx, (void**)out, (size_t)n * 8);
+  };
+  auto settle = [&](int j) -> hs_status {   // adds the contributions to gamma_j into lam
+    auto it = pending.find(j);
+    if (it == pending.end()) return HS_OK;
+    HS_LAUNCH(ctx, axpy_kernel, blocks_for(n, kBlock, 1024), kBlock, n, (const double*)it->second, lam);
+    t->pool.push_back(it->second);
+    pending.erase(it);
+    return HS_OK;
+  };
   const int last0 = ((p.steps - 1) / K) * K;
   for (int s0 = last0; s0 >= 0; s0 -= K) {
     const int s1 = std::min(s0 + K, p.steps);
@@ -270,14 +313,36 @@ hs_status hs_traj_backward(hs_ctx* ctx, hs_tape* t, const double* lam_T, double*
                                            "(inputs or basis changed since hs_traj_forward)");
     // the step adjoints in reverse order
     for (int k = s1; k > s0; --k) {
+      if (through_psi) HS_TRY(settle(k));
       if (t->kind[k] == 0) {
         HS_TRY(hdm_step_adjoint(ctx, t->seg[k - s0], lam, lam2, nullptr));
       } else {
         const hs_tape::Basis& b = t->bases[t->bver[k]];
-        HS_TRY(rom_hybrid_step_adjoint(ctx, b.Phi, b.m, t->ht[k], lam, lam2, nullptr));
+        if (!through_psi) {
+          HS_TRY(rom_hybrid_step_adjoint(ctx, b.Phi, b.m, t->ht[k], lam, lam2, nullptr));
+        } else {
+          HS_TRY(rom_hybrid_step_adjoint_psi(ctx, b.Phi, b.m, t->ht[k], lam, lam2, t->lam_psi, nullptr));
+          for (int j = b.k_update - p.w + 1; j <= b.k_update; ++j) {
+            auto it = pending.find(j);
+            if (it == pending.end()) {
+              double* buf = nullptr;
+              HS_TRY(take(&buf));
+              HS_LAUNCH(ctx, share_kernel, blocks_for(n, kBlock, 1024), kBlock, n, (const double*)t->lam_psi,
+                        (double)p.w, buf, 0);
+              pending[j] = buf;
+            } else {
+              HS_LAUNCH(ctx, share_kernel, blocks_for(n, kBlock, 1024), kBlock, n, (const double*)t->lam_psi,
+                        (double)p.w, it->second, 1);
+            }
+          }
+        }
       }
       std::swap(lam, lam2);
     }
+  }
+  if (through_psi) {
+    HS_TRY(settle(0));
+    if (!pending.empty()) return ctx->fail(HS_ERR_INVALID_ARG, "hs_traj_backward: a psi contribution was not settled");
   }
   HS_TRY(dcopy(ctx, lam_0, lam, n));
   return hs_sync(ctx);

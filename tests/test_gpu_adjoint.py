@@ -297,3 +297,99 @@ def test_traj_forward_equals_driver(name):
                 Phi, _, m = traj.bases[v]
                 lam2, _ = c.rom_hybrid_step_adjoint(Phi, m, traj.tapes[k], lam2)
     assert torch.equal(g, lam2)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hybrid_step_psi_adjoint_matches_oracle(name):
+    """rom_hybrid_step_adjoint_psi: the step adjoint equals
+    rom_hybrid_step_adjoint's bit for bit, and the adjoint with respect to
+    the step's reference state equals the oracle's to 1e-10; central
+    differences of the GPU's own replayed step in psi agree with it."""
+    need_gpu()
+    print_case("rom_hybrid_step_adjoint_psi", name)
+    import paper_2301_01718_amd as hs
+    prob, g, Phi_o, psi, me, sel = hybrid_setup(name)
+    ctx = ctx_for(prob)
+    s = ctx.samples_set(dev(sel["hat"]))
+    Phi = dev(np.ascontiguousarray(Phi_o.T).reshape(-1))
+    qg, psig = dev(g), dev(psi)
+    tape = ctx.tape()
+    ctx.rom_hybrid_step_taped(qg, Phi, psig, me, tape, hs.TAPE_RECORD, samples=s)
+    ctx.rom_hybrid_step_taped(qg, Phi, psig, me, tape, hs.TAPE_REPLAY)
+    J, passes = tape.info()
+    ref = hybrid.hybrid_step(prob, g, Phi_o, psi, sel["hat"], sel["tilde"])
+    assert J == ref["J"]
+    st = {"type": "hybrid", "hat": sel["hat"], "tilde": sel["tilde"], "Phi": Phi_o, "psi": psi, "J": J,
+          "masks": ref["masks"], "us": ref["us"]}
+    st["masks"] = shared_masks(prob, g, st, passes)
+    lam = np.random.default_rng(6).standard_normal(prob.n)
+    out0, _ = ctx.rom_hybrid_step_adjoint(Phi, me, tape, dev(lam))
+    out, lpsi, _ = ctx.rom_hybrid_step_adjoint_psi(Phi, me, tape, dev(lam))
+    assert torch.equal(out, out0)
+    _, want = A.hybrid_step_adjoint_psi(prob, st, lam, hybrid.HybridParams())
+    e = rel(host(lpsi), want)
+    print("  psi adjoint rel", e, flush=True)
+    assert e < 1e-10
+    lam_t = dev(lam)
+    gl = host(lpsi)
+    rng = np.random.default_rng(10)
+    h = 1e-6
+    for _ in range(4):
+        d = rng.standard_normal(prob.n)
+        fp, _ = ctx.rom_hybrid_step_taped(qg, Phi, dev(psi + h * d), me, tape, hs.TAPE_REPLAY)
+        fm, _ = ctx.rom_hybrid_step_taped(qg, Phi, dev(psi - h * d), me, tape, hs.TAPE_REPLAY)
+        fd = float(torch.dot(lam_t, fp - fm)) / (2 * h)
+        gd = float(gl @ d)
+        assert abs(gd - fd) <= 1e-6 * max(abs(gd), 1e-8 * np.linalg.norm(gl) * np.linalg.norm(d)), (gd, fd)
+
+
+@pytest.mark.parametrize("name", list(TRAJ))
+def test_trajectory_gradient_through_psi_matches_oracle(name):
+    """hs_traj_backward through the reference states (psi_adjoint): the
+    oracle's backward with psi live over the GPU run's own frozen decisions
+    and bases (its psi of hybrid step k the mean of gamma_{k-w} ..
+    gamma_{k-1}, the update after step k - 1) agrees to 1e-10; the psi path
+    moves the gradient measurably."""
+    need_gpu()
+    print_case("trajectory adjoint through psi", name)
+    from paper_2301_01718_amd.adjoint import Trajectory
+    from paper_2301_01718_amd.driver import AromConfig
+    wl, extra, seed = TRAJ[name]
+    prob, q0 = W.make(wl, seed)
+    steps = wl.w + extra
+    cfg = AromConfig(w=wl.w, m=wl.m, z=wl.z, fraction=wl.frac, halo=wl.halo)
+    traj = Trajectory(prob, cfg, steps, checkpoint_every=7, psi_adjoint=True)
+    qT = traj.forward(dev(q0))
+    c = np.random.default_rng(3).standard_normal(prob.n)
+    g_live = host(traj.backward(dev(c)))
+    traj0 = Trajectory(prob, cfg, steps, checkpoint_every=7, ctx=traj.ctx)
+    traj0.forward(dev(q0))
+    g_frozen = host(traj0.backward(dev(c)))
+    hp = hybrid.HybridParams()
+    tape_b, q = [], q0.copy()
+    for k in range(1, steps + 1):
+        kind, v = traj.kinds[k]
+        if kind == "full":
+            q, _ = fv.hdm_step(prob, q)
+            tape_b.append({"type": "full", "out": q})
+            continue
+        t = traj.tapes[k]
+        Phi_g, psi_g, m = traj.bases[v]
+        hat, tilde, _ = (host(x) for x in t.samples().export())
+        J, passes = t.info()
+        st = {"type": "hybrid", "hat": hat, "tilde": tilde, "Phi": host(Phi_g).reshape(m, prob.n).T,
+              "psi": host(psi_g), "J": J, "psi_idx": list(range(k - wl.w, k))}
+        ref = hybrid.hybrid_step(prob, q, st["Phi"], st["psi"], hat, tilde, hp)
+        st["masks"] = ref["masks"]
+        st["masks"] = shared_masks(prob, q, st, passes)
+        q_next, st["us"] = A.replay_hybrid(prob, q, st, hp, states=True)
+        st["out"] = q_next
+        tape_b.append(st)
+        q = q_next
+    assert rel(host(qT), q) < 1e-11
+    want = A.backward(prob, tape_b, c, hp, psi_live=True)
+    e = rel(g_live, want)
+    moved = rel(g_live, g_frozen)
+    print(f"  gradient through psi: rel {e:.2e} against the oracle; the psi path moves it by {moved:.2e}", flush=True)
+    assert e < 1e-10
+    assert moved > 1e-6

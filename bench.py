@@ -368,11 +368,18 @@ def adjoint_bench(name, seed):
         loss = 0.5 * torch.sum(qT * qT)
         loss.backward()
     kinds = [traj.kinds[k][0] for k in range(1, wl.steps + 1)]
+    # the same run differentiated through the reference states psi as well
+    tp = Trajectory(prob, cfg, wl.steps, checkpoint_every=K, ctx=traj.ctx, psi_adjoint=True)
+    qp = torch.from_numpy(q0).to(traj.ctx.device).requires_grad_(True)
+    qTp = HybridTrajectory.apply(qp, tp)
+    (0.5 * torch.sum(qTp * qTp)).backward()
     return {"workload": name, "nx": prob.nx, "ny": prob.ny, "steps": wl.steps, "checkpoint_every": K,
             "hybrid_steps": kinds.count("hybrid"),
             "forward_taped_s_per_step": traj.timing["forward_s"] / wl.steps,
             "backward_s_per_step": traj.timing["backward_s"] / wl.steps,
-            "grad_norm": float(torch.linalg.vector_norm(q.grad))}
+            "grad_norm": float(torch.linalg.vector_norm(q.grad)),
+            "backward_through_psi_s_per_step": tp.timing["backward_s"] / wl.steps,
+            "grad_norm_through_psi": float(torch.linalg.vector_norm(qp.grad))}
 
 
 def main():

@@ -142,6 +142,47 @@ hs_status hs_jvp(hs_ctx* ctx, const double* q, const double* v, double* out);
  * HS_ERR_NONFINITE. */
 hs_status hdm_step(hs_ctx* ctx, const double* q_prev, double* q_out, hs_step_info* info /* host, may be NULL */);
 
+/* ------------------------------------------------- the paper's own HDM */
+/* Sec. 3.1's full-order scheme on an HS_EULER_2D context (its nx, ny, dx, dy,
+ * dt, gamma, newton_rtol, newton_maxit, lin_maxit): MUSCL reconstruction of
+ * the primitive variables (rho, u, v, P) with the minmod limiter, slope
+ * minmod(w_i - w_{i-1}, w_{i+1} - w_i) and face states w_i +- slope_i / 2;
+ * Roe's approximate Riemann solver at every face (no entropy fix); BDF2 in
+ * time (eq. bdf, a_0 = 1/3, a_1 = -4/3, a_2 = 1, beta = 2/3), BDF1 when
+ * q_prev2 is NULL.  With ny = 1 the scheme is one-dimensional (no y fluxes).
+ * Boundaries come with each call and replace the context's bc:
+ *   HS_PAPER_BC_FIXED  two ghost layers hold the given conservative states
+ *                      (Sec. 3.2: the initial boundary states), ghost[0..3]
+ *                      outside the left, right, bottom, top boundary (bottom
+ *                      and top ignored when ny = 1); density must be > 0;
+ *   HS_PAPER_BC_WALL   reflective walls (Sec. 3.3): the ghosts mirror the
+ *                      boundary cells with the normal momentum reversed; needs
+ *                      nx >= 2.
+ * State layout as everywhere: component-major (rho | rho u | rho v | E), cell
+ * i + nx j; all vectors are device pointers of 4 nx ny doubles. */
+#define HS_PAPER_BC_FIXED 0
+#define HS_PAPER_BC_WALL  1
+typedef struct hs_paper_hdm {
+  int32_t bc;            /* HS_PAPER_BC_* */
+  int32_t reserved;
+  double  ghost[4][4];   /* FIXED: (rho, rho u, rho v, E) of the left, right, bottom, top ghosts */
+} hs_paper_hdm;
+/* R = a_2 q - beta dt f*(q) + a_0 q_prev2 + a_1 q_prev (eq. hdm with BDF2),
+ * or q - dt f*(q) - q_prev when q_prev2 is NULL.  R must not alias an input.
+ * Errors: HS_ERR_INVALID_ARG (not an Euler context, bad bc or ghosts). */
+hs_status hs_paper_residual(hs_ctx* ctx, const hs_paper_hdm* hdm /* host */, const double* q, const double* q_prev,
+                            const double* q_prev2 /* may be NULL */, double* R);
+/* One step of the paper's scheme: q_out solves R(q_out) = 0 to
+ * ||R||_inf <= newton_rtol * max(1, ||q_prev||_inf), from the guess q_prev,
+ * by defect correction (each iteration relaxes the first-order Rusanov
+ * Jacobian of the step against the second-order residual; at most
+ * 4 newton_maxit iterations).  info->newton_iters counts the corrections,
+ * info->lin_sweeps their relaxation sweeps.  q_out must not alias an input.
+ * Errors: HS_ERR_INVALID_ARG, HS_ERR_NOT_CONVERGED, HS_ERR_NONFINITE (a
+ * state without positive density or pressure). */
+hs_status hdm_step_bdf2(hs_ctx* ctx, const hs_paper_hdm* hdm /* host */, const double* q_prev,
+                        const double* q_prev2 /* may be NULL */, double* q_out, hs_step_info* info /* host, may be NULL */);
+
 /* -------------------------------------------------------- sample_select */
 #define HS_RULE_FRACTION 0   /* n_g = min(ceil(fraction * ncell), #{eps > 0}) */
 #define HS_RULE_RRE      1   /* smallest n_g with RRE(n_g) >= delta (eq. rre) */

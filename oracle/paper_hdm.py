@@ -34,7 +34,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 BDF2 = (1.0 / 3.0, -4.0 / 3.0, 1.0, 2.0 / 3.0)    # a_0, a_1, a_2, beta (eq. bdf, Sec. 3.1)
-WALL, FIXED = 0, 1
+FIXED, WALL = 0, 1                                 # ghosts from given states; reflective walls
 
 
 @dataclass(frozen=True)
@@ -222,10 +222,11 @@ def fd_jacobian(prob: PaperProblem, q, q1, q2=None):
     return sp.csc_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
 
 
-def hdm_step(prob: PaperProblem, q1, q2=None, maxit=30):
-    """One time step: Newton on eq. hdm from q_{k-1}; returns (q_k, iterations)."""
+def hdm_step(prob: PaperProblem, q1, q2=None, maxit=30, rtol=1e-12):
+    """One time step: Newton on eq. hdm from q_{k-1} until
+    ||R||_inf <= rtol max(1, |q_{k-1}|_inf); returns (q_k, iterations)."""
     q = q1.copy()
-    tol = 1e-12 * max(1.0, float(np.max(np.abs(q1))))
+    tol = rtol * max(1.0, float(np.max(np.abs(q1))))
     for it in range(maxit + 1):
         R = residual(prob, q, q1, q2)
         if np.max(np.abs(R)) <= tol:
@@ -236,12 +237,12 @@ def hdm_step(prob: PaperProblem, q1, q2=None, maxit=30):
     raise RuntimeError("Newton on the paper's HDM did not converge")
 
 
-def run(prob: PaperProblem, q0, steps):
+def run(prob: PaperProblem, q0, steps, rtol=1e-12):
     """N_t steps: BDF1 for the first, BDF2 after; returns every state."""
     states = [q0.copy()]
     for k in range(steps):
         q2 = states[-2] if k >= 1 else None
-        q, _ = hdm_step(prob, states[-1], q2)
+        q, _ = hdm_step(prob, states[-1], q2, rtol=rtol)
         states.append(q)
     return states
 

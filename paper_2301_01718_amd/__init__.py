@@ -7,4 +7,4 @@ adjoint (``paper_2301_01718_amd.adjoint``).
 """
 from ._lib import (Context, Samples, Tape, HsError, hybrid_params, lib, exported_symbols,  # noqa: F401
                    BURGERS_1D, BURGERS_2D, EULER_2D, FP64, MIXED_FP32, RULE_FRACTION, RULE_RRE,
-                   TAPE_RECORD, TAPE_REPLAY, BASIS_PENDING)
+                   TAPE_RECORD, TAPE_REPLAY, BASIS_PENDING, PAPER_BC_FIXED, PAPER_BC_WALL, PaperHDM, paper_hdm)

@@ -71,6 +71,24 @@ class TrajParams(ctypes.Structure):
                 ("sample", SampleParams), ("hybrid", HybridParams), ("psi_adjoint", ctypes.c_int32)]
 
 
+PAPER_BC_FIXED, PAPER_BC_WALL = 0, 1   # HS_PAPER_BC_*
+
+
+class PaperHDM(ctypes.Structure):
+    _fields_ = [("bc", ctypes.c_int32), ("reserved", ctypes.c_int32), ("ghost", (ctypes.c_double * 4) * 4)]
+
+
+def paper_hdm(bc=PAPER_BC_FIXED, ghost=()) -> PaperHDM:
+    """Boundary data of the paper's scheme: ghost = up to four conservative
+    4-vectors (left, right, bottom, top) for PAPER_BC_FIXED."""
+    h = PaperHDM()
+    h.bc = bc
+    for s, g in enumerate(ghost):
+        for a in range(4):
+            h.ghost[s][a] = float(g[a])
+    return h
+
+
 def hybrid_params(eps_y=1e-4, jmax=10, filter_orders=(1, 2, 3), eps_f=1e-2, jfmax=10,
                   rcond_fit=1e-8, floor_rel=1e-14, precision=FP64) -> HybridParams:
     hp = HybridParams()
@@ -96,6 +114,8 @@ _SIGS = {
     "hs_residual": [P, P, P, P],
     "hs_jvp": [P, P, P, P],
     "hdm_step": [P, P, P, ctypes.POINTER(StepInfo)],
+    "hs_paper_residual": [P, ctypes.POINTER(PaperHDM), P, P, P, P],
+    "hdm_step_bdf2": [P, ctypes.POINTER(PaperHDM), P, P, P, ctypes.POINTER(StepInfo)],
     "hs_samples_create": [P, ctypes.POINTER(P)],
     "hs_samples_destroy": [P],
     "sample_select": [P, P, ctypes.POINTER(SampleParams), P],
@@ -306,6 +326,23 @@ class Context:
         out = self.empty() if out is None else out
         info = StepInfo()
         self._check(lib().hdm_step(self.h, _ptr(self._in(q_prev)), _ptr(self._in(out)), ctypes.byref(info)))
+        return out, info.as_dict()
+
+    def paper_residual(self, hdm, q, q_prev, q_prev2=None, out=None):
+        """The paper's BDF2 residual (BDF1 without q_prev2); hdm: PaperHDM."""
+        out = self.empty() if out is None else out
+        p2 = None if q_prev2 is None else _ptr(self._in(q_prev2))
+        self._check(lib().hs_paper_residual(self.h, ctypes.byref(hdm), _ptr(self._in(q)), _ptr(self._in(q_prev)),
+                                            p2, _ptr(self._in(out))))
+        return out
+
+    def hdm_step_bdf2(self, hdm, q_prev, q_prev2=None, out=None):
+        """One step of the paper's scheme; returns (q, info)."""
+        out = self.empty() if out is None else out
+        info = StepInfo()
+        p2 = None if q_prev2 is None else _ptr(self._in(q_prev2))
+        self._check(lib().hdm_step_bdf2(self.h, ctypes.byref(hdm), _ptr(self._in(q_prev)), p2,
+                                        _ptr(self._in(out)), ctypes.byref(info)))
         return out, info.as_dict()
 
     # ----------------------------------------------------------- sampling

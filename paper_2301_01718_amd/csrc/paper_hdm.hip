@@ -1,0 +1,345 @@
+// The paper's own full-order scheme (Sec. 3.1) on the 2D Euler mesh of a
+// context: MUSCL reconstruction of the primitive variables (rho, u, v, P)
+// limited by minmod, Roe's approximate Riemann solver at every face, BDF2 in
+// time (eq. bdf with a_0 = 1/3, a_1 = -4/3, a_2 = 1, beta = 2/3; BDF1 where
+// q_{k-2} is absent) and the residual of eq. hdm.  Boundaries: ghosts holding
+// given states (the initial boundary states, Sec. 3.2) or reflective walls
+// (Sec. 3.3).
+//
+// One thread per cell gathers its radius-2 cross stencil (ghosts applied),
+// reconstructs the two faces on each axis and differences their Roe fluxes;
+// every face is evaluated by both of its cells with the same operations and
+// operands, so the two values agree bit for bit and the scheme stays
+// discretely conservative.
+//
+// The implicit step is a defect correction: each iteration evaluates the
+// second-order BDF residual and relaxes the first-order Rusanov Jacobian of
+// the same step (a_2 I - beta dt dF_1/dq, transmissive ghosts) against it;
+// the iteration converges to the root of the second-order residual, at a
+// rate set by the gap between the two Jacobians (about 0.1 per iteration at
+// the paper's Courant numbers).  The limiter's kinks make the exact Jacobian
+// only piecewise defined, which a Newton method would have to differentiate.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "common.hpp"
+#include "physics.hpp"
+
+namespace hs {
+
+hs_status linear_solve(hs_ctx* ctx, const hs_samples* s, double rho, double eta, double* q, int* sweeps);
+
+struct PaperBC {
+  int kind;              // HS_PAPER_BC_FIXED or HS_PAPER_BC_WALL
+  double ghost[4][4];    // FIXED: states outside the left, right, bottom, top boundaries
+};
+
+// Conservative state of cell (i, j), with ghosts: at most one of i, j lies
+// outside the mesh, by at most two cells.
+__device__ inline void paper_state(const Grid& g, const PaperBC& bc, const double* __restrict__ q, int i, int j,
+                                   double s[4]) {
+  int side = -1;
+  if (i < 0) side = 0;
+  else if (i >= g.nx) side = 1;
+  else if (j < 0) side = 2;
+  else if (j >= g.ny) side = 3;
+  if (side >= 0 && bc.kind == HS_PAPER_BC_FIXED) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) s[a] = bc.ghost[side][a];
+    return;
+  }
+  // wall: the mirror cell, its normal momentum reversed
+  if (side == 0) i = -1 - i;
+  else if (side == 1) i = 2 * g.nx - 1 - i;
+  else if (side == 2) j = -1 - j;
+  else if (side == 3) j = 2 * g.ny - 1 - j;
+  const int cell = i + g.nx * j;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) s[a] = q[a * g.ncell + cell];
+  if (side == 0 || side == 1) s[1] = -s[1];
+  if (side == 2 || side == 3) s[2] = -s[2];
+}
+
+__device__ inline void to_primitive(const double s[4], double gamma, double w[4]) {
+#pragma clang fp contract(off)
+  const double rho = s[0];
+  const double u = s[1] / rho;
+  const double v = s[2] / rho;
+  w[0] = rho;
+  w[1] = u;
+  w[2] = v;
+  w[3] = (gamma - 1.0) * (s[3] - 0.5 * rho * (u * u + v * v));
+}
+
+// Zero unless a and b share a sign; then the one of smaller magnitude.
+__device__ inline double minmod(double a, double b) {
+  if (!(a * b > 0.0)) return 0.0;
+  return fabs(a) <= fabs(b) ? a : b;
+}
+
+// Roe's flux between reconstructed primitive states wL | wR across a face
+// normal to axis (0: x, 1: y).  The states are rotated so that component n
+// carries the normal velocity and t the tangential one; the four waves are
+// the acoustic u_n -+ c, the entropy wave and the shear wave at u_n.
+__device__ inline void roe_flux(const double wL[4], const double wR[4], double gamma, int axis, double F[4]) {
+#pragma clang fp contract(off)
+  const int n = axis == 0 ? 1 : 2, t = axis == 0 ? 2 : 1;
+  const double g1 = gamma - 1.0;
+  const double rL = wL[0], nL = wL[n], tL = wL[t], pL = wL[3];
+  const double rR = wR[0], nR = wR[n], tR = wR[t], pR = wR[3];
+  const double eL = pL / g1 + 0.5 * rL * (wL[1] * wL[1] + wL[2] * wL[2]);
+  const double eR = pR / g1 + 0.5 * rR * (wR[1] * wR[1] + wR[2] * wR[2]);
+  const double hL = (eL + pL) / rL, hR = (eR + pR) / rR;
+  // physical fluxes in the face frame: mass, normal, tangential momentum, energy
+  const double fL[4] = {rL * nL, rL * nL * nL + pL, rL * nL * tL, (eL + pL) * nL};
+  const double fR[4] = {rR * nR, rR * nR * nR + pR, rR * nR * tR, (eR + pR) * nR};
+  // Roe averages
+  const double sL = sqrt(rL), sR = sqrt(rR);
+  const double den = sL + sR;
+  const double un = (sL * nL + sR * nR) / den;
+  const double ut = (sL * tL + sR * tR) / den;
+  const double h = (sL * hL + sR * hR) / den;
+  const double kin = 0.5 * (un * un + ut * ut);
+  const double c2 = g1 * (h - kin);
+  const double c = sqrt(c2);
+  const double rho = sL * sR;
+  const double dp = pR - pL, dn = nR - nL;
+  // wave strengths times |speed|
+  const double w1 = fabs(un - c) * ((dp - rho * c * dn) / (2.0 * c2));
+  const double w2 = fabs(un) * ((rR - rL) - dp / c2);
+  const double w3 = fabs(un) * (rho * (tR - tL));
+  const double w4 = fabs(un + c) * ((dp + rho * c * dn) / (2.0 * c2));
+  double d[4];
+  d[0] = w1 + w2 + w4;
+  d[1] = w1 * (un - c) + w2 * un + w4 * (un + c);
+  d[2] = (w1 + w2 + w4) * ut + w3;
+  d[3] = w1 * (h - un * c) + w2 * kin + w3 * ut + w4 * (h + un * c);
+  double Ff[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) Ff[a] = 0.5 * (fL[a] + fR[a]) - 0.5 * d[a];
+  F[0] = Ff[0];
+  F[n] = Ff[1];
+  F[t] = Ff[2];
+  F[3] = Ff[3];
+}
+
+// dt f*(q) of one cell: minus dt times its flux divergence.
+__device__ inline void paper_dt_rhs(const Grid& g, const PaperBC& bc, const double* __restrict__ q, int cell,
+                                    double out[4]) {
+#pragma clang fp contract(off)
+  int i, j;
+  cell_ij(g, cell, i, j);
+  const int naxes = g.ny > 1 ? 2 : 1;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) out[a] = 0.0;
+  for (int axis = 0; axis < naxes; ++axis) {
+    double w[5][4];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      double s[4];
+      if (axis == 0) paper_state(g, bc, q, i - 2 + k, j, s);
+      else paper_state(g, bc, q, i, j - 2 + k, s);
+      to_primitive(s, g.gamma, w[k]);
+    }
+    double sl[3][4];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) sl[m][a] = minmod(w[m + 1][a] - w[m][a], w[m + 2][a] - w[m + 1][a]);
+    double lo_l[4], lo_r[4], hi_l[4], hi_r[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      lo_l[a] = w[1][a] + 0.5 * sl[0][a];
+      lo_r[a] = w[2][a] - 0.5 * sl[1][a];
+      hi_l[a] = w[2][a] + 0.5 * sl[1][a];
+      hi_r[a] = w[3][a] - 0.5 * sl[2][a];
+    }
+    double Flo[4], Fhi[4];
+    roe_flux(lo_l, lo_r, g.gamma, axis, Flo);
+    roe_flux(hi_l, hi_r, g.gamma, axis, Fhi);
+    const double l = axis == 0 ? g.lx : g.ly;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) out[a] = out[a] - l * (Fhi[a] - Flo[a]);
+  }
+}
+
+// BDF residual of one cell: a_2 q - beta dt f*(q) + a_0 q_{k-2} + a_1 q_{k-1}
+// (BDF2), or q - dt f*(q) - q_{k-1} (BDF1, q2 == nullptr).
+__device__ inline void paper_cell_residual(const Grid& g, const PaperBC& bc, const double* __restrict__ q,
+                                           const double* __restrict__ q1, const double* __restrict__ q2, int cell,
+                                           double R[4]) {
+#pragma clang fp contract(off)
+  double f[4];
+  paper_dt_rhs(g, bc, q, cell, f);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int k = a * g.ncell + cell;
+    if (q2) R[a] = q[k] - (2.0 / 3.0) * f[a] + (1.0 / 3.0) * q2[k] - (4.0 / 3.0) * q1[k];
+    else R[a] = q[k] - f[a] - q1[k];
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) paper_residual_kernel(Grid g, PaperBC bc, const double* __restrict__ q,
+                                                                const double* __restrict__ q1,
+                                                                const double* __restrict__ q2,
+                                                                double* __restrict__ R) {
+  for (int cell = blockIdx.x * blockDim.x + threadIdx.x; cell < g.ncell; cell += gridDim.x * blockDim.x) {
+    double r[4];
+    paper_cell_residual(g, bc, q, q1, q2, cell, r);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) R[a * g.ncell + cell] = r[a];
+  }
+}
+
+// The second-order residual and, from the first-order Jacobian on grid gj,
+// the block-Jacobi relaxation data of the correction (as for the first-order
+// Newton step: rhs = -D^-1 R, coef[d] = D^-1 O[d]), with max |R| and the
+// relaxation's contraction bound as block partials.
+__global__ void __launch_bounds__(kBlock) paper_resjac_kernel(Grid g, Grid gj, PaperBC bc,
+                                                              const double* __restrict__ q,
+                                                              const double* __restrict__ q1,
+                                                              const double* __restrict__ q2,
+                                                              double* __restrict__ coef, double* __restrict__ rhs,
+                                                              double* __restrict__ part) {
+  __shared__ double lds[kBlock / kWave];
+  double rmax = 0.0, rho = 0.0;
+  bool bad = false;
+  const int cap = g.ncell;
+  for (int cell = blockIdx.x * blockDim.x + threadIdx.x; cell < g.ncell; cell += gridDim.x * blockDim.x) {
+    double R[4];
+    paper_cell_residual(g, bc, q, q1, q2, cell, R);
+    Stencil<4> st;
+    load_stencil<4>(gj, q, cell, st);
+    double D[16], O[4][16], Di[16];
+    cell_jacobian<4>(gj, st, D, O);
+    small_inverse<4>(D, Di);
+    double rowsum[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      rmax = nan_max(rmax, fabs(R[a]));
+      bad |= !isfinite(R[a]);
+      double b = 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) b -= Di[a * 4 + c] * R[c];
+      rhs[a * cap + cell] = b;
+      rowsum[a] = 0.0;
+    }
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          double m = 0.0;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) m += Di[a * 4 + c] * O[d][c * 4 + b];
+          coef[((d * 4 + a) * 4 + b) * (size_t)cap + cell] = m;
+          rowsum[a] += fabs(m);
+        }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) rho = nan_max(rho, rowsum[a]);
+    if (!isfinite(rho)) bad = true;
+  }
+  rmax = block_max(bad ? INFINITY : rmax, lds);
+  rho = block_max(rho, lds);
+  if (threadIdx.x == 0) {
+    stat_part(part, kStatResMax, rmax);
+    stat_part(part, kStatRho, rho);
+  }
+}
+
+// Relative accuracy of each relaxed correction: the defect correction itself
+// reduces the residual by about 0.1 per iteration, so a finer solve buys
+// nothing.
+constexpr double kDefectEta = 0.02;
+
+static hs_status paper_bc(hs_ctx* ctx, const hs_paper_hdm* hdm, PaperBC* bc) {
+  if (ctx->nc != 4) return ctx->fail(HS_ERR_INVALID_ARG, "the paper's scheme needs an HS_EULER_2D context");
+  if (hdm->bc != HS_PAPER_BC_FIXED && hdm->bc != HS_PAPER_BC_WALL)
+    return ctx->fail(HS_ERR_INVALID_ARG, "hs_paper_hdm.bc must be HS_PAPER_BC_FIXED or HS_PAPER_BC_WALL");
+  if (hdm->bc == HS_PAPER_BC_WALL && ctx->g.nx < 2)
+    return ctx->fail(HS_ERR_INVALID_ARG, "reflective walls need two cells along x");
+  bc->kind = hdm->bc;
+  for (int s = 0; s < 4; ++s)
+    for (int a = 0; a < 4; ++a) {
+      const double v = hdm->ghost[s][a];
+      if (hdm->bc == HS_PAPER_BC_FIXED && (s < 2 || ctx->g.ny > 1)) {
+        if (!std::isfinite(v) || (a == 0 && !(v > 0.0)))
+          return ctx->fail(HS_ERR_INVALID_ARG, "ghost states must be finite with positive density");
+      }
+      bc->ghost[s][a] = v;
+    }
+  return HS_OK;
+}
+
+static int paper_blocks(const hs_ctx* ctx) { return stat_blocks(ctx->ncell); }
+
+}  // namespace hs
+
+using namespace hs;
+
+extern "C" {
+
+hs_status hs_paper_residual(hs_ctx* ctx, const hs_paper_hdm* hdm, const double* q, const double* q_prev,
+                            const double* q_prev2, double* R) {
+  if (!ctx || !hdm || !q || !q_prev || !R) return HS_ERR_INVALID_ARG;
+  if (R == q || R == q_prev || (q_prev2 && R == q_prev2)) return ctx->fail(HS_ERR_INVALID_ARG, "R aliases an input");
+  PaperBC bc;
+  HS_TRY(paper_bc(ctx, hdm, &bc));
+  HS_LAUNCH(ctx, paper_residual_kernel, blocks_for(ctx->ncell), kBlock, ctx->g, bc, q, q_prev, q_prev2, R);
+  return HS_OK;
+}
+
+hs_status hdm_step_bdf2(hs_ctx* ctx, const hs_paper_hdm* hdm, const double* q_prev, const double* q_prev2,
+                        double* q_out, hs_step_info* info) {
+  if (!ctx || !hdm || !q_prev || !q_out) return HS_ERR_INVALID_ARG;
+  if (q_out == q_prev || (q_prev2 && q_out == q_prev2))
+    return ctx->fail(HS_ERR_INVALID_ARG, "q_out aliases an input");
+  if (info) std::memset(info, 0, sizeof *info);
+  PaperBC bc;
+  HS_TRY(paper_bc(ctx, hdm, &bc));
+  double qmax;
+  HS_TRY(max_abs(ctx, q_prev, ctx->n, &qmax));
+  if (!std::isfinite(qmax)) return ctx->fail(HS_ERR_NONFINITE, "non-finite q_prev");
+  const double tol = ctx->p.newton_rtol * std::max(1.0, qmax);
+  HIP_TRY(ctx, hipMemcpyAsync(q_out, q_prev, ctx->n * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  // the correction's Jacobian: first-order Rusanov, transmissive ghosts, the
+  // step's beta dt
+  Grid gj = ctx->g;
+  gj.bc = HS_BC_TRANSMISSIVE;
+  const double beta = q_prev2 ? 2.0 / 3.0 : 1.0;
+  gj.lx *= beta;
+  gj.ly *= beta;
+  const int maxit = 4 * ctx->p.newton_maxit;
+  const int nb = paper_blocks(ctx);
+  int sweeps = 0;
+  for (int it = 0;; ++it) {
+    HS_LAUNCH(ctx, paper_resjac_kernel, nb, kBlock, ctx->g, gj, bc, q_out, q_prev, q_prev2, ctx->coef, ctx->rhs,
+              ctx->part);
+    unsigned long long st[kStatSlots];
+    HS_TRY(finish_stats(ctx, nb, (1u << kStatResMax) | (1u << kStatRho), 0u, st));
+    const double rmax = bits_to_double(st[kStatResMax]);
+    const double rho = bits_to_double(st[kStatRho]);
+    if (!std::isfinite(rmax)) return ctx->fail(HS_ERR_NONFINITE, "non-finite residual of the paper's scheme");
+    if (info) info->residual_inf = rmax;
+    if (rmax <= tol) {
+      if (info) {
+        info->newton_iters = it;
+        info->lin_sweeps = sweeps;
+        info->n_s = ctx->ncell;
+      }
+      return HS_OK;
+    }
+    if (it >= maxit) {
+      char msg[160];
+      std::snprintf(msg, sizeof msg, "defect correction: ||R||_inf = %.3e > %.3e after %d iterations", rmax, tol, it);
+      return ctx->fail(HS_ERR_NOT_CONVERGED, msg);
+    }
+    if (!std::isfinite(rho)) return ctx->fail(HS_ERR_NONFINITE, "non-finite Jacobian");
+    HS_TRY(linear_solve(ctx, nullptr, rho, std::max(kDefectEta, ctx->p.lin_rtol), q_out, &sweeps));
+  }
+}
+
+}  // extern "C"

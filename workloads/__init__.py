@@ -214,6 +214,75 @@ def make(wl: Workload | str, seed: int = 0):
     return prob, np.ascontiguousarray(q0, dtype=np.float64)
 
 
+# ------------------------------------------------- the paper's experiments
+PAPER_BC_FIXED, PAPER_BC_WALL = 0, 1   # HS_PAPER_BC_* (public header)
+
+
+@dataclasses.dataclass(frozen=True)
+class PaperCase:
+    """Inputs of an experiment run with the paper's own scheme: mesh, step,
+    boundary kind, ghost states (conservative, left/right/bottom/top) and the
+    initial state q0 (component-major)."""
+    name: str
+    nx: int
+    ny: int
+    dx: float
+    dy: float
+    dt: float
+    steps: int
+    gamma: float
+    bc: int
+    ghost: tuple
+    q0: np.ndarray
+
+
+def _conservative(rho, u, v, p):
+    return np.stack([rho, rho * u, rho * v, p / (GAMMA - 1.0) + 0.5 * rho * (u * u + v * v)])
+
+
+def paper_sod(nx: int = 499, steps: int = 999, T: float = 0.2) -> PaperCase:
+    """Sod's shock tube (Sec. 3.2): (0, 1), (rho, u, P) = (1, 0, 1) left of
+    0.5 and (0.125, 0, 0.1) right of it, T = 0.2, N = 499 cells and
+    N_t = 999 steps by default; ghosts hold the initial boundary states."""
+    x = cell_centres(nx)
+    left = x < 0.5
+    rho = np.where(left, 1.0, 0.125)
+    p = np.where(left, 1.0, 0.1)
+    q = _conservative(rho, 0 * x, 0 * x, p)
+    ghost = (tuple(q[:, 0]), tuple(q[:, -1]), tuple(q[:, 0]), tuple(q[:, 0]))
+    return PaperCase("sod", nx, 1, 1.0 / nx, 1.0, T / steps, steps, GAMMA, PAPER_BC_FIXED, ghost,
+                     np.ascontiguousarray(q.reshape(-1)))
+
+
+def paper_implosion(n: int = 100, steps: int = 1650, T: float = 0.5) -> PaperCase:
+    """The model implosion (Sec. 3.3): (0, 0.3)^2 with reflective walls,
+    (rho, P) = (0.125, 0.14) where x_1 + x_2 <= 0.15 and (1, 1) elsewhere, at
+    rest; T = 0.5 over 1650 steps on 100^2 cells by default."""
+    h = 0.3 / n
+    c = (np.arange(n) + 0.5) * h
+    X, Y = np.meshgrid(c, c)                      # row j = y, column i = x
+    inner = (X + Y <= 0.15).reshape(-1)
+    rho = np.where(inner, 0.125, 1.0)
+    p = np.where(inner, 0.14, 1.0)
+    z = np.zeros(n * n)
+    q = _conservative(rho, z, z, p)
+    return PaperCase("implosion", n, n, h, h, T / steps, steps, GAMMA, PAPER_BC_WALL, (),
+                     np.ascontiguousarray(q.reshape(-1)))
+
+
+def random_euler_state(nx: int, ny: int, seed: int, mach: float = 0.8) -> np.ndarray:
+    """Seeded cell-wise random Euler states: rho in [0.5, 1.5], P in
+    [0.3, 1.3], velocity components up to mach times the sound speed."""
+    rng = np.random.default_rng(seed)
+    n = nx * ny
+    rho = 0.5 + rng.random(n)
+    p = 0.3 + rng.random(n)
+    c = np.sqrt(GAMMA * p / rho)
+    u = mach * c * (2 * rng.random(n) - 1)
+    v = mach * c * (2 * rng.random(n) - 1) if ny > 1 else 0 * u
+    return np.ascontiguousarray(_conservative(rho, u, v, p).reshape(-1))
+
+
 def random_unit_vectors(n: int, count: int, seed: int) -> np.ndarray:
     """Seeded N(0,1) directions, normalised (for finite-difference checks)."""
     rng = np.random.default_rng(seed)

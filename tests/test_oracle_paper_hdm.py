@@ -315,3 +315,90 @@ def test_sod_converges_to_exact_riemann_solution_and_beats_first_order():
             e1 = np.mean(np.abs(q1[:nx] - re))
             assert errs[0] < 0.6 * e1, (errs[0], e1)
     assert errs[0] < 0.01 and errs[0] / errs[1] > 1.6, errs
+
+
+# ------------------------------------------- Alg. 1 with the paper's HDM
+
+from oracle import arom, paper_arom as pa, pod, sampling  # noqa: E402
+
+
+def _sod_states(nx, steps, k):
+    prob, q0 = ph.sod(nx, steps)
+    return prob, ph.run(prob, q0, k, rtol=1e-13)
+
+
+@pytest.mark.parametrize("nx,ny", [(17, 1), (9, 8)])
+def test_ring_holds_everything_the_sampled_residual_reads(nx, ny):
+    """Brute force: replacing every cell outside the sampled set and its ring
+    by another state leaves the sampled cells' residual bit for bit the same,
+    and every cell on which that residual depends numerically (a non-zero
+    column of the Jacobian's sampled rows) lies in the ring."""
+    rng = np.random.default_rng(nx)
+    n = nx * ny
+
+    def state():
+        w = np.stack([0.8 + 0.4 * rng.random(n), 0.3 * rng.standard_normal(n), 0.3 * rng.standard_normal(n),
+                      0.8 + 0.4 * rng.random(n)])
+        if ny == 1:
+            w[2] = 0.0
+        return ph.conservative(w, G).reshape(-1)
+
+    prob = ph.PaperProblem(nx=nx, ny=ny, dx=1 / nx, dy=1 / ny, dt=0.01, gamma=G, bc=ph.WALL)
+    q, q1, other = state(), state(), state()
+    J = ph.fd_jacobian(prob, q, q1, q1).toarray()
+    for trial in range(6):
+        mask = rng.random(n) < 0.2
+        rg = pa.ring(prob, mask)
+        rows = pa.dofs(prob, np.flatnonzero(mask))
+        far = pa.dofs(prob, np.flatnonzero(~mask & ~rg))
+        qf = q.copy()
+        qf[far] = other[far]
+        assert np.array_equal(ph.residual(prob, qf, q1, q1)[rows], ph.residual(prob, q, q1, q1)[rows]), trial
+        touched = np.any(J[rows] != 0.0, axis=0).reshape(4, n).any(axis=0)
+        assert not np.any(touched & ~mask & ~rg), trial
+
+
+def test_paper_hybrid_all_sampled_equals_hdm_step():
+    prob, states = _sod_states(60, 120, 12)
+    q1, q2 = states[-1], states[-2]
+    snaps = states[-6:-1]
+    b = pod.pod(snaps, 5, 4)
+    out = pa.hybrid_step(prob, q1, q2, b["Phi"], b["psi_new"], np.arange(prob.ncell))
+    q, _ = ph.hdm_step(prob, q1, q2, rtol=1e-13)
+    assert out["l"] == 0 and out["J"] == 2
+    assert np.max(np.abs(out["gamma"] - q)) < 1e-11
+
+
+def test_paper_hybrid_recovers_a_state_in_the_affine_subspace():
+    """psi = gamma_{k-1} and Phi the direction to the HDM's gamma_k: the
+    subiterations converge to gamma_k (the fixed point is the exact state),
+    which the filters keep."""
+    prob, states = _sod_states(80, 160, 20)
+    q1, q2 = states[-1], states[-2]
+    q, _ = ph.hdm_step(prob, q1, q2, rtol=1e-13)
+    d = q - q1
+    Phi = (d / np.linalg.norm(d))[:, None]
+    hat = np.arange(30, 50)                       # around the waves
+    params = pa.HybridParams(eps_y=1e-13, jmax=60)
+    out = pa.hybrid_step(prob, q1, q2, Phi, q1, hat, params)
+    assert out["l"] == 4 and 2 <= out["J"] <= 60
+    assert np.max(np.abs(out["gamma"] - q)) < 1e-10
+
+
+def test_paper_arom_on_sod():
+    """Alg. 1 on Sod's tube (100 cells, 201 steps) with the paper's w = 5,
+    m = 4, delta = 0.8 and filters 2, 4, 6 (z = 5): every hybrid snapshot
+    stays within 1 % (relative L1) of the full-order state, with fewer
+    than half of the cells sampled on hybrid steps and J in [2, j_max]."""
+    nx, steps = 100, 201
+    prob, q0 = ph.sod(nx, steps)
+    hdm = ph.run(prob, q0, steps, rtol=1e-13)
+    p = arom.AromParams(w=5, m=4, z=5, rule=sampling.RULE_RRE, delta=0.8, halo=2)
+    errs = []
+    res = pa.run(prob, q0, steps, p, on_step=lambda k, g, rec: errs.append(arom.relative_l1_error(g, hdm[k])))
+    recs = res["records"]
+    hyb = [r for r in recs if r["type"] == "hybrid"]
+    sbar, sbar_h = arom.sampling_stats(prob, recs)
+    assert len(hyb) > 100
+    assert max(errs) < 0.01 and np.mean(errs) < 0.005, (max(errs), np.mean(errs))
+    assert sbar_h < 0.5 and all(2 <= r["J"] <= 10 for r in hyb)

@@ -307,6 +307,20 @@ hs_status rom_hybrid_step(hs_ctx* ctx, const double* q_prev, const void* Phi, co
                           int32_t m, const hs_samples* s, const hs_hybrid_params* params /* host */,
                           double* q_out, double* eps_out, double* y_out, hs_step_info* info /* host */);
 
+/* One hybrid snapshot with the paper's own scheme (Sec. 3.1; see
+ * hs_paper_hdm): rom_hybrid_step with the BDF residual (q_prev2 =
+ * gamma_{k-2}; NULL: BDF1) in the partial solve (eq. partial_hdm2, by the
+ * defect correction of hdm_step_bdf2 restricted to hat-S) and in the filter
+ * gate.  The residual of a sampled cell reads two cells along each axis, so
+ * after every fit every unsampled entry takes psi + Phi y (info->l reports
+ * their count).  Needs an HS_EULER_2D context created with
+ * HS_BC_TRANSMISSIVE (its filters extrapolate by zeroth order at the
+ * boundaries); m >= 1 (no HS_BASIS_PENDING).  Errors as rom_hybrid_step. */
+hs_status rom_hybrid_step_bdf2(hs_ctx* ctx, const hs_paper_hdm* hdm /* host */, const double* q_prev,
+                               const double* q_prev2 /* may be NULL */, const void* Phi, const double* psi,
+                               int32_t m, const hs_samples* s, const hs_hybrid_params* params /* host */,
+                               double* q_out, double* eps_out, double* y_out, hs_step_info* info /* host */);
+
 /* The residual-gated filter sequence alone (Sec. 2.3.4), on a full state. */
 hs_status hs_filter(hs_ctx* ctx, const double* gamma_in, const double* q_prev,
                     const hs_hybrid_params* params /* host */, double* gamma_out, hs_step_info* info);

@@ -116,6 +116,8 @@ _SIGS = {
     "hdm_step": [P, P, P, ctypes.POINTER(StepInfo)],
     "hs_paper_residual": [P, ctypes.POINTER(PaperHDM), P, P, P, P],
     "hdm_step_bdf2": [P, ctypes.POINTER(PaperHDM), P, P, P, ctypes.POINTER(StepInfo)],
+    "rom_hybrid_step_bdf2": [P, ctypes.POINTER(PaperHDM), P, P, P, P, I32, P, ctypes.POINTER(HybridParams), P, P, P,
+                             ctypes.POINTER(StepInfo)],
     "hs_samples_create": [P, ctypes.POINTER(P)],
     "hs_samples_destroy": [P],
     "sample_select": [P, P, ctypes.POINTER(SampleParams), P],
@@ -434,6 +436,18 @@ class Context:
         finally:
             if m == BASIS_PENDING:
                 self._pending = False        # the step completes the update on every path
+        return out, info.as_dict()
+
+    def rom_hybrid_step_bdf2(self, hdm, q_prev, q_prev2, Phi, psi, m, samples, params=None, out=None, eps=None,
+                             y=None):
+        """rom_hybrid_step with the paper's scheme (hdm: PaperHDM; q_prev2 may be None)."""
+        params = _with_precision(params or hybrid_params(), self._basis(Phi, m))
+        out = self.empty() if out is None else out
+        info = StepInfo()
+        p2 = None if q_prev2 is None else _ptr(self._in(q_prev2))
+        self._check(lib().rom_hybrid_step_bdf2(self.h, ctypes.byref(hdm), _ptr(self._in(q_prev)), p2, _ptr(Phi),
+                                               _ptr(self._in(psi)), m, samples.h, ctypes.byref(params),
+                                               _ptr(self._in(out)), _ptr(eps), _ptr(y), ctypes.byref(info)))
         return out, info.as_dict()
 
     def filter(self, gamma, q_prev, params=None, out=None):

@@ -18,6 +18,7 @@
 // workloads measure kappa <= 1e3).
 constexpr double kFitEigFloor = 64 * 2.220446049250313e-16;
 #include "dense.hpp"
+#include "paper_hdm.hpp"
 #include "physics.hpp"
 
 #include <algorithm>
@@ -1432,6 +1433,133 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const void* Phi,
   return HS_OK;
 }
 
+// ------------------------------------------ the paper's full-order scheme
+// Gate of one filter pass with precomputed norms: keep the filtered value
+// where its cell residual norm rf is below r (all components), count the kept
+// cells (kStatCount partials, as doubles).
+__global__ void __launch_bounds__(kBlock) paper_gate_kernel(int ncell, const double* __restrict__ r,
+                                                            const double* __restrict__ rf,
+                                                            const double* __restrict__ gf, double* __restrict__ cur,
+                                                            uint8_t* __restrict__ keep_out, double* __restrict__ part) {
+  __shared__ double lds[kBlock / kWave];
+  double kept = 0.0;
+  for (int cell = blockIdx.x * blockDim.x + threadIdx.x; cell < ncell; cell += gridDim.x * blockDim.x) {
+    const bool keep = rf[cell] < r[cell];
+    if (keep) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) cur[(size_t)a * ncell + cell] = gf[(size_t)a * ncell + cell];
+      kept += 1.0;
+    }
+    if (keep_out) keep_out[cell] = keep ? 1 : 0;
+  }
+  kept = block_sum(kept, lds);
+  if (threadIdx.x == 0) stat_part(part, kStatCount, kept);
+}
+
+// The residual-gated filters of Sec. 2.3.4 with the paper scheme's cell
+// residual norms (the loop of run_filter, host-driven: one read-back per pass).
+static hs_status paper_filter(hs_ctx* ctx, const PaperBC& bc, double* gamma, const double* q1, const double* q2,
+                              const hs_hybrid_params* hp, hs_step_info* info) {
+  if (hp->n_orders <= 0 || hp->jfmax <= 0) return HS_OK;
+  double* r = ctx->rcell;
+  double* rf = ctx->rcell2;
+  int nb;
+  unsigned long long st[kStatSlots];
+  HS_TRY(paper_cell_norms(ctx, bc, gamma, q1, q2, r, &nb));
+  HS_TRY(finish_stats(ctx, nb, 0u, 1u << kStatSum, st));
+  double sum_r = bits_to_double(st[kStatSum]);
+  for (int o = 0; o < hp->n_orders; ++o) {
+    const int nord = hp->filter_orders[o];
+    for (int it = 1; it <= hp->jfmax; ++it) {
+      HS_TRY(filter_apply(ctx, gamma, ctx->gf, nord));
+      HS_TRY(paper_cell_norms(ctx, bc, ctx->gf, q1, q2, rf, &nb));
+      HS_LAUNCH(ctx, paper_gate_kernel, stat_blocks(ctx->ncell), kBlock, ctx->ncell, (const double*)r,
+                (const double*)rf, (const double*)ctx->gf, gamma, (uint8_t*)nullptr, ctx->part);
+      HS_TRY(paper_cell_norms(ctx, bc, gamma, q1, q2, r, &nb));
+      HS_TRY(finish_stats(ctx, nb, 0u, (1u << kStatCount) | (1u << kStatSum), st));
+      const long long kept = (long long)bits_to_double(st[kStatCount]);
+      if (info) {
+        info->filter_passes += 1;
+        info->filter_kept += (int)kept;
+      }
+      if (kept == 0) break;
+      const double sum_new = bits_to_double(st[kStatSum]);
+      const double dec = (sum_r - sum_new) / sum_r;
+      sum_r = sum_new;
+      if (dec < hp->eps_f) break;
+    }
+  }
+  return HS_OK;
+}
+
+// One hybrid step with the paper's scheme: the subiterations of hybrid_impl
+// with the BDF residual (q2: q_{k-2}) in the partial solve and the filter
+// gate.  The residual of a sampled cell reads two cells along each axis, so
+// after every fit all unsampled entries take psi + Phi y (a superset of the
+// cells that residual reads).
+static hs_status hybrid_paper_impl(hs_ctx* ctx, const hs_paper_hdm* hdm, const double* q_prev, const double* q_prev2,
+                                   const void* Phi, const double* psi, int m, const hs_samples* s,
+                                   const hs_hybrid_params* hp, double* q_out, double* eps_out, double* y_out,
+                                   hs_step_info* info) {
+  if (!ctx || !hdm || !q_prev || !Phi || !psi || !hp || !q_out || !s) return HS_ERR_INVALID_ARG;
+  if (q_out == q_prev || q_out == psi || (const void*)q_out == Phi || (q_prev2 && q_out == q_prev2))
+    return ctx->fail(HS_ERR_INVALID_ARG, "q_out aliases an input");
+  if (s->ctx != ctx) return HS_ERR_INVALID_ARG;
+  if (ctx->p.bc != HS_BC_TRANSMISSIVE)
+    return ctx->fail(HS_ERR_INVALID_ARG, "the paper's hybrid step needs a context with HS_BC_TRANSMISSIVE");
+  PaperBC bc;
+  HS_TRY(paper_bc(ctx, hdm, &bc));
+  if (m < 1 || m > ctx->p.m_max) return ctx->fail(HS_ERR_RANK, "empty basis");
+  if (hp->jmax < 1 || hp->n_orders < 0 || hp->n_orders > 4 || !(hp->rcond_fit > 0) || !(hp->eps_y >= 0))
+    return HS_ERR_INVALID_ARG;
+  for (int o = 0; o < hp->n_orders; ++o)
+    if (hp->filter_orders[o] < 1 || hp->filter_orders[o] > 3) return HS_ERR_INVALID_ARG;
+  const int prec = hp->precision;
+  if (prec != HS_FP64 && prec != HS_MIXED_FP32) return HS_ERR_INVALID_ARG;
+  if (s->n_s == 0) return ctx->fail(HS_ERR_RANK, "empty sampled set");
+  hs_step_info local{};
+  hs_step_info* inf = info ? info : &local;
+  std::memset(inf, 0, sizeof *inf);
+  inf->n_s = s->n_s;
+  inf->l = ctx->ncell - s->n_s;
+  double* u = ctx->u;
+  double* u_next = ctx->gtmp;
+  double* sm = ctx->small;
+  HS_TRY(max_abs_launch(ctx, q_prev, ctx->n));
+  HIP_TRY(ctx, hipMemcpyAsync(u, q_prev, ctx->n * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  HS_TRY(fit_factor(ctx, Phi, prec, m, s->hat, s->n_s, hp->rcond_fit));
+  unsigned long long st[kStatSlots];
+  HS_TRY(read_stats(ctx, st));
+  const double qmax = bits_to_double(st[kStatQMax]);
+  if (!std::isfinite(qmax)) return ctx->fail(HS_ERR_NONFINITE, "non-finite q_prev");
+  const double tol = ctx->p.newton_rtol * std::max(1.0, qmax);
+  inf->fit_rank = (int)bits_to_double(st[kStatFitRank]);
+  inf->fit_cond = bits_to_double(st[kStatFitCond]);
+  if (inf->fit_rank == 0) return ctx->fail(HS_ERR_RANK, "rank-zero fit");
+  for (int j = 1; j <= hp->jmax; ++j) {
+    HS_TRY(paper_solve(ctx, bc, u, q_prev, q_prev2, tol, s, inf));
+    HS_TRY(fit_solve(ctx, Phi, prec, m, s->hat, s->n_s, u, psi, j == 1));
+    // unsampled entries (the ring among them) = psi + Phi y; rho = psi + Phi y
+    HS_TRY(reconstruct(ctx, Phi, prec, m, psi, sm + kSmY, s->mask, u, u_next, ctx->rho));
+    std::swap(u, u_next);
+    inf->subiters = j;
+    HS_TRY(read_stats(ctx, st));
+    const double dy = bits_to_double(st[kStatDy]);
+    inf->dy_last = dy;
+    if (j >= 2 && dy < hp->eps_y) break;
+  }
+  HIP_TRY(ctx, hipMemcpyAsync(q_out, u, ctx->n * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  HS_TRY(paper_filter(ctx, bc, q_out, q_prev, q_prev2, hp, inf));
+  if (eps_out) {
+    int nbq;
+    HS_TRY(max_abs_partials(ctx, q_out, ctx->n, &nbq));
+    HS_LAUNCH(ctx, indicator_kernel, blocks_for(ctx->ncell), kBlock, ctx->ncell, ctx->nc, q_out, ctx->rho,
+              hp->floor_rel, (const double*)ctx->part, nbq, eps_out);
+  }
+  if (y_out) HIP_TRY(ctx, hipMemcpyAsync(y_out, sm + kSmY, m * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  return HS_OK;
+}
+
 }  // namespace hs
 
 using namespace hs;
@@ -1477,6 +1605,13 @@ hs_status rom_hybrid_step(hs_ctx* ctx, const double* q_prev, const void* Phi, co
                           const hs_samples* s, const hs_hybrid_params* hp, double* q_out, double* eps_out,
                           double* y_out, hs_step_info* info) {
   return hybrid_impl(ctx, q_prev, Phi, psi, m, s, hp, q_out, eps_out, y_out, info, nullptr, -1);
+}
+
+hs_status rom_hybrid_step_bdf2(hs_ctx* ctx, const hs_paper_hdm* hdm, const double* q_prev, const double* q_prev2,
+                               const void* Phi, const double* psi, int32_t m, const hs_samples* s,
+                               const hs_hybrid_params* hp, double* q_out, double* eps_out, double* y_out,
+                               hs_step_info* info) {
+  return hybrid_paper_impl(ctx, hdm, q_prev, q_prev2, Phi, psi, m, s, hp, q_out, eps_out, y_out, info);
 }
 
 hs_status rom_hybrid_step_taped(hs_ctx* ctx, const double* q_prev, const void* Phi, const double* psi,

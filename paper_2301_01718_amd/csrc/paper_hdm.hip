@@ -25,16 +25,12 @@
 #include <cstring>
 
 #include "common.hpp"
+#include "paper_hdm.hpp"
 #include "physics.hpp"
 
 namespace hs {
 
 hs_status linear_solve(hs_ctx* ctx, const hs_samples* s, double rho, double eta, double* q, int* sweeps);
-
-struct PaperBC {
-  int kind;              // HS_PAPER_BC_FIXED or HS_PAPER_BC_WALL
-  double ghost[4][4];    // FIXED: states outside the left, right, bottom, top boundaries
-};
 
 // Conservative state of cell (i, j), with ghosts: at most one of i, j lies
 // outside the mesh, by at most two cells.
@@ -196,24 +192,37 @@ __global__ void __launch_bounds__(kBlock) paper_residual_kernel(Grid g, PaperBC 
 // The second-order residual and, from the first-order Jacobian on grid gj,
 // the block-Jacobi relaxation data of the correction (as for the first-order
 // Newton step: rhs = -D^-1 R, coef[d] = D^-1 O[d]), with max |R| and the
-// relaxation's contraction bound as block partials.
+// relaxation's contraction bound as block partials.  On the full mesh
+// (hat == nullptr) or on the compact list hat[0..count) of sampled cells,
+// whose in-set neighbours are nbr[d * cap + p] (the couplings to every other
+// cell are dropped: those entries are held).
 __global__ void __launch_bounds__(kBlock) paper_resjac_kernel(Grid g, Grid gj, PaperBC bc,
                                                               const double* __restrict__ q,
                                                               const double* __restrict__ q1,
                                                               const double* __restrict__ q2,
+                                                              const int* __restrict__ hat,
+                                                              const int* __restrict__ nbr, int count,
                                                               double* __restrict__ coef, double* __restrict__ rhs,
                                                               double* __restrict__ part) {
   __shared__ double lds[kBlock / kWave];
   double rmax = 0.0, rho = 0.0;
   bool bad = false;
   const int cap = g.ncell;
-  for (int cell = blockIdx.x * blockDim.x + threadIdx.x; cell < g.ncell; cell += gridDim.x * blockDim.x) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < count; p += gridDim.x * blockDim.x) {
+    const int cell = hat ? hat[p] : p;
     double R[4];
     paper_cell_residual(g, bc, q, q1, q2, cell, R);
     Stencil<4> st;
     load_stencil<4>(gj, q, cell, st);
     double D[16], O[4][16], Di[16];
     cell_jacobian<4>(gj, st, D, O);
+    if (hat) {
+#pragma unroll
+      for (int d = 0; d < 4; ++d)
+        if (nbr[d * cap + p] < 0)
+#pragma unroll
+          for (int e = 0; e < 16; ++e) O[d][e] = 0.0;
+    }
     small_inverse<4>(D, Di);
     double rowsum[4];
 #pragma unroll
@@ -223,7 +232,7 @@ __global__ void __launch_bounds__(kBlock) paper_resjac_kernel(Grid g, Grid gj, P
       double b = 0.0;
 #pragma unroll
       for (int c = 0; c < 4; ++c) b -= Di[a * 4 + c] * R[c];
-      rhs[a * cap + cell] = b;
+      rhs[a * cap + p] = b;
       rowsum[a] = 0.0;
     }
 #pragma unroll
@@ -235,7 +244,7 @@ __global__ void __launch_bounds__(kBlock) paper_resjac_kernel(Grid g, Grid gj, P
           double m = 0.0;
 #pragma unroll
           for (int c = 0; c < 4; ++c) m += Di[a * 4 + c] * O[d][c * 4 + b];
-          coef[((d * 4 + a) * 4 + b) * (size_t)cap + cell] = m;
+          coef[((d * 4 + a) * 4 + b) * (size_t)cap + p] = m;
           rowsum[a] += fabs(m);
         }
 #pragma unroll
@@ -250,12 +259,31 @@ __global__ void __launch_bounds__(kBlock) paper_resjac_kernel(Grid g, Grid gj, P
   }
 }
 
+// rcell = cellwise 2-norm of the BDF residual; block sums to the kStatSum partials.
+__global__ void __launch_bounds__(kBlock) paper_norms_kernel(Grid g, PaperBC bc, const double* __restrict__ q,
+                                                             const double* __restrict__ q1,
+                                                             const double* __restrict__ q2,
+                                                             double* __restrict__ rcell, double* __restrict__ part) {
+#pragma clang fp contract(off)
+  __shared__ double lds[kBlock / kWave];
+  double acc = 0.0;
+  for (int cell = blockIdx.x * blockDim.x + threadIdx.x; cell < g.ncell; cell += gridDim.x * blockDim.x) {
+    double R[4];
+    paper_cell_residual(g, bc, q, q1, q2, cell, R);
+    const double rn = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2] + R[3] * R[3]);
+    rcell[cell] = rn;
+    acc += rn;
+  }
+  acc = block_sum(acc, lds);
+  if (threadIdx.x == 0) stat_part(part, kStatSum, acc);
+}
+
 // Relative accuracy of each relaxed correction: the defect correction itself
 // reduces the residual by about 0.1 per iteration, so a finer solve buys
 // nothing.
 constexpr double kDefectEta = 0.02;
 
-static hs_status paper_bc(hs_ctx* ctx, const hs_paper_hdm* hdm, PaperBC* bc) {
+hs_status paper_bc(hs_ctx* ctx, const hs_paper_hdm* hdm, PaperBC* bc) {
   if (ctx->nc != 4) return ctx->fail(HS_ERR_INVALID_ARG, "the paper's scheme needs an HS_EULER_2D context");
   if (hdm->bc != HS_PAPER_BC_FIXED && hdm->bc != HS_PAPER_BC_WALL)
     return ctx->fail(HS_ERR_INVALID_ARG, "hs_paper_hdm.bc must be HS_PAPER_BC_FIXED or HS_PAPER_BC_WALL");
@@ -274,7 +302,52 @@ static hs_status paper_bc(hs_ctx* ctx, const hs_paper_hdm* hdm, PaperBC* bc) {
   return HS_OK;
 }
 
-static int paper_blocks(const hs_ctx* ctx) { return stat_blocks(ctx->ncell); }
+hs_status paper_solve(hs_ctx* ctx, const PaperBC& bc, double* u, const double* q1, const double* q2, double tol,
+                      const hs_samples* s, hs_step_info* info) {
+  const int count = s ? s->n_s : ctx->ncell;
+  if (count == 0) return HS_OK;
+  // the correction's Jacobian: first-order Rusanov, transmissive ghosts, the
+  // step's beta dt
+  Grid gj = ctx->g;
+  gj.bc = HS_BC_TRANSMISSIVE;
+  const double beta = q2 ? 2.0 / 3.0 : 1.0;
+  gj.lx *= beta;
+  gj.ly *= beta;
+  const int maxit = 4 * ctx->p.newton_maxit;
+  const int nb = stat_blocks(count);
+  int sweeps = 0;
+  for (int it = 0;; ++it) {
+    HS_LAUNCH(ctx, paper_resjac_kernel, nb, kBlock, ctx->g, gj, bc, u, q1, q2, s ? s->hat : nullptr,
+              s ? s->nbr : nullptr, count, ctx->coef, ctx->rhs, ctx->part);
+    unsigned long long st[kStatSlots];
+    HS_TRY(finish_stats(ctx, nb, (1u << kStatResMax) | (1u << kStatRho), 0u, st));
+    const double rmax = bits_to_double(st[kStatResMax]);
+    const double rho = bits_to_double(st[kStatRho]);
+    if (!std::isfinite(rmax)) return ctx->fail(HS_ERR_NONFINITE, "non-finite residual of the paper's scheme");
+    if (info) info->residual_inf = rmax;
+    if (rmax <= tol) {
+      if (info) {
+        info->newton_iters += it;
+        info->lin_sweeps += sweeps;
+      }
+      return HS_OK;
+    }
+    if (it >= maxit) {
+      char msg[160];
+      std::snprintf(msg, sizeof msg, "defect correction: ||R||_inf = %.3e > %.3e after %d iterations", rmax, tol, it);
+      return ctx->fail(HS_ERR_NOT_CONVERGED, msg);
+    }
+    if (!std::isfinite(rho)) return ctx->fail(HS_ERR_NONFINITE, "non-finite Jacobian");
+    HS_TRY(linear_solve(ctx, s, rho, std::max(kDefectEta, ctx->p.lin_rtol), u, &sweeps));
+  }
+}
+
+hs_status paper_cell_norms(hs_ctx* ctx, const PaperBC& bc, const double* q, const double* q1, const double* q2,
+                           double* rcell, int* nb) {
+  *nb = stat_blocks(ctx->ncell);
+  HS_LAUNCH(ctx, paper_norms_kernel, *nb, kBlock, ctx->g, bc, q, q1, q2, rcell, ctx->part);
+  return HS_OK;
+}
 
 }  // namespace hs
 
@@ -305,41 +378,9 @@ hs_status hdm_step_bdf2(hs_ctx* ctx, const hs_paper_hdm* hdm, const double* q_pr
   if (!std::isfinite(qmax)) return ctx->fail(HS_ERR_NONFINITE, "non-finite q_prev");
   const double tol = ctx->p.newton_rtol * std::max(1.0, qmax);
   HIP_TRY(ctx, hipMemcpyAsync(q_out, q_prev, ctx->n * 8, hipMemcpyDeviceToDevice, ctx->stream));
-  // the correction's Jacobian: first-order Rusanov, transmissive ghosts, the
-  // step's beta dt
-  Grid gj = ctx->g;
-  gj.bc = HS_BC_TRANSMISSIVE;
-  const double beta = q_prev2 ? 2.0 / 3.0 : 1.0;
-  gj.lx *= beta;
-  gj.ly *= beta;
-  const int maxit = 4 * ctx->p.newton_maxit;
-  const int nb = paper_blocks(ctx);
-  int sweeps = 0;
-  for (int it = 0;; ++it) {
-    HS_LAUNCH(ctx, paper_resjac_kernel, nb, kBlock, ctx->g, gj, bc, q_out, q_prev, q_prev2, ctx->coef, ctx->rhs,
-              ctx->part);
-    unsigned long long st[kStatSlots];
-    HS_TRY(finish_stats(ctx, nb, (1u << kStatResMax) | (1u << kStatRho), 0u, st));
-    const double rmax = bits_to_double(st[kStatResMax]);
-    const double rho = bits_to_double(st[kStatRho]);
-    if (!std::isfinite(rmax)) return ctx->fail(HS_ERR_NONFINITE, "non-finite residual of the paper's scheme");
-    if (info) info->residual_inf = rmax;
-    if (rmax <= tol) {
-      if (info) {
-        info->newton_iters = it;
-        info->lin_sweeps = sweeps;
-        info->n_s = ctx->ncell;
-      }
-      return HS_OK;
-    }
-    if (it >= maxit) {
-      char msg[160];
-      std::snprintf(msg, sizeof msg, "defect correction: ||R||_inf = %.3e > %.3e after %d iterations", rmax, tol, it);
-      return ctx->fail(HS_ERR_NOT_CONVERGED, msg);
-    }
-    if (!std::isfinite(rho)) return ctx->fail(HS_ERR_NONFINITE, "non-finite Jacobian");
-    HS_TRY(linear_solve(ctx, nullptr, rho, std::max(kDefectEta, ctx->p.lin_rtol), q_out, &sweeps));
-  }
+  HS_TRY(paper_solve(ctx, bc, q_out, q_prev, q_prev2, tol, nullptr, info));
+  if (info) info->n_s = ctx->ncell;
+  return HS_OK;
 }
 
 }  // extern "C"

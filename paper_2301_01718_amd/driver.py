@@ -1,7 +1,9 @@
 """Algorithm 1 (hybrid snapshot AROM) on the GPU library.
 
 The driver only sequences the four calls of the C ABI (hdm_step,
-sample_select, rom_hybrid_step, basis_update) and keeps the window of the
+sample_select, rom_hybrid_step, basis_update; with the paper's own scheme
+hdm_step_bdf2 and rom_hybrid_step_bdf2, which also take gamma_{k-2}) and
+keeps the window of the
 last w + 1 snapshots resident in HBM as a ring of device buffers.  The
 schedule follows Alg. 1: full solves for the first w - 1 steps and every z
 steps; after step k (k >= w - 1, step k + 1 not full) the indicator of the
@@ -57,7 +59,7 @@ class Arom:
 
     RING_STAGGER = 320   # doubles between consecutive ring slots beyond N (2560 B: whole 128-B lines)
 
-    def __init__(self, prob, cfg: AromConfig, device="cuda", ctx: Context | None = None):
+    def __init__(self, prob, cfg: AromConfig, device="cuda", ctx: Context | None = None, paper=None):
         self.prob = prob
         self.cfg = cfg
         self.ctx = ctx or Context(prob, m_max=cfg.m, w_max=cfg.w, device=device)
@@ -88,6 +90,12 @@ class Arom:
         # optional: an object with tape(k) -> Tape, called for every hybrid
         # step; the step then records its frozen decisions (adjoint use)
         self.recorder = None
+        # the paper's own scheme (a PaperHDM: MUSCL + minmod, Roe, BDF2 with
+        # gamma_{k-2}, Sec. 3.1) instead of the first-order one; its steps
+        # take the basis once the update is complete
+        self.paper = paper
+        if paper is not None:
+            self.defer_basis = False
 
     def slot(self, k):
         return self.ring[k % (self.cfg.w + 2)]
@@ -121,10 +129,14 @@ class Arom:
             self._complete()
         used = {"q_prev": prev, "Phi": self.Phi, "psi": self.psi, "m": self.m_eff,
                 "basis_version": self.basis_version}
+        prev2 = self.slot(k - 2) if k >= 2 else None
         if hybrid:
             m_arg = BASIS_PENDING if self.pending is not None else self.m_eff
             try:
-                if self.recorder is not None:
+                if self.paper is not None:
+                    _, info = c.rom_hybrid_step_bdf2(self.paper, prev, prev2, self.Phi, self.psi, self.m_eff,
+                                                     self.samples, self.hp, out=out, eps=self.eps)
+                elif self.recorder is not None:
                     _, info = c.rom_hybrid_step_taped(prev, self.Phi, self.psi, m_arg,
                                                       self.recorder.tape(k), TAPE_RECORD,
                                                       samples=self.samples, params=self.hp, out=out,
@@ -143,7 +155,10 @@ class Arom:
             finally:
                 self._complete()        # the step completed the update on every path
                 used["m"] = self.m_eff
-        if not hybrid:
+        if not hybrid and self.paper is not None:
+            _, info = c.hdm_step_bdf2(self.paper, prev, prev2, out=out)
+            rec.update(type="full", n_s=c.ncell, newton=info["newton_iters"], sweeps=info["lin_sweeps"])
+        elif not hybrid:
             _, info = c.hdm_step(prev, out=out)
             rec.update(type="full", n_s=c.ncell, newton=info["newton_iters"], sweeps=info["lin_sweeps"])
         if on_step is not None:

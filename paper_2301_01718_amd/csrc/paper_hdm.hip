@@ -177,25 +177,57 @@ __device__ inline void paper_cell_residual(const Grid& g, const PaperBC& bc, con
   }
 }
 
-__global__ void __launch_bounds__(kBlock) paper_residual_kernel(Grid g, PaperBC bc, const double* __restrict__ q,
-                                                                const double* __restrict__ q1,
-                                                                const double* __restrict__ q2,
-                                                                double* __restrict__ R) {
-  for (int cell = blockIdx.x * blockDim.x + threadIdx.x; cell < g.ncell; cell += gridDim.x * blockDim.x) {
-    double r[4];
-    paper_cell_residual(g, bc, q, q1, q2, cell, r);
+// The block-Jacobi relaxation data of one cell's correction from the
+// first-order Jacobian on grid gj (rhs = -D^-1 R, coef[d] = D^-1 O[d]; with
+// nbr, the couplings to cells outside the sampled set are dropped), and the
+// running max |R| and contraction bound of the thread.
+__device__ inline void relax_data(const Grid& gj, const double* __restrict__ q, int cell, int p, int cap,
+                                  const int* __restrict__ nbr, const double R[4], double* __restrict__ coef,
+                                  double* __restrict__ rhs, double& rmax, double& rho, bool& bad) {
+  Stencil<4> st;
+  load_stencil<4>(gj, q, cell, st);
+  double D[16], O[4][16], Di[16];
+  cell_jacobian<4>(gj, st, D, O);
+  if (nbr) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a) R[a * g.ncell + cell] = r[a];
+    for (int d = 0; d < 4; ++d)
+      if (nbr[d * cap + p] < 0)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) O[d][e] = 0.0;
   }
+  small_inverse<4>(D, Di);
+  double rowsum[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    rmax = nan_max(rmax, fabs(R[a]));
+    bad |= !isfinite(R[a]);
+    double b = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) b -= Di[a * 4 + c] * R[c];
+    rhs[a * cap + p] = b;
+    rowsum[a] = 0.0;
+  }
+#pragma unroll
+  for (int d = 0; d < 4; ++d)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        double m = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) m += Di[a * 4 + c] * O[d][c * 4 + b];
+        coef[((d * 4 + a) * 4 + b) * (size_t)cap + p] = m;
+        rowsum[a] += fabs(m);
+      }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) rho = nan_max(rho, rowsum[a]);
+  if (!isfinite(rho)) bad = true;
 }
 
-// The second-order residual and, from the first-order Jacobian on grid gj,
-// the block-Jacobi relaxation data of the correction (as for the first-order
-// Newton step: rhs = -D^-1 R, coef[d] = D^-1 O[d]), with max |R| and the
-// relaxation's contraction bound as block partials.  On the full mesh
-// (hat == nullptr) or on the compact list hat[0..count) of sampled cells,
-// whose in-set neighbours are nbr[d * cap + p] (the couplings to every other
-// cell are dropped: those entries are held).
+// The residual and the relaxation data of the correction on the compact list
+// hat[0..count) of sampled cells, whose in-set neighbours are nbr[d * cap + p]
+// (the couplings to every other cell are dropped: those entries are held);
+// max |R| and the contraction bound as block partials.
 __global__ void __launch_bounds__(kBlock) paper_resjac_kernel(Grid g, Grid gj, PaperBC bc,
                                                               const double* __restrict__ q,
                                                               const double* __restrict__ q1,
@@ -207,49 +239,11 @@ __global__ void __launch_bounds__(kBlock) paper_resjac_kernel(Grid g, Grid gj, P
   __shared__ double lds[kBlock / kWave];
   double rmax = 0.0, rho = 0.0;
   bool bad = false;
-  const int cap = g.ncell;
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < count; p += gridDim.x * blockDim.x) {
-    const int cell = hat ? hat[p] : p;
+    const int cell = hat[p];
     double R[4];
     paper_cell_residual(g, bc, q, q1, q2, cell, R);
-    Stencil<4> st;
-    load_stencil<4>(gj, q, cell, st);
-    double D[16], O[4][16], Di[16];
-    cell_jacobian<4>(gj, st, D, O);
-    if (hat) {
-#pragma unroll
-      for (int d = 0; d < 4; ++d)
-        if (nbr[d * cap + p] < 0)
-#pragma unroll
-          for (int e = 0; e < 16; ++e) O[d][e] = 0.0;
-    }
-    small_inverse<4>(D, Di);
-    double rowsum[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      rmax = nan_max(rmax, fabs(R[a]));
-      bad |= !isfinite(R[a]);
-      double b = 0.0;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) b -= Di[a * 4 + c] * R[c];
-      rhs[a * cap + p] = b;
-      rowsum[a] = 0.0;
-    }
-#pragma unroll
-    for (int d = 0; d < 4; ++d)
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          double m = 0.0;
-#pragma unroll
-          for (int c = 0; c < 4; ++c) m += Di[a * 4 + c] * O[d][c * 4 + b];
-          coef[((d * 4 + a) * 4 + b) * (size_t)cap + p] = m;
-          rowsum[a] += fabs(m);
-        }
-#pragma unroll
-    for (int a = 0; a < 4; ++a) rho = nan_max(rho, rowsum[a]);
-    if (!isfinite(rho)) bad = true;
+    relax_data(gj, q, cell, p, g.ncell, nbr, R, coef, rhs, rmax, rho, bad);
   }
   rmax = block_max(bad ? INFINITY : rmax, lds);
   rho = block_max(rho, lds);
@@ -259,23 +253,160 @@ __global__ void __launch_bounds__(kBlock) paper_resjac_kernel(Grid g, Grid gj, P
   }
 }
 
-// rcell = cellwise 2-norm of the BDF residual; block sums to the kStatSum partials.
-__global__ void __launch_bounds__(kBlock) paper_norms_kernel(Grid g, PaperBC bc, const double* __restrict__ q,
+// ------------------------------------------------------------ tiled form
+// The full-mesh evaluations by TX x TY tiles (16 x 16; 256 x 1 in 1D): the
+// primitive states of the tile and its two-cell cross halo are formed once
+// into LDS, every face flux of the tile once, then each cell differences its
+// faces.  The arithmetic of each state, slope, face flux and difference is
+// that of the per-cell form, so the two give the same bits; a face on a tile
+// edge is evaluated by both tiles from the same operands.  Tiles go to the
+// blocks XCD by XCD (consecutive tiles share halo rows in that XCD's L2).
+enum PaperTileMode : int { kTileResidual = 0, kTileNorms = 1, kTileResjac = 2 };
+
+template <int TX, int TY>
+struct PaperTile {
+  static constexpr int WR = TY == 1 ? 1 : TY + 4;   // staged rows (1D: the tile's own row)
+  static constexpr int WC = TX + 4;
+  static constexpr int NT = TX * TY;
+  double w[4][WR][WC];
+  double fx[4][TY][TX + 1];
+  double fy[4][TY == 1 ? 1 : TY + 1][TX];
+};
+
+template <int TX, int TY, int MODE>
+__global__ void __launch_bounds__(TX * TY) paper_tile_kernel(Grid g, Grid gj, PaperBC bc,
+                                                             const double* __restrict__ q,
                                                              const double* __restrict__ q1,
-                                                             const double* __restrict__ q2,
-                                                             double* __restrict__ rcell, double* __restrict__ part) {
+                                                             const double* __restrict__ q2, int ntx, int ntiles,
+                                                             double* __restrict__ out, double* __restrict__ coef,
+                                                             double* __restrict__ rhs, double* __restrict__ part) {
 #pragma clang fp contract(off)
-  __shared__ double lds[kBlock / kWave];
-  double acc = 0.0;
-  for (int cell = blockIdx.x * blockDim.x + threadIdx.x; cell < g.ncell; cell += gridDim.x * blockDim.x) {
-    double R[4];
-    paper_cell_residual(g, bc, q, q1, q2, cell, R);
-    const double rn = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2] + R[3] * R[3]);
-    rcell[cell] = rn;
-    acc += rn;
+  using T = PaperTile<TX, TY>;
+  __shared__ T sh;
+  __shared__ double lds[T::NT / kWave];
+  const int nslot = gridDim.x;   // a multiple of 8
+  const int slot0 = (int)(blockIdx.x % 8) * (nslot / 8) + (int)(blockIdx.x / 8);
+  double acc = 0.0, rmax = 0.0, rho = 0.0;
+  bool bad = false;
+  for (int t = slot0; t < ntiles; t += nslot) {
+    const int tx0 = (t % ntx) * TX, ty0 = (t / ntx) * TY;
+    // primitive states: tile cells and the cross halo (no corners), each
+    // position inside the mesh or a ghost on one side only
+    for (int e = threadIdx.x; e < T::WR * T::WC; e += T::NT) {
+      const int lx = e % T::WC, lr = e / T::WC;
+      const int ly = TY == 1 ? 2 : lr;
+      const int gx = tx0 + lx - 2, gy = ty0 + ly - 2;
+      const bool xin = gx >= 0 && gx < g.nx, yin = gy >= 0 && gy < g.ny;
+      const bool col = lx >= 2 && lx < TX + 2, row = ly >= 2 && ly < TY + 2;
+      if (!(col || row) || !(xin || yin) || gx < -2 || gx >= g.nx + 2 || gy < -2 || gy >= g.ny + 2) continue;
+      double st[4], w[4];
+      paper_state(g, bc, q, gx, gy, st);
+      to_primitive(st, g.gamma, w);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) sh.w[a][lr][lx] = w[a];
+    }
+    __syncthreads();
+    // x faces: face fx sits left of tile column fx (cells fx - 1 | fx)
+    for (int e = threadIdx.x; e < (TX + 1) * TY; e += T::NT) {
+      const int fx = e % (TX + 1), fr = e / (TX + 1);
+      if (ty0 + fr >= g.ny || tx0 + fx > g.nx) continue;
+      const int r = TY == 1 ? 0 : fr + 2;
+      double wl[4], wr[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const double* v = sh.w[a][r];
+        const double sl = minmod(v[fx + 1] - v[fx], v[fx + 2] - v[fx + 1]);
+        const double sr = minmod(v[fx + 2] - v[fx + 1], v[fx + 3] - v[fx + 2]);
+        wl[a] = v[fx + 1] + 0.5 * sl;
+        wr[a] = v[fx + 2] - 0.5 * sr;
+      }
+      double F[4];
+      roe_flux(wl, wr, g.gamma, 0, F);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) sh.fx[a][fr][fx] = F[a];
+    }
+    if (TY > 1) {
+      // y faces: face fy sits below tile row fy (cells fy - 1 | fy)
+      for (int e = threadIdx.x; e < TX * (TY + 1); e += T::NT) {
+        const int cx = e % TX, fy = e / TX;
+        if (tx0 + cx >= g.nx || ty0 + fy > g.ny) continue;
+        const int c = cx + 2;
+        double wl[4], wr[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const double v0 = sh.w[a][fy][c], v1 = sh.w[a][fy + 1][c], v2 = sh.w[a][fy + 2][c],
+                       v3 = sh.w[a][fy + 3][c];
+          const double sl = minmod(v1 - v0, v2 - v1);
+          const double sr = minmod(v2 - v1, v3 - v2);
+          wl[a] = v1 + 0.5 * sl;
+          wr[a] = v2 - 0.5 * sr;
+        }
+        double F[4];
+        roe_flux(wl, wr, g.gamma, 1, F);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) sh.fy[a][fy][cx] = F[a];
+      }
+    }
+    __syncthreads();
+    const int cx = threadIdx.x % TX, cy = threadIdx.x / TX;
+    const int gx = tx0 + cx, gy = ty0 + cy;
+    if (gx < g.nx && gy < g.ny) {
+      const int cell = gx + g.nx * gy;
+      double R[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        double f = 0.0;
+        f = f - g.lx * (sh.fx[a][cy][cx + 1] - sh.fx[a][cy][cx]);
+        if (TY > 1) f = f - g.ly * (sh.fy[a][cy + 1][cx] - sh.fy[a][cy][cx]);
+        const int k = a * g.ncell + cell;
+        if (q2) R[a] = q[k] - (2.0 / 3.0) * f + (1.0 / 3.0) * q2[k] - (4.0 / 3.0) * q1[k];
+        else R[a] = q[k] - f - q1[k];
+      }
+      if (MODE == kTileResidual) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) out[a * g.ncell + cell] = R[a];
+      } else if (MODE == kTileNorms) {
+        const double rn = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2] + R[3] * R[3]);
+        out[cell] = rn;
+        acc += rn;
+      } else {
+        relax_data(gj, q, cell, cell, g.ncell, nullptr, R, coef, rhs, rmax, rho, bad);
+      }
+    }
+    __syncthreads();
   }
-  acc = block_sum(acc, lds);
-  if (threadIdx.x == 0) stat_part(part, kStatSum, acc);
+  if (MODE == kTileNorms) {
+    acc = block_sum(acc, lds);
+    if (threadIdx.x == 0) stat_part(part, kStatSum, acc);
+  } else if (MODE == kTileResjac) {
+    rmax = block_max(bad ? INFINITY : rmax, lds);
+    rho = block_max(rho, lds);
+    if (threadIdx.x == 0) {
+      stat_part(part, kStatResMax, rmax);
+      stat_part(part, kStatRho, rho);
+    }
+  }
+}
+
+// Launch of a tiled full-mesh evaluation; *nb: its blocks (the partials).
+template <int MODE>
+static hs_status paper_tiles(hs_ctx* ctx, const Grid& gj, const PaperBC& bc, const double* q, const double* q1,
+                             const double* q2, double* out, int* nb) {
+  const Grid& g = ctx->g;
+  const bool one_d = g.ny == 1;
+  const int TX = one_d ? 256 : 16, TY = one_d ? 1 : 16;
+  const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY;
+  const int ntiles = ntx * nty;
+  // a multiple of 8 blocks, at most the partials' capacity
+  const int grid = std::min((ntiles + 7) / 8 * 8, kPartCap / 8 * 8);
+  *nb = grid;
+  if (one_d)
+    HS_LAUNCH(ctx, (paper_tile_kernel<256, 1, MODE>), grid, 256, g, gj, bc, q, q1, q2, ntx, ntiles, out, ctx->coef,
+              ctx->rhs, ctx->part);
+  else
+    HS_LAUNCH(ctx, (paper_tile_kernel<16, 16, MODE>), grid, 256, g, gj, bc, q, q1, q2, ntx, ntiles, out, ctx->coef,
+              ctx->rhs, ctx->part);
+  return HS_OK;
 }
 
 // Relative accuracy of each relaxed correction: the defect correction itself
@@ -317,10 +448,14 @@ hs_status paper_solve(hs_ctx* ctx, const PaperBC& bc, double* u, const double* q
   const int nb = stat_blocks(count);
   int sweeps = 0;
   for (int it = 0;; ++it) {
-    HS_LAUNCH(ctx, paper_resjac_kernel, nb, kBlock, ctx->g, gj, bc, u, q1, q2, s ? s->hat : nullptr,
-              s ? s->nbr : nullptr, count, ctx->coef, ctx->rhs, ctx->part);
+    int nbs = nb;
+    if (s)
+      HS_LAUNCH(ctx, paper_resjac_kernel, nb, kBlock, ctx->g, gj, bc, u, q1, q2, s->hat, s->nbr, count, ctx->coef,
+                ctx->rhs, ctx->part);
+    else
+      HS_TRY(paper_tiles<kTileResjac>(ctx, gj, bc, u, q1, q2, nullptr, &nbs));
     unsigned long long st[kStatSlots];
-    HS_TRY(finish_stats(ctx, nb, (1u << kStatResMax) | (1u << kStatRho), 0u, st));
+    HS_TRY(finish_stats(ctx, nbs, (1u << kStatResMax) | (1u << kStatRho), 0u, st));
     const double rmax = bits_to_double(st[kStatResMax]);
     const double rho = bits_to_double(st[kStatRho]);
     if (!std::isfinite(rmax)) return ctx->fail(HS_ERR_NONFINITE, "non-finite residual of the paper's scheme");
@@ -344,9 +479,7 @@ hs_status paper_solve(hs_ctx* ctx, const PaperBC& bc, double* u, const double* q
 
 hs_status paper_cell_norms(hs_ctx* ctx, const PaperBC& bc, const double* q, const double* q1, const double* q2,
                            double* rcell, int* nb) {
-  *nb = stat_blocks(ctx->ncell);
-  HS_LAUNCH(ctx, paper_norms_kernel, *nb, kBlock, ctx->g, bc, q, q1, q2, rcell, ctx->part);
-  return HS_OK;
+  return paper_tiles<kTileNorms>(ctx, ctx->g, bc, q, q1, q2, rcell, nb);
 }
 
 }  // namespace hs
@@ -361,8 +494,8 @@ hs_status hs_paper_residual(hs_ctx* ctx, const hs_paper_hdm* hdm, const double* 
   if (R == q || R == q_prev || (q_prev2 && R == q_prev2)) return ctx->fail(HS_ERR_INVALID_ARG, "R aliases an input");
   PaperBC bc;
   HS_TRY(paper_bc(ctx, hdm, &bc));
-  HS_LAUNCH(ctx, paper_residual_kernel, blocks_for(ctx->ncell), kBlock, ctx->g, bc, q, q_prev, q_prev2, R);
-  return HS_OK;
+  int nb;
+  return paper_tiles<kTileResidual>(ctx, ctx->g, bc, q, q_prev, q_prev2, R, &nb);
 }
 
 hs_status hdm_step_bdf2(hs_ctx* ctx, const hs_paper_hdm* hdm, const double* q_prev, const double* q_prev2,

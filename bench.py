@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--adjoint-workload", default="burgers2d_256")
     ap.add_argument("--no-paper", action="store_true",
                     help="skip the paper's experiments (its own scheme: Sod's tube, the implosion)")
+    ap.add_argument("--paper-only", choices=("all", "residual"), default=None,
+                    help="run only the paper's experiments (all) or only its residual kernel's timing (residual)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 1 GiB elementwise copy (counter calibration for rocprofv3 --pmc)")
     return ap.parse_args()
@@ -67,7 +69,8 @@ def log(*a):
 
 
 # the sources each measured kernel is built from (a change voids its counters)
-KERNEL_SOURCES = {"basis_form": ["basis.hip", "dense.hpp", "common.hpp"],
+KERNEL_SOURCES = {"paper_residual": ["paper_hdm.hip", "paper_hdm.hpp", "physics.hpp", "common.hpp"],
+                  "basis_form": ["basis.hip", "dense.hpp", "common.hpp"],
                   "basis_gram": ["basis.hip", "dense.hpp", "common.hpp"],
                   "basis_pgram": ["basis.hip", "dense.hpp", "common.hpp"],
                   "sweep": ["relax.hip", "hdm.hip", "physics.hpp", "common.hpp"]}
@@ -394,7 +397,7 @@ PAPER_IMPLOSION = {"s_bar_pct": 18.35, "s_bar_star_pct": 4.07, "J_bar": 2.73, "s
                    "p_bar_pct": 0.23}
 
 
-def paper_experiments():
+def paper_experiments(residual_only=False):
     """Alg. 1 with the paper's own scheme on its two experiments at full size
     (both through the driver, errors against the full-order run of the same
     scheme on the GPU), and the rate of its residual kernel on a 1024^2
@@ -450,6 +453,8 @@ def paper_experiments():
                 "hybrid_steps": len(hyb), "fallbacks": sum("fallback" in r for r in recs), "seconds": secs}
 
     out = {}
+    if residual_only:
+        return {"residual_kernel": paper_residual_rate()}
     case = W.paper_sod()
     hdm = hs.paper_hdm(case.bc, case.ghost)
     ctx = hs.Context(problem(case), m_max=4, w_max=6)
@@ -477,31 +482,52 @@ def paper_experiments():
     out["implosion"] = {"config": {"n": case.nx, "steps": case.steps, "w": 6, "m": 4, "z": 7, "delta": 0.9,
                                    "filters": [2, 4, 6], "halo": 2}, **r}
     del ref
-    # residual kernel rate on a 1024^2 mesh of random states (BDF2: reads q,
-    # q_{k-1}, q_{k-2}, writes R: 128 bytes per cell)
-    nx = 1024
-    q = [torch.from_numpy(W.random_euler_state(nx, nx, s)).cuda() for s in range(3)]
-    rc = W.PaperCase("random", nx, nx, 1 / nx, 1 / nx, 0.1 / nx, 0, W.GAMMA, W.PAPER_BC_WALL, (), None)
-    ctx = hs.Context(problem(rc), m_max=1, w_max=1)
+    out["residual_kernel"] = paper_residual_rate()
+    return out
+
+
+def paper_residual_rate(nx=1024, reps=20):
+    """hs_paper_residual (BDF2: reads q, q_{k-1}, q_{k-2}, writes R: 128
+    algorithmic bytes per cell) on an nx^2 mesh of random states, each launch
+    bracketed by HIP events on the context's stream."""
+    import numpy as np
+    import torch
+    import workloads as W
+    import paper_2301_01718_amd as hs
+    prob = W.Problem(kind=W.EULER_2D, nx=nx, ny=nx, bc=W.BC_TRANSMISSIVE, dx=1 / nx, dy=1 / nx, dt=0.1 / nx,
+                     gamma=W.GAMMA, inflow=0.0)
+    ctx = hs.Context(prob, m_max=1, w_max=1)
+    q = [torch.from_numpy(W.random_euler_state(nx, nx, s)).to(ctx.device) for s in range(3)]
     wall = hs.paper_hdm(W.PAPER_BC_WALL)
     R = ctx.empty()
     for _ in range(3):
         ctx.paper_residual(wall, q[0], q[1], q[2], out=R)
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
-    for a, b in evs:
-        a.record()
-        ctx.paper_residual(wall, q[0], q[1], q[2], out=R)
-        b.record()
-    torch.cuda.synchronize()
-    us = float(np.median([a.elapsed_time(b) for a, b in evs])) * 1e3
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    with torch.cuda.stream(ctx.stream):
+        for a, b in evs:
+            a.record()
+            ctx.paper_residual(wall, q[0], q[1], q[2], out=R)
+            b.record()
+    torch.cuda.synchronize(ctx.device)
+    us = float(np.mean([a.elapsed_time(b) for a, b in evs])) * 1e3
     by = 128.0 * nx * nx
-    out["residual_kernel"] = {"mesh": [nx, nx], "avg_launch_us": us, "bytes_per_launch": by,
-                              "achieved_GBs": by / (us * 1e-6) / 1e9, "frac_hbm": by / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}
-    return out
+    gbs = by / (us * 1e-6) / 1e9
+    return {"mesh": [nx, nx], "launches": reps, "avg_launch_us": us, "bytes_per_launch": by,
+            "achieved_GBs": gbs, "frac_hbm": gbs / HBM_PEAK_GBS, "traffic": traffic_for("paper_residual", "1024")}
 
 
 def main():
     args = parse()
+    if args.paper_only and args.gpus == 1:
+        out = paper_experiments(args.paper_only == "residual")
+        if args.copy_probe:
+            import torch
+            a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+            b = torch.empty_like(a)
+            torch.add(a, 0.0, out=b)      # one elementwise copy: 1 GiB read + 1 GiB written
+            torch.cuda.synchronize()
+        print(json.dumps({"paper_experiments": out}), flush=True)
+        return 0
     if args.gpus != 1:
         print("bench.py: only one GPU is measured; the hybrid step's multi-GPU (sharded) "
               "layout is a design, not built, so --gpus must be 1.", file=sys.stderr)

@@ -315,11 +315,35 @@ hs_status rom_hybrid_step(hs_ctx* ctx, const double* q_prev, const void* Phi, co
  * after every fit every unsampled entry takes psi + Phi y (info->l reports
  * their count).  Needs an HS_EULER_2D context created with
  * HS_BC_TRANSMISSIVE (its filters extrapolate by zeroth order at the
- * boundaries); m >= 1 (no HS_BASIS_PENDING).  Errors as rom_hybrid_step. */
+ * boundaries); m >= 1 (no HS_BASIS_PENDING).  fit_points (device, n_fit
+ * state entries in sampled cells, e.g. hs_odeim's points): the fit of
+ * eq. red_coord uses those rows only; NULL / 0: every entry of the sampled
+ * cells.  Errors as rom_hybrid_step. */
 hs_status rom_hybrid_step_bdf2(hs_ctx* ctx, const hs_paper_hdm* hdm /* host */, const double* q_prev,
                                const double* q_prev2 /* may be NULL */, const void* Phi, const double* psi,
-                               int32_t m, const hs_samples* s, const hs_hybrid_params* params /* host */,
+                               int32_t m, const hs_samples* s, const int32_t* fit_points /* may be NULL */,
+                               int32_t n_fit, const hs_hybrid_params* params /* host */,
                                double* q_out, double* eps_out, double* y_out, hs_step_info* info /* host */);
+
+/* ODEIM points of a basis (eq. odeim): n_p entries of the state vector
+ * (indices a ncell + cell into the component-major layout) written to
+ * points (device, n_p int32, in the order taken).  The first m are QDEIM's:
+ * step j takes the row phi_i of Phi whose component orthogonal to the rows
+ * already taken is longest (the pivots of a column-pivoted QR of Phi^T).
+ * Each further point maximises the lower bound (g + |phi|^2 - sqrt((g +
+ * |phi|^2)^2 - 4 g (u_1^T phi)^2)) / 2 of the increase of the smallest
+ * eigenvalue of the sampled Gram Phi_P^T Phi_P (l_1 <= l_2 its two smallest
+ * eigenvalues, u_1 the eigenvector of l_1, g = l_2 - l_1; (u_1^T phi)^2 when
+ * m = 1).  Ties go to the lowest index.  Phi: FP64, column-major (column j at
+ * Phi + j N), orthonormal columns.  1 <= m <= min(16, m_max), m <= n_p <= N.
+ * Uses the context's scratch (no call of the context may overlap).  Errors:
+ * HS_ERR_INVALID_ARG. */
+hs_status hs_odeim(hs_ctx* ctx, const double* Phi, int32_t m, int32_t n_p, int32_t* points);
+/* Adds the cells of n_p state entries (as hs_odeim returns them) to the
+ * sampled set s (Sec. 2.3.3: hat-S = G u P) and rebuilds its ring, lists and
+ * neighbour table; n_g is kept.  The fit rows of rom_hybrid_step_bdf2 must
+ * lie in sampled cells: pass the same points as its fit_points. */
+hs_status hs_samples_add_points(hs_ctx* ctx, hs_samples* s, const int32_t* points, int32_t n_p);
 
 /* The residual-gated filter sequence alone (Sec. 2.3.4), on a full state. */
 hs_status hs_filter(hs_ctx* ctx, const double* gamma_in, const double* q_prev,

@@ -25,6 +25,7 @@ import scipy.sparse.linalg as spla
 
 from workloads import BC_TRANSMISSIVE, EULER_2D, Problem
 
+from . import odeim as od
 from . import paper_hdm as ph
 from . import pod, sampling
 from .arom import AromParams, is_full_step, wants_update
@@ -115,21 +116,25 @@ def spatial_filter(prob: ph.PaperProblem, gamma, q1, q2, params: HybridParams, l
     return gamma
 
 
-def hybrid_step(prob: ph.PaperProblem, q1, q2, Phi, psi, hat, params: HybridParams = None):
-    """One hybrid snapshot gamma_k from gamma_{k-1} = q1 (and q_{k-2} = q2)."""
+def hybrid_step(prob: ph.PaperProblem, q1, q2, Phi, psi, hat, params: HybridParams = None, fit_points=None):
+    """One hybrid snapshot gamma_k from gamma_{k-1} = q1 (and q_{k-2} = q2).
+    With fit_points (entries of the state, their cells sampled) the fit of
+    eq. red_coord uses those rows only; otherwise every entry of the sampled
+    cells."""
     params = params or HybridParams()
     hat = np.asarray(hat)
     mask = np.zeros(prob.ncell, dtype=bool)
     mask[hat] = True
     tilde = np.flatnonzero(ring(prob, mask))
     hd, td = dofs(prob, hat), dofs(prob, tilde)
-    Phi_hat = Phi[hd]
+    fd = hd if fit_points is None else np.asarray(fit_points, dtype=np.int64)
+    Phi_fit = Phi[fd]
     u = q1.copy()
     y_old, newton, dy, J = None, [], [], 0
     for j in range(1, params.jmax + 1):
         u, its = partial_solve(prob, u, q1, q2, hat)
         newton.append(its)
-        y = fit(Phi_hat, u[hd] - psi[hd], params.rcond_fit)
+        y = fit(Phi_fit, u[fd] - psi[fd], params.rcond_fit)
         u[td] = psi[td] + Phi[td] @ y
         J = j
         if y_old is not None:
@@ -147,9 +152,13 @@ def hybrid_step(prob: ph.PaperProblem, q1, q2, Phi, psi, hat, params: HybridPara
             "filter_log": flog, "masks": masks, "l": int(tilde.size)}
 
 
-def run(prob: ph.PaperProblem, q0, steps, p: AromParams, keep_all=False, on_step=None):
+def run(prob: ph.PaperProblem, q0, steps, p: AromParams, keep_all=False, on_step=None, odeim_factor=0):
     """Alg. 1 with this scheme (the schedule, updates and fallback of
-    oracle.arom.run).  Returns dict(q, records, gammas)."""
+    oracle.arom.run).  With odeim_factor > 0 the sampled set of each hybrid
+    step also holds the cells of n_p = odeim_factor m_eff ODEIM points of its
+    basis (eq. odeim; Alg. 1: P_{k+1} from Phi_{k+1}, then the union with G),
+    and the fit uses those points only (eq. red_coord).  Returns dict(q,
+    records, gammas)."""
     v = view(prob)
     gammas = [q0.copy()]
     basis, samples, records = None, None, []
@@ -162,10 +171,11 @@ def run(prob: ph.PaperProblem, q0, steps, p: AromParams, keep_all=False, on_step
         eps = None
         if hybrid_ok:
             try:
-                out = hybrid_step(prob, q1, q2, basis[0], basis[1], samples["hat"], p.hybrid)
+                out = hybrid_step(prob, q1, q2, basis[0], basis[1], samples["hat"], p.hybrid,
+                                  fit_points=samples.get("points"))
                 g, eps = out["gamma"], out["eps"]
                 rec.update(type="hybrid", n_s=int(samples["hat"].size), l=out["l"], J=out["J"],
-                           newton=out["newton"])
+                           newton=out["newton"], n_p=len(samples.get("points", ())))
             except NotConverged:
                 hybrid_ok = False
         if not hybrid_ok:
@@ -185,6 +195,10 @@ def run(prob: ph.PaperProblem, q0, steps, p: AromParams, keep_all=False, on_step
             b = pod.pod(window, p.w, p.m, p.tau_pod)
             basis = (b["Phi"], b["psi_new"])
             rec["m_eff"] = b["m_eff"]
+            if odeim_factor and samples is not None and b["m_eff"] > 0:
+                pts = od.odeim(b["Phi"], min(odeim_factor * b["m_eff"], prob.n))
+                hat = np.union1d(samples["hat"], od.cells_of(pts, prob.ncell)).astype(np.int32)
+                samples = {**samples, "hat": hat, "points": pts}
         records.append(rec)
         if on_step is not None:
             on_step(k, g, rec)

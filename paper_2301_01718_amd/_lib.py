@@ -116,8 +116,10 @@ _SIGS = {
     "hdm_step": [P, P, P, ctypes.POINTER(StepInfo)],
     "hs_paper_residual": [P, ctypes.POINTER(PaperHDM), P, P, P, P],
     "hdm_step_bdf2": [P, ctypes.POINTER(PaperHDM), P, P, P, ctypes.POINTER(StepInfo)],
-    "rom_hybrid_step_bdf2": [P, ctypes.POINTER(PaperHDM), P, P, P, P, I32, P, ctypes.POINTER(HybridParams), P, P, P,
-                             ctypes.POINTER(StepInfo)],
+    "rom_hybrid_step_bdf2": [P, ctypes.POINTER(PaperHDM), P, P, P, P, I32, P, P, I32, ctypes.POINTER(HybridParams),
+                             P, P, P, ctypes.POINTER(StepInfo)],
+    "hs_odeim": [P, P, I32, I32, P],
+    "hs_samples_add_points": [P, P, P, I32],
     "hs_samples_create": [P, ctypes.POINTER(P)],
     "hs_samples_destroy": [P],
     "sample_select": [P, P, ctypes.POINTER(SampleParams), P],
@@ -439,16 +441,32 @@ class Context:
         return out, info.as_dict()
 
     def rom_hybrid_step_bdf2(self, hdm, q_prev, q_prev2, Phi, psi, m, samples, params=None, out=None, eps=None,
-                             y=None):
-        """rom_hybrid_step with the paper's scheme (hdm: PaperHDM; q_prev2 may be None)."""
+                             y=None, fit_points=None):
+        """rom_hybrid_step with the paper's scheme (hdm: PaperHDM; q_prev2 may
+        be None; fit_points: int32 state entries for the fit, or None)."""
         params = _with_precision(params or hybrid_params(), self._basis(Phi, m))
         out = self.empty() if out is None else out
         info = StepInfo()
         p2 = None if q_prev2 is None else _ptr(self._in(q_prev2))
+        nf = 0 if fit_points is None else fit_points.numel()
+        fp = None if fit_points is None else _ptr(self._in(fit_points, nf, torch.int32))
         self._check(lib().rom_hybrid_step_bdf2(self.h, ctypes.byref(hdm), _ptr(self._in(q_prev)), p2, _ptr(Phi),
-                                               _ptr(self._in(psi)), m, samples.h, ctypes.byref(params),
+                                               _ptr(self._in(psi)), m, samples.h, fp, nf, ctypes.byref(params),
                                                _ptr(self._in(out)), _ptr(eps), _ptr(y), ctypes.byref(info)))
         return out, info.as_dict()
+
+    def odeim(self, Phi, m, n_p, out=None):
+        """hs_odeim: n_p ODEIM points (int32 state entries, in the order taken)."""
+        if Phi.dtype != torch.float64 or not Phi.is_contiguous() or Phi.numel() < m * self.n:
+            raise ValueError("ODEIM needs a contiguous float64 basis of at least m x N entries")
+        out = torch.empty(n_p, dtype=torch.int32, device=self.device) if out is None else out
+        self._check(lib().hs_odeim(self.h, _ptr(Phi), m, n_p, _ptr(self._in(out, n_p, torch.int32))))
+        return out
+
+    def samples_add_points(self, samples, points):
+        self._check(lib().hs_samples_add_points(self.h, samples.h, _ptr(self._in(points, points.numel(), torch.int32)),
+                                                points.numel()))
+        return samples
 
     def filter(self, gamma, q_prev, params=None, out=None):
         params = params or hybrid_params()

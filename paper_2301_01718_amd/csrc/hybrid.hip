@@ -1180,26 +1180,29 @@ static int pad16(int m) { return (m + 15) / 16 * 16; }
 
 template <typename TP>
 static hs_status launch_project_t(hs_ctx* ctx, const TP* Phi, int m, const int* hat, int ns, const double* u,
-                                  const double* psi, const double* y0, int mode, int nb) {
+                                  const double* psi, const double* y0, int mode, int nb, int nc) {
   const long long n = ctx->n;
   switch (pad16(m)) {
-    case 16: HS_LAUNCH(ctx, (project_kernel<16, TP>), nb, kBlock, Phi, n, m, ctx->nc, ctx->ncell, hat, ns, u, psi, y0, mode, ctx->red); break;
-    case 32: HS_LAUNCH(ctx, (project_kernel<32, TP>), nb, kBlock, Phi, n, m, ctx->nc, ctx->ncell, hat, ns, u, psi, y0, mode, ctx->red); break;
-    case 48: HS_LAUNCH(ctx, (project_kernel<48, TP>), nb, kBlock, Phi, n, m, ctx->nc, ctx->ncell, hat, ns, u, psi, y0, mode, ctx->red); break;
-    default: HS_LAUNCH(ctx, (project_kernel<64, TP>), nb, kBlock, Phi, n, m, ctx->nc, ctx->ncell, hat, ns, u, psi, y0, mode, ctx->red); break;
+    case 16: HS_LAUNCH(ctx, (project_kernel<16, TP>), nb, kBlock, Phi, n, m, nc, ctx->ncell, hat, ns, u, psi, y0, mode, ctx->red); break;
+    case 32: HS_LAUNCH(ctx, (project_kernel<32, TP>), nb, kBlock, Phi, n, m, nc, ctx->ncell, hat, ns, u, psi, y0, mode, ctx->red); break;
+    case 48: HS_LAUNCH(ctx, (project_kernel<48, TP>), nb, kBlock, Phi, n, m, nc, ctx->ncell, hat, ns, u, psi, y0, mode, ctx->red); break;
+    default: HS_LAUNCH(ctx, (project_kernel<64, TP>), nb, kBlock, Phi, n, m, nc, ctx->ncell, hat, ns, u, psi, y0, mode, ctx->red); break;
   }
   return HS_OK;
 }
 
-// Phi is double (HS_FP64) or float (HS_MIXED_FP32).
+// Phi is double (HS_FP64) or float (HS_MIXED_FP32).  The rows are every
+// component of the listed cells, or (nc = 1) the listed entries themselves.
 static hs_status launch_project(hs_ctx* ctx, const void* Phi, int prec, int m, const int* hat, int ns,
-                                const double* u, const double* psi, const double* y0, int mode, int* nb_out) {
-  const long long rows = hat ? (long long)ctx->nc * ns : ctx->n;
+                                const double* u, const double* psi, const double* y0, int mode, int* nb_out,
+                                int nc = -1) {
+  if (nc < 0) nc = ctx->nc;
+  const long long rows = hat ? (long long)nc * ns : ctx->n;
   const int nb = (int)std::max<long long>(1, std::min<long long>((rows + kBlock - 1) / kBlock, 512));
   *nb_out = nb;
   if (prec == HS_MIXED_FP32)
-    return launch_project_t(ctx, (const float*)Phi, m, hat, ns, u, psi, y0, mode, nb);
-  return launch_project_t(ctx, (const double*)Phi, m, hat, ns, u, psi, y0, mode, nb);
+    return launch_project_t(ctx, (const float*)Phi, m, hat, ns, u, psi, y0, mode, nb, nc);
+  return launch_project_t(ctx, (const double*)Phi, m, hat, ns, u, psi, y0, mode, nb, nc);
 }
 
 template <typename TP>
@@ -1234,21 +1237,23 @@ static hs_status reconstruct(hs_ctx* ctx, const void* Phi, int prec, int m, cons
 // the basis entries in either storage precision).
 template <typename TP>
 static hs_status launch_fit_gram(hs_ctx* ctx, const TP* Phi, int m, const int* hat, int ns, int nb, int wp,
-                                 long long rows) {
-  GatherLoader<TP> ld{Phi, (long long)ctx->n, m, ctx->nc, ctx->ncell, ns, hat};
+                                 long long rows, int nc) {
+  GatherLoader<TP> ld{Phi, (long long)ctx->n, m, nc, ctx->ncell, ns, hat};
   const size_t lds = (size_t)kChunk * (wp + 1) * sizeof(double);
   hipLaunchKernelGGL(gram_kernel<GatherLoader<TP>>, dim3(nb), dim3(256), lds, ctx->stream, ld, rows, wp, ctx->red);
   HIP_TRY(ctx, hipGetLastError());
   return HS_OK;
 }
 
-static hs_status fit_factor(hs_ctx* ctx, const void* Phi, int prec, int m, const int* hat, int ns, double rcond) {
+static hs_status fit_factor(hs_ctx* ctx, const void* Phi, int prec, int m, const int* hat, int ns, double rcond,
+                            int nc = -1) {
+  if (nc < 0) nc = ctx->nc;
   const int wp = pad16(m);
-  const long long rows = hat ? (long long)ctx->nc * ns : ctx->n;
+  const long long rows = hat ? (long long)nc * ns : ctx->n;
   const long long nchunks = (rows + kChunk - 1) / kChunk;
   const int nb = (int)std::max<long long>(1, std::min<long long>(nchunks, 512));
-  if (prec == HS_MIXED_FP32) HS_TRY(launch_fit_gram(ctx, (const float*)Phi, m, hat, ns, nb, wp, rows));
-  else HS_TRY(launch_fit_gram(ctx, (const double*)Phi, m, hat, ns, nb, wp, rows));
+  if (prec == HS_MIXED_FP32) HS_TRY(launch_fit_gram(ctx, (const float*)Phi, m, hat, ns, nb, wp, rows, nc));
+  else HS_TRY(launch_fit_gram(ctx, (const double*)Phi, m, hat, ns, nb, wp, rows, nc));
   HS_LAUNCH(ctx, gram_reduce_kernel, m * m, kBlock, ctx->red, nb, wp, m, ctx->small + kSmG);
   if (ctx->small_pinv && m >= 1 && m <= 8)
     HS_LAUNCH(ctx, pinv_small_kernel, 1, kWave, ctx->small + kSmG, m, rcond, ctx->small + kSmGp,
@@ -1261,13 +1266,13 @@ static hs_status fit_factor(hs_ctx* ctx, const void* Phi, int prec, int m, const
 
 // y = pinv fit of (u - psi) on the rows, with one refinement step.
 static hs_status fit_solve(hs_ctx* ctx, const void* Phi, int prec, int m, const int* hat, int ns, const double* u,
-                           const double* psi, int first) {
+                           const double* psi, int first, int nc = -1) {
   double* sm = ctx->small;
   int nb;
-  HS_TRY(launch_project(ctx, Phi, prec, m, hat, ns, u, psi, nullptr, 0, &nb));
+  HS_TRY(launch_project(ctx, Phi, prec, m, hat, ns, u, psi, nullptr, 0, &nb, nc));
   HS_LAUNCH(ctx, project_finish_kernel, 1, 256, ctx->red, nb, pad16(m), m, sm + kSmGp, 0, sm + kSmY0, sm + kSmY,
             sm + kSmYPrev, sm + kSmMisc, first, (unsigned long long*)nullptr);
-  HS_TRY(launch_project(ctx, Phi, prec, m, hat, ns, u, psi, sm + kSmY0, 1, &nb));
+  HS_TRY(launch_project(ctx, Phi, prec, m, hat, ns, u, psi, sm + kSmY0, 1, &nb, nc));
   HS_LAUNCH(ctx, project_finish_kernel, 1, 256, ctx->red, nb, pad16(m), m, sm + kSmGp, 1, sm + kSmY0, sm + kSmY,
             sm + kSmYPrev, sm + kSmMisc, first, ctx->stats);
   return HS_OK;
@@ -1499,8 +1504,8 @@ static hs_status paper_filter(hs_ctx* ctx, const PaperBC& bc, double* gamma, con
 // cells that residual reads).
 static hs_status hybrid_paper_impl(hs_ctx* ctx, const hs_paper_hdm* hdm, const double* q_prev, const double* q_prev2,
                                    const void* Phi, const double* psi, int m, const hs_samples* s,
-                                   const hs_hybrid_params* hp, double* q_out, double* eps_out, double* y_out,
-                                   hs_step_info* info) {
+                                   const int32_t* fit_points, int32_t n_fit, const hs_hybrid_params* hp,
+                                   double* q_out, double* eps_out, double* y_out, hs_step_info* info) {
   if (!ctx || !hdm || !q_prev || !Phi || !psi || !hp || !q_out || !s) return HS_ERR_INVALID_ARG;
   if (q_out == q_prev || q_out == psi || (const void*)q_out == Phi || (q_prev2 && q_out == q_prev2))
     return ctx->fail(HS_ERR_INVALID_ARG, "q_out aliases an input");
@@ -1517,6 +1522,11 @@ static hs_status hybrid_paper_impl(hs_ctx* ctx, const hs_paper_hdm* hdm, const d
   const int prec = hp->precision;
   if (prec != HS_FP64 && prec != HS_MIXED_FP32) return HS_ERR_INVALID_ARG;
   if (s->n_s == 0) return ctx->fail(HS_ERR_RANK, "empty sampled set");
+  if (n_fit < 0 || n_fit > ctx->n || (n_fit > 0 && !fit_points)) return ctx->fail(HS_ERR_INVALID_ARG, "fit points");
+  // the fit's rows: every entry of the sampled cells, or the given entries
+  const int* frows = n_fit > 0 ? fit_points : s->hat;
+  const int nfr = n_fit > 0 ? n_fit : s->n_s;
+  const int fnc = n_fit > 0 ? 1 : ctx->nc;
   hs_step_info local{};
   hs_step_info* inf = info ? info : &local;
   std::memset(inf, 0, sizeof *inf);
@@ -1527,7 +1537,7 @@ static hs_status hybrid_paper_impl(hs_ctx* ctx, const hs_paper_hdm* hdm, const d
   double* sm = ctx->small;
   HS_TRY(max_abs_launch(ctx, q_prev, ctx->n));
   HIP_TRY(ctx, hipMemcpyAsync(u, q_prev, ctx->n * 8, hipMemcpyDeviceToDevice, ctx->stream));
-  HS_TRY(fit_factor(ctx, Phi, prec, m, s->hat, s->n_s, hp->rcond_fit));
+  HS_TRY(fit_factor(ctx, Phi, prec, m, frows, nfr, hp->rcond_fit, fnc));
   unsigned long long st[kStatSlots];
   HS_TRY(read_stats(ctx, st));
   const double qmax = bits_to_double(st[kStatQMax]);
@@ -1538,7 +1548,7 @@ static hs_status hybrid_paper_impl(hs_ctx* ctx, const hs_paper_hdm* hdm, const d
   if (inf->fit_rank == 0) return ctx->fail(HS_ERR_RANK, "rank-zero fit");
   for (int j = 1; j <= hp->jmax; ++j) {
     HS_TRY(paper_solve(ctx, bc, u, q_prev, q_prev2, tol, s, inf));
-    HS_TRY(fit_solve(ctx, Phi, prec, m, s->hat, s->n_s, u, psi, j == 1));
+    HS_TRY(fit_solve(ctx, Phi, prec, m, frows, nfr, u, psi, j == 1, fnc));
     // unsampled entries (the ring among them) = psi + Phi y; rho = psi + Phi y
     HS_TRY(reconstruct(ctx, Phi, prec, m, psi, sm + kSmY, s->mask, u, u_next, ctx->rho));
     std::swap(u, u_next);
@@ -1609,9 +1619,10 @@ hs_status rom_hybrid_step(hs_ctx* ctx, const double* q_prev, const void* Phi, co
 
 hs_status rom_hybrid_step_bdf2(hs_ctx* ctx, const hs_paper_hdm* hdm, const double* q_prev, const double* q_prev2,
                                const void* Phi, const double* psi, int32_t m, const hs_samples* s,
-                               const hs_hybrid_params* hp, double* q_out, double* eps_out, double* y_out,
-                               hs_step_info* info) {
-  return hybrid_paper_impl(ctx, hdm, q_prev, q_prev2, Phi, psi, m, s, hp, q_out, eps_out, y_out, info);
+                               const int32_t* fit_points, int32_t n_fit, const hs_hybrid_params* hp,
+                               double* q_out, double* eps_out, double* y_out, hs_step_info* info) {
+  return hybrid_paper_impl(ctx, hdm, q_prev, q_prev2, Phi, psi, m, s, fit_points, n_fit, hp, q_out, eps_out, y_out,
+                           info);
 }
 
 hs_status rom_hybrid_step_taped(hs_ctx* ctx, const double* q_prev, const void* Phi, const double* psi,

@@ -778,6 +778,15 @@ static hs_status finish_sets(hs_ctx* ctx, hs_samples* s, const long long* ngd = 
   return HS_OK;
 }
 
+// mask[point % ncell] = 1 for entries of the state vector (points < nc ncell).
+__global__ void point_cells_kernel(const int32_t* __restrict__ points, int np, int ncell, long long n,
+                                   uint8_t* __restrict__ mask) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const int p = points[i];
+  if (p >= 0 && p < n) mask[p % ncell] = 1;
+}
+
 }  // namespace hs
 
 using namespace hs;
@@ -887,6 +896,16 @@ hs_status hs_samples_set(hs_ctx* ctx, hs_samples* s, const int32_t* hat, int32_t
   HS_TRY(finish_sets(ctx, s));
   if (s->n_s != n_s) return ctx->fail(HS_ERR_INVALID_ARG, "hat list has duplicates or out-of-range cells");
   s->n_g = n_s;
+  return HS_OK;
+}
+
+hs_status hs_samples_add_points(hs_ctx* ctx, hs_samples* s, const int32_t* points, int32_t n_p) {
+  if (!ctx || !s || s->ctx != ctx || n_p < 0 || (n_p > 0 && !points)) return HS_ERR_INVALID_ARG;
+  if (n_p == 0) return HS_OK;
+  HS_LAUNCH(ctx, point_cells_kernel, blocks_for(n_p), kBlock, points, n_p, ctx->ncell, (long long)ctx->n, s->mask);
+  const int n_g = s->n_g;
+  HS_TRY(finish_sets(ctx, s));
+  s->n_g = n_g;
   return HS_OK;
 }
 

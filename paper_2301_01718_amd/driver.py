@@ -41,6 +41,9 @@ class AromConfig:
     rcond_fit: float = 1e-8
     floor_rel: float = 1e-14
     precision: int = FP64
+    # with the paper's scheme: ODEIM points (eq. odeim), n_p = odeim_factor
+    # m_eff, join the sampled set and are the fit's rows (eq. red_coord); 0: none
+    odeim_factor: int = 0
 
 
 def is_full_step(k, w, z):
@@ -96,6 +99,7 @@ class Arom:
         self.paper = paper
         if paper is not None:
             self.defer_basis = False
+        self.points = None
 
     def slot(self, k):
         return self.ring[k % (self.cfg.w + 2)]
@@ -135,7 +139,9 @@ class Arom:
             try:
                 if self.paper is not None:
                     _, info = c.rom_hybrid_step_bdf2(self.paper, prev, prev2, self.Phi, self.psi, self.m_eff,
-                                                     self.samples, self.hp, out=out, eps=self.eps)
+                                                     self.samples, self.hp, out=out, eps=self.eps,
+                                                     fit_points=self.points)
+                    rec["n_p"] = 0 if self.points is None else self.points.numel()
                 elif self.recorder is not None:
                     _, info = c.rom_hybrid_step_taped(prev, self.Phi, self.psi, m_arg,
                                                       self.recorder.tape(k), TAPE_RECORD,
@@ -193,11 +199,17 @@ class Arom:
                 nxt_hybrid = (not is_full_step(k + 1, cfg.w, cfg.z) and self.have_samples and k < self.steps)
                 if on_update is not None or not self.defer_basis or not nxt_hybrid:
                     self._complete()
+            self.points = None
+            if self.paper is not None and cfg.odeim_factor > 0 and self.have_samples and self.m_eff > 0:
+                # P_{k+1} = ODEIM(Phi_{k+1}) and hat-S = G u P (Alg. 1), the basis complete
+                n_p = min(cfg.odeim_factor * self.m_eff, c.n)
+                self.points = c.odeim(self.Phi, self.m_eff, n_p)
+                c.samples_add_points(self.samples, self.points)
             self.basis_version += 1
             if on_update is not None:
                 on_update(k, rec, {"eps": self.eps, "samples": self.samples if self.have_samples else None,
                                    "window": window, "Phi": self.Phi, "psi": self.psi,
-                                   "sigma": self.sigma, "m_eff": self.m_eff})
+                                   "sigma": self.sigma, "m_eff": self.m_eff, "points": self.points})
         return rec
 
     def state(self):

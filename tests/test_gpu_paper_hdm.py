@@ -272,7 +272,8 @@ def test_paper_hybrid_step_matches_oracle(which):
     assert ok, d
 
 
-def test_paper_arom_sod_trajectory_resync():
+@pytest.mark.parametrize("halo,odeim_factor", [(2, 0), (0, 2)])
+def test_paper_arom_sod_trajectory_resync(halo, odeim_factor):
     """Alg. 1 on Sod's tube (100 cells, 201 steps; w = 5, m = 4, delta = 0.8,
     z = 5, filters 2/4/6) through the driver, every step recomputed by the
     oracle from the GPU's inputs to it (gamma_{k-1}, gamma_{k-2}, the basis
@@ -286,7 +287,10 @@ def test_paper_arom_sod_trajectory_resync():
       span within the Wedin bound of both SVDs);
     * sampled set: the oracle's selection from the oracle's indicator, bit for
       bit, or a near tie of the relative-energy cut (|RRE - delta| <= 1e-9);
-    * hybrid step: J equal, state 1e-12 relative, indicator cell by cell."""
+    * hybrid step: J equal, state 1e-12 relative, indicator cell by cell;
+    * with ODEIM points (n_p = 2 m_eff, no halo: hat-S = G u P as the paper
+      has it): the oracle's points on the GPU's basis, in the same order (a
+      near tie of the scores accepted), hat-S the union, the fit over them."""
     need_gpu()
     from paper_2301_01718_amd.driver import Arom, AromConfig
     import paper_2301_01718_amd as hs
@@ -296,9 +300,10 @@ def test_paper_arom_sod_trajectory_resync():
     prob = oracle_problem(case)
     v = pa.view(prob)
     n = prob.n
-    cfg = AromConfig(w=w, m=m, z=5, rule=hs.RULE_RRE, delta=delta, halo=2)
+    cfg = AromConfig(w=w, m=m, z=5, rule=hs.RULE_RRE, delta=delta, halo=halo, odeim_factor=odeim_factor)
     drv = Arom(problem(case), cfg, paper=hs.paper_hdm(case.bc, case.ghost))
-    st = {"hist": [case.q0], "eps_o": None, "used": None, "sets_o": None, "worst": 0.0, "ties": [], "hyb": 0}
+    st = {"hist": [case.q0], "eps_o": None, "used": None, "sets_o": None, "worst": 0.0, "ties": [], "hyb": 0,
+          "points": None}
 
     def on_step(k, rec, used, out):
         qp, g = host(used["q_prev"]), host(out)
@@ -318,7 +323,7 @@ def test_paper_arom_sod_trajectory_resync():
                 assert np.array_equal(hat, st["sets_o"]), k
             me = used["m"]
             Phi = host(used["Phi"])[: me * n].reshape(me, n).T.copy()
-            ref = pa.hybrid_step(prob, qp, qp2, Phi, host(used["psi"]), hat)
+            ref = pa.hybrid_step(prob, qp, qp2, Phi, host(used["psi"]), hat, fit_points=st["points"])
             assert rec["J"] == ref["J"], (k, rec["J"], ref["J"])
             e = rel(g, ref["gamma"])
             assert e <= 1e-12, (k, "hybrid", e)
@@ -342,13 +347,21 @@ def test_paper_arom_sod_trajectory_resync():
         d = np.linalg.norm(Q @ (Q.T @ X) - b["Phi"] @ (b["Phi"].T @ X)) / np.linalg.norm(X)
         assert d <= projector_tol(so, me), (k, "projector", d)
         st["sets_o"] = None
+        st["points"] = None
         if s["samples"] is not None:
             eps_o = st["eps_o"]
             if eps_o is None:
                 Phi_u, psi_u = st["used"]
                 eps_o, _ = sampling.indicator_full(v, window[-1], Phi_u, psi_u)
-            sel = sampling.select(v, eps_o, sampling.RULE_RRE, delta=delta, halo=2)
+            sel = sampling.select(v, eps_o, sampling.RULE_RRE, delta=delta, halo=halo)
             hat = host(s["samples"].export()[0])
+            if odeim_factor and s["points"] is not None:
+                pts = host(s["points"]).tolist()
+                agree = odeim_agree(P, pts, len(pts))
+                if agree < len(pts):
+                    st["ties"].append((k, "points", agree))
+                st["points"] = np.asarray(pts)
+                sel["hat"] = np.union1d(sel["hat"], odeim.cells_of(pts, prob.ncell)).astype(np.int32)
             if np.array_equal(hat, sel["hat"]):
                 st["sets_o"] = sel["hat"]
             else:
@@ -364,14 +377,16 @@ def test_paper_arom_sod_trajectory_resync():
     assert st["hyb"] > 100
 
 
-def test_sod_paper_experiment_full_size():
+@pytest.mark.parametrize("halo,odeim_factor", [(2, 0), (0, 2)])
+def test_sod_paper_experiment_full_size(halo, odeim_factor):
     """Sec. 3.2's experiment at the paper's size (N = 499, N_t = 999, w = 5,
-    m = 4, delta = 0.8, filters 2/4/6, z = 5) through the driver: the mean
-    relative L1 error of the snapshots against the full-order run (e-bar,
-    Sec. 3.1) stays below 0.5 % (the paper prints 0.122 % for this setting,
-    with ODEIM points in the fit that this build does not have), at least
-    half of the steps are hybrid, and the hybrid steps sample less than a
-    quarter of the mesh."""
+    m = 4, delta = 0.8, filters 2/4/6, z = 5) through the driver, with a
+    2-cell halo around G and the fit over the sampled cells, or as the paper
+    has it (hat-S = G u P, n_p = 2 m ODEIM points, the fit over them): the
+    mean relative L1 error of the snapshots against the full-order run
+    (e-bar, Sec. 3.1) stays below 0.5 % (the paper prints 0.122 % for this
+    setting), at least half of the steps are hybrid, and the hybrid steps
+    sample less than a quarter of the mesh."""
     need_gpu()
     from paper_2301_01718_amd.driver import Arom, AromConfig
     import paper_2301_01718_amd as hs
@@ -382,7 +397,7 @@ def test_sod_paper_experiment_full_size():
     for k in range(case.steps):
         out, _ = ctx.hdm_step_bdf2(hdm, ref[-1], ref[-2] if k >= 1 else None)
         ref.append(out)
-    cfg = AromConfig(w=5, m=4, z=5, rule=hs.RULE_RRE, delta=0.8, halo=2)
+    cfg = AromConfig(w=5, m=4, z=5, rule=hs.RULE_RRE, delta=0.8, halo=halo, odeim_factor=odeim_factor)
     drv = Arom(problem(case), cfg, paper=hdm)
     errs = []
     _, recs = drv.run(dev(case.q0), case.steps,
@@ -392,6 +407,100 @@ def test_sod_paper_experiment_full_size():
     sbar = np.mean([r["n_s"] / case.nx for r in recs])
     sbar_h = np.mean([r["n_s"] / case.nx for r in hyb])
     print(f"e-bar {100 * np.mean(errs):.4f} %  max {100 * max(errs):.4f} %  s-bar {100 * sbar:.2f} %  "
-          f"s-bar* {100 * sbar_h:.2f} %  J-bar {np.mean([r['J'] for r in hyb]):.2f}  hybrid {len(hyb)}/{case.steps}")
+          f"s-bar* {100 * sbar_h:.2f} %  p-bar {np.mean([r.get('n_p', 0) for r in hyb]):.1f}  "
+          f"J-bar {np.mean([r['J'] for r in hyb]):.2f}  hybrid {len(hyb)}/{case.steps}")
     assert np.mean(errs) < 0.005
     assert len(hyb) > case.steps // 2 and sbar_h < 0.25
+
+
+# ------------------------------------------------------- ODEIM points (eq. odeim)
+
+from oracle import odeim  # noqa: E402
+
+
+def odeim_agree(Phi, pts_gpu, n_p, tie_rel=1e-12):
+    """The GPU's points against the oracle's, step by step: equal, or at the
+    first difference a near tie of the oracle's own scores (the two choices
+    within tie_rel of the best score); returns the number of points compared
+    before such a tie (n_p when all agree)."""
+    pts_o = odeim.odeim(Phi, n_p)
+    for k, (a, b) in enumerate(zip(pts_gpu, pts_o)):
+        if a == b:
+            continue
+        # the oracle's scores at step k on the common prefix
+        n, m = Phi.shape
+        taken = np.zeros(n, bool)
+        taken[pts_o[:k]] = True
+        if k < m:
+            Q = np.zeros((m, 0))
+            for p in pts_o[:k]:
+                v = Phi[p].copy()
+                for _ in range(2):
+                    v = v - Q @ (Q.T @ v)
+                Q = np.column_stack([Q, v / np.linalg.norm(v)])
+            pr = Phi @ Q
+            sc = np.einsum("ij,ij->i", Phi, Phi) - np.einsum("ij,ij->i", pr, pr)
+        else:
+            M = Phi[pts_o[:k]].T @ Phi[pts_o[:k]]
+            lam, U = np.linalg.eigh(M)
+            sc = odeim.bound_gain(lam[0], lam[1] if m > 1 else None, U[:, 0], Phi)
+        sc[taken] = -np.inf
+        assert not taken[a] and abs(sc[a] - sc[b]) <= tie_rel * max(1e-300, abs(sc[b])), (k, a, b, sc[a], sc[b])
+        return k
+    return n_p
+
+
+@pytest.mark.parametrize("m,fac", [(1, 3), (4, 2), (8, 2), (16, 2)])
+def test_odeim_points_match_oracle(m, fac):
+    """hs_odeim on random orthonormal bases with localised columns (the shape
+    of POD modes near moving waves), 2D Euler mesh 30 x 20 (2400 entries):
+    the same points in the same order as the oracle (integer decisions; a
+    near tie of the scores is accepted and ends the comparison)."""
+    need_gpu()
+    print_case("hs_odeim", m, fac)
+    rng = np.random.default_rng(m)
+    case = W.PaperCase("r", 30, 20, 1 / 30, 1 / 20, 1e-3, 0, W.GAMMA, W.PAPER_BC_WALL, (), None)
+    n = 4 * 30 * 20
+    x = np.linspace(0, 1, n)
+    A = np.stack([np.exp(-((x - c) / 0.02) ** 2) + 0.01 * rng.standard_normal(n) for c in rng.uniform(0.1, 0.9, m)],
+                 axis=1)
+    Phi, _ = np.linalg.qr(A)
+    import paper_2301_01718_amd as hs
+    ctx = hs.Context(problem(case), m_max=16, w_max=16)
+    pts = host(ctx.odeim(dev(np.ascontiguousarray(Phi.T).reshape(-1)), m, fac * m)).tolist()
+    agree = odeim_agree(Phi, pts, fac * m)
+    print("points", pts, "agree", agree)
+    assert len(set(pts)) == fac * m and agree == fac * m
+
+
+def test_paper_hybrid_step_with_odeim_matches_oracle():
+    """The hybrid step with the ODEIM points as the fit's rows (eq. red_coord)
+    and their cells added to the sampled set (hat-S = G u P), from the
+    oracle's mid-run Sod state: same J and filter passes, state within 1e-12
+    relative, indicator cell by cell."""
+    need_gpu()
+    case = W.paper_sod()
+    K, w, m = 40, 5, 4
+    prob, states, b, sel = _mid_run(case, K, w, m, 0.8)
+    me = b["m_eff"]
+    ctx, hdm = context(case)
+    Phi = dev(np.ascontiguousarray(b["Phi"].T).reshape(-1))
+    pts = ctx.odeim(Phi, me, 2 * me)
+    assert odeim_agree(b["Phi"], host(pts).tolist(), 2 * me) == 2 * me
+    hat = np.union1d(sel["hat"], odeim.cells_of(host(pts), prob.ncell)).astype(np.int32)
+    import paper_2301_01718_amd as hs
+    eps_o, _ = sampling.indicator_full(pa.view(prob), states[K], b["Phi"], b["psi_new"])
+    s = ctx.sample_select(dev(eps_o), 0.0, halo=2, rule=hs.RULE_RRE, delta=0.8)
+    ctx.samples_add_points(s, pts)
+    assert np.array_equal(host(s.export()[0]), hat)
+    g1, g2 = states[K], states[K - 1]
+    ref = pa.hybrid_step(prob, g1, g2, b["Phi"], b["psi_new"], hat, fit_points=host(pts))
+    eps_g = ctx.empty(prob.ncell)
+    out, info = ctx.rom_hybrid_step_bdf2(hdm, dev(g1), dev(g2), Phi, dev(b["psi_new"]), me, s, eps=eps_g,
+                                         fit_points=pts)
+    d = rel(host(out), ref["gamma"])
+    print(f"n_s {hat.size} points {host(pts).tolist()} J {info['subiters']}/{ref['J']} state {d:.3e}")
+    assert info["subiters"] == ref["J"] and info["filter_passes"] == len(ref["filter_log"])
+    assert d < state_tol(info["fit_cond"], tol=1e-12)
+    ok, dd = indicator_close(host(eps_g), ref["eps"], ref["gamma"], tol=1e-12, cell_tol=1e-10)
+    assert ok, dd

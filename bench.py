@@ -424,7 +424,7 @@ def paper_experiments(residual_only=False):
         return ref, time.perf_counter() - t
 
     def arom(case, hdm, ref, **kw):
-        cfg = D.AromConfig(rule=hs.RULE_RRE, halo=2, **kw)
+        cfg = D.AromConfig(rule=hs.RULE_RRE, **kw)
         drv = D.Arom(problem(case), cfg, paper=hdm)
         q0 = torch.from_numpy(case.q0).to(drv.ctx.device)
         drv.start(q0, case.steps)
@@ -450,6 +450,8 @@ def paper_experiments(residual_only=False):
                 "s_bar_pct": 100 * float(np.mean([r["n_s"] / n for r in recs])),
                 "s_bar_star_pct": 100 * float(np.mean([r["n_s"] / n for r in hyb])) if hyb else None,
                 "J_bar": float(np.mean([r["J"] for r in hyb])) if hyb else None,
+                "p_bar": float(np.mean([r.get("n_p", 0) for r in hyb])) if hyb else None,
+                "p_bar_pct_of_entries": 100 * float(np.mean([r.get("n_p", 0) for r in hyb])) / (4 * n) if hyb else None,
                 "hybrid_steps": len(hyb), "fallbacks": sum("fallback" in r for r in recs), "seconds": secs}
 
     out = {}
@@ -459,28 +461,37 @@ def paper_experiments(residual_only=False):
     hdm = hs.paper_hdm(case.bc, case.ghost)
     ctx = hs.Context(problem(case), m_max=4, w_max=6)
     ref, t_full = full_order(case, hdm, ctx)
-    runs = {}
-    for z in ("inf", "15", "5", "2"):
-        log(f"Sod, z = {z} ...")
-        zz = 10 ** 9 if z == "inf" else int(z)
-        r = arom(case, hdm, ref, w=5, m=4, z=zz, delta=0.8)
-        r["paper"] = PAPER_SOD[z]
-        runs[z] = r
-    out["sod"] = {"config": {"nx": case.nx, "steps": case.steps, "w": 5, "m": 4, "delta": 0.8,
-                             "filters": [2, 4, 6], "halo": 2},
-                  "full_order_s": t_full, "by_z": runs}
+    variants = {"paper_sets": {"halo": 0, "odeim_factor": 2}, "halo2_no_odeim": {"halo": 2, "odeim_factor": 0}}
+    sod = {"config": {"nx": case.nx, "steps": case.steps, "w": 5, "m": 4, "delta": 0.8, "filters": [2, 4, 6],
+                      "variants": {"paper_sets": "hat-S = G u P, n_p = 2 m_eff ODEIM points, the fit over them",
+                                   "halo2_no_odeim": "hat-S = G dilated by 2 cells, the fit over every sampled entry"}},
+           "full_order_s": t_full}
+    for name, kw in variants.items():
+        runs = {}
+        for z in ("inf", "15", "5", "2"):
+            log(f"Sod ({name}), z = {z} ...")
+            zz = 10 ** 9 if z == "inf" else int(z)
+            r = arom(case, hdm, ref, w=5, m=4, z=zz, delta=0.8, **kw)
+            r["paper"] = PAPER_SOD[z]
+            runs[z] = r
+        sod[name] = runs
+    out["sod"] = sod
     del ref
     log("implosion ...")
     case = W.paper_implosion()
     hdm = hs.paper_hdm(case.bc)
     ctx = hs.Context(problem(case), m_max=4, w_max=6)
     ref, t_full = full_order(case, hdm, ctx)
-    r = arom(case, hdm, ref, w=6, m=4, z=7, delta=0.9)
-    r["speedup_S_wall"] = t_full / r["seconds"]
-    r["full_order_s"] = t_full
-    r["paper"] = PAPER_IMPLOSION
-    out["implosion"] = {"config": {"n": case.nx, "steps": case.steps, "w": 6, "m": 4, "z": 7, "delta": 0.9,
-                                   "filters": [2, 4, 6], "halo": 2}, **r}
+    imp = {"config": {"n": case.nx, "steps": case.steps, "w": 6, "m": 4, "z": 7, "delta": 0.9, "filters": [2, 4, 6],
+                      "variants": {"paper_sets": "hat-S = G u P, n_p = 2 m_eff ODEIM points, the fit over them",
+                                   "halo1_odeim": "hat-S = (G dilated by 1 cell) u P, n_p = 2 m_eff, the fit over P"}},
+           "full_order_s": t_full, "paper": PAPER_IMPLOSION}
+    for name, kw in (("paper_sets", {"halo": 0, "odeim_factor": 2}), ("halo1_odeim", {"halo": 1, "odeim_factor": 2})):
+        log(f"implosion ({name}) ...")
+        r = arom(case, hdm, ref, w=6, m=4, z=7, delta=0.9, **kw)
+        r["speedup_S_wall"] = t_full / r["seconds"]
+        imp[name] = r
+    out["implosion"] = imp
     del ref
     out["residual_kernel"] = paper_residual_rate()
     return out

@@ -307,6 +307,24 @@ hs_status rom_hybrid_step(hs_ctx* ctx, const double* q_prev, const void* Phi, co
                           int32_t m, const hs_samples* s, const hs_hybrid_params* params /* host */,
                           double* q_out, double* eps_out, double* y_out, hs_step_info* info /* host */);
 
+/* One hybrid snapshot whose subiterations are Gauss-Newton steps on the
+ * reduced coordinates (Sec. 2.3.2 with the sampled solution's dependence on
+ * the ring values kept): minimise |Phi_S y - (v(y) - psi_S)| where v(y)
+ * solves the partial HDM (eq. partial_hdm2) with the ring at psi + Phi y;
+ * dv/dy = -J_S^-1 J_T Phi_T (J_S, J_T: the sampled rows of the Jacobian on
+ * the sampled and ring columns), so each step takes m relaxed solves with
+ * J_S into work and the pseudo-inverse of A^T A, A = Phi_S + J_S^-1 J_T Phi_T.
+ * The first iterate is the paper's first subiteration; the loop stops when
+ * ||dy||_2 < eps_y or after jmax iterations (info->subiters), and a final
+ * partial solve makes the sampled values consistent with the last y.  The
+ * reconstruction, filter and indicator are rom_hybrid_step's.  FP64 basis
+ * (params->precision = HS_FP64) and the context's first-order scheme.
+ * work: device, m N doubles (caller-owned scratch).  Errors as
+ * rom_hybrid_step. */
+hs_status rom_hybrid_step_gn(hs_ctx* ctx, const double* q_prev, const double* Phi, const double* psi, int32_t m,
+                             const hs_samples* s, const hs_hybrid_params* params /* host */, double* work,
+                             double* q_out, double* eps_out, double* y_out, hs_step_info* info /* host */);
+
 /* One hybrid snapshot with the paper's own scheme (Sec. 3.1; see
  * hs_paper_hdm): rom_hybrid_step with the BDF residual (q_prev2 =
  * gamma_{k-2}; NULL: BDF1) in the partial solve (eq. partial_hdm2, by the

@@ -119,6 +119,7 @@ _SIGS = {
     "rom_hybrid_step_bdf2": [P, ctypes.POINTER(PaperHDM), P, P, P, P, I32, P, P, I32, ctypes.POINTER(HybridParams),
                              P, P, P, ctypes.POINTER(StepInfo)],
     "hs_odeim": [P, P, I32, I32, P],
+    "rom_hybrid_step_gn": [P, P, P, P, I32, P, ctypes.POINTER(HybridParams), P, P, P, P, ctypes.POINTER(StepInfo)],
     "hs_samples_add_points": [P, P, P, I32],
     "hs_samples_create": [P, ctypes.POINTER(P)],
     "hs_samples_destroy": [P],
@@ -453,6 +454,19 @@ class Context:
         self._check(lib().rom_hybrid_step_bdf2(self.h, ctypes.byref(hdm), _ptr(self._in(q_prev)), p2, _ptr(Phi),
                                                _ptr(self._in(psi)), m, samples.h, fp, nf, ctypes.byref(params),
                                                _ptr(self._in(out)), _ptr(eps), _ptr(y), ctypes.byref(info)))
+        return out, info.as_dict()
+
+    def rom_hybrid_step_gn(self, q_prev, Phi, psi, m, samples, params=None, out=None, eps=None, y=None, work=None):
+        """The hybrid step with Gauss-Newton subiterations (FP64 basis)."""
+        params = _with_precision(params or hybrid_params(), FP64)
+        if Phi.dtype != torch.float64 or not Phi.is_contiguous() or Phi.numel() < m * self.n:
+            raise ValueError("Gauss-Newton subiterations need a contiguous float64 basis of at least m x N entries")
+        out = self.empty() if out is None else out
+        work = self.empty(m * self.n) if work is None else work
+        info = StepInfo()
+        self._check(lib().rom_hybrid_step_gn(self.h, _ptr(self._in(q_prev)), _ptr(Phi), _ptr(self._in(psi)), m,
+                                             samples.h, ctypes.byref(params), _ptr(self._in(work, m * self.n)),
+                                             _ptr(self._in(out)), _ptr(eps), _ptr(y), ctypes.byref(info)))
         return out, info.as_dict()
 
     def odeim(self, Phi, m, n_p, out=None):

@@ -1438,6 +1438,238 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const void* Phi,
   return HS_OK;
 }
 
+// ------------------------------------------- Gauss-Newton subiterations
+// Rows of the misfit's Jacobian A = Phi_S + X (X = J_S^-1 J_T Phi_T, column
+// j at X + j N in the compact layout a ncell + p of the sampled list): the
+// gathered rows of Phi plus those of X, for the Gram A^T A on MFMA.
+struct GnLoader {
+  const double* Phi;
+  const double* X;
+  long long n;
+  int m, nc, ncell, ns;
+  const int* hat;
+  struct Regs {
+    double v[kMaxBasis / 4];
+  };
+  __device__ void init(Regs&) const {}
+  __device__ void prefetch(long long row0, Regs& R) const {
+    const int r = threadIdx.x % kChunk;
+    const long long row = row0 + r;
+    long long dof = -1, xo = 0;
+    if (row < (long long)nc * ns) {
+      const int a = (int)(row / ns), p = (int)(row % ns);
+      dof = (long long)a * ncell + hat[p];
+      xo = (long long)a * ncell + p;
+    }
+#pragma unroll
+    for (int i = 0; i < kMaxBasis / 4; ++i) {
+      const int j = threadIdx.x / kChunk + 4 * i;
+      R.v[i] = (dof >= 0 && j < m) ? Phi[(size_t)j * n + dof] + X[(size_t)j * n + xo] : 0.0;
+    }
+  }
+  __device__ void commit(long long, const Regs& R, double* Xl, int ldx, int wp) const {
+    const int r = threadIdx.x % kChunk;
+#pragma unroll
+    for (int i = 0; i < kMaxBasis / 4; ++i) {
+      const int j = threadIdx.x / kChunk + 4 * i;
+      if (j < wp) Xl[r * ldx + j] = R.v[i];
+    }
+  }
+};
+
+// out = D^-1 J_T phi on the sampled list: for each sampled cell the
+// Jacobian blocks of its neighbours outside the sampled set (the ring; a
+// ghost that copies the cell is part of D, an inflow ghost is constant)
+// applied to column phi of the basis, then the cell's diagonal block
+// inverted (the right-hand side of the relaxation of J_S x = J_T phi).
+template <int NC>
+__global__ void __launch_bounds__(kBlock) gn_coupling_kernel(Grid g, const double* __restrict__ u,
+                                                             const int* __restrict__ hat,
+                                                             const int* __restrict__ nbr, int count,
+                                                             const double* __restrict__ phi,
+                                                             double* __restrict__ out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= count) return;
+  const int cap = g.ncell;
+  const int cell = hat[p];
+  Stencil<NC> st;
+  load_stencil<NC>(g, u, cell, st);
+  double D[NC * NC], O[4][NC * NC], Di[NC * NC];
+  cell_jacobian<NC>(g, st, D, O);
+  small_inverse<NC>(D, Di);
+  double b[NC];
+#pragma unroll
+  for (int a = 0; a < NC; ++a) b[a] = 0.0;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const int nb = st.idx[d];
+    if (nbr[d * cap + p] >= 0 || nb < 0 || nb == cell) continue;
+#pragma unroll
+    for (int a = 0; a < NC; ++a)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) b[a] += O[d][a * NC + c] * phi[(size_t)c * g.ncell + nb];
+  }
+#pragma unroll
+  for (int a = 0; a < NC; ++a) {
+    double v = 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) v += Di[a * NC + c] * b[c];
+    out[(size_t)a * cap + p] = v;
+  }
+}
+
+// Per-block partials of -A^T r over the sampled rows, r = Phi_S y - (u_S - psi_S).
+template <int MP>
+__global__ void __launch_bounds__(256) gn_grad_kernel(const double* __restrict__ Phi, const double* __restrict__ X,
+                                                      long long n, int m, int nc, int ncell,
+                                                      const int* __restrict__ hat, int ns,
+                                                      const double* __restrict__ u,
+                                                      const double* __restrict__ psi,
+                                                      const double* __restrict__ y, double* __restrict__ part) {
+  __shared__ double yl[MP];
+  __shared__ double wsum[4][MP];
+  for (int j = threadIdx.x; j < MP; j += blockDim.x) yl[j] = j < m ? y[j] : 0.0;
+  __syncthreads();
+  double acc[MP];
+#pragma unroll
+  for (int j = 0; j < MP; ++j) acc[j] = 0.0;
+  const long long rows = (long long)nc * ns;
+  for (long long row = blockIdx.x * (long long)blockDim.x + threadIdx.x; row < rows;
+       row += (long long)gridDim.x * blockDim.x) {
+    const long long a = row / ns, p = row % ns;
+    const long long dof = a * ncell + hat[p], xo = a * ncell + p;
+    double ph[MP];
+    double r = 0.0;
+#pragma unroll
+    for (int j = 0; j < MP; ++j) {
+      ph[j] = j < m ? Phi[(size_t)j * n + dof] : 0.0;
+      r += ph[j] * yl[j];
+    }
+    r -= u[dof] - psi[dof];
+#pragma unroll
+    for (int j = 0; j < MP; ++j) acc[j] -= (j < m ? ph[j] + X[(size_t)j * n + xo] : 0.0) * r;
+  }
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int j = 0; j < MP; ++j) {
+    const double v = wave_sum(acc[j]);
+    if (lane == 0) wsum[wave][j] = v;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < m; j += blockDim.x)
+    part[(size_t)blockIdx.x * MP + j] = ((wsum[0][j] + wsum[1][j]) + wsum[2][j]) + wsum[3][j];
+}
+
+// One Gauss-Newton subiteration's step after the partial solve in u: the
+// relaxation data of the sampled Jacobian at u, X by m relaxed solves into
+// work, A^T A and its pseudo-inverse, y <- y - (A^T A)^+ A^T r; ||dy|| to the
+// statistics.
+template <int NC>
+static hs_status gn_step(hs_ctx* ctx, const double* Phi, int m, const hs_samples* s, const double* psi,
+                         const double* q_prev, double rcond, double* work, hs_step_info* inf) {
+  double* sm = ctx->small;
+  const long long n = ctx->n;
+  unsigned long long st[kStatSlots];
+  HS_TRY(newton_first_launch(ctx, ctx->u, q_prev, s, st));
+  const double rho = bits_to_double(st[kStatRho]);
+  for (int k = 0; k < m; ++k) {
+    HS_LAUNCH(ctx, gn_coupling_kernel<NC>, blocks_for(s->n_s), kBlock, ctx->g, (const double*)ctx->u, s->hat,
+              s->nbr, s->n_s, Phi + (size_t)k * n, ctx->adj);
+    int sweeps = 0;
+    HS_TRY(relax_solve(ctx, s, ctx->coef, ctx->adj, rho, ctx->p.lin_rtol, work + (size_t)k * n, &sweeps));
+    inf->lin_sweeps += sweeps;
+  }
+  // A^T A on MFMA and its pseudo-inverse (rank and condition to the statistics)
+  const int wp = pad16(m);
+  const long long rows = (long long)NC * s->n_s;
+  const long long nchunks = (rows + kChunk - 1) / kChunk;
+  const int nb = (int)std::max<long long>(1, std::min<long long>(nchunks, 512));
+  GnLoader ld{Phi, work, n, m, NC, ctx->ncell, s->n_s, s->hat};
+  const size_t lds = (size_t)kChunk * (wp + 1) * sizeof(double);
+  hipLaunchKernelGGL(gram_kernel<GnLoader>, dim3(nb), dim3(256), lds, ctx->stream, ld, rows, wp, ctx->red);
+  HIP_TRY(ctx, hipGetLastError());
+  HS_LAUNCH(ctx, gram_reduce_kernel, m * m, kBlock, ctx->red, nb, wp, m, sm + kSmG);
+  if (ctx->small_pinv && m <= 8)
+    HS_LAUNCH(ctx, pinv_small_kernel, 1, kWave, sm + kSmG, m, rcond, sm + kSmGp, sm + kSmMisc, ctx->stats);
+  else
+    HS_LAUNCH(ctx, pinv_kernel, 1, 256, sm + kSmG, m, rcond, sm + kSmGp, sm + kSmMisc, ctx->stats, ctx->fit_chol);
+  // y0 = y_prev = y; y = y0 + G+ (-A^T r)
+  HIP_TRY(ctx, hipMemcpyAsync(sm + kSmY0, sm + kSmY, m * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(sm + kSmYPrev, sm + kSmY, m * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  const int nbg = (int)std::max<long long>(1, std::min<long long>((rows + kBlock - 1) / kBlock, 512));
+  switch (wp) {
+    case 16: HS_LAUNCH(ctx, gn_grad_kernel<16>, nbg, 256, Phi, (const double*)work, n, m, NC, ctx->ncell, s->hat, s->n_s, (const double*)ctx->u, psi, (const double*)(sm + kSmY), ctx->red); break;
+    case 32: HS_LAUNCH(ctx, gn_grad_kernel<32>, nbg, 256, Phi, (const double*)work, n, m, NC, ctx->ncell, s->hat, s->n_s, (const double*)ctx->u, psi, (const double*)(sm + kSmY), ctx->red); break;
+    case 48: HS_LAUNCH(ctx, gn_grad_kernel<48>, nbg, 256, Phi, (const double*)work, n, m, NC, ctx->ncell, s->hat, s->n_s, (const double*)ctx->u, psi, (const double*)(sm + kSmY), ctx->red); break;
+    default: HS_LAUNCH(ctx, gn_grad_kernel<64>, nbg, 256, Phi, (const double*)work, n, m, NC, ctx->ncell, s->hat, s->n_s, (const double*)ctx->u, psi, (const double*)(sm + kSmY), ctx->red); break;
+  }
+  HS_LAUNCH(ctx, project_finish_kernel, 1, 256, ctx->red, nbg, wp, m, sm + kSmGp, 1, sm + kSmY0, sm + kSmY,
+            sm + kSmYPrev, sm + kSmMisc, 0, ctx->stats);
+  return HS_OK;
+}
+
+// The hybrid step with Gauss-Newton subiterations on the reduced coordinates
+// (the first iterate is the paper's first subiteration); FP64 basis.
+static hs_status hybrid_gn_impl(hs_ctx* ctx, const double* q_prev, const double* Phi, const double* psi, int m,
+                                const hs_samples* s, const hs_hybrid_params* hp, double* work, double* q_out,
+                                double* eps_out, double* y_out, hs_step_info* info) {
+  if (!ctx || !q_prev || !Phi || !psi || !hp || !q_out || !s || !work) return HS_ERR_INVALID_ARG;
+  if (q_out == q_prev || q_out == psi || q_out == Phi || s->ctx != ctx) return HS_ERR_INVALID_ARG;
+  if (m < 1 || m > ctx->p.m_max) return ctx->fail(HS_ERR_RANK, "empty basis");
+  if (hp->precision != HS_FP64) return ctx->fail(HS_ERR_INVALID_ARG, "Gauss-Newton subiterations need an FP64 basis");
+  if (hp->jmax < 1 || hp->n_orders < 0 || hp->n_orders > 4 || !(hp->rcond_fit > 0) || !(hp->eps_y >= 0))
+    return HS_ERR_INVALID_ARG;
+  for (int o = 0; o < hp->n_orders; ++o)
+    if (hp->filter_orders[o] < 1 || hp->filter_orders[o] > 3) return HS_ERR_INVALID_ARG;
+  if (s->n_s == 0) return ctx->fail(HS_ERR_RANK, "empty sampled set");
+  hs_step_info local{};
+  hs_step_info* inf = info ? info : &local;
+  std::memset(inf, 0, sizeof *inf);
+  inf->n_s = s->n_s;
+  inf->l = s->l;
+  double* u = ctx->u;
+  double* sm = ctx->small;
+  HS_TRY(max_abs_launch(ctx, q_prev, ctx->n));
+  HIP_TRY(ctx, hipMemcpyAsync(u, q_prev, ctx->n * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  HS_TRY(fit_factor(ctx, Phi, HS_FP64, m, s->hat, s->n_s, hp->rcond_fit));
+  unsigned long long st[kStatSlots];
+  HS_TRY(read_stats(ctx, st));
+  const double qmax = bits_to_double(st[kStatQMax]);
+  if (!std::isfinite(qmax)) return ctx->fail(HS_ERR_NONFINITE, "non-finite q_prev");
+  const double tol = ctx->p.newton_rtol * std::max(1.0, qmax);
+  inf->fit_rank = (int)bits_to_double(st[kStatFitRank]);
+  inf->fit_cond = bits_to_double(st[kStatFitCond]);
+  if (inf->fit_rank == 0) return ctx->fail(HS_ERR_RANK, "rank-zero fit");
+  // the first iterate: the paper's first subiteration
+  HS_TRY(newton_solve(ctx, u, q_prev, tol, s, inf));
+  HS_TRY(fit_solve(ctx, Phi, HS_FP64, m, s->hat, s->n_s, u, psi, 1));
+  inf->subiters = 1;
+  for (int j = 2; j <= hp->jmax; ++j) {
+    if (s->l > 0) HS_TRY(ring_update(ctx, Phi, HS_FP64, m, s, psi, sm + kSmY, u));
+    HS_TRY(newton_solve(ctx, u, q_prev, tol, s, inf));
+    if (ctx->nc == 1) HS_TRY(gn_step<1>(ctx, Phi, m, s, psi, q_prev, hp->rcond_fit, work, inf));
+    else HS_TRY(gn_step<4>(ctx, Phi, m, s, psi, q_prev, hp->rcond_fit, work, inf));
+    HS_TRY(read_stats(ctx, st));
+    inf->subiters = j;
+    inf->dy_last = bits_to_double(st[kStatDy]);
+    if (!std::isfinite(inf->dy_last)) return ctx->fail(HS_ERR_NONFINITE, "non-finite Gauss-Newton step");
+    if (inf->dy_last < hp->eps_y) break;
+  }
+  // the sampled values consistent with the final coordinates
+  if (s->l > 0) HS_TRY(ring_update(ctx, Phi, HS_FP64, m, s, psi, sm + kSmY, u));
+  HS_TRY(newton_solve(ctx, u, q_prev, tol, s, inf));
+  HS_TRY(reconstruct(ctx, Phi, HS_FP64, m, psi, sm + kSmY, s->mask, u, q_out, ctx->rho));
+  HS_TRY(run_filter(ctx, q_out, q_prev, hp, inf, nullptr));
+  if (eps_out) {
+    int nbq;
+    HS_TRY(max_abs_partials(ctx, q_out, ctx->n, &nbq));
+    HS_LAUNCH(ctx, indicator_kernel, blocks_for(ctx->ncell), kBlock, ctx->ncell, ctx->nc, q_out, ctx->rho,
+              hp->floor_rel, (const double*)ctx->part, nbq, eps_out);
+  }
+  if (y_out) HIP_TRY(ctx, hipMemcpyAsync(y_out, sm + kSmY, m * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  return hs_sync(ctx);
+}
+
 // ------------------------------------------ the paper's full-order scheme
 // Gate of one filter pass with precomputed norms: keep the filtered value
 // where its cell residual norm rf is below r (all components), count the kept
@@ -1615,6 +1847,12 @@ hs_status rom_hybrid_step(hs_ctx* ctx, const double* q_prev, const void* Phi, co
                           const hs_samples* s, const hs_hybrid_params* hp, double* q_out, double* eps_out,
                           double* y_out, hs_step_info* info) {
   return hybrid_impl(ctx, q_prev, Phi, psi, m, s, hp, q_out, eps_out, y_out, info, nullptr, -1);
+}
+
+hs_status rom_hybrid_step_gn(hs_ctx* ctx, const double* q_prev, const double* Phi, const double* psi, int32_t m,
+                             const hs_samples* s, const hs_hybrid_params* hp, double* work, double* q_out,
+                             double* eps_out, double* y_out, hs_step_info* info) {
+  return hybrid_gn_impl(ctx, q_prev, Phi, psi, m, s, hp, work, q_out, eps_out, y_out, info);
 }
 
 hs_status rom_hybrid_step_bdf2(hs_ctx* ctx, const hs_paper_hdm* hdm, const double* q_prev, const double* q_prev2,

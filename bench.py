@@ -497,6 +497,38 @@ def paper_experiments(residual_only=False):
     return out
 
 
+def gauss_newton_bench(drv, reps=3):
+    """The next step of the timed run (same state, basis and sampled set)
+    with the paper's frozen subiterations and with Gauss-Newton ones
+    (rom_hybrid_step_gn): wall time per step, iterations, and each output's
+    relative L2 distance to the full-order step from the same state."""
+    import numpy as np
+    import torch
+    if not drv.have_samples or drv.m_eff < 1:
+        return None
+    c = drv.ctx
+    q, m = drv.state().clone(), drv.m_eff
+    full, _ = c.hdm_step(q)
+    work = c.empty(m * c.n)
+    out = {}
+    for name, call in (("frozen", lambda: c.rom_hybrid_step(q, drv.Phi, drv.psi, m, drv.samples, drv.hp)),
+                       ("gauss_newton", lambda: c.rom_hybrid_step_gn(q, drv.Phi, drv.psi, m, drv.samples, drv.hp,
+                                                                     work=work))):
+        g, info = call()
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize(c.device)
+            t = time.perf_counter()
+            g, info = call()
+            torch.cuda.synchronize(c.device)
+            ts.append(time.perf_counter() - t)
+        out[name] = {"ms": 1e3 * float(np.median(ts)), "J": info["subiters"], "dy_last": info["dy_last"],
+                     "rel_to_full_step": float(torch.linalg.vector_norm(g - full) / torch.linalg.vector_norm(full))}
+    out["m"] = m
+    out["n_s"] = drv.samples.counts()["n_s"]
+    return out
+
+
 def paper_residual_rate(nx=1024, reps=20):
     """hs_paper_residual (BDF2: reads q, q_{k-1}, q_{k-2}, writes R: 128
     algorithmic bytes per cell) on an nx^2 mesh of random states, each launch
@@ -617,6 +649,11 @@ def main():
         th.append(time.perf_counter() - t)
     t_H = float(np.median(th))
 
+    gnb = None
+    if not args.no_paper:
+        log("Gauss-Newton subiterations on the next step ...")
+        gnb = gauss_newton_bench(drv)
+
     log("residual kernel rates ...")
     prev_state = drv.slot(drv.k - 1).clone()
     resk = residual_kernels(prob, drv.state(), prev_state, args.seed)
@@ -706,6 +743,7 @@ def main():
         "adjoint": adj,
         "other_workloads": others,
         "paper_experiments": paper,
+        "gauss_newton": gnb,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -462,7 +462,7 @@ class Context:
         if Phi.dtype != torch.float64 or not Phi.is_contiguous() or Phi.numel() < m * self.n:
             raise ValueError("Gauss-Newton subiterations need a contiguous float64 basis of at least m x N entries")
         out = self.empty() if out is None else out
-        work = self.empty(m * self.n) if work is None else work
+        work = self.empty(m * self.n) if work is None else work[: m * self.n]   # at least m N doubles
         info = StepInfo()
         self._check(lib().rom_hybrid_step_gn(self.h, _ptr(self._in(q_prev)), _ptr(Phi), _ptr(self._in(psi)), m,
                                              samples.h, ctypes.byref(params), _ptr(self._in(work, m * self.n)),

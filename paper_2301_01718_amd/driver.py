@@ -44,6 +44,8 @@ class AromConfig:
     # with the paper's scheme: ODEIM points (eq. odeim), n_p = odeim_factor
     # m_eff, join the sampled set and are the fit's rows (eq. red_coord); 0: none
     odeim_factor: int = 0
+    # Gauss-Newton subiterations (rom_hybrid_step_gn; first-order scheme, FP64)
+    gauss_newton: bool = False
 
 
 def is_full_step(k, w, z):
@@ -100,6 +102,12 @@ class Arom:
         if paper is not None:
             self.defer_basis = False
         self.points = None
+        self.gn_work = None
+        if cfg.gauss_newton:
+            if cfg.precision != FP64 or paper is not None:
+                raise ValueError("Gauss-Newton subiterations run with the first-order scheme on an FP64 basis")
+            self.gn_work = c.empty(cfg.m * c.n)
+            self.defer_basis = False
 
     def slot(self, k):
         return self.ring[k % (self.cfg.w + 2)]
@@ -142,6 +150,9 @@ class Arom:
                                                      self.samples, self.hp, out=out, eps=self.eps,
                                                      fit_points=self.points)
                     rec["n_p"] = 0 if self.points is None else self.points.numel()
+                elif self.gn_work is not None:
+                    _, info = c.rom_hybrid_step_gn(prev, self.Phi, self.psi, self.m_eff, self.samples, self.hp,
+                                                   out=out, eps=self.eps, work=self.gn_work)
                 elif self.recorder is not None:
                     _, info = c.rom_hybrid_step_taped(prev, self.Phi, self.psi, m_arg,
                                                       self.recorder.tape(k), TAPE_RECORD,

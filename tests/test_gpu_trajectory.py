@@ -31,7 +31,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import arom, fv, hybrid, pod, sampling
+from oracle import arom, fv, gauss_newton, hybrid, pod, sampling
 
 from gpu_common import dev, fit_tols, host, indicator_close, need_gpu, print_case, projector_tol, rel
 
@@ -68,14 +68,21 @@ def gate_flips(k, masks_gpu, masks_o, norms_o, scale):
     return flips
 
 
-def run_resync(wl, seed, steps, check_from=1, tol=1e-12):
+def run_resync(wl, seed, steps, check_from=1, tol=1e-12, gn=False):
+    """gn: the hybrid steps with Gauss-Newton subiterations on both sides."""
     import paper_2301_01718_amd.driver as D
     prob, q0 = W.make(wl, seed)
     n = prob.n
     hp = hybrid.HybridParams()
-    cfg = D.AromConfig(w=wl.w, m=wl.m, z=wl.z, fraction=wl.frac, halo=wl.halo)
+    cfg = D.AromConfig(w=wl.w, m=wl.m, z=wl.z, fraction=wl.frac, halo=wl.halo, gauss_newton=gn)
     drv = D.Arom(prob, cfg)
-    drv.recorder = _Tapes(drv.ctx)
+    if not gn:
+        drv.recorder = _Tapes(drv.ctx)
+
+    def step(qp, Phi, psi, hat, tilde, norms=None):
+        if gn:
+            return gauss_newton.gn_hybrid_step(prob, qp, Phi, psi, hat, tilde, hp)
+        return hybrid.hybrid_step(prob, qp, Phi, psi, hat, tilde, hp, norms=norms)
     st = {"eps_o": None, "basis_used": None, "basis_o": None, "sets_o": None, "worst": 0.0, "worst_own": 0.0,
           "ties": [], "checked": 0, "types": []}
 
@@ -101,10 +108,11 @@ def run_resync(wl, seed, steps, check_from=1, tol=1e-12):
             Phi = host(used["Phi"])[: m * n].reshape(m, n).T.copy()
             psi = host(used["psi"])
             norms = []
-            ref = hybrid.hybrid_step(prob, qp, Phi, psi, hat, tilde, hp, norms=norms)
+            ref = step(qp, Phi, psi, hat, tilde, norms=norms)
             assert rec["J"] == ref["J"], (k, rec["J"], ref["J"])
             e = rel(g, ref["gamma"])
             if e > tol:
+                assert not gn, (k, "hybrid (Gauss-Newton)", e)
                 flips = gate_flips(k, drv.recorder.tapes[k].info()[1], ref["masks"], norms, scale)
                 assert flips > 0, (k, "hybrid", e)
                 st["ties"].append((k, "gate", flips, e))
@@ -123,7 +131,7 @@ def run_resync(wl, seed, steps, check_from=1, tol=1e-12):
                       "state rel", e, flush=True)
             assert ok, (k, "indicator", d, rec["fit_cond"])
             if st["basis_o"] is not None and st["basis_o"]["m_eff"] == m:
-                own = hybrid.hybrid_step(prob, qp, st["basis_o"]["Phi"], st["basis_o"]["psi_new"], hat, tilde, hp)
+                own = step(qp, st["basis_o"]["Phi"], st["basis_o"]["psi_new"], hat, tilde)
                 st["worst_own"] = max(st["worst_own"], rel(host(out), own["gamma"]))
             st["eps_o"] = ref["eps"]
         st["worst"] = max(st["worst"], e)
@@ -216,3 +224,23 @@ def test_euler2d_small_trajectory():
     wl = W.WORKLOADS["euler2d_512"].resized(24, 20, m=8)
     prob, q0, qT, recs, st = run_resync(wl, 2, wl.w + 25)
     assert any(t == "hybrid" for t in st["types"])
+
+
+def test_burgers1d_1k_trajectory_gauss_newton():
+    """Alg. 1 with Gauss-Newton subiterations (rom_hybrid_step_gn in the
+    driver), resynchronised at every step against the oracle's Gauss-Newton
+    step: 1D Burgers 1024 cells, 120 steps."""
+    need_gpu()
+    print_case("trajectory burgers1d_1k with Gauss-Newton subiterations, 120 steps, resync every step")
+    wl = W.WORKLOADS["burgers1d_1k"]
+    prob, q0, qT, recs, st = run_resync(wl, 0, 120, gn=True)
+    assert sum(r["type"] == "hybrid" for r in recs) > 60
+    assert st["worst"] <= 1e-12
+
+
+def test_burgers2d_small_trajectory_gauss_newton():
+    need_gpu()
+    print_case("trajectory burgers2d 40x36 (m = 10) with Gauss-Newton subiterations, resync every step")
+    wl = W.WORKLOADS["burgers2d_1024"].resized(40, 36, m=10)
+    prob, q0, qT, recs, st = run_resync(wl, 1, wl.w + 30, gn=True)
+    assert st["worst"] <= 1e-12

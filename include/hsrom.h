@@ -363,6 +363,15 @@ hs_status hs_odeim(hs_ctx* ctx, const double* Phi, int32_t m, int32_t n_p, int32
  * lie in sampled cells: pass the same points as its fit_points. */
 hs_status hs_samples_add_points(hs_ctx* ctx, hs_samples* s, const int32_t* points, int32_t n_p);
 
+/* rom_hybrid_step whose fit (eq. red_coord) uses the given n_fit state
+ * entries (device int32, in sampled cells: e.g. hs_odeim's points after
+ * hs_samples_add_points) instead of every entry of the sampled cells.
+ * n_fit = 0 is rom_hybrid_step. */
+hs_status rom_hybrid_step_fit(hs_ctx* ctx, const double* q_prev, const void* Phi, const double* psi, int32_t m,
+                              const hs_samples* s, const int32_t* fit_points, int32_t n_fit,
+                              const hs_hybrid_params* params /* host */, double* q_out, double* eps_out,
+                              double* y_out, hs_step_info* info /* host */);
+
 /* The residual-gated filter sequence alone (Sec. 2.3.4), on a full state. */
 hs_status hs_filter(hs_ctx* ctx, const double* gamma_in, const double* q_prev,
                     const hs_hybrid_params* params /* host */, double* gamma_out, hs_step_info* info);

@@ -127,8 +127,11 @@ def fit(Phi_rows, d, rcond):
     return y
 
 
-def hybrid_step(prob: Problem, q_prev, Phi, psi, hat, tilde, params: HybridParams = None, norms=None):
-    """One hybrid snapshot gamma_k from gamma_{k-1} = q_prev.
+def hybrid_step(prob: Problem, q_prev, Phi, psi, hat, tilde, params: HybridParams = None, norms=None,
+                fit_points=None):
+    """One hybrid snapshot gamma_k from gamma_{k-1} = q_prev.  With
+    fit_points (entries of the state in sampled cells, e.g. ODEIM points:
+    eq. red_coord's P) the fit uses those rows only.
 
     Returns dict(gamma, y, J, eps, rho, dy, newton, us, masks) where rho = psi + Phi y
     is the reconstruction, eps the indicator of the filtered snapshot, dy the
@@ -138,7 +141,8 @@ def hybrid_step(prob: Problem, q_prev, Phi, psi, hat, tilde, params: HybridParam
     params = params or HybridParams()
     hd = fv.dofs_of_cells(prob, hat)
     td = fv.dofs_of_cells(prob, tilde)
-    Phi_hat = Phi[hd]
+    fd = hd if fit_points is None else np.asarray(fit_points, dtype=np.int64)
+    Phi_hat = Phi[fd]
     u = q_prev.copy()             # v_hat guess and v_tilde^(1) both from gamma_{k-1}
     y_old = None
     newton = []
@@ -149,7 +153,7 @@ def hybrid_step(prob: Problem, q_prev, Phi, psi, hat, tilde, params: HybridParam
         u, its = fv.partial_hdm_solve(prob, u, q_prev, hat)
         newton.append(its)
         us.append(u.copy())
-        y = fit(Phi_hat, u[hd] - psi[hd], params.rcond_fit)
+        y = fit(Phi_hat, u[fd] - psi[fd], params.rcond_fit)
         u[td] = psi[td] + Phi[td] @ y
         J = j
         if y_old is not None:

@@ -119,6 +119,8 @@ _SIGS = {
     "rom_hybrid_step_bdf2": [P, ctypes.POINTER(PaperHDM), P, P, P, P, I32, P, P, I32, ctypes.POINTER(HybridParams),
                              P, P, P, ctypes.POINTER(StepInfo)],
     "hs_odeim": [P, P, I32, I32, P],
+    "rom_hybrid_step_fit": [P, P, P, P, I32, P, P, I32, ctypes.POINTER(HybridParams), P, P, P,
+                            ctypes.POINTER(StepInfo)],
     "rom_hybrid_step_gn": [P, P, P, P, I32, P, ctypes.POINTER(HybridParams), P, P, P, P, ctypes.POINTER(StepInfo)],
     "hs_samples_add_points": [P, P, P, I32],
     "hs_samples_create": [P, ctypes.POINTER(P)],
@@ -428,14 +430,24 @@ class Context:
         return me.value
 
     # -------------------------------------------------------------- hybrid
-    def rom_hybrid_step(self, q_prev, Phi, psi, m, samples, params=None, out=None, eps=None, y=None):
+    def rom_hybrid_step(self, q_prev, Phi, psi, m, samples, params=None, out=None, eps=None, y=None,
+                        fit_points=None):
+        """One hybrid step; fit_points (int32 state entries): the fit's rows
+        (rom_hybrid_step_fit), else every entry of the sampled cells."""
         params = _with_precision(params or hybrid_params(), self._basis(Phi, m))
         out = self.empty() if out is None else out
         info = StepInfo()
         try:
-            self._check(lib().rom_hybrid_step(self.h, _ptr(self._in(q_prev)), _ptr(Phi), _ptr(self._in(psi)), m,
-                                              samples.h, ctypes.byref(params), _ptr(self._in(out)),
-                                              _ptr(eps), _ptr(y), ctypes.byref(info)))
+            if fit_points is not None:
+                nf = fit_points.numel()
+                self._check(lib().rom_hybrid_step_fit(self.h, _ptr(self._in(q_prev)), _ptr(Phi), _ptr(self._in(psi)),
+                                                      m, samples.h, _ptr(self._in(fit_points, nf, torch.int32)), nf,
+                                                      ctypes.byref(params), _ptr(self._in(out)), _ptr(eps), _ptr(y),
+                                                      ctypes.byref(info)))
+            else:
+                self._check(lib().rom_hybrid_step(self.h, _ptr(self._in(q_prev)), _ptr(Phi), _ptr(self._in(psi)),
+                                                  m, samples.h, ctypes.byref(params), _ptr(self._in(out)),
+                                                  _ptr(eps), _ptr(y), ctypes.byref(info)))
         finally:
             if m == BASIS_PENDING:
                 self._pending = False        # the step completes the update on every path

@@ -1281,7 +1281,8 @@ static hs_status fit_solve(hs_ctx* ctx, const void* Phi, int prec, int m, const 
 // mode: -1 plain step, HS_TAPE_RECORD, HS_TAPE_REPLAY (see the header).
 static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const void* Phi, const double* psi, int m,
                              const hs_samples* s, const hs_hybrid_params* hp, double* q_out, double* eps_out,
-                             double* y_out, hs_step_info* info, hs_htape* tape, int mode) {
+                             double* y_out, hs_step_info* info, hs_htape* tape, int mode,
+                             const int32_t* fit_points = nullptr, int32_t n_fit = 0) {
   if (!ctx) return HS_ERR_INVALID_ARG;
   // HS_BASIS_PENDING: the basis is still being formed on the context's
   // second stream; it is completed after the first Newton solve, and on
@@ -1314,6 +1315,12 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const void* Phi,
   const int prec = hp->precision;
   if (prec != HS_FP64 && prec != HS_MIXED_FP32) return HS_ERR_INVALID_ARG;
   if (s->n_s == 0) return ctx->fail(HS_ERR_RANK, "empty sampled set");
+  if (n_fit < 0 || n_fit > ctx->n || (n_fit > 0 && !fit_points)) return ctx->fail(HS_ERR_INVALID_ARG, "fit points");
+  if (n_fit > 0 && mode >= 0) return ctx->fail(HS_ERR_INVALID_ARG, "a taped step fits over the sampled cells");
+  // the fit's rows: every entry of the sampled cells, or the given entries
+  const int* frows = n_fit > 0 ? fit_points : s->hat;
+  const int nfr = n_fit > 0 ? n_fit : s->n_s;
+  const int fnc = n_fit > 0 ? 1 : ctx->nc;
   hs_step_info local{};
   hs_step_info* inf = info ? info : &local;
   std::memset(inf, 0, sizeof *inf);
@@ -1340,7 +1347,7 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const void* Phi,
   // iteration, whose sweep launch forms the tolerance from the same value
   HS_TRY(max_abs_launch(ctx, q_prev, ctx->n));
   HIP_TRY(ctx, hipMemcpyAsync(u, q_prev, ctx->n * 8, hipMemcpyDeviceToDevice, ctx->stream));
-  if (!pending) HS_TRY(fit_factor(ctx, Phi, prec, m, s->hat, s->n_s, hp->rcond_fit));
+  if (!pending) HS_TRY(fit_factor(ctx, Phi, prec, m, frows, nfr, hp->rcond_fit, fnc));
   unsigned long long st[kStatSlots];
   double primed[3];
   bool have_primed = false;
@@ -1379,13 +1386,13 @@ static hs_status hybrid_impl(hs_ctx* ctx, const double* q_prev, const void* Phi,
       if (me < 1 || me > ctx->p.m_max) return ctx->fail(HS_ERR_RANK, "empty basis");
       m = me;
       // its rank and condition come back with this subiteration's decision
-      HS_TRY(fit_factor(ctx, Phi, prec, m, s->hat, s->n_s, hp->rcond_fit));
+      HS_TRY(fit_factor(ctx, Phi, prec, m, frows, nfr, hp->rcond_fit, fnc));
       fit_check = true;
     }
     if (replay)
       HIP_TRY(ctx, hipMemcpyAsync(tape->us + (size_t)(j - 1) * ctx->n, u, ctx->n * 8, hipMemcpyDeviceToDevice,
                                   ctx->stream));
-    HS_TRY(fit_solve(ctx, Phi, prec, m, s->hat, s->n_s, u, psi, j == 1));
+    HS_TRY(fit_solve(ctx, Phi, prec, m, frows, nfr, u, psi, j == 1, fnc));
     if (s->l > 0) HS_TRY(ring_update(ctx, Phi, prec, m, s, psi, sm + kSmY, u));
     inf->subiters = j;
     if (replay) continue;
@@ -1861,6 +1868,13 @@ hs_status rom_hybrid_step_bdf2(hs_ctx* ctx, const hs_paper_hdm* hdm, const doubl
                                double* q_out, double* eps_out, double* y_out, hs_step_info* info) {
   return hybrid_paper_impl(ctx, hdm, q_prev, q_prev2, Phi, psi, m, s, fit_points, n_fit, hp, q_out, eps_out, y_out,
                            info);
+}
+
+hs_status rom_hybrid_step_fit(hs_ctx* ctx, const double* q_prev, const void* Phi, const double* psi, int32_t m,
+                              const hs_samples* s, const int32_t* fit_points, int32_t n_fit,
+                              const hs_hybrid_params* hp, double* q_out, double* eps_out, double* y_out,
+                              hs_step_info* info) {
+  return hybrid_impl(ctx, q_prev, Phi, psi, m, s, hp, q_out, eps_out, y_out, info, nullptr, -1, fit_points, n_fit);
 }
 
 hs_status rom_hybrid_step_taped(hs_ctx* ctx, const double* q_prev, const void* Phi, const double* psi,

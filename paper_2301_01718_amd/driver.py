@@ -41,8 +41,8 @@ class AromConfig:
     rcond_fit: float = 1e-8
     floor_rel: float = 1e-14
     precision: int = FP64
-    # with the paper's scheme: ODEIM points (eq. odeim), n_p = odeim_factor
-    # m_eff, join the sampled set and are the fit's rows (eq. red_coord); 0: none
+    # ODEIM points (eq. odeim), n_p = odeim_factor m_eff, join the sampled set
+    # and are the fit's rows (eq. red_coord); 0: none (FP64 basis)
     odeim_factor: int = 0
     # Gauss-Newton subiterations (rom_hybrid_step_gn; first-order scheme, FP64)
     gauss_newton: bool = False
@@ -99,8 +99,8 @@ class Arom:
         # gamma_{k-2}, Sec. 3.1) instead of the first-order one; its steps
         # take the basis once the update is complete
         self.paper = paper
-        if paper is not None:
-            self.defer_basis = False
+        if paper is not None or cfg.odeim_factor > 0:
+            self.defer_basis = False   # these steps take the basis (and its points) complete
         self.points = None
         self.gn_work = None
         if cfg.gauss_newton:
@@ -154,13 +154,15 @@ class Arom:
                     _, info = c.rom_hybrid_step_gn(prev, self.Phi, self.psi, self.m_eff, self.samples, self.hp,
                                                    out=out, eps=self.eps, work=self.gn_work)
                 elif self.recorder is not None:
+                    if self.points is not None:
+                        raise ValueError("a taped hybrid step fits over the sampled cells (no ODEIM points)")
                     _, info = c.rom_hybrid_step_taped(prev, self.Phi, self.psi, m_arg,
                                                       self.recorder.tape(k), TAPE_RECORD,
                                                       samples=self.samples, params=self.hp, out=out,
                                                       eps=self.eps)
                 else:
                     _, info = c.rom_hybrid_step(prev, self.Phi, self.psi, m_arg, self.samples,
-                                                self.hp, out=out, eps=self.eps)
+                                                self.hp, out=out, eps=self.eps, fit_points=self.points)
                 rec.update(type="hybrid", n_s=info["n_s"], l=info["l"], J=info["subiters"],
                            newton=info["newton_iters"], sweeps=info["lin_sweeps"],
                            filter_passes=info["filter_passes"], fit_cond=info["fit_cond"])
@@ -211,7 +213,7 @@ class Arom:
                 if on_update is not None or not self.defer_basis or not nxt_hybrid:
                     self._complete()
             self.points = None
-            if self.paper is not None and cfg.odeim_factor > 0 and self.have_samples and self.m_eff > 0:
+            if cfg.odeim_factor > 0 and self.have_samples and self.m_eff > 0:
                 # P_{k+1} = ODEIM(Phi_{k+1}) and hat-S = G u P (Alg. 1), the basis complete
                 n_p = min(cfg.odeim_factor * self.m_eff, c.n)
                 self.points = c.odeim(self.Phi, self.m_eff, n_p)

@@ -504,3 +504,40 @@ def test_paper_hybrid_step_with_odeim_matches_oracle():
     assert d < state_tol(info["fit_cond"], tol=1e-12)
     ok, dd = indicator_close(host(eps_g), ref["eps"], ref["gamma"], tol=1e-12, cell_tol=1e-10)
     assert ok, dd
+
+
+def test_odeim_gauss_newton_and_paper_hybrid_argument_errors():
+    """Argument errors of the newer entry points are reported before any
+    work (HS_ERR_INVALID_ARG), and the context keeps working."""
+    need_gpu()
+    import ctypes
+    import paper_2301_01718_amd as hs
+    from paper_2301_01718_amd._lib import _ptr, lib
+    case = W.paper_sod(64, 128)
+    ctx, hdm = context(case)
+    n = 4 * case.nx
+    Phi = dev(np.linalg.qr(np.random.default_rng(0).standard_normal((n, 3)))[0].T.copy().reshape(-1))
+    pts = torch.zeros(8, dtype=torch.int32, device="cuda")
+    assert lib().hs_odeim(ctx.h, _ptr(Phi), 17, 40, _ptr(pts)) == -1       # m beyond 16 (and m_max)
+    assert lib().hs_odeim(ctx.h, _ptr(Phi), 3, 2, _ptr(pts)) == -1         # n_p < m
+    assert lib().hs_odeim(ctx.h, _ptr(Phi), 3, n + 1, _ptr(pts)) == -1     # n_p > N
+    s = ctx.samples()
+    assert lib().hs_samples_add_points(ctx.h, s.h, _ptr(pts), -1) == -1
+    # the Gauss-Newton step without its workspace
+    hp = hs.hybrid_params()
+    s = ctx.samples_set(dev(np.arange(10, 20, dtype=np.int32)))
+    q = dev(case.q0)
+    out = ctx.empty()
+    assert lib().rom_hybrid_step_gn(ctx.h, _ptr(q), _ptr(Phi), _ptr(q), 3, s.h, ctypes.byref(hp), None, _ptr(out),
+                                    None, None, None) == -1
+    # the paper's hybrid step on a periodic context
+    prob = W.Problem(kind=W.EULER_2D, nx=64, ny=1, bc=W.BC_PERIODIC, dx=1 / 64, dy=1.0, dt=1e-3, gamma=W.GAMMA,
+                     inflow=0.0)
+    pctx = hs.Context(prob, m_max=4, w_max=8)
+    ps = pctx.samples_set(dev(np.arange(10, 20, dtype=np.int32)))
+    with pytest.raises(hs.HsError) as e:
+        pctx.rom_hybrid_step_bdf2(hdm, q, None, Phi, q, 3, ps)
+    assert e.value.status == -1
+    # still working: ODEIM points of the basis
+    got = host(ctx.odeim(Phi, 3, 6)).tolist()
+    assert len(set(got)) == 6

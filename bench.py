@@ -529,6 +529,31 @@ def gauss_newton_bench(drv, reps=3):
     return out
 
 
+def odeim_bench(drv, reps=3):
+    """hs_odeim on the timed run's basis (its first min(m_eff, 16) columns,
+    an orthonormal set), n_p = 2 m points: time per call and the rate of its
+    passes over Phi (one pass of 8 m N bytes per point)."""
+    import numpy as np
+    import torch
+    c = drv.ctx
+    m = min(drv.m_eff, 16)
+    if m < 1:
+        return None
+    n_p = 2 * m
+    c.odeim(drv.Phi, m, n_p)
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize(c.device)
+        t = time.perf_counter()
+        c.odeim(drv.Phi, m, n_p)
+        torch.cuda.synchronize(c.device)
+        ts.append(time.perf_counter() - t)
+    sec = float(np.median(ts))
+    by = 8.0 * m * c.n * n_p
+    return {"m": m, "n_p": n_p, "ms": 1e3 * sec, "bytes": by, "achieved_GBs": by / sec / 1e9,
+            "frac_hbm": by / sec / 1e9 / HBM_PEAK_GBS}
+
+
 def paper_residual_rate(nx=1024, reps=20):
     """hs_paper_residual (BDF2: reads q, q_{k-1}, q_{k-2}, writes R: 128
     algorithmic bytes per cell) on an nx^2 mesh of random states, each launch
@@ -653,6 +678,7 @@ def main():
     if not args.no_paper:
         log("Gauss-Newton subiterations on the next step ...")
         gnb = gauss_newton_bench(drv)
+        gnb = {"gauss_newton": gnb, "odeim": odeim_bench(drv)}
 
     log("residual kernel rates ...")
     prev_state = drv.slot(drv.k - 1).clone()
@@ -743,7 +769,7 @@ def main():
         "adjoint": adj,
         "other_workloads": others,
         "paper_experiments": paper,
-        "gauss_newton": gnb,
+        "next_rows": gnb,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -13,10 +13,10 @@
 // and (u_1^T phi)^2 when m = 1.  Ties go to the lowest index.
 //
 // Every step is one pass over Phi (one thread per row, the row's m entries
-// in registers, a block argmax) and one single-block pick that reduces the
+// in registers, a block argmax) and a one-wave pick that reduces the
 // partials in a fixed order, marks the point, extends the orthonormal basis
 // or the Gram, and (from the m-th point on) diagonalises the m x m Gram by
-// cyclic Jacobi.  m <= 16.
+// cyclic Jacobi in LDS.  m <= 16.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -109,59 +109,39 @@ __global__ void __launch_bounds__(kBlock) odeim_score_kernel(const double* __res
   }
 }
 
-// Cyclic Jacobi on the symmetric m x m matrix A (destroyed): eigenvalues on
-// the diagonal, eigenvectors in the columns of V.
-__device__ inline void jacobi_eig(double (*A)[kOdeimMax], double (*V)[kOdeimMax], int m) {
-  for (int i = 0; i < m; ++i)
-    for (int j = 0; j < m; ++j) V[i][j] = i == j ? 1.0 : 0.0;
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) {
-        tot += A[i][j] * A[i][j];
-        if (i != j) off += A[i][j] * A[i][j];
-      }
-    if (off <= 1e-34 * tot) break;
-    for (int p = 0; p < m - 1; ++p)
-      for (int r = p + 1; r < m; ++r) {
-        const double apr = A[p][r];
-        if (apr == 0.0) continue;
-        const double theta = (A[r][r] - A[p][p]) / (2.0 * apr);
-        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-        for (int k = 0; k < m; ++k) {
-          const double akp = A[k][p], akr = A[k][r];
-          A[k][p] = c * akp - s * akr;
-          A[k][r] = s * akp + c * akr;
-        }
-        for (int k = 0; k < m; ++k) {
-          const double apk = A[p][k], ark = A[r][k];
-          A[p][k] = c * apk - s * ark;
-          A[r][k] = s * apk + c * ark;
-        }
-        for (int k = 0; k < m; ++k) {
-          const double vkp = V[k][p], vkr = V[k][r];
-          V[k][p] = c * vkp - s * vkr;
-          V[k][r] = s * vkp + c * vkr;
-        }
-      }
-  }
-}
-
-// One thread: reduce the partials, take the point, extend the state.
-__global__ void odeim_pick_kernel(const double* __restrict__ Phi, long long n, int m, int qdeim, int slot, int nb,
-                                  const double* __restrict__ pval, const int* __restrict__ pidx, OdeimState* st,
-                                  uint8_t* __restrict__ taken, int32_t* __restrict__ points) {
-  if (threadIdx.x != 0) return;
+// One wave: reduce the partials (lanes stride the blocks, then a lane tree;
+// ties to the lowest index), take the point, extend the orthonormal basis of
+// the QDEIM rows or the Gram, and from the m-th point on diagonalise the Gram
+// by cyclic Jacobi in LDS (each rotation's rows and columns updated by m
+// lanes) for l_1, the gap and u_1.
+__global__ void __launch_bounds__(kWave) odeim_pick_kernel(const double* __restrict__ Phi, long long n, int m,
+                                                           int qdeim, int slot, int nb,
+                                                           const double* __restrict__ pval,
+                                                           const int* __restrict__ pidx, OdeimState* st,
+                                                           uint8_t* __restrict__ taken, int32_t* __restrict__ points) {
+  __shared__ double A[kOdeimMax][kOdeimMax + 1], V[kOdeimMax][kOdeimMax + 1];
+  __shared__ double ph[kOdeimMax], rot[2];
+  __shared__ int pick;
+  const int t = threadIdx.x;
   double best = -INFINITY;
   int bi = 0x7fffffff;
-  for (int b = 0; b < nb; ++b) argmax_merge(best, bi, pval[b], pidx[b]);
-  if (bi < 0 || bi >= n) bi = 0;   // no candidate left (cannot happen for n_p <= n)
-  taken[bi] = 1;
-  points[slot] = bi;
-  double ph[kOdeimMax];
-  for (int j = 0; j < m; ++j) ph[j] = Phi[(size_t)j * n + bi];
-  if (qdeim) {
+  for (int b = t; b < nb; b += kWave) argmax_merge(best, bi, pval[b], pidx[b]);
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const double v2 = __shfl_xor(best, o, kWave);
+    const int i2 = __shfl_xor(bi, o, kWave);
+    argmax_merge(best, bi, v2, i2);
+  }
+  if (t == 0) {
+    if (bi < 0 || bi >= n) bi = 0;   // no candidate left (cannot happen for n_p <= n)
+    pick = bi;
+    taken[bi] = 1;
+    points[slot] = bi;
+  }
+  __syncthreads();
+  const int p0 = pick;
+  if (t < m) ph[t] = Phi[(size_t)t * n + p0];
+  __syncthreads();
+  if (qdeim && t == 0) {
     // Gram-Schmidt of the row against the basis, twice, then normalise
     double v[kOdeimMax];
     for (int j = 0; j < m; ++j) v[j] = ph[j];
@@ -177,13 +157,62 @@ __global__ void odeim_pick_kernel(const double* __restrict__ Phi, long long n, i
     for (int j = 0; j < m; ++j) st->q[st->nq][j] = nv > 0.0 ? v[j] / nv : 0.0;
     st->nq += 1;
   }
-  for (int i = 0; i < m; ++i)
-    for (int j = 0; j < m; ++j) st->M[i][j] += ph[i] * ph[j];
-  if (slot + 1 >= m) {
-    double A[kOdeimMax][kOdeimMax], V[kOdeimMax][kOdeimMax];
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) A[i][j] = st->M[i][j];
-    jacobi_eig(A, V, m);
+  if (t < m)
+    for (int j = 0; j < m; ++j) st->M[t][j] += ph[t] * ph[j];
+  __syncthreads();
+  if (slot + 1 < m) return;
+  if (t < m)
+    for (int j = 0; j < m; ++j) {
+      A[t][j] = st->M[t][j];
+      V[t][j] = t == j ? 1.0 : 0.0;
+    }
+  __syncthreads();
+  // sweeps until one applies no rotation: an off-diagonal entry is rotated
+  // away unless it is below 1e-16 of the geometric mean of its diagonal pair
+  // (the eigenvalues then carry errors of second order in it)
+  __shared__ int nrot;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (t == 0) nrot = 0;
+    __syncthreads();
+    for (int p = 0; p < m - 1; ++p)
+      for (int r = p + 1; r < m; ++r) {
+        if (t == 0) {
+          const double apr = A[p][r];
+          double c = 1.0, sn = 0.0;
+          if (fabs(apr) > 1e-16 * sqrt(fabs(A[p][p] * A[r][r]))) {
+            const double theta = (A[r][r] - A[p][p]) / (2.0 * apr);
+            const double tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(tt * tt + 1.0);
+            sn = tt * c;
+            nrot += 1;
+          }
+          rot[0] = c;
+          rot[1] = sn;
+        }
+        __syncthreads();
+        const double c = rot[0], sn = rot[1];
+        if (sn != 0.0) {
+          if (t < m) {
+            const double akp = A[t][p], akr = A[t][r];
+            A[t][p] = c * akp - sn * akr;
+            A[t][r] = sn * akp + c * akr;
+            const double vkp = V[t][p], vkr = V[t][r];
+            V[t][p] = c * vkp - sn * vkr;
+            V[t][r] = sn * vkp + c * vkr;
+          }
+          __syncthreads();
+          if (t < m) {
+            const double apk = A[p][t], ark = A[r][t];
+            A[p][t] = c * apk - sn * ark;
+            A[r][t] = sn * apk + c * ark;
+          }
+        }
+        __syncthreads();
+      }
+    if (nrot == 0) break;
+    __syncthreads();
+  }
+  if (t == 0) {
     int i1 = 0;
     for (int i = 1; i < m; ++i)
       if (A[i][i] < A[i1][i1]) i1 = i;

@@ -402,3 +402,20 @@ def test_paper_arom_on_sod():
     assert len(hyb) > 100
     assert max(errs) < 0.01 and np.mean(errs) < 0.005, (max(errs), np.mean(errs))
     assert sbar_h < 0.5 and all(2 <= r["J"] <= 10 for r in hyb)
+
+
+def test_paper_arom_with_odeim_on_sod():
+    """Alg. 1 with the paper's sampled set (hat-S = G u P, n_p = 2 m_eff ODEIM
+    points, the fit over them, no halo) on Sod's tube (100 cells, z = 5):
+    every hybrid step's sampled set holds the points' cells, and the
+    snapshots stay within 1 % of the full-order run."""
+    nx, steps = 100, 201
+    prob, q0 = ph.sod(nx, steps)
+    hdm = ph.run(prob, q0, steps, rtol=1e-13)
+    p = arom.AromParams(w=5, m=4, z=5, rule=sampling.RULE_RRE, delta=0.8, halo=0)
+    errs = []
+    res = pa.run(prob, q0, steps, p, odeim_factor=2,
+                 on_step=lambda k, g, rec: errs.append(arom.relative_l1_error(g, hdm[k])))
+    hyb = [r for r in res["records"] if r["type"] == "hybrid"]
+    assert len(hyb) > 100 and all(r["n_p"] == 8 for r in hyb)
+    assert max(errs) < 0.01 and np.mean(errs) < 0.005, (max(errs), np.mean(errs))

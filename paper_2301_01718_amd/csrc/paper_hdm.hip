@@ -61,8 +61,9 @@ __device__ inline void paper_state(const Grid& g, const PaperBC& bc, const doubl
 __device__ inline void to_primitive(const double s[4], double gamma, double w[4]) {
 #pragma clang fp contract(off)
   const double rho = s[0];
-  const double u = s[1] / rho;
-  const double v = s[2] / rho;
+  const double irho = 1.0 / rho;   // one division per state (a division is a multi-instruction sequence)
+  const double u = s[1] * irho;
+  const double v = s[2] * irho;
   w[0] = rho;
   w[1] = u;
   w[2] = v;
@@ -83,30 +84,32 @@ __device__ inline void roe_flux(const double wL[4], const double wR[4], double g
 #pragma clang fp contract(off)
   const int n = axis == 0 ? 1 : 2, t = axis == 0 ? 2 : 1;
   const double g1 = gamma - 1.0;
+  const double ig1 = 1.0 / g1;
   const double rL = wL[0], nL = wL[n], tL = wL[t], pL = wL[3];
   const double rR = wR[0], nR = wR[n], tR = wR[t], pR = wR[3];
-  const double eL = pL / g1 + 0.5 * rL * (wL[1] * wL[1] + wL[2] * wL[2]);
-  const double eR = pR / g1 + 0.5 * rR * (wR[1] * wR[1] + wR[2] * wR[2]);
-  const double hL = (eL + pL) / rL, hR = (eR + pR) / rR;
+  const double eL = pL * ig1 + 0.5 * rL * (wL[1] * wL[1] + wL[2] * wL[2]);
+  const double eR = pR * ig1 + 0.5 * rR * (wR[1] * wR[1] + wR[2] * wR[2]);
+  const double hL = (eL + pL) * (1.0 / rL), hR = (eR + pR) * (1.0 / rR);
   // physical fluxes in the face frame: mass, normal, tangential momentum, energy
   const double fL[4] = {rL * nL, rL * nL * nL + pL, rL * nL * tL, (eL + pL) * nL};
   const double fR[4] = {rR * nR, rR * nR * nR + pR, rR * nR * tR, (eR + pR) * nR};
-  // Roe averages
+  // Roe averages (each reciprocal formed once: divisions dominate the face's cost)
   const double sL = sqrt(rL), sR = sqrt(rR);
-  const double den = sL + sR;
-  const double un = (sL * nL + sR * nR) / den;
-  const double ut = (sL * tL + sR * tR) / den;
-  const double h = (sL * hL + sR * hR) / den;
+  const double iden = 1.0 / (sL + sR);
+  const double un = (sL * nL + sR * nR) * iden;
+  const double ut = (sL * tL + sR * tR) * iden;
+  const double h = (sL * hL + sR * hR) * iden;
   const double kin = 0.5 * (un * un + ut * ut);
   const double c2 = g1 * (h - kin);
   const double c = sqrt(c2);
+  const double ic2 = 1.0 / c2;
   const double rho = sL * sR;
   const double dp = pR - pL, dn = nR - nL;
   // wave strengths times |speed|
-  const double w1 = fabs(un - c) * ((dp - rho * c * dn) / (2.0 * c2));
-  const double w2 = fabs(un) * ((rR - rL) - dp / c2);
+  const double w1 = fabs(un - c) * ((dp - rho * c * dn) * (0.5 * ic2));
+  const double w2 = fabs(un) * ((rR - rL) - dp * ic2);
   const double w3 = fabs(un) * (rho * (tR - tL));
-  const double w4 = fabs(un + c) * ((dp + rho * c * dn) / (2.0 * c2));
+  const double w4 = fabs(un + c) * ((dp + rho * c * dn) * (0.5 * ic2));
   double d[4];
   d[0] = w1 + w2 + w4;
   d[1] = w1 * (un - c) + w2 * un + w4 * (un + c);

@@ -161,8 +161,9 @@ class Arom:
                                                       samples=self.samples, params=self.hp, out=out,
                                                       eps=self.eps)
                 else:
+                    fit = {} if self.points is None else {"fit_points": self.points}
                     _, info = c.rom_hybrid_step(prev, self.Phi, self.psi, m_arg, self.samples,
-                                                self.hp, out=out, eps=self.eps, fit_points=self.points)
+                                                self.hp, out=out, eps=self.eps, **fit)
                 rec.update(type="hybrid", n_s=info["n_s"], l=info["l"], J=info["subiters"],
                            newton=info["newton_iters"], sweeps=info["lin_sweeps"],
                            filter_passes=info["filter_passes"], fit_cond=info["fit_cond"])

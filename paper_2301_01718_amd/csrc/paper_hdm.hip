@@ -412,6 +412,63 @@ static hs_status paper_tiles(hs_ctx* ctx, const Grid& gj, const PaperBC& bc, con
   return HS_OK;
 }
 
+// The relaxation of one correction on a small set (count * NC <= 4096: the
+// compact list of sampled cells, or the whole mesh) in one workgroup: the
+// iterate lives in LDS, nsw Jacobi sweeps x <- rhs - sum_d coef[d] x[nb_d]
+// from x_1 = rhs are separated by workgroup barriers instead of launches, and
+// the result is added to the state.  Neighbours: the list's in-set table, or
+// on the whole mesh the grid's (a transmissive ghost is the cell itself,
+// whose coefficient block is zero).
+constexpr int kSmallRelax = 4096;
+
+template <int NC>
+__global__ void __launch_bounds__(1024) small_relax_kernel(Grid gj, const int* __restrict__ hat,
+                                                           const int* __restrict__ nbr, int count,
+                                                           const double* __restrict__ coef,
+                                                           const double* __restrict__ rhs, int nsw,
+                                                           double* __restrict__ q) {
+  __shared__ double xs[2 * kSmallRelax];
+  const int cap = gj.ncell;
+  double* x0 = xs;
+  double* x1 = xs + NC * count;
+  for (int e = threadIdx.x; e < NC * count; e += blockDim.x) x0[e] = rhs[(size_t)(e / count) * cap + e % count];
+  __syncthreads();
+  for (int k = 1; k < nsw; ++k) {
+    for (int p = threadIdx.x; p < count; p += blockDim.x) {
+      int nb[4];
+      if (hat) {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) nb[d] = nbr[d * cap + p];
+      } else {
+        int i, j;
+        cell_ij(gj, p, i, j);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) nb[d] = (gj.ny == 1 && d >= 2) ? -1 : neighbour(gj, i, j, d);
+      }
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        double v = rhs[(size_t)a * cap + p];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          if (nb[d] < 0) continue;
+#pragma unroll
+          for (int b = 0; b < NC; ++b) v -= coef[((size_t)(d * NC + a) * NC + b) * cap + p] * x0[b * count + nb[d]];
+        }
+        x1[a * count + p] = v;
+      }
+    }
+    __syncthreads();
+    double* t = x0;
+    x0 = x1;
+    x1 = t;
+  }
+  for (int e = threadIdx.x; e < NC * count; e += blockDim.x) {
+    const int a = e / count, p = e % count;
+    const int cell = hat ? hat[p] : p;
+    q[(size_t)a * cap + cell] += x0[e];
+  }
+}
+
 // Relative accuracy of each relaxed correction: the defect correction itself
 // reduces the residual by about 0.1 per iteration, so a finer solve buys
 // nothing.
@@ -476,7 +533,16 @@ hs_status paper_solve(hs_ctx* ctx, const PaperBC& bc, double* u, const double* q
       return ctx->fail(HS_ERR_NOT_CONVERGED, msg);
     }
     if (!std::isfinite(rho)) return ctx->fail(HS_ERR_NONFINITE, "non-finite Jacobian");
-    HS_TRY(linear_solve(ctx, s, rho, std::max(kDefectEta, ctx->p.lin_rtol), u, &sweeps));
+    const double eta = std::max(kDefectEta, ctx->p.lin_rtol);
+    const int nsw = rho > 0.0 && rho < 1.0 ? std::max(1, (int)std::ceil(std::log(eta) / std::log(rho))) : 1;
+    if (4 * count <= kSmallRelax && rho < 1.0 && nsw <= ctx->p.lin_maxit) {
+      // the whole correction in one workgroup (the set is small)
+      HS_LAUNCH(ctx, small_relax_kernel<4>, 1, 1024, gj, s ? s->hat : nullptr, s ? s->nbr : nullptr, count,
+                (const double*)ctx->coef, (const double*)ctx->rhs, nsw, u);
+      sweeps += nsw;
+    } else {
+      HS_TRY(linear_solve(ctx, s, rho, eta, u, &sweeps));
+    }
   }
 }
 

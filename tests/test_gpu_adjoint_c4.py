@@ -4,7 +4,7 @@ full-HDM run of 100 steps from the seed + 1 initial state.
 
 * Central differences of the GPU's frozen trajectory map (every step
   replayed with the recorded decisions), h = 1e-6, 16 seeded directions:
-  |g.d - FD| <= 1e-6 max(|g.d|, 1e-8 |g| |d|) (SURVEY C-12 (ii)).
+  |g.d - FD| <= 1e-6 max(|g.d|, 1e-8 |g| |d|).
 * Step by step against the oracle adjoint, resynchronised: walking the
   checkpointed segments backwards as the GPU does, every hybrid step's and
   every eighth full step's adjoint lambda_{k-1} is recomputed by the oracle

@@ -1,4 +1,4 @@
-"""Error paths of the C ABI on the GPU (SURVEY §8(b) errors): a non-finite
+"""Error paths of the C ABI on the GPU: a non-finite
 input is reported as HS_ERR_NONFINITE (also a single NaN among many finite
 values: every maximum the library checks propagates NaN), an empty sampled
 set and a rank-zero fit as HS_ERR_RANK, Newton's iteration limit as

@@ -31,7 +31,7 @@ Readings
   rounding noise, not reproducible by any two correct SVDs.  Modes above
   1e-8 sigma_1 are determined to about eps sigma_1 / gap; the dropped ones
   carry less than 1e-16 of the window energy.  (With 1e-4 instead, the
-  c0 and 2D Burgers runs keep 4 and 18 modes instead of 10 and 32 and their
+  1D Burgers (1024 cells) and 2D Burgers runs keep 4 and 18 modes instead of 10 and 32 and their
   error against the full model is 1.5 to 3 times larger.)
 * Sign: each right singular vector has its largest-magnitude entry
   positive (lowest index on ties); the left vector takes the same sign.

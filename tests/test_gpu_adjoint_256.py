@@ -1,4 +1,4 @@
-"""The adjoint at config 4's size: 2D Burgers 256 x 256, 100 steps, a
+"""The adjoint on 2D Burgers 256 x 256 over 100 steps, a
 checkpoint every 10 steps, loss 0.5 ||u_T - u_target||^2 with u_target a
 full-HDM run of 100 steps from the seed + 1 initial state.
 
@@ -28,7 +28,7 @@ pytestmark = pytest.mark.gpu
 
 def test_c4_gradient_full_size():
     need_gpu()
-    print_case("adjoint c4: burgers2d 256^2, 100 steps, K = 10")
+    print_case("adjoint: burgers2d 256^2, 100 steps, K = 10")
     from paper_2301_01718_amd._lib import TAPE_REPLAY
     from paper_2301_01718_amd.adjoint import HybridTrajectory, Trajectory
     from paper_2301_01718_amd.driver import AromConfig

@@ -577,3 +577,25 @@ def test_implosion_paper_experiment_alg1():
     print(f"e-bar {100 * np.mean(errs):.3f} %  max {100 * max(errs):.3f} %  hybrid {len(hyb)}/{steps}  "
           f"s-bar* {100 * np.mean([r['n_s'] / case.nx ** 2 for r in hyb]):.2f} %")
     assert max(errs) < 0.01 and len(hyb) > steps // 2
+
+
+def test_odeim_points_full_size():
+    """hs_odeim at the size of the bench workload's basis (2D Burgers 1024^2:
+    2^20 entries), m = 8 localised columns, n_p = 16: the oracle's points in
+    the same order."""
+    need_gpu()
+    import paper_2301_01718_amd as hs
+    print_case("hs_odeim full size", 1024, 8)
+    n, m = 1 << 20, 8
+    rng = np.random.default_rng(5)
+    x = np.linspace(0, 1, n)
+    A = np.stack([np.exp(-((x - c) / 0.01) ** 2) + 1e-3 * rng.standard_normal(n) for c in rng.uniform(0.1, 0.9, m)],
+                 axis=1)
+    Phi, _ = np.linalg.qr(A)
+    prob = W.Problem(kind=W.BURGERS_2D, nx=1024, ny=1024, bc=W.BC_PERIODIC, dx=1 / 1024, dy=1 / 1024, dt=1e-3,
+                     gamma=W.GAMMA, inflow=0.0)
+    ctx = hs.Context(prob, m_max=8, w_max=8)
+    pts = host(ctx.odeim(dev(np.ascontiguousarray(Phi.T).reshape(-1)), m, 2 * m)).tolist()
+    agree = odeim_agree(Phi, pts, 2 * m)
+    print("points", pts, "agree", agree)
+    assert agree == 2 * m

@@ -335,8 +335,8 @@ hs_status rom_hybrid_step_gn(hs_ctx* ctx, const double* q_prev, const double* Ph
  * HS_BC_TRANSMISSIVE (its filters extrapolate by zeroth order at the
  * boundaries); m >= 1 (no HS_BASIS_PENDING).  fit_points (device, n_fit
  * state entries in sampled cells, e.g. hs_odeim's points): the fit of
- * eq. red_coord uses those rows only; NULL / 0: every entry of the sampled
- * cells.  Errors as rom_hybrid_step. */
+ * eq. red_coord uses those rows only (entries outside [0, N) add no row);
+ * NULL / 0: every entry of the sampled cells.  Errors as rom_hybrid_step. */
 hs_status rom_hybrid_step_bdf2(hs_ctx* ctx, const hs_paper_hdm* hdm /* host */, const double* q_prev,
                                const double* q_prev2 /* may be NULL */, const void* Phi, const double* psi,
                                int32_t m, const hs_samples* s, const int32_t* fit_points /* may be NULL */,
@@ -359,14 +359,14 @@ hs_status rom_hybrid_step_bdf2(hs_ctx* ctx, const hs_paper_hdm* hdm /* host */, 
 hs_status hs_odeim(hs_ctx* ctx, const double* Phi, int32_t m, int32_t n_p, int32_t* points);
 /* Adds the cells of n_p state entries (as hs_odeim returns them) to the
  * sampled set s (Sec. 2.3.3: hat-S = G u P) and rebuilds its ring, lists and
- * neighbour table; n_g is kept.  The fit rows of rom_hybrid_step_bdf2 must
+ * neighbour table; n_g is kept; entries outside [0, N) are ignored.  The fit rows of rom_hybrid_step_bdf2 must
  * lie in sampled cells: pass the same points as its fit_points. */
 hs_status hs_samples_add_points(hs_ctx* ctx, hs_samples* s, const int32_t* points, int32_t n_p);
 
 /* rom_hybrid_step whose fit (eq. red_coord) uses the given n_fit state
  * entries (device int32, in sampled cells: e.g. hs_odeim's points after
- * hs_samples_add_points) instead of every entry of the sampled cells.
- * n_fit = 0 is rom_hybrid_step. */
+ * hs_samples_add_points) instead of every entry of the sampled cells;
+ * entries outside [0, N) add no row.  n_fit = 0 is rom_hybrid_step. */
 hs_status rom_hybrid_step_fit(hs_ctx* ctx, const double* q_prev, const void* Phi, const double* psi, int32_t m,
                               const hs_samples* s, const int32_t* fit_points, int32_t n_fit,
                               const hs_hybrid_params* params /* host */, double* q_out, double* eps_out,

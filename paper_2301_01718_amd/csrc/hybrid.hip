@@ -46,6 +46,7 @@ struct GatherLoader {
     if (row < (long long)nc * ns) {
       const int a = (int)(row / ns), p = (int)(row % ns);
       dof = (long long)a * ncell + hat[p];
+      if (dof >= n) dof = -1;   // a caller's fit point outside the state: no row
     }
 #pragma unroll
     for (int i = 0; i < kMaxBasis / 4; ++i) {
@@ -311,6 +312,7 @@ __global__ void __launch_bounds__(256) project_kernel(const TP* __restrict__ Phi
        row += (long long)gridDim.x * blockDim.x) {
     long long dof = row;
     if (hat) dof = (row / ns) * (long long)ncell + hat[row % ns];
+    if (dof < 0 || dof >= n) continue;   // a caller's fit point outside the state: no row
     double ph[MP];
 #pragma unroll
     for (int j = 0; j < MP; ++j) ph[j] = j < m ? (double)Phi[(size_t)j * n + dof] : 0.0;

@@ -56,6 +56,9 @@ def wants_update(k, w, z, steps):
     return k >= w - 1 and (k + 1) % z != 0 and k < steps
 
 
+ODEIM_MAX_MODES = 16   # the largest basis hs_odeim takes
+
+
 class Arom:
     """Runs Alg. 1 on one device.  ``on_step(k, rec, used, out)`` is called
     after every step with the step record, the device tensors the step used
@@ -65,6 +68,10 @@ class Arom:
     RING_STAGGER = 320   # doubles between consecutive ring slots beyond N (2560 B: whole 128-B lines)
 
     def __init__(self, prob, cfg: AromConfig, device="cuda", ctx: Context | None = None, paper=None):
+        if cfg.odeim_factor > 0 and (cfg.precision != FP64 or cfg.m > ODEIM_MAX_MODES):
+            raise ValueError(f"ODEIM points need an FP64 basis of at most {ODEIM_MAX_MODES} modes")
+        if cfg.gauss_newton and (cfg.precision != FP64 or paper is not None):
+            raise ValueError("Gauss-Newton subiterations run with the first-order scheme on an FP64 basis")
         self.prob = prob
         self.cfg = cfg
         self.ctx = ctx or Context(prob, m_max=cfg.m, w_max=cfg.w, device=device)
@@ -104,8 +111,6 @@ class Arom:
         self.points = None
         self.gn_work = None
         if cfg.gauss_newton:
-            if cfg.precision != FP64 or paper is not None:
-                raise ValueError("Gauss-Newton subiterations run with the first-order scheme on an FP64 basis")
             self.gn_work = c.empty(cfg.m * c.n)
             self.defer_basis = False
 

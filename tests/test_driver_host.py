@@ -116,3 +116,18 @@ def test_other_errors_propagate():
     w, z, steps = 6, 50, 10
     with pytest.raises(HsError):
         run(steps, w, z, fail_at={8}, fail=-6)
+
+
+@pytest.mark.parametrize("kw", [dict(odeim_factor=2, m=17), dict(odeim_factor=2, m=4, precision=D.MIXED_FP32),
+                                dict(gauss_newton=True, m=4, precision=D.MIXED_FP32)])
+def test_unsupported_option_combinations_fail_before_any_allocation(kw):
+    """ODEIM points need an FP64 basis of at most 16 modes and Gauss-Newton
+    subiterations an FP64 basis: the driver says so at construction, before
+    it creates a context or allocates device memory."""
+    with pytest.raises(ValueError):
+        D.Arom(None, D.AromConfig(w=6, z=5, **kw), ctx=None)
+
+
+def test_gauss_newton_with_the_paper_scheme_fails_at_construction():
+    with pytest.raises(ValueError):
+        D.Arom(None, D.AromConfig(w=6, m=4, z=5, gauss_newton=True), ctx=None, paper=object())

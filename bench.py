@@ -98,7 +98,7 @@ def traffic_for(kernel, workload):
     return d.get("bytes_per_launch")
 
 
-def kernel_rates(ctx, q, q_prev, reps=3):
+def kernel_rates(ctx, q, q_prev, reps=3, classes=("residual", "resjac", "filter")):
     """Achieved HBM rate (algorithmic bytes / HIP-event launch time) of the
     residual kernel classes on the full mesh: hs_residual, the residual +
     Jacobian data of a full Newton step, and the fused filter pass."""
@@ -111,6 +111,7 @@ def kernel_rates(ctx, q, q_prev, reps=3):
             # one pass per order: every pass is a full pass (a later pass of an
             # order computes only the tiles near the previous pass's changes)
             "filter": lambda: ctx.filter(q, q_prev, params=hybrid_params(jfmax=1), out=R)}
+    jobs = {c: jobs[c] for c in classes}
     for cls, fn in jobs.items():
         fn()
         torch.cuda.synchronize(ctx.device)
@@ -142,18 +143,67 @@ def kernel_rates(ctx, q, q_prev, reps=3):
     return out
 
 
+def stream_ceiling(ctx, burst=20):
+    """hs_stream_add over the residual's traffic (read two arrays of N
+    doubles, write one), timed as the residual is (per-launch events, and 20
+    launches back to back): what a launch of this many bytes reaches at all."""
+    import torch
+    n = ctx.n
+    a = torch.rand(n, dtype=torch.float64, device=ctx.device)
+    b = torch.rand(n, dtype=torch.float64, device=ctx.device)
+    c = torch.empty_like(a)
+    ctx.stream_add(a, b, c)
+    torch.cuda.synchronize(ctx.device)
+    ctx.prof_enable("stream")
+    for _ in range(3):
+        ctx.stream_add(a, b, c)
+    ms, cnt, by = ctx.prof_read()
+    ctx.prof_enable(0)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize(ctx.device)
+    t0.record()
+    for _ in range(burst):
+        ctx.stream_add(a, b, c)
+    t1.record()
+    torch.cuda.synchronize(ctx.device)
+    us = 1e3 * t0.elapsed_time(t1) / burst
+    by = by / cnt
+    return {"bytes_per_launch": by, "avg_launch_us": 1e3 * ms / cnt,
+            "frac": by / (ms / cnt * 1e-3) / 1e9 / HBM_PEAK_GBS, "burst_avg_launch_us": us,
+            "burst_frac": by / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}
+
+
 def residual_kernels(prob, q, q_prev, seed):
-    """kernel_rates on this workload's mesh and on the 2D Euler 512^2 mesh."""
+    """kernel_rates on this workload's mesh, on the 2D Euler 512^2 mesh and
+    (the residual alone) on a 4096^2 mesh of the same 2D Burgers recipe, each
+    beside a plain streaming kernel of the same bytes."""
+    import dataclasses
     import torch
     import workloads as W
     from paper_2301_01718_amd import Context
-    res = {"burgers2d_1024" if prob.nx == 1024 else "this": kernel_rates(Context(prob), q, q_prev)}
+    key = "burgers2d_1024" if prob.nx == 1024 else "this"
+    ctx = Context(prob)
+    res = {key: kernel_rates(ctx, q, q_prev)}
+    res[key]["stream_ceiling"] = stream_ceiling(ctx)
     wl_e = W.WORKLOADS["euler2d_512"]
     prob_e, q0_e = W.make(wl_e, seed)
     ce = Context(prob_e)
     qe0 = torch.from_numpy(q0_e).to(ce.device)
     qe1, _ = ce.hdm_step(qe0)
     res["euler2d_512"] = kernel_rates(ce, qe1, qe0)
+    res["euler2d_512"]["stream_ceiling"] = stream_ceiling(ce)
+    del ce, qe0, qe1
+    # 4096^2 cells: 403 MB per launch, where the launch's ramp no longer
+    # dominates; q_prev is the seeded state, q a scaled copy of it
+    wl_b = W.WORKLOADS["burgers2d_1024"]
+    wl_big = dataclasses.replace(wl_b, name="burgers2d_4096", nx=4096, ny=4096)
+    prob_b, q0_b = W.make(wl_big, seed)
+    cb = Context(prob_b, m_max=1, w_max=2)
+    qb0 = torch.from_numpy(q0_b).to(cb.device)
+    qb1 = 1.01 * qb0
+    res["burgers2d_4096"] = kernel_rates(cb, qb1, qb0, classes=("residual",))
+    res["burgers2d_4096"]["stream_ceiling"] = stream_ceiling(cb)
+    del cb, qb0, qb1
     return res
 
 

@@ -516,6 +516,7 @@ hs_status hs_set_option(hs_ctx* ctx, int32_t option, int64_t value);
 #define HS_PROF_FILTER      7   /* fused filter pass: S_y S_x, gate, merged residual norms */
 #define HS_PROF_RESIDUAL    8   /* hs_residual: R(q; q_prev) on the full mesh */
 #define HS_PROF_BASIS_PGRAM 9   /* second window pass of basis_update: Gram of the preconditioned window */
+#define HS_PROF_STREAM      10  /* hs_stream_add: the plain streaming reference */
 /* Start timing every launch of one kernel class (HS_PROF_NONE stops).  Each
  * launch is bracketed by two HIP events recorded on the context's stream, and
  * the algorithmic bytes of that launch (the minimum reads and writes the
@@ -525,6 +526,13 @@ hs_status hs_prof_enable(hs_ctx* ctx, int32_t kernel_class);
  * algorithmic bytes since enable or the last read, and reset the counters. */
 hs_status hs_prof_read(hs_ctx* ctx, double* total_ms /* host */, int32_t* launches /* host */,
                        double* bytes /* host */);
+
+/* A plain streaming kernel, c = a + b over n doubles (device; reads 16 n
+ * bytes, writes 8 n, one element per thread): what a launch with the full-mesh
+ * residual's traffic reaches on this device at all, the reference beside which
+ * the residual kernels' HBM rates are read.  Not part of the method.  c may
+ * alias neither input; n <= 2^38.  Errors: HS_ERR_INVALID_ARG. */
+hs_status hs_stream_add(hs_ctx* ctx, const double* a, const double* b, double* c, int64_t n);
 
 #ifdef __cplusplus
 }

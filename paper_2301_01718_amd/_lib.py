@@ -112,6 +112,7 @@ _SIGS = {
     "hs_status_string": [I32],
     "hs_last_error": [P],
     "hs_residual": [P, P, P, P],
+    "hs_stream_add": [P, P, P, P, ctypes.c_int64],
     "hs_jvp": [P, P, P, P],
     "hdm_step": [P, P, P, ctypes.POINTER(StepInfo)],
     "hs_paper_residual": [P, ctypes.POINTER(PaperHDM), P, P, P, P],
@@ -162,7 +163,7 @@ _SIGS = {
 BASIS_PENDING = -1   # rom_hybrid_step's m for a basis still being formed (HS_BASIS_PENDING)
 
 PROF_CLASSES = {"basis_gram": 1, "basis_form": 2, "recon": 3, "resjac": 4, "sweep": 5, "cellres": 6, "basis_pgram": 9,
-                "filter": 7, "residual": 8}
+                "filter": 7, "residual": 8, "stream": 10}
 
 
 def lib():
@@ -322,6 +323,13 @@ class Context:
     def residual(self, q, q_prev, out=None):
         out = self.empty() if out is None else out
         self._check(lib().hs_residual(self.h, _ptr(self._in(q)), _ptr(self._in(q_prev)), _ptr(self._in(out))))
+        return out
+
+    def stream_add(self, a, b, out):
+        """hs_stream_add: out = a + b (float64, equal sizes; the streaming reference)."""
+        n = a.numel()
+        self._check(lib().hs_stream_add(self.h, _ptr(self._in(a, n)), _ptr(self._in(b, n)),
+                                        _ptr(self._in(out, n)), n))
         return out
 
     def jvp(self, q, v, out=None):

@@ -235,6 +235,68 @@ __global__ void residual_kernel(Grid g, const double* __restrict__ q, const doub
   for (int a = 0; a < NC; ++a) R[a * g.ncell + cell] = r[a];
 }
 
+// The same residual with each thread marching down K rows of one column (a
+// block covers 256 columns): the column's K + 2 states along y are loaded
+// once and kept in registers, so of the five stencil loads per cell only the
+// two along x remain (hits in the lines the wave's own loads bring in).  The
+// stencil values, and so the arithmetic, are the per-cell kernel's.  Rows past
+// the mesh (a ragged last band) are skipped.
+template <int NC, int K>
+__global__ void __launch_bounds__(256) residual_col_kernel(Grid g, const double* __restrict__ q,
+                                                           const double* __restrict__ qp, double* __restrict__ R) {
+  const int i = blockIdx.x * 256 + threadIdx.x, j0 = blockIdx.y * K;
+  if (i >= g.nx || j0 >= g.ny) return;
+  const int kn = min(K, g.ny - j0);
+  const int c_dn = neighbour(g, i, j0, 2), c_up = neighbour(g, i, j0 + kn - 1, 3);
+  // w[s]: the state below the band (s = 0), its rows (1..kn), the state above it (kn + 1)
+  double w[K + 2][NC];
+  double pv[K][NC];
+#pragma unroll
+  for (int s = 0; s < K + 2; ++s) {
+    const int c = s == 0 ? c_dn : (s <= kn ? i + g.nx * (j0 + s - 1) : (s == kn + 1 ? c_up : -1));
+#pragma unroll
+    for (int a = 0; a < NC; ++a) w[s][a] = c >= 0 ? q[(size_t)a * g.ncell + c] : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int a = 0; a < NC; ++a) pv[k][a] = k < kn ? qp[(size_t)a * g.ncell + i + g.nx * (j0 + k)] : 0.0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if (k >= kn) break;
+    const int j = j0 + k, cell = i + g.nx * j;
+    Stencil<NC> st;
+    st.self = cell;
+#pragma unroll
+    for (int a = 0; a < NC; ++a) st.c[a] = w[k + 1][a];
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const int nb = neighbour(g, i, j, d);
+      st.idx[d] = nb;
+#pragma unroll
+      for (int a = 0; a < NC; ++a) st.nb[d][a] = nb < 0 ? g.inflow : q[(size_t)a * g.ncell + nb];
+    }
+    st.idx[2] = neighbour(g, i, j, 2);
+    st.idx[3] = neighbour(g, i, j, 3);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      st.nb[2][a] = w[k][a];
+      st.nb[3][a] = w[k + 2][a];
+    }
+    double r[NC];
+    cell_residual<NC>(g, st, pv[k], r);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) R[(size_t)a * g.ncell + cell] = r[a];
+  }
+}
+
+// c = a + b, one element per thread: the streaming reference.
+__global__ void __launch_bounds__(kBlock) stream_add_kernel(long long n, const double* __restrict__ a,
+                                                            const double* __restrict__ b, double* __restrict__ c) {
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e < n) c[e] = a[e] + b[e];
+}
+
 // out = J(q) v
 template <int NC>
 __global__ void __launch_bounds__(kBlock) jvp_kernel(Grid g, const double* __restrict__ q, const double* __restrict__ v,
@@ -676,7 +738,7 @@ hs_status hs_create(const hs_problem* pr, void* stream, hs_ctx** out) {
 }
 
 hs_status hs_prof_enable(hs_ctx* ctx, int32_t cls) {
-  if (!ctx || cls < HS_PROF_NONE || cls > HS_PROF_BASIS_PGRAM) return HS_ERR_INVALID_ARG;
+  if (!ctx || cls < HS_PROF_NONE || cls > HS_PROF_STREAM) return HS_ERR_INVALID_ARG;
   ctx->prof_class = cls;
   ctx->prof_used = 0;
   ctx->prof_bytes.clear();
@@ -724,12 +786,32 @@ hs_status hs_sync(hs_ctx* ctx) {
   return HS_OK;
 }
 
+hs_status hs_stream_add(hs_ctx* ctx, const double* a, const double* b, double* c, int64_t n) {
+  if (!ctx || !a || !b || !c || n < 0 || n > (1LL << 38) || c == a || c == b) return HS_ERR_INVALID_ARG;
+  if (n == 0) return HS_OK;
+  HS_TRY(prof_begin(ctx, HS_PROF_STREAM));
+  HS_LAUNCH(ctx, stream_add_kernel, (unsigned)((n + kBlock - 1) / kBlock), kBlock, (long long)n, a, b, c);
+  return prof_end(ctx, HS_PROF_STREAM, 24.0 * (double)n);
+}
+
 hs_status hs_residual(hs_ctx* ctx, const double* q, const double* q_prev, double* R) {
   if (!ctx || !q || !q_prev || !R) return HS_ERR_INVALID_ARG;
   const int nb = blocks_for(ctx->ncell);
   HS_TRY(prof_begin(ctx, HS_PROF_RESIDUAL));
-  if (ctx->nc == 1) HS_LAUNCH(ctx, residual_kernel<1>, nb, kBlock, ctx->g, q, q_prev, R);
-  else HS_LAUNCH(ctx, residual_kernel<4>, nb, kBlock, ctx->g, q, q_prev, R);
+  // Column bands pay on large 2D meshes (measured, same bits: 2D Burgers
+  // 4096^2 with 4 rows 103 -> 76 us; Euler 2048^2 with 2 rows 115 -> 99 us,
+  // 512^2 9.3 -> 8.8 us); on 2D Burgers up to 1024^2 one cell per thread is
+  // about 5 % faster.
+  const Grid& g = ctx->g;
+  const dim3 bands1((g.nx + 255) / 256, (g.ny + 3) / 4), bands4((g.nx + 255) / 256, (g.ny + 1) / 2);
+  if (ctx->nc == 1 && g.ny > 1 && ctx->ncell > (1 << 20))
+    HS_LAUNCH(ctx, (residual_col_kernel<1, 4>), bands1, 256, g, q, q_prev, R);
+  else if (ctx->nc == 1)
+    HS_LAUNCH(ctx, residual_kernel<1>, nb, kBlock, g, q, q_prev, R);
+  else if (g.ny > 1 && ctx->ncell >= (1 << 18))
+    HS_LAUNCH(ctx, (residual_col_kernel<4, 2>), bands4, 256, g, q, q_prev, R);
+  else
+    HS_LAUNCH(ctx, residual_kernel<4>, nb, kBlock, g, q, q_prev, R);
   // reads q and q_prev once, writes R
   return prof_end(ctx, HS_PROF_RESIDUAL, 24.0 * ctx->n);
 }

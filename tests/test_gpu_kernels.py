@@ -28,6 +28,40 @@ def test_residual_bitwise(name):
     assert np.array_equal(R, Ro), np.max(np.abs(R - Ro))
 
 
+@pytest.mark.parametrize("name,nx,ny", [("burgers2d_1024", 1100, 1001), ("euler2d_512", 520, 505)])
+def test_residual_column_bands_bitwise(name, nx, ny):
+    """Meshes large enough for the residual's column-band form (2D Burgers
+    above 2^20 cells: 4 rows per thread; 2D Euler from 2^18 cells: 2 rows),
+    with a ragged last band and a partial last block of columns: the same
+    bits as the oracle."""
+    import dataclasses
+    need_gpu()
+    print_case("residual (column bands)", name, nx, ny)
+    wl = dataclasses.replace(W.WORKLOADS[name], nx=nx, ny=ny)
+    prob, q0 = W.make(wl, 3)
+    rng = np.random.default_rng(4)
+    q = q0 * (1 + 1e-3 * rng.standard_normal(q0.size))
+    qp = q0 * (1 + 1e-3 * rng.standard_normal(q0.size))
+    ctx = ctx_for(prob, m_max=1, w_max=2)
+    R = host(ctx.residual(dev(q), dev(qp)))
+    Ro = fv.residual(prob, q, qp)
+    assert np.array_equal(R, Ro), np.max(np.abs(R - Ro))
+
+
+def test_stream_add_reference():
+    """The streaming reference of the bandwidth measurements adds exactly
+    (a ragged element count)."""
+    need_gpu()
+    print_case("hs_stream_add")
+    wl, prob, q0 = case("burgers2d", 0)
+    ctx = ctx_for(prob, m_max=1, w_max=2)
+    rng = np.random.default_rng(7)
+    a, b = rng.standard_normal(100003), rng.standard_normal(100003)
+    out = dev(np.zeros(100003))
+    ctx.stream_add(dev(a), dev(b), out)
+    assert np.array_equal(host(out), a + b)
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_jvp_matches_oracle_jacobian(name):
     need_gpu()

@@ -59,6 +59,8 @@ def parse():
                     help="skip the paper's experiments (its own scheme: Sod's tube, the implosion)")
     ap.add_argument("--paper-only", choices=("all", "residual"), default=None,
                     help="run only the paper's experiments (all) or only its residual kernel's timing (residual)")
+    ap.add_argument("--residual-only", action="store_true",
+                    help="run only the full-mesh residual kernels' timing (residual_kernels) and print it")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 1 GiB elementwise copy (counter calibration for rocprofv3 --pmc)")
     return ap.parse_args()
@@ -645,6 +647,18 @@ def main():
             torch.add(a, 0.0, out=b)      # one elementwise copy: 1 GiB read + 1 GiB written
             torch.cuda.synchronize()
         print(json.dumps({"paper_experiments": out}), flush=True)
+        return 0
+    if args.residual_only and args.gpus == 1:
+        import torch
+        import workloads as W
+        from paper_2301_01718_amd import Context
+        wl = W.WORKLOADS[args.workload]
+        prob, q0 = W.make(wl, args.seed)
+        c = Context(prob, m_max=1, w_max=2)
+        qa = torch.from_numpy(q0).to(c.device)
+        qb, _ = c.hdm_step(qa)
+        del c
+        print(json.dumps({"residual_kernels": residual_kernels(prob, qb, qa, args.seed)}), flush=True)
         return 0
     if args.gpus != 1:
         print("bench.py: only one GPU is measured; the hybrid step's multi-GPU (sharded) "

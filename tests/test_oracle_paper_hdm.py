@@ -419,3 +419,38 @@ def test_paper_arom_with_odeim_on_sod():
     hyb = [r for r in res["records"] if r["type"] == "hybrid"]
     assert len(hyb) > 100 and all(r["n_p"] == 8 for r in hyb)
     assert max(errs) < 0.01 and np.mean(errs) < 0.005, (max(errs), np.mean(errs))
+
+
+def test_paper_filter_moves_a_converged_state_only_below_its_residual():
+    """The gated filter sequence on a converged BDF2 state of Sod's tube:
+    a filter pass lowers a cell's residual only where the state is already a
+    root up to rounding (the implicit solve leaves momenta of 1e-25..1e-54 in
+    the constant regions, and the strict gate compares residuals exactly), so
+    the state moves by less than its own residual size, nowhere by O(h^2)."""
+    prob, states = _sod_states(120, 240, 30)
+    q2, q1, q = states[-3], states[-2], states[-1]
+    r = pa.cell_residual_norm(prob, q, q1, q2)
+    g = pa.spatial_filter(prob, q, q1, q2, pa.HybridParams())
+    assert np.max(np.abs(g - q)) <= np.max(r)
+
+
+def test_paper_filter_removes_a_planted_two_cell_oscillation():
+    """A 2-dx oscillation of 1e-3 planted on eight cells of the constant left
+    state (all four components) of a converged state: the order-2 pass
+    annihilates it in the interior and the gates keep those cells, so the
+    filtered state is back at the converged one to 1e-6 of the amplitude and
+    the sum of the cell residual norms falls by more than 1e6."""
+    prob, states = _sod_states(120, 240, 30)
+    q2, q1, q = states[-3], states[-2], states[-1]
+    n = prob.ncell
+    cells = np.arange(10, 18)
+    noisy = q.copy()
+    for a in range(4):
+        noisy[a * n + cells] += 1e-3 * (1 + a) * (-1.0) ** cells
+    log = []
+    g = pa.spatial_filter(prob, noisy, q1, q2, pa.HybridParams(), log)
+    assert log[0][0] == 1 and log[0][2] >= cells.size
+    assert np.max(np.abs(g - q)) < 1e-6 * 4e-3
+    r0 = pa.cell_residual_norm(prob, noisy, q1, q2).sum()
+    r1 = pa.cell_residual_norm(prob, g, q1, q2).sum()
+    assert r1 < 1e-6 * r0
